@@ -1,0 +1,133 @@
+"""The synthetic workloads: surfaces, coefficients and right-hand sides, all seeded.
+
+=====  ==========================================================================
+name   workload
+=====  ==========================================================================
+sphere unit sphere, cube-sphere k=2, q=8 (24 patches, 1,536 nodes);
+       a = 1 + 0.5 sin(2 x1) cos(x2) (or a = 1); f from u = (x^2 - y^2) z
+ellip  ellipsoid (1, 0.8, 0.6), cube-sphere k=16, q=10 (1,536 patches,
+       153,600 nodes); a = exp(0.3 x1 x2); f = 20 solid harmonics, N(0,1)
+star   r = 1 + 0.25 sum_8 w_k Y_k (1 <= l <= 4, w ~ U(-1,1)), cube-sphere
+       k=37, q=8 (8,214 patches, 525,696 nodes); a = 2^tanh(s(x)) seed field
+torus  wobbly torus R = 1, r = 0.4 (1 + 0.2 cos 5 theta sin 3 phi), 256 x 128
+       patches, q=8 (2,097,152 nodes); a = 1 + 0.5 tanh(sin 3 x1); 16 RHS
+serve  request stream: sphere / random-axis ellipsoid / torus, 2e3..2e5 nodes
+=====  ==========================================================================
+
+Every builder takes a size knob so that tests can run the same family at
+oracle-friendly sizes.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import fields as F
+from .surfaces import Surface, cube_sphere, real_sph_harm_cartesian, torus
+
+__all__ = [
+    "Problem", "sphere_problem", "ellipsoid_problem", "star_problem", "wobbly_torus_problem",
+    "serving_requests", "random_density",
+]
+
+
+@dataclass
+class Problem:
+    surface: Surface
+    a: np.ndarray            # (N,)
+    grad_a: np.ndarray       # (N, 3) ambient gradient
+    f: np.ndarray            # (N, n_rhs)
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.surface.n
+
+
+def _sphere_manufactured_rhs(x: np.ndarray, a_fn) -> tuple[np.ndarray, np.ndarray]:
+    """On the unit sphere (exact normal = position): u = (x^2 - y^2) z and
+    f = div_G(a grad_G u) = a * (-12 u) + grad_G a . grad_G u (u is a degree-3 harmonic)."""
+    X = torch.tensor(x, dtype=torch.float64)
+    nrm = X / torch.linalg.norm(X, dim=1, keepdim=True)
+    u = (X[:, 0] ** 2 - X[:, 1] ** 2) * X[:, 2]
+    gu = torch.stack([2 * X[:, 0] * X[:, 2], -2 * X[:, 1] * X[:, 2], X[:, 0] ** 2 - X[:, 1] ** 2], dim=1)
+    a, ga = F.eval_field(a_fn, x)
+    ga = torch.tensor(ga)
+    tang = lambda g: g - nrm * (nrm * g).sum(dim=1, keepdim=True)
+    f = torch.tensor(a) * (-12.0 * u) + (tang(ga) * tang(gu)).sum(dim=1)
+    return f.numpy().copy(), u.numpy().copy()
+
+
+def sphere_problem(k: int = 2, q: int = 8, const_a: bool = False) -> Problem:
+    s = cube_sphere(k, q, name="sphere")
+    a_fn = F.a_const(1.0) if const_a else F.a_sphere_cfg
+    a, ga = F.eval_field(a_fn, s.x)
+    f, u = _sphere_manufactured_rhs(s.x, a_fn)
+    return Problem(s, a, ga, f[:, None], name=f"sphere_k{k}_q{q}" + ("_a1" if const_a else ""),
+                   meta={"u_exact": u})
+
+
+def ellipsoid_problem(k: int = 16, q: int = 10, axes=(1.0, 0.8, 0.6), seed: int = 1, n_rhs: int = 1) -> Problem:
+    s = cube_sphere(k, q, axes=axes, name="ellipsoid")
+    a, ga = F.eval_field(F.a_exp_xy, s.x)
+    f = np.stack([F.solid_harmonic_rhs(s.x, seed + 100 * r) for r in range(n_rhs)], axis=1)
+    return Problem(s, a, ga, f, name=f"ellipsoid_k{k}_q{q}")
+
+
+def _star_radial(seed: int):
+    rng = np.random.default_rng(seed)
+    pool = [(l, m) for l in range(1, 5) for m in range(-l, l + 1)]
+    pick = rng.choice(len(pool), size=8, replace=False)
+    lms = [pool[i] for i in sorted(pick)]
+    w = rng.uniform(-1, 1, 8)
+
+    def radial(s):
+        acc = torch.zeros(s.shape[0], dtype=s.dtype)
+        for wk, (l, m) in zip(w, lms):
+            acc = acc + float(wk) * real_sph_harm_cartesian(l, m, s)
+        return 1.0 + 0.25 * acc
+
+    return radial
+
+
+def star_problem(k: int = 37, q: int = 8, seed: int = 2, n_rhs: int = 1) -> Problem:
+    s = cube_sphere(k, q, radial=_star_radial(seed), name="star")
+    a, ga = F.eval_field(F.a_seed_field(seed), s.x)
+    f = np.stack([F.solid_harmonic_rhs(s.x, seed + 100 * r) for r in range(n_rhs)], axis=1)
+    return Problem(s, a, ga, f, name=f"star_k{k}_q{q}")
+
+
+def wobbly_torus_problem(n_theta: int = 256, n_phi: int = 128, q: int = 8, n_rhs: int = 16) -> Problem:
+    rfun = lambda th, ph: 0.4 * (1.0 + 0.2 * torch.cos(5 * th) * torch.sin(3 * ph))
+    s = torus(n_theta, n_phi, q, R=1.0, r=rfun, name="wobbly_torus")
+    a, ga = F.eval_field(F.a_tanh_sin, s.x)
+    f = np.stack([F.solid_harmonic_rhs(s.x, 4 * 100 + r) for r in range(n_rhs)], axis=1)
+    return Problem(s, a, ga, f, name=f"wobbly_torus_{n_theta}x{n_phi}_q{q}")
+
+
+def serving_requests(n_requests: int = 256, seed: int = 3, n_min: float = 2e3, n_max: float = 2e5, q: int = 8):
+    """Yield ``n_requests`` (kind, Problem) pairs with log-uniform node counts."""
+    rng = np.random.default_rng(seed)
+    for r in range(n_requests):
+        kind = ["sphere", "ellipsoid", "torus"][rng.integers(3)]
+        n_target = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+        if kind == "torus":
+            n = max(4, int(round(math.sqrt(n_target / (2 * q * q)))))
+            rr = float(rng.uniform(0.3, 0.5))
+            s = torus(2 * n, n, q, R=1.0, r=rr, name="torus")
+        else:
+            k = max(2, int(round(math.sqrt(n_target / (6 * q * q)))))
+            axes = (1.0, 1.0, 1.0) if kind == "sphere" else tuple(rng.uniform(0.5, 1.5, 3))
+            s = cube_sphere(k, q, axes=axes, name=kind)
+        a, ga = F.eval_field(F.a_seed_field(int(rng.integers(1 << 30))), s.x)
+        f = F.solid_harmonic_rhs(s.x, int(rng.integers(1 << 30)))[:, None]
+        yield kind, Problem(s, a, ga, f, name=f"req{r}_{kind}_{s.n}")
+
+
+def random_density(n: int, n_rhs: int = 1, seed: int = 0) -> np.ndarray:
+    """Seeded N(0,1) density (N, n_rhs) for operator-apply tests."""
+    return np.random.default_rng(seed).normal(size=(n, n_rhs))
