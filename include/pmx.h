@@ -1,0 +1,174 @@
+/*
+ * pmx.h -- C ABI of the MI355X parametrix surface-PDE library.
+ *
+ * Solves div_G(a grad_G u) = f on a smooth closed surface G (the c = 0, b = 0
+ * case of the surface PDE in the paper's introduction, eq:surf_PDE) through
+ * the second-kind integral equation of the parametrix method (eq:IE):
+ *
+ *     sigma(x) + int_G R(x, x') sigma(x') da(x') + int_G sigma = f(x),
+ *     u(x) = int_G K(x, x') sigma(x') da(x')  - its mean,
+ *
+ * with K(x, x') = log|x - x'| / (2 pi a(x')) (Section 4.1, eq:diff_param) and
+ * the remainder R of eq:explicit_remainder; the rank-one term int_G sigma
+ * removes the one-dimensional null space (Section 3).  The system is
+ * discretized by the Nystrom method on quad patches with tensor
+ * Gauss-Legendre nodes (Section 6.1), with singular (Section 6.1.1),
+ * nearly singular (Section 6.1.2) and smooth (Section 6.1.3) quadrature.
+ *
+ * Conventions
+ *  - Every function returns a pmx_status (0 = OK, < 0 = error) and never
+ *    throws; pmx_last_error() returns a message for the calling thread.
+ *  - Ownership: the caller owns every array it passes.  The library copies
+ *    inputs during *_create, so they may be freed on return.  Handles are
+ *    owned by the library and released by *_destroy (NULL-safe).
+ *  - mem_kind says where caller arrays live: PMX_MEM_HOST (pageable or pinned
+ *    host memory) or PMX_MEM_DEVICE (device memory of the context's GPU).
+ *  - stream: a hipStream_t (may be NULL = the null stream).  All device work
+ *    of a call is enqueued on it; calls with host outputs return after the
+ *    results are copied out.
+ *  - Node order: node i = P*q*q + iu*q + iv sits at the Gauss-Legendre pair
+ *    (t_iu, t_iv) of patch P on [-1,1]^2.  Arrays of 3-vectors are row-major
+ *    N x 3.  Multi-RHS arrays are n_rhs contiguous vectors of length N
+ *    (element r*N + i).
+ */
+#ifndef PMX_H
+#define PMX_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define PMX_API __attribute__((visibility("default")))
+#else
+#define PMX_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pmx_status;
+typedef struct pmx_ctx pmx_ctx;
+typedef struct pmx_surface pmx_surface;
+typedef struct pmx_operator pmx_operator;
+typedef struct pmx_server pmx_server;
+
+enum {
+  PMX_OK = 0,
+  PMX_PENDING = 1,
+  PMX_ERR_INVALID = -1,        /* bad argument: shape, q < 2, a <= 0, non-finite data */
+  PMX_ERR_OOM = -2,            /* device allocation failed */
+  PMX_ERR_TOO_LARGE = -3,      /* footprint over the context's HBM budget */
+  PMX_ERR_NOT_CONVERGED = -4,  /* iteration limit reached; best iterate written */
+  PMX_ERR_ORIENTATION = -5,    /* surface normals point inward (sum w n.x <= 0) */
+  PMX_ERR_DEVICE = -6,         /* HIP runtime error */
+  PMX_ERR_CANCELLED = -7
+};
+
+enum { PMX_MEM_HOST = 0, PMX_MEM_DEVICE = 1 };
+
+/* Far-field evaluation of the apply. */
+enum {
+  PMX_PREC_FP64_DIRECT = 0,  /* FP64 direct sum over all pairs (the reference operator A64) */
+  PMX_PREC_MIXED_FMM = 1,    /* FP32 interpolation FMM far field, FP64 near field (A32) */
+  PMX_PREC_FP32_DIRECT = 2   /* FP32 direct sum, FP64 near field */
+};
+
+typedef struct pmx_options {
+  double eta_near;     /* near criterion: within eta patch radii of the centroid (Section 6.1.2: 1.5) */
+  int n_gl;            /* Gauss-Legendre order of the local rules (Section 6.1.1: 16) */
+  int fmm_order;       /* Chebyshev points per box edge of the FMM (default 6) */
+  int fmm_leaf;        /* target points per FMM leaf box (default 128) */
+  double gmres_tol;    /* relative residual target of GMRES (FP64 path) */
+  int gmres_restart;   /* Krylov space size before restart */
+  int max_iter;        /* total GMRES iteration limit */
+  double ir_tol;       /* mixed path: final relative residual (FP64 operator) */
+  double inner_tol;    /* mixed path: relative residual of each inner GMRES */
+  int max_ir;          /* mixed path: outer refinement step limit */
+  int precision;       /* PMX_PREC_* used by pmx_solve */
+} pmx_options;
+
+typedef struct pmx_info {
+  int iters_total;       /* GMRES iterations (all inner solves) */
+  int ir_steps;          /* outer refinement steps (mixed path), 0 otherwise */
+  int applies_fp64;      /* FP64 operator applies */
+  int applies_low;       /* FP32-far-field operator applies */
+  double rel_residual;   /* ||f - A64 sigma|| / ||f|| (2-norm of the Nystrom system) */
+  double removed_mean;   /* weighted mean removed from f (c = 0 needs mean-zero data) */
+  double t_setup;        /* seconds spent in operator setup */
+  double t_solve;        /* seconds spent in the solve */
+} pmx_info;
+
+typedef struct pmx_operator_stats {
+  int64_t n_nodes;
+  int64_t n_patches;
+  int32_t q;
+  int32_t fmm_levels;     /* 0 until the FMM tree is built */
+  int64_t near_pairs;     /* (target, patch) pairs with local-rule correction blocks */
+  int64_t fmm_boxes;
+  int64_t fmm_m2l_pairs;
+  int64_t fmm_p2p_pairs;  /* source-target point pairs handled directly by the FMM */
+  uint64_t device_bytes;  /* device memory held by the operator */
+} pmx_operator_stats;
+
+/* Context on one GPU.  hbm_budget_bytes bounds what the context's operators and
+ * server may hold (0 = no bound).  Errors: INVALID (no such device), DEVICE. */
+PMX_API pmx_status pmx_ctx_create(int device, uint64_t hbm_budget_bytes, pmx_ctx** out);
+PMX_API void pmx_ctx_destroy(pmx_ctx* ctx);
+/* Message of the last error on the calling thread ("" if none). */
+PMX_API const char* pmx_last_error(void);
+/* Defaults: eta 1.5, n_gl 16, fmm_order 6, fmm_leaf 128, gmres_tol 1e-10, restart 60,
+ * max_iter 400, ir_tol 1e-8, inner_tol 1e-4, max_ir 20, precision FP64_DIRECT. */
+PMX_API void pmx_default_options(pmx_options* opts);
+
+/* Surface from node data (Section 6.1: patches y_P(u, v) on [-1,1]^2): position x and
+ * the parameter derivatives x_u, x_v, x_uu, x_uv, x_vv at the N = n_patches*q*q nodes.
+ * Computes normals, area elements, weights, mean curvature (Section 2.2), patch
+ * centroids and radii (Section 6.1.2).  Errors: INVALID (q < 2 or q > 16, n_patches < 1,
+ * non-finite data, degenerate metric), ORIENTATION (inward normals), OOM, DEVICE. */
+PMX_API pmx_status pmx_surface_create(pmx_ctx* ctx, int n_patches, int q, const double* x, const double* xu,
+                              const double* xv, const double* xuu, const double* xuv, const double* xvv,
+                              int mem_kind, void* stream, pmx_surface** out);
+PMX_API void pmx_surface_destroy(pmx_surface* s);
+
+/* Operator for the coefficient a > 0 at the nodes (N) with its ambient or surface
+ * gradient (N x 3; the tangential part is used, Section 4.1).  Builds near lists and
+ * the FP64 correction blocks of the self and near rules (Sections 6.1.1, 6.1.2).
+ * opts may be NULL (defaults).  The surface must outlive the operator.
+ * Errors: INVALID (a <= 0 or non-finite), TOO_LARGE (budget), OOM, DEVICE. */
+PMX_API pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* grad_a, const pmx_options* opts,
+                               int mem_kind, void* stream, pmx_operator** out);
+PMX_API void pmx_operator_destroy(pmx_operator* op);
+PMX_API pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* out);
+
+/* y = A sigma for n_rhs densities (eq:IE discretized, with the rank-one term):
+ * y_i = sigma_i + sum_{j != i} w_j R(x_i, x_j) sigma_j + sum_{P near i} C_{i,P,:} sigma_P
+ *       + sum_j w_j sigma_j.  precision selects the far-field evaluation (PMX_PREC_*).
+ * Errors: INVALID, OOM, DEVICE. */
+PMX_API pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, int mem_kind,
+                     void* stream);
+
+/* Solve A sigma = f - mean_w(f) for n_rhs right-hand sides.  opts->precision (or the
+ * operator's options when opts is NULL) selects GMRES on A64 (FP64 path) or iterative
+ * refinement with residuals on A64 and inner GMRES on A32 (mixed path).  sigma: in =
+ * warm start (pass sigma_in_is_guess = 1) or ignored, out = solution.  u (nullable):
+ * the mean-zero representation K[sigma] (eq:representation).  info (nullable): n_rhs
+ * entries.  Errors: INVALID, NOT_CONVERGED (best iterate written, info filled), OOM, DEVICE. */
+PMX_API pmx_status pmx_solve(pmx_operator* op, const pmx_options* opts, int n_rhs, const double* f, double* sigma,
+                     int sigma_in_is_guess, double* u, int mem_kind, void* stream, pmx_info* info);
+
+/* u = K[sigma] - mean_w(K[sigma]) (eq:representation), FP64.  Builds the parametrix
+ * correction blocks on first use.  Errors: INVALID, OOM, DEVICE. */
+PMX_API pmx_status pmx_represent(pmx_operator* op, int n_rhs, const double* sigma, double* u, int mem_kind, void* stream);
+
+/* Copy-out of operator internals to host arrays (any pointer may be NULL):
+ * node normal n (N x 3), mean curvature H (N), weight w (N), surface gradient of a (N x 3). */
+PMX_API pmx_status pmx_operator_export_geometry(pmx_operator* op, double* n, double* H, double* w, double* grad_s_a);
+/* Near lists in CSR form by target (ptr: N + 1, patch: near_pairs, sorted per target) and
+ * the FP64 correction blocks C (near_pairs x q*q; D for the parametrix, NULL to skip). */
+PMX_API pmx_status pmx_operator_export_near(pmx_operator* op, int64_t* ptr, int32_t* patch, double* C, double* D);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMX_H */

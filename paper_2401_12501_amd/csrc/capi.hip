@@ -1,0 +1,361 @@
+// C ABI: handles, argument checks, host/device staging and the apply/solve drivers.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "pmx_internal.hpp"
+
+namespace pmx {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+double now_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+void apply_device(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, hipStream_t st) {
+  switch (precision) {
+    case PMX_PREC_FP64_DIRECT: {
+      source_prep(op, sigma, n_rhs, false, st);
+      far_direct(op, true, n_rhs, st);
+      near_combine(op, sigma, y, n_rhs, far_direct_chunks(op, true), false, false, st);
+      break;
+    }
+    case PMX_PREC_FP32_DIRECT: {
+      source_prep(op, sigma, n_rhs, true, st);
+      far_direct(op, false, n_rhs, st);
+      near_combine(op, sigma, y, n_rhs, far_direct_chunks(op, false), false, false, st);
+      break;
+    }
+    case PMX_PREC_MIXED_FMM: {
+      if (!op->fmm) fmm_build(op, st);
+      source_prep(op, sigma, n_rhs, true, st);
+      fmm_far(op, n_rhs, st);
+      near_combine(op, sigma, y, n_rhs, 1, true, false, st);
+      break;
+    }
+    default:
+      throw Error(PMX_ERR_INVALID, "unknown precision mode");
+  }
+}
+
+void represent_device(pmx_operator* op, int n_rhs, const double* sigma, double* u, hipStream_t st) {
+  if (!op->nl.have_D) build_near_weights(&op->s->ctx->c, op->s->g, op->co, op->nl, op->opts, true, st);
+  source_prep(op, sigma, n_rhs, false, st);
+  far_direct_log(op, n_rhs, st);
+  near_combine(op, sigma, u, n_rhs, far_direct_chunks(op, true), false, true, st);
+  weighted_mean_remove(op, u, n_rhs, st);
+}
+
+}  // namespace pmx
+
+using namespace pmx;
+
+namespace {
+
+template <class F>
+pmx_status guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return PMX_OK;
+  } catch (const pmx::Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return PMX_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return PMX_ERR_DEVICE;
+  }
+}
+
+// Device view of a caller array: the pointer itself (device) or a staged copy (host).
+const double* stage_in(Ctx* ctx, DBuf<double>& buf, const double* p, size_t n, int mem_kind, hipStream_t st) {
+  PMX_REQUIRE(p != nullptr, PMX_ERR_INVALID, "null input array");
+  if (mem_kind == PMX_MEM_DEVICE) return p;
+  PMX_REQUIRE(mem_kind == PMX_MEM_HOST, PMX_ERR_INVALID, "mem_kind must be PMX_MEM_HOST or PMX_MEM_DEVICE");
+  buf.alloc(ctx, n);
+  PMX_HIP(hipMemcpyAsync(buf.p, p, n * sizeof(double), hipMemcpyHostToDevice, st));
+  return buf.p;
+}
+
+void check_opts(const pmx_options& o) {
+  PMX_REQUIRE(o.eta_near > 0.0 && std::isfinite(o.eta_near), PMX_ERR_INVALID, "eta_near must be positive");
+  PMX_REQUIRE(o.n_gl >= 2 && o.n_gl <= 16, PMX_ERR_INVALID, "n_gl must be in [2, 16]");
+  PMX_REQUIRE(o.fmm_order >= 2 && o.fmm_order <= 12, PMX_ERR_INVALID, "fmm_order must be in [2, 12]");
+  PMX_REQUIRE(o.fmm_leaf >= 8, PMX_ERR_INVALID, "fmm_leaf must be >= 8");
+  PMX_REQUIRE(o.gmres_restart >= 1 && o.gmres_restart <= 500, PMX_ERR_INVALID, "gmres_restart must be in [1, 500]");
+  PMX_REQUIRE(o.max_iter >= 1, PMX_ERR_INVALID, "max_iter must be >= 1");
+  PMX_REQUIRE(o.gmres_tol > 0 && o.ir_tol > 0 && o.inner_tol > 0, PMX_ERR_INVALID, "tolerances must be positive");
+  PMX_REQUIRE(o.precision >= 0 && o.precision <= 2, PMX_ERR_INVALID, "unknown precision mode");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pmx_last_error(void) { return g_last_error.c_str(); }
+
+void pmx_default_options(pmx_options* o) {
+  if (!o) return;
+  o->eta_near = 1.5;
+  o->n_gl = 16;
+  o->fmm_order = 6;
+  o->fmm_leaf = 128;
+  o->gmres_tol = 1e-10;
+  o->gmres_restart = 60;
+  o->max_iter = 400;
+  o->ir_tol = 1e-8;
+  o->inner_tol = 1e-4;
+  o->max_ir = 20;
+  o->precision = PMX_PREC_FP64_DIRECT;
+}
+
+pmx_status pmx_ctx_create(int device, uint64_t hbm_budget_bytes, pmx_ctx** out) {
+  return guarded([&] {
+    PMX_REQUIRE(out != nullptr, PMX_ERR_INVALID, "out is null");
+    *out = nullptr;
+    int n = 0;
+    PMX_HIP(hipGetDeviceCount(&n));
+    PMX_REQUIRE(device >= 0 && device < n, PMX_ERR_INVALID, "no such device");
+    PMX_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    PMX_HIP(hipGetDeviceProperties(&prop, device));
+    auto* c = new pmx_ctx;
+    c->c.device = device;
+    c->c.budget = hbm_budget_bytes;
+    c->c.n_cu = prop.multiProcessorCount;
+    *out = c;
+  });
+}
+
+void pmx_ctx_destroy(pmx_ctx* ctx) { delete ctx; }
+
+pmx_status pmx_surface_create(pmx_ctx* ctx, int n_patches, int q, const double* x, const double* xu,
+                              const double* xv, const double* xuu, const double* xuv, const double* xvv, int mem_kind,
+                              void* stream, pmx_surface** out) {
+  return guarded([&] {
+    PMX_REQUIRE(ctx && out, PMX_ERR_INVALID, "null handle");
+    *out = nullptr;
+    PMX_REQUIRE(n_patches >= 1 && q >= 2 && q <= 16, PMX_ERR_INVALID, "need n_patches >= 1 and 2 <= q <= 16");
+    PMX_REQUIRE((int64_t)n_patches * q * q < ((int64_t)1 << 31), PMX_ERR_INVALID, "too many nodes");
+    PMX_HIP(hipSetDevice(ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    auto* s = new pmx_surface;
+    try {
+      s->ctx = ctx;
+      s->g.M = n_patches;
+      s->g.q = q;
+      s->g.N = (int64_t)n_patches * q * q;
+      const size_t n3 = 3 * (size_t)s->g.N;
+      DBuf<double> b[6];
+      const double* d[6];
+      const double* src[6] = {x, xu, xv, xuu, xuv, xvv};
+      for (int k = 0; k < 6; ++k) d[k] = stage_in(&ctx->c, b[k], src[k], n3, mem_kind, st);
+      build_geometry(&ctx->c, s->g, d[0], d[1], d[2], d[3], d[4], d[5], st);
+      PMX_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+void pmx_surface_destroy(pmx_surface* s) { delete s; }
+
+pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* grad_a, const pmx_options* opts,
+                               int mem_kind, void* stream, pmx_operator** out) {
+  return guarded([&] {
+    PMX_REQUIRE(s && out, PMX_ERR_INVALID, "null handle");
+    *out = nullptr;
+    PMX_HIP(hipSetDevice(s->ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    auto* op = new pmx_operator;
+    try {
+      op->s = s;
+      if (opts) op->opts = *opts; else pmx_default_options(&op->opts);
+      check_opts(op->opts);
+      const double t0 = now_seconds();
+      Ctx* ctx = &s->ctx->c;
+      DBuf<double> ba, bg;
+      const double* da = stage_in(ctx, ba, a, s->g.N, mem_kind, st);
+      const double* dg = stage_in(ctx, bg, grad_a, 3 * (size_t)s->g.N, mem_kind, st);
+      build_coeff(ctx, s->g, op->co, da, dg, st);
+      build_near_lists(ctx, s->g, op->opts.eta_near, op->nl, st);
+      build_near_weights(ctx, s->g, op->co, op->nl, op->opts, false, st);
+      PMX_HIP(hipStreamSynchronize(st));
+      op->t_setup = now_seconds() - t0;
+    } catch (...) {
+      if (op->fmm) fmm_destroy(op->fmm);
+      delete op;
+      throw;
+    }
+    *out = op;
+  });
+}
+
+void pmx_operator_destroy(pmx_operator* op) {
+  if (!op) return;
+  if (op->fmm) fmm_destroy(op->fmm);
+  delete op;
+}
+
+pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* out) {
+  return guarded([&] {
+    PMX_REQUIRE(op && out, PMX_ERR_INVALID, "null handle");
+    std::memset(out, 0, sizeof(*out));
+    out->n_nodes = op->s->g.N;
+    out->n_patches = op->s->g.M;
+    out->q = op->s->g.q;
+    out->near_pairs = op->nl.nnz;
+    uint64_t b = op->co.a.bytes() + op->co.gs.bytes() + op->co.tgt.bytes() + op->co.tg.bytes() +
+                 op->co.tgt32.bytes() + op->co.w_over_a.bytes() + op->nl.ptr.bytes() + op->nl.patch.bytes() +
+                 op->nl.target.bytes() + op->nl.C.bytes() + op->nl.D.bytes() + op->part.bytes() +
+                 op->qt64.bytes() + op->qt32.bytes() + op->phi.bytes();
+    if (op->fmm) {
+      fmm_stats(op->fmm, out);
+      b += fmm_bytes(op->fmm);
+    }
+    out->device_bytes = b;
+  });
+}
+
+pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, int mem_kind,
+                     void* stream) {
+  return guarded([&] {
+    PMX_REQUIRE(op && sigma && y, PMX_ERR_INVALID, "null argument");
+    PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    PMX_HIP(hipSetDevice(op->s->ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    Ctx* ctx = &op->s->ctx->c;
+    const size_t n = (size_t)n_rhs * op->s->g.N;
+    DBuf<double> bin, bout;
+    const double* ds = stage_in(ctx, bin, sigma, n, mem_kind, st);
+    double* dy = y;
+    if (mem_kind == PMX_MEM_HOST) {
+      bout.alloc(ctx, n);
+      dy = bout.p;
+    }
+    apply_device(op, precision, n_rhs, ds, dy, st);
+    if (mem_kind == PMX_MEM_HOST) {
+      PMX_HIP(hipMemcpyAsync(y, dy, n * sizeof(double), hipMemcpyDeviceToHost, st));
+      PMX_HIP(hipStreamSynchronize(st));
+    }
+  });
+}
+
+pmx_status pmx_solve(pmx_operator* op, const pmx_options* opts, int n_rhs, const double* f, double* sigma,
+                     int sigma_in_is_guess, double* u, int mem_kind, void* stream, pmx_info* info) {
+  pmx_status conv = PMX_OK;
+  pmx_status st_ = guarded([&] {
+    PMX_REQUIRE(op && f && sigma, PMX_ERR_INVALID, "null argument");
+    PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    PMX_HIP(hipSetDevice(op->s->ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    pmx_options o = opts ? *opts : op->opts;
+    check_opts(o);
+    Ctx* ctx = &op->s->ctx->c;
+    const size_t n = (size_t)n_rhs * op->s->g.N;
+    const double t0 = now_seconds();
+    DBuf<double> bf, bs, bu;
+    const double* df = stage_in(ctx, bf, f, n, mem_kind, st);
+    double* dsig = sigma;
+    double* du = u;
+    if (mem_kind == PMX_MEM_HOST) {
+      bs.alloc(ctx, n);
+      dsig = bs.p;
+      if (sigma_in_is_guess) PMX_HIP(hipMemcpyAsync(dsig, sigma, n * sizeof(double), hipMemcpyHostToDevice, st));
+      if (u) {
+        bu.alloc(ctx, n);
+        du = bu.p;
+      }
+    }
+    std::vector<double> removed;
+    SolveResult r = solve_device(op, o, n_rhs, df, dsig, sigma_in_is_guess != 0, st, removed);
+    if (u) represent_device(op, n_rhs, dsig, du, st);
+    if (mem_kind == PMX_MEM_HOST) {
+      PMX_HIP(hipMemcpyAsync(sigma, dsig, n * sizeof(double), hipMemcpyDeviceToHost, st));
+      if (u) PMX_HIP(hipMemcpyAsync(u, du, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    PMX_HIP(hipStreamSynchronize(st));
+    const double t1 = now_seconds();
+    if (info) {
+      for (int k = 0; k < n_rhs; ++k) {
+        info[k].iters_total = r.iters[k];
+        info[k].ir_steps = r.ir_steps;
+        info[k].applies_fp64 = r.applies64;
+        info[k].applies_low = r.applies_low;
+        info[k].rel_residual = r.relres[k];
+        info[k].removed_mean = removed[k];
+        info[k].t_setup = op->t_setup;
+        info[k].t_solve = t1 - t0;
+      }
+    }
+    if (!r.converged) conv = PMX_ERR_NOT_CONVERGED;
+  });
+  if (st_ == PMX_OK && conv != PMX_OK) set_last_error("iteration limit reached before the tolerance");
+  return st_ != PMX_OK ? st_ : conv;
+}
+
+pmx_status pmx_represent(pmx_operator* op, int n_rhs, const double* sigma, double* u, int mem_kind, void* stream) {
+  return guarded([&] {
+    PMX_REQUIRE(op && sigma && u, PMX_ERR_INVALID, "null argument");
+    PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    PMX_HIP(hipSetDevice(op->s->ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    Ctx* ctx = &op->s->ctx->c;
+    const size_t n = (size_t)n_rhs * op->s->g.N;
+    DBuf<double> bin, bout;
+    const double* ds = stage_in(ctx, bin, sigma, n, mem_kind, st);
+    double* du = u;
+    if (mem_kind == PMX_MEM_HOST) {
+      bout.alloc(ctx, n);
+      du = bout.p;
+    }
+    represent_device(op, n_rhs, ds, du, st);
+    if (mem_kind == PMX_MEM_HOST) PMX_HIP(hipMemcpyAsync(u, du, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    PMX_HIP(hipStreamSynchronize(st));
+  });
+}
+
+pmx_status pmx_operator_export_geometry(pmx_operator* op, double* n, double* H, double* w, double* grad_s_a) {
+  return guarded([&] {
+    PMX_REQUIRE(op, PMX_ERR_INVALID, "null handle");
+    PMX_HIP(hipSetDevice(op->s->ctx->c.device));
+    const int64_t N = op->s->g.N;
+    std::vector<double> tmp(3 * N);
+    auto aos = [&](const double* src, double* dst) {
+      PMX_HIP(hipMemcpy(tmp.data(), src, 3 * N * sizeof(double), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) dst[3 * i + c] = tmp[c * N + i];
+    };
+    if (n) aos(op->s->g.n.p, n);
+    if (grad_s_a) aos(op->co.gs.p, grad_s_a);
+    if (H) PMX_HIP(hipMemcpy(H, op->s->g.H.p, N * sizeof(double), hipMemcpyDeviceToHost));
+    if (w) PMX_HIP(hipMemcpy(w, op->s->g.w.p, N * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+pmx_status pmx_operator_export_near(pmx_operator* op, int64_t* ptr, int32_t* patch, double* C, double* D) {
+  return guarded([&] {
+    PMX_REQUIRE(op, PMX_ERR_INVALID, "null handle");
+    PMX_HIP(hipSetDevice(op->s->ctx->c.device));
+    const int64_t N = op->s->g.N, nnz = op->nl.nnz;
+    const int q2 = op->s->g.q * op->s->g.q;
+    if (ptr) PMX_HIP(hipMemcpy(ptr, op->nl.ptr.p, (N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (patch) PMX_HIP(hipMemcpy(patch, op->nl.patch.p, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (C) PMX_HIP(hipMemcpy(C, op->nl.C.p, (size_t)nnz * q2 * sizeof(double), hipMemcpyDeviceToHost));
+    if (D) {
+      if (!op->nl.have_D) build_near_weights(&op->s->ctx->c, op->s->g, op->co, op->nl, op->opts, true, nullptr);
+      PMX_HIP(hipMemcpy(D, op->nl.D.p, (size_t)nnz * q2 * sizeof(double), hipMemcpyDeviceToHost));
+    }
+  });
+}
+
+}  // extern "C"

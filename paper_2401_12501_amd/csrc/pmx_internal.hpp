@@ -1,0 +1,214 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pmx.h"
+
+namespace pmx {
+
+// ----------------------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  pmx_status code;
+  Error(pmx_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define PMX_HIP(call)                                                                           \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      throw ::pmx::Error(e_ == hipErrorOutOfMemory ? PMX_ERR_OOM : PMX_ERR_DEVICE,              \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+#define PMX_REQUIRE(cond, code, msg) \
+  do {                               \
+    if (!(cond)) throw ::pmx::Error((code), (msg)); \
+  } while (0)
+
+// ----------------------------------------------------------------------------- device buffers
+// Owning device allocation; the context tracks bytes against its HBM budget.
+struct Ctx;
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  Ctx* ctx = nullptr;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { swap(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    swap(o);
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void swap(DBuf& o) {
+    std::swap(p, o.p);
+    std::swap(n, o.n);
+    std::swap(ctx, o.ctx);
+  }
+  void alloc(Ctx* c, size_t count);
+  void release();
+  size_t bytes() const { return n * sizeof(T); }
+  T* get() const { return p; }
+};
+
+struct Ctx {
+  int device = 0;
+  uint64_t budget = 0;   // 0 = unbounded
+  uint64_t in_use = 0;
+  int n_cu = 256;
+  int n_xcd = 8;
+  void reserve(uint64_t bytes) {
+    if (budget && in_use + bytes > budget)
+      throw Error(PMX_ERR_TOO_LARGE, "device footprint exceeds the context's HBM budget");
+    in_use += bytes;
+  }
+  void unreserve(uint64_t bytes) { in_use -= bytes < in_use ? bytes : in_use; }
+};
+
+template <class T>
+void DBuf<T>::alloc(Ctx* c, size_t count) {
+  release();
+  if (count == 0) return;
+  c->reserve(count * sizeof(T));
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) {
+    c->unreserve(count * sizeof(T));
+    p = nullptr;
+    throw Error(PMX_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  n = count;
+  ctx = c;
+}
+
+template <class T>
+void DBuf<T>::release() {
+  if (p) {
+    (void)hipFree(p);
+    if (ctx) ctx->unreserve(n * sizeof(T));
+  }
+  p = nullptr;
+  n = 0;
+}
+
+// ----------------------------------------------------------------------------- data on the device
+// Node-wise geometry in structure-of-arrays layout.  Target factors of the
+// factored c = 0 remainder:
+//   R(x_i, x_j) = (1/a_j) [ g_i . r / r^2 + A_i (n_i.r)^2 / r^4 - B_i (n_i.r) / r^2 ],
+//   A_i = a_i / pi, B_i = a_i H_i / pi, g_i = grad_G a_i / (2 pi), r = x_i - x_j.
+struct Geometry {
+  int64_t N = 0, M = 0;
+  int q = 0;
+  DBuf<double> x;       // 3N  (x | y | z)
+  DBuf<double> n;       // 3N
+  DBuf<double> J, w, H; // N each
+  DBuf<double> corner;  // M * 12  (4 corner images)
+  DBuf<double> cent;    // M * 4   (centroid xyz, radius)
+  DBuf<double> xu_p, xv_p;  // patch-local copies of x_u, x_v (3N each) for the local rules
+  DBuf<double> tnodes;  // q Gauss-Legendre nodes
+  DBuf<double> tweights;
+  double area = 0.0;
+};
+
+struct Coeff {
+  DBuf<double> a;       // N
+  DBuf<double> gs;      // 3N surface gradient
+  DBuf<double> tgt;     // 8N: x y z nx ny nz A B | (g stored below)
+  DBuf<double> tg;      // 3N: g = grad_G a / (2 pi)
+  DBuf<float> tgt32;    // 11N: x y z nx ny nz A B gx gy gz (FP32)
+  DBuf<double> w_over_a;  // N
+};
+
+struct NearLists {
+  int64_t nnz = 0;
+  DBuf<int64_t> ptr;        // N + 1
+  DBuf<int32_t> patch;      // nnz
+  DBuf<int32_t> target;     // nnz (pair -> target node)
+  DBuf<double> C;           // nnz * q*q (remainder)
+  DBuf<double> D;           // nnz * q*q (parametrix), built on demand
+  bool have_D = false;
+};
+
+struct FMM;  // fmm.hip
+
+}  // namespace pmx
+
+struct pmx_ctx {
+  pmx::Ctx c;
+};
+
+struct pmx_surface {
+  pmx_ctx* ctx = nullptr;
+  pmx::Geometry g;
+};
+
+struct pmx_operator {
+  pmx_surface* s = nullptr;
+  pmx_options opts{};
+  pmx::Coeff co;
+  pmx::NearLists nl;
+  pmx::FMM* fmm = nullptr;
+  double t_setup = 0.0;
+  // scratch reused across applies
+  pmx::DBuf<double> part;      // far-field partial sums
+  pmx::DBuf<double> qt64;      // w sigma / a (FP64)
+  pmx::DBuf<float> qt32;       // same in FP32
+  pmx::DBuf<double> ssum_part; // partial sums of w sigma
+  pmx::DBuf<double> ssum;      // s_r = sum_j w_j sigma_rj
+  pmx::DBuf<double> phi;       // far field result (FP64 accumulate of FMM output)
+  pmx::DBuf<double> io_a, io_b;  // staging for host arrays
+};
+
+namespace pmx {
+
+// geometry.hip
+void build_geometry(Ctx* ctx, Geometry& g, const double* x, const double* xu, const double* xv, const double* xuu,
+                    const double* xuv, const double* xvv, hipStream_t st);
+void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const double* grad_a, hipStream_t st);
+void build_near_lists(Ctx* ctx, const Geometry& g, double eta, NearLists& nl, hipStream_t st);
+// nearweights.hip
+void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists& nl, const pmx_options& o,
+                        bool parametrix, hipStream_t st);
+// direct.hip
+void far_direct(pmx_operator* op, bool fp64, int n_rhs, hipStream_t st);   // fills op->part + chunk count
+int far_direct_chunks(const pmx_operator* op, bool fp64);
+void far_direct_log(pmx_operator* op, int n_rhs, hipStream_t st);          // representation far field (FP64)
+// nearapply.hip
+void source_prep(pmx_operator* op, const double* sigma, int n_rhs, bool need32, hipStream_t st);
+void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, int n_part, bool use_phi,
+                  bool parametrix, hipStream_t st);
+void weighted_mean_remove(pmx_operator* op, double* u, int n_rhs, hipStream_t st);
+// apply.cpp
+void apply_device(pmx_operator* op, int precision, int n_rhs, const double* sigma_d, double* y_d, hipStream_t st);
+void represent_device(pmx_operator* op, int n_rhs, const double* sigma_d, double* u_d, hipStream_t st);
+// krylov.hip
+struct SolveResult {
+  std::vector<int> iters;
+  std::vector<double> relres;
+  int ir_steps = 0, applies64 = 0, applies_low = 0;
+  bool converged = true;
+};
+SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, const double* f_d, double* sigma_d,
+                         bool warm, hipStream_t st, std::vector<double>& removed_mean);
+// fmm.hip
+void fmm_build(pmx_operator* op, hipStream_t st);
+void fmm_destroy(FMM* f);
+void fmm_far(pmx_operator* op, int n_rhs, hipStream_t st);   // writes op->phi (FP64, n_rhs * N)
+void fmm_stats(const FMM* f, pmx_operator_stats* s);
+uint64_t fmm_bytes(const FMM* f);
+
+double now_seconds();
+void gauss_legendre_host(int n, double* t, double* w);
+void lagrange_host(int q, const double* t, double s, double* out);
+
+}  // namespace pmx

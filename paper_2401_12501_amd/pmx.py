@@ -1,0 +1,282 @@
+"""ctypes binding of libpmx.so (the C ABI declared in include/pmx.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+The module-level functions carry the C names; ``Context``, ``Surface`` and
+``Operator`` are small owning wrappers.  Host arrays are numpy float64; device
+arrays are torch CUDA tensors (their memory and the current stream are handed
+to the library as plain pointers).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmx.so")
+
+PMX_OK, PMX_PENDING = 0, 1
+PMX_ERR_INVALID, PMX_ERR_OOM, PMX_ERR_TOO_LARGE, PMX_ERR_NOT_CONVERGED = -1, -2, -3, -4
+PMX_ERR_ORIENTATION, PMX_ERR_DEVICE, PMX_ERR_CANCELLED = -5, -6, -7
+PMX_MEM_HOST, PMX_MEM_DEVICE = 0, 1
+PMX_PREC_FP64_DIRECT, PMX_PREC_MIXED_FMM, PMX_PREC_FP32_DIRECT = 0, 1, 2
+
+_ERRNAMES = {-1: "INVALID", -2: "OOM", -3: "TOO_LARGE", -4: "NOT_CONVERGED", -5: "ORIENTATION", -6: "DEVICE",
+             -7: "CANCELLED"}
+
+
+class PmxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pmx error {code} ({_ERRNAMES.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class pmx_options(C.Structure):
+    _fields_ = [("eta_near", C.c_double), ("n_gl", C.c_int), ("fmm_order", C.c_int), ("fmm_leaf", C.c_int),
+                ("gmres_tol", C.c_double), ("gmres_restart", C.c_int), ("max_iter", C.c_int),
+                ("ir_tol", C.c_double), ("inner_tol", C.c_double), ("max_ir", C.c_int), ("precision", C.c_int)]
+
+
+class pmx_info(C.Structure):
+    _fields_ = [("iters_total", C.c_int), ("ir_steps", C.c_int), ("applies_fp64", C.c_int),
+                ("applies_low", C.c_int), ("rel_residual", C.c_double), ("removed_mean", C.c_double),
+                ("t_setup", C.c_double), ("t_solve", C.c_double)]
+
+
+class pmx_operator_stats(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_patches", C.c_int64), ("q", C.c_int32), ("fmm_levels", C.c_int32),
+                ("near_pairs", C.c_int64), ("fmm_boxes", C.c_int64), ("fmm_m2l_pairs", C.c_int64),
+                ("fmm_p2p_pairs", C.c_int64), ("device_bytes", C.c_uint64)]
+
+
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_SIGS = {
+    "pmx_ctx_create": (C.c_int32, [C.c_int, C.c_uint64, C.POINTER(_vp)]),
+    "pmx_ctx_destroy": (None, [_vp]),
+    "pmx_last_error": (C.c_char_p, []),
+    "pmx_default_options": (None, [C.POINTER(pmx_options)]),
+    "pmx_surface_create": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp,
+                                        C.POINTER(_vp)]),
+    "pmx_surface_destroy": (None, [_vp]),
+    "pmx_operator_create": (C.c_int32, [_vp, _vp, _vp, C.POINTER(pmx_options), C.c_int, _vp, C.POINTER(_vp)]),
+    "pmx_operator_destroy": (None, [_vp]),
+    "pmx_operator_get_stats": (C.c_int32, [_vp, C.POINTER(pmx_operator_stats)]),
+    "pmx_apply": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_int, _vp]),
+    "pmx_solve": (C.c_int32, [_vp, C.POINTER(pmx_options), C.c_int, _vp, _vp, C.c_int, _vp, C.c_int, _vp,
+                              C.POINTER(pmx_info)]),
+    "pmx_represent": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.c_int, _vp]),
+    "pmx_operator_export_geometry": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "pmx_operator_export_near": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpmx.so (raises if it has not been built: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2401_12501_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code not in (PMX_OK, PMX_PENDING):
+        raise PmxError(code, lib().pmx_last_error().decode())
+    return code
+
+
+# ------------------------------------------------------------------ C names
+def pmx_default_options() -> pmx_options:
+    o = pmx_options()
+    lib().pmx_default_options(C.byref(o))
+    return o
+
+
+def pmx_last_error() -> str:
+    return lib().pmx_last_error().decode()
+
+
+def pmx_ctx_create(device: int = 0, hbm_budget_bytes: int = 0):
+    h = _vp()
+    _check(lib().pmx_ctx_create(device, hbm_budget_bytes, C.byref(h)))
+    return h
+
+
+def pmx_ctx_destroy(h):
+    lib().pmx_ctx_destroy(h)
+
+
+# ------------------------------------------------------------------ array marshalling
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _stream_ptr(arrs):
+    import torch
+    for a in arrs:
+        if _is_torch(a) and a.is_cuda:
+            return torch.cuda.current_stream(a.device).cuda_stream
+    return None
+
+
+def _host(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _marshal(*arrs):
+    """(pointers, mem_kind, stream, keepalive) for numpy (host) or torch CUDA (device) arrays."""
+    dev = [_is_torch(a) and a.is_cuda for a in arrs if a is not None]
+    if any(dev) and not all(dev):
+        raise ValueError("mix of host and device arrays")
+    kind = PMX_MEM_DEVICE if dev and all(dev) else PMX_MEM_HOST
+    ptrs, keep = [], []
+    for a in arrs:
+        if a is None:
+            ptrs.append(None)
+            continue
+        if kind == PMX_MEM_DEVICE:
+            import torch
+            if a.dtype != torch.float64 or not a.is_contiguous():
+                raise ValueError("device arrays must be contiguous float64 tensors")
+            ptrs.append(a.data_ptr())
+        else:
+            if _is_torch(a):
+                a = a.detach().cpu().numpy()
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            keep.append(a)
+            ptrs.append(a.ctypes.data)
+    stream = _stream_ptr(arrs) if kind == PMX_MEM_DEVICE else None
+    return ptrs, kind, stream, keep
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.h = pmx_ctx_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.h:
+            pmx_ctx_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+
+class Surface:
+    """pmx_surface_create: node positions and parameter derivatives (N x 3 each)."""
+
+    def __init__(self, ctx: Context, n_patches: int, q: int, x, xu, xv, xuu, xuv, xvv):
+        self.ctx = ctx
+        self.n_patches, self.q = n_patches, q
+        self.N = n_patches * q * q
+        ptrs, kind, stream, keep = _marshal(x, xu, xv, xuu, xuv, xvv)
+        h = _vp()
+        _check(lib().pmx_surface_create(ctx.h, n_patches, q, *ptrs, kind, stream, C.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_inputs(cls, ctx, s):
+        return cls(ctx, s.n_patches, s.q, s.x, s.xu, s.xv, s.xuu, s.xuv, s.xvv)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pmx_surface_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+
+class Operator:
+    """pmx_operator_create and the calls on an operator."""
+
+    def __init__(self, surface: Surface, a, grad_a, opts: pmx_options | None = None):
+        self.surface = surface
+        self.N = surface.N
+        self.q = surface.q
+        self.opts = opts if opts is not None else pmx_default_options()
+        ptrs, kind, stream, keep = _marshal(a, grad_a)
+        h = _vp()
+        _check(lib().pmx_operator_create(surface.h, ptrs[0], ptrs[1], C.byref(self.opts), kind, stream, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pmx_operator_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def stats(self) -> pmx_operator_stats:
+        s = pmx_operator_stats()
+        _check(lib().pmx_operator_get_stats(self.h, C.byref(s)))
+        return s
+
+    def _rhs(self, a):
+        n_rhs = (a.numel() if _is_torch(a) else np.size(a)) // self.N
+        if n_rhs * self.N != (a.numel() if _is_torch(a) else np.size(a)):
+            raise ValueError("array size is not a multiple of N")
+        return n_rhs
+
+    def apply(self, sigma, precision: int = PMX_PREC_FP64_DIRECT, out=None):
+        """y = A sigma; sigma is (n_rhs, N) (host numpy or device tensor)."""
+        n_rhs = self._rhs(sigma)
+        if out is None:
+            out = np.empty((n_rhs, self.N)) if not _is_torch(sigma) else sigma.new_empty(sigma.shape)
+        ptrs, kind, stream, keep = _marshal(sigma, out)
+        _check(lib().pmx_apply(self.h, precision, n_rhs, ptrs[0], ptrs[1], kind, stream))
+        return out
+
+    def solve(self, f, opts: pmx_options | None = None, sigma0=None, want_u: bool = False, check: bool = True):
+        """(sigma, u or None, [pmx_info]) for f of shape (n_rhs, N)."""
+        n_rhs = self._rhs(f)
+        torch_in = _is_torch(f)
+        mk = (lambda: f.new_empty(f.shape)) if torch_in else (lambda: np.empty((n_rhs, self.N)))
+        sigma = mk() if sigma0 is None else (sigma0.clone() if torch_in else np.array(sigma0, dtype=np.float64))
+        u = mk() if want_u else None
+        ptrs, kind, stream, keep = _marshal(f, sigma, u)
+        if kind == PMX_MEM_HOST:        # outputs must be the arrays the library writes
+            sigma, u = keep[1], (keep[2] if want_u else None)
+        infos = (pmx_info * n_rhs)()
+        code = lib().pmx_solve(self.h, C.byref(opts) if opts is not None else None, n_rhs, ptrs[0], ptrs[1],
+                               1 if sigma0 is not None else 0, ptrs[2], kind, stream, infos)
+        if check:
+            _check(code)
+        return sigma, u, list(infos)
+
+    def represent(self, sigma, out=None):
+        n_rhs = self._rhs(sigma)
+        if out is None:
+            out = np.empty((n_rhs, self.N)) if not _is_torch(sigma) else sigma.new_empty(sigma.shape)
+        ptrs, kind, stream, keep = _marshal(sigma, out)
+        _check(lib().pmx_represent(self.h, n_rhs, ptrs[0], ptrs[1], kind, stream))
+        return out
+
+    def export_geometry(self):
+        N = self.N
+        n, H, w, gs = np.empty((N, 3)), np.empty(N), np.empty(N), np.empty((N, 3))
+        _check(lib().pmx_operator_export_geometry(self.h, n.ctypes.data, H.ctypes.data, w.ctypes.data,
+                                                   gs.ctypes.data))
+        return {"n": n, "H": H, "w": w, "gs": gs}
+
+    def export_near(self, with_D: bool = False):
+        st = self.stats()
+        N, nnz, q2 = self.N, st.near_pairs, self.q * self.q
+        ptr = np.empty(N + 1, dtype=np.int64)
+        patch = np.empty(nnz, dtype=np.int32)
+        Cb = np.empty((nnz, q2))
+        Db = np.empty((nnz, q2)) if with_D else None
+        _check(lib().pmx_operator_export_near(self.h, ptr.ctypes.data, patch.ctypes.data, Cb.ctypes.data,
+                                               Db.ctypes.data if with_D else None))
+        return ptr, patch, Cb, Db
