@@ -160,6 +160,27 @@ PMX_API pmx_status pmx_solve(pmx_operator* op, const pmx_options* opts, int n_rh
  * correction blocks on first use.  Errors: INVALID, OOM, DEVICE. */
 PMX_API pmx_status pmx_represent(pmx_operator* op, int n_rhs, const double* sigma, double* u, int mem_kind, void* stream);
 
+/* Per-phase device timing of the apply (HIP events recorded on the call's stream around
+ * each phase while enabled).  Phases: PMX_PHASE_*.  pmx_profile_read synchronizes the
+ * recorded events and returns, per phase, the summed milliseconds and the number of
+ * timed launches; reading resets the accumulators.  Errors: INVALID, DEVICE. */
+enum {
+  PMX_PHASE_PREP = 0,        /* qt = w sigma / a and sum w sigma */
+  PMX_PHASE_DIRECT64 = 1,    /* FP64 direct far-field kernel */
+  PMX_PHASE_DIRECT32 = 2,    /* FP32 direct far-field kernel */
+  PMX_PHASE_NEAR = 3,        /* near correction + combine */
+  PMX_PHASE_FMM_P2M = 4,
+  PMX_PHASE_FMM_M2M = 5,
+  PMX_PHASE_FMM_M2L = 6,
+  PMX_PHASE_FMM_L2L = 7,
+  PMX_PHASE_FMM_L2P = 8,
+  PMX_PHASE_FMM_P2P = 9,
+  PMX_PHASE_LOG = 10,        /* representation far field */
+  PMX_N_PHASES = 11
+};
+PMX_API pmx_status pmx_profile_enable(pmx_operator* op, int enable);
+PMX_API pmx_status pmx_profile_read(pmx_operator* op, double* ms /* PMX_N_PHASES */, int64_t* count /* PMX_N_PHASES */);
+
 /* Copy-out of operator internals to host arrays (any pointer may be NULL):
  * node normal n (N x 3), mean curvature H (N), weight w (N), surface gradient of a (N x 3). */
 PMX_API pmx_status pmx_operator_export_geometry(pmx_operator* op, double* n, double* H, double* w, double* grad_s_a);

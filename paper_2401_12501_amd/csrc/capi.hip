@@ -19,22 +19,38 @@ double now_seconds() {
 void apply_device(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, hipStream_t st) {
   switch (precision) {
     case PMX_PREC_FP64_DIRECT: {
+      int t = op->prof.begin(PMX_PHASE_PREP, st);
       source_prep(op, sigma, n_rhs, false, st);
+      op->prof.end(t, st);
+      t = op->prof.begin(PMX_PHASE_DIRECT64, st);
       far_direct(op, true, n_rhs, st);
+      op->prof.end(t, st);
+      t = op->prof.begin(PMX_PHASE_NEAR, st);
       near_combine(op, sigma, y, n_rhs, far_direct_chunks(op, true), false, false, st);
+      op->prof.end(t, st);
       break;
     }
     case PMX_PREC_FP32_DIRECT: {
+      int t = op->prof.begin(PMX_PHASE_PREP, st);
       source_prep(op, sigma, n_rhs, true, st);
+      op->prof.end(t, st);
+      t = op->prof.begin(PMX_PHASE_DIRECT32, st);
       far_direct(op, false, n_rhs, st);
+      op->prof.end(t, st);
+      t = op->prof.begin(PMX_PHASE_NEAR, st);
       near_combine(op, sigma, y, n_rhs, far_direct_chunks(op, false), false, false, st);
+      op->prof.end(t, st);
       break;
     }
     case PMX_PREC_MIXED_FMM: {
       if (!op->fmm) fmm_build(op, st);
+      int t = op->prof.begin(PMX_PHASE_PREP, st);
       source_prep(op, sigma, n_rhs, true, st);
-      fmm_far(op, n_rhs, st);
+      op->prof.end(t, st);
+      fmm_far(op, n_rhs, st);   // records its own phases
+      t = op->prof.begin(PMX_PHASE_NEAR, st);
       near_combine(op, sigma, y, n_rhs, 1, true, false, st);
+      op->prof.end(t, st);
       break;
     }
     default:
@@ -45,7 +61,9 @@ void apply_device(pmx_operator* op, int precision, int n_rhs, const double* sigm
 void represent_device(pmx_operator* op, int n_rhs, const double* sigma, double* u, hipStream_t st) {
   if (!op->nl.have_D) build_near_weights(&op->s->ctx->c, op->s->g, op->co, op->nl, op->opts, true, st);
   source_prep(op, sigma, n_rhs, false, st);
+  const int t = op->prof.begin(PMX_PHASE_LOG, st);
   far_direct_log(op, n_rhs, st);
+  op->prof.end(t, st);
   near_combine(op, sigma, u, n_rhs, far_direct_chunks(op, true), false, true, st);
   weighted_mean_remove(op, u, n_rhs, st);
 }
@@ -355,6 +373,33 @@ pmx_status pmx_operator_export_near(pmx_operator* op, int64_t* ptr, int32_t* pat
       if (!op->nl.have_D) build_near_weights(&op->s->ctx->c, op->s->g, op->co, op->nl, op->opts, true, nullptr);
       PMX_HIP(hipMemcpy(D, op->nl.D.p, (size_t)nnz * q2 * sizeof(double), hipMemcpyDeviceToHost));
     }
+  });
+}
+
+pmx_status pmx_profile_enable(pmx_operator* op, int enable) {
+  return guarded([&] {
+    PMX_REQUIRE(op, PMX_ERR_INVALID, "null handle");
+    op->prof.on = enable != 0;
+  });
+}
+
+pmx_status pmx_profile_read(pmx_operator* op, double* ms, int64_t* count) {
+  return guarded([&] {
+    PMX_REQUIRE(op && ms && count, PMX_ERR_INVALID, "null argument");
+    for (int k = 0; k < PMX_N_PHASES; ++k) {
+      ms[k] = 0.0;
+      count[k] = 0;
+    }
+    for (auto& r : op->prof.recs) {
+      PMX_HIP(hipEventSynchronize(r.b));
+      float t = 0.0f;
+      PMX_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      ms[r.phase] += t;
+      count[r.phase] += 1;
+      op->prof.pool.push_back(r.a);
+      op->prof.pool.push_back(r.b);
+    }
+    op->prof.recs.clear();
   });
 }
 

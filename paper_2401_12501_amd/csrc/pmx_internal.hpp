@@ -141,6 +141,44 @@ struct NearLists {
 
 struct FMM;  // fmm.hip
 
+// Optional per-phase timing with HIP events on the launch stream.
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    PMX_HIP(hipEventCreate(&e));
+    return e;
+  }
+  int begin(int phase, hipStream_t st) {
+    if (!on) return -1;
+    Rec r{phase, get(), get()};
+    PMX_HIP(hipEventRecord(r.a, st));
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int id, hipStream_t st) {
+    if (id >= 0) PMX_HIP(hipEventRecord(recs[id].b, st));
+  }
+  ~Profiler() {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace pmx
 
 struct pmx_ctx {
@@ -167,6 +205,7 @@ struct pmx_operator {
   pmx::DBuf<double> ssum;      // s_r = sum_j w_j sigma_rj
   pmx::DBuf<double> phi;       // far field result (FP64 accumulate of FMM output)
   pmx::DBuf<double> io_a, io_b;  // staging for host arrays
+  pmx::Profiler prof;
 };
 
 namespace pmx {

@@ -69,7 +69,12 @@ _SIGS = {
     "pmx_represent": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.c_int, _vp]),
     "pmx_operator_export_geometry": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
     "pmx_operator_export_near": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "pmx_profile_enable": (C.c_int32, [_vp, C.c_int]),
+    "pmx_profile_read": (C.c_int32, [_vp, _vp, _vp]),
 }
+
+PHASES = ["prep", "direct64", "direct32", "near", "fmm_p2m", "fmm_m2m", "fmm_m2l", "fmm_l2l", "fmm_l2p",
+          "fmm_p2p", "log"]
 
 _lib = None
 
@@ -262,6 +267,16 @@ class Operator:
         ptrs, kind, stream, keep = _marshal(sigma, out)
         _check(lib().pmx_represent(self.h, n_rhs, ptrs[0], ptrs[1], kind, stream))
         return out
+
+    def profile(self, enable: bool = True):
+        _check(lib().pmx_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{phase: (total ms, launches)} since the last read."""
+        ms = np.zeros(len(PHASES))
+        cnt = np.zeros(len(PHASES), dtype=np.int64)
+        _check(lib().pmx_profile_read(self.h, ms.ctypes.data, cnt.ctypes.data))
+        return {p: (float(m), int(c)) for p, m, c in zip(PHASES, ms, cnt)}
 
     def export_geometry(self):
         N = self.N
