@@ -1,11 +1,692 @@
-// Interpolation FMM far field (FP32): placeholder until the tree code lands.
+// Chebyshev-interpolation FMM for the far field of the remainder operator (FP32).
+//
+// The far-field sum of the c = 0 remainder (eq:explicit_remainder) at target i is
+//   phi_i = A_i n_i^T F2_i n_i - B_i n_i . F1_i + g_i . F1_i,
+//   F1_i = sum_j qt_j r/r^2,  F2_i = sum_j qt_j r r^T / r^4,  r = x_i - x_j,
+// so it needs the nine translation-invariant, homogeneous kernel components
+// k(r) = [r/r^2 (3), r r^T/r^4 (6)] applied to the scalar strengths qt = w sigma / a.
+// The paper accelerates the apply with an interpolative-decomposition FMM
+// (Section 6.2); this file instead uses a tensor Chebyshev interpolation FMM on
+// an octree of uniform depth:
+//   P2M  leaf multipoles  W_m = sum_j S(t_m, x_j) qt_j  (p^3 Chebyshev nodes per box)
+//   M2M  parent W from the children's W by interpolation
+//   M2L  L_c,l += sum_m k_c(x_l - y_m) W_m for every well-separated pair (FP32 MFMA)
+//   L2L  children's L from the parent's L by interpolation
+//   L2P  F_c(x_i) = sum_l S(t_l, x_i) L_c,l, then the target contraction above
+//   P2P  direct sum over adjacent leaves (the U-list), j = i excluded.
+// S is the tensor product of 1-D Chebyshev interpolation weights
+//   S1(t_k, x) = 1/p + (2/p) sum_{n=1}^{p-1} T_n(t_k) T_n(x).
+// M2L uses translation invariance and homogeneity: for boxes of half-width h at
+// offset o (in box widths), x_l - y_m = h (2 o + t_l - t_m), and the kernel of a
+// unit box is generated on the fly in registers as the MFMA A operand, then
+// scaled by h^-1 (F1) or h^-2 (F2).  Work is grouped by (level, offset) so one
+// generated kernel block serves up to 64 target boxes.
+#include <algorithm>
+#include <type_traits>
+#include <cmath>
+#include <unordered_map>
+
 #include "pmx_internal.hpp"
 
 namespace pmx {
-struct FMM {};
-void fmm_build(pmx_operator*, hipStream_t) { throw Error(PMX_ERR_INVALID, "FMM far field is not available yet"); }
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int kMaxLevel = 20;
+constexpr int kItemCols = 64;   // target boxes per M2L work item
+}  // namespace
+
+struct FMM {
+  int p = 6, p3 = 216, L = 0;
+  double c0[3] = {0, 0, 0}, h0 = 1.0;
+  std::vector<int64_t> lev_off;      // first global box index of each level, size L + 2
+  int64_t n_boxes = 0, n_leaves = 0;
+  int64_t m2l_pairs = 0, p2p_pairs = 0;
+  int64_t n_items = 0;
+  DBuf<float> center;        // 3 * n_boxes
+  DBuf<int32_t> child_begin; // n_boxes (global index of first child, levels < L)
+  DBuf<int32_t> child_end;
+  DBuf<int32_t> parent;      // n_boxes
+  DBuf<int32_t> octant;      // n_boxes (child position bits x | y << 1 | z << 2)
+  DBuf<int32_t> leaf_start;  // n_leaves + 1 (sorted point ranges)
+  DBuf<int32_t> perm;        // N: sorted position -> node
+  DBuf<float> pts;           // 11 N sorted: x y z nx ny nz A B gx gy gz
+  DBuf<float> qs;            // N sorted strengths (one rhs at a time)
+  DBuf<int32_t> u_ptr, u_idx;        // U-list of leaves (leaf-local indices)
+  DBuf<int32_t> p2p_leaf, p2p_first; // P2P waves: leaf and first target offset
+  int64_t n_p2p_waves = 0;
+  DBuf<int32_t> m2l_t, m2l_s;        // global box indices of the pairs, sorted by (level, offset)
+  DBuf<int4> items;                  // (first pair, count, level, offset code)
+  DBuf<float> tab;                   // t_k (p), M1[2][p][p], node table (3 p^3)
+  DBuf<float> W, Lc;                 // multipoles n_boxes*p3, locals n_boxes*9*p3
+  DBuf<float> phis;                  // N sorted P2P sums
+};
+
+// ----------------------------------------------------------------------------- device helpers
+template <int P>
+__device__ __forceinline__ void cheb_weights(const float* __restrict__ t, float x, float* out) {
+  // out[k] = S1(t_k, x) = 1/P + (2/P) sum_{n>=1} T_n(t_k) T_n(x)
+  float Tx[P];
+  Tx[0] = 1.0f;
+  if (P > 1) Tx[1] = x;
+#pragma unroll
+  for (int n = 2; n < P; ++n) Tx[n] = 2.0f * x * Tx[n - 1] - Tx[n - 2];
+  constexpr float ip = 1.0f / (float)P;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const float tk = t[k];
+    float a0 = 1.0f, a1 = tk, s = 0.0f;
+#pragma unroll
+    for (int n = 1; n < P; ++n) {
+      s = fmaf(a1, Tx[n], s);
+      const float a2 = 2.0f * tk * a1 - a0;
+      a0 = a1;
+      a1 = a2;
+    }
+    out[k] = ip + 2.0f * ip * s;
+  }
+}
+
+// qs[k] = qt[perm[k]]
+__global__ void k_permute(int64_t N, const int32_t* __restrict__ perm, const float* __restrict__ q,
+                          float* __restrict__ qs) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) qs[k] = q[perm[k]];
+}
+
+// P2M: one block per leaf; thread m accumulates over the leaf's sources.
+template <int P>
+__global__ void __launch_bounds__(256) k_p2m(int64_t leaf_off, float h, const float* __restrict__ tab,
+                                             const float* __restrict__ center, const int32_t* __restrict__ leaf_start,
+                                             const float* __restrict__ pts, int64_t N, const float* __restrict__ qs,
+                                             float* __restrict__ W) {
+  constexpr int p = P, p3 = P * P * P;
+  __shared__ float sw[256][3 * P + 1];
+  const int leaf = blockIdx.x;
+  const int64_t box = leaf_off + leaf;
+  const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
+  const float cx = center[3 * box], cy = center[3 * box + 1], cz = center[3 * box + 2];
+  const float ih = 1.0f / h;
+  const int m = threadIdx.x;
+  const int m1 = m / (p * p), m2 = (m / p) % p, m3 = m % p;
+  float acc = 0.0f;
+  for (int j0 = s0; j0 < s1; j0 += 256) {
+    const int j = j0 + threadIdx.x;
+    __syncthreads();
+    if (j < s1) {
+      cheb_weights<P>(tab, (pts[j] - cx) * ih, &sw[threadIdx.x][0]);
+      cheb_weights<P>(tab, (pts[N + j] - cy) * ih, &sw[threadIdx.x][p]);
+      cheb_weights<P>(tab, (pts[2 * N + j] - cz) * ih, &sw[threadIdx.x][2 * p]);
+      sw[threadIdx.x][3 * p] = qs[j];
+    }
+    __syncthreads();
+    const int lim = min(256, s1 - j0);
+    if (m < p3)
+      for (int t = 0; t < lim; ++t) acc = fmaf(sw[t][m1] * sw[t][p + m2] * sw[t][2 * p + m3], sw[t][3 * p], acc);
+  }
+  if (m < p3) W[box * p3 + m] = acc;
+}
+
+// M2M: parent W from its children (one block per parent box of one level).
+template <int P>
+__global__ void __launch_bounds__(256) k_m2m(int64_t lev_first, const float* __restrict__ tab,
+                                             const int32_t* __restrict__ child_begin,
+                                             const int32_t* __restrict__ child_end,
+                                             const int32_t* __restrict__ octant, float* __restrict__ W) {
+  constexpr int p = P, p3 = P * P * P;
+  const int64_t Pb = lev_first + blockIdx.x;
+  const float* M1 = tab + p;   // M1[b][k][k'] = S1(t_k, (b ? 0.5 : -0.5) + t_k' / 2)
+  const int m = threadIdx.x;
+  if (m >= p3) return;
+  const int m1 = m / (p * p), m2 = (m / p) % p, m3 = m % p;
+  float acc = 0.0f;
+  for (int c = child_begin[Pb]; c < child_end[Pb]; ++c) {
+    const int o = octant[c];
+    const float* Ax = M1 + (o & 1) * p * p + m1 * p;
+    const float* Ay = M1 + ((o >> 1) & 1) * p * p + m2 * p;
+    const float* Az = M1 + ((o >> 2) & 1) * p * p + m3 * p;
+    const float* Wc = W + (int64_t)c * p3;
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b) {
+        const float xy = Ax[a] * Ay[b];
+        const float* w = Wc + (a * p + b) * p;
+        for (int d = 0; d < p; ++d) acc = fmaf(xy * Az[d], w[d], acc);
+      }
+  }
+  W[Pb * p3 + m] = acc;
+}
+
+// L2L: child L += interpolation of the parent's L (one block per child box of one level).
+template <int P>
+__global__ void __launch_bounds__(256) k_l2l(int64_t lev_first, const float* __restrict__ tab,
+                                             const int32_t* __restrict__ parent, const int32_t* __restrict__ octant,
+                                             float* __restrict__ Lc) {
+  constexpr int p = P, p3 = P * P * P;
+  const int64_t C = lev_first + blockIdx.x;
+  const int64_t Pb = parent[C];
+  const int o = octant[C];
+  const float* M1 = tab + p;
+  const float* Mx = M1 + (o & 1) * p * p;
+  const float* My = M1 + ((o >> 1) & 1) * p * p;
+  const float* Mz = M1 + ((o >> 2) & 1) * p * p;
+  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) {
+    const int c = e / p3, l = e - c * p3;
+    const int l1 = l / (p * p), l2 = (l / p) % p, l3 = l % p;
+    const float* LP = Lc + (Pb * 9 + c) * p3;
+    float acc = 0.0f;
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b) {
+        const float xy = Mx[a * p + l1] * My[b * p + l2];
+        const float* lp = LP + (a * p + b) * p;
+        for (int d = 0; d < p; ++d) acc = fmaf(xy * Mz[d * p + l3], lp[d], acc);
+      }
+    Lc[(C * 9 + c) * p3 + l] += acc;
+  }
+}
+
+// M2L on MFMA: one wave per (item, component, 16-row tile).  The A operand is the
+// unit-box kernel k_c(2 o + t_l - t_m) generated in registers; B gathers the
+// multipoles of the item's source boxes; D is scaled and added into the targets'
+// locals (several offsets update one target box, hence atomics).
+template <int P>
+__global__ void __launch_bounds__(256) k_m2l(const float* __restrict__ tab,
+                                             const int4* __restrict__ items, const int32_t* __restrict__ pt,
+                                             const int32_t* __restrict__ ps, const float* __restrict__ W,
+                                             float* __restrict__ Lc, double h0) {
+  constexpr int p = P, p3 = P * P * P;
+  const int4 it = items[blockIdx.x];
+  const int comp = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rt = blockIdx.z * 4 + wave;
+  const int n_rt = (p3 + 15) / 16;
+  if (rt >= n_rt) return;
+  const int level = it.z;
+  const int code = it.w;
+  const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
+              oz = 2.0f * (float)(code % 7 - 3);
+  const float* nodes = tab + p + 2 * p * p;   // 3 * p3: node coordinates t_l
+  const int row = rt * 16 + (lane & 15);
+  const bool row_ok = row < p3;
+  const float tlx = row_ok ? nodes[3 * row] : 0.0f;
+  const float tly = row_ok ? nodes[3 * row + 1] : 0.0f;
+  const float tlz = row_ok ? nodes[3 * row + 2] : 0.0f;
+  const int kq = lane >> 4;     // k index within a step of 4
+  const int col = lane & 15;
+  // source box of each column block for this lane
+  int64_t src[4];
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    const int pj = jb * 16 + col;
+    src[jb] = pj < it.y ? (int64_t)ps[it.x + pj] * p3 : -1;
+  }
+  floatx4 acc[4];
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int a_ = comp < 3 ? comp : (comp == 3 || comp == 4 || comp == 5 ? 0 : (comp == 6 || comp == 7 ? 1 : 2));
+  const int b_ = comp < 3 ? comp : (comp == 3 ? 0 : (comp == 4 ? 1 : (comp == 5 ? 2 : (comp == 6 ? 1 : (comp == 7 ? 2 : 2)))));
+  for (int k0 = 0; k0 < p3; k0 += 4) {
+    const int m = k0 + kq;
+    float a = 0.0f;
+    if (row_ok && m < p3) {
+      const float rx = ox + tlx - nodes[3 * m], ry = oy + tly - nodes[3 * m + 1], rz = oz + tlz - nodes[3 * m + 2];
+      const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+      const float va = a_ == 0 ? rx : (a_ == 1 ? ry : rz);
+      const float vb = b_ == 0 ? rx : (b_ == 1 ? ry : rz);
+      a = comp < 3 ? va * inv : va * vb * inv * inv;
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const float b = (src[jb] >= 0 && m < p3) ? W[src[jb] + m] : 0.0f;
+      acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[jb], 0, 0, 0);
+    }
+  }
+  const double h = h0 / (double)(1 << level);
+  const float scale = comp < 3 ? (float)(1.0 / h) : (float)(1.0 / (h * h));
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    const int pj = jb * 16 + col;
+    if (pj >= it.y) continue;
+    const int64_t T = pt[it.x + pj];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int l = rt * 16 + 4 * (lane >> 4) + r;
+      if (l < p3) atomicAdd(&Lc[(T * 9 + comp) * p3 + l], scale * acc[jb][r]);
+    }
+  }
+}
+
+// P2P over the U-list: one wave per (leaf, 64 targets); sources are wave-uniform.
+__global__ void __launch_bounds__(64) k_p2p(int64_t N, const int32_t* __restrict__ wleaf,
+                                            const int32_t* __restrict__ wfirst, const int32_t* __restrict__ leaf_start,
+                                            const int32_t* __restrict__ u_ptr, const int32_t* __restrict__ u_idx,
+                                            const float* __restrict__ pts, const float* __restrict__ qs,
+                                            float* __restrict__ phis) {
+  const int leaf = wleaf[blockIdx.x];
+  const int k0 = leaf_start[leaf] + wfirst[blockIdx.x];
+  const int kend = leaf_start[leaf + 1];
+  const int k = k0 + threadIdx.x;
+  const int kk = k < kend ? k : kend - 1;
+  const float xi = pts[kk], yi = pts[N + kk], zi = pts[2 * N + kk];
+  const float nx = pts[3 * N + kk], ny = pts[4 * N + kk], nz = pts[5 * N + kk];
+  const float A = pts[6 * N + kk], B = pts[7 * N + kk];
+  const float gx = pts[8 * N + kk], gy = pts[9 * N + kk], gz = pts[10 * N + kk];
+  float acc = 0.0f;
+  for (int u = u_ptr[leaf]; u < u_ptr[leaf + 1]; ++u) {
+    const int S = u_idx[u];
+    const int j1 = leaf_start[S + 1];
+    for (int j = leaf_start[S]; j < j1; ++j) {
+      const float dx = xi - pts[j], dy = yi - pts[N + j], dz = zi - pts[2 * N + j];
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-30f)));
+      const float inv = __builtin_amdgcn_rcpf(r2);
+      const float nr = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
+      const float gr = fmaf(gx, dx, fmaf(gy, dy, gz * dz));
+      const float s = nr * inv;
+      acc = fmaf(qs[j], fmaf(s, fmaf(A, s, -B), gr * inv), acc);
+    }
+  }
+  if (k < kend) phis[k] = acc;
+}
+
+// L2P + contraction + P2P sum; writes phi (FP64, node order).
+template <int P>
+__global__ void __launch_bounds__(256) k_l2p(int64_t leaf_off, float h, const float* __restrict__ tab,
+                                             const float* __restrict__ center, const int32_t* __restrict__ leaf_start,
+                                             const float* __restrict__ pts, int64_t N, const float* __restrict__ Lc,
+                                             const float* __restrict__ phis, const int32_t* __restrict__ perm,
+                                             double* __restrict__ phi) {
+  constexpr int p = P, p3 = P * P * P;
+  __shared__ float sL[9 * p3];
+  const int leaf = blockIdx.x;
+  const int64_t box = leaf_off + leaf;
+  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) sL[e] = Lc[box * 9 * p3 + e];
+  __syncthreads();
+  const float cx = center[3 * box], cy = center[3 * box + 1], cz = center[3 * box + 2];
+  const float ih = 1.0f / h;
+  const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
+  for (int k = s0 + threadIdx.x; k < s1; k += blockDim.x) {
+    float sx[P], sy[P], sz[P];
+    cheb_weights<P>(tab, (pts[k] - cx) * ih, sx);
+    cheb_weights<P>(tab, (pts[N + k] - cy) * ih, sy);
+    cheb_weights<P>(tab, (pts[2 * N + k] - cz) * ih, sz);
+    float F[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < p; ++a)
+#pragma unroll
+      for (int b = 0; b < p; ++b) {
+        const float xy = sx[a] * sy[b];
+#pragma unroll
+        for (int d = 0; d < p; ++d) {
+          const float s = xy * sz[d];
+          const int l = (a * p + b) * p + d;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) F[c] = fmaf(s, sL[c * p3 + l], F[c]);
+        }
+      }
+    const float nx = pts[3 * N + k], ny = pts[4 * N + k], nz = pts[5 * N + k];
+    const float A = pts[6 * N + k], B = pts[7 * N + k];
+    const float gx = pts[8 * N + k], gy = pts[9 * N + k], gz = pts[10 * N + k];
+    // F1 = F[0..2]; F2 = (xx, xy, xz, yy, yz, zz) = F[3..8]
+    const float nF2n = nx * nx * F[3] + 2.f * nx * ny * F[4] + 2.f * nx * nz * F[5] + ny * ny * F[6] +
+                       2.f * ny * nz * F[7] + nz * nz * F[8];
+    const float nF1 = nx * F[0] + ny * F[1] + nz * F[2];
+    const float gF1 = gx * F[0] + gy * F[1] + gz * F[2];
+    phi[perm[k]] = (double)(A * nF2n - B * nF1 + gF1) + (double)phis[k];
+  }
+}
+
+__global__ void k_gather_pts(int64_t N, const int32_t* __restrict__ perm, const float* __restrict__ t32,
+                             float* __restrict__ pts) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int64_t i = perm[k];
+  for (int c = 0; c < 11; ++c) pts[c * N + k] = t32[c * N + i];
+}
+
+// ----------------------------------------------------------------------------- host: tree build
+namespace {
+
+inline uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) { return spread3(x) | spread3(y) << 1 | spread3(z) << 2; }
+inline uint64_t compact3(uint64_t v) {
+  v &= 0x1249249249249249ULL;
+  v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ULL;
+  v = (v ^ (v >> 4)) & 0x100f00f00f00f00fULL;
+  v = (v ^ (v >> 8)) & 0x1f0000ff0000ffULL;
+  v = (v ^ (v >> 16)) & 0x1f00000000ffffULL;
+  v = (v ^ (v >> 32)) & 0x1fffff;
+  return v;
+}
+constexpr int kBits = 21;
+
+double cheb_w_host(int p, double tk, double x) {
+  double s = 0.0, a0 = 1.0, a1 = tk, b0 = 1.0, b1 = x;
+  for (int n = 1; n < p; ++n) {
+    s += a1 * b1;
+    const double a2 = 2 * tk * a1 - a0, b2 = 2 * x * b1 - b0;
+    a0 = a1; a1 = a2; b0 = b1; b1 = b2;
+  }
+  return 1.0 / p + 2.0 / p * s;
+}
+
+}  // namespace
+
+void fmm_build(pmx_operator* op, hipStream_t st) {
+  Ctx* ctx = &op->s->ctx->c;
+  const int64_t N = op->s->g.N;
+  auto* F = new FMM;
+  try {
+    F->p = op->opts.fmm_order;
+    F->p3 = F->p * F->p * F->p;
+    PMX_REQUIRE(F->p >= 3 && F->p <= 6, PMX_ERR_INVALID, "fmm_order must be in [3, 6]");
+    const int p = F->p, p3 = F->p3;
+    std::vector<double> X(3 * N);
+    PMX_HIP(hipMemcpyAsync(X.data(), op->s->g.x.p, 3 * N * sizeof(double), hipMemcpyDeviceToHost, st));
+    PMX_HIP(hipStreamSynchronize(st));
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = *std::min_element(X.begin() + c * N, X.begin() + (c + 1) * N);
+      hi[c] = *std::max_element(X.begin() + c * N, X.begin() + (c + 1) * N);
+      F->c0[c] = 0.5 * (lo[c] + hi[c]);
+    }
+    F->h0 = 0.5 * std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]}) * (1.0 + 1e-6) + 1e-12;
+    const double cells = (double)(1u << kBits);
+    std::vector<std::pair<uint64_t, int32_t>> key(N);
+    for (int64_t i = 0; i < N; ++i) {
+      uint64_t ic[3];
+      for (int c = 0; c < 3; ++c) {
+        double s = (X[c * N + i] - (F->c0[c] - F->h0)) / (2.0 * F->h0) * cells;
+        int64_t v = (int64_t)std::floor(s);
+        v = std::min<int64_t>(std::max<int64_t>(v, 0), (1 << kBits) - 1);
+        ic[c] = (uint64_t)v;
+      }
+      key[i] = {morton(ic[0], ic[1], ic[2]), (int32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    // leaf level: smallest level >= 2 whose mean occupancy is at most fmm_leaf
+    int L = 2;
+    for (; L < kMaxLevel; ++L) {
+      const int sh = 3 * (kBits - L);
+      int64_t nb = 0;
+      uint64_t prev = ~0ULL;
+      for (auto& kv : key) {
+        const uint64_t b = kv.first >> sh;
+        if (b != prev) { ++nb; prev = b; }
+      }
+      if ((double)N / (double)nb <= (double)op->opts.fmm_leaf) break;
+    }
+    F->L = L;
+    // boxes per level (sorted Morton prefixes)
+    std::vector<std::vector<uint64_t>> bkey(L + 1);
+    for (int l = 0; l <= L; ++l) {
+      const int sh = 3 * (kBits - l);
+      uint64_t prev = ~0ULL;
+      for (auto& kv : key) {
+        const uint64_t b = kv.first >> sh;
+        if (b != prev) { bkey[l].push_back(b); prev = b; }
+      }
+    }
+    F->lev_off.assign(L + 2, 0);
+    for (int l = 0; l <= L; ++l) F->lev_off[l + 1] = F->lev_off[l] + (int64_t)bkey[l].size();
+    F->n_boxes = F->lev_off[L + 1];
+    F->n_leaves = (int64_t)bkey[L].size();
+    std::vector<std::unordered_map<uint64_t, int32_t>> idx(L + 1);
+    for (int l = 0; l <= L; ++l) {
+      idx[l].reserve(bkey[l].size() * 2);
+      for (size_t b = 0; b < bkey[l].size(); ++b) idx[l][bkey[l][b]] = (int32_t)b;
+    }
+    std::vector<float> center(3 * F->n_boxes);
+    std::vector<int32_t> cb(F->n_boxes, 0), ce(F->n_boxes, 0), par(F->n_boxes, -1), oct(F->n_boxes, 0);
+    for (int l = 0; l <= L; ++l) {
+      const double h = F->h0 / (double)(1 << l);
+      for (size_t b = 0; b < bkey[l].size(); ++b) {
+        const uint64_t k = bkey[l][b];
+        const int64_t g = F->lev_off[l] + b;
+        const uint64_t ix = compact3(k), iy = compact3(k >> 1), iz = compact3(k >> 2);
+        center[3 * g] = (float)(F->c0[0] - F->h0 + (2.0 * ix + 1.0) * h);
+        center[3 * g + 1] = (float)(F->c0[1] - F->h0 + (2.0 * iy + 1.0) * h);
+        center[3 * g + 2] = (float)(F->c0[2] - F->h0 + (2.0 * iz + 1.0) * h);
+        if (l > 0) {
+          par[g] = (int32_t)(F->lev_off[l - 1] + idx[l - 1][k >> 3]);
+          oct[g] = (int32_t)(k & 7);
+        }
+      }
+    }
+    for (int l = 1; l <= L; ++l)
+      for (size_t b = 0; b < bkey[l].size(); ++b) {
+        const int64_t g = F->lev_off[l] + b;
+        const int32_t P = par[g];
+        if (ce[P] == 0) cb[P] = (int32_t)g;
+        ce[P] = (int32_t)g + 1;
+      }
+    // leaf point ranges and permutation
+    std::vector<int32_t> lstart(F->n_leaves + 1, 0), perm(N);
+    {
+      const int sh = 3 * (kBits - L);
+      int64_t b = -1;
+      uint64_t prev = ~0ULL;
+      for (int64_t k = 0; k < N; ++k) {
+        perm[k] = key[k].second;
+        const uint64_t bk = key[k].first >> sh;
+        if (bk != prev) { ++b; lstart[b] = (int32_t)k; prev = bk; }
+      }
+      lstart[F->n_leaves] = (int32_t)N;
+    }
+    auto coords = [](uint64_t k, int64_t c[3]) {
+      c[0] = (int64_t)compact3(k); c[1] = (int64_t)compact3(k >> 1); c[2] = (int64_t)compact3(k >> 2);
+    };
+    auto lookup = [&](int l, int64_t x, int64_t y, int64_t z) -> int32_t {
+      const int64_t n = (int64_t)1 << l;
+      if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) return -1;
+      auto it = idx[l].find(morton((uint64_t)x, (uint64_t)y, (uint64_t)z));
+      return it == idx[l].end() ? -1 : it->second;
+    };
+    // U-list of leaves
+    std::vector<int32_t> uptr(F->n_leaves + 1, 0), uidx;
+    int64_t p2p = 0;
+    for (int64_t b = 0; b < F->n_leaves; ++b) {
+      int64_t c[3];
+      coords(bkey[L][b], c);
+      const int64_t nt = lstart[b + 1] - lstart[b];
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            const int32_t s = lookup(L, c[0] + dx, c[1] + dy, c[2] + dz);
+            if (s >= 0) {
+              uidx.push_back(s);
+              p2p += nt * (int64_t)(lstart[s + 1] - lstart[s]);
+            }
+          }
+      uptr[b + 1] = (int32_t)uidx.size();
+    }
+    F->p2p_pairs = p2p;
+    // V-lists grouped by (level, offset)
+    struct Pair { int32_t lev, code, t, s; };
+    std::vector<Pair> pairs;
+    for (int l = 2; l <= L; ++l) {
+      for (size_t b = 0; b < bkey[l].size(); ++b) {
+        int64_t cB[3];
+        coords(bkey[l][b], cB);
+        const int64_t pc[3] = {cB[0] >> 1, cB[1] >> 1, cB[2] >> 1};
+        for (int dx = -1; dx <= 1; ++dx)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+              const int32_t nb = lookup(l - 1, pc[0] + dx, pc[1] + dy, pc[2] + dz);
+              if (nb < 0) continue;
+              const int64_t gN = F->lev_off[l - 1] + nb;
+              for (int32_t c = cb[gN]; c < ce[gN]; ++c) {
+                int64_t cC[3];
+                coords(bkey[l][c - F->lev_off[l]], cC);
+                const int64_t ox = cC[0] - cB[0], oy = cC[1] - cB[1], oz = cC[2] - cB[2];
+                if (std::max({std::llabs(ox), std::llabs(oy), std::llabs(oz)}) < 2) continue;
+                // offset of the target relative to the source, in box widths
+                const int32_t code = (int32_t)((-ox + 3) * 49 + (-oy + 3) * 7 + (-oz + 3));
+                pairs.push_back({l, code, (int32_t)(F->lev_off[l] + b), c});
+              }
+            }
+      }
+    }
+    std::sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) {
+      if (a.lev != b.lev) return a.lev < b.lev;
+      if (a.code != b.code) return a.code < b.code;
+      return a.t < b.t;
+    });
+    F->m2l_pairs = (int64_t)pairs.size();
+    std::vector<int32_t> pt(pairs.size()), ps(pairs.size());
+    std::vector<int4> items;
+    for (size_t k = 0; k < pairs.size();) {
+      size_t e = k;
+      while (e < pairs.size() && pairs[e].lev == pairs[k].lev && pairs[e].code == pairs[k].code) ++e;
+      for (size_t s = k; s < e; s += kItemCols)
+        items.push_back(make_int4((int)s, (int)std::min<size_t>(kItemCols, e - s), pairs[k].lev, pairs[k].code));
+      k = e;
+    }
+    for (size_t k = 0; k < pairs.size(); ++k) { pt[k] = pairs[k].t; ps[k] = pairs[k].s; }
+    F->n_items = (int64_t)items.size();
+    // P2P waves
+    std::vector<int32_t> wl, wf;
+    for (int64_t b = 0; b < F->n_leaves; ++b)
+      for (int32_t f = 0; f < lstart[b + 1] - lstart[b]; f += 64) { wl.push_back((int32_t)b); wf.push_back(f); }
+    F->n_p2p_waves = (int64_t)wl.size();
+    // tables: t_k, M1[2][p][p] (M1[b][k][k'] = S1(t_k, +-0.5 + t_k'/2)), node coordinates
+    std::vector<float> tab(p + 2 * p * p + 3 * p3);
+    std::vector<double> t(p);
+    for (int k = 0; k < p; ++k) t[k] = std::cos((2.0 * k + 1.0) * M_PI / (2.0 * p));
+    for (int k = 0; k < p; ++k) tab[k] = (float)t[k];
+    for (int b = 0; b < 2; ++b)
+      for (int k = 0; k < p; ++k)
+        for (int kk = 0; kk < p; ++kk)
+          tab[p + b * p * p + k * p + kk] = (float)cheb_w_host(p, t[k], (b ? 0.5 : -0.5) + 0.5 * t[kk]);
+    for (int l = 0; l < p3; ++l) {
+      tab[p + 2 * p * p + 3 * l] = (float)t[l / (p * p)];
+      tab[p + 2 * p * p + 3 * l + 1] = (float)t[(l / p) % p];
+      tab[p + 2 * p * p + 3 * l + 2] = (float)t[l % p];
+    }
+    // device copies
+    auto up = [&](auto& buf, const auto& v) {
+      using T = typename std::decay_t<decltype(v)>::value_type;
+      buf.alloc(ctx, v.size());
+      if (!v.empty()) PMX_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    };
+    up(F->center, center);
+    up(F->child_begin, cb);
+    up(F->child_end, ce);
+    up(F->parent, par);
+    up(F->octant, oct);
+    up(F->leaf_start, lstart);
+    up(F->perm, perm);
+    up(F->u_ptr, uptr);
+    up(F->u_idx, uidx);
+    up(F->m2l_t, pt);
+    up(F->m2l_s, ps);
+    up(F->items, items);
+    up(F->p2p_leaf, wl);
+    up(F->p2p_first, wf);
+    up(F->tab, tab);
+    F->pts.alloc(ctx, 11 * (size_t)N);
+    F->qs.alloc(ctx, N);
+    F->phis.alloc(ctx, N);
+    F->W.alloc(ctx, (size_t)F->n_boxes * p3);
+    F->Lc.alloc(ctx, (size_t)F->n_boxes * 9 * p3);
+    hipLaunchKernelGGL(k_gather_pts, dim3((N + 255) / 256), dim3(256), 0, st, N, F->perm.p, op->co.tgt32.p,
+                       F->pts.p);
+    PMX_HIP(hipGetLastError());
+    PMX_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    delete F;
+    throw;
+  }
+  op->fmm = F;
+}
+
 void fmm_destroy(FMM* f) { delete f; }
-void fmm_far(pmx_operator*, int, hipStream_t) { throw Error(PMX_ERR_INVALID, "FMM far field is not available yet"); }
-void fmm_stats(const FMM*, pmx_operator_stats*) {}
-uint64_t fmm_bytes(const FMM*) { return 0; }
+
+template <int P>
+static void fmm_far_p(pmx_operator* op, int n_rhs, hipStream_t st) {
+  FMM* F = op->fmm;
+  const int64_t N = op->s->g.N;
+  constexpr int p3 = P * P * P;
+  const int L = F->L;
+  const int64_t leaf_off = F->lev_off[L];
+  const float hL = (float)(F->h0 / (double)(1 << L));
+  for (int r = 0; r < n_rhs; ++r) {
+    int t = op->prof.begin(PMX_PHASE_FMM_P2M, st);
+    hipLaunchKernelGGL(k_permute, dim3((N + 255) / 256), dim3(256), 0, st, N, F->perm.p,
+                       op->qt32.p + (int64_t)r * N, F->qs.p);
+    PMX_HIP(hipMemsetAsync(F->Lc.p, 0, F->Lc.bytes(), st));
+    hipLaunchKernelGGL(k_p2m<P>, dim3(F->n_leaves), dim3(256), 0, st, leaf_off, hL, F->tab.p, F->center.p,
+                       F->leaf_start.p, F->pts.p, N, F->qs.p, F->W.p);
+    PMX_HIP(hipGetLastError());
+    op->prof.end(t, st);
+    t = op->prof.begin(PMX_PHASE_FMM_M2M, st);
+    for (int l = L - 1; l >= 2; --l) {
+      const int64_t nb = F->lev_off[l + 1] - F->lev_off[l];
+      hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(256), 0, st, F->lev_off[l], F->tab.p, F->child_begin.p,
+                         F->child_end.p, F->octant.p, F->W.p);
+      PMX_HIP(hipGetLastError());
+    }
+    op->prof.end(t, st);
+    t = op->prof.begin(PMX_PHASE_FMM_M2L, st);
+    if (F->n_items > 0) {
+      constexpr int n_rt = (p3 + 15) / 16;
+      hipLaunchKernelGGL(k_m2l<P>, dim3(F->n_items, 9, (n_rt + 3) / 4), dim3(256), 0, st, F->tab.p, F->items.p,
+                         F->m2l_t.p, F->m2l_s.p, F->W.p, F->Lc.p, F->h0);
+      PMX_HIP(hipGetLastError());
+    }
+    op->prof.end(t, st);
+    t = op->prof.begin(PMX_PHASE_FMM_L2L, st);
+    for (int l = 3; l <= L; ++l) {
+      const int64_t nb = F->lev_off[l + 1] - F->lev_off[l];
+      hipLaunchKernelGGL(k_l2l<P>, dim3(nb), dim3(256), 0, st, F->lev_off[l], F->tab.p, F->parent.p,
+                         F->octant.p, F->Lc.p);
+      PMX_HIP(hipGetLastError());
+    }
+    op->prof.end(t, st);
+    t = op->prof.begin(PMX_PHASE_FMM_P2P, st);
+    hipLaunchKernelGGL(k_p2p, dim3(F->n_p2p_waves), dim3(64), 0, st, N, F->p2p_leaf.p, F->p2p_first.p,
+                       F->leaf_start.p, F->u_ptr.p, F->u_idx.p, F->pts.p, F->qs.p, F->phis.p);
+    PMX_HIP(hipGetLastError());
+    op->prof.end(t, st);
+    t = op->prof.begin(PMX_PHASE_FMM_L2P, st);
+    hipLaunchKernelGGL(k_l2p<P>, dim3(F->n_leaves), dim3(256), 0, st, leaf_off, hL, F->tab.p, F->center.p,
+                       F->leaf_start.p, F->pts.p, N, F->Lc.p, F->phis.p, F->perm.p, op->phi.p + (int64_t)r * N);
+    PMX_HIP(hipGetLastError());
+    op->prof.end(t, st);
+  }
+}
+
+void fmm_far(pmx_operator* op, int n_rhs, hipStream_t st) {
+  const int64_t N = op->s->g.N;
+  if (op->phi.n < (size_t)n_rhs * N) op->phi.alloc(&op->s->ctx->c, (size_t)n_rhs * N);
+  switch (op->fmm->p) {
+    case 3: fmm_far_p<3>(op, n_rhs, st); break;
+    case 4: fmm_far_p<4>(op, n_rhs, st); break;
+    case 5: fmm_far_p<5>(op, n_rhs, st); break;
+    case 6: fmm_far_p<6>(op, n_rhs, st); break;
+    default: throw Error(PMX_ERR_INVALID, "fmm_order must be in [3, 6]");
+  }
+}
+
+void fmm_stats(const FMM* f, pmx_operator_stats* s) {
+  s->fmm_levels = f->L;
+  s->fmm_boxes = f->n_boxes;
+  s->fmm_m2l_pairs = f->m2l_pairs;
+  s->fmm_p2p_pairs = f->p2p_pairs;
+}
+
+uint64_t fmm_bytes(const FMM* f) {
+  return f->center.bytes() + f->child_begin.bytes() + f->child_end.bytes() + f->parent.bytes() +
+         f->octant.bytes() + f->leaf_start.bytes() + f->perm.bytes() + f->pts.bytes() + f->qs.bytes() +
+         f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_leaf.bytes() + f->p2p_first.bytes() + f->m2l_t.bytes() +
+         f->m2l_s.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes();
+}
+
 }  // namespace pmx

@@ -163,6 +163,8 @@ GmresOut gmres(pmx_operator* op, int precision, int n_rhs, const double* b, doub
   res.iters.assign(n_rhs, 0);
   res.est.assign(n_rhs, 1.0);
 
+  // a zero initial guess is taken literally: x is cleared, not assumed clear
+  if (x_zero) PMX_HIP(hipMemsetAsync(x, 0, ldk * sizeof(double), st));
   std::vector<double> bnorm = norms(D, b, st);
   for (auto& v : bnorm)
     if (v == 0.0) v = 1.0;

@@ -1,0 +1,122 @@
+"""The interpolation-FMM far field and the mixed-precision solve against brute force.
+
+The FMM far field (FP32, M2L on MFMA) must agree with brute-force summation:
+the FP64 direct far field, which is itself pinned to the oracle, and the oracle's
+dense operator on small surfaces.  Its error must fall as the interpolation
+order grows.  The mixed solve (FP64 residuals, FMM inner solves) must reach the
+oracle's dense-LU solution within 1e-8.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2401_12501_amd.inputs import sphere_problem, ellipsoid_problem, random_density
+from oracle.operator import OracleOperator
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2401_12501_amd import pmx
+    return pmx.Context(0)
+
+
+def far_part(op, y, sig):
+    """The remainder part of an apply: y - sigma - sum_j w_j sigma_j."""
+    w = op.export_geometry()["w"]
+    return y - sig - (sig @ w)[:, None]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make(ctx, prob, order=6, leaf=128):
+    from paper_2401_12501_amd import pmx
+    o = pmx.pmx_default_options()
+    o.fmm_order = order
+    o.fmm_leaf = leaf
+    surf = pmx.Surface.from_inputs(ctx, prob.surface)
+    return surf, pmx.Operator(surf, prob.a, prob.grad_a, o)
+
+
+@pytest.mark.parametrize("k", [4, 8])
+def test_fmm_vs_direct_and_order(ctx, k):
+    """Ellipsoid with 96 (k=4, 9,600 nodes) or 384 (k=8, 38,400 nodes) patches:
+    FMM far field vs the FP64 direct far field, p = 4 and p = 6."""
+    from paper_2401_12501_amd import pmx
+    p = ellipsoid_problem(k=k, q=10)
+    sig = random_density(p.n, 2, seed=21).T.copy()        # (2, N)
+    errs = {}
+    for order in (4, 6):
+        surf, op = make(ctx, p, order=order, leaf=64)
+        y64 = op.apply(sig, pmx.PMX_PREC_FP64_DIRECT)
+        yf = op.apply(sig, pmx.PMX_PREC_MIXED_FMM)
+        st = op.stats()
+        ref = far_part(op, y64, sig)
+        errs[order] = rel(far_part(op, yf, sig), ref)
+        say(f"[fmm] N={p.n} p={order}: levels {st.fmm_levels}, boxes {st.fmm_boxes}, m2l pairs "
+            f"{st.fmm_m2l_pairs}, rel err of far field {errs[order]:.3e}")
+        assert st.fmm_m2l_pairs > 0
+        # apply is linear in sigma: the two right-hand sides computed together equal one at a time
+        y1 = op.apply(sig[1].copy(), pmx.PMX_PREC_MIXED_FMM)
+        assert rel(y1[0], yf[1]) < 1e-6
+    assert errs[6] < 1e-3          # p = 6 interpolation error; the mixed solve refines with FP64 residuals
+    assert errs[6] < errs[4] / 3
+
+
+def test_fmm_vs_oracle_sphere(ctx):
+    """Unit-sphere workload (1,536 nodes): mixed apply against the oracle's dense operator."""
+    from paper_2401_12501_amd import pmx
+    p = sphere_problem(k=2, q=8)
+    surf, op = make(ctx, p, leaf=32)
+    orc = OracleOperator.from_problem(p)
+    A = orc.dense_matrix()
+    sig = random_density(p.n, 1, seed=22)
+    ref = A @ sig
+    y = op.apply(np.ascontiguousarray(sig.T), pmx.PMX_PREC_MIXED_FMM).T
+    err = rel(y, ref)
+    st = op.stats()
+    say(f"[fmm] sphere: levels {st.fmm_levels}, m2l pairs {st.fmm_m2l_pairs}, apply rel err {err:.3e}")
+    assert st.fmm_m2l_pairs > 0 and err < 1e-4
+    # mixed solve against the oracle's dense LU: within 1e-8
+    o = pmx.pmx_default_options()
+    o.precision = pmx.PMX_PREC_MIXED_FMM
+    o.ir_tol = 1e-11
+    s, _, info = op.solve(np.ascontiguousarray(p.f.T), o)
+    s_ref = orc.solve(p.f, A)
+    serr = rel(s.T, s_ref)
+    say(f"[mixed solve] sphere: rel err {serr:.3e}, ir steps {info[0].ir_steps}, iters {info[0].iters_total}, "
+        f"res {info[0].rel_residual:.2e}")
+    assert serr < 1e-8 and info[0].ir_steps >= 1
+
+
+def test_mixed_solve_full_ellipsoid(ctx):
+    """Ellipsoid workload at full size (153,600 nodes): the mixed path reaches a 1e-8
+    relative residual of the FP64 operator and agrees with the FP64-path solution."""
+    from paper_2401_12501_amd import pmx
+    p = ellipsoid_problem()
+    surf, op = make(ctx, p)
+    f = np.ascontiguousarray(p.f.T)
+    o = pmx.pmx_default_options()
+    o.precision = pmx.PMX_PREC_MIXED_FMM
+    o.ir_tol = 1e-9
+    sm, _, im = op.solve(f, o)
+    o.precision = pmx.PMX_PREC_FP64_DIRECT
+    o.gmres_tol = 1e-11
+    s64, _, i64 = op.solve(f, o)
+    err = rel(sm, s64)
+    st = op.stats()
+    say(f"[mixed solve] ellipsoid N={p.n}: levels {st.fmm_levels}, boxes {st.fmm_boxes}, m2l {st.fmm_m2l_pairs}, "
+        f"p2p pairs {st.fmm_p2p_pairs}; mixed res {im[0].rel_residual:.2e} (ir {im[0].ir_steps}, "
+        f"inner iters {im[0].iters_total}, t {im[0].t_solve:.3f}s); fp64 res {i64[0].rel_residual:.2e} "
+        f"(iters {i64[0].iters_total}, t {i64[0].t_solve:.3f}s); diff {err:.2e}")
+    assert im[0].rel_residual <= 1e-9 and err <= 1e-8
