@@ -92,6 +92,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--fmm-leaf", type=int, default=0, help="FMM leaf occupancy target (0: library default)")
+    ap.add_argument("--fmm-order", type=int, default=0, help="FMM interpolation order (0: library default)")
+    ap.add_argument("--calib-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (a known-size kernel for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
@@ -102,13 +106,24 @@ def main():
     from paper_2401_12501_amd import pmx
     from paper_2401_12501_amd.inputs import ellipsoid_problem, random_density
 
+    if args.calib_mb:
+        src = torch.ones(args.calib_mb * 2 ** 18, device="cuda:0", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = ellipsoid_problem(k=args.k, q=10, n_rhs=args.n_rhs)
     N, n_rhs = prob.n, args.n_rhs
     log(f"[bench] workload {prob.name} N={N} n_rhs={n_rhs} path={args.path}")
     ctx = pmx.Context(0)
     surf = pmx.Surface.from_inputs(ctx, prob.surface)
     t0 = time.perf_counter()
-    op = pmx.Operator(surf, prob.a, prob.grad_a)
+    opts = pmx.pmx_default_options()
+    if args.fmm_leaf:
+        opts.fmm_leaf = args.fmm_leaf
+    if args.fmm_order:
+        opts.fmm_order = args.fmm_order
+    op = pmx.Operator(surf, prob.a, prob.grad_a, opts)
     t_setup = time.perf_counter() - t0
     prec = {"mixed": pmx.PMX_PREC_MIXED_FMM, "fp64": pmx.PMX_PREC_FP64_DIRECT}
     other = "fp64" if args.path == "mixed" else "mixed"
@@ -205,7 +220,7 @@ def main():
         "dtype": "f32+f64" if args.path == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": f"ellipsoid (1, 0.8, 0.6), {prob.surface.n_patches} patches x 10x10 "
                                f"Gauss-Legendre nodes, N={N}, a=exp(0.3 x1 x2)", "n_rhs": n_rhs,
-                   "path": args.path, "fmm_order": op.opts.fmm_order},
+                   "path": args.path, "fmm_order": op.opts.fmm_order, "fmm_leaf": op.opts.fmm_leaf},
         "roofline": roof,
         "other_path": ({"path": other, "gpts_per_s": round(N * n_rhs / other_s / 1e9, 4),
                         "ms_per_apply": round(other_s * 1e3, 4)} if other_s else None),

@@ -77,7 +77,7 @@ typedef struct pmx_options {
   double eta_near;     /* near criterion: within eta patch radii of the centroid (Section 6.1.2: 1.5) */
   int n_gl;            /* Gauss-Legendre order of the local rules (Section 6.1.1: 16) */
   int fmm_order;       /* Chebyshev points per box edge of the FMM (default 6) */
-  int fmm_leaf;        /* target points per FMM leaf box (default 128) */
+  int fmm_leaf;        /* mean points per FMM leaf box: the leaf level is the first with at most this (default 256) */
   double gmres_tol;    /* relative residual target of GMRES (FP64 path) */
   int gmres_restart;   /* Krylov space size before restart */
   int max_iter;        /* total GMRES iteration limit */
@@ -116,7 +116,7 @@ PMX_API pmx_status pmx_ctx_create(int device, uint64_t hbm_budget_bytes, pmx_ctx
 PMX_API void pmx_ctx_destroy(pmx_ctx* ctx);
 /* Message of the last error on the calling thread ("" if none). */
 PMX_API const char* pmx_last_error(void);
-/* Defaults: eta 1.5, n_gl 16, fmm_order 6, fmm_leaf 128, gmres_tol 1e-10, restart 60,
+/* Defaults: eta 1.5, n_gl 16, fmm_order 6, fmm_leaf 256, gmres_tol 1e-10, restart 60,
  * max_iter 400, ir_tol 1e-8, inner_tol 1e-4, max_ir 20, precision FP64_DIRECT. */
 PMX_API void pmx_default_options(pmx_options* opts);
 

@@ -124,7 +124,7 @@ void pmx_default_options(pmx_options* o) {
   o->eta_near = 1.5;
   o->n_gl = 16;
   o->fmm_order = 6;
-  o->fmm_leaf = 128;
+  o->fmm_leaf = 256;
   o->gmres_tol = 1e-10;
   o->gmres_restart = 60;
   o->max_iter = 400;

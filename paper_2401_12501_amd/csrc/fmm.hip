@@ -60,6 +60,8 @@ struct FMM {
   DBuf<int4> items;                  // (first pair, count, level, offset code)
   DBuf<float> tab;                   // t_k (p), M1[2][p][p], node table (3 p^3)
   DBuf<float> W, Lc;                 // multipoles n_boxes*p3, locals n_boxes*9*p3
+  DBuf<float> slots;                 // M2L output per pair (9*p3 each)
+  DBuf<int32_t> r_ptr, r_idx;        // per box of levels >= 2: its pairs (CSR, pair order)
   DBuf<float> phis;                  // N sorted P2P sums
 };
 
@@ -185,74 +187,112 @@ __global__ void __launch_bounds__(256) k_l2l(int64_t lev_first, const float* __r
   }
 }
 
-// M2L on MFMA: one wave per (item, component, 16-row tile).  The A operand is the
-// unit-box kernel k_c(2 o + t_l - t_m) generated in registers; B gathers the
-// multipoles of the item's source boxes; D is scaled and added into the targets'
-// locals (several offsets update one target box, hence atomics).
+// M2L on MFMA.  One workgroup per work item (up to 64 target boxes sharing a level
+// and an offset).  The item's source multipoles are staged in LDS once; each wave
+// takes 16-row tiles of the local expansion, generates the unit-box kernel for all
+// nine components of its (row, m) pair in registers as MFMA A operands, and keeps
+// 9 x 4 accumulator tiles (9 components x 64 target columns).  Each pair writes
+// its own output slot; k_m2l_reduce then sums a target's slots in a fixed order,
+// so no atomics are needed and the result does not depend on scheduling.
+constexpr int kM2LStride = 226;   // LDS row stride (== 2 mod 32: conflict-free B reads)
+
 template <int P>
-__global__ void __launch_bounds__(256) k_m2l(const float* __restrict__ tab,
-                                             const int4* __restrict__ items, const int32_t* __restrict__ pt,
-                                             const int32_t* __restrict__ ps, const float* __restrict__ W,
-                                             float* __restrict__ Lc, double h0) {
-  constexpr int p = P, p3 = P * P * P;
+__global__ void __launch_bounds__(512) k_m2l(const float* __restrict__ tab, const int4* __restrict__ items,
+                                             const int32_t* __restrict__ pt, const int32_t* __restrict__ ps,
+                                             const float* __restrict__ W, float* __restrict__ slots, double h0) {
+  constexpr int p3 = P * P * P;
+  static_assert(p3 <= kM2LStride, "multipole does not fit the LDS row");
+  constexpr int n_rt = (p3 + 15) / 16;
+  constexpr int n_waves = 8;
+  __shared__ float sB[kItemCols * kM2LStride];
+  __shared__ float4 sN[p3];
   const int4 it = items[blockIdx.x];
-  const int comp = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rt = blockIdx.z * 4 + wave;
-  const int n_rt = (p3 + 15) / 16;
-  if (rt >= n_rt) return;
-  const int level = it.z;
-  const int code = it.w;
+  const int ncol = it.y;
+  // stage B[m][j] = W[source box of column j][m] as sB[j][m]
+  for (int e = threadIdx.x; e < kItemCols * p3; e += blockDim.x) {
+    const int j = e / p3, m = e - j * p3;
+    sB[j * kM2LStride + m] = j < ncol ? W[(int64_t)ps[it.x + j] * p3 + m] : 0.0f;
+  }
+  for (int m = threadIdx.x; m < p3; m += blockDim.x) {
+    const float* nd = tab + P + 2 * P * P + 3 * m;
+    sN[m] = make_float4(nd[0], nd[1], nd[2], 0.0f);
+  }
+  __syncthreads();
+  const int level = it.z, code = it.w;
   const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
               oz = 2.0f * (float)(code % 7 - 3);
-  const float* nodes = tab + p + 2 * p * p;   // 3 * p3: node coordinates t_l
-  const int row = rt * 16 + (lane & 15);
-  const bool row_ok = row < p3;
-  const float tlx = row_ok ? nodes[3 * row] : 0.0f;
-  const float tly = row_ok ? nodes[3 * row + 1] : 0.0f;
-  const float tlz = row_ok ? nodes[3 * row + 2] : 0.0f;
-  const int kq = lane >> 4;     // k index within a step of 4
-  const int col = lane & 15;
-  // source box of each column block for this lane
-  int64_t src[4];
-#pragma unroll
-  for (int jb = 0; jb < 4; ++jb) {
-    const int pj = jb * 16 + col;
-    src[jb] = pj < it.y ? (int64_t)ps[it.x + pj] * p3 : -1;
-  }
-  floatx4 acc[4];
-#pragma unroll
-  for (int jb = 0; jb < 4; ++jb) acc[jb] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int a_ = comp < 3 ? comp : (comp == 3 || comp == 4 || comp == 5 ? 0 : (comp == 6 || comp == 7 ? 1 : 2));
-  const int b_ = comp < 3 ? comp : (comp == 3 ? 0 : (comp == 4 ? 1 : (comp == 5 ? 2 : (comp == 6 ? 1 : (comp == 7 ? 2 : 2)))));
-  for (int k0 = 0; k0 < p3; k0 += 4) {
-    const int m = k0 + kq;
-    float a = 0.0f;
-    if (row_ok && m < p3) {
-      const float rx = ox + tlx - nodes[3 * m], ry = oy + tly - nodes[3 * m + 1], rz = oz + tlz - nodes[3 * m + 2];
-      const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
-      const float va = a_ == 0 ? rx : (a_ == 1 ? ry : rz);
-      const float vb = b_ == 0 ? rx : (b_ == 1 ? ry : rz);
-      a = comp < 3 ? va * inv : va * vb * inv * inv;
-    }
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      const float b = (src[jb] >= 0 && m < p3) ? W[src[jb] + m] : 0.0f;
-      acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[jb], 0, 0, 0);
-    }
-  }
   const double h = h0 / (double)(1 << level);
-  const float scale = comp < 3 ? (float)(1.0 / h) : (float)(1.0 / (h * h));
+  const float s1 = (float)(1.0 / h), s2 = (float)(1.0 / (h * h));
+  const int kq = lane >> 4, col = lane & 15;
+  const int n_half = (ncol + 31) / 32;              // 32-column halves in use
+  const int n_tasks = n_rt * n_half;
+  for (int task = wave; task < n_tasks; task += n_waves) {
+    const int rt = task % n_rt, half = task / n_rt;
+    const int nbj = min(2, (ncol - half * 32 + 15) / 16);   // 16-column blocks in this half
+    const int row = rt * 16 + col;
+    const bool row_ok = row < p3;
+    const float4 tl = sN[row_ok ? row : 0];
+    const float tlx = tl.x + ox, tly = tl.y + oy, tlz = tl.z + oz;
+    floatx4 acc[9][2];
 #pragma unroll
-  for (int jb = 0; jb < 4; ++jb) {
-    const int pj = jb * 16 + col;
-    if (pj >= it.y) continue;
-    const int64_t T = pt[it.x + pj];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int l = rt * 16 + 4 * (lane >> 4) + r;
-      if (l < p3) atomicAdd(&Lc[(T * 9 + comp) * p3 + l], scale * acc[jb][r]);
+    for (int c = 0; c < 9; ++c) {
+      acc[c][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+      acc[c][1] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
+    const float* sBh = sB + (half * 32 + col) * kM2LStride;
+#pragma unroll 2
+    for (int k0 = 0; k0 < p3; k0 += 4) {
+      const int m = k0 + kq;
+      const bool ok = row_ok && m < p3;
+      const float4 tm = sN[m < p3 ? m : 0];
+      const float rx = tlx - tm.x, ry = tly - tm.y, rz = tlz - tm.z;
+      const float inv = ok ? __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz))) : 0.0f;
+      const float i2 = inv * inv;
+      float a[9];
+      a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
+      a[3] = rx * rx * i2; a[4] = rx * ry * i2; a[5] = rx * rz * i2;
+      a[6] = ry * ry * i2; a[7] = ry * rz * i2; a[8] = rz * rz * i2;
+      const int mm = m < p3 ? m : 0;
+      const float b0 = sBh[mm];
+      const float b1 = sBh[16 * kM2LStride + mm];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[c][0], 0, 0, 0);
+      if (nbj > 1) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b1, acc[c][1], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      const int pj = half * 32 + jb * 16 + col;
+      if (jb >= nbj || pj >= ncol) continue;
+      float* out = slots + (int64_t)(it.x + pj) * 9 * p3;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const float sc = c < 3 ? s1 : s2;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = rt * 16 + 4 * kq + r;
+          if (l < p3) out[c * p3 + l] = sc * acc[c][jb][r];
+        }
+      }
+    }
+  }
+}
+
+// L[T] = sum of T's M2L output slots, in pair order (one block per box of levels >= 2).
+template <int P>
+__global__ void __launch_bounds__(256) k_m2l_reduce(int64_t box0, const int32_t* __restrict__ rptr,
+                                                    const int32_t* __restrict__ ridx, const float* __restrict__ slots,
+                                                    float* __restrict__ Lc) {
+  constexpr int n = 9 * P * P * P;
+  const int64_t b = blockIdx.x;
+  const int k0 = rptr[b], k1 = rptr[b + 1];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    float acc = 0.0f;
+    for (int k = k0; k < k1; ++k) acc += slots[(int64_t)ridx[k] * n + e];
+    Lc[(box0 + b) * n + e] = acc;
   }
 }
 
@@ -550,6 +590,15 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
       k = e;
     }
     for (size_t k = 0; k < pairs.size(); ++k) { pt[k] = pairs[k].t; ps[k] = pairs[k].s; }
+    // per-target lists of pair slots (boxes of levels >= 2, pairs in sorted order)
+    const int64_t box2 = F->lev_off[2];
+    std::vector<int32_t> rptr(F->n_boxes - box2 + 1, 0), ridx(pairs.size());
+    for (auto& pr : pairs) rptr[pr.t - box2 + 1]++;
+    for (size_t b = 1; b < rptr.size(); ++b) rptr[b] += rptr[b - 1];
+    {
+      std::vector<int32_t> fill(rptr.begin(), rptr.end() - 1);
+      for (size_t k = 0; k < pairs.size(); ++k) ridx[fill[pairs[k].t - box2]++] = (int32_t)k;
+    }
     F->n_items = (int64_t)items.size();
     // P2P waves
     std::vector<int32_t> wl, wf;
@@ -586,6 +635,8 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     up(F->u_ptr, uptr);
     up(F->u_idx, uidx);
     up(F->m2l_t, pt);
+    up(F->r_ptr, rptr);
+    up(F->r_idx, ridx);
     up(F->m2l_s, ps);
     up(F->items, items);
     up(F->p2p_leaf, wl);
@@ -596,6 +647,7 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     F->phis.alloc(ctx, N);
     F->W.alloc(ctx, (size_t)F->n_boxes * p3);
     F->Lc.alloc(ctx, (size_t)F->n_boxes * 9 * p3);
+    F->slots.alloc(ctx, (size_t)std::max<int64_t>(F->m2l_pairs, 1) * 9 * p3);
     hipLaunchKernelGGL(k_gather_pts, dim3((N + 255) / 256), dim3(256), 0, st, N, F->perm.p, op->co.tgt32.p,
                        F->pts.p);
     PMX_HIP(hipGetLastError());
@@ -621,7 +673,6 @@ static void fmm_far_p(pmx_operator* op, int n_rhs, hipStream_t st) {
     int t = op->prof.begin(PMX_PHASE_FMM_P2M, st);
     hipLaunchKernelGGL(k_permute, dim3((N + 255) / 256), dim3(256), 0, st, N, F->perm.p,
                        op->qt32.p + (int64_t)r * N, F->qs.p);
-    PMX_HIP(hipMemsetAsync(F->Lc.p, 0, F->Lc.bytes(), st));
     hipLaunchKernelGGL(k_p2m<P>, dim3(F->n_leaves), dim3(256), 0, st, leaf_off, hL, F->tab.p, F->center.p,
                        F->leaf_start.p, F->pts.p, N, F->qs.p, F->W.p);
     PMX_HIP(hipGetLastError());
@@ -636,9 +687,14 @@ static void fmm_far_p(pmx_operator* op, int n_rhs, hipStream_t st) {
     op->prof.end(t, st);
     t = op->prof.begin(PMX_PHASE_FMM_M2L, st);
     if (F->n_items > 0) {
-      constexpr int n_rt = (p3 + 15) / 16;
-      hipLaunchKernelGGL(k_m2l<P>, dim3(F->n_items, 9, (n_rt + 3) / 4), dim3(256), 0, st, F->tab.p, F->items.p,
-                         F->m2l_t.p, F->m2l_s.p, F->W.p, F->Lc.p, F->h0);
+      hipLaunchKernelGGL(k_m2l<P>, dim3(F->n_items), dim3(512), 0, st, F->tab.p, F->items.p, F->m2l_t.p,
+                         F->m2l_s.p, F->W.p, F->slots.p, F->h0);
+      PMX_HIP(hipGetLastError());
+    }
+    {
+      const int64_t box2 = F->lev_off[2];
+      hipLaunchKernelGGL(k_m2l_reduce<P>, dim3(F->n_boxes - box2), dim3(256), 0, st, box2, F->r_ptr.p, F->r_idx.p,
+                         F->slots.p, F->Lc.p);
       PMX_HIP(hipGetLastError());
     }
     op->prof.end(t, st);
@@ -686,7 +742,8 @@ uint64_t fmm_bytes(const FMM* f) {
   return f->center.bytes() + f->child_begin.bytes() + f->child_end.bytes() + f->parent.bytes() +
          f->octant.bytes() + f->leaf_start.bytes() + f->perm.bytes() + f->pts.bytes() + f->qs.bytes() +
          f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_leaf.bytes() + f->p2p_first.bytes() + f->m2l_t.bytes() +
-         f->m2l_s.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes();
+         f->m2l_s.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
+         f->slots.bytes() + f->r_ptr.bytes() + f->r_idx.bytes();
 }
 
 }  // namespace pmx

@@ -319,7 +319,8 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
     out.iters = g.iters;
     out.converged = g.converged;
   } else {
-    // iterative refinement: residuals with A64, corrections with A32
+    // iterative refinement: residuals with A64, corrections with A32; the loop ends
+    // with r = f - A64 sigma for the returned sigma, so no extra apply is needed
     DBuf<double> d;
     d.alloc(ctx, ld);
     for (int k = 0;; ++k) {
@@ -333,7 +334,10 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
       }
       const std::vector<double> rn = norms(D, r.p, st);
       bool all = true;
-      for (int q = 0; q < n_rhs; ++q) all = all && rn[q] <= o.ir_tol * (fn[q] > 0 ? fn[q] : 1.0);
+      for (int q = 0; q < n_rhs; ++q) {
+        out.relres[q] = rn[q] / (fn[q] > 0 ? fn[q] : 1.0);
+        all = all && out.relres[q] <= o.ir_tol;
+      }
       if (all) break;
       if (k >= o.max_ir) {
         out.converged = false;
@@ -347,8 +351,9 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
       PMX_HIP(hipGetLastError());
       out.ir_steps++;
     }
+    return out;
   }
-  // final true residual with the FP64 operator
+  // FP64 / FP32 path: report the true residual with the FP64 operator
   apply_device(op, PMX_PREC_FP64_DIRECT, n_rhs, sigma, r.p, st);
   out.applies64++;
   hipLaunchKernelGGL(k_sub, g1, dim3(kBlock), 0, st, ld, f.p, r.p, r.p);
