@@ -232,7 +232,7 @@ pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* out) {
     out->n_patches = op->s->g.M;
     out->q = op->s->g.q;
     out->near_pairs = op->nl.nnz;
-    uint64_t b = op->co.a.bytes() + op->co.gs.bytes() + op->co.tgt.bytes() + op->co.tg.bytes() +
+    uint64_t b = op->co.a.bytes() + op->co.gs.bytes() + op->co.tgt.bytes() + op->co.tg.bytes() + op->co.tf64.bytes() +
                  op->co.tgt32.bytes() + op->co.w_over_a.bytes() + op->nl.ptr.bytes() + op->nl.patch.bytes() +
                  op->nl.target.bytes() + op->nl.C.bytes() + op->nl.D.bytes() + op->part.bytes() +
                  op->qt64.bytes() + op->qt32.bytes() + op->phi.bytes();

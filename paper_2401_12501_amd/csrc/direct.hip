@@ -1,8 +1,8 @@
 // Direct far-field sums over all source nodes (smooth rule, Section 6.1.3).
 //
 //   phi_i = sum_{j != i} w_j R(x_i, x_j) sigma_j
-//         = sum_j qt_j [ s_ij (A_i s_ij - B_i) + (g_i . r_ij) / r_ij^2 ],
-//   s_ij = (n_i . r_ij) / r_ij^2,  qt_j = w_j sigma_j / a_j,  r_ij = x_i - x_j,
+//         = sum_j qt_j (1/r^2) [ (n'_i . r)^2 / r^2 + h_i . r ],   r = x_i - x_j,
+//   qt_j = w_j sigma_j / a_j,  n' = sqrt(A) n,  h = g - B n,
 // the c = 0 remainder of eq:explicit_remainder with G = log(r) / (2 pi a(x'))
 // written with the target factors A = a/pi, B = a H/pi, g = grad_G a / (2 pi).
 //
@@ -21,50 +21,63 @@ namespace {
 constexpr int kBlock = 256;
 
 __device__ __forceinline__ double rcp64(double x) {
-  // hardware reciprocal, then two Newton steps (each doubles the correct bits)
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  // hardware reciprocal (about 24 correct bits), then one Newton step: 2e-15 relative
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 }  // namespace
 
-template <int NR>
-__global__ void __launch_bounds__(kBlock) k_direct64(int64_t N, const double* __restrict__ tgt,
-                                                     const double* __restrict__ tg, const double* __restrict__ X,
-                                                     const double* __restrict__ qt, int64_t ldq, int64_t chunk,
-                                                     double* __restrict__ part, int64_t ldp, int64_t ldc) {
-  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t i = i0 < N ? i0 : N - 1;
+// TPL targets per lane (targets i0 and i0 + kBlock of a 2*kBlock target tile): one
+// scalar source load feeds TPL pair evaluations.
+template <int NR, int TPL>
+__global__ void __launch_bounds__(kBlock) k_direct64(int64_t N, const double* __restrict__ tf,
+                                                     const double* __restrict__ X, const double* __restrict__ qt,
+                                                     int64_t ldq, int64_t chunk, double* __restrict__ part,
+                                                     int64_t ldp, int64_t ldc) {
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
-  const double xi = tgt[i], yi = tgt[N + i], zi = tgt[2 * N + i];
-  const double nx = tgt[3 * N + i], ny = tgt[4 * N + i], nz = tgt[5 * N + i];
-  const double A = tgt[6 * N + i], B = tgt[7 * N + i];
-  const double gx = tg[i], gy = tg[N + i], gz = tg[2 * N + i];
+  double xi[TPL], yi[TPL], zi[TPL], px[TPL], py[TPL], pz[TPL], hx[TPL], hy[TPL], hz[TPL];
+  int64_t it[TPL];
+#pragma unroll
+  for (int t = 0; t < TPL; ++t) {
+    it[t] = (int64_t)blockIdx.x * kBlock * TPL + t * kBlock + threadIdx.x;
+    const int64_t i = it[t] < N ? it[t] : N - 1;
+    xi[t] = tf[i]; yi[t] = tf[N + i]; zi[t] = tf[2 * N + i];
+    px[t] = tf[3 * N + i]; py[t] = tf[4 * N + i]; pz[t] = tf[5 * N + i];
+    hx[t] = tf[6 * N + i]; hy[t] = tf[7 * N + i]; hz[t] = tf[8 * N + i];
+  }
   const double* __restrict__ Xs = X;
   const double* __restrict__ Ys = X + N;
   const double* __restrict__ Zs = X + 2 * N;
-  double acc[NR];
+  double acc[TPL][NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  for (int t = 0; t < TPL; ++t)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[t][r] = 0.0;
 #pragma unroll 2
   for (int64_t j = j0; j < j1; ++j) {
-    const double dx = xi - Xs[j], dy = yi - Ys[j], dz = zi - Zs[j];
-    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
-    const double inv = rcp64(r2);
-    const double nr = fma(nx, dx, fma(ny, dy, nz * dz));
-    const double gr = fma(gx, dx, fma(gy, dy, gz * dz));
-    const double s = nr * inv;
-    const double v = fma(s, fma(A, s, -B), gr * inv);
+    const double xs = Xs[j], ys = Ys[j], zs = Zs[j];
+    double q[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = fma(qt[r * ldq + j], v, acc[r]);
-  }
-  if (i0 < N) {
+    for (int r = 0; r < NR; ++r) q[r] = qt[r * ldq + j];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) part[(int64_t)blockIdx.y * ldc + r * ldp + i0] = acc[r];
+    for (int t = 0; t < TPL; ++t) {
+      const double dx = xi[t] - xs, dy = yi[t] - ys, dz = zi[t] - zs;
+      const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
+      const double inv = rcp64(r2);
+      const double pr = fma(px[t], dx, fma(py[t], dy, pz[t] * dz));
+      const double hr = fma(hx[t], dx, fma(hy[t], dy, hz[t] * dz));
+      const double v = fma(pr * inv, pr, hr) * inv;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[t][r] = fma(q[r], v, acc[t][r]);
+    }
   }
+#pragma unroll
+  for (int t = 0; t < TPL; ++t)
+    if (it[t] < N) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) part[(int64_t)blockIdx.y * ldc + r * ldp + it[t]] = acc[t][r];
+    }
 }
 
 template <int NR>
@@ -76,9 +89,8 @@ __global__ void __launch_bounds__(kBlock) k_direct32(int64_t N, const float* __r
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
   const float xi = t32[i], yi = t32[N + i], zi = t32[2 * N + i];
-  const float nx = t32[3 * N + i], ny = t32[4 * N + i], nz = t32[5 * N + i];
-  const float A = t32[6 * N + i], B = t32[7 * N + i];
-  const float gx = t32[8 * N + i], gy = t32[9 * N + i], gz = t32[10 * N + i];
+  const float px = t32[3 * N + i], py = t32[4 * N + i], pz = t32[5 * N + i];
+  const float hx = t32[6 * N + i], hy = t32[7 * N + i], hz = t32[8 * N + i];
   const float* __restrict__ Xs = t32;
   const float* __restrict__ Ys = t32 + N;
   const float* __restrict__ Zs = t32 + 2 * N;
@@ -90,10 +102,9 @@ __global__ void __launch_bounds__(kBlock) k_direct32(int64_t N, const float* __r
     const float dx = xi - Xs[j], dy = yi - Ys[j], dz = zi - Zs[j];
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-30f)));
     const float inv = __builtin_amdgcn_rcpf(r2);
-    const float nr = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
-    const float gr = fmaf(gx, dx, fmaf(gy, dy, gz * dz));
-    const float s = nr * inv;
-    const float v = fmaf(s, fmaf(A, s, -B), gr * inv);
+    const float pr = fmaf(px, dx, fmaf(py, dy, pz * dz));
+    const float hr = fmaf(hx, dx, fmaf(hy, dy, hz * dz));
+    const float v = fmaf(pr * inv, pr, hr) * inv;
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = fmaf(qt[r * ldq + j], v, acc[r]);
   }
@@ -132,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) k_direct_log(int64_t N, const double* 
 namespace {
 // Source chunks so that the grid holds enough workgroups to fill 256 CUs.
 int64_t n_chunks_for(int64_t N) {
-  const int64_t tb = (N + kBlock - 1) / kBlock;
+  const int64_t tb = (N + 2 * kBlock - 1) / (2 * kBlock);
   int64_t c = (8 * 256 + tb - 1) / tb;
   if (c < 1) c = 1;
   if (c > 64) c = 64;
@@ -150,9 +161,12 @@ void launch_group(pmx_operator* op, int mode, int n_rhs, int r0, int64_t nc, hip
   dim3 grid((unsigned)((N + kBlock - 1) / kBlock), (unsigned)nc);
   double* part = op->part.p + (int64_t)r0 * N;
   const int64_t ldc = (int64_t)n_rhs * N;
-  if (mode == 0)
-    hipLaunchKernelGGL(k_direct64<NR>, grid, dim3(kBlock), 0, st, N, op->co.tgt.p, op->co.tg.p, op->s->g.x.p,
+  if (mode == 0) {
+    constexpr int TPL = NR <= 2 ? 2 : 1;
+    dim3 g64((unsigned)((N + TPL * kBlock - 1) / (TPL * kBlock)), (unsigned)nc);
+    hipLaunchKernelGGL((k_direct64<NR, TPL>), g64, dim3(kBlock), 0, st, N, op->co.tf64.p, op->s->g.x.p,
                        op->qt64.p + (int64_t)r0 * N, N, chunk, part, N, ldc);
+  }
   else if (mode == 1)
     hipLaunchKernelGGL(k_direct32<NR>, grid, dim3(kBlock), 0, st, N, op->co.tgt32.p, op->qt32.p + (int64_t)r0 * N,
                        N, chunk, part, N, ldc);

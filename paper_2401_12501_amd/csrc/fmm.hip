@@ -3,6 +3,7 @@
 // The far-field sum of the c = 0 remainder (eq:explicit_remainder) at target i is
 //   phi_i = A_i n_i^T F2_i n_i - B_i n_i . F1_i + g_i . F1_i,
 //   F1_i = sum_j qt_j r/r^2,  F2_i = sum_j qt_j r r^T / r^4,  r = x_i - x_j,
+// (equivalently n'^T F2 n' + h . F1 with n' = sqrt(A) n, h = g - B n),
 // so it needs the nine translation-invariant, homogeneous kernel components
 // k(r) = [r/r^2 (3), r r^T/r^4 (6)] applied to the scalar strengths qt = w sigma / a.
 // The paper accelerates the apply with an interpolative-decomposition FMM
@@ -51,10 +52,10 @@ struct FMM {
   DBuf<int32_t> octant;      // n_boxes (child position bits x | y << 1 | z << 2)
   DBuf<int32_t> leaf_start;  // n_leaves + 1 (sorted point ranges)
   DBuf<int32_t> perm;        // N: sorted position -> node
-  DBuf<float> pts;           // 11 N sorted: x y z nx ny nz A B gx gy gz
+  DBuf<float> pts;           // 9 N sorted: x y z n'x n'y n'z hx hy hz (n' = sqrt(A) n, h = g - B n)
   DBuf<float> qs;            // N sorted strengths (one rhs at a time)
   DBuf<int32_t> u_ptr, u_idx;        // U-list of leaves (leaf-local indices)
-  DBuf<int32_t> p2p_leaf, p2p_first; // P2P waves: leaf and first target offset
+  DBuf<int32_t> p2p_leaf, p2p_first, p2p_slot;  // P2P waves: leaf, first target offset, U-list slot
   int64_t n_p2p_waves = 0;
   DBuf<int32_t> m2l_t, m2l_s;        // global box indices of the pairs, sorted by (level, offset)
   DBuf<int4> items;                  // (first pair, count, level, offset code)
@@ -62,7 +63,7 @@ struct FMM {
   DBuf<float> W, Lc;                 // multipoles n_boxes*p3, locals n_boxes*9*p3
   DBuf<float> slots;                 // M2L output per pair (9*p3 each)
   DBuf<int32_t> r_ptr, r_idx;        // per box of levels >= 2: its pairs (CSR, pair order)
-  DBuf<float> phis;                  // N sorted P2P sums
+  DBuf<float> phis;                  // 27 N: P2P partial sums per U-list slot (sorted order)
 };
 
 // ----------------------------------------------------------------------------- device helpers
@@ -296,36 +297,35 @@ __global__ void __launch_bounds__(256) k_m2l_reduce(int64_t box0, const int32_t*
   }
 }
 
-// P2P over the U-list: one wave per (leaf, 64 targets); sources are wave-uniform.
+// P2P over the U-list: one wave per (leaf, 64 targets, U-list slot); sources of the
+// slot's neighbour leaf are wave-uniform.  part[slot][k] is summed in slot order by L2P.
 __global__ void __launch_bounds__(64) k_p2p(int64_t N, const int32_t* __restrict__ wleaf,
-                                            const int32_t* __restrict__ wfirst, const int32_t* __restrict__ leaf_start,
-                                            const int32_t* __restrict__ u_ptr, const int32_t* __restrict__ u_idx,
-                                            const float* __restrict__ pts, const float* __restrict__ qs,
-                                            float* __restrict__ phis) {
+                                            const int32_t* __restrict__ wfirst, const int32_t* __restrict__ wslot,
+                                            const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ u_ptr,
+                                            const int32_t* __restrict__ u_idx, const float* __restrict__ pts,
+                                            const float* __restrict__ qs, float* __restrict__ part) {
   const int leaf = wleaf[blockIdx.x];
+  const int slot = wslot[blockIdx.x];
   const int k0 = leaf_start[leaf] + wfirst[blockIdx.x];
   const int kend = leaf_start[leaf + 1];
   const int k = k0 + threadIdx.x;
   const int kk = k < kend ? k : kend - 1;
   const float xi = pts[kk], yi = pts[N + kk], zi = pts[2 * N + kk];
-  const float nx = pts[3 * N + kk], ny = pts[4 * N + kk], nz = pts[5 * N + kk];
-  const float A = pts[6 * N + kk], B = pts[7 * N + kk];
-  const float gx = pts[8 * N + kk], gy = pts[9 * N + kk], gz = pts[10 * N + kk];
+  const float px = pts[3 * N + kk], py = pts[4 * N + kk], pz = pts[5 * N + kk];
+  const float hx = pts[6 * N + kk], hy = pts[7 * N + kk], hz = pts[8 * N + kk];
+  const int S = u_idx[u_ptr[leaf] + slot];
+  const int j0 = leaf_start[S], j1 = leaf_start[S + 1];
   float acc = 0.0f;
-  for (int u = u_ptr[leaf]; u < u_ptr[leaf + 1]; ++u) {
-    const int S = u_idx[u];
-    const int j1 = leaf_start[S + 1];
-    for (int j = leaf_start[S]; j < j1; ++j) {
-      const float dx = xi - pts[j], dy = yi - pts[N + j], dz = zi - pts[2 * N + j];
-      const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-30f)));
-      const float inv = __builtin_amdgcn_rcpf(r2);
-      const float nr = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
-      const float gr = fmaf(gx, dx, fmaf(gy, dy, gz * dz));
-      const float s = nr * inv;
-      acc = fmaf(qs[j], fmaf(s, fmaf(A, s, -B), gr * inv), acc);
-    }
+#pragma unroll 4
+  for (int j = j0; j < j1; ++j) {
+    const float dx = xi - pts[j], dy = yi - pts[N + j], dz = zi - pts[2 * N + j];
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-30f)));
+    const float inv = __builtin_amdgcn_rcpf(r2);
+    const float pr = fmaf(px, dx, fmaf(py, dy, pz * dz));
+    const float hr = fmaf(hx, dx, fmaf(hy, dy, hz * dz));
+    acc = fmaf(qs[j], fmaf(pr * inv, pr, hr) * inv, acc);
   }
-  if (k < kend) phis[k] = acc;
+  if (k < kend) part[(int64_t)slot * N + k] = acc;
 }
 
 // L2P + contraction + P2P sum; writes phi (FP64, node order).
@@ -333,8 +333,8 @@ template <int P>
 __global__ void __launch_bounds__(256) k_l2p(int64_t leaf_off, float h, const float* __restrict__ tab,
                                              const float* __restrict__ center, const int32_t* __restrict__ leaf_start,
                                              const float* __restrict__ pts, int64_t N, const float* __restrict__ Lc,
-                                             const float* __restrict__ phis, const int32_t* __restrict__ perm,
-                                             double* __restrict__ phi) {
+                                             const float* __restrict__ part, const int32_t* __restrict__ u_ptr,
+                                             const int32_t* __restrict__ perm, double* __restrict__ phi) {
   constexpr int p = P, p3 = P * P * P;
   __shared__ float sL[9 * p3];
   const int leaf = blockIdx.x;
@@ -344,7 +344,10 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t leaf_off, float h, const fl
   const float cx = center[3 * box], cy = center[3 * box + 1], cz = center[3 * box + 2];
   const float ih = 1.0f / h;
   const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
+  const int n_slot = u_ptr[leaf + 1] - u_ptr[leaf];
   for (int k = s0 + threadIdx.x; k < s1; k += blockDim.x) {
+    float near_sum = 0.0f;
+    for (int sl = 0; sl < n_slot; ++sl) near_sum += part[(int64_t)sl * N + k];
     float sx[P], sy[P], sz[P];
     cheb_weights<P>(tab, (pts[k] - cx) * ih, sx);
     cheb_weights<P>(tab, (pts[N + k] - cy) * ih, sy);
@@ -364,14 +367,12 @@ __global__ void __launch_bounds__(256) k_l2p(int64_t leaf_off, float h, const fl
         }
       }
     const float nx = pts[3 * N + k], ny = pts[4 * N + k], nz = pts[5 * N + k];
-    const float A = pts[6 * N + k], B = pts[7 * N + k];
-    const float gx = pts[8 * N + k], gy = pts[9 * N + k], gz = pts[10 * N + k];
-    // F1 = F[0..2]; F2 = (xx, xy, xz, yy, yz, zz) = F[3..8]
+    const float hx = pts[6 * N + k], hy = pts[7 * N + k], hz = pts[8 * N + k];
+    // F1 = F[0..2]; F2 = (xx, xy, xz, yy, yz, zz) = F[3..8]; phi = n'^T F2 n' + h . F1
     const float nF2n = nx * nx * F[3] + 2.f * nx * ny * F[4] + 2.f * nx * nz * F[5] + ny * ny * F[6] +
                        2.f * ny * nz * F[7] + nz * nz * F[8];
-    const float nF1 = nx * F[0] + ny * F[1] + nz * F[2];
-    const float gF1 = gx * F[0] + gy * F[1] + gz * F[2];
-    phi[perm[k]] = (double)(A * nF2n - B * nF1 + gF1) + (double)phis[k];
+    const float hF1 = hx * F[0] + hy * F[1] + hz * F[2];
+    phi[perm[k]] = (double)(nF2n + hF1) + (double)near_sum;
   }
 }
 
@@ -380,7 +381,7 @@ __global__ void k_gather_pts(int64_t N, const int32_t* __restrict__ perm, const 
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const int64_t i = perm[k];
-  for (int c = 0; c < 11; ++c) pts[c * N + k] = t32[c * N + i];
+  for (int c = 0; c < 9; ++c) pts[c * N + k] = t32[c * N + i];
 }
 
 // ----------------------------------------------------------------------------- host: tree build
@@ -600,10 +601,15 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
       for (size_t k = 0; k < pairs.size(); ++k) ridx[fill[pairs[k].t - box2]++] = (int32_t)k;
     }
     F->n_items = (int64_t)items.size();
-    // P2P waves
-    std::vector<int32_t> wl, wf;
+    // P2P waves: (leaf, 64-target chunk, U-list slot)
+    std::vector<int32_t> wl, wf, ws;
     for (int64_t b = 0; b < F->n_leaves; ++b)
-      for (int32_t f = 0; f < lstart[b + 1] - lstart[b]; f += 64) { wl.push_back((int32_t)b); wf.push_back(f); }
+      for (int32_t f = 0; f < lstart[b + 1] - lstart[b]; f += 64)
+        for (int32_t sl = 0; sl < uptr[b + 1] - uptr[b]; ++sl) {
+          wl.push_back((int32_t)b);
+          wf.push_back(f);
+          ws.push_back(sl);
+        }
     F->n_p2p_waves = (int64_t)wl.size();
     // tables: t_k, M1[2][p][p] (M1[b][k][k'] = S1(t_k, +-0.5 + t_k'/2)), node coordinates
     std::vector<float> tab(p + 2 * p * p + 3 * p3);
@@ -641,10 +647,11 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     up(F->items, items);
     up(F->p2p_leaf, wl);
     up(F->p2p_first, wf);
+    up(F->p2p_slot, ws);
     up(F->tab, tab);
-    F->pts.alloc(ctx, 11 * (size_t)N);
+    F->pts.alloc(ctx, 9 * (size_t)N);
     F->qs.alloc(ctx, N);
-    F->phis.alloc(ctx, N);
+    F->phis.alloc(ctx, 27 * (size_t)N);
     F->W.alloc(ctx, (size_t)F->n_boxes * p3);
     F->Lc.alloc(ctx, (size_t)F->n_boxes * 9 * p3);
     F->slots.alloc(ctx, (size_t)std::max<int64_t>(F->m2l_pairs, 1) * 9 * p3);
@@ -708,12 +715,13 @@ static void fmm_far_p(pmx_operator* op, int n_rhs, hipStream_t st) {
     op->prof.end(t, st);
     t = op->prof.begin(PMX_PHASE_FMM_P2P, st);
     hipLaunchKernelGGL(k_p2p, dim3(F->n_p2p_waves), dim3(64), 0, st, N, F->p2p_leaf.p, F->p2p_first.p,
-                       F->leaf_start.p, F->u_ptr.p, F->u_idx.p, F->pts.p, F->qs.p, F->phis.p);
+                       F->p2p_slot.p, F->leaf_start.p, F->u_ptr.p, F->u_idx.p, F->pts.p, F->qs.p, F->phis.p);
     PMX_HIP(hipGetLastError());
     op->prof.end(t, st);
     t = op->prof.begin(PMX_PHASE_FMM_L2P, st);
     hipLaunchKernelGGL(k_l2p<P>, dim3(F->n_leaves), dim3(256), 0, st, leaf_off, hL, F->tab.p, F->center.p,
-                       F->leaf_start.p, F->pts.p, N, F->Lc.p, F->phis.p, F->perm.p, op->phi.p + (int64_t)r * N);
+                       F->leaf_start.p, F->pts.p, N, F->Lc.p, F->phis.p, F->u_ptr.p, F->perm.p,
+                       op->phi.p + (int64_t)r * N);
     PMX_HIP(hipGetLastError());
     op->prof.end(t, st);
   }
@@ -741,7 +749,7 @@ void fmm_stats(const FMM* f, pmx_operator_stats* s) {
 uint64_t fmm_bytes(const FMM* f) {
   return f->center.bytes() + f->child_begin.bytes() + f->child_end.bytes() + f->parent.bytes() +
          f->octant.bytes() + f->leaf_start.bytes() + f->perm.bytes() + f->pts.bytes() + f->qs.bytes() +
-         f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_leaf.bytes() + f->p2p_first.bytes() + f->m2l_t.bytes() +
+         f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_leaf.bytes() + f->p2p_first.bytes() + f->p2p_slot.bytes() + f->m2l_t.bytes() +
          f->m2l_s.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
          f->slots.bytes() + f->r_ptr.bytes() + f->r_idx.bytes();
 }

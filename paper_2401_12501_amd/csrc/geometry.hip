@@ -150,8 +150,8 @@ __global__ void k_patch_bounds(int64_t M, int q, const double* __restrict__ X, i
 __global__ void k_coeff(int64_t N, const double* __restrict__ a_in, const double* __restrict__ ga_in,
                         const double* __restrict__ X, const double* __restrict__ Nn, const double* __restrict__ H,
                         const double* __restrict__ W, double* __restrict__ a, double* __restrict__ gs,
-                        double* __restrict__ tgt, double* __restrict__ tg, float* __restrict__ t32,
-                        double* __restrict__ woa, int* __restrict__ bad) {
+                        double* __restrict__ tgt, double* __restrict__ tg, double* __restrict__ tf,
+                        float* __restrict__ t32, double* __restrict__ woa, int* __restrict__ bad) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   double ai = a_in[i];
@@ -169,9 +169,14 @@ __global__ void k_coeff(int64_t N, const double* __restrict__ a_in, const double
   double v[8] = {x0, x1, x2, n0, n1, n2, A, B};
   for (int k = 0; k < 8; ++k) tgt[k * N + i] = v[k];
   tg[i] = s0 * inv_2pi; tg[N + i] = s1 * inv_2pi; tg[2 * N + i] = s2 * inv_2pi;
-  float f[11] = {(float)x0, (float)x1, (float)x2, (float)n0, (float)n1, (float)n2, (float)A, (float)B,
-                 (float)(s0 * inv_2pi), (float)(s1 * inv_2pi), (float)(s2 * inv_2pi)};
-  for (int k = 0; k < 11; ++k) t32[k * N + i] = f[k];
+  // n' = sqrt(A) n and h = g - B n: A (n.r)^2 - B (n.r) r^2 + (g.r) r^2 = (n'.r)^2 + (h.r) r^2
+  const double sa = sqrt(A);
+  double v9[9] = {x0, x1, x2, sa * n0, sa * n1, sa * n2, s0 * inv_2pi - B * n0, s1 * inv_2pi - B * n1,
+                  s2 * inv_2pi - B * n2};
+  for (int k = 0; k < 9; ++k) {
+    tf[k * N + i] = v9[k];
+    t32[k * N + i] = (float)v9[k];
+  }
   woa[i] = W[i] / ai;
 }
 
@@ -281,13 +286,14 @@ void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const 
   co.gs.alloc(ctx, 3 * N);
   co.tgt.alloc(ctx, 8 * N);
   co.tg.alloc(ctx, 3 * N);
-  co.tgt32.alloc(ctx, 11 * N);
+  co.tf64.alloc(ctx, 9 * N);
+  co.tgt32.alloc(ctx, 9 * N);
   co.w_over_a.alloc(ctx, N);
   DBuf<int> bad;
   bad.alloc(ctx, 1);
   PMX_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
   hipLaunchKernelGGL(k_coeff, dim3((N + 255) / 256), dim3(256), 0, st, N, a, grad_a, g.x.p, g.n.p, g.H.p, g.w.p,
-                     co.a.p, co.gs.p, co.tgt.p, co.tg.p, co.tgt32.p, co.w_over_a.p, bad.p);
+                     co.a.p, co.gs.p, co.tgt.p, co.tg.p, co.tf64.p, co.tgt32.p, co.w_over_a.p, bad.p);
   PMX_HIP(hipGetLastError());
   int hbad = 0;
   PMX_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));

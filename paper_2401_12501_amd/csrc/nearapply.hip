@@ -65,9 +65,13 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(int64_t nb, const doubl
 }
 
 // One wavefront per target.  identity != 0: add sigma_i and s_r (the operator A);
-// identity == 0: representation (near blocks D plus far field only).
+// identity == 0: representation (near blocks D plus far field only).  The target's
+// near-patch ids sit in lane registers and are fetched by shuffle, so the loads of
+// the streaming loop (C and the gathered sigma) do not wait on index loads.
+// Block index of element e: e / q2 = (e * magic) >> 32, magic = ceil(2^32 / q2)
+// (exact for e < 2^32 / q2; e is below 64 q2 here).
 template <int NR>
-__global__ void __launch_bounds__(kBlock) k_near_combine(int64_t N, int q2, int n_rhs, int r0,
+__global__ void __launch_bounds__(kBlock) k_near_combine(int64_t N, int q2, uint32_t magic, int n_rhs, int r0,
                                                          const int64_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ patch,
                                                          const double* __restrict__ Cb,
@@ -78,19 +82,32 @@ __global__ void __launch_bounds__(kBlock) k_near_combine(int64_t N, int q2, int 
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
   if (i >= N) return;
-  const int64_t e0 = ptr[i] * q2, e1 = ptr[i + 1] * q2;
   const int64_t b0 = ptr[i];
+  const int nb = (int)(ptr[i + 1] - b0);
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  for (int64_t e = e0 + lane; e < e1; e += kWave) {
-    const int64_t rel = e - e0;
-    const int64_t blk = rel / q2;
-    const int64_t loc = rel - blk * q2;
-    const int64_t col = (int64_t)patch[b0 + blk] * q2 + loc;
-    const double c = Cb[e];
+  for (int g = 0; g < nb; g += kWave) {          // groups of up to 64 near patches
+    const int ng = nb - g < kWave ? nb - g : kWave;
+    const int my_patch = lane < ng ? patch[b0 + g + lane] : 0;
+    const double* Cg = Cb + (b0 + g) * q2;
+    const uint32_t len = (uint32_t)(ng * q2);
+    // wave-uniform trip count: every lane takes part in the shuffle, loads are predicated
+#pragma unroll 4
+    for (uint32_t e0 = 0; e0 < len; e0 += kWave) {
+      const uint32_t e = e0 + lane;
+      const bool ok = e < len;
+      const uint32_t ee = ok ? e : len - 1;
+      const uint32_t blk = (uint32_t)(((uint64_t)ee * magic) >> 32);
+      const uint32_t loc = ee - blk * (uint32_t)q2;
+      const int P = __shfl(my_patch, (int)blk, kWave);
+      if (ok) {
+        const double c = Cg[e];
+        const int64_t col = (int64_t)P * q2 + loc;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = fma(c, sigma[(int64_t)(r0 + r) * N + col], acc[r]);
+        for (int r = 0; r < NR; ++r) acc[r] = fma(c, sigma[(int64_t)(r0 + r) * N + col], acc[r]);
+      }
+    }
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = wave_sum(acc[r]);
@@ -150,7 +167,8 @@ static void combine_group(pmx_operator* op, const double* sigma, double* y, int 
   const int64_t N = op->s->g.N;
   const int q2 = op->s->g.q * op->s->g.q;
   const int64_t nb = (N + (kBlock / kWave) - 1) / (kBlock / kWave);
-  hipLaunchKernelGGL(k_near_combine<NR>, dim3(nb), dim3(kBlock), 0, st, N, q2, n_rhs, r0, op->nl.ptr.p,
+  const uint32_t magic = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)q2 - 1) / (uint64_t)q2);
+  hipLaunchKernelGGL(k_near_combine<NR>, dim3(nb), dim3(kBlock), 0, st, N, q2, magic, n_rhs, r0, op->nl.ptr.p,
                      op->nl.patch.p, parametrix ? op->nl.D.p : op->nl.C.p, sigma, far, n_far, op->ssum.p,
                      parametrix ? 0 : 1, y);
   PMX_HIP(hipGetLastError());

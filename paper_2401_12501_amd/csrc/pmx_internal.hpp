@@ -120,12 +120,15 @@ struct Geometry {
   double area = 0.0;
 };
 
+// The far-field kernels use the equivalent form
+//   R(x_i, x_j) a_j = (1/r^2) [ (n'_i . r)^2 / r^2 + h_i . r ],  n' = sqrt(A) n,  h = g - B n.
 struct Coeff {
   DBuf<double> a;       // N
   DBuf<double> gs;      // 3N surface gradient
   DBuf<double> tgt;     // 8N: x y z nx ny nz A B | (g stored below)
   DBuf<double> tg;      // 3N: g = grad_G a / (2 pi)
-  DBuf<float> tgt32;    // 11N: x y z nx ny nz A B gx gy gz (FP32)
+  DBuf<double> tf64;    // 9N: x y z n'x n'y n'z hx hy hz
+  DBuf<float> tgt32;    // 9N: the same in FP32
   DBuf<double> w_over_a;  // N
 };
 
