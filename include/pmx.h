@@ -160,6 +160,35 @@ PMX_API pmx_status pmx_solve(pmx_operator* op, const pmx_options* opts, int n_rh
  * correction blocks on first use.  Errors: INVALID, OOM, DEVICE. */
 PMX_API pmx_status pmx_represent(pmx_operator* op, int n_rhs, const double* sigma, double* u, int mem_kind, void* stream);
 
+/* ---- Continuous-batching solve server (many independent problems of eq:IE) ----
+ * Requests queue in arrival order; pmx_server_step admits them while fewer than
+ * max_active run and the estimated device footprint fits the context's HBM budget.
+ * Each admitted request gets its own stream and worker thread, builds its surface and
+ * operator on the device, solves with opts->precision (NULL opts: defaults with the
+ * mixed path), and releases its device memory; active requests run concurrently.
+ * No call blocks on another request's work.  All input arrays are host memory and are
+ * copied by submit. */
+PMX_API pmx_status pmx_server_create(pmx_ctx* ctx, const pmx_options* opts, int max_active, pmx_server** out);
+/* Queue one problem (same node layout as pmx_surface_create; a, grad_a, f as in
+ * pmx_operator_create and pmx_solve with n_rhs = 1).  want_u: also compute u.
+ * Errors: INVALID, TOO_LARGE (estimated footprint above the budget even when idle). */
+PMX_API pmx_status pmx_server_submit(pmx_server* sv, int n_patches, int q, const double* x, const double* xu,
+                                     const double* xv, const double* xuu, const double* xuv, const double* xvv,
+                                     const double* a, const double* grad_a, const double* f, int want_u,
+                                     uint64_t* ticket);
+/* Retire finished requests and admit queued ones; reports active and queued counts. */
+PMX_API pmx_status pmx_server_step(pmx_server* sv, int* n_active, int* n_queued);
+/* PMX_PENDING while queued or running.  When finished: copies sigma (N) and u (N, if
+ * requested; either pointer may be NULL), info, and times[3] = seconds queued, in service,
+ * and submit-to-done; returns the request's status (OK, NOT_CONVERGED with the best
+ * iterate, CANCELLED, ...) and forgets the ticket.  Unknown ticket: INVALID. */
+PMX_API pmx_status pmx_server_poll(pmx_server* sv, uint64_t ticket, double* sigma, double* u, pmx_info* info,
+                                   double* times);
+/* Cancel a queued or running request (its poll then returns CANCELLED). */
+PMX_API pmx_status pmx_server_cancel(pmx_server* sv, uint64_t ticket);
+/* Cancels running requests, waits for their workers, frees the server (NULL-safe). */
+PMX_API void pmx_server_destroy(pmx_server* sv);
+
 /* Per-phase device timing of the apply (HIP events recorded on the call's stream around
  * each phase while enabled).  Phases: PMX_PHASE_*.  pmx_profile_read synchronizes the
  * recorded events and returns, per phase, the summed milliseconds and the number of

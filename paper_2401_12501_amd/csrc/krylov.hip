@@ -207,6 +207,7 @@ GmresOut gmres(pmx_operator* op, int precision, int n_rhs, const double* b, doub
     int j = 0;
     std::vector<double> hh1((size_t)n_rhs * (m + 1)), hh2((size_t)n_rhs * (m + 1)), hn(n_rhs);
     for (; j < m && total < max_iter; ++j) {
+      if (op->cancel && op->cancel->load()) throw Error(PMX_ERR_CANCELLED, "solve cancelled");
       apply_device(op, precision, n_rhs, V.p + (int64_t)j * ldk, W.p, st);
       res.applies++;
       const int nk = j + 1;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -62,18 +63,20 @@ struct DBuf {
   T* get() const { return p; }
 };
 
+// Device memory accounting of a context (shared by the server's worker threads).
 struct Ctx {
   int device = 0;
   uint64_t budget = 0;   // 0 = unbounded
-  uint64_t in_use = 0;
+  std::atomic<uint64_t> in_use{0};
   int n_cu = 256;
-  int n_xcd = 8;
   void reserve(uint64_t bytes) {
-    if (budget && in_use + bytes > budget)
-      throw Error(PMX_ERR_TOO_LARGE, "device footprint exceeds the context's HBM budget");
-    in_use += bytes;
+    uint64_t cur = in_use.load();
+    do {
+      if (budget && cur + bytes > budget)
+        throw Error(PMX_ERR_TOO_LARGE, "device footprint exceeds the context's HBM budget");
+    } while (!in_use.compare_exchange_weak(cur, cur + bytes));
   }
-  void unreserve(uint64_t bytes) { in_use -= bytes < in_use ? bytes : in_use; }
+  void unreserve(uint64_t bytes) { in_use.fetch_sub(bytes); }
 };
 
 template <class T>
@@ -209,6 +212,7 @@ struct pmx_operator {
   pmx::DBuf<double> phi;       // far field result (FP64 accumulate of FMM output)
   pmx::DBuf<double> io_a, io_b;  // staging for host arrays
   pmx::Profiler prof;
+  const std::atomic<int>* cancel = nullptr;   // set by the server: abandon the solve when nonzero
 };
 
 namespace pmx {

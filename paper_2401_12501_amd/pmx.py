@@ -69,6 +69,13 @@ _SIGS = {
     "pmx_represent": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.c_int, _vp]),
     "pmx_operator_export_geometry": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
     "pmx_operator_export_near": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "pmx_server_create": (C.c_int32, [_vp, C.POINTER(pmx_options), C.c_int, C.POINTER(_vp)]),
+    "pmx_server_submit": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int,
+                                      C.POINTER(C.c_uint64)]),
+    "pmx_server_step": (C.c_int32, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "pmx_server_poll": (C.c_int32, [_vp, C.c_uint64, _vp, _vp, C.POINTER(pmx_info), _vp]),
+    "pmx_server_cancel": (C.c_int32, [_vp, C.c_uint64]),
+    "pmx_server_destroy": (None, [_vp]),
     "pmx_profile_enable": (C.c_int32, [_vp, C.c_int]),
     "pmx_profile_read": (C.c_int32, [_vp, _vp, _vp]),
 }
@@ -295,3 +302,52 @@ class Operator:
         _check(lib().pmx_operator_export_near(self.h, ptr.ctypes.data, patch.ctypes.data, Cb.ctypes.data,
                                                Db.ctypes.data if with_D else None))
         return ptr, patch, Cb, Db
+
+
+class Server:
+    """pmx_server_*: continuous-batching solve server (host arrays, copied on submit)."""
+
+    def __init__(self, ctx: Context, opts: pmx_options | None = None, max_active: int = 4):
+        self.ctx = ctx
+        h = _vp()
+        _check(lib().pmx_server_create(ctx.h, C.byref(opts) if opts is not None else None, max_active, C.byref(h)))
+        self.h = h
+        self.n = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pmx_server_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def submit(self, surface, a, grad_a, f, want_u: bool = False) -> int:
+        arrs = [np.ascontiguousarray(v, dtype=np.float64) for v in
+                (surface.x, surface.xu, surface.xv, surface.xuu, surface.xuv, surface.xvv, a, grad_a, f)]
+        t = C.c_uint64()
+        _check(lib().pmx_server_submit(self.h, surface.n_patches, surface.q, *[v.ctypes.data for v in arrs],
+                                       1 if want_u else 0, C.byref(t)))
+        self.n[t.value] = (surface.n, want_u)
+        return t.value
+
+    def step(self):
+        na, nq = C.c_int(), C.c_int()
+        _check(lib().pmx_server_step(self.h, C.byref(na), C.byref(nq)))
+        return na.value, nq.value
+
+    def poll(self, ticket: int):
+        """None while pending; else (status, sigma, u, info, times)."""
+        N, want_u = self.n[ticket]
+        sig = np.empty(N)
+        u = np.empty(N) if want_u else None
+        info = pmx_info()
+        times = np.zeros(3)
+        code = lib().pmx_server_poll(self.h, ticket, sig.ctypes.data, u.ctypes.data if want_u else None,
+                                     C.byref(info), times.ctypes.data)
+        if code == PMX_PENDING:
+            return None
+        del self.n[ticket]
+        return code, sig, u, info, times
+
+    def cancel(self, ticket: int):
+        _check(lib().pmx_server_cancel(self.h, ticket))
