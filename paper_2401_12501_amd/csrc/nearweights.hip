@@ -179,8 +179,17 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
   T.A = A.tgt[6 * N + i];
   T.B = A.tgt[7 * N + i];
 
-  for (int e = tid; e < q2; e += kThreads) W[e] = 0.0;
   const int ngl = A.n_gl;
+  // near-rule layout (tensor leaves): Xp[10][q2] T[10][q][16] Lu16[16][q] Lv16[16][q] c[256] T2[16][q] Wn[q2]
+  double* Xp = lds;
+  double* Tm = Xp + 10 * q2;
+  double* Lu16 = Tm + 10 * q * kNglMax;
+  double* Lv16 = Lu16 + kNglMax * q;
+  double* cw2 = Lv16 + kNglMax * q;
+  double* T2 = cw2 + kThreads;
+  double* Wn = T2 + kNglMax * q;
+  double* Wacc = self ? W : Wn;
+  for (int e = tid; e < q2; e += kThreads) Wacc[e] = 0.0;
 
   // ------------------------------------------------------------------ cells
   double u0 = 0.0, v0 = 0.0;
@@ -325,7 +334,7 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
   // ------------------------------------------------------------------ quadrature points
   const int n_rad = (self && KERNEL == 1) ? 4 * ngl : ngl;
   const int64_t pts_per_cell = self ? (int64_t)ngl * n_rad : (int64_t)ngl * ngl;
-  const int64_t n_pts = pts_per_cell * nc;
+  const int64_t n_pts = self ? pts_per_cell * nc : 0;   // near leaves use the tensor path below
   for (int64_t p0 = 0; p0 < n_pts; p0 += kThreads) {
     const int64_t p = p0 + tid;
     double c = 0.0;
@@ -397,10 +406,80 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
     __syncthreads();
   }
 
+
+  // ------------------------------------------------------------------ near rule: tensor leaves
+  // For a leaf with nodes u_i, v_k (i, k < n_gl): field values are Lu (X Lv^T) and the block
+  // update is W += Lu^T diag(c) Lv, both as small contractions through LDS.
+  if (!self && nc > 0) {
+    const int64_t N = A.N;
+    for (int e = tid; e < 10 * q2; e += kThreads) {
+      const int f = e / q2, j = e - f * q2;
+      const int64_t g = base + j;
+      const double* src = f < 3 ? A.X + f * N : (f < 6 ? A.XU + (f - 3) * N : (f < 9 ? A.XV + (f - 6) * N : A.a));
+      Xp[e] = src[g];
+    }
+    const int npt = ngl * ngl;
+    for (int cell = 0; cell < nc; ++cell) {
+      const Cell C = cells[cell];
+      const double h = 2.0 / (double)(1 << C.k);
+      const double ua = -1.0 + C.iu * h, va = -1.0 + C.iv * h;
+      const double hh = 0.5 * h;
+      __syncthreads();
+      if (tid < ngl) lagrange_dev(q, A.tn, A.cinv, ua + hh * (A.gl_t[tid] + 1.0), Lu16 + tid * q, 1);
+      else if (tid < 2 * ngl) lagrange_dev(q, A.tn, A.cinv, va + hh * (A.gl_t[tid - ngl] + 1.0), Lv16 + (tid - ngl) * q, 1);
+      __syncthreads();
+      // T[f][a][k] = sum_b X[f][a][b] Lv[k][b]
+      for (int e = tid; e < 10 * q * ngl; e += kThreads) {
+        const int f = e / (q * ngl), r = e - f * q * ngl, aa = r / ngl, k = r - aa * ngl;
+        const double* xr = Xp + f * q2 + aa * q;
+        const double* lv = Lv16 + k * q;
+        double acc = 0.0;
+        for (int b = 0; b < q; ++b) acc = fma(xr[b], lv[b], acc);
+        Tm[(f * q + aa) * kNglMax + k] = acc;
+      }
+      __syncthreads();
+      double c = 0.0;
+      if (tid < npt) {
+        const int i = tid / ngl, k = tid - i * ngl;
+        double g[10];
+        for (int f = 0; f < 10; ++f) {
+          double acc = 0.0;
+          for (int aa = 0; aa < q; ++aa) acc = fma(Lu16[i * q + aa], Tm[(f * q + aa) * kNglMax + k], acc);
+          g[f] = acc;
+        }
+        const double c0 = g[4] * g[8] - g[5] * g[7];
+        const double c1 = g[5] * g[6] - g[3] * g[8];
+        const double c2 = g[3] * g[7] - g[4] * g[6];
+        const double Jt = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+        const double inv_as = 1.0 / g[9];
+        const double F = KERNEL == 0 ? remainder_dev(T, g, inv_as) : parametrix_dev(T, g, inv_as);
+        c = A.gl_w[i] * A.gl_w[k] * hh * hh * F * Jt;
+      }
+      cw2[tid] = c;
+      __syncthreads();
+      // T2[i][b] = sum_k c[i][k] Lv[k][b]
+      for (int e = tid; e < ngl * q; e += kThreads) {
+        const int i = e / q, b = e - i * q;
+        double acc = 0.0;
+        for (int k = 0; k < ngl; ++k) acc = fma(cw2[i * ngl + k], Lv16[k * q + b], acc);
+        T2[i * q + b] = acc;
+      }
+      __syncthreads();
+      // W[a][b] += sum_i Lu[i][a] T2[i][b]
+      for (int e = tid; e < q2; e += kThreads) {
+        const int aa = e / q, b = e - aa * q;
+        double acc = 0.0;
+        for (int i = 0; i < ngl; ++i) acc = fma(Lu16[i * q + aa], T2[i * q + b], acc);
+        Wn[e] += acc;
+      }
+    }
+    __syncthreads();
+  }
+
   // ------------------------------------------------------------------ subtract the smooth rule
   for (int e = tid; e < q2; e += kThreads) {
     const int64_t j = base + e;
-    double val = W[e];
+    double val = Wacc[e];
     if (j != i) {
       const double y[3] = {A.X[j], A.X[N + j], A.X[2 * N + j]};
       const double inv_a = 1.0 / A.a[j];
@@ -442,7 +521,9 @@ void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists&
   A.tgt = co.tgt.p; A.tg = co.tg.p;
   A.tn = tab.p; A.cinv = tab.p + q; A.gl_t = tab.p + 2 * q; A.gl_w = tab.p + 2 * q + o.n_gl;
   A.pair_patch = nl.patch.p; A.pair_target = nl.target.p; A.out = out.p; A.err = err.p;
-  const size_t lds = (size_t)(2 * q * kLS + kThreads + q2) * sizeof(double);
+  const size_t lds_self = (size_t)(2 * q * kLS + kThreads + q2) * sizeof(double);
+  const size_t lds_near = (size_t)(11 * q2 + 10 * q * kNglMax + 3 * kNglMax * q + kThreads) * sizeof(double);
+  const size_t lds = lds_self > lds_near ? lds_self : lds_near;
   int dev = 0;
   PMX_HIP(hipGetDevice(&dev));
   hipDeviceProp_t prop;
