@@ -81,6 +81,65 @@ def cpu_baseline(prob, sigma, budget_s: float = 15.0):
                       f"{t_setup / rows * 1e3:.1f} ms/row timed separately"}
 
 
+def serving(ctx, n_req: int, slots: int):
+    """Serving workload: requests from the sphere / random-axis ellipsoid / torus families with
+    2e3..2e5 nodes (log-uniform), mixed path, memory-admitted.  The first quarter of the requests,
+    submitted at once, measures the saturated rate mu; the rest arrive as a Poisson stream at
+    0.7 mu.  Latency = submit -> result ready (server clock)."""
+    from paper_2401_12501_amd import pmx
+    from paper_2401_12501_amd.inputs import serving_requests
+    log(f"[serve] generating {n_req} requests ...")
+    reqs = [p for _, p in serving_requests(n_req, seed=3)]
+    o = pmx.pmx_default_options()
+    o.precision = pmx.PMX_PREC_MIXED_FMM
+    sv = pmx.Server(ctx, o, max_active=slots)
+
+    def drain(tickets, lat, status):
+        for t in list(tickets):
+            r = sv.poll(t)
+            if r is not None:
+                tickets.remove(t)
+                lat.append(r[4][2])
+                status.append(r[0])
+
+    n_cal = max(4, n_req // 4)
+    lat_cal, st_cal, out = [], [], set()
+    t0 = time.perf_counter()
+    for p in reqs[:n_cal]:
+        out.add(sv.submit(p.surface, p.a, p.grad_a, p.f[:, 0]))
+    while out:
+        sv.step()
+        drain(out, lat_cal, st_cal)
+        time.sleep(0.001)
+    mu = n_cal / (time.perf_counter() - t0)
+    lam = 0.7 * mu
+    rng = np.random.default_rng(33)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req - n_cal))
+    lat, status = [], []
+    t0 = time.perf_counter()
+    nxt = 0
+    while nxt < len(arrivals) or out:
+        now = time.perf_counter() - t0
+        while nxt < len(arrivals) and arrivals[nxt] <= now:
+            p = reqs[n_cal + nxt]
+            out.add(sv.submit(p.surface, p.a, p.grad_a, p.f[:, 0]))
+            nxt += 1
+        sv.step()
+        drain(out, lat, status)
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    sv.close()
+    lat = np.array(lat)
+    res = {"requests": n_req, "calibration_requests": n_cal, "slots": slots,
+           "saturated_solves_per_s": round(mu, 3), "arrival_rate_per_s": round(lam, 3),
+           "solves_per_s": round(len(lat) / wall, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+           "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+           "ok": int(sum(1 for s in status + st_cal if s == 0)),
+           "nodes_min_max": [int(min(p.n for p in reqs)), int(max(p.n for p in reqs))]}
+    log(f"[serve] {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +153,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--fmm-leaf", type=int, default=0, help="FMM leaf occupancy target (0: library default)")
     ap.add_argument("--fmm-order", type=int, default=0, help="FMM interpolation order (0: library default)")
+    ap.add_argument("--serve", type=int, default=64,
+                    help="serving requests to run (0: skip); the first quarter calibrates the saturated rate")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calib-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size kernel for traffic counters)")
     args = ap.parse_args()
@@ -156,12 +218,12 @@ def main():
         ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms" for k, v in phases.items() if v[1]))
     y_main = y.cpu().numpy().T.copy()
     try:
-        other_s, _ = timed(other, max(3, args.steps // 4), 1, False)
+        other_s, other_phases = timed(other, max(3, args.steps // 4), 1, True)
         y_other = y.cpu().numpy().T.copy()
         log(f"[bench] {other}: {other_s * 1e3:.3f} ms/apply")
     except pmx.PmxError as e:
         log(f"[bench] {other} path unavailable: {e}")
-        other_s, y_other = None, None
+        other_s, y_other, other_phases = None, None, {}
 
     st = op.stats()
     # dominant kernel of the timed path
@@ -176,6 +238,26 @@ def main():
         roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom[0],
                 "avg_ms": round(avg_s * launches_per_step * 1e3, 4)}
+
+    # every kernel with a defined algorithmic work, both paths
+    kernels = []
+    for path, ph, steps in ((args.path, phases, args.steps), (other, other_phases, max(3, args.steps // 4))):
+        for name, (ms, cnt) in ph.items():
+            w = algorithmic_work(name, st, N, prob.surface.q, n_rhs, op.opts.fmm_order) if cnt else None
+            if w:
+                amount, unit, bound, peak = w
+                t = ms / 1e3 / steps
+                kernels.append({"path": path, "kernel": name, "bound": bound, "ms": round(t * 1e3, 4),
+                                "achieved": round(amount / t, 3), "peak": peak, "unit": unit,
+                                "frac": round(amount / t / peak, 4)})
+
+    # PCIe-inclusive rate: the same apply with host arrays (staged through device buffers)
+    sig_host = np.ascontiguousarray(sig_h.T)
+    op.apply(sig_host, prec[args.path])
+    th0 = time.perf_counter()
+    for _ in range(5):
+        op.apply(sig_host, prec[args.path])
+    host_s = (time.perf_counter() - th0) / 5
 
     # apply error against the oracle on sampled rows
     from oracle.operator import OracleOperator
@@ -227,11 +309,15 @@ def main():
         "apply_rel_err_vs_oracle": err,
         "solve_to_1e-8": solve,
         "setup_s": round(t_setup, 3),
+        "kernels": kernels,
+        "host_buffers_gpts_per_s": round(N * n_rhs / host_s / 1e9, 4),
         "phases_ms": {k: round(v[0] / v[1], 4) for k, v in phases.items() if v[1]},
         "fmm": {"levels": st.fmm_levels, "boxes": st.fmm_boxes, "m2l_pairs": st.fmm_m2l_pairs,
                 "p2p_pairs": st.fmm_p2p_pairs},
         "near_pairs": st.near_pairs,
     }
+    if args.serve:
+        out["serving"] = serving(ctx, args.serve, args.serve_slots)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob, sig_h, args.cpu_budget)

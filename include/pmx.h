@@ -76,7 +76,7 @@ enum {
 typedef struct pmx_options {
   double eta_near;     /* near criterion: within eta patch radii of the centroid (Section 6.1.2: 1.5) */
   int n_gl;            /* Gauss-Legendre order of the local rules (Section 6.1.1: 16) */
-  int fmm_order;       /* Chebyshev points per box edge of the FMM (default 6) */
+  int fmm_order;       /* Chebyshev points per box edge of the FMM: 4 or 6 (default 6) */
   int fmm_leaf;        /* mean points per FMM leaf box: the leaf level is the first with at most this (default 256) */
   double gmres_tol;    /* relative residual target of GMRES (FP64 path) */
   int gmres_restart;   /* Krylov space size before restart */

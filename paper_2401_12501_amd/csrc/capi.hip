@@ -105,7 +105,7 @@ const double* stage_in(Ctx* ctx, DBuf<double>& buf, const double* p, size_t n, i
 void check_opts(const pmx_options& o) {
   PMX_REQUIRE(o.eta_near > 0.0 && std::isfinite(o.eta_near), PMX_ERR_INVALID, "eta_near must be positive");
   PMX_REQUIRE(o.n_gl >= 2 && o.n_gl <= 16, PMX_ERR_INVALID, "n_gl must be in [2, 16]");
-  PMX_REQUIRE(o.fmm_order >= 2 && o.fmm_order <= 12, PMX_ERR_INVALID, "fmm_order must be in [2, 12]");
+  PMX_REQUIRE(o.fmm_order == 4 || o.fmm_order == 6, PMX_ERR_INVALID, "fmm_order must be 4 or 6");
   PMX_REQUIRE(o.fmm_leaf >= 8, PMX_ERR_INVALID, "fmm_leaf must be >= 8");
   PMX_REQUIRE(o.gmres_restart >= 1 && o.gmres_restart <= 500, PMX_ERR_INVALID, "gmres_restart must be in [1, 500]");
   PMX_REQUIRE(o.max_iter >= 1, PMX_ERR_INVALID, "max_iter must be >= 1");

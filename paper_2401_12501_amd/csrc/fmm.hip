@@ -283,17 +283,26 @@ __global__ void __launch_bounds__(512) k_m2l(const float* __restrict__ tab, cons
 }
 
 // L[T] = sum of T's M2L output slots, in pair order (one block per box of levels >= 2).
+// Each thread owns four consecutive entries (float4); the pair loop is unrolled so the
+// independent slot loads are in flight together.
 template <int P>
-__global__ void __launch_bounds__(256) k_m2l_reduce(int64_t box0, const int32_t* __restrict__ rptr,
+__global__ void __launch_bounds__(512) k_m2l_reduce(int64_t box0, const int32_t* __restrict__ rptr,
                                                     const int32_t* __restrict__ ridx, const float* __restrict__ slots,
                                                     float* __restrict__ Lc) {
   constexpr int n = 9 * P * P * P;
+  static_assert(n % 4 == 0, "slot size must be a multiple of 4");
+  constexpr int n4 = n / 4;
   const int64_t b = blockIdx.x;
   const int k0 = rptr[b], k1 = rptr[b + 1];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    float acc = 0.0f;
-    for (int k = k0; k < k1; ++k) acc += slots[(int64_t)ridx[k] * n + e];
-    Lc[(box0 + b) * n + e] = acc;
+  const float4* __restrict__ s4 = reinterpret_cast<const float4*>(slots);
+  for (int e = threadIdx.x; e < n4; e += blockDim.x) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) {
+      const float4 v = s4[(int64_t)ridx[k] * n4 + e];
+      acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+    }
+    reinterpret_cast<float4*>(Lc)[(box0 + b) * n4 + e] = acc;
   }
 }
 
@@ -427,7 +436,7 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
   try {
     F->p = op->opts.fmm_order;
     F->p3 = F->p * F->p * F->p;
-    PMX_REQUIRE(F->p >= 3 && F->p <= 6, PMX_ERR_INVALID, "fmm_order must be in [3, 6]");
+    PMX_REQUIRE(F->p == 4 || F->p == 6, PMX_ERR_INVALID, "fmm_order must be 4 or 6");
     const int p = F->p, p3 = F->p3;
     std::vector<double> X(3 * N);
     PMX_HIP(hipMemcpyAsync(X.data(), op->s->g.x.p, 3 * N * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -700,7 +709,7 @@ static void fmm_far_p(pmx_operator* op, int n_rhs, hipStream_t st) {
     }
     {
       const int64_t box2 = F->lev_off[2];
-      hipLaunchKernelGGL(k_m2l_reduce<P>, dim3(F->n_boxes - box2), dim3(256), 0, st, box2, F->r_ptr.p, F->r_idx.p,
+      hipLaunchKernelGGL(k_m2l_reduce<P>, dim3(F->n_boxes - box2), dim3(512), 0, st, box2, F->r_ptr.p, F->r_idx.p,
                          F->slots.p, F->Lc.p);
       PMX_HIP(hipGetLastError());
     }
@@ -731,11 +740,9 @@ void fmm_far(pmx_operator* op, int n_rhs, hipStream_t st) {
   const int64_t N = op->s->g.N;
   if (op->phi.n < (size_t)n_rhs * N) op->phi.alloc(&op->s->ctx->c, (size_t)n_rhs * N);
   switch (op->fmm->p) {
-    case 3: fmm_far_p<3>(op, n_rhs, st); break;
     case 4: fmm_far_p<4>(op, n_rhs, st); break;
-    case 5: fmm_far_p<5>(op, n_rhs, st); break;
     case 6: fmm_far_p<6>(op, n_rhs, st); break;
-    default: throw Error(PMX_ERR_INVALID, "fmm_order must be in [3, 6]");
+    default: throw Error(PMX_ERR_INVALID, "fmm_order must be 4 or 6");
   }
 }
 
