@@ -35,6 +35,31 @@ sys.path.insert(0, ROOT)
 METRIC = "operator-apply Gpts/s @1e-8 rel err, mixed vs FP64; solves/s + p50/p99 latency"
 PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0}
 
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB) on this workload
+# (ellipsoid, 153,600 nodes, mixed path, 1 RHS), scaled by what the counters read for a plain
+# 256 MiB device copy (FETCH_SIZE 131,088 KiB -> x2.0, WRITE_SIZE 262,144 KiB -> x1.0).  Each
+# record is tied to the kernel's source file; a different file means a changed kernel and the
+# traffic is reported as null.
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+TRAFFIC = {
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "3d91538a2fef6065",
+                "kib": [("k_m2l", 8963.2, 375646.8), ("k_m2l_reduce", 168262.2, 7378.5)]},
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "8b0735de6c1193d2",
+             "kib": [("k_near_combine", 281207.6, 1203.2)]},
+}
+
+
+def traffic_bytes(phase: str, n_rhs: int, k: int):
+    """Measured HBM bytes per launch of a phase, or None if not measured for this kernel/workload."""
+    import hashlib
+    rec = TRAFFIC.get(phase)
+    if rec is None or n_rhs != 1 or k != 16:
+        return None
+    with open(os.path.join(ROOT, rec["src"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest()[:16] != rec["sha"]:
+            return None
+    return sum((f * FETCH_SCALE + w * WRITE_SCALE) * 1024.0 for _, f, w in rec["kib"])
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -235,8 +260,10 @@ def main():
         avg_s = dom[1][0] / dom[1][1] / 1e3
         launches_per_step = dom[1][1] / args.steps
         achieved = amount / (avg_s * launches_per_step)
+        tb = traffic_bytes(dom[0], n_rhs, args.k)
         roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom[0],
+                "frac": round(achieved / peak, 4), "traffic": (round(tb / 1e9, 4) if tb else None),
+                "traffic_unit": "GB per launch", "kernel": dom[0],
                 "avg_ms": round(avg_s * launches_per_step * 1e3, 4)}
 
     # every kernel with a defined algorithmic work, both paths
