@@ -21,10 +21,15 @@
 // from the sub-square's corner images), depth <= 20; each leaf carries an
 // n_gl x n_gl tensor Gauss-Legendre rule.
 //
-// Layout: one workgroup per (target, patch) pair.  Quadrature points are taken in
-// batches of one point per thread; each thread evaluates its point's Lagrange
-// values, interpolated geometry and kernel, writes (l_a(u), l_b(v), c) to LDS, and
-// the q*q block entries are then accumulated in a fixed order.
+// Layout: one workgroup per (target, patch) pair, specialised on the patch order q.
+// After the cells (self panels or near leaves) are built, each wave takes its own
+// batches of 64 quadrature points, one point per lane: the lane evaluates its
+// point's Lagrange values (registers), interpolates the ten patch fields with the
+// node data read through the scalar cache (all lanes use the same node values),
+// evaluates the kernel and writes (c l_a(u), l_b(v)) to its wave's LDS rows.  The
+// block update W += Lu^T diag(c) Lv is then sixteen FP64 MFMA steps of 4 points
+// each; the 16 x 16 accumulator stays in registers across batches and the waves'
+// accumulators are summed in a fixed order at the end.
 #include <cmath>
 
 #include "pmx_internal.hpp"
@@ -33,11 +38,13 @@ namespace pmx {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kLS = kThreads + 1;   // LDS row stride (odd: rows fall in different banks)
 constexpr int kMaxCells = 256;   // panels (self) or leaves (near) per pair
 constexpr int kMaxDepth = 20;
 constexpr int kNglMax = 16;
+constexpr int kStage = 65;       // LDS row stride of the staging rows, in doubles (odd)
+
+// Pointer whose loads go through the scalar cache when the address is uniform.
+typedef const __attribute__((address_space(4))) double* sdp;
 
 struct NWArgs {
   int64_t N;
@@ -45,8 +52,7 @@ struct NWArgs {
   int n_gl;
   double eta;
   const double* X;      // 3N SoA
-  const double* XU;     // 3N
-  const double* XV;     // 3N
+  const double* XP;     // 10N node-major: x y z x_u x_v a per node
   const double* a;      // N
   const double* w;      // N
   const double* tgt;    // 8N: x y z nx ny nz A B
@@ -62,59 +68,66 @@ struct NWArgs {
   int64_t pair0;
 };
 
+template <int Q>
+constexpr int waves_for() { return Q <= 12 ? 4 : 2; }
+
 // Lagrange values of the q nodes at s: l_j(s) = cinv_j prod_{k != j} (s - t_k),
 // from prefix and suffix products (no division by s - t_j).
-__device__ inline void lagrange_dev(int q, const double* tn, const double* cinv, double s, double* out,
-                                    int stride) {
+template <int Q>
+__device__ inline void lagrange_q(sdp tn, sdp cinv, double s, double (&l)[Q]) {
+  double d[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) d[j] = s - tn[j];
   double pre = 1.0;
-  for (int j = 0; j < q; ++j) {
-    out[j * stride] = pre;
-    pre *= (s - tn[j]);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    l[j] = pre;
+    pre *= d[j];
   }
   double suf = 1.0;
-  for (int j = q - 1; j >= 0; --j) {
-    out[j * stride] *= suf * cinv[j];
-    suf *= (s - tn[j]);
+#pragma unroll
+  for (int j = Q - 1; j >= 0; --j) {
+    l[j] *= suf * cinv[j];
+    suf *= d[j];
   }
 }
 
-// Tensor interpolation of the patch fields at one point, with l_a(u) in Lu and
-// l_b(v) in Lv (LDS rows of this thread, stride kThreads).
-struct PointGeo {
-  double y[3], yu[3], yv[3], as;
-};
-
-__device__ inline void interp_point(const NWArgs& A, int64_t base, const double* Lu, const double* Lv,
-                                    PointGeo& pg) {
-  const int q = A.q;
-  const int64_t N = A.N;
-  double acc[10];
-  for (int f = 0; f < 10; ++f) acc[f] = 0.0;
-  for (int aa = 0; aa < q; ++aa) {
-    double t[10];
-    for (int f = 0; f < 10; ++f) t[f] = 0.0;
-    const int64_t row = base + (int64_t)aa * q;
-    for (int b = 0; b < q; ++b) {
-      const double lv = Lv[b * kLS];
-      const int64_t j = row + b;
-      t[0] = fma(lv, A.X[j], t[0]);
-      t[1] = fma(lv, A.X[N + j], t[1]);
-      t[2] = fma(lv, A.X[2 * N + j], t[2]);
-      t[3] = fma(lv, A.XU[j], t[3]);
-      t[4] = fma(lv, A.XU[N + j], t[4]);
-      t[5] = fma(lv, A.XU[2 * N + j], t[5]);
-      t[6] = fma(lv, A.XV[j], t[6]);
-      t[7] = fma(lv, A.XV[N + j], t[7]);
-      t[8] = fma(lv, A.XV[2 * N + j], t[8]);
-      t[9] = fma(lv, A.a[j], t[9]);
+// Tensor interpolation of the first NF of the ten node fields (x, x_u, x_v, a; node-major,
+// ten per node): g_f = sum_a l_a(u) sum_b l_b(v) X[(a q + b) 10 + f].  The node values are
+// uniform across the wave and come through the scalar cache; each node's loads are
+// issued one node ahead of its FMAs and the scheduling barriers keep the compiler from
+// hoisting more of them (which would exhaust the scalar registers).
+template <int Q, int NF>
+__device__ inline void interp_q(sdp XP, const double (&lu)[Q], const double (&lv)[Q], double (&g)[NF]) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f) g[f] = 0.0;
+  double cur[NF], nxt[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) cur[f] = XP[f];
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    double t[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) t[f] = 0.0;
+#pragma unroll
+    for (int b = 0; b < Q; ++b) {
+      const int n = a * Q + b;
+      if (n + 1 < Q * Q) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) nxt[f] = XP[(n + 1) * 10 + f];
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        t[f] = fma(lv[b], cur[f], t[f]);
+        asm volatile("" : "+v"(t[f]));   // keep this node's FMAs ahead of the next node's loads
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) cur[f] = nxt[f];
     }
-    const double lu = Lu[aa * kLS];
-    for (int f = 0; f < 10; ++f) acc[f] = fma(lu, t[f], acc[f]);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) g[f] = fma(lu[a], t[f], g[f]);
   }
-  pg.y[0] = acc[0]; pg.y[1] = acc[1]; pg.y[2] = acc[2];
-  pg.yu[0] = acc[3]; pg.yu[1] = acc[4]; pg.yu[2] = acc[5];
-  pg.yv[0] = acc[6]; pg.yv[1] = acc[7]; pg.yv[2] = acc[8];
-  pg.as = acc[9];
 }
 
 struct Target {
@@ -138,37 +151,51 @@ __device__ inline double parametrix_dev(const Target& T, const double* y, double
   return 0.5 * log(rr) * 0.15915494309189533577 * inv_as;
 }
 
-struct Cell {   // self: panel on edge k [phi0, phi1]; near: leaf (depth, iu, iv)
-  double p0, p1;
-  int k;
-  int iu, iv;
+union Cell {                    // self: angular panel [p0, p1] of one edge; near: leaf (depth, iu, iv)
+  struct { double p0, p1; } s;
+  struct { int depth, iu, iv, pad; } n;
 };
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// The same pointer, opaque to the optimiser: node loads through it are neither hoisted
+// out of the enclosing loop nor shared between calls, so they stay next to their FMAs.
+__device__ inline sdp opaque(sdp p) {
+  uint64_t v = (uint64_t)p;
+  asm volatile("" : "+s"(v));
+  return (sdp)v;
+}
 
 }  // namespace
 
 // KERNEL: 0 = remainder R (correction blocks C), 1 = parametrix K (blocks D).
-template <int KERNEL>
-__global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
+template <int KERNEL, int Q>
+__global__ void __launch_bounds__(64 * waves_for<Q>()) k_near_weights(NWArgs A) {
+  constexpr int kW = waves_for<Q>();
+  constexpr int kT = 64 * kW;
+  constexpr int q2 = Q * Q;
   extern __shared__ double lds[];
-  const int q = A.q, q2 = q * q;
-  const int tid = threadIdx.x;
-  // LDS layout: Lu[q][kLS], Lv[q][kLS], c[kThreads], W[q2]
-  double* Lu = lds;
-  double* Lv = Lu + q * kLS;
-  double* cw = Lv + q * kLS;
-  double* W = cw + kThreads;
+  // stage[w][2][Q][kStage]; the subdivision front and flags overlay it before the point loop
+  double* stage = lds;
+  int2* front = reinterpret_cast<int2*>(lds);                 // [2][kMaxCells]
+  int* flag_split = reinterpret_cast<int*>(front + 2 * kMaxCells);
   __shared__ Cell cells[kMaxCells];
+  __shared__ int cell_edge[kMaxCells];
   __shared__ int n_cells;
-  __shared__ int2 front[2][kMaxCells];  // near: sub-square (iu, iv) at the current depth
   __shared__ int n_front[2];
-  __shared__ int flag_split[kThreads];
+  __shared__ double W[q2];
 
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int64_t pair = A.pair0 + blockIdx.x;
   const int P = A.pair_patch[pair];
   const int64_t i = A.pair_target[pair];
   const int64_t N = A.N;
   const int64_t base = (int64_t)P * q2;
   const bool self = (i / q2) == P;
+
+  const sdp F = (sdp)(A.XP + base * 10);
+  const sdp tn = (sdp)A.tn, cinv = (sdp)A.cinv, gl_t = (sdp)A.gl_t, gl_w = (sdp)A.gl_w;
 
   Target T;
   for (int c = 0; c < 3; ++c) {
@@ -178,38 +205,22 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
   }
   T.A = A.tgt[6 * N + i];
   T.B = A.tgt[7 * N + i];
-
   const int ngl = A.n_gl;
-  // near-rule layout (tensor leaves): Xp[10][q2] T[10][q][16] Lu16[16][q] Lv16[16][q] c[256] T2[16][q] Wn[q2]
-  double* Xp = lds;
-  double* Tm = Xp + 10 * q2;
-  double* Lu16 = Tm + 10 * q * kNglMax;
-  double* Lv16 = Lu16 + kNglMax * q;
-  double* cw2 = Lv16 + kNglMax * q;
-  double* T2 = cw2 + kThreads;
-  double* Wn = T2 + kNglMax * q;
-  double* Wacc = self ? W : Wn;
-  for (int e = tid; e < q2; e += kThreads) Wacc[e] = 0.0;
 
   // ------------------------------------------------------------------ cells
   double u0 = 0.0, v0 = 0.0;
   if (self) {
     const int loc = (int)(i - base);
-    u0 = A.tn[loc / q];
-    v0 = A.tn[loc % q];
+    u0 = tn[loc / Q];
+    v0 = tn[loc % Q];
     if (tid == 0) {
       int nc = 0;
-      const double PI = 3.14159265358979323846;
-      const double thn[4] = {-PI / 2, 0.0, PI / 2, PI};
       const double dd[4] = {v0 + 1.0, 1.0 - u0, 1.0 - v0, u0 + 1.0};
-      const double cu[4] = {-1.0, 1.0, 1.0, -1.0};
-      const double cv[4] = {-1.0, -1.0, 1.0, 1.0};
+      // tangential coordinate (along the edge, counter-clockwise) of the edge's two corners
+      const double sa[4] = {-1.0 - u0, -1.0 - v0, u0 - 1.0, v0 - 1.0};
+      const double sb[4] = {1.0 - u0, 1.0 - v0, u0 + 1.0, v0 + 1.0};
       for (int k = 0; k < 4; ++k) {
-        const double tx = -sin(thn[k]), ty = cos(thn[k]);
-        const int k1 = (k + 1) & 3;
-        const double sa = (cu[k] - u0) * tx + (cv[k] - v0) * ty;
-        const double sb = (cu[k1] - u0) * tx + (cv[k1] - v0) * ty;
-        const double pa = atan2(sa, dd[k]), pb = atan2(sb, dd[k]);
+        const double pa = atan2(sa[k], dd[k]), pb = atan2(sb[k], dd[k]);
         // positive side [0, pb], then negative side [pa, 0]
         for (int side = 0; side < 2; ++side) {
           const double end = side == 0 ? pb : -pa;
@@ -219,10 +230,9 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
             const bool last = !(b < end);
             const double hi = last ? end : b;
             if (nc < kMaxCells) {
-              Cell& C = cells[nc];
-              C.k = k;
-              C.p0 = side == 0 ? prev : -hi;
-              C.p1 = side == 0 ? hi : -prev;
+              cells[nc].s.p0 = side == 0 ? prev : -hi;
+              cells[nc].s.p1 = side == 0 ? hi : -prev;
+              cell_edge[nc] = k;
             }
             ++nc;
             prev = hi;
@@ -232,13 +242,12 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
       }
       n_cells = nc;
     }
-    __syncthreads();
   } else {
     // level-synchronous subdivision of [-1, 1]^2; a square at depth d is (iu, iv) * 2^(1-d) - 1
     if (tid == 0) {
       n_front[0] = 1;
       n_front[1] = 0;
-      front[0][0] = make_int2(0, 0);
+      front[0] = make_int2(0, 0);
       n_cells = 0;
     }
     __syncthreads();
@@ -246,34 +255,22 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
     for (int depth = 0; depth <= kMaxDepth; ++depth) {
       const int nf = n_front[cur];
       if (nf == 0) break;
-      for (int f0 = 0; f0 < nf; f0 += kThreads) {
+      for (int f0 = 0; f0 < nf; f0 += kT) {
         const int f = f0 + tid;
         int split = 0;
         if (f < nf) {
-          const int iu = front[cur][f].x, iv = front[cur][f].y;
+          const int iu = front[cur * kMaxCells + f].x, iv = front[cur * kMaxCells + f].y;
           const double h = 2.0 / (double)(1 << depth);
           const double ua = -1.0 + iu * h, va = -1.0 + iv * h;
           const double cuu[4] = {ua, ua + h, ua + h, ua};
           const double cvv[4] = {va, va, va + h, va + h};
           double cx[4][3];
           for (int k = 0; k < 4; ++k) {
-            double lu[kNglMax], lv[kNglMax];
-            lagrange_dev(q, A.tn, A.cinv, cuu[k], lu, 1);
-            lagrange_dev(q, A.tn, A.cinv, cvv[k], lv, 1);
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int aa = 0; aa < q; ++aa) {
-              double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-              for (int b = 0; b < q; ++b) {
-                const int64_t j = base + aa * q + b;
-                t0 = fma(lv[b], A.X[j], t0);
-                t1 = fma(lv[b], A.X[N + j], t1);
-                t2 = fma(lv[b], A.X[2 * N + j], t2);
-              }
-              s0 = fma(lu[aa], t0, s0);
-              s1 = fma(lu[aa], t1, s1);
-              s2 = fma(lu[aa], t2, s2);
-            }
-            cx[k][0] = s0; cx[k][1] = s1; cx[k][2] = s2;
+            double lu[Q], lv[Q], g[3];
+            lagrange_q<Q>(tn, cinv, cuu[k], lu);
+            lagrange_q<Q>(tn, cinv, cvv[k], lv);
+            interp_q<Q, 3>(opaque(F), lu, lv, g);
+            cx[k][0] = g[0]; cx[k][1] = g[1]; cx[k][2] = g[2];
           }
           double m[3];
           for (int c = 0; c < 3; ++c) m[c] = 0.25 * (cx[0][c] + cx[1][c] + cx[2][c] + cx[3][c]);
@@ -290,22 +287,21 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
         __syncthreads();
         if (tid == 0) {
           const int nxt = cur ^ 1;
-          const int lim = nf - f0 < kThreads ? nf - f0 : kThreads;
+          const int lim = nf - f0 < kT ? nf - f0 : kT;
           for (int t = 0; t < lim; ++t) {
-            const int iu = front[cur][f0 + t].x, iv = front[cur][f0 + t].y;
+            const int iu = front[cur * kMaxCells + f0 + t].x, iv = front[cur * kMaxCells + f0 + t].y;
             if (flag_split[t]) {
               const int cu2[4] = {2 * iu, 2 * iu + 1, 2 * iu, 2 * iu + 1};
               const int cv2[4] = {2 * iv, 2 * iv, 2 * iv + 1, 2 * iv + 1};
               for (int c = 0; c < 4; ++c) {
-                if (n_front[nxt] < kMaxCells) front[nxt][n_front[nxt]] = make_int2(cu2[c], cv2[c]);
+                if (n_front[nxt] < kMaxCells) front[nxt * kMaxCells + n_front[nxt]] = make_int2(cu2[c], cv2[c]);
                 n_front[nxt]++;
               }
             } else {
               if (n_cells < kMaxCells) {
-                Cell& C = cells[n_cells];
-                C.k = depth;
-                C.iu = iu;
-                C.iv = iv;
+                cells[n_cells].n.depth = depth;
+                cells[n_cells].n.iu = iu;
+                cells[n_cells].n.iv = iv;
               }
               n_cells++;
             }
@@ -332,163 +328,178 @@ __global__ void __launch_bounds__(kThreads) k_near_weights(NWArgs A) {
   }
 
   // ------------------------------------------------------------------ quadrature points
-  const int n_rad = (self && KERNEL == 1) ? 4 * ngl : ngl;
-  const int64_t pts_per_cell = self ? (int64_t)ngl * n_rad : (int64_t)ngl * ngl;
-  const int64_t n_pts = self ? pts_per_cell * nc : 0;   // near leaves use the tensor path below
-  for (int64_t p0 = 0; p0 < n_pts; p0 += kThreads) {
-    const int64_t p = p0 + tid;
-    double c = 0.0;
-    if (p < n_pts) {
-      const int cell = (int)(p / pts_per_cell);
-      const int r = (int)(p - (int64_t)cell * pts_per_cell);
-      const Cell C = cells[cell];
-      double u, v, wq;
+  const unsigned n_rad = (self && KERNEL == 1) ? 4 * ngl : ngl;
+  const unsigned ppc = self ? (unsigned)ngl * n_rad : (unsigned)(ngl * ngl);
+  const unsigned n_pts = ppc * (unsigned)nc;
+  double* CL = stage + (size_t)wave * 2 * Q * kStage;   // c l_a(u) at [a][point]
+  double* LV = CL + Q * kStage;                          // l_b(v) at [b][point]
+  const int r16 = lane & 15, g4 = lane >> 4;
+  const int rq = r16 < Q ? r16 : 0;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (unsigned p0 = (unsigned)wave * 64; p0 < n_pts; p0 += kT) {
+    const unsigned p = p0 + lane;
+    const bool valid = p < n_pts;
+    double u = 0.0, v = 0.0, wq = 0.0;
+    if (valid) {
+      const unsigned cell = p / ppc;
+      const unsigned r = p - cell * ppc;
       if (self) {
-        const int ia = r / n_rad, ir = r - ia * n_rad;
-        const double PI = 3.14159265358979323846;
-        const double thn = (C.k == 0) ? -PI / 2 : (C.k == 1 ? 0.0 : (C.k == 2 ? PI / 2 : PI));
-        const double dk = (C.k == 0) ? v0 + 1.0 : (C.k == 1 ? 1.0 - u0 : (C.k == 2 ? 1.0 - v0 : u0 + 1.0));
-        const double mid = 0.5 * (C.p0 + C.p1), half = 0.5 * (C.p1 - C.p0);
-        const double phi = mid + half * A.gl_t[ia];
-        const double L = dk / cos(phi);
+        const int k = cell_edge[cell];
+        const double c0 = cells[cell].s.p0, c1 = cells[cell].s.p1;
+        const unsigned ia = r / n_rad, ir = r - ia * n_rad;
+        const double dk = k == 0 ? v0 + 1.0 : (k == 1 ? 1.0 - u0 : (k == 2 ? 1.0 - v0 : u0 + 1.0));
+        const double mid = 0.5 * (c0 + c1), half = 0.5 * (c1 - c0);
+        const double phi = mid + half * gl_t[ia];
+        double sp, cp;
+        sincos(phi, &sp, &cp);
+        const double L = dk / cp;
         // radial node s in (0, 1] and weight for int_0^L F rho drho = L^2 sum w F(L s)
         double s, wr;
-        const int pr = ir / ngl, jr = ir - pr * ngl;
-        const double t = 0.5 * (A.gl_t[jr] + 1.0), wt = 0.5 * A.gl_w[jr];
+        const unsigned pr = ir / ngl, jr = ir - pr * ngl;
+        const double t = 0.5 * (gl_t[jr] + 1.0), wt = 0.5 * gl_w[jr];
         if (KERNEL == 0 || pr < 3) {
-          const double lo = KERNEL == 0 ? 0.0 : ldexp(1.0, -(pr + 1));
-          const double hi = KERNEL == 0 ? 1.0 : ldexp(1.0, -pr);
+          const double lo = KERNEL == 0 ? 0.0 : ldexp(1.0, -(int)(pr + 1));
+          const double hi = KERNEL == 0 ? 1.0 : ldexp(1.0, -(int)pr);
           s = lo + (hi - lo) * t;
           wr = (hi - lo) * wt * s;
         } else {
           s = t * t * t * 0.125;
           wr = wt * 3.0 * t * t * t * t * t / 64.0;
         }
-        wq = half * A.gl_w[ia] * L * L * wr;
-        const double ang = thn + phi;
-        u = u0 + L * s * cos(ang);
-        v = v0 + L * s * sin(ang);
+        wq = half * gl_w[ia] * L * L * wr;
+        // direction at angle (edge normal + phi); the edge normals point along -v, +u, +v, -u
+        const double ca = k == 0 ? sp : (k == 1 ? cp : (k == 2 ? -sp : -cp));
+        const double sa = k == 0 ? -cp : (k == 1 ? sp : (k == 2 ? cp : -sp));
+        u = u0 + L * s * ca;
+        v = v0 + L * s * sa;
       } else {
-        const int ia = r / ngl, ib = r - ia * ngl;
-        const double h = 2.0 / (double)(1 << C.k);
-        const double ua = -1.0 + C.iu * h, va = -1.0 + C.iv * h;
+        const Cell C = cells[cell];
+        const unsigned ia = r / ngl, ib = r - ia * ngl;
+        const double h = 2.0 / (double)(1 << C.n.depth);
+        const double ua = -1.0 + C.n.iu * h, va = -1.0 + C.n.iv * h;
         const double hh = 0.5 * h;
-        u = ua + hh * (A.gl_t[ia] + 1.0);
-        v = va + hh * (A.gl_t[ib] + 1.0);
-        wq = A.gl_w[ia] * A.gl_w[ib] * hh * hh;
-      }
-      lagrange_dev(q, A.tn, A.cinv, u, Lu + tid, kLS);
-      lagrange_dev(q, A.tn, A.cinv, v, Lv + tid, kLS);
-      PointGeo pg;
-      interp_point(A, base, Lu + tid, Lv + tid, pg);
-      const double c0 = pg.yu[1] * pg.yv[2] - pg.yu[2] * pg.yv[1];
-      const double c1 = pg.yu[2] * pg.yv[0] - pg.yu[0] * pg.yv[2];
-      const double c2 = pg.yu[0] * pg.yv[1] - pg.yu[1] * pg.yv[0];
-      const double Jt = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-      const double inv_as = 1.0 / pg.as;
-      const double F = KERNEL == 0 ? remainder_dev(T, pg.y, inv_as) : parametrix_dev(T, pg.y, inv_as);
-      c = wq * F * Jt;
-    } else {
-      for (int aa = 0; aa < q; ++aa) {
-        Lu[aa * kLS + tid] = 0.0;
-        Lv[aa * kLS + tid] = 0.0;
+        u = ua + hh * (gl_t[ia] + 1.0);
+        v = va + hh * (gl_t[ib] + 1.0);
+        wq = gl_w[ia] * gl_w[ib] * hh * hh;
       }
     }
-    cw[tid] = c;
-    __syncthreads();
-    const int lim = (n_pts - p0) < kThreads ? (int)(n_pts - p0) : kThreads;
-    for (int e = tid; e < q2; e += kThreads) {
-      const int aa = e / q, b = e - aa * q;
-      double acc = 0.0;
-      for (int t = 0; t < lim; ++t) acc = fma(cw[t] * Lu[aa * kLS + t], Lv[b * kLS + t], acc);
-      W[e] += acc;
+    double lu[Q], lv[Q], g[10];
+    lagrange_q<Q>(tn, cinv, u, lu);
+    lagrange_q<Q>(tn, cinv, v, lv);
+    interp_q<Q, 10>(opaque(F), lu, lv, g);
+    const double x0 = g[4] * g[8] - g[5] * g[7];
+    const double x1 = g[5] * g[6] - g[3] * g[8];
+    const double x2 = g[3] * g[7] - g[4] * g[6];
+    const double Jt = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+    const double inv_as = 1.0 / g[9];
+    const double Fk = KERNEL == 0 ? remainder_dev(T, g, inv_as) : parametrix_dev(T, g, inv_as);
+    const double c = valid ? wq * Fk * Jt : 0.0;
+    // stage this wave's 64 points; LDS operations of one wave complete in order
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      CL[a * kStage + lane] = c * lu[a];
+      LV[a * kStage + lane] = lv[a];
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // W[a][b] += sum_t CL[a][t] LV[b][t]: A[a][k] = CL[a][4s + k], B[k][b] = LV[b][4s + k]
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const double av = CL[rq * kStage + 4 * s + g4];
+      const double bv = LV[rq * kStage + 4 * s + g4];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(r16 < Q ? av : 0.0, r16 < Q ? bv : 0.0, acc, 0, 0, 0);
+    }
   }
 
-
-  // ------------------------------------------------------------------ near rule: tensor leaves
-  // For a leaf with nodes u_i, v_k (i, k < n_gl): field values are Lu (X Lv^T) and the block
-  // update is W += Lu^T diag(c) Lv, both as small contractions through LDS.
-  if (!self && nc > 0) {
-    const int64_t N = A.N;
-    for (int e = tid; e < 10 * q2; e += kThreads) {
-      const int f = e / q2, j = e - f * q2;
-      const int64_t g = base + j;
-      const double* src = f < 3 ? A.X + f * N : (f < 6 ? A.XU + (f - 3) * N : (f < 9 ? A.XV + (f - 6) * N : A.a));
-      Xp[e] = src[g];
-    }
-    const int npt = ngl * ngl;
-    for (int cell = 0; cell < nc; ++cell) {
-      const Cell C = cells[cell];
-      const double h = 2.0 / (double)(1 << C.k);
-      const double ua = -1.0 + C.iu * h, va = -1.0 + C.iv * h;
-      const double hh = 0.5 * h;
-      __syncthreads();
-      if (tid < ngl) lagrange_dev(q, A.tn, A.cinv, ua + hh * (A.gl_t[tid] + 1.0), Lu16 + tid * q, 1);
-      else if (tid < 2 * ngl) lagrange_dev(q, A.tn, A.cinv, va + hh * (A.gl_t[tid - ngl] + 1.0), Lv16 + (tid - ngl) * q, 1);
-      __syncthreads();
-      // T[f][a][k] = sum_b X[f][a][b] Lv[k][b]
-      for (int e = tid; e < 10 * q * ngl; e += kThreads) {
-        const int f = e / (q * ngl), r = e - f * q * ngl, aa = r / ngl, k = r - aa * ngl;
-        const double* xr = Xp + f * q2 + aa * q;
-        const double* lv = Lv16 + k * q;
-        double acc = 0.0;
-        for (int b = 0; b < q; ++b) acc = fma(xr[b], lv[b], acc);
-        Tm[(f * q + aa) * kNglMax + k] = acc;
-      }
-      __syncthreads();
-      double c = 0.0;
-      if (tid < npt) {
-        const int i = tid / ngl, k = tid - i * ngl;
-        double g[10];
-        for (int f = 0; f < 10; ++f) {
-          double acc = 0.0;
-          for (int aa = 0; aa < q; ++aa) acc = fma(Lu16[i * q + aa], Tm[(f * q + aa) * kNglMax + k], acc);
-          g[f] = acc;
-        }
-        const double c0 = g[4] * g[8] - g[5] * g[7];
-        const double c1 = g[5] * g[6] - g[3] * g[8];
-        const double c2 = g[3] * g[7] - g[4] * g[6];
-        const double Jt = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-        const double inv_as = 1.0 / g[9];
-        const double F = KERNEL == 0 ? remainder_dev(T, g, inv_as) : parametrix_dev(T, g, inv_as);
-        c = A.gl_w[i] * A.gl_w[k] * hh * hh * F * Jt;
-      }
-      cw2[tid] = c;
-      __syncthreads();
-      // T2[i][b] = sum_k c[i][k] Lv[k][b]
-      for (int e = tid; e < ngl * q; e += kThreads) {
-        const int i = e / q, b = e - i * q;
-        double acc = 0.0;
-        for (int k = 0; k < ngl; ++k) acc = fma(cw2[i * ngl + k], Lv16[k * q + b], acc);
-        T2[i * q + b] = acc;
-      }
-      __syncthreads();
-      // W[a][b] += sum_i Lu[i][a] T2[i][b]
-      for (int e = tid; e < q2; e += kThreads) {
-        const int aa = e / q, b = e - aa * q;
-        double acc = 0.0;
-        for (int i = 0; i < ngl; ++i) acc = fma(Lu16[i * q + aa], T2[i * q + b], acc);
-        Wn[e] += acc;
-      }
-    }
-    __syncthreads();
+  // ------------------------------------------------------------------ sum the waves' accumulators
+  __syncthreads();
+  double* red = stage;   // [wave][16][16]; for the FP64 16x16x4 MFMA, lane holds D[g4 + 4 r][r16]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave * 256 + (g4 + 4 * r) * 16 + r16] = acc[r];
+  __syncthreads();
+  for (int e = tid; e < q2; e += kT) {
+    const int aa = e / Q, b = e - aa * Q;
+    double s = 0.0;
+    for (int w = 0; w < kW; ++w) s += red[w * 256 + aa * 16 + b];
+    W[e] = s;
   }
+  __syncthreads();
 
   // ------------------------------------------------------------------ subtract the smooth rule
-  for (int e = tid; e < q2; e += kThreads) {
+  for (int e = tid; e < q2; e += kT) {
     const int64_t j = base + e;
-    double val = Wacc[e];
+    double val = W[e];
     if (j != i) {
       const double y[3] = {A.X[j], A.X[N + j], A.X[2 * N + j]};
       const double inv_a = 1.0 / A.a[j];
-      const double F = KERNEL == 0 ? remainder_dev(T, y, inv_a) : parametrix_dev(T, y, inv_a);
-      val -= A.w[j] * F;
+      const double Fs = KERNEL == 0 ? remainder_dev(T, y, inv_a) : parametrix_dev(T, y, inv_a);
+      val -= A.w[j] * Fs;
     }
     A.out[pair * q2 + e] = val;
   }
 }
+
+__global__ void k_interleave(int64_t N, const double* __restrict__ x, const double* __restrict__ xu,
+                             const double* __restrict__ xv, const double* __restrict__ a, double* __restrict__ xp) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double* o = xp + j * 10;
+  for (int c = 0; c < 3; ++c) {
+    o[c] = x[c * N + j];
+    o[3 + c] = xu[c * N + j];
+    o[6 + c] = xv[c * N + j];
+  }
+  o[9] = a[j];
+}
+
+namespace {
+
+template <int Q>
+size_t lds_bytes() {
+  const size_t stage = (size_t)waves_for<Q>() * 2 * Q * kStage * sizeof(double);
+  const size_t front = 2 * kMaxCells * sizeof(int2) + 64 * waves_for<Q>() * sizeof(int);
+  const size_t red = (size_t)waves_for<Q>() * 256 * sizeof(double);
+  size_t m = stage > front ? stage : front;
+  return m > red ? m : red;
+}
+
+template <int Q>
+void launch_q(const NWArgs& A, int64_t n, bool parametrix, hipStream_t st, size_t lds_limit) {
+  const size_t lds = lds_bytes<Q>();
+  PMX_REQUIRE(lds + 12 * 1024 <= lds_limit, PMX_ERR_INVALID,
+              "q too large for the local-rule kernel's LDS on this device");
+  const dim3 block(64 * waves_for<Q>());
+  if (parametrix)
+    hipLaunchKernelGGL((k_near_weights<1, Q>), dim3(n), block, lds, st, A);
+  else
+    hipLaunchKernelGGL((k_near_weights<0, Q>), dim3(n), block, lds, st, A);
+  PMX_HIP(hipGetLastError());
+}
+
+void launch_dispatch(int q, const NWArgs& A, int64_t n, bool parametrix, hipStream_t st, size_t lds_limit) {
+  switch (q) {
+    case 2: launch_q<2>(A, n, parametrix, st, lds_limit); break;
+    case 3: launch_q<3>(A, n, parametrix, st, lds_limit); break;
+    case 4: launch_q<4>(A, n, parametrix, st, lds_limit); break;
+    case 5: launch_q<5>(A, n, parametrix, st, lds_limit); break;
+    case 6: launch_q<6>(A, n, parametrix, st, lds_limit); break;
+    case 7: launch_q<7>(A, n, parametrix, st, lds_limit); break;
+    case 8: launch_q<8>(A, n, parametrix, st, lds_limit); break;
+    case 9: launch_q<9>(A, n, parametrix, st, lds_limit); break;
+    case 10: launch_q<10>(A, n, parametrix, st, lds_limit); break;
+    case 11: launch_q<11>(A, n, parametrix, st, lds_limit); break;
+    case 12: launch_q<12>(A, n, parametrix, st, lds_limit); break;
+    case 13: launch_q<13>(A, n, parametrix, st, lds_limit); break;
+    case 14: launch_q<14>(A, n, parametrix, st, lds_limit); break;
+    case 15: launch_q<15>(A, n, parametrix, st, lds_limit); break;
+    case 16: launch_q<16>(A, n, parametrix, st, lds_limit); break;
+    default: PMX_REQUIRE(false, PMX_ERR_INVALID, "q must be in [2, 16]");
+  }
+}
+
+}  // namespace
 
 void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists& nl, const pmx_options& o,
                         bool parametrix, hipStream_t st) {
@@ -517,28 +528,24 @@ void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists&
   PMX_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
   NWArgs A;
   A.N = g.N; A.q = q; A.n_gl = o.n_gl; A.eta = o.eta_near;
-  A.X = g.x.p; A.XU = g.xu_p.p; A.XV = g.xv_p.p; A.a = co.a.p; A.w = g.w.p;
+  DBuf<double> xp;
+  xp.alloc(ctx, (size_t)g.N * 10);
+  hipLaunchKernelGGL(k_interleave, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, (int64_t)g.N, g.x.p,
+                     g.xu_p.p, g.xv_p.p, co.a.p, xp.p);
+  PMX_HIP(hipGetLastError());
+  A.X = g.x.p; A.XP = xp.p; A.a = co.a.p; A.w = g.w.p;
   A.tgt = co.tgt.p; A.tg = co.tg.p;
   A.tn = tab.p; A.cinv = tab.p + q; A.gl_t = tab.p + 2 * q; A.gl_w = tab.p + 2 * q + o.n_gl;
   A.pair_patch = nl.patch.p; A.pair_target = nl.target.p; A.out = out.p; A.err = err.p;
-  const size_t lds_self = (size_t)(2 * q * kLS + kThreads + q2) * sizeof(double);
-  const size_t lds_near = (size_t)(11 * q2 + 10 * q * kNglMax + 3 * kNglMax * q + kThreads) * sizeof(double);
-  const size_t lds = lds_self > lds_near ? lds_self : lds_near;
   int dev = 0;
   PMX_HIP(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   PMX_HIP(hipGetDeviceProperties(&prop, dev));
-  PMX_REQUIRE(lds + 12 * 1024 <= prop.sharedMemPerBlock, PMX_ERR_INVALID,
-              "q too large for the local-rule kernel's LDS on this device");
   const int64_t chunk = 1 << 20;
   for (int64_t p0 = 0; p0 < nl.nnz; p0 += chunk) {
     A.pair0 = p0;
     const int64_t n = nl.nnz - p0 < chunk ? nl.nnz - p0 : chunk;
-    if (parametrix)
-      hipLaunchKernelGGL(k_near_weights<1>, dim3(n), dim3(kThreads), lds, st, A);
-    else
-      hipLaunchKernelGGL(k_near_weights<0>, dim3(n), dim3(kThreads), lds, st, A);
-    PMX_HIP(hipGetLastError());
+    launch_dispatch(q, A, n, parametrix, st, prop.sharedMemPerBlock);
   }
   int herr = 0;
   PMX_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
