@@ -172,7 +172,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--n-rhs", type=int, default=1)
-    ap.add_argument("--k", type=int, default=16, help="cube-sphere patches per face edge (16: 153,600 nodes)")
+    ap.add_argument("--workload", choices=["ellipsoid", "star", "torus"], default="ellipsoid",
+                    help="ellipsoid: 153,600 nodes, 1 RHS (default); star: 525,696 nodes, 1 RHS; "
+                         "torus: wobbly torus, 2,097,152 nodes, 16 RHS")
+    ap.add_argument("--k", type=int, default=16, help="ellipsoid: cube-sphere patches per face edge (16: 153,600 nodes)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -191,7 +194,7 @@ def main():
 
     import torch
     from paper_2401_12501_amd import pmx
-    from paper_2401_12501_amd.inputs import ellipsoid_problem, random_density
+    from paper_2401_12501_amd.inputs import ellipsoid_problem, star_problem, wobbly_torus_problem, random_density
 
     if args.calib_mb:
         src = torch.ones(args.calib_mb * 2 ** 18, device="cuda:0", dtype=torch.float32)
@@ -199,8 +202,22 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prob = ellipsoid_problem(k=args.k, q=10, n_rhs=args.n_rhs)
-    N, n_rhs = prob.n, args.n_rhs
+    if args.workload == "ellipsoid":
+        prob = ellipsoid_problem(k=args.k, q=10, n_rhs=args.n_rhs)
+        n_rhs = args.n_rhs
+        desc = (f"ellipsoid (1, 0.8, 0.6), {prob.surface.n_patches} patches x 10x10 Gauss-Legendre nodes, "
+                f"N={prob.n}, a=exp(0.3 x1 x2)")
+    elif args.workload == "star":
+        prob = star_problem()
+        n_rhs = 1
+        desc = (f"star r = 1 + 0.25 (8 real spherical harmonics, l <= 4), {prob.surface.n_patches} patches x 8x8 "
+                f"Gauss-Legendre nodes, N={prob.n}, a = 2^tanh(smooth seed field)")
+    else:
+        prob = wobbly_torus_problem()
+        n_rhs = prob.f.shape[1]
+        desc = (f"wobbly torus R=1, r=0.4(1+0.2 cos 5t sin 3p), {prob.surface.n_patches} patches x 8x8 "
+                f"Gauss-Legendre nodes, N={prob.n}, a=1+0.5 tanh(sin 3 x1), {n_rhs} right-hand sides")
+    N = prob.n
     log(f"[bench] workload {prob.name} N={N} n_rhs={n_rhs} path={args.path}")
     ctx = pmx.Context(0)
     surf = pmx.Surface.from_inputs(ctx, prob.surface)
@@ -260,7 +277,7 @@ def main():
         avg_s = dom[1][0] / dom[1][1] / 1e3
         launches_per_step = dom[1][1] / args.steps
         achieved = amount / (avg_s * launches_per_step)
-        tb = traffic_bytes(dom[0], n_rhs, args.k)
+        tb = traffic_bytes(dom[0], n_rhs, args.k if args.workload == "ellipsoid" else -1)
         roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": (round(tb / 1e9, 4) if tb else None),
                 "traffic_unit": "GB per launch", "kernel": dom[0],
@@ -292,6 +309,7 @@ def main():
     rng = np.random.default_rng(5)
     tg = np.concatenate([[0, N - 1], rng.choice(N, 10, replace=False)])
     ref = orc.apply_rows(tg, sig_h)
+    f_rows = prob.f[tg] - (prob.f * orc.w[:, None]).sum(0) / orc.w.sum()   # mean-zero data at the rows
     scale = np.abs(ref).max()
     ys = {args.path: y_main, other: y_other} if y_other is not None else {args.path: y_main}
     err = {k: float(np.abs(v[tg] - ref).max() / scale) for k, v in ys.items()}
@@ -301,6 +319,9 @@ def main():
     if not args.no_solve:
         f = torch.tensor(np.ascontiguousarray(prob.f.T), device="cuda:0")
         for path in ("mixed", "fp64"):
+            if path == "fp64" and N * n_rhs > 4_000_000:
+                log(f"[bench] solve fp64 skipped at N*n_rhs = {N * n_rhs} (one FP64 apply is timed above)")
+                continue
             o = pmx.pmx_default_options()
             o.precision = prec[path]
             o.gmres_tol = 1e-8
@@ -314,9 +335,14 @@ def main():
                 continue
             torch.cuda.synchronize()
             dt = time.perf_counter() - ts
-            solve[path] = {"seconds": round(dt, 4), "iters": info[0].iters_total, "ir_steps": info[0].ir_steps,
+            # residual of the returned density in the oracle's discrete system, on the sampled rows
+            s_h = s_out.T if isinstance(s_out, np.ndarray) else s_out.cpu().numpy().T
+            r_rows = f_rows - orc.apply_rows(tg, s_h)
+            solve[path] = {"seconds": round(dt, 4), "iters": max(i.iters_total for i in info),
+                           "ir_steps": max(i.ir_steps for i in info),
                            "applies_fp64": info[0].applies_fp64, "applies_fp32": info[0].applies_low,
-                           "rel_residual": info[0].rel_residual}
+                           "rel_residual": max(i.rel_residual for i in info),
+                           "oracle_rows_rel_residual": float(np.abs(r_rows).max() / np.abs(f_rows).max())}
             log(f"[bench] solve {path}: {dt:.3f} s {solve[path]}")
         if "mixed" in solve:
             solve["solves_per_s_mixed"] = round(1.0 / solve["mixed"]["seconds"], 3)
@@ -327,8 +353,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if args.path == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": f"ellipsoid (1, 0.8, 0.6), {prob.surface.n_patches} patches x 10x10 "
-                               f"Gauss-Legendre nodes, N={N}, a=exp(0.3 x1 x2)", "n_rhs": n_rhs,
+        "config": {"workload": desc, "n_rhs": n_rhs,
                    "path": args.path, "fmm_order": op.opts.fmm_order, "fmm_leaf": op.opts.fmm_leaf},
         "roofline": roof,
         "other_path": ({"path": other, "gpts_per_s": round(N * n_rhs / other_s / 1e9, 4),

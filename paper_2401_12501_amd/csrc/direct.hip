@@ -6,13 +6,16 @@
 // the c = 0 remainder of eq:explicit_remainder with G = log(r) / (2 pi a(x'))
 // written with the target factors A = a/pi, B = a H/pi, g = grad_G a / (2 pi).
 //
-// Each thread owns one target and walks a contiguous chunk of sources.  Source
-// coordinates and densities are the same for every lane of a wavefront, so they
-// are read through the scalar data cache and live in scalar registers; the only
-// per-pair memory traffic is zero.  The pair j = i is removed without a branch:
-// r^2 gets a tiny epsilon, so the self pair has 1/r^2 finite while n.r = g.r = 0
-// make its contribution exactly zero.  Partial sums per source chunk go to
-// part[chunk][rhs][i] and are added in a fixed order afterwards (deterministic).
+// Each thread owns one (or two) targets and walks a contiguous chunk of sources.
+// Before the sum, the sources of a group of NR right-hand sides are packed into
+// rows (x, y, z, qt_1 .. qt_NR, padding): one row is the same for every lane of a
+// wavefront, so it is read with one or two wide loads through the scalar data
+// cache and lives in scalar registers, and consecutive sources share cache lines.
+// The pair kernel is evaluated once per pair for all NR densities.  The pair
+// j = i is removed without a branch: r^2 gets a tiny epsilon, so the self pair has
+// 1/r^2 finite while n.r = h.r = 0 make its contribution exactly zero.  Partial
+// sums per source chunk go to part[chunk][rhs][i] and are added in a fixed order
+// afterwards (deterministic).
 #include "pmx_internal.hpp"
 
 namespace pmx {
@@ -20,20 +23,47 @@ namespace pmx {
 namespace {
 constexpr int kBlock = 256;
 
+// Pointers whose uniform-address loads go through the scalar cache.
+typedef const __attribute__((address_space(4))) double* sdp;
+typedef const __attribute__((address_space(4))) float* sfp;
+
 __device__ __forceinline__ double rcp64(double x) {
   // hardware reciprocal (about 24 correct bits), then one Newton step: 2e-15 relative
   const double r = __builtin_amdgcn_rcp(x);
   return fma(r, fma(-x, r, 1.0), r);
 }
+
+// Row length of a packed source row: x, y, z, NR densities, padded to 16 bytes.
+template <int NR, typename T>
+constexpr int row_len() { return sizeof(T) == 8 ? ((3 + NR + 1) / 2) * 2 : ((3 + NR + 3) / 4) * 4; }
 }  // namespace
 
-// TPL targets per lane (targets i0 and i0 + kBlock of a 2*kBlock target tile): one
-// scalar source load feeds TPL pair evaluations.
+// rows[j] = (x_j, y_j, z_j, q_{r0}[j], ..., q_{r0+NR-1}[j], 0...)
+template <int NR, typename T>
+__global__ void __launch_bounds__(kBlock) k_pack_sources(int64_t N, const T* __restrict__ X, const T* __restrict__ q,
+                                                         int64_t ldq, T* __restrict__ rows) {
+  constexpr int RL = row_len<NR, T>();
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= N) return;
+  T v[RL];
+  v[0] = X[j];
+  v[1] = X[N + j];
+  v[2] = X[2 * N + j];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) v[3 + r] = q[r * ldq + j];
+#pragma unroll
+  for (int c = 3 + NR; c < RL; ++c) v[c] = T(0);
+#pragma unroll
+  for (int c = 0; c < RL; ++c) rows[j * RL + c] = v[c];
+}
+
+// TPL targets per lane (targets i0 and i0 + kBlock of a TPL*kBlock target tile): one
+// source row feeds TPL pair evaluations.
 template <int NR, int TPL>
 __global__ void __launch_bounds__(kBlock) k_direct64(int64_t N, const double* __restrict__ tf,
-                                                     const double* __restrict__ X, const double* __restrict__ qt,
-                                                     int64_t ldq, int64_t chunk, double* __restrict__ part,
-                                                     int64_t ldp, int64_t ldc) {
+                                                     const double* __restrict__ rows, int64_t chunk,
+                                                     double* __restrict__ part, int64_t ldp, int64_t ldc) {
+  constexpr int RL = row_len<NR, double>();
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
   double xi[TPL], yi[TPL], zi[TPL], px[TPL], py[TPL], pz[TPL], hx[TPL], hy[TPL], hz[TPL];
@@ -46,20 +76,16 @@ __global__ void __launch_bounds__(kBlock) k_direct64(int64_t N, const double* __
     px[t] = tf[3 * N + i]; py[t] = tf[4 * N + i]; pz[t] = tf[5 * N + i];
     hx[t] = tf[6 * N + i]; hy[t] = tf[7 * N + i]; hz[t] = tf[8 * N + i];
   }
-  const double* __restrict__ Xs = X;
-  const double* __restrict__ Ys = X + N;
-  const double* __restrict__ Zs = X + 2 * N;
+  const sdp S = (sdp)rows;
   double acc[TPL][NR];
 #pragma unroll
   for (int t = 0; t < TPL; ++t)
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[t][r] = 0.0;
-#pragma unroll 2
+#pragma unroll(NR <= 4 ? 2 : 1)
   for (int64_t j = j0; j < j1; ++j) {
-    const double xs = Xs[j], ys = Ys[j], zs = Zs[j];
-    double q[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) q[r] = qt[r * ldq + j];
+    const sdp row = S + j * RL;
+    const double xs = row[0], ys = row[1], zs = row[2];
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
       const double dx = xi[t] - xs, dy = yi[t] - ys, dz = zi[t] - zs;
@@ -69,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) k_direct64(int64_t N, const double* __
       const double hr = fma(hx[t], dx, fma(hy[t], dy, hz[t] * dz));
       const double v = fma(pr * inv, pr, hr) * inv;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[t][r] = fma(q[r], v, acc[t][r]);
+      for (int r = 0; r < NR; ++r) acc[t][r] = fma(row[3 + r], v, acc[t][r]);
     }
   }
 #pragma unroll
@@ -82,8 +108,9 @@ __global__ void __launch_bounds__(kBlock) k_direct64(int64_t N, const double* __
 
 template <int NR>
 __global__ void __launch_bounds__(kBlock) k_direct32(int64_t N, const float* __restrict__ t32,
-                                                     const float* __restrict__ qt, int64_t ldq, int64_t chunk,
+                                                     const float* __restrict__ rows, int64_t chunk,
                                                      double* __restrict__ part, int64_t ldp, int64_t ldc) {
+  constexpr int RL = row_len<NR, float>();
   const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = i0 < N ? i0 : N - 1;
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
@@ -91,22 +118,21 @@ __global__ void __launch_bounds__(kBlock) k_direct32(int64_t N, const float* __r
   const float xi = t32[i], yi = t32[N + i], zi = t32[2 * N + i];
   const float px = t32[3 * N + i], py = t32[4 * N + i], pz = t32[5 * N + i];
   const float hx = t32[6 * N + i], hy = t32[7 * N + i], hz = t32[8 * N + i];
-  const float* __restrict__ Xs = t32;
-  const float* __restrict__ Ys = t32 + N;
-  const float* __restrict__ Zs = t32 + 2 * N;
+  const sfp S = (sfp)rows;
   float acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0f;
-#pragma unroll 4
+#pragma unroll(NR <= 4 ? 4 : 1)
   for (int64_t j = j0; j < j1; ++j) {
-    const float dx = xi - Xs[j], dy = yi - Ys[j], dz = zi - Zs[j];
+    const sfp row = S + j * RL;
+    const float dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-30f)));
     const float inv = __builtin_amdgcn_rcpf(r2);
     const float pr = fmaf(px, dx, fmaf(py, dy, pz * dz));
     const float hr = fmaf(hx, dx, fmaf(hy, dy, hz * dz));
     const float v = fmaf(pr * inv, pr, hr) * inv;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = fmaf(qt[r * ldq + j], v, acc[r]);
+    for (int r = 0; r < NR; ++r) acc[r] = fmaf(row[3 + r], v, acc[r]);
   }
   if (i0 < N) {
 #pragma unroll
@@ -117,22 +143,25 @@ __global__ void __launch_bounds__(kBlock) k_direct32(int64_t N, const float* __r
 // Representation far field: u_i = sum_{j != i} qt_j log(r_ij) / (2 pi), qt = w sigma / a.
 template <int NR>
 __global__ void __launch_bounds__(kBlock) k_direct_log(int64_t N, const double* __restrict__ X,
-                                                       const double* __restrict__ qt, int64_t ldq, int64_t chunk,
+                                                       const double* __restrict__ rows, int64_t chunk,
                                                        double* __restrict__ part, int64_t ldp, int64_t ldc) {
+  constexpr int RL = row_len<NR, double>();
   const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t i = i0 < N ? i0 : N - 1;
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
   const double xi = X[i], yi = X[N + i], zi = X[2 * N + i];
+  const sdp S = (sdp)rows;
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
   for (int64_t j = j0; j < j1; ++j) {
-    const double dx = xi - X[j], dy = yi - X[N + j], dz = zi - X[2 * N + j];
+    const sdp row = S + j * RL;
+    const double dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const double v = j == i ? 0.0 : 0.5 * log(r2) * 0.15915494309189533577;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = fma(qt[r * ldq + j], v, acc[r]);
+    for (int r = 0; r < NR; ++r) acc[r] = fma(row[3 + r], v, acc[r]);
   }
   if (i0 < N) {
 #pragma unroll
@@ -158,21 +187,32 @@ template <int NR>
 void launch_group(pmx_operator* op, int mode, int n_rhs, int r0, int64_t nc, hipStream_t st) {
   const int64_t N = op->s->g.N;
   const int64_t chunk = (N + nc - 1) / nc;
-  dim3 grid((unsigned)((N + kBlock - 1) / kBlock), (unsigned)nc);
+  const dim3 grid((unsigned)((N + kBlock - 1) / kBlock), (unsigned)nc);
+  const dim3 gN((unsigned)((N + kBlock - 1) / kBlock));
   double* part = op->part.p + (int64_t)r0 * N;
   const int64_t ldc = (int64_t)n_rhs * N;
-  if (mode == 0) {
-    constexpr int TPL = NR <= 2 ? 2 : 1;
-    dim3 g64((unsigned)((N + TPL * kBlock - 1) / (TPL * kBlock)), (unsigned)nc);
-    hipLaunchKernelGGL((k_direct64<NR, TPL>), g64, dim3(kBlock), 0, st, N, op->co.tf64.p, op->s->g.x.p,
-                       op->qt64.p + (int64_t)r0 * N, N, chunk, part, N, ldc);
+  if (mode == 1) {
+    constexpr int RL = row_len<NR, float>();
+    if (op->rows32.n < (size_t)N * RL) op->rows32.alloc(&op->s->ctx->c, (size_t)N * RL);
+    hipLaunchKernelGGL((k_pack_sources<NR, float>), gN, dim3(kBlock), 0, st, N, op->co.tgt32.p,
+                       op->qt32.p + (int64_t)r0 * N, N, op->rows32.p);
+    hipLaunchKernelGGL(k_direct32<NR>, grid, dim3(kBlock), 0, st, N, op->co.tgt32.p, op->rows32.p, chunk, part, N,
+                       ldc);
+  } else {
+    constexpr int RL = row_len<NR, double>();
+    if (op->rows64.n < (size_t)N * RL) op->rows64.alloc(&op->s->ctx->c, (size_t)N * RL);
+    hipLaunchKernelGGL((k_pack_sources<NR, double>), gN, dim3(kBlock), 0, st, N, op->s->g.x.p,
+                       op->qt64.p + (int64_t)r0 * N, N, op->rows64.p);
+    if (mode == 0) {
+      constexpr int TPL = NR <= 2 ? 2 : 1;
+      const dim3 g64((unsigned)((N + TPL * kBlock - 1) / (TPL * kBlock)), (unsigned)nc);
+      hipLaunchKernelGGL((k_direct64<NR, TPL>), g64, dim3(kBlock), 0, st, N, op->co.tf64.p, op->rows64.p, chunk,
+                         part, N, ldc);
+    } else {
+      hipLaunchKernelGGL(k_direct_log<NR>, grid, dim3(kBlock), 0, st, N, op->s->g.x.p, op->rows64.p, chunk, part,
+                         N, ldc);
+    }
   }
-  else if (mode == 1)
-    hipLaunchKernelGGL(k_direct32<NR>, grid, dim3(kBlock), 0, st, N, op->co.tgt32.p, op->qt32.p + (int64_t)r0 * N,
-                       N, chunk, part, N, ldc);
-  else
-    hipLaunchKernelGGL(k_direct_log<NR>, grid, dim3(kBlock), 0, st, N, op->s->g.x.p, op->qt64.p + (int64_t)r0 * N,
-                       N, chunk, part, N, ldc);
   PMX_HIP(hipGetLastError());
 }
 
@@ -184,7 +224,8 @@ void far_direct_mode(pmx_operator* op, int mode, int n_rhs, hipStream_t st) {
   int r0 = 0;
   while (r0 < n_rhs) {
     const int left = n_rhs - r0;
-    if (left >= 8) { launch_group<8>(op, mode, n_rhs, r0, nc, st); r0 += 8; }
+    if (left >= 16) { launch_group<16>(op, mode, n_rhs, r0, nc, st); r0 += 16; }
+    else if (left >= 8) { launch_group<8>(op, mode, n_rhs, r0, nc, st); r0 += 8; }
     else if (left >= 4) { launch_group<4>(op, mode, n_rhs, r0, nc, st); r0 += 4; }
     else if (left >= 2) { launch_group<2>(op, mode, n_rhs, r0, nc, st); r0 += 2; }
     else { launch_group<1>(op, mode, n_rhs, r0, nc, st); r0 += 1; }

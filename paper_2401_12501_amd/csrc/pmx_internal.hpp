@@ -207,6 +207,8 @@ struct pmx_operator {
   pmx::DBuf<double> part;      // far-field partial sums
   pmx::DBuf<double> qt64;      // w sigma / a (FP64)
   pmx::DBuf<float> qt32;       // same in FP32
+  pmx::DBuf<double> rows64;    // packed source rows (x, y, z, densities) of the direct sums
+  pmx::DBuf<float> rows32;
   pmx::DBuf<double> ssum_part; // partial sums of w sigma
   pmx::DBuf<double> ssum;      // s_r = sum_j w_j sigma_rj
   pmx::DBuf<double> phi;       // far field result (FP64 accumulate of FMM output)

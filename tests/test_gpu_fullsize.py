@@ -51,10 +51,27 @@ def check_rows(ctx, prob, n_rhs_64, n_rhs_mixed, n_rows, seed):
     say(f"[fullsize] sampled rows: FP64 rel err {e64:.2e} ({n_rhs_64} rhs), mixed rel err {em:.2e} "
         f"({n_rhs_mixed} rhs)")
     assert e64 <= 1e-12 and em <= 1e-4
+    return op, orc
 
 
 def test_star_full(ctx):
-    check_rows(ctx, star_problem(), 1, 1, 12, seed=41)
+    """Rows of both applies, then the mixed solve (FMM inner GMRES, FP64 refinement) to 1e-8: the
+    returned density's residual in the oracle's discrete system, on sampled rows, is at that level."""
+    from paper_2401_12501_amd import pmx
+    prob = star_problem()
+    op, orc = check_rows(ctx, prob, 1, 1, 12, seed=41)
+    o = pmx.pmx_default_options()
+    o.precision = pmx.PMX_PREC_MIXED_FMM
+    o.ir_tol = 1e-8
+    sig, _, info = op.solve(np.ascontiguousarray(prob.f.T), o)
+    rng = np.random.default_rng(43)
+    tg = np.concatenate([[0, prob.n - 1], rng.choice(prob.n, 10, replace=False)])
+    f0 = prob.f - (prob.f * orc.w[:, None]).sum(0) / orc.w.sum()
+    r = f0[tg] - orc.apply_rows(tg, sig.T)
+    rel = np.abs(r).max() / np.abs(f0[tg]).max()
+    say(f"[fullsize] star mixed solve: ir {info[0].ir_steps}, inner iters {info[0].iters_total}, "
+        f"residual {info[0].rel_residual:.2e}, oracle-row residual {rel:.2e}")
+    assert info[0].rel_residual <= 1e-8 and rel <= 1e-7
 
 
 def test_wobbly_torus_full_16rhs(ctx):

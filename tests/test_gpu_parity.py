@@ -112,6 +112,24 @@ def test_apply_fp64(which, request):
     assert np.array_equal(y1.ravel(), y[:, 1])
 
 
+def test_apply_many_rhs(ragged):
+    """27 right-hand sides run as groups of 16, 8, 2 and 1 through the direct sums (FP64 and FP32):
+    every column matches the oracle, and the FP64 columns equal single-column applies exactly."""
+    from paper_2401_12501_amd import pmx
+    case = ragged
+    sig = random_density(case.prob.n, 27, seed=15)
+    ref = case.A @ sig
+    y = case.op.apply(np.ascontiguousarray(sig.T), pmx.PMX_PREC_FP64_DIRECT).T
+    err = max(wrel(y[:, r], ref[:, r], case.orc.w) for r in range(27))
+    y32 = case.op.apply(np.ascontiguousarray(sig.T), pmx.PMX_PREC_FP32_DIRECT).T
+    err32 = max(wrel(y32[:, r], ref[:, r], case.orc.w) for r in range(27))
+    say(f"[apply64] 27 rhs: max rel err {err:.3e}; FP32 direct {err32:.3e}")
+    assert err <= 1e-12 and err32 <= 1e-5
+    for r in (3, 20, 26):
+        y1 = case.op.apply(np.ascontiguousarray(sig[:, r]), pmx.PMX_PREC_FP64_DIRECT)
+        assert np.array_equal(y1.ravel(), y[:, r])
+
+
 @pytest.mark.parametrize("which", ["ragged", "sphere"])
 def test_apply_fp32_direct(which, request):
     from paper_2401_12501_amd import pmx
