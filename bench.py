@@ -153,6 +153,7 @@ def serving(ctx, n_req: int, slots: int):
         drain(out, lat, status)
         time.sleep(0.0005)
     wall = time.perf_counter() - t0
+    bstats = sv.stats()
     sv.close()
     lat = np.array(lat)
     res = {"requests": n_req, "calibration_requests": n_cal, "slots": slots,
@@ -160,6 +161,8 @@ def serving(ctx, n_req: int, slots: int):
            "solves_per_s": round(len(lat) / wall, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
            "ok": int(sum(1 for s in status + st_cal if s == 0)),
+           "batched_applies": bstats["applies"], "shared_launch_batches": bstats["batches"],
+           "mean_batch": round(bstats["applies"] / max(bstats["batches"], 1), 2), "max_batch": bstats["max_batch"],
            "nodes_min_max": [int(min(p.n for p in reqs)), int(max(p.n for p in reqs))]}
     log(f"[serve] {res}")
     return res

@@ -166,8 +166,11 @@ PMX_API pmx_status pmx_represent(pmx_operator* op, int n_rhs, const double* sigm
  * Each admitted request gets its own stream and worker thread, builds its surface and
  * operator on the device, solves with opts->precision (NULL opts: defaults with the
  * mixed path), and releases its device memory; active requests run concurrently.
- * No call blocks on another request's work.  All input arrays are host memory and are
- * copied by submit. */
+ * The operator applies of all solving requests are batched: every kernel of the apply
+ * path is launched once for all requests that have an apply pending (one argument
+ * record per request), on the server's own stream.  A request that finishes setup
+ * joins the next batch.  No call blocks on another request's work.  All input arrays
+ * are host memory and are copied by submit. */
 PMX_API pmx_status pmx_server_create(pmx_ctx* ctx, const pmx_options* opts, int max_active, pmx_server** out);
 /* Queue one problem (same node layout as pmx_surface_create; a, grad_a, f as in
  * pmx_operator_create and pmx_solve with n_rhs = 1).  want_u: also compute u.
@@ -188,6 +191,10 @@ PMX_API pmx_status pmx_server_poll(pmx_server* sv, uint64_t ticket, double* sigm
 PMX_API pmx_status pmx_server_cancel(pmx_server* sv, uint64_t ticket);
 /* Cancels running requests, waits for their workers, frees the server (NULL-safe). */
 PMX_API void pmx_server_destroy(pmx_server* sv);
+/* Batching counters since creation: number of shared launches of the apply path
+ * (batches), applies they carried, and the largest batch.  Any pointer may be NULL. */
+PMX_API pmx_status pmx_server_get_stats(pmx_server* sv, uint64_t* n_batches, uint64_t* n_applies,
+                                        uint64_t* max_batch);
 
 /* Per-phase device timing of the apply (HIP events recorded on the call's stream around
  * each phase while enabled).  Phases: PMX_PHASE_*.  pmx_profile_read synchronizes the

@@ -16,46 +16,86 @@ double now_seconds() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-void apply_device(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, hipStream_t st) {
+void apply_batch(const std::vector<ApplyJob>& jobs, int precision, int n_rhs, hipStream_t st) {
+  if (jobs.empty()) return;
+  Profiler* prof = jobs.size() == 1 ? &jobs[0].op->prof : nullptr;
+  auto begin = [&](int ph) { return prof ? prof->begin(ph, st) : -1; };
+  auto end = [&](int t) {
+    if (prof) prof->end(t, st);
+  };
   switch (precision) {
     case PMX_PREC_FP64_DIRECT: {
-      int t = op->prof.begin(PMX_PHASE_PREP, st);
-      source_prep(op, sigma, n_rhs, false, st);
-      op->prof.end(t, st);
-      t = op->prof.begin(PMX_PHASE_DIRECT64, st);
-      far_direct(op, true, n_rhs, st);
-      op->prof.end(t, st);
-      t = op->prof.begin(PMX_PHASE_NEAR, st);
-      near_combine(op, sigma, y, n_rhs, far_direct_chunks(op, true), false, false, st);
-      op->prof.end(t, st);
+      int t = begin(PMX_PHASE_PREP);
+      source_prep_batch(jobs, n_rhs, false, st);
+      end(t);
+      t = begin(PMX_PHASE_DIRECT64);
+      far_direct64_batch(jobs, n_rhs, st);
+      end(t);
+      t = begin(PMX_PHASE_NEAR);
+      near_combine_batch(jobs, n_rhs, false, st);
+      end(t);
       break;
     }
     case PMX_PREC_FP32_DIRECT: {
-      int t = op->prof.begin(PMX_PHASE_PREP, st);
-      source_prep(op, sigma, n_rhs, true, st);
-      op->prof.end(t, st);
-      t = op->prof.begin(PMX_PHASE_DIRECT32, st);
-      far_direct(op, false, n_rhs, st);
-      op->prof.end(t, st);
-      t = op->prof.begin(PMX_PHASE_NEAR, st);
-      near_combine(op, sigma, y, n_rhs, far_direct_chunks(op, false), false, false, st);
-      op->prof.end(t, st);
+      for (const ApplyJob& j : jobs) {
+        pmx_operator* op = j.op;
+        Profiler* pf = jobs.size() == 1 ? &op->prof : nullptr;
+        int t = pf ? pf->begin(PMX_PHASE_PREP, st) : -1;
+        source_prep(op, j.sigma, n_rhs, true, st);
+        if (pf) pf->end(t, st);
+        t = pf ? pf->begin(PMX_PHASE_DIRECT32, st) : -1;
+        far_direct(op, false, n_rhs, st);
+        if (pf) pf->end(t, st);
+        t = pf ? pf->begin(PMX_PHASE_NEAR, st) : -1;
+        near_combine(op, j.sigma, j.y, n_rhs, far_direct_chunks(op, false), false, false, st);
+        if (pf) pf->end(t, st);
+      }
       break;
     }
     case PMX_PREC_MIXED_FMM: {
-      if (!op->fmm) fmm_build(op, st);
-      int t = op->prof.begin(PMX_PHASE_PREP, st);
-      source_prep(op, sigma, n_rhs, true, st);
-      op->prof.end(t, st);
-      fmm_far(op, n_rhs, st);   // records its own phases
-      t = op->prof.begin(PMX_PHASE_NEAR, st);
-      near_combine(op, sigma, y, n_rhs, 1, true, false, st);
-      op->prof.end(t, st);
+      for (const ApplyJob& j : jobs)
+        if (!j.op->fmm) fmm_build(j.op, st);
+      int t = begin(PMX_PHASE_PREP);
+      source_prep_batch(jobs, n_rhs, true, st);
+      end(t);
+      fmm_far_batch(jobs, n_rhs, st);   // records its own phases
+      t = begin(PMX_PHASE_NEAR);
+      near_combine_batch(jobs, n_rhs, true, st);
+      end(t);
       break;
     }
     default:
       throw Error(PMX_ERR_INVALID, "unknown precision mode");
   }
+}
+
+void apply_device(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, hipStream_t st) {
+  if (op->batcher) {
+    batcher_apply(op->batcher, op, precision, n_rhs, sigma, y, st);
+    return;
+  }
+  apply_batch({ApplyJob{op, sigma, y}}, precision, n_rhs, st);
+}
+
+void prepare_apply(pmx_operator* op, int precision, int n_rhs, hipStream_t st) {
+  const int64_t N = op->s->g.N;
+  Ctx* ctx = &op->s->ctx->c;
+  const size_t nr = (size_t)n_rhs;
+  const size_t nb = (size_t)((N + 255) / 256);
+  if (op->qt64.n < nr * N) op->qt64.alloc(ctx, nr * N);
+  if (op->qt32.n < nr * N) op->qt32.alloc(ctx, nr * N);
+  if (op->ssum_part.n < nr * nb) op->ssum_part.alloc(ctx, nr * nb);
+  if (op->ssum.n < nr) op->ssum.alloc(ctx, nr);
+  if (precision == PMX_PREC_MIXED_FMM) {
+    if (!op->fmm) fmm_build(op, st);
+    if (op->phi.n < nr * N) op->phi.alloc(ctx, nr * N);
+  }
+  // FP64 residuals of the refinement (and the FP64 path): chunk partials and packed rows
+  const size_t part = (size_t)far_direct_chunks(op, true) * nr * N;
+  if (op->part.n < part) op->part.alloc(ctx, part);
+  const int g = n_rhs >= 16 ? 16 : (n_rhs >= 8 ? 8 : (n_rhs >= 4 ? 4 : (n_rhs >= 2 ? 2 : 1)));
+  const size_t rl = (size_t)((3 + g + 1) / 2) * 2;
+  if (op->rows64.n < rl * N) op->rows64.alloc(ctx, rl * N);
 }
 
 void represent_device(pmx_operator* op, int n_rhs, const double* sigma, double* u, hipStream_t st) {
@@ -221,6 +261,8 @@ pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* gr
 void pmx_operator_destroy(pmx_operator* op) {
   if (!op) return;
   if (op->fmm) fmm_destroy(op->fmm);
+  if (op->ev_ready) (void)hipEventDestroy(op->ev_ready);
+  if (op->ev_done) (void)hipEventDestroy(op->ev_done);
   delete op;
 }
 

@@ -39,44 +39,65 @@ constexpr int row_len() { return sizeof(T) == 8 ? ((3 + NR + 1) / 2) * 2 : ((3 +
 }  // namespace
 
 // rows[j] = (x_j, y_j, z_j, q_{r0}[j], ..., q_{r0+NR-1}[j], 0...)
+template <typename T>
+struct PackArgs {
+  int64_t N;
+  const T* X;        // 3N SoA coordinates
+  const T* q;        // densities of the group's first right-hand side
+  int64_t ldq;
+  T* rows;
+};
+
 template <int NR, typename T>
-__global__ void __launch_bounds__(kBlock) k_pack_sources(int64_t N, const T* __restrict__ X, const T* __restrict__ q,
-                                                         int64_t ldq, T* __restrict__ rows) {
+__global__ void __launch_bounds__(kBlock) k_pack_sources(Group<PackArgs<T>> g) {
   constexpr int RL = row_len<NR, T>();
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  int64_t lb;
+  const PackArgs<T>& A = seg_of(g, blockIdx.x, lb);
+  const int64_t N = A.N;
+  const int64_t j = lb * kBlock + threadIdx.x;
   if (j >= N) return;
   T v[RL];
-  v[0] = X[j];
-  v[1] = X[N + j];
-  v[2] = X[2 * N + j];
+  v[0] = A.X[j];
+  v[1] = A.X[N + j];
+  v[2] = A.X[2 * N + j];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) v[3 + r] = q[r * ldq + j];
+  for (int r = 0; r < NR; ++r) v[3 + r] = A.q[r * A.ldq + j];
 #pragma unroll
   for (int c = 3 + NR; c < RL; ++c) v[c] = T(0);
 #pragma unroll
-  for (int c = 0; c < RL; ++c) rows[j * RL + c] = v[c];
+  for (int c = 0; c < RL; ++c) A.rows[j * RL + c] = v[c];
 }
 
 // TPL targets per lane (targets i0 and i0 + kBlock of a TPL*kBlock target tile): one
-// source row feeds TPL pair evaluations.
+// source row feeds TPL pair evaluations.  Grid: nbx target tiles x nc source chunks.
+struct Direct64Args {
+  int64_t N, chunk, nbx, ldp, ldc;
+  const double* tf;    // 9N target factors
+  const double* rows;  // packed sources
+  double* part;        // part[chunk][rhs][i]
+};
+
 template <int NR, int TPL>
-__global__ void __launch_bounds__(kBlock) k_direct64(int64_t N, const double* __restrict__ tf,
-                                                     const double* __restrict__ rows, int64_t chunk,
-                                                     double* __restrict__ part, int64_t ldp, int64_t ldc) {
+__global__ void __launch_bounds__(kBlock) k_direct64(Group<Direct64Args> g) {
   constexpr int RL = row_len<NR, double>();
-  const int64_t j0 = (int64_t)blockIdx.y * chunk;
-  const int64_t j1 = j0 + chunk < N ? j0 + chunk : N;
+  int64_t lb;
+  const Direct64Args& A = seg_of(g, blockIdx.x, lb);
+  const int64_t N = A.N;
+  const int64_t by = lb / A.nbx, bx = lb - by * A.nbx;
+  const int64_t j0 = by * A.chunk;
+  const int64_t j1 = j0 + A.chunk < N ? j0 + A.chunk : N;
+  const double* __restrict__ tf = A.tf;
   double xi[TPL], yi[TPL], zi[TPL], px[TPL], py[TPL], pz[TPL], hx[TPL], hy[TPL], hz[TPL];
   int64_t it[TPL];
 #pragma unroll
   for (int t = 0; t < TPL; ++t) {
-    it[t] = (int64_t)blockIdx.x * kBlock * TPL + t * kBlock + threadIdx.x;
+    it[t] = bx * kBlock * TPL + t * kBlock + threadIdx.x;
     const int64_t i = it[t] < N ? it[t] : N - 1;
     xi[t] = tf[i]; yi[t] = tf[N + i]; zi[t] = tf[2 * N + i];
     px[t] = tf[3 * N + i]; py[t] = tf[4 * N + i]; pz[t] = tf[5 * N + i];
     hx[t] = tf[6 * N + i]; hy[t] = tf[7 * N + i]; hz[t] = tf[8 * N + i];
   }
-  const sdp S = (sdp)rows;
+  const sdp S = (sdp)A.rows;
   double acc[TPL][NR];
 #pragma unroll
   for (int t = 0; t < TPL; ++t)
@@ -102,7 +123,7 @@ __global__ void __launch_bounds__(kBlock) k_direct64(int64_t N, const double* __
   for (int t = 0; t < TPL; ++t)
     if (it[t] < N) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) part[(int64_t)blockIdx.y * ldc + r * ldp + it[t]] = acc[t][r];
+      for (int r = 0; r < NR; ++r) A.part[by * A.ldc + r * A.ldp + it[t]] = acc[t][r];
     }
 }
 
@@ -182,41 +203,87 @@ int64_t n_chunks_for(int64_t N) {
   return c;
 }
 
-// mode 0: FP64 remainder, 1: FP32 remainder, 2: FP64 log kernel.
+template <int NR, typename T>
+void pack_launch(const std::vector<PackArgs<T>>& recs, hipStream_t st) {
+  std::vector<int64_t> nb;
+  for (const auto& r : recs) nb.push_back((r.N + kBlock - 1) / kBlock);
+  launch_grouped(recs, nb, [&](const Group<PackArgs<T>>& g, int64_t nblk) {
+    hipLaunchKernelGGL((k_pack_sources<NR, T>), dim3((unsigned)nblk), dim3(kBlock), 0, st, g);
+    PMX_HIP(hipGetLastError());
+  });
+}
+
+// FP64 remainder sums of one group of NR right-hand sides (from r0) for several operators.
+template <int NR>
+void direct64_group(const std::vector<pmx_operator*>& ops, int n_rhs, int r0, hipStream_t st) {
+  constexpr int RL = row_len<NR, double>();
+  constexpr int TPL = NR <= 2 ? 2 : 1;
+  std::vector<PackArgs<double>> pk;
+  std::vector<Direct64Args> da;
+  std::vector<int64_t> nb;
+  for (pmx_operator* op : ops) {
+    const int64_t N = op->s->g.N;
+    const int64_t nc = n_chunks_for(N);
+    if (op->rows64.n < (size_t)N * RL) op->rows64.alloc(&op->s->ctx->c, (size_t)N * RL);
+    pk.push_back({N, op->s->g.x.p, op->qt64.p + (int64_t)r0 * N, N, op->rows64.p});
+    const int64_t nbx = (N + TPL * kBlock - 1) / (TPL * kBlock);
+    da.push_back({N, (N + nc - 1) / nc, nbx, N, (int64_t)n_rhs * N, op->co.tf64.p, op->rows64.p,
+                  op->part.p + (int64_t)r0 * N});
+    nb.push_back(nbx * nc);
+  }
+  pack_launch<NR, double>(pk, st);
+  launch_grouped(da, nb, [&](const Group<Direct64Args>& g, int64_t nblk) {
+    hipLaunchKernelGGL((k_direct64<NR, TPL>), dim3((unsigned)nblk), dim3(kBlock), 0, st, g);
+    PMX_HIP(hipGetLastError());
+  });
+}
+
+void direct64_all(const std::vector<pmx_operator*>& ops, int n_rhs, hipStream_t st) {
+  for (pmx_operator* op : ops) {
+    const int64_t N = op->s->g.N;
+    const size_t need = (size_t)n_chunks_for(N) * n_rhs * N;
+    if (op->part.n < need) op->part.alloc(&op->s->ctx->c, need);
+  }
+  int r0 = 0;
+  while (r0 < n_rhs) {
+    const int left = n_rhs - r0;
+    if (left >= 16) { direct64_group<16>(ops, n_rhs, r0, st); r0 += 16; }
+    else if (left >= 8) { direct64_group<8>(ops, n_rhs, r0, st); r0 += 8; }
+    else if (left >= 4) { direct64_group<4>(ops, n_rhs, r0, st); r0 += 4; }
+    else if (left >= 2) { direct64_group<2>(ops, n_rhs, r0, st); r0 += 2; }
+    else { direct64_group<1>(ops, n_rhs, r0, st); r0 += 1; }
+  }
+}
+
+// mode 1: FP32 remainder, 2: FP64 log kernel (single operator).
 template <int NR>
 void launch_group(pmx_operator* op, int mode, int n_rhs, int r0, int64_t nc, hipStream_t st) {
   const int64_t N = op->s->g.N;
   const int64_t chunk = (N + nc - 1) / nc;
   const dim3 grid((unsigned)((N + kBlock - 1) / kBlock), (unsigned)nc);
-  const dim3 gN((unsigned)((N + kBlock - 1) / kBlock));
   double* part = op->part.p + (int64_t)r0 * N;
   const int64_t ldc = (int64_t)n_rhs * N;
   if (mode == 1) {
     constexpr int RL = row_len<NR, float>();
     if (op->rows32.n < (size_t)N * RL) op->rows32.alloc(&op->s->ctx->c, (size_t)N * RL);
-    hipLaunchKernelGGL((k_pack_sources<NR, float>), gN, dim3(kBlock), 0, st, N, op->co.tgt32.p,
-                       op->qt32.p + (int64_t)r0 * N, N, op->rows32.p);
+    pack_launch<NR, float>({{N, op->co.tgt32.p, op->qt32.p + (int64_t)r0 * N, N, op->rows32.p}}, st);
     hipLaunchKernelGGL(k_direct32<NR>, grid, dim3(kBlock), 0, st, N, op->co.tgt32.p, op->rows32.p, chunk, part, N,
                        ldc);
   } else {
     constexpr int RL = row_len<NR, double>();
     if (op->rows64.n < (size_t)N * RL) op->rows64.alloc(&op->s->ctx->c, (size_t)N * RL);
-    hipLaunchKernelGGL((k_pack_sources<NR, double>), gN, dim3(kBlock), 0, st, N, op->s->g.x.p,
-                       op->qt64.p + (int64_t)r0 * N, N, op->rows64.p);
-    if (mode == 0) {
-      constexpr int TPL = NR <= 2 ? 2 : 1;
-      const dim3 g64((unsigned)((N + TPL * kBlock - 1) / (TPL * kBlock)), (unsigned)nc);
-      hipLaunchKernelGGL((k_direct64<NR, TPL>), g64, dim3(kBlock), 0, st, N, op->co.tf64.p, op->rows64.p, chunk,
-                         part, N, ldc);
-    } else {
-      hipLaunchKernelGGL(k_direct_log<NR>, grid, dim3(kBlock), 0, st, N, op->s->g.x.p, op->rows64.p, chunk, part,
-                         N, ldc);
-    }
+    pack_launch<NR, double>({{N, op->s->g.x.p, op->qt64.p + (int64_t)r0 * N, N, op->rows64.p}}, st);
+    hipLaunchKernelGGL(k_direct_log<NR>, grid, dim3(kBlock), 0, st, N, op->s->g.x.p, op->rows64.p, chunk, part, N,
+                       ldc);
   }
   PMX_HIP(hipGetLastError());
 }
 
 void far_direct_mode(pmx_operator* op, int mode, int n_rhs, hipStream_t st) {
+  if (mode == 0) {
+    direct64_all({op}, n_rhs, st);
+    return;
+  }
   const int64_t N = op->s->g.N;
   const int64_t nc = n_chunks_for(N);
   const size_t need = (size_t)nc * n_rhs * N;
@@ -236,6 +303,12 @@ void far_direct_mode(pmx_operator* op, int mode, int n_rhs, hipStream_t st) {
 int far_direct_chunks(const pmx_operator* op, bool) { return (int)n_chunks_for(op->s->g.N); }
 
 void far_direct(pmx_operator* op, bool fp64, int n_rhs, hipStream_t st) { far_direct_mode(op, fp64 ? 0 : 1, n_rhs, st); }
+
+void far_direct64_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
+  std::vector<pmx_operator*> ops;
+  for (const ApplyJob& j : jobs) ops.push_back(j.op);
+  direct64_all(ops, n_rhs, st);
+}
 
 void far_direct_log(pmx_operator* op, int n_rhs, hipStream_t st) { far_direct_mode(op, 2, n_rhs, st); }
 

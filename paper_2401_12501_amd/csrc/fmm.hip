@@ -92,21 +92,47 @@ __device__ __forceinline__ void cheb_weights(const float* __restrict__ t, float 
 }
 
 // qs[k] = qt[perm[k]]
-__global__ void k_permute(int64_t N, const int32_t* __restrict__ perm, const float* __restrict__ q,
-                          float* __restrict__ qs) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < N) qs[k] = q[perm[k]];
+struct PermArgs {
+  int64_t N;
+  const int32_t* perm;
+  const float* q;
+  float* qs;
+};
+
+__global__ void __launch_bounds__(256) k_permute(Group<PermArgs> g) {
+  int64_t lb;
+  const PermArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t k = lb * 256 + threadIdx.x;
+  if (k < A.N) A.qs[k] = A.q[A.perm[k]];
 }
 
 // P2M: one block per leaf; thread m accumulates over the leaf's sources.
+struct P2MArgs {
+  int64_t leaf_off, N;
+  float h;
+  const float* tab;
+  const float* center;
+  const int32_t* leaf_start;
+  const float* pts;
+  const float* qs;
+  float* W;
+};
+
 template <int P>
-__global__ void __launch_bounds__(256) k_p2m(int64_t leaf_off, float h, const float* __restrict__ tab,
-                                             const float* __restrict__ center, const int32_t* __restrict__ leaf_start,
-                                             const float* __restrict__ pts, int64_t N, const float* __restrict__ qs,
-                                             float* __restrict__ W) {
+__global__ void __launch_bounds__(256) k_p2m(Group<P2MArgs> g) {
   constexpr int p = P, p3 = P * P * P;
   __shared__ float sw[256][3 * P + 1];
-  const int leaf = blockIdx.x;
+  int64_t lb;
+  const P2MArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t leaf_off = A.leaf_off, N = A.N;
+  const float h = A.h;
+  const float* __restrict__ tab = A.tab;
+  const float* __restrict__ center = A.center;
+  const int32_t* __restrict__ leaf_start = A.leaf_start;
+  const float* __restrict__ pts = A.pts;
+  const float* __restrict__ qs = A.qs;
+  float* __restrict__ W = A.W;
+  const int leaf = (int)lb;
   const int64_t box = leaf_off + leaf;
   const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
   const float cx = center[3 * box], cy = center[3 * box + 1], cz = center[3 * box + 2];
@@ -132,13 +158,26 @@ __global__ void __launch_bounds__(256) k_p2m(int64_t leaf_off, float h, const fl
 }
 
 // M2M: parent W from its children (one block per parent box of one level).
+struct M2MArgs {
+  int64_t lev_first;
+  const float* tab;
+  const int32_t* child_begin;
+  const int32_t* child_end;
+  const int32_t* octant;
+  float* W;
+};
+
 template <int P>
-__global__ void __launch_bounds__(256) k_m2m(int64_t lev_first, const float* __restrict__ tab,
-                                             const int32_t* __restrict__ child_begin,
-                                             const int32_t* __restrict__ child_end,
-                                             const int32_t* __restrict__ octant, float* __restrict__ W) {
+__global__ void __launch_bounds__(256) k_m2m(Group<M2MArgs> g) {
   constexpr int p = P, p3 = P * P * P;
-  const int64_t Pb = lev_first + blockIdx.x;
+  int64_t lb;
+  const M2MArgs& A = seg_of(g, blockIdx.x, lb);
+  const float* __restrict__ tab = A.tab;
+  const int32_t* __restrict__ child_begin = A.child_begin;
+  const int32_t* __restrict__ child_end = A.child_end;
+  const int32_t* __restrict__ octant = A.octant;
+  float* __restrict__ W = A.W;
+  const int64_t Pb = A.lev_first + lb;
   const float* M1 = tab + p;   // M1[b][k][k'] = S1(t_k, (b ? 0.5 : -0.5) + t_k' / 2)
   const int m = threadIdx.x;
   if (m >= p3) return;
@@ -161,12 +200,24 @@ __global__ void __launch_bounds__(256) k_m2m(int64_t lev_first, const float* __r
 }
 
 // L2L: child L += interpolation of the parent's L (one block per child box of one level).
+struct L2LArgs {
+  int64_t lev_first;
+  const float* tab;
+  const int32_t* parent;
+  const int32_t* octant;
+  float* Lc;
+};
+
 template <int P>
-__global__ void __launch_bounds__(256) k_l2l(int64_t lev_first, const float* __restrict__ tab,
-                                             const int32_t* __restrict__ parent, const int32_t* __restrict__ octant,
-                                             float* __restrict__ Lc) {
+__global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
   constexpr int p = P, p3 = P * P * P;
-  const int64_t C = lev_first + blockIdx.x;
+  int64_t lb;
+  const L2LArgs& A = seg_of(g, blockIdx.x, lb);
+  const float* __restrict__ tab = A.tab;
+  const int32_t* __restrict__ parent = A.parent;
+  const int32_t* __restrict__ octant = A.octant;
+  float* __restrict__ Lc = A.Lc;
+  const int64_t C = A.lev_first + lb;
   const int64_t Pb = parent[C];
   const int o = octant[C];
   const float* M1 = tab + p;
@@ -197,17 +248,31 @@ __global__ void __launch_bounds__(256) k_l2l(int64_t lev_first, const float* __r
 // so no atomics are needed and the result does not depend on scheduling.
 constexpr int kM2LStride = 226;   // LDS row stride (== 2 mod 32: conflict-free B reads)
 
+struct M2LArgs {
+  const float* tab;
+  const int4* items;
+  const int32_t* ps;
+  const float* W;
+  float* slots;
+  double h0;
+};
+
 template <int P>
-__global__ void __launch_bounds__(512) k_m2l(const float* __restrict__ tab, const int4* __restrict__ items,
-                                             const int32_t* __restrict__ pt, const int32_t* __restrict__ ps,
-                                             const float* __restrict__ W, float* __restrict__ slots, double h0) {
+__global__ void __launch_bounds__(512) k_m2l(Group<M2LArgs> g) {
   constexpr int p3 = P * P * P;
+  int64_t lb;
+  const M2LArgs& A = seg_of(g, blockIdx.x, lb);
+  const float* __restrict__ tab = A.tab;
+  const int32_t* __restrict__ ps = A.ps;
+  const float* __restrict__ W = A.W;
+  float* __restrict__ slots = A.slots;
+  const double h0 = A.h0;
   static_assert(p3 <= kM2LStride, "multipole does not fit the LDS row");
   constexpr int n_rt = (p3 + 15) / 16;
   constexpr int n_waves = 8;
   __shared__ float sB[kItemCols * kM2LStride];
   __shared__ float4 sN[p3];
-  const int4 it = items[blockIdx.x];
+  const int4 it = A.items[lb];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ncol = it.y;
   // stage B[m][j] = W[source box of column j][m] as sB[j][m]
@@ -285,14 +350,26 @@ __global__ void __launch_bounds__(512) k_m2l(const float* __restrict__ tab, cons
 // L[T] = sum of T's M2L output slots, in pair order (one block per box of levels >= 2).
 // Each thread owns four consecutive entries (float4); the pair loop is unrolled so the
 // independent slot loads are in flight together.
+struct RedArgs {
+  int64_t box0;
+  const int32_t* rptr;
+  const int32_t* ridx;
+  const float* slots;
+  float* Lc;
+};
+
 template <int P>
-__global__ void __launch_bounds__(512) k_m2l_reduce(int64_t box0, const int32_t* __restrict__ rptr,
-                                                    const int32_t* __restrict__ ridx, const float* __restrict__ slots,
-                                                    float* __restrict__ Lc) {
+__global__ void __launch_bounds__(512) k_m2l_reduce(Group<RedArgs> g) {
   constexpr int n = 9 * P * P * P;
   static_assert(n % 4 == 0, "slot size must be a multiple of 4");
   constexpr int n4 = n / 4;
-  const int64_t b = blockIdx.x;
+  int64_t b;
+  const RedArgs& A = seg_of(g, blockIdx.x, b);
+  const int64_t box0 = A.box0;
+  const int32_t* __restrict__ rptr = A.rptr;
+  const int32_t* __restrict__ ridx = A.ridx;
+  const float* __restrict__ slots = A.slots;
+  float* __restrict__ Lc = A.Lc;
   const int k0 = rptr[b], k1 = rptr[b + 1];
   const float4* __restrict__ s4 = reinterpret_cast<const float4*>(slots);
   for (int e = threadIdx.x; e < n4; e += blockDim.x) {
@@ -308,21 +385,36 @@ __global__ void __launch_bounds__(512) k_m2l_reduce(int64_t box0, const int32_t*
 
 // P2P over the U-list: one wave per (leaf, 64 targets, U-list slot); sources of the
 // slot's neighbour leaf are wave-uniform.  part[slot][k] is summed in slot order by L2P.
-__global__ void __launch_bounds__(64) k_p2p(int64_t N, const int32_t* __restrict__ wleaf,
-                                            const int32_t* __restrict__ wfirst, const int32_t* __restrict__ wslot,
-                                            const int32_t* __restrict__ leaf_start, const int32_t* __restrict__ u_ptr,
-                                            const int32_t* __restrict__ u_idx, const float* __restrict__ pts,
-                                            const float* __restrict__ qs, float* __restrict__ part) {
-  const int leaf = wleaf[blockIdx.x];
-  const int slot = wslot[blockIdx.x];
-  const int k0 = leaf_start[leaf] + wfirst[blockIdx.x];
+struct P2PArgs {
+  int64_t N;
+  const int32_t* wleaf;
+  const int32_t* wfirst;
+  const int32_t* wslot;
+  const int32_t* leaf_start;
+  const int32_t* u_ptr;
+  const int32_t* u_idx;
+  const float* pts;
+  const float* qs;
+  float* part;
+};
+
+__global__ void __launch_bounds__(64) k_p2p(Group<P2PArgs> g) {
+  int64_t lb;
+  const P2PArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t N = A.N;
+  const int32_t* __restrict__ leaf_start = A.leaf_start;
+  const float* __restrict__ pts = A.pts;
+  const float* __restrict__ qs = A.qs;
+  const int leaf = A.wleaf[lb];
+  const int slot = A.wslot[lb];
+  const int k0 = leaf_start[leaf] + A.wfirst[lb];
   const int kend = leaf_start[leaf + 1];
   const int k = k0 + threadIdx.x;
   const int kk = k < kend ? k : kend - 1;
   const float xi = pts[kk], yi = pts[N + kk], zi = pts[2 * N + kk];
   const float px = pts[3 * N + kk], py = pts[4 * N + kk], pz = pts[5 * N + kk];
   const float hx = pts[6 * N + kk], hy = pts[7 * N + kk], hz = pts[8 * N + kk];
-  const int S = u_idx[u_ptr[leaf] + slot];
+  const int S = A.u_idx[A.u_ptr[leaf] + slot];
   const int j0 = leaf_start[S], j1 = leaf_start[S + 1];
   float acc = 0.0f;
 #pragma unroll 4
@@ -334,19 +426,42 @@ __global__ void __launch_bounds__(64) k_p2p(int64_t N, const int32_t* __restrict
     const float hr = fmaf(hx, dx, fmaf(hy, dy, hz * dz));
     acc = fmaf(qs[j], fmaf(pr * inv, pr, hr) * inv, acc);
   }
-  if (k < kend) part[(int64_t)slot * N + k] = acc;
+  if (k < kend) A.part[(int64_t)slot * N + k] = acc;
 }
 
 // L2P + contraction + P2P sum; writes phi (FP64, node order).
+struct L2PArgs {
+  int64_t leaf_off, N;
+  float h;
+  const float* tab;
+  const float* center;
+  const int32_t* leaf_start;
+  const float* pts;
+  const float* Lc;
+  const float* part;
+  const int32_t* u_ptr;
+  const int32_t* perm;
+  double* phi;
+};
+
 template <int P>
-__global__ void __launch_bounds__(256) k_l2p(int64_t leaf_off, float h, const float* __restrict__ tab,
-                                             const float* __restrict__ center, const int32_t* __restrict__ leaf_start,
-                                             const float* __restrict__ pts, int64_t N, const float* __restrict__ Lc,
-                                             const float* __restrict__ part, const int32_t* __restrict__ u_ptr,
-                                             const int32_t* __restrict__ perm, double* __restrict__ phi) {
+__global__ void __launch_bounds__(256) k_l2p(Group<L2PArgs> g) {
   constexpr int p = P, p3 = P * P * P;
   __shared__ float sL[9 * p3];
-  const int leaf = blockIdx.x;
+  int64_t lb;
+  const L2PArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t leaf_off = A.leaf_off, N = A.N;
+  const float h = A.h;
+  const float* __restrict__ tab = A.tab;
+  const float* __restrict__ center = A.center;
+  const int32_t* __restrict__ leaf_start = A.leaf_start;
+  const float* __restrict__ pts = A.pts;
+  const float* __restrict__ Lc = A.Lc;
+  const float* __restrict__ part = A.part;
+  const int32_t* __restrict__ u_ptr = A.u_ptr;
+  const int32_t* __restrict__ perm = A.perm;
+  double* __restrict__ phi = A.phi;
+  const int leaf = (int)lb;
   const int64_t box = leaf_off + leaf;
   for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) sL[e] = Lc[box * 9 * p3 + e];
   __syncthreads();
@@ -677,74 +792,157 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
 
 void fmm_destroy(FMM* f) { delete f; }
 
+// One far-field pass for one right-hand side r of several operators: every stage
+// is one launch over all operators (M2M and L2L: one launch per level).
 template <int P>
-static void fmm_far_p(pmx_operator* op, int n_rhs, hipStream_t st) {
-  FMM* F = op->fmm;
-  const int64_t N = op->s->g.N;
+static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* prof, hipStream_t st) {
   constexpr int p3 = P * P * P;
-  const int L = F->L;
-  const int64_t leaf_off = F->lev_off[L];
-  const float hL = (float)(F->h0 / (double)(1 << L));
-  for (int r = 0; r < n_rhs; ++r) {
-    int t = op->prof.begin(PMX_PHASE_FMM_P2M, st);
-    hipLaunchKernelGGL(k_permute, dim3((N + 255) / 256), dim3(256), 0, st, N, F->perm.p,
-                       op->qt32.p + (int64_t)r * N, F->qs.p);
-    hipLaunchKernelGGL(k_p2m<P>, dim3(F->n_leaves), dim3(256), 0, st, leaf_off, hL, F->tab.p, F->center.p,
-                       F->leaf_start.p, F->pts.p, N, F->qs.p, F->W.p);
-    PMX_HIP(hipGetLastError());
-    op->prof.end(t, st);
-    t = op->prof.begin(PMX_PHASE_FMM_M2M, st);
-    for (int l = L - 1; l >= 2; --l) {
-      const int64_t nb = F->lev_off[l + 1] - F->lev_off[l];
-      hipLaunchKernelGGL(k_m2m<P>, dim3(nb), dim3(256), 0, st, F->lev_off[l], F->tab.p, F->child_begin.p,
-                         F->child_end.p, F->octant.p, F->W.p);
-      PMX_HIP(hipGetLastError());
+  (void)p3;
+  auto phase = [&](int ph) { return prof ? prof->begin(ph, st) : -1; };
+  auto done = [&](int t) { if (prof) prof->end(t, st); };
+  const size_t n = ops.size();
+  int maxL = 0;
+  for (pmx_operator* op : ops) maxL = std::max(maxL, op->fmm->L);
+
+  int t = phase(PMX_PHASE_FMM_P2M);
+  {
+    std::vector<PermArgs> pa;
+    std::vector<P2MArgs> ma;
+    std::vector<int64_t> pb, mb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      const int64_t N = op->s->g.N;
+      pa.push_back({N, F->perm.p, op->qt32.p + (int64_t)r * N, F->qs.p});
+      pb.push_back((N + 255) / 256);
+      const float hL = (float)(F->h0 / (double)(1 << F->L));
+      ma.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->qs.p, F->W.p});
+      mb.push_back(F->n_leaves);
     }
-    op->prof.end(t, st);
-    t = op->prof.begin(PMX_PHASE_FMM_M2L, st);
-    if (F->n_items > 0) {
-      hipLaunchKernelGGL(k_m2l<P>, dim3(F->n_items), dim3(512), 0, st, F->tab.p, F->items.p, F->m2l_t.p,
-                         F->m2l_s.p, F->W.p, F->slots.p, F->h0);
+    launch_grouped(pa, pb, [&](const Group<PermArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_permute, dim3((unsigned)nb), dim3(256), 0, st, g);
       PMX_HIP(hipGetLastError());
+    });
+    launch_grouped(ma, mb, [&](const Group<P2MArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_p2m<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+  t = phase(PMX_PHASE_FMM_M2M);
+  for (int l = maxL - 1; l >= 2; --l) {
+    std::vector<M2MArgs> ma;
+    std::vector<int64_t> mb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      if (l >= F->L) continue;
+      ma.push_back({F->lev_off[l], F->tab.p, F->child_begin.p, F->child_end.p, F->octant.p, F->W.p});
+      mb.push_back(F->lev_off[l + 1] - F->lev_off[l]);
     }
-    {
+    launch_grouped(ma, mb, [&](const Group<M2MArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_m2m<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+  t = phase(PMX_PHASE_FMM_M2L);
+  {
+    std::vector<M2LArgs> la;
+    std::vector<RedArgs> ra;
+    std::vector<int64_t> lb, rb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      la.push_back({F->tab.p, F->items.p, F->m2l_s.p, F->W.p, F->slots.p, F->h0});
+      lb.push_back(F->n_items);
       const int64_t box2 = F->lev_off[2];
-      hipLaunchKernelGGL(k_m2l_reduce<P>, dim3(F->n_boxes - box2), dim3(512), 0, st, box2, F->r_ptr.p, F->r_idx.p,
-                         F->slots.p, F->Lc.p);
-      PMX_HIP(hipGetLastError());
+      ra.push_back({box2, F->r_ptr.p, F->r_idx.p, F->slots.p, F->Lc.p});
+      rb.push_back(F->n_boxes - box2);
     }
-    op->prof.end(t, st);
-    t = op->prof.begin(PMX_PHASE_FMM_L2L, st);
-    for (int l = 3; l <= L; ++l) {
-      const int64_t nb = F->lev_off[l + 1] - F->lev_off[l];
-      hipLaunchKernelGGL(k_l2l<P>, dim3(nb), dim3(256), 0, st, F->lev_off[l], F->tab.p, F->parent.p,
-                         F->octant.p, F->Lc.p);
+    launch_grouped(la, lb, [&](const Group<M2LArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_m2l<P>, dim3((unsigned)nb), dim3(512), 0, st, g);
       PMX_HIP(hipGetLastError());
+    });
+    launch_grouped(ra, rb, [&](const Group<RedArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_m2l_reduce<P>, dim3((unsigned)nb), dim3(512), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+  t = phase(PMX_PHASE_FMM_L2L);
+  for (int l = 3; l <= maxL; ++l) {
+    std::vector<L2LArgs> la;
+    std::vector<int64_t> lb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      if (l > F->L) continue;
+      la.push_back({F->lev_off[l], F->tab.p, F->parent.p, F->octant.p, F->Lc.p});
+      lb.push_back(F->lev_off[l + 1] - F->lev_off[l]);
     }
-    op->prof.end(t, st);
-    t = op->prof.begin(PMX_PHASE_FMM_P2P, st);
-    hipLaunchKernelGGL(k_p2p, dim3(F->n_p2p_waves), dim3(64), 0, st, N, F->p2p_leaf.p, F->p2p_first.p,
-                       F->p2p_slot.p, F->leaf_start.p, F->u_ptr.p, F->u_idx.p, F->pts.p, F->qs.p, F->phis.p);
-    PMX_HIP(hipGetLastError());
-    op->prof.end(t, st);
-    t = op->prof.begin(PMX_PHASE_FMM_L2P, st);
-    hipLaunchKernelGGL(k_l2p<P>, dim3(F->n_leaves), dim3(256), 0, st, leaf_off, hL, F->tab.p, F->center.p,
-                       F->leaf_start.p, F->pts.p, N, F->Lc.p, F->phis.p, F->u_ptr.p, F->perm.p,
-                       op->phi.p + (int64_t)r * N);
-    PMX_HIP(hipGetLastError());
-    op->prof.end(t, st);
+    launch_grouped(la, lb, [&](const Group<L2LArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_l2l<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+  t = phase(PMX_PHASE_FMM_P2P);
+  {
+    std::vector<P2PArgs> pa;
+    std::vector<int64_t> pb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      pa.push_back({op->s->g.N, F->p2p_leaf.p, F->p2p_first.p, F->p2p_slot.p, F->leaf_start.p, F->u_ptr.p,
+                    F->u_idx.p, F->pts.p, F->qs.p, F->phis.p});
+      pb.push_back(F->n_p2p_waves);
+    }
+    launch_grouped(pa, pb, [&](const Group<P2PArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_p2p, dim3((unsigned)nb), dim3(64), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+  t = phase(PMX_PHASE_FMM_L2P);
+  {
+    std::vector<L2PArgs> la;
+    std::vector<int64_t> lb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      const int64_t N = op->s->g.N;
+      const float hL = (float)(F->h0 / (double)(1 << F->L));
+      la.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->Lc.p, F->phis.p,
+                    F->u_ptr.p, F->perm.p, op->phi.p + (int64_t)r * N});
+      lb.push_back(F->n_leaves);
+    }
+    launch_grouped(la, lb, [&](const Group<L2PArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_l2p<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+  (void)n;
+}
+
+void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
+  std::vector<pmx_operator*> ops;
+  int p = 0;
+  for (const ApplyJob& j : jobs) {
+    pmx_operator* op = j.op;
+    PMX_REQUIRE(op->fmm != nullptr, PMX_ERR_INVALID, "FMM tree not built");
+    const int64_t N = op->s->g.N;
+    if (op->phi.n < (size_t)n_rhs * N) op->phi.alloc(&op->s->ctx->c, (size_t)n_rhs * N);
+    PMX_REQUIRE(p == 0 || op->fmm->p == p, PMX_ERR_INVALID, "operators of one batch need the same FMM order");
+    p = op->fmm->p;
+    ops.push_back(op);
+  }
+  Profiler* prof = jobs.size() == 1 ? &jobs[0].op->prof : nullptr;
+  for (int r = 0; r < n_rhs; ++r) {
+    switch (p) {
+      case 4: fmm_far_rhs<4>(ops, r, prof, st); break;
+      case 6: fmm_far_rhs<6>(ops, r, prof, st); break;
+      default: throw Error(PMX_ERR_INVALID, "fmm_order must be 4 or 6");
+    }
   }
 }
 
-void fmm_far(pmx_operator* op, int n_rhs, hipStream_t st) {
-  const int64_t N = op->s->g.N;
-  if (op->phi.n < (size_t)n_rhs * N) op->phi.alloc(&op->s->ctx->c, (size_t)n_rhs * N);
-  switch (op->fmm->p) {
-    case 4: fmm_far_p<4>(op, n_rhs, st); break;
-    case 6: fmm_far_p<6>(op, n_rhs, st); break;
-    default: throw Error(PMX_ERR_INVALID, "fmm_order must be 4 or 6");
-  }
-}
+void fmm_far(pmx_operator* op, int n_rhs, hipStream_t st) { fmm_far_batch({ApplyJob{op, nullptr, nullptr}}, n_rhs, st); }
 
 void fmm_stats(const FMM* f, pmx_operator_stats* s) {
   s->fmm_levels = f->L;

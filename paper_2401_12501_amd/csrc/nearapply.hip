@@ -24,19 +24,29 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 }  // namespace
 
-__global__ void __launch_bounds__(kBlock) k_source_prep(int64_t N, int n_rhs, const double* __restrict__ sigma,
-                                                        const double* __restrict__ w,
-                                                        const double* __restrict__ woa, double* __restrict__ q64,
-                                                        float* __restrict__ q32, double* __restrict__ spart) {
-  const int r = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+struct PrepArgs {
+  int64_t N, nbx;                 // nodes, blocks per right-hand side
+  const double* sigma;
+  const double* w;
+  const double* woa;              // w / a
+  double* q64;
+  float* q32;                     // may be null
+  double* spart;                  // [rhs][nbx]
+};
+
+__global__ void __launch_bounds__(kBlock) k_source_prep(Group<PrepArgs> g) {
+  int64_t lb;
+  const PrepArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t r = lb / A.nbx, bx = lb - r * A.nbx;
+  const int64_t N = A.N;
+  const int64_t i = bx * kBlock + threadIdx.x;
   double ws = 0.0;
   if (i < N) {
-    const double s = sigma[(int64_t)r * N + i];
-    const double qv = woa[i] * s;
-    q64[(int64_t)r * N + i] = qv;
-    if (q32) q32[(int64_t)r * N + i] = (float)qv;
-    ws = w[i] * s;
+    const double s = A.sigma[r * N + i];
+    const double qv = A.woa[i] * s;
+    A.q64[r * N + i] = qv;
+    if (A.q32) A.q32[r * N + i] = (float)qv;
+    ws = A.w[i] * s;
   }
   __shared__ double red[kBlock];
   red[threadIdx.x] = ws;
@@ -45,15 +55,21 @@ __global__ void __launch_bounds__(kBlock) k_source_prep(int64_t N, int n_rhs, co
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) spart[(int64_t)r * gridDim.x + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) A.spart[r * A.nbx + bx] = red[0];
 }
 
 // Fixed-order sum of nb partials per rhs (one block per rhs).
-__global__ void __launch_bounds__(kBlock) k_sum_partials(int64_t nb, const double* __restrict__ part,
-                                                         double* __restrict__ out) {
-  const int r = blockIdx.x;
+struct SumArgs {
+  int64_t nb;
+  const double* part;
+  double* out;
+};
+
+__global__ void __launch_bounds__(kBlock) k_sum_partials(Group<SumArgs> g) {
+  int64_t r;
+  const SumArgs& A = seg_of(g, blockIdx.x, r);
   double acc = 0.0;
-  for (int64_t b = threadIdx.x; b < nb; b += kBlock) acc += part[(int64_t)r * nb + b];
+  for (int64_t b = threadIdx.x; b < A.nb; b += kBlock) acc += A.part[r * A.nb + b];
   __shared__ double red[kBlock];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -61,7 +77,7 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(int64_t nb, const doubl
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[r] = red[0];
+  if (threadIdx.x == 0) A.out[r] = red[0];
 }
 
 // One wavefront per target.  identity != 0: add sigma_i and s_r (the operator A);
@@ -70,27 +86,38 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(int64_t nb, const doubl
 // the streaming loop (C and the gathered sigma) do not wait on index loads.
 // Block index of element e: e / q2 = (e * magic) >> 32, magic = ceil(2^32 / q2)
 // (exact for e < 2^32 / q2; e is below 64 q2 here).
+struct CombineArgs {
+  int64_t N;
+  int q2, n_rhs, r0, n_far, identity;
+  uint32_t magic;
+  const int64_t* ptr;
+  const int32_t* patch;
+  const double* Cb;
+  const double* sigma;
+  const double* far;
+  const double* ssum;
+  double* y;
+};
+
 template <int NR>
-__global__ void __launch_bounds__(kBlock) k_near_combine(int64_t N, int q2, uint32_t magic, int n_rhs, int r0,
-                                                         const int64_t* __restrict__ ptr,
-                                                         const int32_t* __restrict__ patch,
-                                                         const double* __restrict__ Cb,
-                                                         const double* __restrict__ sigma,
-                                                         const double* __restrict__ far, int n_far,
-                                                         const double* __restrict__ ssum, int identity,
-                                                         double* __restrict__ y) {
+__global__ void __launch_bounds__(kBlock) k_near_combine(Group<CombineArgs> g) {
+  int64_t lb;
+  const CombineArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t N = A.N;
+  const int q2 = A.q2;
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+  const int64_t i = lb * (kBlock / kWave) + (threadIdx.x / kWave);
   if (i >= N) return;
-  const int64_t b0 = ptr[i];
-  const int nb = (int)(ptr[i + 1] - b0);
+  const int64_t b0 = A.ptr[i];
+  const int nb = (int)(A.ptr[i + 1] - b0);
+  const double* __restrict__ sigma = A.sigma;
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  for (int g = 0; g < nb; g += kWave) {          // groups of up to 64 near patches
-    const int ng = nb - g < kWave ? nb - g : kWave;
-    const int my_patch = lane < ng ? patch[b0 + g + lane] : 0;
-    const double* Cg = Cb + (b0 + g) * q2;
+  for (int gq = 0; gq < nb; gq += kWave) {          // groups of up to 64 near patches
+    const int ng = nb - gq < kWave ? nb - gq : kWave;
+    const int my_patch = lane < ng ? A.patch[b0 + gq + lane] : 0;
+    const double* __restrict__ Cg = A.Cb + (b0 + gq) * q2;
     const uint32_t len = (uint32_t)(ng * q2);
     // wave-uniform trip count: every lane takes part in the shuffle, loads are predicated
 #pragma unroll 4
@@ -98,14 +125,14 @@ __global__ void __launch_bounds__(kBlock) k_near_combine(int64_t N, int q2, uint
       const uint32_t e = e0 + lane;
       const bool ok = e < len;
       const uint32_t ee = ok ? e : len - 1;
-      const uint32_t blk = (uint32_t)(((uint64_t)ee * magic) >> 32);
+      const uint32_t blk = (uint32_t)(((uint64_t)ee * A.magic) >> 32);
       const uint32_t loc = ee - blk * (uint32_t)q2;
       const int P = __shfl(my_patch, (int)blk, kWave);
       if (ok) {
         const double c = Cg[e];
         const int64_t col = (int64_t)P * q2 + loc;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = fma(c, sigma[(int64_t)(r0 + r) * N + col], acc[r]);
+        for (int r = 0; r < NR; ++r) acc[r] = fma(c, sigma[(int64_t)(A.r0 + r) * N + col], acc[r]);
       }
     }
   }
@@ -114,13 +141,13 @@ __global__ void __launch_bounds__(kBlock) k_near_combine(int64_t N, int q2, uint
   if (lane == 0) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const int rr = r0 + r;
+      const int rr = A.r0 + r;
       double v = acc[r];
       double f = 0.0;
-      for (int c = 0; c < n_far; ++c) f += far[((int64_t)c * n_rhs + rr) * N + i];
+      for (int c = 0; c < A.n_far; ++c) f += A.far[((int64_t)c * A.n_rhs + rr) * N + i];
       v += f;
-      if (identity) v += sigma[(int64_t)rr * N + i] + ssum[rr];
-      y[(int64_t)rr * N + i] = v;
+      if (A.identity) v += sigma[(int64_t)rr * N + i] + A.ssum[rr];
+      A.y[(int64_t)rr * N + i] = v;
     }
   }
 }
@@ -146,7 +173,8 @@ __global__ void k_sub_mean(int64_t N, double* __restrict__ u, const double* __re
   if (i < N) u[(int64_t)r * N + i] -= s[r] / area;
 }
 
-void source_prep(pmx_operator* op, const double* sigma, int n_rhs, bool need32, hipStream_t st) {
+namespace {
+void size_prep_buffers(pmx_operator* op, int n_rhs, bool need32) {
   const int64_t N = op->s->g.N;
   Ctx* ctx = &op->s->ctx->c;
   const int64_t nb = (N + kBlock - 1) / kBlock;
@@ -154,38 +182,100 @@ void source_prep(pmx_operator* op, const double* sigma, int n_rhs, bool need32, 
   if (need32 && op->qt32.n < (size_t)n_rhs * N) op->qt32.alloc(ctx, (size_t)n_rhs * N);
   if (op->ssum_part.n < (size_t)n_rhs * nb) op->ssum_part.alloc(ctx, (size_t)n_rhs * nb);
   if (op->ssum.n < (size_t)n_rhs) op->ssum.alloc(ctx, n_rhs);
-  hipLaunchKernelGGL(k_source_prep, dim3(nb, n_rhs), dim3(kBlock), 0, st, N, n_rhs, sigma, op->s->g.w.p,
-                     op->co.w_over_a.p, op->qt64.p, need32 ? op->qt32.p : (float*)nullptr, op->ssum_part.p);
-  PMX_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sum_partials, dim3(n_rhs), dim3(kBlock), 0, st, nb, op->ssum_part.p, op->ssum.p);
-  PMX_HIP(hipGetLastError());
+}
+}  // namespace
+
+void source_prep_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool need32, hipStream_t st) {
+  std::vector<PrepArgs> pa;
+  std::vector<SumArgs> sa;
+  std::vector<int64_t> pb, sb;
+  for (const ApplyJob& j : jobs) {
+    pmx_operator* op = j.op;
+    size_prep_buffers(op, n_rhs, need32);
+    const int64_t N = op->s->g.N, nb = (N + kBlock - 1) / kBlock;
+    pa.push_back({N, nb, j.sigma, op->s->g.w.p, op->co.w_over_a.p, op->qt64.p, need32 ? op->qt32.p : nullptr,
+                  op->ssum_part.p});
+    pb.push_back(nb * n_rhs);
+    sa.push_back({nb, op->ssum_part.p, op->ssum.p});
+    sb.push_back(n_rhs);
+  }
+  launch_grouped(pa, pb, [&](const Group<PrepArgs>& g, int64_t nblk) {
+    hipLaunchKernelGGL(k_source_prep, dim3((unsigned)nblk), dim3(kBlock), 0, st, g);
+    PMX_HIP(hipGetLastError());
+  });
+  launch_grouped(sa, sb, [&](const Group<SumArgs>& g, int64_t nblk) {
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)nblk), dim3(kBlock), 0, st, g);
+    PMX_HIP(hipGetLastError());
+  });
 }
 
+void source_prep(pmx_operator* op, const double* sigma, int n_rhs, bool need32, hipStream_t st) {
+  source_prep_batch({ApplyJob{op, sigma, nullptr}}, n_rhs, need32, st);
+}
+
+namespace {
 template <int NR>
-static void combine_group(pmx_operator* op, const double* sigma, double* y, int n_rhs, int r0, int n_far,
-                          const double* far, bool parametrix, hipStream_t st) {
-  const int64_t N = op->s->g.N;
-  const int q2 = op->s->g.q * op->s->g.q;
-  const int64_t nb = (N + (kBlock / kWave) - 1) / (kBlock / kWave);
-  const uint32_t magic = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)q2 - 1) / (uint64_t)q2);
-  hipLaunchKernelGGL(k_near_combine<NR>, dim3(nb), dim3(kBlock), 0, st, N, q2, magic, n_rhs, r0, op->nl.ptr.p,
-                     op->nl.patch.p, parametrix ? op->nl.D.p : op->nl.C.p, sigma, far, n_far, op->ssum.p,
-                     parametrix ? 0 : 1, y);
-  PMX_HIP(hipGetLastError());
+void combine_launch(const std::vector<CombineArgs>& recs, hipStream_t st) {
+  std::vector<int64_t> nb;
+  for (const CombineArgs& c : recs) nb.push_back((c.N + (kBlock / kWave) - 1) / (kBlock / kWave));
+  launch_grouped(recs, nb, [&](const Group<CombineArgs>& g, int64_t nblk) {
+    hipLaunchKernelGGL(k_near_combine<NR>, dim3((unsigned)nblk), dim3(kBlock), 0, st, g);
+    PMX_HIP(hipGetLastError());
+  });
 }
 
-void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, int n_part, bool use_phi,
-                  bool parametrix, hipStream_t st) {
-  const double* far = use_phi ? op->phi.p : op->part.p;
-  const int n_far = use_phi ? 1 : n_part;
+CombineArgs combine_args(pmx_operator* op, const double* sigma, double* y, int n_rhs, int r0, int n_far,
+                         const double* far, bool parametrix) {
+  const int q2 = op->s->g.q * op->s->g.q;
+  CombineArgs c;
+  c.N = op->s->g.N;
+  c.q2 = q2;
+  c.n_rhs = n_rhs;
+  c.r0 = r0;
+  c.n_far = n_far;
+  c.identity = parametrix ? 0 : 1;
+  c.magic = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)q2 - 1) / (uint64_t)q2);
+  c.ptr = op->nl.ptr.p;
+  c.patch = op->nl.patch.p;
+  c.Cb = parametrix ? op->nl.D.p : op->nl.C.p;
+  c.sigma = sigma;
+  c.far = far;
+  c.ssum = op->ssum.p;
+  c.y = y;
+  return c;
+}
+
+// Near correction and combination for several operators; n_far[k] partial far fields each.
+void combine_all(const std::vector<ApplyJob>& jobs, const std::vector<int>& n_far, bool use_phi, bool parametrix,
+                 int n_rhs, hipStream_t st) {
   int r0 = 0;
   while (r0 < n_rhs) {
     const int left = n_rhs - r0;
-    if (left >= 8) { combine_group<8>(op, sigma, y, n_rhs, r0, n_far, far, parametrix, st); r0 += 8; }
-    else if (left >= 4) { combine_group<4>(op, sigma, y, n_rhs, r0, n_far, far, parametrix, st); r0 += 4; }
-    else if (left >= 2) { combine_group<2>(op, sigma, y, n_rhs, r0, n_far, far, parametrix, st); r0 += 2; }
-    else { combine_group<1>(op, sigma, y, n_rhs, r0, n_far, far, parametrix, st); r0 += 1; }
+    const int nr = left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
+    std::vector<CombineArgs> recs;
+    for (size_t k = 0; k < jobs.size(); ++k) {
+      pmx_operator* op = jobs[k].op;
+      recs.push_back(combine_args(op, jobs[k].sigma, jobs[k].y, n_rhs, r0, n_far[k], use_phi ? op->phi.p : op->part.p,
+                                  parametrix));
+    }
+    if (nr == 8) combine_launch<8>(recs, st);
+    else if (nr == 4) combine_launch<4>(recs, st);
+    else if (nr == 2) combine_launch<2>(recs, st);
+    else combine_launch<1>(recs, st);
+    r0 += nr;
   }
+}
+}  // namespace
+
+void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, int n_part, bool use_phi,
+                  bool parametrix, hipStream_t st) {
+  combine_all({ApplyJob{op, sigma, y}}, {use_phi ? 1 : n_part}, use_phi, parametrix, n_rhs, st);
+}
+
+void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool use_phi, hipStream_t st) {
+  std::vector<int> nf;
+  for (const ApplyJob& j : jobs) nf.push_back(use_phi ? 1 : far_direct_chunks(j.op, true));
+  combine_all(jobs, nf, use_phi, false, n_rhs, st);
 }
 
 void weighted_mean_remove(pmx_operator* op, double* u, int n_rhs, hipStream_t st) {
@@ -197,7 +287,11 @@ void weighted_mean_remove(pmx_operator* op, double* u, int n_rhs, hipStream_t st
   s.alloc(ctx, n_rhs);
   hipLaunchKernelGGL(k_wdot_partial, dim3(nb, n_rhs), dim3(kBlock), 0, st, N, u, op->s->g.w.p, op->ssum_part.p);
   PMX_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sum_partials, dim3(n_rhs), dim3(kBlock), 0, st, nb, op->ssum_part.p, s.p);
+  Group<SumArgs> g;
+  g.n = 1;
+  g.off[1] = n_rhs;
+  g.a[0] = SumArgs{nb, op->ssum_part.p, s.p};
+  hipLaunchKernelGGL(k_sum_partials, dim3(n_rhs), dim3(kBlock), 0, st, g);
   PMX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_sub_mean, dim3(nb, n_rhs), dim3(kBlock), 0, st, N, u, s.p, op->s->g.area);
   PMX_HIP(hipGetLastError());

@@ -12,6 +12,8 @@
 
 #include "../../include/pmx.h"
 
+struct pmx_batcher;
+
 namespace pmx {
 
 // ----------------------------------------------------------------------------- errors
@@ -147,6 +149,51 @@ struct NearLists {
 
 struct FMM;  // fmm.hip
 
+// ----------------------------------------------------------------------------- grouped launches
+// One launch serves up to kMaxSeg operators: segment s owns the blocks
+// [off[s], off[s + 1]) of the grid and its own argument record.  A single-operator
+// launch is a group of one.  The arguments travel by value in the kernel
+// arguments, so forming a group needs no device memory.
+constexpr int kMaxSeg = 8;
+
+template <class A>
+struct Group {
+  int n = 0;
+  int64_t off[kMaxSeg + 1] = {};
+  A a[kMaxSeg];
+};
+
+// Segment of block b and the block's index inside it.
+template <class A>
+__device__ __forceinline__ const A& seg_of(const Group<A>& g, int64_t b, int64_t& local) {
+  int s = 0;
+  while (s + 1 < g.n && b >= g.off[s + 1]) ++s;
+  local = b - g.off[s];
+  return g.a[s];
+}
+
+// Launch `fn(group, total_blocks)` for the records in chunks of kMaxSeg; segments
+// with no blocks are left out.
+template <class A, class F>
+void launch_grouped(const std::vector<A>& recs, const std::vector<int64_t>& blocks, F fn) {
+  Group<A> g;
+  int64_t total = 0;
+  auto flush = [&]() {
+    if (g.n > 0 && total > 0) fn(g, total);
+    g = Group<A>();
+    total = 0;
+  };
+  for (size_t k = 0; k < recs.size(); ++k) {
+    if (blocks[k] <= 0) continue;
+    if (g.n == kMaxSeg) flush();
+    g.a[g.n] = recs[k];
+    g.off[g.n] = total;
+    total += blocks[k];
+    g.off[++g.n] = total;
+  }
+  flush();
+}
+
 // Optional per-phase timing with HIP events on the launch stream.
 struct Profiler {
   bool on = false;
@@ -215,9 +262,18 @@ struct pmx_operator {
   pmx::DBuf<double> io_a, io_b;  // staging for host arrays
   pmx::Profiler prof;
   const std::atomic<int>* cancel = nullptr;   // set by the server: abandon the solve when nonzero
+  struct pmx_batcher* batcher = nullptr;      // set by the server: applies join shared launches
+  hipEvent_t ev_ready = nullptr, ev_done = nullptr;   // hand-over events of batched applies
 };
 
 namespace pmx {
+
+// One operator apply y = A sigma of a batch (device arrays).
+struct ApplyJob {
+  pmx_operator* op;
+  const double* sigma;
+  double* y;
+};
 
 // geometry.hip
 void build_geometry(Ctx* ctx, Geometry& g, const double* x, const double* xu, const double* xv, const double* xuu,
@@ -235,9 +291,21 @@ void far_direct_log(pmx_operator* op, int n_rhs, hipStream_t st);          // re
 void source_prep(pmx_operator* op, const double* sigma, int n_rhs, bool need32, hipStream_t st);
 void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, int n_part, bool use_phi,
                   bool parametrix, hipStream_t st);
+void source_prep_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool need32, hipStream_t st);
+void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool use_phi, hipStream_t st);
+void far_direct64_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);
 void weighted_mean_remove(pmx_operator* op, double* u, int n_rhs, hipStream_t st);
-// apply.cpp
+// capi.hip
+// One operator apply y = A sigma (device arrays); through the server's batcher when one is set.
 void apply_device(pmx_operator* op, int precision, int n_rhs, const double* sigma_d, double* y_d, hipStream_t st);
+// Applies of several operators (same precision and n_rhs) whose every kernel is one shared launch.
+void apply_batch(const std::vector<ApplyJob>& jobs, int precision, int n_rhs, hipStream_t st);
+// Sizes the per-operator scratch of the apply path (no allocation happens in later applies).
+void prepare_apply(pmx_operator* op, int precision, int n_rhs, hipStream_t st);
+// serve.cpp: hands one apply to the server's batcher, which runs it inside a shared launch
+// on its own stream; the caller's stream then waits for that launch.
+void batcher_apply(pmx_batcher* b, pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y,
+                   hipStream_t st);
 void represent_device(pmx_operator* op, int n_rhs, const double* sigma_d, double* u_d, hipStream_t st);
 // krylov.hip
 struct SolveResult {
@@ -252,6 +320,7 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
 void fmm_build(pmx_operator* op, hipStream_t st);
 void fmm_destroy(FMM* f);
 void fmm_far(pmx_operator* op, int n_rhs, hipStream_t st);   // writes op->phi (FP64, n_rhs * N)
+void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);
 void fmm_stats(const FMM* f, pmx_operator_stats* s);
 uint64_t fmm_bytes(const FMM* f);
 

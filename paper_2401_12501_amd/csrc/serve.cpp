@@ -6,10 +6,19 @@
 // HBM budget; each admitted request gets its own HIP stream and worker thread,
 // which builds its surface and operator (geometry, near lists, correction
 // blocks, FMM tree), keeps them and its Krylov state resident while it solves,
-// then releases them.  Work of all active requests is in flight on the device
-// at once, so a request that arrives while others run starts as soon as a slot
-// and memory are free.  Every kernel of the path reduces in a fixed order, so a
-// request's result does not depend on what else runs beside it.
+// then releases them.
+//
+// Operator applies of all solving requests are batched: a worker hands each
+// apply (GMRES matvec or refinement residual) to the server's batcher and
+// blocks until it is launched.  The batcher collects the applies that are
+// pending (it waits until every solving request has one, or a short window has
+// passed), makes its stream wait for each request's inputs, and runs every
+// kernel of the apply path once for all of them (grouped launches, one argument
+// record per request); the workers' streams then wait for that launch and carry
+// on with their own Krylov updates.  Requests that arrive while others are on the
+// GPU join the next batch once their setup is done.  Every kernel reduces in a
+// fixed order and a grouped launch computes each request's data exactly as a
+// single launch would, so a request's result does not depend on what else runs.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -51,8 +60,34 @@ struct Request {
 
 }  // namespace
 
+// Applies waiting for the next shared launch.
+struct pmx_batcher {
+  struct Pending {
+    pmx_operator* op;
+    int precision, n_rhs;
+    const double* sigma;
+    double* y;
+    hipEvent_t ready, done;
+    bool launched = false;
+    pmx_status code = PMX_OK;
+    std::string err;
+  };
+  int device = 0;
+  hipStream_t st = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::vector<Pending*> pending;
+  int solving = 0;                 // requests between the start and the end of their solve
+  bool stop = false;
+  std::thread thr;
+  double window_s = 500e-6;        // longest wait for the remaining solving requests
+  // statistics
+  uint64_t n_batches = 0, n_applies = 0, max_batch = 0;
+};
+
 struct pmx_server {
   pmx_ctx* ctx = nullptr;
+  pmx_batcher* batcher = nullptr;
   pmx_options opts{};
   int max_active = 1;
   uint64_t next_id = 1;
@@ -71,7 +106,71 @@ uint64_t estimate_bytes(const pmx_options& o, int64_t N, int q, bool want_u) {
   return (uint64_t)(per_node * (double)N) + (16u << 20);
 }
 
-void run_request(pmx_ctx* ctx, pmx_options opts, Request* r) {
+void batcher_loop(pmx_batcher* b) {
+  (void)hipSetDevice(b->device);
+  std::unique_lock<std::mutex> lk(b->mu);
+  while (true) {
+    b->cv_work.wait(lk, [&] { return b->stop || !b->pending.empty(); });
+    if (b->stop && b->pending.empty()) break;
+    // wait (bounded) until every solving request has an apply pending
+    const auto t0 = std::chrono::steady_clock::now();
+    const auto limit = t0 + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                std::chrono::duration<double>(b->window_s));
+    b->cv_work.wait_until(lk, limit, [&] { return b->stop || (int)b->pending.size() >= b->solving; });
+    std::vector<pmx_batcher::Pending*> batch;
+    batch.swap(b->pending);
+    lk.unlock();
+    // group by precision and right-hand-side count; each group is one set of shared launches
+    std::vector<bool> taken(batch.size(), false);
+    for (size_t k = 0; k < batch.size(); ++k) {
+      if (taken[k]) continue;
+      std::vector<pmx_batcher::Pending*> grp;
+      for (size_t m = k; m < batch.size(); ++m)
+        if (!taken[m] && batch[m]->precision == batch[k]->precision && batch[m]->n_rhs == batch[k]->n_rhs) {
+          taken[m] = true;
+          grp.push_back(batch[m]);
+        }
+      std::vector<pmx::ApplyJob> jobs;
+      pmx_status code = PMX_OK;
+      std::string err;
+      try {
+        for (auto* p : grp) {
+          PMX_HIP(hipStreamWaitEvent(b->st, p->ready, 0));
+          jobs.push_back(pmx::ApplyJob{p->op, p->sigma, p->y});
+        }
+        pmx::apply_batch(jobs, grp[0]->precision, grp[0]->n_rhs, b->st);
+      } catch (const pmx::Error& e) {
+        code = e.code;
+        err = e.what();
+      } catch (const std::exception& e) {
+        code = PMX_ERR_DEVICE;
+        err = e.what();
+      }
+      for (auto* p : grp) {
+        if (code == PMX_OK && hipEventRecord(p->done, b->st) != hipSuccess) {
+          code = PMX_ERR_DEVICE;
+          err = "cannot record the batch completion event";
+        }
+        p->code = code;
+        p->err = err;
+      }
+    }
+    lk.lock();
+    b->n_batches++;
+    b->n_applies += batch.size();
+    if (batch.size() > b->max_batch) b->max_batch = batch.size();
+    for (auto* p : batch) p->launched = true;
+    b->cv_done.notify_all();
+  }
+}
+
+void solving_delta(pmx_batcher* b, int d) {
+  std::lock_guard<std::mutex> lk(b->mu);
+  b->solving += d;
+  b->cv_work.notify_all();
+}
+
+void run_request(pmx_ctx* ctx, pmx_options opts, Request* r, pmx_batcher* batcher) {
   hipStream_t st = nullptr;
   pmx_surface* s = nullptr;
   pmx_operator* op = nullptr;
@@ -90,11 +189,27 @@ void run_request(pmx_ctx* ctx, pmx_options opts, Request* r) {
                                      r->xuu.data(), r->xuv.data(), r->xvv.data(), PMX_MEM_HOST, st, &s);
   if (rc == PMX_OK) rc = pmx_operator_create(s, r->a.data(), r->ga.data(), &opts, PMX_MEM_HOST, st, &op);
   if (rc == PMX_OK) {
+    try {
+      pmx::prepare_apply(op, opts.precision, 1, st);   // FMM tree and apply scratch, before joining batches
+    } catch (const pmx::Error& e) {
+      pmx::set_last_error(e.what());
+      rc = e.code;
+    }
+  }
+  if (rc == PMX_OK) {
     op->cancel = &r->cancel;
     r->sigma.assign(r->N, 0.0);
     if (r->want_u) r->u.assign(r->N, 0.0);
+    if (batcher) {
+      op->batcher = batcher;
+      solving_delta(batcher, +1);
+    }
     rc = pmx_solve(op, &opts, 1, r->f.data(), r->sigma.data(), 0, r->want_u ? r->u.data() : nullptr, PMX_MEM_HOST,
                    st, &r->info);
+    if (batcher) {
+      solving_delta(batcher, -1);
+      op->batcher = nullptr;
+    }
   }
   if (rc != PMX_OK) fail(rc); else r->status = PMX_OK;
   pmx_operator_destroy(op);
@@ -137,6 +252,16 @@ pmx_status pmx_server_create(pmx_ctx* ctx, const pmx_options* opts, int max_acti
   sv->ctx = ctx;
   if (opts) sv->opts = *opts; else { pmx_default_options(&sv->opts); sv->opts.precision = PMX_PREC_MIXED_FMM; }
   sv->max_active = max_active;
+  auto* b = new pmx_batcher;
+  b->device = ctx->c.device;
+  if (hipSetDevice(b->device) != hipSuccess || hipStreamCreate(&b->st) != hipSuccess) {
+    delete b;
+    delete sv;
+    pmx::set_last_error("cannot create the batch stream");
+    return PMX_ERR_DEVICE;
+  }
+  b->thr = std::thread(batcher_loop, b);
+  sv->batcher = b;
   *out = sv;
   return PMX_OK;
 }
@@ -194,7 +319,7 @@ pmx_status pmx_server_step(pmx_server* sv, int* n_active, int* n_queued) {
     r->t_admit = now_s();
     sv->reserved += r->est_bytes;
     sv->active[r->id] = r;
-    r->worker = std::thread(run_request, sv->ctx, sv->opts, r.get());
+    r->worker = std::thread(run_request, sv->ctx, sv->opts, r.get(), sv->batcher);
   }
   if (n_active) *n_active = (int)sv->active.size();
   if (n_queued) *n_queued = (int)sv->queue.size();
@@ -253,6 +378,18 @@ pmx_status pmx_server_cancel(pmx_server* sv, uint64_t ticket) {
   return PMX_ERR_INVALID;
 }
 
+pmx_status pmx_server_get_stats(pmx_server* sv, uint64_t* n_batches, uint64_t* n_applies, uint64_t* max_batch) {
+  if (!sv || !sv->batcher) {
+    pmx::set_last_error("null server");
+    return PMX_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(sv->batcher->mu);
+  if (n_batches) *n_batches = sv->batcher->n_batches;
+  if (n_applies) *n_applies = sv->batcher->n_applies;
+  if (max_batch) *max_batch = sv->batcher->max_batch;
+  return PMX_OK;
+}
+
 void pmx_server_destroy(pmx_server* sv) {
   if (!sv) return;
   {
@@ -261,7 +398,56 @@ void pmx_server_destroy(pmx_server* sv) {
   }
   for (auto& kv : sv->active)
     if (kv.second->worker.joinable()) kv.second->worker.join();
+  if (pmx_batcher* b = sv->batcher) {
+    {
+      std::lock_guard<std::mutex> lk(b->mu);
+      b->stop = true;
+      b->cv_work.notify_all();
+    }
+    if (b->thr.joinable()) b->thr.join();
+    (void)hipStreamSynchronize(b->st);
+    (void)hipStreamDestroy(b->st);
+    delete b;
+  }
   delete sv;
 }
 
 }  // extern "C"
+
+namespace pmx {
+
+void batcher_apply(pmx_batcher* b, pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y,
+                   hipStream_t st) {
+  pmx_batcher::Pending p;
+  p.op = op;
+  p.precision = precision;
+  p.n_rhs = n_rhs;
+  p.sigma = sigma;
+  p.y = y;
+  // the operator's two events are reused: it has at most one apply in flight, and each
+  // record happens after the other stream's wait on the previous record was enqueued
+  if (!op->ev_ready) PMX_HIP(hipEventCreateWithFlags(&op->ev_ready, hipEventDisableTiming));
+  if (!op->ev_done) PMX_HIP(hipEventCreateWithFlags(&op->ev_done, hipEventDisableTiming));
+  p.ready = op->ev_ready;
+  p.done = op->ev_done;
+  pmx_status code = PMX_OK;
+  std::string err;
+  if (hipEventRecord(p.ready, st) != hipSuccess) {
+    code = PMX_ERR_DEVICE;
+    err = "cannot record the apply input event";
+  } else {
+    std::unique_lock<std::mutex> lk(b->mu);
+    b->pending.push_back(&p);
+    b->cv_work.notify_all();
+    b->cv_done.wait(lk, [&] { return p.launched; });
+    code = p.code;
+    err = p.err;
+  }
+  if (code == PMX_OK && hipStreamWaitEvent(st, p.done, 0) != hipSuccess) {
+    code = PMX_ERR_DEVICE;
+    err = "cannot wait for the batched apply";
+  }
+  if (code != PMX_OK) throw Error(code, err);
+}
+
+}  // namespace pmx

@@ -76,6 +76,7 @@ _SIGS = {
     "pmx_server_poll": (C.c_int32, [_vp, C.c_uint64, _vp, _vp, C.POINTER(pmx_info), _vp]),
     "pmx_server_cancel": (C.c_int32, [_vp, C.c_uint64]),
     "pmx_server_destroy": (None, [_vp]),
+    "pmx_server_get_stats": (C.c_int32, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "pmx_profile_enable": (C.c_int32, [_vp, C.c_int]),
     "pmx_profile_read": (C.c_int32, [_vp, _vp, _vp]),
 }
@@ -351,3 +352,9 @@ class Server:
 
     def cancel(self, ticket: int):
         _check(lib().pmx_server_cancel(self.h, ticket))
+
+    def stats(self) -> dict:
+        """Batching counters: shared launches of the apply path, applies carried, largest batch."""
+        b, a, m = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().pmx_server_get_stats(self.h, C.byref(b), C.byref(a), C.byref(m)))
+        return {"batches": b.value, "applies": a.value, "max_batch": m.value}

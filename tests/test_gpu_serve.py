@@ -79,6 +79,9 @@ def test_alone_vs_mixed(ctx):
     tickets = [sv.submit(s, a, ga, f, want_u=True) for (_, s, a, ga, f) in probs]
     res, max_active = run_all(sv, tickets)
     assert max_active >= 2
+    bs = sv.stats()
+    say(f"[serve mix] batches {bs['batches']}, applies {bs['applies']}, largest batch {bs['max_batch']}")
+    assert bs["max_batch"] >= 2 and bs["applies"] > bs["batches"]      # applies shared launches
     for (sig0, u0), t, (kind, s, *_rest) in zip(alone, tickets, probs):
         code, sig, u, info, times = res[t]
         assert code == pmx.PMX_OK
