@@ -217,7 +217,7 @@ void pack_launch(const std::vector<PackArgs<T>>& recs, hipStream_t st) {
 template <int NR>
 void direct64_group(const std::vector<pmx_operator*>& ops, int n_rhs, int r0, hipStream_t st) {
   constexpr int RL = row_len<NR, double>();
-  constexpr int TPL = NR <= 2 ? 2 : 1;
+  constexpr int TPL = 1;   // one target per lane: more waves in flight beat reuse of a source row
   std::vector<PackArgs<double>> pk;
   std::vector<Direct64Args> da;
   std::vector<int64_t> nb;

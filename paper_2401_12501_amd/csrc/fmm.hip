@@ -57,8 +57,9 @@ struct FMM {
   DBuf<int32_t> u_ptr, u_idx;        // U-list of leaves (leaf-local indices)
   DBuf<int32_t> p2p_leaf, p2p_first, p2p_slot;  // P2P waves: leaf, first target offset, U-list slot
   int64_t n_p2p_waves = 0;
-  DBuf<int32_t> m2l_t, m2l_s;        // global box indices of the pairs, sorted by (level, offset)
-  DBuf<int4> items;                  // (first pair, count, level, offset code)
+  DBuf<int32_t> m2l_t, m2l_s;        // global box indices of the pairs, sorted by (offset, level)
+  DBuf<int32_t> m2l_lv;              // level of each pair
+  DBuf<int4> items;                  // (first pair, count, -, offset code)
   DBuf<float> tab;                   // t_k (p), M1[2][p][p], node table (3 p^3)
   DBuf<float> W, Lc;                 // multipoles n_boxes*p3, locals n_boxes*9*p3
   DBuf<float> slots;                 // M2L output per pair (9*p3 each)
@@ -239,19 +240,22 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
   }
 }
 
-// M2L on MFMA.  One workgroup per work item (up to 64 target boxes sharing a level
-// and an offset).  The item's source multipoles are staged in LDS once; each wave
-// takes 16-row tiles of the local expansion, generates the unit-box kernel for all
-// nine components of its (row, m) pair in registers as MFMA A operands, and keeps
-// 9 x 4 accumulator tiles (9 components x 64 target columns).  Each pair writes
-// its own output slot; k_m2l_reduce then sums a target's slots in a fixed order,
-// so no atomics are needed and the result does not depend on scheduling.
+// M2L on MFMA.  One workgroup per work item: up to 64 target boxes whose sources sit at
+// the same offset (in box widths).  By homogeneity the unit-box kernel of an offset is
+// the same at every level, so an item may mix levels; each column is scaled by its
+// level's h^-1 (F1) or h^-2 (F2) when written.  The item's source multipoles are
+// staged in LDS once; each wave takes (16-row tile, 16-column block) tasks, generates
+// the unit-box kernel for all nine components of its (row, m) pairs in registers as
+// MFMA A operands and keeps nine accumulator tiles.  Each pair writes its own output
+// slot; k_m2l_reduce then sums a target's slots in a fixed order, so no atomics are
+// needed and the result does not depend on scheduling.
 constexpr int kM2LStride = 226;   // LDS row stride (== 2 mod 32: conflict-free B reads)
 
 struct M2LArgs {
   const float* tab;
-  const int4* items;
-  const int32_t* ps;
+  const int4* items;      // (first pair, count, -, offset code)
+  const int32_t* ps;      // source box per pair
+  const int32_t* plev;    // level per pair
   const float* W;
   float* slots;
   double h0;
@@ -266,12 +270,12 @@ __global__ void __launch_bounds__(512) k_m2l(Group<M2LArgs> g) {
   const int32_t* __restrict__ ps = A.ps;
   const float* __restrict__ W = A.W;
   float* __restrict__ slots = A.slots;
-  const double h0 = A.h0;
   static_assert(p3 <= kM2LStride, "multipole does not fit the LDS row");
   constexpr int n_rt = (p3 + 15) / 16;
   constexpr int n_waves = 8;
   __shared__ float sB[kItemCols * kM2LStride];
   __shared__ float4 sN[p3];
+  __shared__ float sS[2][kItemCols];
   const int4 it = A.items[lb];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ncol = it.y;
@@ -284,29 +288,29 @@ __global__ void __launch_bounds__(512) k_m2l(Group<M2LArgs> g) {
     const float* nd = tab + P + 2 * P * P + 3 * m;
     sN[m] = make_float4(nd[0], nd[1], nd[2], 0.0f);
   }
+  if (threadIdx.x < kItemCols) {
+    const int j = threadIdx.x;
+    const double h = A.h0 / (double)(1 << (j < ncol ? A.plev[it.x + j] : 0));
+    sS[0][j] = (float)(1.0 / h);
+    sS[1][j] = (float)(1.0 / (h * h));
+  }
   __syncthreads();
-  const int level = it.z, code = it.w;
+  const int code = it.w;
   const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
               oz = 2.0f * (float)(code % 7 - 3);
-  const double h = h0 / (double)(1 << level);
-  const float s1 = (float)(1.0 / h), s2 = (float)(1.0 / (h * h));
   const int kq = lane >> 4, col = lane & 15;
-  const int n_half = (ncol + 31) / 32;              // 32-column halves in use
-  const int n_tasks = n_rt * n_half;
+  const int n_cb = (ncol + 15) / 16;                // 16-column blocks in use
+  const int n_tasks = n_rt * n_cb;
   for (int task = wave; task < n_tasks; task += n_waves) {
-    const int rt = task % n_rt, half = task / n_rt;
-    const int nbj = min(2, (ncol - half * 32 + 15) / 16);   // 16-column blocks in this half
+    const int rt = task % n_rt, cb = task / n_rt;
     const int row = rt * 16 + col;
     const bool row_ok = row < p3;
     const float4 tl = sN[row_ok ? row : 0];
     const float tlx = tl.x + ox, tly = tl.y + oy, tlz = tl.z + oz;
-    floatx4 acc[9][2];
+    floatx4 acc[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      acc[c][0] = floatx4{0.f, 0.f, 0.f, 0.f};
-      acc[c][1] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-    const float* sBh = sB + (half * 32 + col) * kM2LStride;
+    for (int c = 0; c < 9; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* sBc = sB + (cb * 16 + col) * kM2LStride;
 #pragma unroll 2
     for (int k0 = 0; k0 < p3; k0 += 4) {
       const int m = k0 + kq;
@@ -319,28 +323,21 @@ __global__ void __launch_bounds__(512) k_m2l(Group<M2LArgs> g) {
       a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
       a[3] = rx * rx * i2; a[4] = rx * ry * i2; a[5] = rx * rz * i2;
       a[6] = ry * ry * i2; a[7] = ry * rz * i2; a[8] = rz * rz * i2;
-      const int mm = m < p3 ? m : 0;
-      const float b0 = sBh[mm];
-      const float b1 = sBh[16 * kM2LStride + mm];
+      const float b0 = sBc[m < p3 ? m : 0];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc[c][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[c][0], 0, 0, 0);
-      if (nbj > 1) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) acc[c][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b1, acc[c][1], 0, 0, 0);
-      }
+      for (int c = 0; c < 9; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[c], 0, 0, 0);
     }
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb) {
-      const int pj = half * 32 + jb * 16 + col;
-      if (jb >= nbj || pj >= ncol) continue;
+    const int pj = cb * 16 + col;
+    if (pj < ncol) {
       float* out = slots + (int64_t)(it.x + pj) * 9 * p3;
+      const float s1 = sS[0][pj], s2 = sS[1][pj];
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         const float sc = c < 3 ? s1 : s2;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int l = rt * 16 + 4 * kq + r;
-          if (l < p3) out[c * p3 + l] = sc * acc[c][jb][r];
+          if (l < p3) out[c * p3 + l] = sc * acc[c][r];
         }
       }
     }
@@ -699,22 +696,23 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
             }
       }
     }
+    // grouped by offset only: the unit-box kernel of an offset serves every level
     std::sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) {
-      if (a.lev != b.lev) return a.lev < b.lev;
       if (a.code != b.code) return a.code < b.code;
+      if (a.lev != b.lev) return a.lev < b.lev;
       return a.t < b.t;
     });
     F->m2l_pairs = (int64_t)pairs.size();
-    std::vector<int32_t> pt(pairs.size()), ps(pairs.size());
+    std::vector<int32_t> pt(pairs.size()), ps(pairs.size()), plv(pairs.size());
     std::vector<int4> items;
     for (size_t k = 0; k < pairs.size();) {
       size_t e = k;
-      while (e < pairs.size() && pairs[e].lev == pairs[k].lev && pairs[e].code == pairs[k].code) ++e;
+      while (e < pairs.size() && pairs[e].code == pairs[k].code) ++e;
       for (size_t s = k; s < e; s += kItemCols)
-        items.push_back(make_int4((int)s, (int)std::min<size_t>(kItemCols, e - s), pairs[k].lev, pairs[k].code));
+        items.push_back(make_int4((int)s, (int)std::min<size_t>(kItemCols, e - s), 0, pairs[k].code));
       k = e;
     }
-    for (size_t k = 0; k < pairs.size(); ++k) { pt[k] = pairs[k].t; ps[k] = pairs[k].s; }
+    for (size_t k = 0; k < pairs.size(); ++k) { pt[k] = pairs[k].t; ps[k] = pairs[k].s; plv[k] = pairs[k].lev; }
     // per-target lists of pair slots (boxes of levels >= 2, pairs in sorted order)
     const int64_t box2 = F->lev_off[2];
     std::vector<int32_t> rptr(F->n_boxes - box2 + 1, 0), ridx(pairs.size());
@@ -768,6 +766,7 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     up(F->r_ptr, rptr);
     up(F->r_idx, ridx);
     up(F->m2l_s, ps);
+    up(F->m2l_lv, plv);
     up(F->items, items);
     up(F->p2p_leaf, wl);
     up(F->p2p_first, wf);
@@ -851,7 +850,7 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
     std::vector<int64_t> lb, rb;
     for (pmx_operator* op : ops) {
       FMM* F = op->fmm;
-      la.push_back({F->tab.p, F->items.p, F->m2l_s.p, F->W.p, F->slots.p, F->h0});
+      la.push_back({F->tab.p, F->items.p, F->m2l_s.p, F->m2l_lv.p, F->W.p, F->slots.p, F->h0});
       lb.push_back(F->n_items);
       const int64_t box2 = F->lev_off[2];
       ra.push_back({box2, F->r_ptr.p, F->r_idx.p, F->slots.p, F->Lc.p});
@@ -955,7 +954,7 @@ uint64_t fmm_bytes(const FMM* f) {
   return f->center.bytes() + f->child_begin.bytes() + f->child_end.bytes() + f->parent.bytes() +
          f->octant.bytes() + f->leaf_start.bytes() + f->perm.bytes() + f->pts.bytes() + f->qs.bytes() +
          f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_leaf.bytes() + f->p2p_first.bytes() + f->p2p_slot.bytes() + f->m2l_t.bytes() +
-         f->m2l_s.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
+         f->m2l_s.bytes() + f->m2l_lv.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
          f->slots.bytes() + f->r_ptr.bytes() + f->r_idx.bytes();
 }
 
