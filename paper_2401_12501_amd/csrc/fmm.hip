@@ -35,7 +35,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 namespace {
 constexpr int kMaxLevel = 20;
-constexpr int kItemCols = 64;   // target boxes per M2L work item
+constexpr int kItemCols = 16;   // target boxes per M2L work item (one MFMA column block)
 }  // namespace
 
 struct FMM {
@@ -240,13 +240,15 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
   }
 }
 
-// M2L on MFMA.  One workgroup per work item: up to 64 target boxes whose sources sit at
-// the same offset (in box widths).  By homogeneity the unit-box kernel of an offset is
-// the same at every level, so an item may mix levels; each column is scaled by its
-// level's h^-1 (F1) or h^-2 (F2) when written.  The item's source multipoles are
-// staged in LDS once; each wave takes (16-row tile, 16-column block) tasks, generates
-// the unit-box kernel for all nine components of its (row, m) pairs in registers as
-// MFMA A operands and keeps nine accumulator tiles.  Each pair writes its own output
+// M2L on MFMA.  One workgroup per work item: up to 16 target boxes (one MFMA column
+// block) whose sources sit at the same offset (in box widths).  By homogeneity the
+// unit-box kernel of an offset is the same at every level, so an item may mix levels;
+// each column is scaled by its level's h^-1 (F1) or h^-2 (F2) when written.  The
+// item's source multipoles are staged in LDS once; each wave takes 16-row tiles,
+// generates the unit-box kernel for all nine components of its (row, m) pairs in
+// registers as MFMA A operands and keeps nine accumulator tiles.  Small items keep
+// the grid many times larger than the number of resident workgroups, so the chip
+// stays busy to the end of the launch; the wave count divides the row tiles evenly.  Each pair writes its own output
 // slot; k_m2l_reduce then sums a target's slots in a fixed order, so no atomics are
 // needed and the result does not depend on scheduling.
 constexpr int kM2LStride = 226;   // LDS row stride (== 2 mod 32: conflict-free B reads)
@@ -262,7 +264,10 @@ struct M2LArgs {
 };
 
 template <int P>
-__global__ void __launch_bounds__(512) k_m2l(Group<M2LArgs> g) {
+constexpr int m2l_waves() { return P == 4 ? 4 : 7; }   // 4 and 14 row tiles
+
+template <int P>
+__global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
   constexpr int p3 = P * P * P;
   int64_t lb;
   const M2LArgs& A = seg_of(g, blockIdx.x, lb);
@@ -272,7 +277,7 @@ __global__ void __launch_bounds__(512) k_m2l(Group<M2LArgs> g) {
   float* __restrict__ slots = A.slots;
   static_assert(p3 <= kM2LStride, "multipole does not fit the LDS row");
   constexpr int n_rt = (p3 + 15) / 16;
-  constexpr int n_waves = 8;
+  constexpr int n_waves = m2l_waves<P>();
   __shared__ float sB[kItemCols * kM2LStride];
   __shared__ float4 sN[p3];
   __shared__ float sS[2][kItemCols];
@@ -299,10 +304,8 @@ __global__ void __launch_bounds__(512) k_m2l(Group<M2LArgs> g) {
   const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
               oz = 2.0f * (float)(code % 7 - 3);
   const int kq = lane >> 4, col = lane & 15;
-  const int n_cb = (ncol + 15) / 16;                // 16-column blocks in use
-  const int n_tasks = n_rt * n_cb;
-  for (int task = wave; task < n_tasks; task += n_waves) {
-    const int rt = task % n_rt, cb = task / n_rt;
+  for (int rt = wave; rt < n_rt; rt += n_waves) {
+    constexpr int cb = 0;
     const int row = rt * 16 + col;
     const bool row_ok = row < p3;
     const float4 tl = sN[row_ok ? row : 0];
@@ -857,7 +860,7 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
       rb.push_back(F->n_boxes - box2);
     }
     launch_grouped(la, lb, [&](const Group<M2LArgs>& g, int64_t nb) {
-      hipLaunchKernelGGL(k_m2l<P>, dim3((unsigned)nb), dim3(512), 0, st, g);
+      hipLaunchKernelGGL(k_m2l<P>, dim3((unsigned)nb), dim3(64 * m2l_waves<P>()), 0, st, g);
       PMX_HIP(hipGetLastError());
     });
     launch_grouped(ra, rb, [&](const Group<RedArgs>& g, int64_t nb) {
