@@ -42,10 +42,12 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0
 # traffic is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "3d91538a2fef6065",
-                "kib": [("k_m2l", 8963.2, 375646.8), ("k_m2l_reduce", 168262.2, 7378.5)]},
-    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "8b0735de6c1193d2",
-             "kib": [("k_near_combine", 281207.6, 1203.2)]},
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "02d9f2d688c60c4f",
+                "kib": [("k_m2l", 13130.9, 413825.8)]},
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "02d9f2d688c60c4f",
+                    "kib": [("k_m2l_reduce", 168537.6, 7393.7)]},
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "1860a663d24d7d3c",
+             "kib": [("k_near_combine", 281207.6, 1202.7)]},
 }
 
 
@@ -76,6 +78,9 @@ def algorithmic_work(phase: str, st, N: int, q: int, n_rhs: int, fmm_order: int)
         return byts / 1e9, "GB/s", "hbm", PEAK["hbm"]
     if phase == "fmm_m2l":
         return 2.0 * 9 * p3 * p3 * st.fmm_m2l_pairs * n_rhs / 1e12, "TFLOP/s", "mfma", PEAK["fp32_mfma"]
+    if phase == "fmm_m2l_sum":
+        byts = 4.0 * 9 * p3 * (st.fmm_m2l_pairs + st.fmm_boxes) * n_rhs + 4.0 * st.fmm_m2l_pairs
+        return byts / 1e9, "GB/s", "hbm", PEAK["hbm"]
     if phase == "fmm_p2p":
         return float(st.fmm_p2p_pairs) * (24 + 2 * n_rhs) / 1e12, "TFLOP/s", "alu", PEAK["fp32_valu"]
     return None

@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(kBlock) k_direct64(Group<Direct64Args> g) {
   for (int t = 0; t < TPL; ++t)
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[t][r] = 0.0;
-#pragma unroll(NR <= 4 ? 2 : 1)
+  // several sources per step: independent pair chains for the scheduler (measured best)
+#pragma unroll(NR == 1 ? 8 : 4)
   for (int64_t j = j0; j < j1; ++j) {
     const sdp row = S + j * RL;
     const double xs = row[0], ys = row[1], zs = row[2];

@@ -863,6 +863,8 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
       hipLaunchKernelGGL(k_m2l<P>, dim3((unsigned)nb), dim3(64 * m2l_waves<P>()), 0, st, g);
       PMX_HIP(hipGetLastError());
     });
+    done(t);
+    t = phase(PMX_PHASE_FMM_M2L_SUM);
     launch_grouped(ra, rb, [&](const Group<RedArgs>& g, int64_t nb) {
       hipLaunchKernelGGL(k_m2l_reduce<P>, dim3((unsigned)nb), dim3(512), 0, st, g);
       PMX_HIP(hipGetLastError());

@@ -82,7 +82,7 @@ _SIGS = {
 }
 
 PHASES = ["prep", "direct64", "direct32", "near", "fmm_p2m", "fmm_m2m", "fmm_m2l", "fmm_l2l", "fmm_l2p",
-          "fmm_p2p", "log"]
+          "fmm_p2p", "log", "fmm_m2l_sum"]
 
 _lib = None
 
