@@ -53,9 +53,10 @@ struct FMM {
   DBuf<int32_t> leaf_start;  // n_leaves + 1 (sorted point ranges)
   DBuf<int32_t> perm;        // N: sorted position -> node
   DBuf<float> pts;           // 9 N sorted: x y z n'x n'y n'z hx hy hz (n' = sqrt(A) n, h = g - B n)
-  DBuf<float> qs;            // N sorted strengths (one rhs at a time)
+  DBuf<float> qs;            // 4 N sorted source rows: x y z qt (one rhs at a time)
   DBuf<int32_t> u_ptr, u_idx;        // U-list of leaves (leaf-local indices)
-  DBuf<int32_t> p2p_leaf, p2p_first, p2p_slot;  // P2P waves: leaf, first target offset, U-list slot
+  DBuf<int4> p2p_desc;       // P2P waves: first and end target, first and end source (sorted positions)
+  DBuf<int32_t> p2p_slot;    // U-list slot of each P2P wave
   int64_t n_p2p_waves = 0;
   DBuf<int32_t> m2l_t, m2l_s;        // global box indices of the pairs, sorted by (offset, level)
   DBuf<int32_t> m2l_lv;              // level of each pair
@@ -92,10 +93,11 @@ __device__ __forceinline__ void cheb_weights(const float* __restrict__ t, float 
   }
 }
 
-// qs[k] = qt[perm[k]]
+// Sorted source rows: qs[k] = (x_k, y_k, z_k, qt[perm[k]]), one 16-byte row per point.
 struct PermArgs {
   int64_t N;
   const int32_t* perm;
+  const float* pts;
   const float* q;
   float* qs;
 };
@@ -103,9 +105,13 @@ struct PermArgs {
 __global__ void __launch_bounds__(256) k_permute(Group<PermArgs> g) {
   int64_t lb;
   const PermArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t N = A.N;
   const int64_t k = lb * 256 + threadIdx.x;
-  if (k < A.N) A.qs[k] = A.q[A.perm[k]];
+  if (k < N)
+    reinterpret_cast<float4*>(A.qs)[k] = make_float4(A.pts[k], A.pts[N + k], A.pts[2 * N + k], A.q[A.perm[k]]);
 }
+
+typedef const __attribute__((address_space(4))) float* sfp;   // uniform loads through the scalar cache
 
 // P2M: one block per leaf; thread m accumulates over the leaf's sources.
 struct P2MArgs {
@@ -145,10 +151,11 @@ __global__ void __launch_bounds__(256) k_p2m(Group<P2MArgs> g) {
     const int j = j0 + threadIdx.x;
     __syncthreads();
     if (j < s1) {
-      cheb_weights<P>(tab, (pts[j] - cx) * ih, &sw[threadIdx.x][0]);
-      cheb_weights<P>(tab, (pts[N + j] - cy) * ih, &sw[threadIdx.x][p]);
-      cheb_weights<P>(tab, (pts[2 * N + j] - cz) * ih, &sw[threadIdx.x][2 * p]);
-      sw[threadIdx.x][3 * p] = qs[j];
+      const float4 sj = reinterpret_cast<const float4*>(qs)[j];
+      cheb_weights<P>(tab, (sj.x - cx) * ih, &sw[threadIdx.x][0]);
+      cheb_weights<P>(tab, (sj.y - cy) * ih, &sw[threadIdx.x][p]);
+      cheb_weights<P>(tab, (sj.z - cz) * ih, &sw[threadIdx.x][2 * p]);
+      sw[threadIdx.x][3 * p] = sj.w;
     }
     __syncthreads();
     const int lim = min(256, s1 - j0);
@@ -383,16 +390,14 @@ __global__ void __launch_bounds__(512) k_m2l_reduce(Group<RedArgs> g) {
   }
 }
 
-// P2P over the U-list: one wave per (leaf, 64 targets, U-list slot); sources of the
-// slot's neighbour leaf are wave-uniform.  part[slot][k] is summed in slot order by L2P.
+// P2P over the U-list: one wave per (leaf, 64 targets, U-list slot).  The wave's
+// target and source ranges come precomputed in one record, so its start needs a single
+// dependent load; the source rows (x, y, z, qt) are wave-uniform and read through the
+// scalar cache.  part[slot][k] is summed in slot order by L2P.
 struct P2PArgs {
   int64_t N;
-  const int32_t* wleaf;
-  const int32_t* wfirst;
+  const int4* desc;      // (first target, end target, first source, end source)
   const int32_t* wslot;
-  const int32_t* leaf_start;
-  const int32_t* u_ptr;
-  const int32_t* u_idx;
   const float* pts;
   const float* qs;
   float* part;
@@ -402,31 +407,27 @@ __global__ void __launch_bounds__(64) k_p2p(Group<P2PArgs> g) {
   int64_t lb;
   const P2PArgs& A = seg_of(g, blockIdx.x, lb);
   const int64_t N = A.N;
-  const int32_t* __restrict__ leaf_start = A.leaf_start;
   const float* __restrict__ pts = A.pts;
-  const float* __restrict__ qs = A.qs;
-  const int leaf = A.wleaf[lb];
+  const int4 d = A.desc[lb];
   const int slot = A.wslot[lb];
-  const int k0 = leaf_start[leaf] + A.wfirst[lb];
-  const int kend = leaf_start[leaf + 1];
-  const int k = k0 + threadIdx.x;
-  const int kk = k < kend ? k : kend - 1;
+  const int k = d.x + threadIdx.x;
+  const int kk = k < d.y ? k : d.y - 1;
   const float xi = pts[kk], yi = pts[N + kk], zi = pts[2 * N + kk];
   const float px = pts[3 * N + kk], py = pts[4 * N + kk], pz = pts[5 * N + kk];
   const float hx = pts[6 * N + kk], hy = pts[7 * N + kk], hz = pts[8 * N + kk];
-  const int S = A.u_idx[A.u_ptr[leaf] + slot];
-  const int j0 = leaf_start[S], j1 = leaf_start[S + 1];
+  const sfp src = (sfp)A.qs;
   float acc = 0.0f;
 #pragma unroll 4
-  for (int j = j0; j < j1; ++j) {
-    const float dx = xi - pts[j], dy = yi - pts[N + j], dz = zi - pts[2 * N + j];
+  for (int j = d.z; j < d.w; ++j) {
+    const sfp sj = src + 4 * (int64_t)j;
+    const float dx = xi - sj[0], dy = yi - sj[1], dz = zi - sj[2];
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-30f)));
     const float inv = __builtin_amdgcn_rcpf(r2);
     const float pr = fmaf(px, dx, fmaf(py, dy, pz * dz));
     const float hr = fmaf(hx, dx, fmaf(hy, dy, hz * dz));
-    acc = fmaf(qs[j], fmaf(pr * inv, pr, hr) * inv, acc);
+    acc = fmaf(sj[3], fmaf(pr * inv, pr, hr) * inv, acc);
   }
-  if (k < kend) A.part[(int64_t)slot * N + k] = acc;
+  if (k < d.y) A.part[(int64_t)slot * N + k] = acc;
 }
 
 // L2P + contraction + P2P sum; writes phi (FP64, node order).
@@ -726,16 +727,17 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
       for (size_t k = 0; k < pairs.size(); ++k) ridx[fill[pairs[k].t - box2]++] = (int32_t)k;
     }
     F->n_items = (int64_t)items.size();
-    // P2P waves: (leaf, 64-target chunk, U-list slot)
-    std::vector<int32_t> wl, wf, ws;
+    // P2P waves: (leaf, 64-target chunk, U-list slot) -> target and source ranges
+    std::vector<int4> wd;
+    std::vector<int32_t> ws;
     for (int64_t b = 0; b < F->n_leaves; ++b)
-      for (int32_t f = 0; f < lstart[b + 1] - lstart[b]; f += 64)
+      for (int32_t f = lstart[b]; f < lstart[b + 1]; f += 64)
         for (int32_t sl = 0; sl < uptr[b + 1] - uptr[b]; ++sl) {
-          wl.push_back((int32_t)b);
-          wf.push_back(f);
+          const int32_t S = uidx[uptr[b] + sl];
+          wd.push_back(make_int4(f, std::min(f + 64, lstart[b + 1]), lstart[S], lstart[S + 1]));
           ws.push_back(sl);
         }
-    F->n_p2p_waves = (int64_t)wl.size();
+    F->n_p2p_waves = (int64_t)wd.size();
     // tables: t_k, M1[2][p][p] (M1[b][k][k'] = S1(t_k, +-0.5 + t_k'/2)), node coordinates
     std::vector<float> tab(p + 2 * p * p + 3 * p3);
     std::vector<double> t(p);
@@ -771,12 +773,11 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     up(F->m2l_s, ps);
     up(F->m2l_lv, plv);
     up(F->items, items);
-    up(F->p2p_leaf, wl);
-    up(F->p2p_first, wf);
+    up(F->p2p_desc, wd);
     up(F->p2p_slot, ws);
     up(F->tab, tab);
     F->pts.alloc(ctx, 9 * (size_t)N);
-    F->qs.alloc(ctx, N);
+    F->qs.alloc(ctx, 4 * N);
     F->phis.alloc(ctx, 27 * (size_t)N);
     F->W.alloc(ctx, (size_t)F->n_boxes * p3);
     F->Lc.alloc(ctx, (size_t)F->n_boxes * 9 * p3);
@@ -814,7 +815,7 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
     for (pmx_operator* op : ops) {
       FMM* F = op->fmm;
       const int64_t N = op->s->g.N;
-      pa.push_back({N, F->perm.p, op->qt32.p + (int64_t)r * N, F->qs.p});
+      pa.push_back({N, F->perm.p, F->pts.p, op->qt32.p + (int64_t)r * N, F->qs.p});
       pb.push_back((N + 255) / 256);
       const float hL = (float)(F->h0 / (double)(1 << F->L));
       ma.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->qs.p, F->W.p});
@@ -893,8 +894,7 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
     std::vector<int64_t> pb;
     for (pmx_operator* op : ops) {
       FMM* F = op->fmm;
-      pa.push_back({op->s->g.N, F->p2p_leaf.p, F->p2p_first.p, F->p2p_slot.p, F->leaf_start.p, F->u_ptr.p,
-                    F->u_idx.p, F->pts.p, F->qs.p, F->phis.p});
+      pa.push_back({op->s->g.N, F->p2p_desc.p, F->p2p_slot.p, F->pts.p, F->qs.p, F->phis.p});
       pb.push_back(F->n_p2p_waves);
     }
     launch_grouped(pa, pb, [&](const Group<P2PArgs>& g, int64_t nb) {
@@ -958,7 +958,7 @@ void fmm_stats(const FMM* f, pmx_operator_stats* s) {
 uint64_t fmm_bytes(const FMM* f) {
   return f->center.bytes() + f->child_begin.bytes() + f->child_end.bytes() + f->parent.bytes() +
          f->octant.bytes() + f->leaf_start.bytes() + f->perm.bytes() + f->pts.bytes() + f->qs.bytes() +
-         f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_leaf.bytes() + f->p2p_first.bytes() + f->p2p_slot.bytes() + f->m2l_t.bytes() +
+         f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_desc.bytes() + f->p2p_slot.bytes() + f->m2l_t.bytes() +
          f->m2l_s.bytes() + f->m2l_lv.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
          f->slots.bytes() + f->r_ptr.bytes() + f->r_idx.bytes();
 }
