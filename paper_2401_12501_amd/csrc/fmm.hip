@@ -175,36 +175,50 @@ struct M2MArgs {
   float* W;
 };
 
+// The interpolation operator is a tensor product, so each child's contribution is
+// applied one axis at a time (3 p^4 multiply-adds instead of p^6), through LDS.
 template <int P>
 __global__ void __launch_bounds__(256) k_m2m(Group<M2MArgs> g) {
   constexpr int p = P, p3 = P * P * P;
+  __shared__ float sW[p3], sT[p3];
+  __shared__ float sM[2 * p * p];
   int64_t lb;
   const M2MArgs& A = seg_of(g, blockIdx.x, lb);
-  const float* __restrict__ tab = A.tab;
-  const int32_t* __restrict__ child_begin = A.child_begin;
-  const int32_t* __restrict__ child_end = A.child_end;
-  const int32_t* __restrict__ octant = A.octant;
-  float* __restrict__ W = A.W;
   const int64_t Pb = A.lev_first + lb;
-  const float* M1 = tab + p;   // M1[b][k][k'] = S1(t_k, (b ? 0.5 : -0.5) + t_k' / 2)
   const int m = threadIdx.x;
-  if (m >= p3) return;
-  const int m1 = m / (p * p), m2 = (m / p) % p, m3 = m % p;
+  for (int e = m; e < 2 * p * p; e += blockDim.x) sM[e] = A.tab[p + e];   // M1[b][k][k']
+  const int i1 = m / (p * p), i2 = (m / p) % p, i3 = m % p;
   float acc = 0.0f;
-  for (int c = child_begin[Pb]; c < child_end[Pb]; ++c) {
-    const int o = octant[c];
-    const float* Ax = M1 + (o & 1) * p * p + m1 * p;
-    const float* Ay = M1 + ((o >> 1) & 1) * p * p + m2 * p;
-    const float* Az = M1 + ((o >> 2) & 1) * p * p + m3 * p;
-    const float* Wc = W + (int64_t)c * p3;
-    for (int a = 0; a < p; ++a)
-      for (int b = 0; b < p; ++b) {
-        const float xy = Ax[a] * Ay[b];
-        const float* w = Wc + (a * p + b) * p;
-        for (int d = 0; d < p; ++d) acc = fmaf(xy * Az[d], w[d], acc);
-      }
+  for (int c = A.child_begin[Pb]; c < A.child_end[Pb]; ++c) {
+    const int o = A.octant[c];
+    const float* Mx = sM + (o & 1) * p * p;
+    const float* My = sM + ((o >> 1) & 1) * p * p;
+    const float* Mz = sM + ((o >> 2) & 1) * p * p;
+    __syncthreads();
+    if (m < p3) sW[m] = A.W[(int64_t)c * p3 + m];
+    __syncthreads();
+    // z: T[a][b][m3] = sum_d Mz[m3][d] W[a][b][d]
+    if (m < p3) {
+      float t = 0.0f;
+      for (int d = 0; d < p; ++d) t = fmaf(Mz[i3 * p + d], sW[(i1 * p + i2) * p + d], t);
+      sT[m] = t;
+    }
+    __syncthreads();
+    // y: W'[a][m2][m3] = sum_b My[m2][b] T[a][b][m3]
+    if (m < p3) {
+      float t = 0.0f;
+      for (int bb = 0; bb < p; ++bb) t = fmaf(My[i2 * p + bb], sT[(i1 * p + bb) * p + i3], t);
+      sW[m] = t;
+    }
+    __syncthreads();
+    // x: out[m1][m2][m3] = sum_a Mx[m1][a] W'[a][m2][m3]
+    if (m < p3) {
+      float t = 0.0f;
+      for (int aa = 0; aa < p; ++aa) t = fmaf(Mx[i1 * p + aa], sW[(aa * p + i2) * p + i3], t);
+      acc += t;
+    }
   }
-  W[Pb * p3 + m] = acc;
+  if (m < p3) A.W[Pb * p3 + m] = acc;
 }
 
 // L2L: child L += interpolation of the parent's L (one block per child box of one level).
@@ -216,34 +230,47 @@ struct L2LArgs {
   float* Lc;
 };
 
+// Child L += the parent's L interpolated to the child, one axis at a time through LDS
+// (3 p^4 multiply-adds per component instead of p^6).
 template <int P>
 __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
   constexpr int p = P, p3 = P * P * P;
+  constexpr int n = 9 * p3;
+  __shared__ float sA[n], sB[n];
+  __shared__ float sM[2 * p * p];
   int64_t lb;
   const L2LArgs& A = seg_of(g, blockIdx.x, lb);
-  const float* __restrict__ tab = A.tab;
-  const int32_t* __restrict__ parent = A.parent;
-  const int32_t* __restrict__ octant = A.octant;
-  float* __restrict__ Lc = A.Lc;
   const int64_t C = A.lev_first + lb;
-  const int64_t Pb = parent[C];
-  const int o = octant[C];
-  const float* M1 = tab + p;
-  const float* Mx = M1 + (o & 1) * p * p;
-  const float* My = M1 + ((o >> 1) & 1) * p * p;
-  const float* Mz = M1 + ((o >> 2) & 1) * p * p;
-  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) {
-    const int c = e / p3, l = e - c * p3;
-    const int l1 = l / (p * p), l2 = (l / p) % p, l3 = l % p;
-    const float* LP = Lc + (Pb * 9 + c) * p3;
-    float acc = 0.0f;
-    for (int a = 0; a < p; ++a)
-      for (int b = 0; b < p; ++b) {
-        const float xy = Mx[a * p + l1] * My[b * p + l2];
-        const float* lp = LP + (a * p + b) * p;
-        for (int d = 0; d < p; ++d) acc = fmaf(xy * Mz[d * p + l3], lp[d], acc);
-      }
-    Lc[(C * 9 + c) * p3 + l] += acc;
+  const int64_t Pb = A.parent[C];
+  const int o = A.octant[C];
+  for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) sM[e] = A.tab[p + e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) sA[e] = A.Lc[Pb * n + e];
+  __syncthreads();
+  const float* Mx = sM + (o & 1) * p * p;          // Mx[a * p + l1] = S1(t_a, child node l1)
+  const float* My = sM + ((o >> 1) & 1) * p * p;
+  const float* Mz = sM + ((o >> 2) & 1) * p * p;
+  // z: B[c][a][b][l3] = sum_d Mz[d][l3] A[c][a][b][d]
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int l3 = e % p, r = e - l3;
+    float t = 0.0f;
+    for (int d = 0; d < p; ++d) t = fmaf(Mz[d * p + l3], sA[r + d], t);
+    sB[e] = t;
+  }
+  __syncthreads();
+  // y: A[c][a][l2][l3] = sum_b My[b][l2] B[c][a][b][l3]
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int l3 = e % p, l2 = (e / p) % p, r = e - l3 - l2 * p;
+    float t = 0.0f;
+    for (int bb = 0; bb < p; ++bb) t = fmaf(My[bb * p + l2], sB[r + bb * p + l3], t);
+    sA[e] = t;
+  }
+  __syncthreads();
+  // x: L[c][l1][l2][l3] += sum_a Mx[a][l1] A[c][a][l2][l3]
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int l23 = e % (p * p), l1 = (e / (p * p)) % p, cc = e / p3;
+    float t = 0.0f;
+    for (int aa = 0; aa < p; ++aa) t = fmaf(Mx[aa * p + l1], sA[cc * p3 + aa * p * p + l23], t);
+    A.Lc[C * n + e] += t;
   }
 }
 
@@ -445,59 +472,86 @@ struct L2PArgs {
   double* phi;
 };
 
+// The leaf's local expansion is the same for all its targets, so the evaluation
+//   F_c(x_t) = sum_l S(t_l, x_t) L_c,l
+// is a [targets x p^3] x [p^3 x 9] product: one MFMA tile covers 16 targets and the
+// nine components (padded to 16 columns).  The K index runs over (a, b, d) with d
+// padded to a multiple of 4, so a lane's share of the tensor weight S = s_x[a] s_y[b]
+// s_z[d] only needs the two s_z values it owns (d = kq and 4 + kq).  The tile's nine
+// components per target go through LDS to the lanes that form the contraction.
 template <int P>
 __global__ void __launch_bounds__(256) k_l2p(Group<L2PArgs> g) {
   constexpr int p = P, p3 = P * P * P;
+  constexpr int n_h = (P + 3) / 4;                    // 4-wide d groups
   __shared__ float sL[9 * p3];
+  __shared__ float sF[4][16][17];                     // per wave: [target][component]
   int64_t lb;
   const L2PArgs& A = seg_of(g, blockIdx.x, lb);
   const int64_t leaf_off = A.leaf_off, N = A.N;
-  const float h = A.h;
   const float* __restrict__ tab = A.tab;
-  const float* __restrict__ center = A.center;
-  const int32_t* __restrict__ leaf_start = A.leaf_start;
   const float* __restrict__ pts = A.pts;
-  const float* __restrict__ Lc = A.Lc;
-  const float* __restrict__ part = A.part;
-  const int32_t* __restrict__ u_ptr = A.u_ptr;
-  const int32_t* __restrict__ perm = A.perm;
-  double* __restrict__ phi = A.phi;
   const int leaf = (int)lb;
   const int64_t box = leaf_off + leaf;
-  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) sL[e] = Lc[box * 9 * p3 + e];
+  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) sL[e] = A.Lc[box * 9 * p3 + e];
   __syncthreads();
-  const float cx = center[3 * box], cy = center[3 * box + 1], cz = center[3 * box + 2];
-  const float ih = 1.0f / h;
-  const int s0 = leaf_start[leaf], s1 = leaf_start[leaf + 1];
-  const int n_slot = u_ptr[leaf + 1] - u_ptr[leaf];
-  for (int k = s0 + threadIdx.x; k < s1; k += blockDim.x) {
-    float near_sum = 0.0f;
-    for (int sl = 0; sl < n_slot; ++sl) near_sum += part[(int64_t)sl * N + k];
+  const float cx = A.center[3 * box], cy = A.center[3 * box + 1], cz = A.center[3 * box + 2];
+  const float ih = 1.0f / A.h;
+  const int s0 = A.leaf_start[leaf], s1 = A.leaf_start[leaf + 1];
+  const int n_slot = A.u_ptr[leaf + 1] - A.u_ptr[leaf];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = lane & 15, kq = lane >> 4;
+  const int c = row;                                   // B column (component) of this lane
+  for (int t0 = s0 + wave * 16; t0 < s1; t0 += 64) {
+    const int k = t0 + row;                            // A row (target) of this lane
+    const bool kv = k < s1;
+    const int kk = kv ? k : s1 - 1;
     float sx[P], sy[P], sz[P];
-    cheb_weights<P>(tab, (pts[k] - cx) * ih, sx);
-    cheb_weights<P>(tab, (pts[N + k] - cy) * ih, sy);
-    cheb_weights<P>(tab, (pts[2 * N + k] - cz) * ih, sz);
-    float F[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    cheb_weights<P>(tab, (pts[kk] - cx) * ih, sx);
+    cheb_weights<P>(tab, (pts[N + kk] - cy) * ih, sy);
+    cheb_weights<P>(tab, (pts[2 * N + kk] - cz) * ih, sz);
+    float wz[n_h];
+#pragma unroll
+    for (int hq = 0; hq < n_h; ++hq) {
+      float v = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4 * hq + q < P && kq == q) v = sz[4 * hq + q];
+      wz[hq] = kv ? v : 0.0f;
+    }
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int a = 0; a < p; ++a)
 #pragma unroll
       for (int b = 0; b < p; ++b) {
         const float xy = sx[a] * sy[b];
 #pragma unroll
-        for (int d = 0; d < p; ++d) {
-          const float s = xy * sz[d];
-          const int l = (a * p + b) * p + d;
-#pragma unroll
-          for (int c = 0; c < 9; ++c) F[c] = fmaf(s, sL[c * p3 + l], F[c]);
+        for (int hq = 0; hq < n_h; ++hq) {
+          const int d = 4 * hq + kq;
+          const float bv = (c < 9 && d < P) ? sL[(c < 9 ? c : 0) * p3 + (a * p + b) * p + (d < P ? d : 0)] : 0.0f;
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xy * wz[hq], bv, acc, 0, 0, 0);
         }
       }
-    const float nx = pts[3 * N + k], ny = pts[4 * N + k], nz = pts[5 * N + k];
-    const float hx = pts[6 * N + k], hy = pts[7 * N + k], hz = pts[8 * N + k];
-    // F1 = F[0..2]; F2 = (xx, xy, xz, yy, yz, zz) = F[3..8]; phi = n'^T F2 n' + h . F1
-    const float nF2n = nx * nx * F[3] + 2.f * nx * ny * F[4] + 2.f * nx * nz * F[5] + ny * ny * F[6] +
-                       2.f * ny * nz * F[7] + nz * nz * F[8];
-    const float hF1 = hx * F[0] + hy * F[1] + hz * F[2];
-    phi[perm[k]] = (double)(nF2n + hF1) + (double)near_sum;
+    // lane holds F[component = row][targets 4 kq + r]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sF[wave][4 * kq + r][row] = acc[r];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 16 && kv) {
+      const float* F = sF[wave][row];
+      float near_sum = 0.0f;
+      for (int sl = 0; sl < n_slot; ++sl) near_sum += A.part[(int64_t)sl * N + k];
+      const float nx = pts[3 * N + k], ny = pts[4 * N + k], nz = pts[5 * N + k];
+      const float hx = pts[6 * N + k], hy = pts[7 * N + k], hz = pts[8 * N + k];
+      // F1 = F[0..2]; F2 = (xx, xy, xz, yy, yz, zz) = F[3..8]; phi = n'^T F2 n' + h . F1
+      const float nF2n = nx * nx * F[3] + 2.f * nx * ny * F[4] + 2.f * nx * nz * F[5] + ny * ny * F[6] +
+                         2.f * ny * nz * F[7] + nz * nz * F[8];
+      const float hF1 = hx * F[0] + hy * F[1] + hz * F[2];
+      A.phi[A.perm[k]] = (double)(nF2n + hF1) + (double)near_sum;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
