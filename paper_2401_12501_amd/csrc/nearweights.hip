@@ -22,14 +22,18 @@
 // n_gl x n_gl tensor Gauss-Legendre rule.
 //
 // Layout: one workgroup per (target, patch) pair, specialised on the patch order q.
-// After the cells (self panels or near leaves) are built, each wave takes its own
-// batches of 64 quadrature points, one point per lane: the lane evaluates its
-// point's Lagrange values (registers), interpolates the ten patch fields with the
-// node data read through the scalar cache (all lanes use the same node values),
-// evaluates the kernel and writes (c l_a(u), l_b(v)) to its wave's LDS rows.  The
-// block update W += Lu^T diag(c) Lv is then sixteen FP64 MFMA steps of 4 points
-// each; the 16 x 16 accumulator stays in registers across batches and the waves'
-// accumulators are summed in a fixed order at the end.
+// After the cells (self panels or near leaves) are built:
+//  * near leaves: each wave takes whole leaves; a leaf's tensor rule turns the field
+//    interpolation and the block update into chained small products on the FP64
+//    MFMA (see below), about a sixth of the work of interpolating point by point;
+//  * self panels: each wave takes its own batches of 64 quadrature points, one per
+//    lane: the lane evaluates its point's Lagrange values (registers), interpolates
+//    the ten patch fields with the node data read through the scalar cache (all
+//    lanes use the same node values), evaluates the kernel and writes
+//    (c l_a(u), l_b(v)) to its wave's LDS rows; the block update W += Lu^T diag(c) Lv
+//    is then sixteen FP64 MFMA steps of 4 points each.
+// Each wave's 16 x 16 accumulator stays in registers and the waves' accumulators are
+// summed in a fixed order at the end.
 #include <cmath>
 
 #include "pmx_internal.hpp"
@@ -61,6 +65,7 @@ struct NWArgs {
   const double* cinv;   // q: 1 / prod_{k != j} (t_j - t_k)
   const double* gl_t;   // n_gl Gauss-Legendre nodes on [-1, 1]
   const double* gl_w;   // n_gl weights
+  const int64_t* ptr;   // N + 1: near-list rows
   const int32_t* pair_patch;
   const int32_t* pair_target;
   double* out;          // nnz * q*q
@@ -169,8 +174,12 @@ __device__ inline sdp opaque(sdp p) {
 }  // namespace
 
 // KERNEL: 0 = remainder R (correction blocks C), 1 = parametrix K (blocks D).
-template <int KERNEL, int Q>
-__global__ void __launch_bounds__(64 * waves_for<Q>()) k_near_weights(NWArgs A) {
+// SELF: one workgroup per target for the pair with its own patch; otherwise one per
+// near-list pair, the self pairs leaving at once (the two launches get their own
+// register allocation: the self rule is VALU work, the near rule MFMA work).
+template <int KERNEL, int Q, bool SELF>
+__global__ void __launch_bounds__(64 * waves_for<Q>()) __attribute__((amdgpu_waves_per_eu(2)))
+k_near_weights(NWArgs A) {
   constexpr int kW = waves_for<Q>();
   constexpr int kT = 64 * kW;
   constexpr int q2 = Q * Q;
@@ -187,12 +196,23 @@ __global__ void __launch_bounds__(64 * waves_for<Q>()) k_near_weights(NWArgs A) 
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t pair = A.pair0 + blockIdx.x;
-  const int P = A.pair_patch[pair];
-  const int64_t i = A.pair_target[pair];
+  int64_t pair, i;
+  int P;
+  if constexpr (SELF) {
+    i = A.pair0 + blockIdx.x;
+    P = (int)(i / q2);
+    pair = A.ptr[i];
+    for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)   // a target is always near its own patch
+      if (A.pair_patch[e] == P) pair = e;
+  } else {
+    pair = A.pair0 + blockIdx.x;
+    P = A.pair_patch[pair];
+    i = A.pair_target[pair];
+    if (i / q2 == P) return;
+  }
   const int64_t N = A.N;
   const int64_t base = (int64_t)P * q2;
-  const bool self = (i / q2) == P;
+  constexpr bool self = SELF;
 
   const sdp F = (sdp)(A.XP + base * 10);
   const sdp tn = (sdp)A.tn, cinv = (sdp)A.cinv, gl_t = (sdp)A.gl_t, gl_w = (sdp)A.gl_w;
@@ -327,15 +347,102 @@ __global__ void __launch_bounds__(64 * waves_for<Q>()) k_near_weights(NWArgs A) 
     nc = 0;
   }
 
-  // ------------------------------------------------------------------ quadrature points
+  const int r16 = lane & 15, g4 = lane >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};   // this wave's share of W: lane holds W[g4 + 4 r][r16]
+
+  // ------------------------------------------------------------------ near rule: tensor leaves
+  // A leaf carries a 16 x 16 tensor rule (points u_i, v_k; unused rows when n_gl < 16
+  // get weight zero).  Everything is a small product done on the FP64 MFMA, in the
+  // register layouts the instruction produces, so no data moves between the steps:
+  //   T_f[a][k]   = sum_b X_f[a][b] l_b(v_k)          (X_f: one of the patch's ten node fields)
+  //   G_f[i][k]   = sum_a l_a(u_i) T_f[a][k]          (the field at the leaf's points)
+  //   c[i][k]     = w_i w_k h^2 F(x_target, y(i,k)) J(i,k)
+  //   U[i][b]     = sum_k c[i][k] l_b(v_k)
+  //   W[a][b]    += sum_i l_a(u_i) U[i][b]
+  // (a 16 x 16 x 4 FP64 MFMA leaves D[g4 + 4 r][r16] in register r of lane 16 g4 + r16,
+  // which is exactly where the next product's A operand for k-step r has to be).
+  if (!self && nc > 0) {
+    constexpr int KS = (Q + 3) / 4;   // k-steps over a patch index (a or b)
+    // Lagrange value l_j(s) of node j (lane-dependent) at s; zero for j >= q
+    auto lag = [&](int j, double s) -> double {
+      double prod = 1.0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) prod *= (m == j) ? 1.0 : (s - tn[m]);
+      return j < Q ? prod * A.cinv[j < Q ? j : 0] : 0.0;
+    };
+    const double* __restrict__ XPp = A.XP + base * 10;
+    for (int cell = wave; cell < nc; cell += kW) {
+      const Cell C = cells[cell];
+      const double h = 2.0 / (double)(1 << C.n.depth);
+      const double ua = -1.0 + C.n.iu * h, va = -1.0 + C.n.iv * h;
+      const double hh = 0.5 * h;
+      auto unode = [&](int i) { return ua + hh * (gl_t[i < ngl ? i : 0] + 1.0); };
+      auto vnode = [&](int k) { return va + hh * (gl_t[k < ngl ? k : 0] + 1.0); };
+      double lvb[KS], lua[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        lvb[ks] = lag(4 * ks + g4, vnode(r16));   // B[b][k] = l_b(v_k), b = 4 ks + g4, k = r16
+        lua[ks] = lag(4 * ks + g4, unode(r16));   // B[a][i] = l_a(u_i), a = 4 ks + g4, i = r16
+      }
+      // G_f^T: lane holds G_f at (k = g4 + 4 r, i = r16)
+      v4d acc2[10];
+#pragma unroll
+      for (int f = 0; f < 10; ++f) {
+        v4d t1 = {0.0, 0.0, 0.0, 0.0};   // T_f[a = g4 + 4 r][k = r16]
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int b = 4 * ks + g4;
+          const double xv = (r16 < Q && b < Q) ? XPp[(r16 < Q ? r16 * Q + b : 0) * 10 + f] : 0.0;
+          t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, lvb[ks], t1, 0, 0, 0);
+        }
+        acc2[f] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)   // A[k][a] = T_f[a = 4 ks + g4][k = r16] = t1[ks]
+          acc2[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[ks], lua[ks], acc2[f], 0, 0, 0);
+      }
+      // kernel at the lane's four points
+      double cval[4];
+      const double wi = gl_w[r16 < ngl ? r16 : 0];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = g4 + 4 * r;
+        double gv[10];
+#pragma unroll
+        for (int f = 0; f < 10; ++f) gv[f] = acc2[f][r];
+        const double x0 = gv[4] * gv[8] - gv[5] * gv[7];
+        const double x1 = gv[5] * gv[6] - gv[3] * gv[8];
+        const double x2 = gv[3] * gv[7] - gv[4] * gv[6];
+        const double Jt = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+        const double inv_as = 1.0 / gv[9];
+        const double Fk = KERNEL == 0 ? remainder_dev(T, gv, inv_as) : parametrix_dev(T, gv, inv_as);
+        const bool ok = r16 < ngl && k < ngl;
+        cval[r] = ok ? wi * gl_w[k < ngl ? k : 0] * hh * hh * Fk * Jt : 0.0;
+      }
+      // U = C L_v: A[i][k] = c[i][k] with k = 4 ks + g4 (register ks of this lane)
+      v4d accU = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int k = 4 * ks + g4;
+        const double lvk = k < ngl ? lag(r16, vnode(k)) : 0.0;
+        accU = __builtin_amdgcn_mfma_f64_16x16x4f64(cval[ks], lvk, accU, 0, 0, 0);
+      }
+      // W += L_u^T U: A[a][i] = l_a(u_i), B[i][b] = U[i][b] with i = 4 ks + g4 (register ks)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int i = 4 * ks + g4;
+        const double lai = i < ngl ? lag(r16, unode(i)) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(lai, accU[ks], acc, 0, 0, 0);
+      }
+    }
+  }
+
+  // ------------------------------------------------------------------ self rule: points
   const unsigned n_rad = (self && KERNEL == 1) ? 4 * ngl : ngl;
   const unsigned ppc = self ? (unsigned)ngl * n_rad : (unsigned)(ngl * ngl);
-  const unsigned n_pts = ppc * (unsigned)nc;
+  const unsigned n_pts = self ? ppc * (unsigned)nc : 0u;
   double* CL = stage + (size_t)wave * 2 * Q * kStage;   // c l_a(u) at [a][point]
   double* LV = CL + Q * kStage;                          // l_b(v) at [b][point]
-  const int r16 = lane & 15, g4 = lane >> 4;
   const int rq = r16 < Q ? r16 : 0;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
   for (unsigned p0 = (unsigned)wave * 64; p0 < n_pts; p0 += kT) {
     const unsigned p = p0 + lane;
     const bool valid = p < n_pts;
@@ -466,35 +573,39 @@ size_t lds_bytes() {
 }
 
 template <int Q>
-void launch_q(const NWArgs& A, int64_t n, bool parametrix, hipStream_t st, size_t lds_limit) {
+void launch_q(const NWArgs& A, int64_t n, bool parametrix, bool self, hipStream_t st, size_t lds_limit) {
   const size_t lds = lds_bytes<Q>();
   PMX_REQUIRE(lds + 12 * 1024 <= lds_limit, PMX_ERR_INVALID,
               "q too large for the local-rule kernel's LDS on this device");
   const dim3 block(64 * waves_for<Q>());
-  if (parametrix)
-    hipLaunchKernelGGL((k_near_weights<1, Q>), dim3(n), block, lds, st, A);
-  else
-    hipLaunchKernelGGL((k_near_weights<0, Q>), dim3(n), block, lds, st, A);
+  if (parametrix) {
+    if (self) hipLaunchKernelGGL((k_near_weights<1, Q, true>), dim3(n), block, lds, st, A);
+    else hipLaunchKernelGGL((k_near_weights<1, Q, false>), dim3(n), block, lds, st, A);
+  } else {
+    if (self) hipLaunchKernelGGL((k_near_weights<0, Q, true>), dim3(n), block, lds, st, A);
+    else hipLaunchKernelGGL((k_near_weights<0, Q, false>), dim3(n), block, lds, st, A);
+  }
   PMX_HIP(hipGetLastError());
 }
 
-void launch_dispatch(int q, const NWArgs& A, int64_t n, bool parametrix, hipStream_t st, size_t lds_limit) {
+void launch_dispatch(int q, const NWArgs& A, int64_t n, bool parametrix, bool self, hipStream_t st,
+                     size_t lds_limit) {
   switch (q) {
-    case 2: launch_q<2>(A, n, parametrix, st, lds_limit); break;
-    case 3: launch_q<3>(A, n, parametrix, st, lds_limit); break;
-    case 4: launch_q<4>(A, n, parametrix, st, lds_limit); break;
-    case 5: launch_q<5>(A, n, parametrix, st, lds_limit); break;
-    case 6: launch_q<6>(A, n, parametrix, st, lds_limit); break;
-    case 7: launch_q<7>(A, n, parametrix, st, lds_limit); break;
-    case 8: launch_q<8>(A, n, parametrix, st, lds_limit); break;
-    case 9: launch_q<9>(A, n, parametrix, st, lds_limit); break;
-    case 10: launch_q<10>(A, n, parametrix, st, lds_limit); break;
-    case 11: launch_q<11>(A, n, parametrix, st, lds_limit); break;
-    case 12: launch_q<12>(A, n, parametrix, st, lds_limit); break;
-    case 13: launch_q<13>(A, n, parametrix, st, lds_limit); break;
-    case 14: launch_q<14>(A, n, parametrix, st, lds_limit); break;
-    case 15: launch_q<15>(A, n, parametrix, st, lds_limit); break;
-    case 16: launch_q<16>(A, n, parametrix, st, lds_limit); break;
+    case 2: launch_q<2>(A, n, parametrix, self, st, lds_limit); break;
+    case 3: launch_q<3>(A, n, parametrix, self, st, lds_limit); break;
+    case 4: launch_q<4>(A, n, parametrix, self, st, lds_limit); break;
+    case 5: launch_q<5>(A, n, parametrix, self, st, lds_limit); break;
+    case 6: launch_q<6>(A, n, parametrix, self, st, lds_limit); break;
+    case 7: launch_q<7>(A, n, parametrix, self, st, lds_limit); break;
+    case 8: launch_q<8>(A, n, parametrix, self, st, lds_limit); break;
+    case 9: launch_q<9>(A, n, parametrix, self, st, lds_limit); break;
+    case 10: launch_q<10>(A, n, parametrix, self, st, lds_limit); break;
+    case 11: launch_q<11>(A, n, parametrix, self, st, lds_limit); break;
+    case 12: launch_q<12>(A, n, parametrix, self, st, lds_limit); break;
+    case 13: launch_q<13>(A, n, parametrix, self, st, lds_limit); break;
+    case 14: launch_q<14>(A, n, parametrix, self, st, lds_limit); break;
+    case 15: launch_q<15>(A, n, parametrix, self, st, lds_limit); break;
+    case 16: launch_q<16>(A, n, parametrix, self, st, lds_limit); break;
     default: PMX_REQUIRE(false, PMX_ERR_INVALID, "q must be in [2, 16]");
   }
 }
@@ -536,16 +647,21 @@ void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists&
   A.X = g.x.p; A.XP = xp.p; A.a = co.a.p; A.w = g.w.p;
   A.tgt = co.tgt.p; A.tg = co.tg.p;
   A.tn = tab.p; A.cinv = tab.p + q; A.gl_t = tab.p + 2 * q; A.gl_w = tab.p + 2 * q + o.n_gl;
-  A.pair_patch = nl.patch.p; A.pair_target = nl.target.p; A.out = out.p; A.err = err.p;
+  A.ptr = nl.ptr.p; A.pair_patch = nl.patch.p; A.pair_target = nl.target.p; A.out = out.p; A.err = err.p;
   int dev = 0;
   PMX_HIP(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   PMX_HIP(hipGetDeviceProperties(&prop, dev));
   const int64_t chunk = 1 << 20;
-  for (int64_t p0 = 0; p0 < nl.nnz; p0 += chunk) {
+  for (int64_t p0 = 0; p0 < g.N; p0 += chunk) {   // self pairs, one per target
+    A.pair0 = p0;
+    const int64_t n = g.N - p0 < chunk ? g.N - p0 : chunk;
+    launch_dispatch(q, A, n, parametrix, true, st, prop.sharedMemPerBlock);
+  }
+  for (int64_t p0 = 0; p0 < nl.nnz; p0 += chunk) {   // the other near pairs
     A.pair0 = p0;
     const int64_t n = nl.nnz - p0 < chunk ? nl.nnz - p0 : chunk;
-    launch_dispatch(q, A, n, parametrix, st, prop.sharedMemPerBlock);
+    launch_dispatch(q, A, n, parametrix, false, st, prop.sharedMemPerBlock);
   }
   int herr = 0;
   PMX_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
