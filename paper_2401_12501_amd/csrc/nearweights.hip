@@ -188,6 +188,7 @@ k_near_weights(NWArgs A) {
   double* stage = lds;
   int2* front = reinterpret_cast<int2*>(lds);                 // [2][kMaxCells]
   int* flag_split = reinterpret_cast<int*>(front + 2 * kMaxCells);
+  double* corner_xyz = reinterpret_cast<double*>(flag_split + kT);   // [kT / 4 squares][4][3]
   __shared__ Cell cells[kMaxCells];
   __shared__ int cell_edge[kMaxCells];
   __shared__ int n_cells;
@@ -275,40 +276,44 @@ k_near_weights(NWArgs A) {
     for (int depth = 0; depth <= kMaxDepth; ++depth) {
       const int nf = n_front[cur];
       if (nf == 0) break;
-      for (int f0 = 0; f0 < nf; f0 += kT) {
-        const int f = f0 + tid;
-        int split = 0;
-        if (f < nf) {
-          const int iu = front[cur * kMaxCells + f].x, iv = front[cur * kMaxCells + f].y;
-          const double h = 2.0 / (double)(1 << depth);
-          const double ua = -1.0 + iu * h, va = -1.0 + iv * h;
-          const double cuu[4] = {ua, ua + h, ua + h, ua};
-          const double cvv[4] = {va, va, va + h, va + h};
-          double cx[4][3];
-          for (int k = 0; k < 4; ++k) {
+      // four threads per square, one corner image each; then one thread per square decides
+      for (int f0 = 0; f0 < nf; f0 += kT / 4) {
+        const int nsq = nf - f0 < kT / 4 ? nf - f0 : kT / 4;
+        {
+          const int sq = tid >> 2, k = tid & 3;
+          if (sq < nsq) {
+            const int iu = front[cur * kMaxCells + f0 + sq].x, iv = front[cur * kMaxCells + f0 + sq].y;
+            const double h = 2.0 / (double)(1 << depth);
+            const double ua = -1.0 + iu * h, va = -1.0 + iv * h;
+            const double cu = (k == 1 || k == 2) ? ua + h : ua;   // corners (ua,va) (ub,va) (ub,vb) (ua,vb)
+            const double cv = (k >= 2) ? va + h : va;
             double lu[Q], lv[Q], g[3];
-            lagrange_q<Q>(tn, cinv, cuu[k], lu);
-            lagrange_q<Q>(tn, cinv, cvv[k], lv);
+            lagrange_q<Q>(tn, cinv, cu, lu);
+            lagrange_q<Q>(tn, cinv, cv, lv);
             interp_q<Q, 3>(opaque(F), lu, lv, g);
-            cx[k][0] = g[0]; cx[k][1] = g[1]; cx[k][2] = g[2];
+            corner_xyz[tid * 3] = g[0];
+            corner_xyz[tid * 3 + 1] = g[1];
+            corner_xyz[tid * 3 + 2] = g[2];
           }
+        }
+        __syncthreads();
+        if (tid < nsq) {
+          const double* cx = corner_xyz + tid * 12;
           double m[3];
-          for (int c = 0; c < 3; ++c) m[c] = 0.25 * (cx[0][c] + cx[1][c] + cx[2][c] + cx[3][c]);
+          for (int c = 0; c < 3; ++c) m[c] = 0.25 * (cx[c] + cx[3 + c] + cx[6 + c] + cx[9 + c]);
           double rad = 0.0;
           for (int k = 0; k < 4; ++k) {
-            const double d0 = cx[k][0] - m[0], d1 = cx[k][1] - m[1], d2 = cx[k][2] - m[2];
+            const double d0 = cx[3 * k] - m[0], d1 = cx[3 * k + 1] - m[1], d2 = cx[3 * k + 2] - m[2];
             rad = fmax(rad, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
           }
           const double e0 = T.x[0] - m[0], e1 = T.x[1] - m[1], e2 = T.x[2] - m[2];
           const double dist = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-          split = (dist < A.eta * rad && depth < kMaxDepth) ? 1 : 0;
+          flag_split[tid] = (dist < A.eta * rad && depth < kMaxDepth) ? 1 : 0;
         }
-        flag_split[tid] = split;
         __syncthreads();
         if (tid == 0) {
           const int nxt = cur ^ 1;
-          const int lim = nf - f0 < kT ? nf - f0 : kT;
-          for (int t = 0; t < lim; ++t) {
+          for (int t = 0; t < nsq; ++t) {
             const int iu = front[cur * kMaxCells + f0 + t].x, iv = front[cur * kMaxCells + f0 + t].y;
             if (flag_split[t]) {
               const int cu2[4] = {2 * iu, 2 * iu + 1, 2 * iu, 2 * iu + 1};
@@ -363,26 +368,48 @@ k_near_weights(NWArgs A) {
   // which is exactly where the next product's A operand for k-step r has to be).
   if (!self && nc > 0) {
     constexpr int KS = (Q + 3) / 4;   // k-steps over a patch index (a or b)
-    // Lagrange value l_j(s) of node j (lane-dependent) at s; zero for j >= q
-    auto lag = [&](int j, double s) -> double {
-      double prod = 1.0;
+    // the patch's node fields go to LDS once per pair (sX[f][a][b]); the rule tables and
+    // Lagrange denominators a lane needs are loaded into registers ahead of the leaves
+    double* sX = stage;   // 10 q^2 doubles (the self rule's staging area is not used here)
+    for (int e = tid; e < 10 * q2; e += kT) {
+      const int f = e / q2, j = e - f * q2;
+      sX[e] = A.XP[(base + j) * 10 + f];
+    }
+    __syncthreads();
+    const bool rin = r16 < ngl;
+    const double t_r = gl_t[rin ? r16 : 0], w_r = rin ? gl_w[r16] : 0.0;
+    double t_g[4], w_g[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int m = 4 * ks + g4;
+      t_g[ks] = gl_t[m < ngl ? m : 0];
+      w_g[ks] = m < ngl ? gl_w[m] : 0.0;
+    }
+    double ci_g[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int j = 4 * ks + g4;
+      ci_g[ks] = j < Q ? A.cinv[j] : 0.0;
+    }
+    const double ci_r = r16 < Q ? A.cinv[r16] : 0.0;
+    // Lagrange value l_j(s) = cinv_j prod_{m != j} (s - t_m); cj = 0 for j >= q
+    auto lag = [&](int j, double s, double cj) -> double {
+      double prod = cj;
 #pragma unroll
       for (int m = 0; m < Q; ++m) prod *= (m == j) ? 1.0 : (s - tn[m]);
-      return j < Q ? prod * A.cinv[j < Q ? j : 0] : 0.0;
+      return prod;
     };
-    const double* __restrict__ XPp = A.XP + base * 10;
     for (int cell = wave; cell < nc; cell += kW) {
       const Cell C = cells[cell];
       const double h = 2.0 / (double)(1 << C.n.depth);
       const double ua = -1.0 + C.n.iu * h, va = -1.0 + C.n.iv * h;
       const double hh = 0.5 * h;
-      auto unode = [&](int i) { return ua + hh * (gl_t[i < ngl ? i : 0] + 1.0); };
-      auto vnode = [&](int k) { return va + hh * (gl_t[k < ngl ? k : 0] + 1.0); };
+      const double u_r = ua + hh * (t_r + 1.0), v_r = va + hh * (t_r + 1.0);
       double lvb[KS], lua[KS];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        lvb[ks] = lag(4 * ks + g4, vnode(r16));   // B[b][k] = l_b(v_k), b = 4 ks + g4, k = r16
-        lua[ks] = lag(4 * ks + g4, unode(r16));   // B[a][i] = l_a(u_i), a = 4 ks + g4, i = r16
+        lvb[ks] = lag(4 * ks + g4, v_r, ci_g[ks]);   // B[b][k] = l_b(v_k), b = 4 ks + g4, k = r16
+        lua[ks] = lag(4 * ks + g4, u_r, ci_g[ks]);   // B[a][i] = l_a(u_i), a = 4 ks + g4, i = r16
       }
       // G_f^T: lane holds G_f at (k = g4 + 4 r, i = r16)
       v4d acc2[10];
@@ -392,7 +419,7 @@ k_near_weights(NWArgs A) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
           const int b = 4 * ks + g4;
-          const double xv = (r16 < Q && b < Q) ? XPp[(r16 < Q ? r16 * Q + b : 0) * 10 + f] : 0.0;
+          const double xv = (r16 < Q && b < Q) ? sX[f * q2 + (r16 < Q ? r16 : 0) * Q + (b < Q ? b : 0)] : 0.0;
           t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, lvb[ks], t1, 0, 0, 0);
         }
         acc2[f] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -400,12 +427,11 @@ k_near_weights(NWArgs A) {
         for (int ks = 0; ks < KS; ++ks)   // A[k][a] = T_f[a = 4 ks + g4][k = r16] = t1[ks]
           acc2[f] = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[ks], lua[ks], acc2[f], 0, 0, 0);
       }
-      // kernel at the lane's four points
+      // kernel at the lane's four points (i = r16, k = g4 + 4 r)
       double cval[4];
-      const double wi = gl_w[r16 < ngl ? r16 : 0];
+      const double hh2 = hh * hh;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int k = g4 + 4 * r;
         double gv[10];
 #pragma unroll
         for (int f = 0; f < 10; ++f) gv[f] = acc2[f][r];
@@ -415,23 +441,20 @@ k_near_weights(NWArgs A) {
         const double Jt = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
         const double inv_as = 1.0 / gv[9];
         const double Fk = KERNEL == 0 ? remainder_dev(T, gv, inv_as) : parametrix_dev(T, gv, inv_as);
-        const bool ok = r16 < ngl && k < ngl;
-        cval[r] = ok ? wi * gl_w[k < ngl ? k : 0] * hh * hh * Fk * Jt : 0.0;
+        cval[r] = w_r * w_g[r] * hh2 * Fk * Jt;   // zero weight outside the n_gl x n_gl rule
       }
       // U = C L_v: A[i][k] = c[i][k] with k = 4 ks + g4 (register ks of this lane)
       v4d accU = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
-        const int k = 4 * ks + g4;
-        const double lvk = k < ngl ? lag(r16, vnode(k)) : 0.0;
-        accU = __builtin_amdgcn_mfma_f64_16x16x4f64(cval[ks], lvk, accU, 0, 0, 0);
+        const double lvk = lag(r16, va + hh * (t_g[ks] + 1.0), ci_r);
+        accU = __builtin_amdgcn_mfma_f64_16x16x4f64(cval[ks], w_g[ks] != 0.0 ? lvk : 0.0, accU, 0, 0, 0);
       }
       // W += L_u^T U: A[a][i] = l_a(u_i), B[i][b] = U[i][b] with i = 4 ks + g4 (register ks)
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
-        const int i = 4 * ks + g4;
-        const double lai = i < ngl ? lag(r16, unode(i)) : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(lai, accU[ks], acc, 0, 0, 0);
+        const double lai = lag(r16, ua + hh * (t_g[ks] + 1.0), ci_r);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w_g[ks] != 0.0 ? lai : 0.0, accU[ks], acc, 0, 0, 0);
       }
     }
   }
@@ -566,7 +589,8 @@ namespace {
 template <int Q>
 size_t lds_bytes() {
   const size_t stage = (size_t)waves_for<Q>() * 2 * Q * kStage * sizeof(double);
-  const size_t front = 2 * kMaxCells * sizeof(int2) + 64 * waves_for<Q>() * sizeof(int);
+  const size_t front = 2 * kMaxCells * sizeof(int2) + 64 * waves_for<Q>() * sizeof(int) +
+                       16 * waves_for<Q>() * 12 * sizeof(double);
   const size_t red = (size_t)waves_for<Q>() * 256 * sizeof(double);
   size_t m = stage > front ? stage : front;
   return m > red ? m : red;
