@@ -291,6 +291,26 @@ def test_funk_hecke_eigenvalues():
         assert np.abs(u[:, c] - ref).max() < 3e-6 * np.abs(ref).max()
 
 
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return [(int(r[0]), float(r[1])) for r in rows]
+
+
+def test_sphere_solve_reproduces_lb_eigenvalues(sphere_a1):
+    """Full path on the unit sphere with a = 1: solve (I + R + rank one) sigma = f and
+    represent u = K[sigma] for f = Y_lm; the paper's eigenvalues (tests/golden,
+    Section 7) give u = f / (-l(l+1))."""
+    p, op, B, A = sphere_a1
+    X = torch.tensor(p.surface.x)
+    for l, lam in _golden("sphere_lb_eigenvalues.txt"):
+        f = real_sph_harm_cartesian(l, min(l, 1), X).numpy()[:, None]
+        sig = op.solve(f, A)
+        u = op.represent(sig, B)
+        assert np.abs(u - f / lam).max() < 1e-4 * np.abs(f / lam).max(), l
+
+
 def test_dilation_invariance():
     """Section 3, observation 3: R_LB[sigma](lambda x) on lambda G equals R_LB[sigma](x) on G.
     The R part of the apply, y - sigma - s, is unchanged and s = int sigma scales by lambda^2
