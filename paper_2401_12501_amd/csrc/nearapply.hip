@@ -80,12 +80,12 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(Group<SumArgs> g) {
   if (threadIdx.x == 0) A.out[r] = red[0];
 }
 
-// One wavefront per target.  identity != 0: add sigma_i and s_r (the operator A);
+// kSub lanes per target (several targets per wavefront).  identity != 0: add sigma_i and s_r (the operator A);
 // identity == 0: representation (near blocks D plus far field only).  The target's
 // near-patch ids sit in lane registers and are fetched by shuffle, so the loads of
 // the streaming loop (C and the gathered sigma) do not wait on index loads.
 // Block index of element e: e / q2 = (e * magic) >> 32, magic = ceil(2^32 / q2)
-// (exact for e < 2^32 / q2; e is below 64 q2 here).
+// (exact for e < 2^32 / q2; e is below kSub q2 here).
 struct CombineArgs {
   int64_t N;
   int q2, n_rhs, r0, n_far, identity;
@@ -99,35 +99,67 @@ struct CombineArgs {
   double* y;
 };
 
+constexpr int kSub = 32;                  // lanes per target: two targets per wavefront
+constexpr int kFarR = 64 / kSub;          // far-field partial registers per lane (up to 64 chunks)
+constexpr int kTPB = kBlock / kSub;       // targets per workgroup
+
+__device__ __forceinline__ double sub_sum(double v) {
+#pragma unroll
+  for (int o = kSub / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kSub);
+  return v;
+}
+
 template <int NR>
 __global__ void __launch_bounds__(kBlock) k_near_combine(Group<CombineArgs> g) {
   int64_t lb;
   const CombineArgs& A = seg_of(g, blockIdx.x, lb);
   const int64_t N = A.N;
   const int q2 = A.q2;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t i = lb * (kBlock / kWave) + (threadIdx.x / kWave);
-  if (i >= N) return;
-  const int64_t b0 = A.ptr[i];
-  const int nb = (int)(A.ptr[i + 1] - b0);
+  const int sl = threadIdx.x & (kSub - 1);
+  const int64_t i = lb * kTPB + (threadIdx.x / kSub);
+  const bool live = i < N;                  // both halves of a wave stay for the shuffles
+  const int64_t ii = live ? i : N - 1;
   const double* __restrict__ sigma = A.sigma;
+  // the terms that do not depend on the near blocks are loaded first, so their latency
+  // overlaps the block stream: register k of lane sl holds far-field partial k kSub + sl
+  double far_p[NR][kFarR], sig_i[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int rr = A.r0 + r;
+#pragma unroll
+    for (int k = 0; k < kFarR; ++k) {
+      const int c = k * kSub + sl;
+      far_p[r][k] = c < A.n_far ? A.far[((int64_t)c * A.n_rhs + rr) * N + ii] : 0.0;
+    }
+    sig_i[r] = (A.identity && sl == 0) ? sigma[(int64_t)rr * N + ii] : 0.0;
+  }
+  const int64_t b0 = A.ptr[ii];
+  const int nb = live ? (int)(A.ptr[ii + 1] - b0) : 0;
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  for (int gq = 0; gq < nb; gq += kWave) {          // groups of up to 64 near patches
-    const int ng = nb - gq < kWave ? nb - gq : kWave;
-    const int my_patch = lane < ng ? A.patch[b0 + gq + lane] : 0;
+  // the targets of a wave may differ in patch count: loop to the largest
+  int nb_max = nb;
+#pragma unroll
+  for (int o = kSub; o < 64; o <<= 1) nb_max = max(nb_max, __shfl_xor(nb_max, o, 64));
+  for (int gq = 0; gq < nb_max; gq += kSub) {     // groups of up to kSub near patches
+    const int ng = nb - gq < kSub ? (nb - gq > 0 ? nb - gq : 0) : kSub;
+    const int my_patch = sl < ng ? A.patch[b0 + gq + sl] : 0;
     const double* __restrict__ Cg = A.Cb + (b0 + gq) * q2;
     const uint32_t len = (uint32_t)(ng * q2);
-    // wave-uniform trip count: every lane takes part in the shuffle, loads are predicated
-#pragma unroll 4
-    for (uint32_t e0 = 0; e0 < len; e0 += kWave) {
-      const uint32_t e = e0 + lane;
+    int ng_max = ng;
+#pragma unroll
+    for (int o = kSub; o < 64; o <<= 1) ng_max = max(ng_max, __shfl_xor(ng_max, o, 64));
+    const uint32_t len_max = (uint32_t)(ng_max * q2);
+    // trip count uniform over the wave: every lane takes part in the shuffles, loads are predicated
+#pragma unroll 8
+    for (uint32_t e0 = 0; e0 < len_max; e0 += kSub) {
+      const uint32_t e = e0 + sl;
       const bool ok = e < len;
-      const uint32_t ee = ok ? e : len - 1;
+      const uint32_t ee = ok ? e : 0;
       const uint32_t blk = (uint32_t)(((uint64_t)ee * A.magic) >> 32);
       const uint32_t loc = ee - blk * (uint32_t)q2;
-      const int P = __shfl(my_patch, (int)blk, kWave);
+      const int P = __shfl(my_patch, (int)blk, kSub);
       if (ok) {
         const double c = Cg[e];
         const int64_t col = (int64_t)P * q2 + loc;
@@ -136,17 +168,27 @@ __global__ void __launch_bounds__(kBlock) k_near_combine(Group<CombineArgs> g) {
       }
     }
   }
+  // near sum over the target's lanes, plus the far-field partials in chunk order
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = wave_sum(acc[r]);
-  if (lane == 0) {
+  for (int r = 0; r < NR; ++r) acc[r] = sub_sum(acc[r]);
+  double f[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    f[r] = 0.0;
+    for (int c = 0; c < A.n_far; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < kFarR; ++k)
+        if (c / kSub == k) v = __shfl(far_p[r][k], c % kSub, kSub);
+      f[r] += v;
+    }
+  }
+  if (sl == 0 && live) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int rr = A.r0 + r;
-      double v = acc[r];
-      double f = 0.0;
-      for (int c = 0; c < A.n_far; ++c) f += A.far[((int64_t)c * A.n_rhs + rr) * N + i];
-      v += f;
-      if (A.identity) v += sigma[(int64_t)rr * N + i] + A.ssum[rr];
+      double v = acc[r] + f[r];
+      if (A.identity) v += sig_i[r] + A.ssum[rr];
       A.y[(int64_t)rr * N + i] = v;
     }
   }
@@ -217,7 +259,7 @@ namespace {
 template <int NR>
 void combine_launch(const std::vector<CombineArgs>& recs, hipStream_t st) {
   std::vector<int64_t> nb;
-  for (const CombineArgs& c : recs) nb.push_back((c.N + (kBlock / kWave) - 1) / (kBlock / kWave));
+  for (const CombineArgs& c : recs) nb.push_back((c.N + kTPB - 1) / kTPB);
   launch_grouped(recs, nb, [&](const Group<CombineArgs>& g, int64_t nblk) {
     hipLaunchKernelGGL(k_near_combine<NR>, dim3((unsigned)nblk), dim3(kBlock), 0, st, g);
     PMX_HIP(hipGetLastError());
