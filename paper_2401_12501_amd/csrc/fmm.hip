@@ -282,9 +282,9 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
 // generates the unit-box kernel for all nine components of its (row, m) pairs in
 // registers as MFMA A operands and keeps nine accumulator tiles.  Small items keep
 // the grid many times larger than the number of resident workgroups, so the chip
-// stays busy to the end of the launch; the wave count divides the row tiles evenly.  Each pair writes its own output
-// slot; k_m2l_reduce then sums a target's slots in a fixed order, so no atomics are
-// needed and the result does not depend on scheduling.
+// stays busy to the end of the launch; the wave count divides the row tiles evenly.
+// Each pair writes its own output slot; k_m2l_reduce then sums a target's slots in a
+// fixed order, so no atomics are needed and the result does not depend on scheduling.
 constexpr int kM2LStride = 226;   // LDS row stride (== 2 mod 32: conflict-free B reads)
 
 struct M2LArgs {
@@ -355,11 +355,11 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
       const float4 tm = sN[m < p3 ? m : 0];
       const float rx = tlx - tm.x, ry = tly - tm.y, rz = tlz - tm.z;
       const float inv = ok ? __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz))) : 0.0f;
-      const float i2 = inv * inv;
+      // r / r^2 and (r r^T) / r^4 = (r / r^2)(r / r^2)^T
       float a[9];
       a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
-      a[3] = rx * rx * i2; a[4] = rx * ry * i2; a[5] = rx * rz * i2;
-      a[6] = ry * ry * i2; a[7] = ry * rz * i2; a[8] = rz * rz * i2;
+      a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
+      a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
       const float b0 = sBc[m < p3 ? m : 0];
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[c], 0, 0, 0);
