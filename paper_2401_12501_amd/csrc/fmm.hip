@@ -64,7 +64,8 @@ struct FMM {
   DBuf<float> tab;                   // t_k (p), M1[2][p][p], node table (3 p^3)
   DBuf<float> W, Lc;                 // multipoles n_boxes*p3, locals n_boxes*9*p3
   DBuf<float> slots;                 // M2L output per pair (9*p3 each)
-  DBuf<int32_t> r_ptr, r_idx;        // per box of levels >= 2: its pairs (CSR, pair order)
+  DBuf<int32_t> r_ptr;              // per box of levels >= 2: its run of output slots
+  DBuf<int32_t> m2l_slot;           // output slot of each pair (a box's slots are contiguous)
   DBuf<float> phis;                  // 27 N: P2P partial sums per U-list slot (sorted order)
 };
 
@@ -292,6 +293,7 @@ struct M2LArgs {
   const int4* items;      // (first pair, count, -, offset code)
   const int32_t* ps;      // source box per pair
   const int32_t* plev;    // level per pair
+  const int32_t* pslot;   // output slot per pair
   const float* W;
   float* slots;
   double h0;
@@ -315,6 +317,7 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
   __shared__ float sB[kItemCols * kM2LStride];
   __shared__ float4 sN[p3];
   __shared__ float sS[2][kItemCols];
+  __shared__ int sP[kItemCols];
   const int4 it = A.items[lb];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ncol = it.y;
@@ -332,6 +335,7 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
     const double h = A.h0 / (double)(1 << (j < ncol ? A.plev[it.x + j] : 0));
     sS[0][j] = (float)(1.0 / h);
     sS[1][j] = (float)(1.0 / (h * h));
+    sP[j] = j < ncol ? A.pslot[it.x + j] : 0;
   }
   __syncthreads();
   const int code = it.w;
@@ -366,28 +370,32 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
     }
     const int pj = cb * 16 + col;
     if (pj < ncol) {
-      float* out = slots + (int64_t)(it.x + pj) * 9 * p3;
+      float* out = slots + (int64_t)sP[pj] * 9 * p3;
       const float s1 = sS[0][pj], s2 = sS[1][pj];
+      const int l0 = rt * 16 + 4 * kq;
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         const float sc = c < 3 ? s1 : s2;
+        if (l0 + 3 < p3 && (p3 % 4) == 0) {   // four consecutive rows: one 16-byte store
+          *reinterpret_cast<float4*>(out + c * p3 + l0) =
+              make_float4(sc * acc[c][0], sc * acc[c][1], sc * acc[c][2], sc * acc[c][3]);
+        } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int l = rt * 16 + 4 * kq + r;
-          if (l < p3) out[c * p3 + l] = sc * acc[c][r];
+          for (int r = 0; r < 4; ++r)
+            if (l0 + r < p3) out[c * p3 + l0 + r] = sc * acc[c][r];
         }
       }
     }
   }
 }
 
-// L[T] = sum of T's M2L output slots, in pair order (one block per box of levels >= 2).
+// L[T] = sum of T's M2L output slots, in pair order (one block per box of levels >= 2);
+// a box's slots are contiguous, so the reads stream.
 // Each thread owns four consecutive entries (float4); the pair loop is unrolled so the
 // independent slot loads are in flight together.
 struct RedArgs {
   int64_t box0;
-  const int32_t* rptr;
-  const int32_t* ridx;
+  const int32_t* rptr;     // a box's slots are [rptr[b], rptr[b + 1])
   const float* slots;
   float* Lc;
 };
@@ -401,7 +409,6 @@ __global__ void __launch_bounds__(512) k_m2l_reduce(Group<RedArgs> g) {
   const RedArgs& A = seg_of(g, blockIdx.x, b);
   const int64_t box0 = A.box0;
   const int32_t* __restrict__ rptr = A.rptr;
-  const int32_t* __restrict__ ridx = A.ridx;
   const float* __restrict__ slots = A.slots;
   float* __restrict__ Lc = A.Lc;
   const int k0 = rptr[b], k1 = rptr[b + 1];
@@ -410,7 +417,7 @@ __global__ void __launch_bounds__(512) k_m2l_reduce(Group<RedArgs> g) {
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll 8
     for (int k = k0; k < k1; ++k) {
-      const float4 v = s4[(int64_t)ridx[k] * n4 + e];
+      const float4 v = s4[(int64_t)k * n4 + e];
       acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
     }
     reinterpret_cast<float4*>(Lc)[(box0 + b) * n4 + e] = acc;
@@ -773,12 +780,13 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     for (size_t k = 0; k < pairs.size(); ++k) { pt[k] = pairs[k].t; ps[k] = pairs[k].s; plv[k] = pairs[k].lev; }
     // per-target lists of pair slots (boxes of levels >= 2, pairs in sorted order)
     const int64_t box2 = F->lev_off[2];
-    std::vector<int32_t> rptr(F->n_boxes - box2 + 1, 0), ridx(pairs.size());
+    std::vector<int32_t> rptr(F->n_boxes - box2 + 1, 0);
     for (auto& pr : pairs) rptr[pr.t - box2 + 1]++;
     for (size_t b = 1; b < rptr.size(); ++b) rptr[b] += rptr[b - 1];
+    std::vector<int32_t> spos(pairs.size());
     {
       std::vector<int32_t> fill(rptr.begin(), rptr.end() - 1);
-      for (size_t k = 0; k < pairs.size(); ++k) ridx[fill[pairs[k].t - box2]++] = (int32_t)k;
+      for (size_t k = 0; k < pairs.size(); ++k) spos[k] = fill[pairs[k].t - box2]++;
     }
     F->n_items = (int64_t)items.size();
     // P2P waves: (leaf, 64-target chunk, U-list slot) -> target and source ranges
@@ -823,7 +831,7 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     up(F->u_idx, uidx);
     up(F->m2l_t, pt);
     up(F->r_ptr, rptr);
-    up(F->r_idx, ridx);
+    up(F->m2l_slot, spos);
     up(F->m2l_s, ps);
     up(F->m2l_lv, plv);
     up(F->items, items);
@@ -908,10 +916,10 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
     std::vector<int64_t> lb, rb;
     for (pmx_operator* op : ops) {
       FMM* F = op->fmm;
-      la.push_back({F->tab.p, F->items.p, F->m2l_s.p, F->m2l_lv.p, F->W.p, F->slots.p, F->h0});
+      la.push_back({F->tab.p, F->items.p, F->m2l_s.p, F->m2l_lv.p, F->m2l_slot.p, F->W.p, F->slots.p, F->h0});
       lb.push_back(F->n_items);
       const int64_t box2 = F->lev_off[2];
-      ra.push_back({box2, F->r_ptr.p, F->r_idx.p, F->slots.p, F->Lc.p});
+      ra.push_back({box2, F->r_ptr.p, F->slots.p, F->Lc.p});
       rb.push_back(F->n_boxes - box2);
     }
     launch_grouped(la, lb, [&](const Group<M2LArgs>& g, int64_t nb) {
@@ -1014,7 +1022,7 @@ uint64_t fmm_bytes(const FMM* f) {
          f->octant.bytes() + f->leaf_start.bytes() + f->perm.bytes() + f->pts.bytes() + f->qs.bytes() +
          f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_desc.bytes() + f->p2p_slot.bytes() + f->m2l_t.bytes() +
          f->m2l_s.bytes() + f->m2l_lv.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
-         f->slots.bytes() + f->r_ptr.bytes() + f->r_idx.bytes();
+         f->slots.bytes() + f->r_ptr.bytes() + f->m2l_slot.bytes();
 }
 
 }  // namespace pmx
