@@ -311,25 +311,36 @@ k_near_weights(NWArgs A) {
           flag_split[tid] = (dist < A.eta * rad && depth < kMaxDepth) ? 1 : 0;
         }
         __syncthreads();
-        if (tid == 0) {
+        // compaction in square order by the first wave (nsq <= 64): a square that splits
+        // appends its four children to the next front, one that does not becomes a leaf
+        if (tid < 64) {
           const int nxt = cur ^ 1;
-          for (int t = 0; t < nsq; ++t) {
-            const int iu = front[cur * kMaxCells + f0 + t].x, iv = front[cur * kMaxCells + f0 + t].y;
-            if (flag_split[t]) {
+          const bool in = tid < nsq;
+          const bool sp = in && flag_split[tid] != 0;
+          const uint64_t m_split = __ballot(sp), m_leaf = __ballot(in && !sp);
+          const uint64_t below = (1ull << tid) - 1ull;
+          const int f_base = n_front[nxt], c_base = n_cells;
+          if (in) {
+            const int iu = front[cur * kMaxCells + f0 + tid].x, iv = front[cur * kMaxCells + f0 + tid].y;
+            if (sp) {
+              const int o = f_base + 4 * __popcll(m_split & below);
               const int cu2[4] = {2 * iu, 2 * iu + 1, 2 * iu, 2 * iu + 1};
               const int cv2[4] = {2 * iv, 2 * iv, 2 * iv + 1, 2 * iv + 1};
-              for (int c = 0; c < 4; ++c) {
-                if (n_front[nxt] < kMaxCells) front[nxt * kMaxCells + n_front[nxt]] = make_int2(cu2[c], cv2[c]);
-                n_front[nxt]++;
-              }
+              for (int c = 0; c < 4; ++c)
+                if (o + c < kMaxCells) front[nxt * kMaxCells + o + c] = make_int2(cu2[c], cv2[c]);
             } else {
-              if (n_cells < kMaxCells) {
-                cells[n_cells].n.depth = depth;
-                cells[n_cells].n.iu = iu;
-                cells[n_cells].n.iv = iv;
+              const int o = c_base + __popcll(m_leaf & below);
+              if (o < kMaxCells) {
+                cells[o].n.depth = depth;
+                cells[o].n.iu = iu;
+                cells[o].n.iv = iv;
               }
-              n_cells++;
             }
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (tid == 0) {
+            n_front[nxt] = f_base + 4 * __popcll(m_split);
+            n_cells = c_base + __popcll(m_leaf);
           }
         }
         __syncthreads();
