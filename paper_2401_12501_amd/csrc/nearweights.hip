@@ -389,38 +389,36 @@ k_near_weights(NWArgs A) {
     __syncthreads();
     const bool rin = r16 < ngl;
     const double t_r = gl_t[rin ? r16 : 0], w_r = rin ? gl_w[r16] : 0.0;
-    double t_g[4], w_g[4];
+    double w_g[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int m = 4 * ks + g4;
-      t_g[ks] = gl_t[m < ngl ? m : 0];
       w_g[ks] = m < ngl ? gl_w[m] : 0.0;
     }
-    double ci_g[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int j = 4 * ks + g4;
-      ci_g[ks] = j < Q ? A.cinv[j] : 0.0;
-    }
-    const double ci_r = r16 < Q ? A.cinv[r16] : 0.0;
-    // Lagrange value l_j(s) = cinv_j prod_{m != j} (s - t_m); cj = 0 for j >= q
-    auto lag = [&](int j, double s, double cj) -> double {
-      double prod = cj;
-#pragma unroll
-      for (int m = 0; m < Q; ++m) prod *= (m == j) ? 1.0 : (s - tn[m]);
-      return prod;
-    };
+    // per wave, per leaf: Lagrange tables Lu[i][a] = l_a(u_i), Lv[k][b] = l_b(v_k) in LDS,
+    // one point's row per lane (lanes 0-15: u_i, lanes 16-31: v_k)
+    double* sLu = stage + 10 * q2 + (size_t)wave * 32 * Q;
+    double* sLv = sLu + 16 * Q;
     for (int cell = wave; cell < nc; cell += kW) {
       const Cell C = cells[cell];
       const double h = 2.0 / (double)(1 << C.n.depth);
       const double ua = -1.0 + C.n.iu * h, va = -1.0 + C.n.iv * h;
       const double hh = 0.5 * h;
-      const double u_r = ua + hh * (t_r + 1.0), v_r = va + hh * (t_r + 1.0);
+      if (lane < 32) {
+        double l[Q];
+        lagrange_q<Q>(tn, cinv, (lane < 16 ? ua : va) + hh * (t_r + 1.0), l);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) sLu[lane * Q + j] = l[j];   // lane >= 16 writes the Lv rows
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       double lvb[KS], lua[KS];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        lvb[ks] = lag(4 * ks + g4, v_r, ci_g[ks]);   // B[b][k] = l_b(v_k), b = 4 ks + g4, k = r16
-        lua[ks] = lag(4 * ks + g4, u_r, ci_g[ks]);   // B[a][i] = l_a(u_i), a = 4 ks + g4, i = r16
+        const int j = 4 * ks + g4;
+        lvb[ks] = j < Q ? sLv[r16 * Q + (j < Q ? j : 0)] : 0.0;   // B[b][k] = l_b(v_k), b = j, k = r16
+        lua[ks] = j < Q ? sLu[r16 * Q + (j < Q ? j : 0)] : 0.0;   // B[a][i] = l_a(u_i), a = j, i = r16
       }
       // G_f^T: lane holds G_f at (k = g4 + 4 r, i = r16)
       v4d acc2[10];
@@ -458,15 +456,18 @@ k_near_weights(NWArgs A) {
       v4d accU = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
-        const double lvk = lag(r16, va + hh * (t_g[ks] + 1.0), ci_r);
+        const double lvk = r16 < Q ? sLv[(4 * ks + g4) * Q + (r16 < Q ? r16 : 0)] : 0.0;   // l_b(v_k), b = r16
         accU = __builtin_amdgcn_mfma_f64_16x16x4f64(cval[ks], w_g[ks] != 0.0 ? lvk : 0.0, accU, 0, 0, 0);
       }
       // W += L_u^T U: A[a][i] = l_a(u_i), B[i][b] = U[i][b] with i = 4 ks + g4 (register ks)
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
-        const double lai = lag(r16, ua + hh * (t_g[ks] + 1.0), ci_r);
+        const double lai = r16 < Q ? sLu[(4 * ks + g4) * Q + (r16 < Q ? r16 : 0)] : 0.0;   // l_a(u_i), a = r16
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w_g[ks] != 0.0 ? lai : 0.0, accU[ks], acc, 0, 0, 0);
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // tables are rewritten for the next leaf
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 
