@@ -42,14 +42,14 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0
 # traffic is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "90ca61b10dfb7bf3",
-                "kib": [("k_m2l", 13138.9, 413950.1)]},
-    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "90ca61b10dfb7bf3",
-                    "kib": [("k_m2l_reduce", 168508.8, 7394.3)]},
-    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "90ca61b10dfb7bf3",
-                "kib": [("k_p2p", 46484.8, 9603.5)]},
-    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "1860a663d24d7d3c",
-             "kib": [("k_near_combine", 281208.2, 1202.7)]},
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "8e6d2530166d5c05",
+                "kib": [("k_m2l", 13656.8, 407773.8)]},
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "8e6d2530166d5c05",
+                    "kib": [("k_m2l_reduce", 166875.0, 7383.7)]},
+    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "8e6d2530166d5c05",
+                "kib": [("k_p2p", 46473.4, 9603.8)]},
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "c400b74ed34f547b",
+             "kib": [("k_near_combine", 281457.1, 1313.1)]},
 }
 
 
