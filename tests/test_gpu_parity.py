@@ -96,6 +96,66 @@ def test_parametrix_blocks(ragged):
     assert worst <= 1e-13 * scale
 
 
+def ulp_sensitivity(orc, i, plist, kernels, base):
+    """max |C(x_i + du t) - C(x_i)| over one-ulp moves du of target i's kernel argument along its
+    tangents and normal t; the patch nodes that the rules interpolate stay where they are.
+
+    With normals taken from the given derivatives, n_i . r is O(eps rho + rho^2) on the
+    interpolated patch (eps: angle between n_i and the interpolant's tangent plane), so
+    (n.r)^2 / r^4 carries an eps^2 / rho^2 part and the rounding of r = x_i - y(u, v) near the
+    target is amplified by about eps^2 / rho_min.  An interpolated source point y is exact only to
+    a few ulps, which is what the move models; on under-resolved surfaces (one patch per cube
+    face) this bounds how closely two correct FP64 evaluations of the self blocks agree."""
+    x_saved = orc.x
+    du = np.spacing(np.abs(x_saved[i]).max())
+    out = {k: 0.0 for k in kernels}
+    try:
+        for t in (orc.xu[i], orc.xv[i], orc.n[i]):
+            orc.x = x_saved.copy()          # patch node arrays keep viewing x_saved
+            orc.x[i] = x_saved[i] + du * t / np.linalg.norm(t)
+            for P, *blk in zip(plist, *(base[k] for k in kernels)):
+                moved = orc.correction_blocks(int(i), int(P), kernels)
+                for k, b in zip(kernels, blk):
+                    out[k] = max(out[k], np.abs(moved[k] - b).max())
+    finally:
+        orc.x = x_saved
+    return out
+
+
+@pytest.mark.parametrize("q,n_gl", [(3, 16), (5, 16), (12, 16), (16, 16), (8, 8), (6, 11)])
+def test_blocks_patch_orders_and_rules(ctx, q, n_gl):
+    """The local-rule kernels are specialised per patch order q and take any n_gl <= 16:
+    correction blocks C (and D for some) on sampled targets match the oracle's, each target within
+    1e-13 of max |C| plus 16 times the oracle's own change under a one-ulp move of the target."""
+    from paper_2401_12501_amd import pmx
+    prob = ellipsoid_problem(k=1, q=q)
+    o = pmx.pmx_default_options()
+    o.n_gl = n_gl
+    surf = pmx.Surface.from_inputs(ctx, prob.surface)
+    op = pmx.Operator(surf, prob.a, prob.grad_a, o)
+    with_D = q in (5, 16)
+    ptr, patch, Cb, Db = op.export_near(with_D=with_D)
+    orc = OracleOperator.from_problem(prob, n_gl=n_gl)
+    rng = np.random.default_rng(q * 100 + n_gl)
+    tg = np.unique(np.concatenate([[0, prob.n - 1], rng.choice(prob.n, 30, replace=False)]))
+    kernels = ("R", "K") if with_D else ("R",)
+    rows = []
+    for i, (plist, blk) in zip(tg, orc.blocks(tg, kernels=kernels)):
+        assert np.array_equal(patch[ptr[i]:ptr[i + 1]], plist)
+        sens = ulp_sensitivity(orc, i, plist, kernels, blk)
+        for k, got in (("R", Cb), ("K", Db)):
+            if k in kernels:
+                rows.append((k, i, np.abs(got[ptr[i]:ptr[i + 1]] - blk[k]).max(), np.abs(blk[k]).max(),
+                             sens[k]))
+    scale = {k: max(r[3] for r in rows if r[0] == k) for k in kernels}
+    worst = {k: max(r[2] for r in rows if r[0] == k) for k in kernels}
+    say(f"[blocks] q={q} n_gl={n_gl}: " + ", ".join(
+        f"{k} {worst[k] / scale[k]:.2e} (max 1-ulp sensitivity "
+        f"{max(r[4] for r in rows if r[0] == k) / scale[k]:.2e})" for k in kernels))
+    for k, i, err, _, sens in rows:
+        assert err <= 1e-13 * scale[k] + 16.0 * sens, f"kernel {k} target {i}: {err:.3e} (1-ulp {sens:.3e})"
+
+
 @pytest.mark.parametrize("which", ["ragged", "sphere"])
 def test_apply_fp64(which, request):
     from paper_2401_12501_amd import pmx
