@@ -191,6 +191,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--fmm-leaf", type=int, default=0, help="FMM leaf occupancy target (0: library default)")
     ap.add_argument("--fmm-order", type=int, default=0, help="FMM interpolation order (0: library default)")
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="mixed solve: inner GMRES tolerance (0: library default)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="mixed applies on one stream (no near/P2P overlap with the M2L chain)")
     ap.add_argument("--serve", type=int, default=64,
                     help="serving requests to run (0: skip); the first quarter calibrates the saturated rate")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -237,6 +241,8 @@ def main():
         opts.fmm_leaf = args.fmm_leaf
     if args.fmm_order:
         opts.fmm_order = args.fmm_order
+    if args.no_overlap:
+        opts.overlap = 0
     op = pmx.Operator(surf, prob.a, prob.grad_a, opts)
     t_setup = time.perf_counter() - t0
     prec = {"mixed": pmx.PMX_PREC_MIXED_FMM, "fp64": pmx.PMX_PREC_FP64_DIRECT}
@@ -336,6 +342,8 @@ def main():
             o.precision = prec[path]
             o.gmres_tol = 1e-8
             o.ir_tol = 1e-8
+            if args.inner_tol:
+                o.inner_tol = args.inner_tol
             torch.cuda.synchronize()
             ts = time.perf_counter()
             try:

@@ -76,7 +76,7 @@ enum {
 typedef struct pmx_options {
   double eta_near;     /* near criterion: within eta patch radii of the centroid (Section 6.1.2: 1.5) */
   int n_gl;            /* Gauss-Legendre order of the local rules (Section 6.1.1: 16) */
-  int fmm_order;       /* Chebyshev points per box edge of the FMM: 4 or 6 (default 6) */
+  int fmm_order;       /* Chebyshev points per box edge of the FMM: 4, 5 or 6 (default 6) */
   int fmm_leaf;        /* mean points per FMM leaf box: the leaf level is the first with at most this (default 256) */
   double gmres_tol;    /* relative residual target of GMRES (FP64 path) */
   int gmres_restart;   /* Krylov space size before restart */
@@ -85,6 +85,9 @@ typedef struct pmx_options {
   double inner_tol;    /* mixed path: relative residual of each inner GMRES */
   int max_ir;          /* mixed path: outer refinement step limit */
   int precision;       /* PMX_PREC_* used by pmx_solve */
+  int overlap;         /* mixed applies: 1 = run the near correction and the P2P sums on a second
+                          stream of the operator, overlapping the FMM's M2L chain (default);
+                          0 = every kernel on the caller's stream */
 } pmx_options;
 
 typedef struct pmx_info {

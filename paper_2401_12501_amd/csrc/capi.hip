@@ -32,7 +32,7 @@ void apply_batch(const std::vector<ApplyJob>& jobs, int precision, int n_rhs, hi
       far_direct64_batch(jobs, n_rhs, st);
       end(t);
       t = begin(PMX_PHASE_NEAR);
-      near_combine_batch(jobs, n_rhs, false, st);
+      near_combine_batch(jobs, n_rhs, st);
       end(t);
       break;
     }
@@ -47,7 +47,7 @@ void apply_batch(const std::vector<ApplyJob>& jobs, int precision, int n_rhs, hi
         far_direct(op, false, n_rhs, st);
         if (pf) pf->end(t, st);
         t = pf ? pf->begin(PMX_PHASE_NEAR, st) : -1;
-        near_combine(op, j.sigma, j.y, n_rhs, far_direct_chunks(op, false), false, false, st);
+        near_combine(op, j.sigma, j.y, n_rhs, far_direct_chunks(op, false), false, st);
         if (pf) pf->end(t, st);
       }
       break;
@@ -55,18 +55,32 @@ void apply_batch(const std::vector<ApplyJob>& jobs, int precision, int n_rhs, hi
     case PMX_PREC_MIXED_FMM: {
       for (const ApplyJob& j : jobs)
         if (!j.op->fmm) fmm_build(j.op, st);
+      pmx_operator* lead = jobs[0].op;
+      if (lead->opts.overlap) side_stream(lead);
+      hipStream_t side = lead->opts.overlap ? lead->side : st;
       int t = begin(PMX_PHASE_PREP);
       source_prep_batch(jobs, n_rhs, true, st);
       end(t);
-      fmm_far_batch(jobs, n_rhs, st);   // records its own phases
-      t = begin(PMX_PHASE_NEAR);
-      near_combine_batch(jobs, n_rhs, true, st);
-      end(t);
+      // the near correction (HBM-bound) writes y on the side stream, followed by the P2P
+      // sums, while the M2L chain (MFMA) runs here; each L2P joins and adds the far field
+      auto near_part = [&](hipStream_t side) {
+        const int tn = prof ? prof->begin(PMX_PHASE_NEAR, side) : -1;
+        near_only_batch(jobs, n_rhs, side);
+        if (prof) prof->end(tn, side);
+      };
+      fmm_far_batch(jobs, n_rhs, st, side, lead->ev_fork, lead->ev_join, near_part);   // records its own phases
       break;
     }
     default:
       throw Error(PMX_ERR_INVALID, "unknown precision mode");
   }
+}
+
+void side_stream(pmx_operator* op) {
+  if (op->side) return;
+  PMX_HIP(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking));
+  PMX_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
+  PMX_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
 }
 
 void apply_device(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, hipStream_t st) {
@@ -88,7 +102,7 @@ void prepare_apply(pmx_operator* op, int precision, int n_rhs, hipStream_t st) {
   if (op->ssum.n < nr) op->ssum.alloc(ctx, nr);
   if (precision == PMX_PREC_MIXED_FMM) {
     if (!op->fmm) fmm_build(op, st);
-    if (op->phi.n < nr * N) op->phi.alloc(ctx, nr * N);
+    if (op->opts.overlap) side_stream(op);
   }
   // FP64 residuals of the refinement (and the FP64 path): chunk partials and packed rows
   const size_t part = (size_t)far_direct_chunks(op, true) * nr * N;
@@ -104,7 +118,7 @@ void represent_device(pmx_operator* op, int n_rhs, const double* sigma, double* 
   const int t = op->prof.begin(PMX_PHASE_LOG, st);
   far_direct_log(op, n_rhs, st);
   op->prof.end(t, st);
-  near_combine(op, sigma, u, n_rhs, far_direct_chunks(op, true), false, true, st);
+  near_combine(op, sigma, u, n_rhs, far_direct_chunks(op, true), true, st);
   weighted_mean_remove(op, u, n_rhs, st);
 }
 
@@ -145,12 +159,13 @@ const double* stage_in(Ctx* ctx, DBuf<double>& buf, const double* p, size_t n, i
 void check_opts(const pmx_options& o) {
   PMX_REQUIRE(o.eta_near > 0.0 && std::isfinite(o.eta_near), PMX_ERR_INVALID, "eta_near must be positive");
   PMX_REQUIRE(o.n_gl >= 2 && o.n_gl <= 16, PMX_ERR_INVALID, "n_gl must be in [2, 16]");
-  PMX_REQUIRE(o.fmm_order == 4 || o.fmm_order == 6, PMX_ERR_INVALID, "fmm_order must be 4 or 6");
+  PMX_REQUIRE(o.fmm_order >= 4 && o.fmm_order <= 6, PMX_ERR_INVALID, "fmm_order must be 4, 5 or 6");
   PMX_REQUIRE(o.fmm_leaf >= 8, PMX_ERR_INVALID, "fmm_leaf must be >= 8");
   PMX_REQUIRE(o.gmres_restart >= 1 && o.gmres_restart <= 500, PMX_ERR_INVALID, "gmres_restart must be in [1, 500]");
   PMX_REQUIRE(o.max_iter >= 1, PMX_ERR_INVALID, "max_iter must be >= 1");
   PMX_REQUIRE(o.gmres_tol > 0 && o.ir_tol > 0 && o.inner_tol > 0, PMX_ERR_INVALID, "tolerances must be positive");
   PMX_REQUIRE(o.precision >= 0 && o.precision <= 2, PMX_ERR_INVALID, "unknown precision mode");
+  PMX_REQUIRE(o.overlap == 0 || o.overlap == 1, PMX_ERR_INVALID, "overlap must be 0 or 1");
 }
 
 }  // namespace
@@ -172,6 +187,7 @@ void pmx_default_options(pmx_options* o) {
   o->inner_tol = 1e-4;
   o->max_ir = 20;
   o->precision = PMX_PREC_FP64_DIRECT;
+  o->overlap = 1;
 }
 
 pmx_status pmx_ctx_create(int device, uint64_t hbm_budget_bytes, pmx_ctx** out) {
@@ -263,6 +279,9 @@ void pmx_operator_destroy(pmx_operator* op) {
   if (op->fmm) fmm_destroy(op->fmm);
   if (op->ev_ready) (void)hipEventDestroy(op->ev_ready);
   if (op->ev_done) (void)hipEventDestroy(op->ev_done);
+  if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
+  if (op->ev_join) (void)hipEventDestroy(op->ev_join);
+  if (op->side) (void)hipStreamDestroy(op->side);
   delete op;
 }
 
@@ -277,7 +296,7 @@ pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* out) {
     uint64_t b = op->co.a.bytes() + op->co.gs.bytes() + op->co.tgt.bytes() + op->co.tg.bytes() + op->co.tf64.bytes() +
                  op->co.tgt32.bytes() + op->co.w_over_a.bytes() + op->nl.ptr.bytes() + op->nl.patch.bytes() +
                  op->nl.target.bytes() + op->nl.C.bytes() + op->nl.D.bytes() + op->part.bytes() +
-                 op->qt64.bytes() + op->qt32.bytes() + op->phi.bytes();
+                 op->qt64.bytes() + op->qt32.bytes();
     if (op->fmm) {
       fmm_stats(op->fmm, out);
       b += fmm_bytes(op->fmm);

@@ -23,6 +23,7 @@
 // scaled by h^-1 (F1) or h^-2 (F2).  Work is grouped by (level, offset) so one
 // generated kernel block serves up to 64 target boxes.
 #include <algorithm>
+#include <functional>
 #include <type_traits>
 #include <cmath>
 #include <unordered_map>
@@ -32,6 +33,12 @@
 namespace pmx {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Floats per box of the local expansions (nine components of p^3 values) and per M2L output
+// slot: padded to a multiple of 4 so the slot sum reads and writes whole float4s.
+constexpr int lstride_of(int p) { return (9 * p * p * p + 3) & ~3; }
+template <int P>
+constexpr int lstride() { return lstride_of(P); }
 
 namespace {
 constexpr int kMaxLevel = 20;
@@ -245,7 +252,7 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
   const int64_t Pb = A.parent[C];
   const int o = A.octant[C];
   for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) sM[e] = A.tab[p + e];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) sA[e] = A.Lc[Pb * n + e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) sA[e] = A.Lc[Pb * lstride<P>() + e];
   __syncthreads();
   const float* Mx = sM + (o & 1) * p * p;          // Mx[a * p + l1] = S1(t_a, child node l1)
   const float* My = sM + ((o >> 1) & 1) * p * p;
@@ -271,7 +278,7 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
     const int l23 = e % (p * p), l1 = (e / (p * p)) % p, cc = e / p3;
     float t = 0.0f;
     for (int aa = 0; aa < p; ++aa) t = fmaf(Mx[aa * p + l1], sA[cc * p3 + aa * p * p + l23], t);
-    A.Lc[C * n + e] += t;
+    A.Lc[C * lstride<P>() + e] += t;
   }
 }
 
@@ -300,7 +307,7 @@ struct M2LArgs {
 };
 
 template <int P>
-constexpr int m2l_waves() { return P == 4 ? 4 : 7; }   // 4 and 14 row tiles
+constexpr int m2l_waves() { return P == 6 ? 7 : 4; }   // 14, 8 and 4 row tiles
 
 template <int P>
 __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
@@ -370,7 +377,7 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
     }
     const int pj = cb * 16 + col;
     if (pj < ncol) {
-      float* out = slots + (int64_t)sP[pj] * 9 * p3;
+      float* out = slots + (int64_t)sP[pj] * lstride<P>();
       const float s1 = sS[0][pj], s2 = sS[1][pj];
       const int l0 = rt * 16 + 4 * kq;
 #pragma unroll
@@ -402,9 +409,7 @@ struct RedArgs {
 
 template <int P>
 __global__ void __launch_bounds__(512) k_m2l_reduce(Group<RedArgs> g) {
-  constexpr int n = 9 * P * P * P;
-  static_assert(n % 4 == 0, "slot size must be a multiple of 4");
-  constexpr int n4 = n / 4;
+  constexpr int n4 = lstride<P>() / 4;   // padding entries are zero in every slot
   int64_t b;
   const RedArgs& A = seg_of(g, blockIdx.x, b);
   const int64_t box0 = A.box0;
@@ -464,7 +469,7 @@ __global__ void __launch_bounds__(64) k_p2p(Group<P2PArgs> g) {
   if (k < d.y) A.part[(int64_t)slot * N + k] = acc;
 }
 
-// L2P + contraction + P2P sum; writes phi (FP64, node order).
+// L2P + contraction + P2P sum, added to y (FP64, node order).
 struct L2PArgs {
   int64_t leaf_off, N;
   float h;
@@ -476,7 +481,7 @@ struct L2PArgs {
   const float* part;
   const int32_t* u_ptr;
   const int32_t* perm;
-  double* phi;
+  double* y;
 };
 
 // The leaf's local expansion is the same for all its targets, so the evaluation
@@ -499,7 +504,7 @@ __global__ void __launch_bounds__(256) k_l2p(Group<L2PArgs> g) {
   const float* __restrict__ pts = A.pts;
   const int leaf = (int)lb;
   const int64_t box = leaf_off + leaf;
-  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) sL[e] = A.Lc[box * 9 * p3 + e];
+  for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) sL[e] = A.Lc[box * lstride<P>() + e];
   __syncthreads();
   const float cx = A.center[3 * box], cy = A.center[3 * box + 1], cz = A.center[3 * box + 2];
   const float ih = 1.0f / A.h;
@@ -554,7 +559,7 @@ __global__ void __launch_bounds__(256) k_l2p(Group<L2PArgs> g) {
       const float nF2n = nx * nx * F[3] + 2.f * nx * ny * F[4] + 2.f * nx * nz * F[5] + ny * ny * F[6] +
                          2.f * ny * nz * F[7] + nz * nz * F[8];
       const float hF1 = hx * F[0] + hy * F[1] + hz * F[2];
-      A.phi[A.perm[k]] = (double)(nF2n + hF1) + (double)near_sum;
+      A.y[A.perm[k]] += (double)(nF2n + hF1) + (double)near_sum;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -613,7 +618,7 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
   try {
     F->p = op->opts.fmm_order;
     F->p3 = F->p * F->p * F->p;
-    PMX_REQUIRE(F->p == 4 || F->p == 6, PMX_ERR_INVALID, "fmm_order must be 4 or 6");
+    PMX_REQUIRE(F->p >= 4 && F->p <= 6, PMX_ERR_INVALID, "fmm_order must be 4, 5 or 6");
     const int p = F->p, p3 = F->p3;
     std::vector<double> X(3 * N);
     PMX_HIP(hipMemcpyAsync(X.data(), op->s->g.x.p, 3 * N * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -842,8 +847,11 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     F->qs.alloc(ctx, 4 * N);
     F->phis.alloc(ctx, 27 * (size_t)N);
     F->W.alloc(ctx, (size_t)F->n_boxes * p3);
-    F->Lc.alloc(ctx, (size_t)F->n_boxes * 9 * p3);
-    F->slots.alloc(ctx, (size_t)std::max<int64_t>(F->m2l_pairs, 1) * 9 * p3);
+    const size_t ls = (size_t)lstride_of(p);
+    F->Lc.alloc(ctx, (size_t)F->n_boxes * ls);
+    F->slots.alloc(ctx, (size_t)std::max<int64_t>(F->m2l_pairs, 1) * ls);
+    if (ls != 9 * (size_t)p3)   // M2L never writes a slot's padding: it stays zero
+      PMX_HIP(hipMemsetAsync(F->slots.p, 0, F->slots.bytes(), st));
     hipLaunchKernelGGL(k_gather_pts, dim3((N + 255) / 256), dim3(256), 0, st, N, F->perm.p, op->co.tgt32.p,
                        F->pts.p);
     PMX_HIP(hipGetLastError());
@@ -860,7 +868,10 @@ void fmm_destroy(FMM* f) { delete f; }
 // One far-field pass for one right-hand side r of several operators: every stage
 // is one launch over all operators (M2M and L2L: one launch per level).
 template <int P>
-static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* prof, hipStream_t st) {
+static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, Profiler* prof, hipStream_t st, hipStream_t side,
+                        hipEvent_t ev_fork, hipEvent_t ev_join, const std::function<void(hipStream_t)>& side_work) {
+  std::vector<pmx_operator*> ops;
+  for (const ApplyJob& j : jobs) ops.push_back(j.op);
   constexpr int p3 = P * P * P;
   (void)p3;
   auto phase = [&](int ph) { return prof ? prof->begin(ph, st) : -1; };
@@ -869,7 +880,7 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
   int maxL = 0;
   for (pmx_operator* op : ops) maxL = std::max(maxL, op->fmm->L);
 
-  int t = phase(PMX_PHASE_FMM_P2M);
+  int t = -1;
   {
     std::vector<PermArgs> pa;
     std::vector<P2MArgs> ma;
@@ -887,6 +898,32 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
       hipLaunchKernelGGL(k_permute, dim3((unsigned)nb), dim3(256), 0, st, g);
       PMX_HIP(hipGetLastError());
     });
+    // fork: the caller's side work (once) and the P2P sums, which need only the permuted
+    // sources, run on the side stream while P2M, M2M, M2L, its slot sum and L2L run here.
+    // Measured on the ellipsoid: starting the side stream here hides more than starting it
+    // with M2L, whose long launch then shares the CUs from its first wave on.
+    if (side != st) {
+      PMX_HIP(hipEventRecord(ev_fork, st));
+      PMX_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+    }
+    if (r == 0 && side_work) side_work(side);
+    {
+      std::vector<P2PArgs> qa;
+      std::vector<int64_t> qb;
+      for (pmx_operator* op : ops) {
+        FMM* F = op->fmm;
+        qa.push_back({op->s->g.N, F->p2p_desc.p, F->p2p_slot.p, F->pts.p, F->qs.p, F->phis.p});
+        qb.push_back(F->n_p2p_waves);
+      }
+      const int tp = prof ? prof->begin(PMX_PHASE_FMM_P2P, side) : -1;
+      launch_grouped(qa, qb, [&](const Group<P2PArgs>& g, int64_t nb) {
+        hipLaunchKernelGGL(k_p2p, dim3((unsigned)nb), dim3(64), 0, side, g);
+        PMX_HIP(hipGetLastError());
+      });
+      if (prof) prof->end(tp, side);
+      if (side != st) PMX_HIP(hipEventRecord(ev_join, side));
+    }
+    t = phase(PMX_PHASE_FMM_P2M);   // P2M alone (the permutation before it is not timed)
     launch_grouped(ma, mb, [&](const Group<P2MArgs>& g, int64_t nb) {
       hipLaunchKernelGGL(k_p2m<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
       PMX_HIP(hipGetLastError());
@@ -950,31 +987,18 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
     });
   }
   done(t);
-  t = phase(PMX_PHASE_FMM_P2P);
-  {
-    std::vector<P2PArgs> pa;
-    std::vector<int64_t> pb;
-    for (pmx_operator* op : ops) {
-      FMM* F = op->fmm;
-      pa.push_back({op->s->g.N, F->p2p_desc.p, F->p2p_slot.p, F->pts.p, F->qs.p, F->phis.p});
-      pb.push_back(F->n_p2p_waves);
-    }
-    launch_grouped(pa, pb, [&](const Group<P2PArgs>& g, int64_t nb) {
-      hipLaunchKernelGGL(k_p2p, dim3((unsigned)nb), dim3(64), 0, st, g);
-      PMX_HIP(hipGetLastError());
-    });
-  }
-  done(t);
+  if (side != st) PMX_HIP(hipStreamWaitEvent(st, ev_join, 0));   // P2P partials and the near part of y are ready
   t = phase(PMX_PHASE_FMM_L2P);
   {
     std::vector<L2PArgs> la;
     std::vector<int64_t> lb;
-    for (pmx_operator* op : ops) {
+    for (const ApplyJob& j : jobs) {
+      pmx_operator* op = j.op;
       FMM* F = op->fmm;
       const int64_t N = op->s->g.N;
       const float hL = (float)(F->h0 / (double)(1 << F->L));
       la.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->Lc.p, F->phis.p,
-                    F->u_ptr.p, F->perm.p, op->phi.p + (int64_t)r * N});
+                    F->u_ptr.p, F->perm.p, j.y + (int64_t)r * N});
       lb.push_back(F->n_leaves);
     }
     launch_grouped(la, lb, [&](const Group<L2PArgs>& g, int64_t nb) {
@@ -986,29 +1010,25 @@ static void fmm_far_rhs(const std::vector<pmx_operator*>& ops, int r, Profiler* 
   (void)n;
 }
 
-void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
-  std::vector<pmx_operator*> ops;
+void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st, hipStream_t side,
+                   hipEvent_t ev_fork, hipEvent_t ev_join, const std::function<void(hipStream_t)>& side_work) {
   int p = 0;
   for (const ApplyJob& j : jobs) {
-    pmx_operator* op = j.op;
-    PMX_REQUIRE(op->fmm != nullptr, PMX_ERR_INVALID, "FMM tree not built");
-    const int64_t N = op->s->g.N;
-    if (op->phi.n < (size_t)n_rhs * N) op->phi.alloc(&op->s->ctx->c, (size_t)n_rhs * N);
-    PMX_REQUIRE(p == 0 || op->fmm->p == p, PMX_ERR_INVALID, "operators of one batch need the same FMM order");
-    p = op->fmm->p;
-    ops.push_back(op);
+    PMX_REQUIRE(j.op->fmm != nullptr, PMX_ERR_INVALID, "FMM tree not built");
+    PMX_REQUIRE(j.y != nullptr, PMX_ERR_INVALID, "FMM far field needs the output array");
+    PMX_REQUIRE(p == 0 || j.op->fmm->p == p, PMX_ERR_INVALID, "operators of one batch need the same FMM order");
+    p = j.op->fmm->p;
   }
   Profiler* prof = jobs.size() == 1 ? &jobs[0].op->prof : nullptr;
   for (int r = 0; r < n_rhs; ++r) {
     switch (p) {
-      case 4: fmm_far_rhs<4>(ops, r, prof, st); break;
-      case 6: fmm_far_rhs<6>(ops, r, prof, st); break;
-      default: throw Error(PMX_ERR_INVALID, "fmm_order must be 4 or 6");
+      case 4: fmm_far_rhs<4>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
+      case 5: fmm_far_rhs<5>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
+      case 6: fmm_far_rhs<6>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
+      default: throw Error(PMX_ERR_INVALID, "fmm_order must be 4, 5 or 6");
     }
   }
 }
-
-void fmm_far(pmx_operator* op, int n_rhs, hipStream_t st) { fmm_far_batch({ApplyJob{op, nullptr, nullptr}}, n_rhs, st); }
 
 void fmm_stats(const FMM* f, pmx_operator_stats* s) {
   s->fmm_levels = f->L;

@@ -288,8 +288,8 @@ CombineArgs combine_args(pmx_operator* op, const double* sigma, double* y, int n
 }
 
 // Near correction and combination for several operators; n_far[k] partial far fields each.
-void combine_all(const std::vector<ApplyJob>& jobs, const std::vector<int>& n_far, bool use_phi, bool parametrix,
-                 int n_rhs, hipStream_t st) {
+void combine_all(const std::vector<ApplyJob>& jobs, const std::vector<int>& n_far, bool parametrix, int n_rhs,
+                 hipStream_t st) {
   int r0 = 0;
   while (r0 < n_rhs) {
     const int left = n_rhs - r0;
@@ -297,7 +297,7 @@ void combine_all(const std::vector<ApplyJob>& jobs, const std::vector<int>& n_fa
     std::vector<CombineArgs> recs;
     for (size_t k = 0; k < jobs.size(); ++k) {
       pmx_operator* op = jobs[k].op;
-      recs.push_back(combine_args(op, jobs[k].sigma, jobs[k].y, n_rhs, r0, n_far[k], use_phi ? op->phi.p : op->part.p,
+      recs.push_back(combine_args(op, jobs[k].sigma, jobs[k].y, n_rhs, r0, n_far[k], n_far[k] > 0 ? op->part.p : nullptr,
                                   parametrix));
     }
     if (nr == 8) combine_launch<8>(recs, st);
@@ -309,15 +309,19 @@ void combine_all(const std::vector<ApplyJob>& jobs, const std::vector<int>& n_fa
 }
 }  // namespace
 
-void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, int n_part, bool use_phi,
-                  bool parametrix, hipStream_t st) {
-  combine_all({ApplyJob{op, sigma, y}}, {use_phi ? 1 : n_part}, use_phi, parametrix, n_rhs, st);
+void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, int n_part, bool parametrix,
+                  hipStream_t st) {
+  combine_all({ApplyJob{op, sigma, y}}, {n_part}, parametrix, n_rhs, st);
 }
 
-void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool use_phi, hipStream_t st) {
+void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
   std::vector<int> nf;
-  for (const ApplyJob& j : jobs) nf.push_back(use_phi ? 1 : far_direct_chunks(j.op, true));
-  combine_all(jobs, nf, use_phi, false, n_rhs, st);
+  for (const ApplyJob& j : jobs) nf.push_back(far_direct_chunks(j.op, true));
+  combine_all(jobs, nf, false, n_rhs, st);
+}
+
+void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
+  combine_all(jobs, std::vector<int>(jobs.size(), 0), false, n_rhs, st);
 }
 
 void weighted_mean_remove(pmx_operator* op, double* u, int n_rhs, hipStream_t st) {

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/pmx.h"
@@ -258,12 +259,16 @@ struct pmx_operator {
   pmx::DBuf<float> rows32;
   pmx::DBuf<double> ssum_part; // partial sums of w sigma
   pmx::DBuf<double> ssum;      // s_r = sum_j w_j sigma_rj
-  pmx::DBuf<double> phi;       // far field result (FP64 accumulate of FMM output)
   pmx::DBuf<double> io_a, io_b;  // staging for host arrays
   pmx::Profiler prof;
   const std::atomic<int>* cancel = nullptr;   // set by the server: abandon the solve when nonzero
   struct pmx_batcher* batcher = nullptr;      // set by the server: applies join shared launches
   hipEvent_t ev_ready = nullptr, ev_done = nullptr;   // hand-over events of batched applies
+  // second stream of the mixed apply: the near correction and the P2P sums run on it while
+  // the FMM's M2L chain runs on the caller's stream (fork after the source preparation,
+  // join before L2P); default priority, created on first use
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace pmx {
@@ -289,10 +294,14 @@ int far_direct_chunks(const pmx_operator* op, bool fp64);
 void far_direct_log(pmx_operator* op, int n_rhs, hipStream_t st);          // representation far field (FP64)
 // nearapply.hip
 void source_prep(pmx_operator* op, const double* sigma, int n_rhs, bool need32, hipStream_t st);
-void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, int n_part, bool use_phi,
-                  bool parametrix, hipStream_t st);
+// y = sigma + C sigma + (sum_j w_j sigma_j) + the n_part far-field partials in op->part
+// (parametrix: y = D sigma + partials)
+void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, int n_part, bool parametrix,
+                  hipStream_t st);
 void source_prep_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool need32, hipStream_t st);
-void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool use_phi, hipStream_t st);
+void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);   // FP64 direct partials
+// y = sigma + C sigma + (sum_j w_j sigma_j): everything but the far field, which the FMM adds later.
+void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);
 void far_direct64_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);
 void weighted_mean_remove(pmx_operator* op, double* u, int n_rhs, hipStream_t st);
 // capi.hip
@@ -319,8 +328,14 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
 // fmm.hip
 void fmm_build(pmx_operator* op, hipStream_t st);
 void fmm_destroy(FMM* f);
-void fmm_far(pmx_operator* op, int n_rhs, hipStream_t st);   // writes op->phi (FP64, n_rhs * N)
-void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);
+// y_r += far field of sigma_r for every job.  After the source permutation of each rhs,
+// the P2P sums run on `side` while P2M, M2M, M2L, its slot sum and L2L run on st;
+// side_work(side) is called once, before the first P2P launch, and st waits for side
+// before each L2P launch (which adds into y), so side_work may write y.  side == st runs
+// everything on one stream in the same order (events unused).
+void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st, hipStream_t side,
+                   hipEvent_t ev_fork, hipEvent_t ev_join, const std::function<void(hipStream_t)>& side_work);
+void side_stream(pmx_operator* op);   // creates op->side, op->ev_fork, op->ev_join once
 void fmm_stats(const FMM* f, pmx_operator_stats* s);
 uint64_t fmm_bytes(const FMM* f);
 

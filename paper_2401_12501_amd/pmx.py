@@ -35,7 +35,8 @@ class PmxError(RuntimeError):
 class pmx_options(C.Structure):
     _fields_ = [("eta_near", C.c_double), ("n_gl", C.c_int), ("fmm_order", C.c_int), ("fmm_leaf", C.c_int),
                 ("gmres_tol", C.c_double), ("gmres_restart", C.c_int), ("max_iter", C.c_int),
-                ("ir_tol", C.c_double), ("inner_tol", C.c_double), ("max_ir", C.c_int), ("precision", C.c_int)]
+                ("ir_tol", C.c_double), ("inner_tol", C.c_double), ("max_ir", C.c_int), ("precision", C.c_int),
+                ("overlap", C.c_int)]
 
 
 class pmx_info(C.Structure):

@@ -3,6 +3,8 @@ include/pmx.h declares, and reports errors as status codes (no GPU needed)."""
 import ctypes
 import os
 import re
+import subprocess
+from pathlib import Path
 
 import pytest
 
@@ -33,16 +35,33 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_options():
     o = pmx.pmx_default_options()
-    assert o.eta_near == 1.5 and o.n_gl == 16 and o.fmm_order == 6
+    assert o.eta_near == 1.5 and o.n_gl == 16 and o.fmm_order == 6 and o.overlap == 1
     assert o.gmres_tol == 1e-10 and o.ir_tol == 1e-8 and o.inner_tol == 1e-4
     assert o.precision == pmx.PMX_PREC_FP64_DIRECT
 
 
-def test_struct_layouts_match_header():
-    # sizes of the ABI structs as laid out by the C compiler on x86-64
-    assert ctypes.sizeof(pmx.pmx_options) == 64
-    assert ctypes.sizeof(pmx.pmx_info) == 48
-    assert ctypes.sizeof(pmx.pmx_operator_stats) == 64
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the binding equals what the C compiler lays out
+    from include/pmx.h (a small program built with gcc prints them)."""
+    structs = {"pmx_options": pmx.pmx_options, "pmx_info": pmx.pmx_info,
+               "pmx_operator_stats": pmx.pmx_operator_stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "pmx.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = Path(__file__).resolve().parents[1] / "include"
+    subprocess.run(["gcc", "-std=c11", f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "sizeof")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
 
 
 def test_null_arguments_are_errors():

@@ -51,12 +51,13 @@ def make(ctx, prob, order=6, leaf=128):
 @pytest.mark.parametrize("k", [4, 8])
 def test_fmm_vs_direct_and_order(ctx, k):
     """Ellipsoid with 96 (k=4, 9,600 nodes) or 384 (k=8, 38,400 nodes) patches:
-    FMM far field vs the FP64 direct far field, p = 4 and p = 6."""
+    FMM far field vs the FP64 direct far field, p = 4, 5 and 6 (p = 5 pads each box's nine
+    local expansions, 1,125 floats, to a multiple of four)."""
     from paper_2401_12501_amd import pmx
     p = ellipsoid_problem(k=k, q=10)
     sig = random_density(p.n, 2, seed=21).T.copy()        # (2, N)
     errs = {}
-    for order in (4, 6):
+    for order in (4, 5, 6):
         surf, op = make(ctx, p, order=order, leaf=64)
         y64 = op.apply(sig, pmx.PMX_PREC_FP64_DIRECT)
         yf = op.apply(sig, pmx.PMX_PREC_MIXED_FMM)
@@ -70,7 +71,28 @@ def test_fmm_vs_direct_and_order(ctx, k):
         y1 = op.apply(sig[1].copy(), pmx.PMX_PREC_MIXED_FMM)
         assert rel(y1[0], yf[1]) < 1e-6
     assert errs[6] < 1e-3          # p = 6 interpolation error; the mixed solve refines with FP64 residuals
+    assert errs[6] < errs[5] < errs[4]
     assert errs[6] < errs[4] / 3
+
+
+@pytest.mark.parametrize("n_rhs", [1, 3])
+def test_overlap_streams_bitwise(ctx, n_rhs):
+    """Mixed applies with the near correction and P2P sums on the operator's second stream
+    (overlap = 1) equal the one-stream order (overlap = 0) bit for bit: the same kernels run
+    with the same per-target summation order, and the far field is added only after the join."""
+    from paper_2401_12501_amd import pmx
+    p = ellipsoid_problem(k=8, q=10)
+    sig = random_density(p.n, n_rhs, seed=23).T.copy()
+    ys = {}
+    for ov in (1, 0):
+        o = pmx.pmx_default_options()
+        o.overlap = ov
+        surf = pmx.Surface.from_inputs(ctx, p.surface)
+        op = pmx.Operator(surf, p.a, p.grad_a, o)
+        ys[ov] = [op.apply(sig, pmx.PMX_PREC_MIXED_FMM) for _ in range(3)]
+    for y in ys[1] + ys[0][1:]:
+        assert np.array_equal(y, ys[0][0])
+    say(f"[overlap] N={p.n} rhs={n_rhs}: two-stream and one-stream applies identical (3 repeats each)")
 
 
 def test_fmm_vs_oracle_sphere(ctx):
