@@ -42,14 +42,14 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0
 # traffic is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "8e6d2530166d5c05",
-                "kib": [("k_m2l", 13656.8, 407773.8)]},
-    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "8e6d2530166d5c05",
-                    "kib": [("k_m2l_reduce", 166875.0, 7383.7)]},
-    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "8e6d2530166d5c05",
-                "kib": [("k_p2p", 46473.4, 9603.8)]},
-    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "c400b74ed34f547b",
-             "kib": [("k_near_combine", 281457.1, 1313.1)]},
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "b89da243b2afd3fc",
+                "kib": [("k_m2l", 13668.5, 407479.9)]},
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "b89da243b2afd3fc",
+                    "kib": [("k_m2l_reduce", 166751.1, 7382.2)]},
+    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "b89da243b2afd3fc",
+                "kib": [("k_p2p", 46498.9, 9602.6)]},
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "663f62da92df6e88",
+             "kib": [("k_near_combine", 280267.2, 1315.4)]},
 }
 
 
@@ -69,14 +69,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_work(phase: str, st, N: int, q: int, n_rhs: int, fmm_order: int):
+def algorithmic_work(phase: str, st, N: int, q: int, n_rhs: int, fmm_order: int, path: str = "mixed"):
     """(amount per launch, unit, bound, peak) of a phase's kernel(s)."""
     p3 = fmm_order ** 3
     if phase in ("direct64", "direct32"):
         flops = float(N) * N * (24 + 2 * n_rhs)          # per ordered pair: 24 + 2 per rhs
         return flops / 1e12, "TFLOP/s", "alu", PEAK["fp64_valu" if phase == "direct64" else "fp32_valu"]
     if phase == "near":
-        byts = 8.0 * st.near_pairs * q * q + 8.0 * N * n_rhs * 3 + 8.0 * (N + 1) + 4.0 * st.near_pairs
+        # blocks C, sigma read and y written per rhs, near lists; the FP64 path also reads its far-field
+        # partials (counted as one array), the mixed path's far field is added later by L2P
+        vecs = 3 if path == "fp64" else 2
+        byts = 8.0 * st.near_pairs * q * q + 8.0 * N * n_rhs * vecs + 8.0 * (N + 1) + 4.0 * st.near_pairs
         return byts / 1e9, "GB/s", "hbm", PEAK["hbm"]
     if phase == "fmm_m2l":
         return 2.0 * 9 * p3 * p3 * st.fmm_m2l_pairs * n_rhs / 1e12, "TFLOP/s", "mfma", PEAK["fp32_mfma"]
@@ -286,7 +289,7 @@ def main():
     st = op.stats()
     # dominant kernel of the timed path
     dom = max(((k, v) for k, v in phases.items() if v[1] and k != "prep"), key=lambda kv: kv[1][0])
-    work = algorithmic_work(dom[0], st, N, prob.surface.q, n_rhs, op.opts.fmm_order)
+    work = algorithmic_work(dom[0], st, N, prob.surface.q, n_rhs, op.opts.fmm_order, args.path)
     roof = None
     if work:
         amount, unit, bound, peak = work
@@ -303,13 +306,50 @@ def main():
     kernels = []
     for path, ph, steps in ((args.path, phases, args.steps), (other, other_phases, max(3, args.steps // 4))):
         for name, (ms, cnt) in ph.items():
-            w = algorithmic_work(name, st, N, prob.surface.q, n_rhs, op.opts.fmm_order) if cnt else None
+            w = algorithmic_work(name, st, N, prob.surface.q, n_rhs, op.opts.fmm_order, path) if cnt else None
             if w:
                 amount, unit, bound, peak = w
                 t = ms / 1e3 / steps
                 kernels.append({"path": path, "kernel": name, "bound": bound, "ms": round(t * 1e3, 4),
                                 "achieved": round(amount / t, 3), "peak": peak, "unit": unit,
                                 "frac": round(amount / t / peak, 4)})
+
+    # the same mixed apply with every kernel on one stream (operator option overlap = 0): the
+    # kernels' own durations without the second stream sharing the CUs, and the overlap's gain
+    one_stream = None
+    if args.path == "mixed" and not args.no_overlap:
+        opts1 = pmx.pmx_default_options()
+        for fld in ("fmm_order", "fmm_leaf"):
+            setattr(opts1, fld, getattr(opts, fld))
+        opts1.overlap = 0
+        op1 = pmx.Operator(surf, prob.a, prob.grad_a, opts1)
+        y1 = torch.empty_like(sig)
+        for _ in range(args.warmup + 1):
+            op1.apply(sig, prec["mixed"], out=y1)
+        torch.cuda.synchronize()
+        op1.profile_read()
+        op1.profile(True)
+        ts1 = time.perf_counter()
+        for _ in range(args.steps):
+            op1.apply(sig, prec["mixed"], out=y1)
+        torch.cuda.synchronize()
+        one_s = (time.perf_counter() - ts1) / args.steps
+        op1.profile(False)
+        ph1 = op1.profile_read()
+        same = bool(np.array_equal(y1.cpu().numpy().T, y_main))
+        one_stream = {"ms_per_apply": round(one_s * 1e3, 4), "overlap_speedup": round(one_s / step_s, 3),
+                      "bitwise_equal": same, "kernels": []}
+        for name, (ms, cnt) in ph1.items():
+            w = algorithmic_work(name, st, N, prob.surface.q, n_rhs, op.opts.fmm_order, "mixed") if cnt else None
+            if w:
+                amount, unit, bound, peak = w
+                t = ms / 1e3 / args.steps
+                one_stream["kernels"].append({"kernel": name, "ms": round(t * 1e3, 4), "achieved": round(amount / t, 3),
+                                              "unit": unit, "frac": round(amount / t / peak, 4)})
+        log(f"[bench] mixed on one stream: {one_s * 1e3:.3f} ms/apply (two streams {step_s * 1e3:.3f}), "
+            f"identical output {same}; " + ", ".join(f"{k['kernel']} {k['ms']:.3f} ms ({k['frac']:.3f})"
+                                                    for k in one_stream["kernels"]))
+        del op1
 
     # PCIe-inclusive rate: the same apply with host arrays (staged through device buffers)
     sig_host = np.ascontiguousarray(sig_h.T)
@@ -376,6 +416,7 @@ def main():
         "roofline": roof,
         "other_path": ({"path": other, "gpts_per_s": round(N * n_rhs / other_s / 1e9, 4),
                         "ms_per_apply": round(other_s * 1e3, 4)} if other_s else None),
+        "one_stream": one_stream,
         "apply_rel_err_vs_oracle": err,
         "solve_to_1e-8": solve,
         "setup_s": round(t_setup, 3),
