@@ -102,6 +102,7 @@ void prepare_apply(pmx_operator* op, int precision, int n_rhs, hipStream_t st) {
   if (op->ssum.n < nr) op->ssum.alloc(ctx, nr);
   if (precision == PMX_PREC_MIXED_FMM) {
     if (!op->fmm) fmm_build(op, st);
+    fmm_reserve(op, n_rhs);
     if (op->opts.overlap) side_stream(op);
   }
   // FP64 residuals of the refinement (and the FP64 path): chunk partials and packed rows

@@ -41,6 +41,7 @@ template <int P>
 constexpr int lstride() { return lstride_of(P); }
 
 namespace {
+constexpr int kRBlock = 16;     // right-hand sides per multi-charge P2P launch
 constexpr int kMaxLevel = 20;
 constexpr int kItemCols = 16;   // target boxes per M2L work item (one MFMA column block)
 }  // namespace
@@ -65,6 +66,12 @@ struct FMM {
   DBuf<int4> p2p_desc;       // P2P waves: first and end target, first and end source (sorted positions)
   DBuf<int32_t> p2p_slot;    // U-list slot of each P2P wave
   int64_t n_p2p_waves = 0;
+  DBuf<int32_t> p2p_cptr;    // waves of each (leaf, 64-target chunk): [cptr[c], cptr[c + 1])
+  int64_t n_p2p_chunks = 0;
+  // several right-hand sides: source rows (x, y, z, qt_0 .. qt_{R-1}, zero padding) of stride
+  // rstride floats, and the P2P sums per (rhs, sorted target)
+  DBuf<float> qsR, partR;
+  int rstride = 0, r_cap = 0;
   DBuf<int32_t> m2l_t, m2l_s;        // global box indices of the pairs, sorted by (offset, level)
   DBuf<int32_t> m2l_lv;              // level of each pair
   DBuf<int4> items;                  // (first pair, count, -, offset code)
@@ -469,6 +476,81 @@ __global__ void __launch_bounds__(64) k_p2p(Group<P2PArgs> g) {
   if (k < d.y) A.part[(int64_t)slot * N + k] = acc;
 }
 
+// Several right-hand sides: one source row per sorted point, (x, y, z, qt_0 .. qt_{R-1}) and
+// zeros up to the row stride.
+struct PermMArgs {
+  int64_t N;
+  int R, stride;
+  const int32_t* perm;
+  const float* pts;
+  const float* q;     // R x N (node order)
+  float* qsR;
+};
+
+__global__ void __launch_bounds__(256) k_permute_multi(Group<PermMArgs> g) {
+  int64_t lb;
+  const PermMArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t k = lb * 256 + threadIdx.x;
+  if (k >= A.N) return;
+  float* row = A.qsR + k * A.stride;
+  const int32_t i = A.perm[k];
+  row[0] = A.pts[k];
+  row[1] = A.pts[A.N + k];
+  row[2] = A.pts[2 * A.N + k];
+  for (int r = 0; r < A.stride - 3; ++r) row[3 + r] = r < A.R ? A.q[(int64_t)r * A.N + i] : 0.0f;
+}
+
+// P2P for several right-hand sides: one wave per (leaf, 64-target chunk) takes every U-list
+// slot of the chunk in order.  The pair kernel ((n'.r)^2 / r^2 + h.r) / r^2 does not depend
+// on the density, so it is evaluated once per pair and applied to all R charges of the source
+// row (wave-uniform, through the scalar cache); the sums stay in registers across the slots.
+struct P2PMArgs {
+  int64_t N;
+  int R, stride;
+  const int32_t* cptr;
+  const int4* desc;
+  const float* pts;
+  const float* qsR;
+  float* partR;       // R x N (sorted order)
+};
+
+template <int RMAX>
+__global__ void __launch_bounds__(64) k_p2p_multi(Group<P2PMArgs> g) {
+  int64_t lb;
+  const P2PMArgs& A = seg_of(g, blockIdx.x, lb);
+  const int64_t N = A.N;
+  const float* __restrict__ pts = A.pts;
+  const int w0 = A.cptr[lb], w1 = A.cptr[lb + 1];
+  const int4 d0 = A.desc[w0];
+  const int k = d0.x + threadIdx.x;
+  const int kk = k < d0.y ? k : d0.y - 1;
+  const float xi = pts[kk], yi = pts[N + kk], zi = pts[2 * N + kk];
+  const float px = pts[3 * N + kk], py = pts[4 * N + kk], pz = pts[5 * N + kk];
+  const float hx = pts[6 * N + kk], hy = pts[7 * N + kk], hz = pts[8 * N + kk];
+  const sfp src = (sfp)A.qsR;
+  const int stride = A.stride;
+  float acc[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) acc[r] = 0.0f;
+  for (int w = w0; w < w1; ++w) {
+    const int4 d = A.desc[w];
+#pragma unroll 2
+    for (int j = d.z; j < d.w; ++j) {
+      const sfp sj = src + (int64_t)stride * j;
+      const float dx = xi - sj[0], dy = yi - sj[1], dz = zi - sj[2];
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-30f)));
+      const float inv = __builtin_amdgcn_rcpf(r2);
+      const float pr = fmaf(px, dx, fmaf(py, dy, pz * dz));
+      const float hr = fmaf(hx, dx, fmaf(hy, dy, hz * dz));
+      const float kv = fmaf(pr * inv, pr, hr) * inv;
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) acc[r] = fmaf(sj[3 + r], kv, acc[r]);
+    }
+  }
+  if (k < d0.y)
+    for (int r = 0; r < A.R; ++r) A.partR[(int64_t)r * N + k] = acc[r];
+}
+
 // L2P + contraction + P2P sum, added to y (FP64, node order).
 struct L2PArgs {
   int64_t leaf_off, N;
@@ -479,7 +561,7 @@ struct L2PArgs {
   const float* pts;
   const float* Lc;
   const float* part;
-  const int32_t* u_ptr;
+  const int32_t* u_ptr;   // null: part holds one sum per target (several right-hand sides)
   const int32_t* perm;
   double* y;
 };
@@ -509,7 +591,7 @@ __global__ void __launch_bounds__(256) k_l2p(Group<L2PArgs> g) {
   const float cx = A.center[3 * box], cy = A.center[3 * box + 1], cz = A.center[3 * box + 2];
   const float ih = 1.0f / A.h;
   const int s0 = A.leaf_start[leaf], s1 = A.leaf_start[leaf + 1];
-  const int n_slot = A.u_ptr[leaf + 1] - A.u_ptr[leaf];
+  const int n_slot = A.u_ptr ? A.u_ptr[leaf + 1] - A.u_ptr[leaf] : 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 15, kq = lane >> 4;
   const int c = row;                                   // B column (component) of this lane
@@ -805,6 +887,13 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
           ws.push_back(sl);
         }
     F->n_p2p_waves = (int64_t)wd.size();
+    std::vector<int32_t> cptr(1, 0);   // waves are ordered by (leaf, chunk, slot)
+    for (int64_t b = 0; b < F->n_leaves; ++b)
+      for (int32_t f = lstart[b]; f < lstart[b + 1]; f += 64)
+        cptr.push_back(cptr.back() + (uptr[b + 1] - uptr[b]));
+    for (int64_t b = 0; b < F->n_leaves; ++b)   // a leaf's U-list holds the leaf itself
+      PMX_REQUIRE(uptr[b + 1] > uptr[b], PMX_ERR_DEVICE, "FMM leaf with an empty U-list");
+    F->n_p2p_chunks = (int64_t)cptr.size() - 1;
     // tables: t_k, M1[2][p][p] (M1[b][k][k'] = S1(t_k, +-0.5 + t_k'/2)), node coordinates
     std::vector<float> tab(p + 2 * p * p + 3 * p3);
     std::vector<double> t(p);
@@ -842,6 +931,7 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     up(F->items, items);
     up(F->p2p_desc, wd);
     up(F->p2p_slot, ws);
+    up(F->p2p_cptr, cptr);
     up(F->tab, tab);
     F->pts.alloc(ctx, 9 * (size_t)N);
     F->qs.alloc(ctx, 4 * N);
@@ -868,8 +958,14 @@ void fmm_destroy(FMM* f) { delete f; }
 // One far-field pass for one right-hand side r of several operators: every stage
 // is one launch over all operators (M2M and L2L: one launch per level).
 template <int P>
-static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, Profiler* prof, hipStream_t st, hipStream_t side,
-                        hipEvent_t ev_fork, hipEvent_t ev_join, const std::function<void(hipStream_t)>& side_work) {
+static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, int n_rhs, Profiler* prof, hipStream_t st,
+                        hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join,
+                        const std::function<void(hipStream_t)>& side_work) {
+  // several right-hand sides: the P2P sums of a block of up to kRBlock of them (this rhs's
+  // block starts at rb) come from one multi-charge launch at the block's first rhs
+  const bool multi = n_rhs > 1;
+  const int rb = (r / kRBlock) * kRBlock, nb_r = std::min(kRBlock, n_rhs - rb);
+  const bool fork = !multi || r == rb;
   std::vector<pmx_operator*> ops;
   for (const ApplyJob& j : jobs) ops.push_back(j.op);
   constexpr int p3 = P * P * P;
@@ -902,24 +998,55 @@ static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, Profiler* prof
     // sources, run on the side stream while P2M, M2M, M2L, its slot sum and L2L run here.
     // Measured on the ellipsoid: starting the side stream here hides more than starting it
     // with M2L, whose long launch then shares the CUs from its first wave on.
-    if (side != st) {
-      PMX_HIP(hipEventRecord(ev_fork, st));
-      PMX_HIP(hipStreamWaitEvent(side, ev_fork, 0));
-    }
-    if (r == 0 && side_work) side_work(side);
-    {
-      std::vector<P2PArgs> qa;
-      std::vector<int64_t> qb;
+    if (multi && fork) {   // source rows with the block's charges, for the multi-charge P2P
+      std::vector<PermMArgs> qm;
+      std::vector<int64_t> qmb;
       for (pmx_operator* op : ops) {
         FMM* F = op->fmm;
-        qa.push_back({op->s->g.N, F->p2p_desc.p, F->p2p_slot.p, F->pts.p, F->qs.p, F->phis.p});
-        qb.push_back(F->n_p2p_waves);
+        const int64_t N = op->s->g.N;
+        qm.push_back({N, nb_r, F->rstride, F->perm.p, F->pts.p, op->qt32.p + (int64_t)rb * N, F->qsR.p});
+        qmb.push_back((N + 255) / 256);
       }
-      const int tp = prof ? prof->begin(PMX_PHASE_FMM_P2P, side) : -1;
-      launch_grouped(qa, qb, [&](const Group<P2PArgs>& g, int64_t nb) {
-        hipLaunchKernelGGL(k_p2p, dim3((unsigned)nb), dim3(64), 0, side, g);
+      launch_grouped(qm, qmb, [&](const Group<PermMArgs>& g, int64_t nb) {
+        hipLaunchKernelGGL(k_permute_multi, dim3((unsigned)nb), dim3(256), 0, st, g);
         PMX_HIP(hipGetLastError());
       });
+    }
+    if (fork) {
+      if (side != st) {
+        PMX_HIP(hipEventRecord(ev_fork, st));
+        PMX_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+      }
+      if (r == 0 && side_work) side_work(side);
+      const int tp = prof ? prof->begin(PMX_PHASE_FMM_P2P, side) : -1;
+      if (!multi) {
+        std::vector<P2PArgs> qa;
+        std::vector<int64_t> qb;
+        for (pmx_operator* op : ops) {
+          FMM* F = op->fmm;
+          qa.push_back({op->s->g.N, F->p2p_desc.p, F->p2p_slot.p, F->pts.p, F->qs.p, F->phis.p});
+          qb.push_back(F->n_p2p_waves);
+        }
+        launch_grouped(qa, qb, [&](const Group<P2PArgs>& g, int64_t nb) {
+          hipLaunchKernelGGL(k_p2p, dim3((unsigned)nb), dim3(64), 0, side, g);
+          PMX_HIP(hipGetLastError());
+        });
+      } else {
+        std::vector<P2PMArgs> qa;
+        std::vector<int64_t> qb;
+        for (pmx_operator* op : ops) {
+          FMM* F = op->fmm;
+          qa.push_back({op->s->g.N, nb_r, F->rstride, F->p2p_cptr.p, F->p2p_desc.p, F->pts.p, F->qsR.p, F->partR.p});
+          qb.push_back(F->n_p2p_chunks);
+        }
+        launch_grouped(qa, qb, [&](const Group<P2PMArgs>& g, int64_t nb) {
+          if (nb_r <= 2) hipLaunchKernelGGL(k_p2p_multi<2>, dim3((unsigned)nb), dim3(64), 0, side, g);
+          else if (nb_r <= 4) hipLaunchKernelGGL(k_p2p_multi<4>, dim3((unsigned)nb), dim3(64), 0, side, g);
+          else if (nb_r <= 8) hipLaunchKernelGGL(k_p2p_multi<8>, dim3((unsigned)nb), dim3(64), 0, side, g);
+          else hipLaunchKernelGGL(k_p2p_multi<16>, dim3((unsigned)nb), dim3(64), 0, side, g);
+          PMX_HIP(hipGetLastError());
+        });
+      }
       if (prof) prof->end(tp, side);
       if (side != st) PMX_HIP(hipEventRecord(ev_join, side));
     }
@@ -997,8 +1124,9 @@ static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, Profiler* prof
       FMM* F = op->fmm;
       const int64_t N = op->s->g.N;
       const float hL = (float)(F->h0 / (double)(1 << F->L));
-      la.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->Lc.p, F->phis.p,
-                    F->u_ptr.p, F->perm.p, j.y + (int64_t)r * N});
+      la.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->Lc.p,
+                    multi ? F->partR.p + (int64_t)(r - rb) * N : F->phis.p, multi ? nullptr : F->u_ptr.p, F->perm.p,
+                    j.y + (int64_t)r * N});
       lb.push_back(F->n_leaves);
     }
     launch_grouped(la, lb, [&](const Group<L2PArgs>& g, int64_t nb) {
@@ -1010,9 +1138,22 @@ static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, Profiler* prof
   (void)n;
 }
 
+void fmm_reserve(pmx_operator* op, int n_rhs) {
+  FMM* F = op->fmm;
+  if (!F || n_rhs <= 1 || F->r_cap >= std::min(n_rhs, kRBlock)) return;
+  const int R = std::min(n_rhs, kRBlock);
+  const int64_t N = op->s->g.N;
+  Ctx* ctx = &op->s->ctx->c;
+  F->rstride = (3 + kRBlock + 3) & ~3;   // rows hold the widest block's charges (k_p2p_multi<16> reads 16)
+  if (F->qsR.n == 0) F->qsR.alloc(ctx, (size_t)N * F->rstride);
+  F->partR.alloc(ctx, (size_t)R * N);
+  F->r_cap = R;
+}
+
 void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st, hipStream_t side,
                    hipEvent_t ev_fork, hipEvent_t ev_join, const std::function<void(hipStream_t)>& side_work) {
   int p = 0;
+  for (const ApplyJob& j : jobs) fmm_reserve(j.op, n_rhs);
   for (const ApplyJob& j : jobs) {
     PMX_REQUIRE(j.op->fmm != nullptr, PMX_ERR_INVALID, "FMM tree not built");
     PMX_REQUIRE(j.y != nullptr, PMX_ERR_INVALID, "FMM far field needs the output array");
@@ -1022,9 +1163,9 @@ void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st,
   Profiler* prof = jobs.size() == 1 ? &jobs[0].op->prof : nullptr;
   for (int r = 0; r < n_rhs; ++r) {
     switch (p) {
-      case 4: fmm_far_rhs<4>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
-      case 5: fmm_far_rhs<5>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
-      case 6: fmm_far_rhs<6>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
+      case 4: fmm_far_rhs<4>(jobs, r, n_rhs, prof, st, side, ev_fork, ev_join, side_work); break;
+      case 5: fmm_far_rhs<5>(jobs, r, n_rhs, prof, st, side, ev_fork, ev_join, side_work); break;
+      case 6: fmm_far_rhs<6>(jobs, r, n_rhs, prof, st, side, ev_fork, ev_join, side_work); break;
       default: throw Error(PMX_ERR_INVALID, "fmm_order must be 4, 5 or 6");
     }
   }
@@ -1042,7 +1183,8 @@ uint64_t fmm_bytes(const FMM* f) {
          f->octant.bytes() + f->leaf_start.bytes() + f->perm.bytes() + f->pts.bytes() + f->qs.bytes() +
          f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_desc.bytes() + f->p2p_slot.bytes() + f->m2l_t.bytes() +
          f->m2l_s.bytes() + f->m2l_lv.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
-         f->slots.bytes() + f->r_ptr.bytes() + f->m2l_slot.bytes();
+         f->slots.bytes() + f->r_ptr.bytes() + f->m2l_slot.bytes() + f->p2p_cptr.bytes() + f->qsR.bytes() +
+         f->partR.bytes();
 }
 
 }  // namespace pmx

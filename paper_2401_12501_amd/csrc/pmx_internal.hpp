@@ -336,6 +336,7 @@ void fmm_destroy(FMM* f);
 void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st, hipStream_t side,
                    hipEvent_t ev_fork, hipEvent_t ev_join, const std::function<void(hipStream_t)>& side_work);
 void side_stream(pmx_operator* op);   // creates op->side, op->ev_fork, op->ev_join once
+void fmm_reserve(pmx_operator* op, int n_rhs);   // multi-rhs P2P buffers (no-op for one rhs)
 void fmm_stats(const FMM* f, pmx_operator_stats* s);
 uint64_t fmm_bytes(const FMM* f);
 

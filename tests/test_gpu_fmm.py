@@ -95,6 +95,27 @@ def test_overlap_streams_bitwise(ctx, n_rhs):
     say(f"[overlap] N={p.n} rhs={n_rhs}: two-stream and one-stream applies identical (3 repeats each)")
 
 
+@pytest.mark.parametrize("n_rhs", [3, 16, 20])
+def test_multi_rhs_p2p_matches_single(ctx, n_rhs):
+    """Several right-hand sides share each P2P pair evaluation (blocks of up to 16 charges per
+    source row; 20 = a block of 16 and one of 4).  Every column equals the single-rhs apply up to
+    the FP32 summation order of the P2P sums (all U-list slots in one register vs per-slot partials)."""
+    from paper_2401_12501_amd import pmx
+    p = ellipsoid_problem(k=8, q=10)
+    sig = random_density(p.n, n_rhs, seed=31).T.copy()
+    surf, op = make(ctx, p, leaf=64)
+    ym = op.apply(sig, pmx.PMX_PREC_MIXED_FMM)
+    worst = 0.0
+    for r in (0, n_rhs // 2, n_rhs - 1):
+        y1 = op.apply(sig[r].copy(), pmx.PMX_PREC_MIXED_FMM)[0]
+        far1 = far_part(op, y1[None], sig[r][None])[0]
+        worst = max(worst, float(np.abs(ym[r] - y1).max() / np.abs(far1).max()))
+    say(f"[multi-rhs] N={p.n} rhs={n_rhs}: max |y_multi - y_single| / max|far| = {worst:.2e}")
+    # FP32 sums over the ~3,000 U-list sources of a target in two orders differ by about
+    # sqrt(3000) * 6e-8 = 3e-6 of the sum; the FMM's own error here is 5e-4
+    assert worst < 1e-5
+
+
 def test_fmm_vs_oracle_sphere(ctx):
     """Unit-sphere workload (1,536 nodes): mixed apply against the oracle's dense operator."""
     from paper_2401_12501_amd import pmx
