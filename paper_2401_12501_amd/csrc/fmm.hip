@@ -356,47 +356,62 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
   const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
               oz = 2.0f * (float)(code % 7 - 3);
   const int kq = lane >> 4, col = lane & 15;
-  for (int rt = wave; rt < n_rt; rt += n_waves) {
-    constexpr int cb = 0;
-    const int row = rt * 16 + col;
-    const bool row_ok = row < p3;
-    const float4 tl = sN[row_ok ? row : 0];
-    const float tlx = tl.x + ox, tly = tl.y + oy, tlz = tl.z + oz;
-    floatx4 acc[9];
+  // each wave takes NT row tiles at once: the source node and B operand of a k-step are
+  // loaded once for all of them, and 9 NT accumulator chains keep the MFMA pipe busy.
+  // Rows past p^3 (last tile) use node 0: with the offset at least two box widths away the
+  // kernel stays finite there, and those rows are never stored.
+  constexpr int NT = n_rt / n_waves;
+  static_assert(NT * n_waves == n_rt, "row tiles must divide evenly over the waves");
+  float tlx[NT], tly[NT], tlz[NT];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float* sBc = sB + (cb * 16 + col) * kM2LStride;
+  for (int t = 0; t < NT; ++t) {
+    const int row = (wave + t * n_waves) * 16 + col;
+    const float4 tl = sN[row < p3 ? row : 0];
+    tlx[t] = tl.x + ox;
+    tly[t] = tl.y + oy;
+    tlz[t] = tl.z + oz;
+  }
+  floatx4 acc[NT][9];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const float* sBc = sB + col * kM2LStride;
 #pragma unroll 2
-    for (int k0 = 0; k0 < p3; k0 += 4) {
-      const int m = k0 + kq;
-      const bool ok = row_ok && m < p3;
-      const float4 tm = sN[m < p3 ? m : 0];
-      const float rx = tlx - tm.x, ry = tly - tm.y, rz = tlz - tm.z;
-      const float inv = ok ? __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz))) : 0.0f;
+  for (int k0 = 0; k0 < p3; k0 += 4) {
+    const int m = k0 + kq;
+    const float4 tm = sN[m < p3 ? m : 0];
+    // k past p^3 (p^3 not a multiple of 4): a zero B row removes the term
+    const float b0 = (p3 % 4 == 0 || m < p3) ? sBc[m < p3 ? m : 0] : 0.0f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const float rx = tlx[t] - tm.x, ry = tly[t] - tm.y, rz = tlz[t] - tm.z;
+      const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
       // r / r^2 and (r r^T) / r^4 = (r / r^2)(r / r^2)^T
       float a[9];
       a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
       a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
       a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
-      const float b0 = sBc[m < p3 ? m : 0];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[c], 0, 0, 0);
+      for (int c = 0; c < 9; ++c) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[t][c], 0, 0, 0);
     }
-    const int pj = cb * 16 + col;
-    if (pj < ncol) {
-      float* out = slots + (int64_t)sP[pj] * lstride<P>();
-      const float s1 = sS[0][pj], s2 = sS[1][pj];
-      const int l0 = rt * 16 + 4 * kq;
+  }
+  if (col < ncol) {
+    float* out = slots + (int64_t)sP[col] * lstride<P>();
+    const float s1 = sS[0][col], s2 = sS[1][col];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int l0 = (wave + t * n_waves) * 16 + 4 * kq;
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         const float sc = c < 3 ? s1 : s2;
         if (l0 + 3 < p3 && (p3 % 4) == 0) {   // four consecutive rows: one 16-byte store
           *reinterpret_cast<float4*>(out + c * p3 + l0) =
-              make_float4(sc * acc[c][0], sc * acc[c][1], sc * acc[c][2], sc * acc[c][3]);
+              make_float4(sc * acc[t][c][0], sc * acc[t][c][1], sc * acc[t][c][2], sc * acc[t][c][3]);
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            if (l0 + r < p3) out[c * p3 + l0 + r] = sc * acc[c][r];
+            if (l0 + r < p3) out[c * p3 + l0 + r] = sc * acc[t][c][r];
         }
       }
     }
