@@ -72,6 +72,11 @@ struct FMM {
   // rstride floats, and the P2P sums per (rhs, sorted target)
   DBuf<float> qsR, partR;
   int rstride = 0, r_cap = 0;
+  // sixteen right-hand sides at once: the M2L sources of each box of levels >= 2 in slot order
+  // (source box, offset code), and multipoles / locals with one slice per right-hand side
+  DBuf<int2> tsrc;
+  DBuf<int64_t> lev_off_d;   // device copy of lev_off
+  DBuf<float> W16, L16;
   DBuf<int32_t> m2l_t, m2l_s;        // global box indices of the pairs, sorted by (offset, level)
   DBuf<int32_t> m2l_lv;              // level of each pair
   DBuf<int4> items;                  // (first pair, count, -, offset code)
@@ -413,6 +418,151 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
           for (int r = 0; r < 4; ++r)
             if (l0 + r < p3) out[c * p3 + l0 + r] = sc * acc[t][c][r];
         }
+      }
+    }
+  }
+}
+
+// M2L for a block of 16 right-hand sides: one workgroup per box of levels >= 2 walks the
+// box's M2L sources in slot order; the 16 right-hand sides are the MFMA's 16 columns, so each
+// generated kernel block serves all of them and the locals stay in registers across the
+// sources (no per-pair output slots and no slot sum).  The next source's multipoles are loaded
+// into registers while the current one is computed, then stored to the other LDS buffer.
+struct M2L16Args {
+  const float* tab;
+  const int32_t* rptr;    // box b's sources are [rptr[b - box2], rptr[b - box2 + 1])
+  const int2* tsrc;       // (source box, offset code)
+  int64_t box2, n_boxes;
+  int L;                  // leaf level: boxes of level l are [lev_off[l], lev_off[l + 1])
+  const int64_t* lev_first;   // device copy of lev_off (L + 2 entries)
+  const float* W16;       // 16 slices of n_boxes * p^3
+  float* L16;             // 16 slices of n_boxes * lstride
+  double h0;
+};
+
+template <int P>
+constexpr int m2l16_waves() { return (P * P * P + 31) / 32; }   // half the row tiles, one per wave
+
+template <int P>
+__global__ void __launch_bounds__(64 * m2l16_waves<P>()) __attribute__((amdgpu_waves_per_eu(4)))
+k_m2l16(Group<M2L16Args> g) {
+  constexpr int p3 = P * P * P;
+  constexpr int n_rt = (p3 + 15) / 16;
+  constexpr int n_waves = m2l16_waves<P>();
+  static_assert(2 * n_waves == n_rt, "two workgroups per box, one row tile per wave");
+  constexpr int NT = 1;
+  constexpr int kThr = 64 * n_waves;
+  constexpr int kPer = (16 * p3 + kThr - 1) / kThr;   // staged multipole values per thread
+  int64_t lb;
+  const M2L16Args& A = seg_of(g, blockIdx.x, lb);
+  const int half = (int)(lb & 1);          // which half of the box's row tiles
+  lb >>= 1;
+  const int64_t box = A.box2 + lb;
+  const int s0 = A.rptr[lb], s1 = A.rptr[lb + 1];
+  const int64_t slice = A.n_boxes * (int64_t)p3;
+  __shared__ float sB[2][16 * kM2LStride];
+  __shared__ float4 sN[p3];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int m = threadIdx.x; m < p3; m += blockDim.x) {
+    const float* nd = A.tab + P + 2 * P * P + 3 * m;
+    sN[m] = make_float4(nd[0], nd[1], nd[2], 0.0f);
+  }
+  float stage[kPer];
+  auto load = [&](int si) {
+    const int64_t sb = A.tsrc[si].x;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + q * kThr;
+      const int j = e / p3, m = e - j * p3;
+      stage[q] = e < 16 * p3 ? A.W16[j * slice + sb * p3 + m] : 0.0f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + q * kThr;
+      const int j = e / p3, m = e - j * p3;
+      if (e < 16 * p3) sB[buf][j * kM2LStride + m] = stage[q];
+    }
+  };
+  if (s0 < s1) {
+    load(s0);
+    store(0);
+  }
+  __syncthreads();
+  const int kq = lane >> 4, col = lane & 15;
+  // one accumulator per source (its p^3-term sums), added to the running total afterwards:
+  // the same two-level summation as per-pair slots, so rounding does not grow with the
+  // number of sources
+  floatx4 tot[NT][9];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) tot[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int si = s0; si < s1; ++si) {
+    floatx4 acc[NT][9];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int buf = (si - s0) & 1;
+    if (si + 1 < s1) load(si + 1);
+    const int code = A.tsrc[si].y;
+    const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
+                oz = 2.0f * (float)(code % 7 - 3);
+    float tlx[NT], tly[NT], tlz[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int row = (wave + half * n_waves) * 16 + col;
+      const float4 tl = sN[row < p3 ? row : 0];
+      tlx[t] = tl.x + ox;
+      tly[t] = tl.y + oy;
+      tlz[t] = tl.z + oz;
+    }
+    const float* sBc = sB[buf] + col * kM2LStride;
+#pragma unroll 2
+    for (int k0 = 0; k0 < p3; k0 += 4) {
+      const int m = k0 + kq;
+      const float4 tm = sN[m < p3 ? m : 0];
+      const float b0 = (p3 % 4 == 0 || m < p3) ? sBc[m < p3 ? m : 0] : 0.0f;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const float rx = tlx[t] - tm.x, ry = tly[t] - tm.y, rz = tlz[t] - tm.z;
+        const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+        float a[9];
+        a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
+        a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
+        a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[t][c], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) tot[t][c] += acc[t][c];
+    if (si + 1 < s1) store(buf ^ 1);
+    __syncthreads();
+  }
+  // every source of the box sits at the box's level: one scale per component group
+  int lev = 2;
+  while (lev < A.L && box >= A.lev_first[lev + 1]) ++lev;
+  const double h = A.h0 / (double)(1 << lev);
+  const float s1f = (float)(1.0 / h), s2f = (float)(1.0 / (h * h));
+  float* out = A.L16 + (int64_t)col * A.n_boxes * lstride<P>() + box * lstride<P>();
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int l0 = (wave + half * n_waves) * 16 + 4 * kq;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const float sc = c < 3 ? s1f : s2f;
+      if (l0 + 3 < p3 && (p3 % 4) == 0) {
+        *reinterpret_cast<float4*>(out + c * p3 + l0) =
+            make_float4(sc * tot[t][c][0], sc * tot[t][c][1], sc * tot[t][c][2], sc * tot[t][c][3]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (l0 + r < p3) out[c * p3 + l0 + r] = sc * tot[t][c][r];
       }
     }
   }
@@ -891,6 +1041,8 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
       for (size_t k = 0; k < pairs.size(); ++k) spos[k] = fill[pairs[k].t - box2]++;
     }
     F->n_items = (int64_t)items.size();
+    std::vector<int2> tsrc(pairs.size());   // a box's sources in its slot order
+    for (size_t k = 0; k < pairs.size(); ++k) tsrc[spos[k]] = make_int2(pairs[k].s, pairs[k].code);
     // P2P waves: (leaf, 64-target chunk, U-list slot) -> target and source ranges
     std::vector<int4> wd;
     std::vector<int32_t> ws;
@@ -947,6 +1099,8 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     up(F->p2p_desc, wd);
     up(F->p2p_slot, ws);
     up(F->p2p_cptr, cptr);
+    up(F->tsrc, tsrc);
+    up(F->lev_off_d, F->lev_off);
     up(F->tab, tab);
     F->pts.alloc(ctx, 9 * (size_t)N);
     F->qs.alloc(ctx, 4 * N);
@@ -1153,6 +1307,157 @@ static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, int n_rhs, Pro
   (void)n;
 }
 
+// A block of 16 right-hand sides [rb, rb + 16): upward passes per right-hand side into the
+// multipole slices, one M2L launch for all 16 (k_m2l16), then the downward passes per
+// right-hand side.  The multi-charge P2P of the block runs on the side stream as in the
+// per-rhs path, joined before the first L2P.
+template <int P>
+static void fmm_far_block16(const std::vector<ApplyJob>& jobs, int rb, Profiler* prof, hipStream_t st,
+                            hipStream_t side, hipEvent_t ev_fork, hipEvent_t ev_join,
+                            const std::function<void(hipStream_t)>& side_work) {
+  constexpr int p3 = P * P * P;
+  std::vector<pmx_operator*> ops;
+  for (const ApplyJob& j : jobs) ops.push_back(j.op);
+  auto phase = [&](int ph) { return prof ? prof->begin(ph, st) : -1; };
+  auto done = [&](int t) { if (prof) prof->end(t, st); };
+  int maxL = 0;
+  for (pmx_operator* op : ops) maxL = std::max(maxL, op->fmm->L);
+  // source rows with the block's charges, fork, near part (first block), multi-charge P2P
+  {
+    std::vector<PermMArgs> qm;
+    std::vector<int64_t> qmb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      const int64_t N = op->s->g.N;
+      qm.push_back({N, kRBlock, F->rstride, F->perm.p, F->pts.p, op->qt32.p + (int64_t)rb * N, F->qsR.p});
+      qmb.push_back((N + 255) / 256);
+    }
+    launch_grouped(qm, qmb, [&](const Group<PermMArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_permute_multi, dim3((unsigned)nb), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+    if (side != st) {
+      PMX_HIP(hipEventRecord(ev_fork, st));
+      PMX_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+    }
+    if (rb == 0 && side_work) side_work(side);
+    std::vector<P2PMArgs> qa;
+    std::vector<int64_t> qb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      qa.push_back({op->s->g.N, kRBlock, F->rstride, F->p2p_cptr.p, F->p2p_desc.p, F->pts.p, F->qsR.p, F->partR.p});
+      qb.push_back(F->n_p2p_chunks);
+    }
+    const int tp = prof ? prof->begin(PMX_PHASE_FMM_P2P, side) : -1;
+    launch_grouped(qa, qb, [&](const Group<P2PMArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_p2p_multi<16>, dim3((unsigned)nb), dim3(64), 0, side, g);
+      PMX_HIP(hipGetLastError());
+    });
+    if (prof) prof->end(tp, side);
+    if (side != st) PMX_HIP(hipEventRecord(ev_join, side));
+  }
+  // upward passes, one right-hand side at a time, into the multipole slices
+  int t = phase(PMX_PHASE_FMM_P2M);
+  for (int j = 0; j < kRBlock; ++j) {
+    std::vector<PermArgs> pa;
+    std::vector<P2MArgs> ma;
+    std::vector<int64_t> pb, mb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      const int64_t N = op->s->g.N;
+      float* Wj = F->W16.p + (int64_t)j * F->n_boxes * p3;
+      pa.push_back({N, F->perm.p, F->pts.p, op->qt32.p + (int64_t)(rb + j) * N, F->qs.p});
+      pb.push_back((N + 255) / 256);
+      const float hL = (float)(F->h0 / (double)(1 << F->L));
+      ma.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->qs.p, Wj});
+      mb.push_back(F->n_leaves);
+    }
+    launch_grouped(pa, pb, [&](const Group<PermArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_permute, dim3((unsigned)nb), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+    launch_grouped(ma, mb, [&](const Group<P2MArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_p2m<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+  t = phase(PMX_PHASE_FMM_M2M);
+  for (int j = 0; j < kRBlock; ++j)
+    for (int l = maxL - 1; l >= 2; --l) {
+      std::vector<M2MArgs> ma;
+      std::vector<int64_t> mb;
+      for (pmx_operator* op : ops) {
+        FMM* F = op->fmm;
+        if (l >= F->L) continue;
+        ma.push_back({F->lev_off[l], F->tab.p, F->child_begin.p, F->child_end.p, F->octant.p,
+                      F->W16.p + (int64_t)j * F->n_boxes * p3});
+        mb.push_back(F->lev_off[l + 1] - F->lev_off[l]);
+      }
+      launch_grouped(ma, mb, [&](const Group<M2MArgs>& g, int64_t nb) {
+        hipLaunchKernelGGL(k_m2m<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+        PMX_HIP(hipGetLastError());
+      });
+    }
+  done(t);
+  t = phase(PMX_PHASE_FMM_M2L);
+  {
+    std::vector<M2L16Args> la;
+    std::vector<int64_t> lb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      const int64_t box2 = F->lev_off[2];
+      la.push_back({F->tab.p, F->r_ptr.p, F->tsrc.p, box2, F->n_boxes, F->L, F->lev_off_d.p, F->W16.p, F->L16.p,
+                    F->h0});
+      lb.push_back(2 * (F->n_boxes - box2));   // two workgroups per box
+    }
+    launch_grouped(la, lb, [&](const Group<M2L16Args>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_m2l16<P>, dim3((unsigned)nb), dim3(64 * m2l16_waves<P>()), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+  t = phase(PMX_PHASE_FMM_L2L);
+  for (int j = 0; j < kRBlock; ++j)
+    for (int l = 3; l <= maxL; ++l) {
+      std::vector<L2LArgs> la;
+      std::vector<int64_t> lb;
+      for (pmx_operator* op : ops) {
+        FMM* F = op->fmm;
+        if (l > F->L) continue;
+        la.push_back({F->lev_off[l], F->tab.p, F->parent.p, F->octant.p,
+                      F->L16.p + (int64_t)j * F->n_boxes * lstride<P>()});
+        lb.push_back(F->lev_off[l + 1] - F->lev_off[l]);
+      }
+      launch_grouped(la, lb, [&](const Group<L2LArgs>& g, int64_t nb) {
+        hipLaunchKernelGGL(k_l2l<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+        PMX_HIP(hipGetLastError());
+      });
+    }
+  done(t);
+  if (side != st) PMX_HIP(hipStreamWaitEvent(st, ev_join, 0));   // P2P sums and the near part of y
+  t = phase(PMX_PHASE_FMM_L2P);
+  for (int j = 0; j < kRBlock; ++j) {
+    std::vector<L2PArgs> la;
+    std::vector<int64_t> lb;
+    for (const ApplyJob& jb : jobs) {
+      pmx_operator* op = jb.op;
+      FMM* F = op->fmm;
+      const int64_t N = op->s->g.N;
+      const float hL = (float)(F->h0 / (double)(1 << F->L));
+      la.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p,
+                    F->L16.p + (int64_t)j * F->n_boxes * lstride<P>(), F->partR.p + (int64_t)j * N, nullptr,
+                    F->perm.p, jb.y + (int64_t)(rb + j) * N});
+      lb.push_back(F->n_leaves);
+    }
+    launch_grouped(la, lb, [&](const Group<L2PArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_l2p<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
+  done(t);
+}
+
 void fmm_reserve(pmx_operator* op, int n_rhs) {
   FMM* F = op->fmm;
   if (!F || n_rhs <= 1 || F->r_cap >= std::min(n_rhs, kRBlock)) return;
@@ -1162,6 +1467,10 @@ void fmm_reserve(pmx_operator* op, int n_rhs) {
   F->rstride = (3 + kRBlock + 3) & ~3;   // rows hold the widest block's charges (k_p2p_multi<16> reads 16)
   if (F->qsR.n == 0) F->qsR.alloc(ctx, (size_t)N * F->rstride);
   F->partR.alloc(ctx, (size_t)R * N);
+  if (R == kRBlock) {
+    F->W16.alloc(ctx, (size_t)kRBlock * F->n_boxes * F->p3);
+    F->L16.alloc(ctx, (size_t)kRBlock * F->n_boxes * lstride_of(F->p));
+  }
   F->r_cap = R;
 }
 
@@ -1176,13 +1485,24 @@ void fmm_far_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st,
     p = j.op->fmm->p;
   }
   Profiler* prof = jobs.size() == 1 ? &jobs[0].op->prof : nullptr;
-  for (int r = 0; r < n_rhs; ++r) {
+  for (int r = 0; r < n_rhs;) {
+    if (n_rhs - r >= kRBlock) {   // whole blocks of 16: M2L with the right-hand sides as columns
+      switch (p) {
+        case 4: fmm_far_block16<4>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
+        case 5: fmm_far_block16<5>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
+        case 6: fmm_far_block16<6>(jobs, r, prof, st, side, ev_fork, ev_join, side_work); break;
+        default: throw Error(PMX_ERR_INVALID, "fmm_order must be 4, 5 or 6");
+      }
+      r += kRBlock;
+      continue;
+    }
     switch (p) {
       case 4: fmm_far_rhs<4>(jobs, r, n_rhs, prof, st, side, ev_fork, ev_join, side_work); break;
       case 5: fmm_far_rhs<5>(jobs, r, n_rhs, prof, st, side, ev_fork, ev_join, side_work); break;
       case 6: fmm_far_rhs<6>(jobs, r, n_rhs, prof, st, side, ev_fork, ev_join, side_work); break;
       default: throw Error(PMX_ERR_INVALID, "fmm_order must be 4, 5 or 6");
     }
+    ++r;
   }
 }
 
@@ -1199,7 +1519,7 @@ uint64_t fmm_bytes(const FMM* f) {
          f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_desc.bytes() + f->p2p_slot.bytes() + f->m2l_t.bytes() +
          f->m2l_s.bytes() + f->m2l_lv.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
          f->slots.bytes() + f->r_ptr.bytes() + f->m2l_slot.bytes() + f->p2p_cptr.bytes() + f->qsR.bytes() +
-         f->partR.bytes();
+         f->partR.bytes() + f->tsrc.bytes() + f->lev_off_d.bytes() + f->W16.bytes() + f->L16.bytes();
 }
 
 }  // namespace pmx
