@@ -21,7 +21,8 @@
 // from the sub-square's corner images), depth <= 20; each leaf carries an
 // n_gl x n_gl tensor Gauss-Legendre rule.
 //
-// Layout: one workgroup per (target, patch) pair, specialised on the patch order q.
+// Layout: one workgroup per (target, patch) pair (one wave for a near pair), specialised
+// on the patch order q.
 // After the cells (self panels or near leaves) are built:
 //  * near leaves: each wave takes whole leaves; a leaf's tensor rule turns the field
 //    interpolation and the block update into chained small products on the FP64
@@ -73,8 +74,12 @@ struct NWArgs {
   int64_t pair0;
 };
 
-template <int Q>
-constexpr int waves_for() { return Q <= 12 ? 4 : 2; }
+// Waves per workgroup.  Self rule: the target's panels are spread over several waves.
+// Near rule: one wave per (target, patch) pair, so the subdivision's barriers and the final
+// sum are those of a single wave, and many pairs are resident per CU to hide each other's
+// latency (the leaves of a pair run one after another on its wave).
+template <int Q, bool SELF>
+constexpr int waves_for() { return SELF ? (Q <= 12 ? 4 : 2) : 1; }
 
 // Lagrange values of the q nodes at s: l_j(s) = cinv_j prod_{k != j} (s - t_k),
 // from prefix and suffix products (no division by s - t_j).
@@ -178,9 +183,9 @@ __device__ inline sdp opaque(sdp p) {
 // near-list pair, the self pairs leaving at once (the two launches get their own
 // register allocation: the self rule is VALU work, the near rule MFMA work).
 template <int KERNEL, int Q, bool SELF>
-__global__ void __launch_bounds__(64 * waves_for<Q>()) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__((64 * waves_for<Q, SELF>())) __attribute__((amdgpu_waves_per_eu(2)))
 k_near_weights(NWArgs A) {
-  constexpr int kW = waves_for<Q>();
+  constexpr int kW = waves_for<Q, SELF>();
   constexpr int kT = 64 * kW;
   constexpr int q2 = Q * Q;
   extern __shared__ double lds[];
@@ -598,22 +603,24 @@ __global__ void k_interleave(int64_t N, const double* __restrict__ x, const doub
 
 namespace {
 
-template <int Q>
+template <int Q, bool SELF>
 size_t lds_bytes() {
-  const size_t stage = (size_t)waves_for<Q>() * 2 * Q * kStage * sizeof(double);
-  const size_t front = 2 * kMaxCells * sizeof(int2) + 64 * waves_for<Q>() * sizeof(int) +
-                       16 * waves_for<Q>() * 12 * sizeof(double);
-  const size_t red = (size_t)waves_for<Q>() * 256 * sizeof(double);
+  constexpr int kW = waves_for<Q, SELF>();
+  // self: the waves' staging rows; near: the patch's node fields and each wave's Lagrange tables
+  const size_t stage = SELF ? (size_t)kW * 2 * Q * kStage * sizeof(double)
+                            : (size_t)(10 * Q * Q + kW * 32 * Q) * sizeof(double);
+  const size_t front = 2 * kMaxCells * sizeof(int2) + 64 * kW * sizeof(int) + 16 * kW * 12 * sizeof(double);
+  const size_t red = (size_t)kW * 256 * sizeof(double);
   size_t m = stage > front ? stage : front;
   return m > red ? m : red;
 }
 
 template <int Q>
 void launch_q(const NWArgs& A, int64_t n, bool parametrix, bool self, hipStream_t st, size_t lds_limit) {
-  const size_t lds = lds_bytes<Q>();
+  const size_t lds = self ? lds_bytes<Q, true>() : lds_bytes<Q, false>();
   PMX_REQUIRE(lds + 12 * 1024 <= lds_limit, PMX_ERR_INVALID,
               "q too large for the local-rule kernel's LDS on this device");
-  const dim3 block(64 * waves_for<Q>());
+  const dim3 block(64 * (self ? waves_for<Q, true>() : waves_for<Q, false>()));
   if (parametrix) {
     if (self) hipLaunchKernelGGL((k_near_weights<1, Q, true>), dim3(n), block, lds, st, A);
     else hipLaunchKernelGGL((k_near_weights<1, Q, false>), dim3(n), block, lds, st, A);
