@@ -42,14 +42,14 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0
 # traffic is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "b89da243b2afd3fc",
-                "kib": [("k_m2l", 13668.5, 407479.9)]},
-    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "b89da243b2afd3fc",
-                    "kib": [("k_m2l_reduce", 166751.1, 7382.2)]},
-    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "b89da243b2afd3fc",
-                "kib": [("k_p2p", 46498.9, 9602.6)]},
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "ad18572cf5e53c64",
+                "kib": [("k_m2l", 12574.0, 414207.2)]},
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "ad18572cf5e53c64",
+                    "kib": [("k_m2l_reduce", 166733.6, 7382.8)]},
+    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "ad18572cf5e53c64",
+                "kib": [("k_p2p", 46528.6, 9598.5)]},
     "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "663f62da92df6e88",
-             "kib": [("k_near_combine", 280267.2, 1315.4)]},
+             "kib": [("k_near_combine", 280270.4, 1317.7)]},
 }
 
 
