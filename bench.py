@@ -39,29 +39,41 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0
 # (ellipsoid, 153,600 nodes, mixed path, 1 RHS), scaled by what the counters read for a plain
 # 256 MiB device copy (FETCH_SIZE 131,088 KiB -> x2.0, WRITE_SIZE 262,144 KiB -> x1.0).  Each
 # record is tied to the kernel's source file; a different file means a changed kernel and the
-# traffic is reported as null.
+# traffic is reported as null (the key hashes the file's code without its comments).
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "ad18572cf5e53c64",
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
                 "kib": [("k_m2l", 12574.0, 414207.2)]},
-    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "ad18572cf5e53c64",
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
                     "kib": [("k_m2l_reduce", 166733.6, 7382.8)]},
-    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "ad18572cf5e53c64",
+    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
                 "kib": [("k_p2p", 46528.6, 9598.5)]},
-    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "663f62da92df6e88",
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "c91ba4b91ef63256",
              "kib": [("k_near_combine", 280270.4, 1317.7)]},
 }
 
 
+def code_hash(path: str) -> str:
+    """Hash of a source file's code: line comments, trailing spaces and blank lines removed, so
+    that editing a comment does not count as changing the kernel."""
+    import hashlib
+    import re
+    lines = []
+    with open(path, encoding="utf-8") as fh:
+        for line in fh:
+            line = re.sub(r"//.*$", "", line.rstrip("\n")).rstrip()
+            if line:
+                lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
 def traffic_bytes(phase: str, n_rhs: int, k: int):
     """Measured HBM bytes per launch of a phase, or None if not measured for this kernel/workload."""
-    import hashlib
     rec = TRAFFIC.get(phase)
     if rec is None or n_rhs != 1 or k != 16:
         return None
-    with open(os.path.join(ROOT, rec["src"]), "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest()[:16] != rec["sha"]:
-            return None
+    if code_hash(os.path.join(ROOT, rec["src"])) != rec["sha"]:
+        return None
     return sum((f * FETCH_SCALE + w * WRITE_SCALE) * 1024.0 for _, f, w in rec["kib"])
 
 

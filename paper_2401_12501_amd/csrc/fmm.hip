@@ -20,8 +20,13 @@
 // M2L uses translation invariance and homogeneity: for boxes of half-width h at
 // offset o (in box widths), x_l - y_m = h (2 o + t_l - t_m), and the kernel of a
 // unit box is generated on the fly in registers as the MFMA A operand, then
-// scaled by h^-1 (F1) or h^-2 (F2).  Work is grouped by (level, offset) so one
-// generated kernel block serves up to 64 target boxes.
+// scaled by h^-1 (F1) or h^-2 (F2).  One right-hand side: pairs are grouped by
+// offset across levels, so one generated kernel block serves the 16 pairs of an
+// MFMA column block, each writing its own output slot (summed per box afterwards).
+// Blocks of 16 right-hand sides: the right-hand sides are the 16 columns and each
+// box walks its own sources.  Several right-hand sides also share the P2P pair
+// evaluations.  The P2P sums (and the caller's near correction) may run on a
+// second stream while P2M, M2M, M2L and L2L run on the caller's stream.
 #include <algorithm>
 #include <functional>
 #include <type_traits>

@@ -81,7 +81,8 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(Group<SumArgs> g) {
 }
 
 // kSub lanes per target (several targets per wavefront).  identity != 0: add sigma_i and s_r (the operator A);
-// identity == 0: representation (near blocks D plus far field only).  The target's
+// identity == 0: representation (near blocks D plus far field only).  The far field comes as
+// n_far partial sums (direct sums) or not at all (n_far = 0: the FMM's L2P adds it later).  The target's
 // near-patch ids sit in lane registers and are fetched by shuffle, so the loads of
 // the streaming loop (C and the gathered sigma) do not wait on index loads.
 // Block index of element e: e / q2 = (e * magic) >> 32, magic = ceil(2^32 / q2)
