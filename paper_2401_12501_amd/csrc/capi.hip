@@ -53,8 +53,10 @@ void apply_batch(const std::vector<ApplyJob>& jobs, int precision, int n_rhs, hi
       break;
     }
     case PMX_PREC_MIXED_FMM: {
-      for (const ApplyJob& j : jobs)
+      for (const ApplyJob& j : jobs) {
         if (!j.op->fmm) fmm_build(j.op, st);
+        if (n_rhs >= 8) build_near_tiles(&j.op->s->ctx->c, j.op->s->g, j.op->nl, st);
+      }
       pmx_operator* lead = jobs[0].op;
       if (lead->opts.overlap) side_stream(lead);
       hipStream_t side = lead->opts.overlap ? lead->side : st;
@@ -103,6 +105,7 @@ void prepare_apply(pmx_operator* op, int precision, int n_rhs, hipStream_t st) {
   if (precision == PMX_PREC_MIXED_FMM) {
     if (!op->fmm) fmm_build(op, st);
     fmm_reserve(op, n_rhs);
+    if (n_rhs >= 8) build_near_tiles(ctx, op->s->g, op->nl, st);
     if (op->opts.overlap) side_stream(op);
   }
   // FP64 residuals of the refinement (and the FP64 path): chunk partials and packed rows

@@ -9,6 +9,8 @@
 // HBM-bound step of the apply); sigma of the near patches is gathered through the
 // caches.  Every reduction runs in a fixed order, so results do not depend on
 // timing.
+#include <algorithm>
+
 #include "pmx_internal.hpp"
 
 namespace pmx {
@@ -216,6 +218,82 @@ __global__ void k_sub_mean(int64_t N, double* __restrict__ u, const double* __re
   if (i < N) u[(int64_t)r * N + i] -= s[r] / area;
 }
 
+// Near correction for a group of RB right-hand sides (8 or 16), one workgroup per target
+// patch T.  The workgroup walks the union of the near patches of T's targets; for each such
+// patch P it stages sigma_P (q^2 x RB) in LDS once, and lane (target t, rhs r) forms
+// C_{t,P} . sigma_P[:, r] with the block row read once per target (the RB lanes of a target
+// read the same address).  Each target sums its patches in union order, so results are
+// deterministic; no cross-lane reduction is needed.
+struct TiledArgs {
+  int64_t N;
+  int q2, r0;
+  const int32_t* tile_ptr;
+  const int32_t* tile_patch;
+  const int32_t* tile_pair;
+  const double* Cb;
+  const double* sigma;
+  const double* ssum;
+  double* y;
+};
+
+template <int RB>
+__global__ void __launch_bounds__(256) k_near_tiled(Group<TiledArgs> g) {
+  constexpr int TPW = 64 / RB;          // targets per wave
+  constexpr int TPP = 4 * TPW;          // targets per pass of the workgroup
+  constexpr int kPass = 256 / TPP;      // passes for q^2 <= 256
+  constexpr int LD = RB + 1;            // LDS row stride (doubles): staging writes spread over banks
+  extern __shared__ double ssig[];      // [q^2][LD]
+  int64_t T;
+  const TiledArgs& A = seg_of(g, blockIdx.x, T);
+  const int64_t N = A.N;
+  const int q2 = A.q2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane % RB, tw = lane / RB;
+  const int npass = (q2 + TPP - 1) / TPP;
+  double acc[kPass];
+#pragma unroll
+  for (int ps = 0; ps < kPass; ++ps) acc[ps] = 0.0;
+  for (int u = A.tile_ptr[T]; u < A.tile_ptr[T + 1]; ++u) {
+    const int64_t P = A.tile_patch[u];
+    __syncthreads();   // the previous patch's densities are no longer read
+    for (int e = threadIdx.x; e < q2 * RB; e += 256) {
+      const int rr = e / q2, j = e - rr * q2;   // consecutive threads read consecutive nodes
+      ssig[j * LD + rr] = A.sigma[(int64_t)(A.r0 + rr) * N + P * q2 + j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ps = 0; ps < kPass; ++ps) {
+      if (ps < npass) {
+        const int t = ps * TPP + wave * TPW + tw;
+        const int pair = t < q2 ? A.tile_pair[(int64_t)u * q2 + t] : -1;
+        if (pair >= 0) {
+          const double* __restrict__ c = A.Cb + (int64_t)pair * q2;
+          // four partial sums (the row in four interleaved strands) keep four FMAs in flight
+          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+          int j = 0;
+          for (; j + 3 < q2; j += 4) {
+            s0 = fma(c[j], ssig[j * LD + r], s0);
+            s1 = fma(c[j + 1], ssig[(j + 1) * LD + r], s1);
+            s2 = fma(c[j + 2], ssig[(j + 2) * LD + r], s2);
+            s3 = fma(c[j + 3], ssig[(j + 3) * LD + r], s3);
+          }
+          for (; j < q2; ++j) s0 = fma(c[j], ssig[j * LD + r], s0);
+          acc[ps] += (s0 + s1) + (s2 + s3);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int ps = 0; ps < kPass; ++ps) {
+    const int t = ps * TPP + wave * TPW + tw;
+    if (ps < npass && t < q2) {
+      const int64_t i = T * q2 + t;
+      const int64_t at = (int64_t)(A.r0 + r) * N + i;
+      A.y[at] = acc[ps] + A.sigma[at] + A.ssum[A.r0 + r];
+    }
+  }
+}
+
 namespace {
 void size_prep_buffers(pmx_operator* op, int n_rhs, bool need32) {
   const int64_t N = op->s->g.N;
@@ -290,8 +368,8 @@ CombineArgs combine_args(pmx_operator* op, const double* sigma, double* y, int n
 
 // Near correction and combination for several operators; n_far[k] partial far fields each.
 void combine_all(const std::vector<ApplyJob>& jobs, const std::vector<int>& n_far, bool parametrix, int n_rhs,
-                 hipStream_t st) {
-  int r0 = 0;
+                 hipStream_t st, int r_begin = 0) {
+  int r0 = r_begin;
   while (r0 < n_rhs) {
     const int left = n_rhs - r0;
     const int nr = left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
@@ -322,7 +400,81 @@ void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_
 }
 
 void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
-  combine_all(jobs, std::vector<int>(jobs.size(), 0), false, n_rhs, st);
+  // whole groups of 16 (then 8) right-hand sides by target patch, the rest per target
+  bool tiles = n_rhs >= 8;
+  for (const ApplyJob& j : jobs) tiles = tiles && j.op->nl.have_tiles;
+  int r0 = 0;
+  while (tiles && n_rhs - r0 >= 8) {
+    const int rb = n_rhs - r0 >= 16 ? 16 : 8;
+    std::vector<TiledArgs> ta;
+    std::vector<int64_t> tb;
+    for (const ApplyJob& j : jobs) {
+      pmx_operator* op = j.op;
+      const int q2 = op->s->g.q * op->s->g.q;
+      ta.push_back({op->s->g.N, q2, r0, op->nl.tile_ptr.p, op->nl.tile_patch.p, op->nl.tile_pair.p, op->nl.C.p,
+                    j.sigma, op->ssum.p, j.y});
+      tb.push_back(op->s->g.M);
+    }
+    const int q2 = jobs[0].op->s->g.q * jobs[0].op->s->g.q;   // grouped operators share one LDS size
+    int q2max = q2;
+    for (const ApplyJob& j : jobs) q2max = std::max(q2max, j.op->s->g.q * j.op->s->g.q);
+    const size_t lds = (size_t)q2max * (rb + 1) * sizeof(double);
+    launch_grouped(ta, tb, [&](const Group<TiledArgs>& g, int64_t nb) {
+      if (rb == 16) hipLaunchKernelGGL(k_near_tiled<16>, dim3((unsigned)nb), dim3(256), lds, st, g);
+      else hipLaunchKernelGGL(k_near_tiled<8>, dim3((unsigned)nb), dim3(256), lds, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+    r0 += rb;
+  }
+  if (r0 == 0) {
+    combine_all(jobs, std::vector<int>(jobs.size(), 0), false, n_rhs, st);
+    return;
+  }
+  if (r0 < n_rhs)   // the remaining right-hand sides, per target
+    combine_all(jobs, std::vector<int>(jobs.size(), 0), false, n_rhs, st, r0);
+}
+
+void build_near_tiles(Ctx* ctx, const Geometry& g, NearLists& nl, hipStream_t st) {
+  if (nl.have_tiles) return;
+  const int64_t N = g.N, M = g.M;
+  const int q2 = g.q * g.q;
+  PMX_REQUIRE(nl.nnz < ((int64_t)1 << 31), PMX_ERR_INVALID, "too many near pairs for the tiled near correction");
+  std::vector<int64_t> ptr(N + 1);
+  std::vector<int32_t> patch(nl.nnz);
+  PMX_HIP(hipMemcpyAsync(ptr.data(), nl.ptr.p, (N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  if (nl.nnz)
+    PMX_HIP(hipMemcpyAsync(patch.data(), nl.patch.p, nl.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  PMX_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> tptr(M + 1, 0), tpatch, tpair, uni;
+  for (int64_t T = 0; T < M; ++T) {
+    uni.clear();
+    for (int t = 0; t < q2; ++t) {
+      const int64_t i = T * q2 + t;
+      for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) uni.push_back(patch[e]);
+    }
+    std::sort(uni.begin(), uni.end());
+    uni.erase(std::unique(uni.begin(), uni.end()), uni.end());
+    const size_t base = tpatch.size();
+    tpatch.insert(tpatch.end(), uni.begin(), uni.end());
+    tpair.resize(tpatch.size() * (size_t)q2, -1);
+    for (int t = 0; t < q2; ++t) {
+      const int64_t i = T * q2 + t;
+      for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+        const size_t u = (size_t)(std::lower_bound(uni.begin(), uni.end(), patch[e]) - uni.begin());
+        tpair[(base + u) * q2 + t] = (int32_t)e;
+      }
+    }
+    tptr[T + 1] = (int32_t)tpatch.size();
+  }
+  auto up = [&](DBuf<int32_t>& buf, const std::vector<int32_t>& v) {
+    buf.alloc(ctx, v.size());
+    if (!v.empty()) PMX_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  };
+  up(nl.tile_ptr, tptr);
+  up(nl.tile_patch, tpatch);
+  up(nl.tile_pair, tpair);
+  PMX_HIP(hipStreamSynchronize(st));   // the host vectors go out of scope
+  nl.have_tiles = true;
 }
 
 void weighted_mean_remove(pmx_operator* op, double* u, int n_rhs, hipStream_t st) {

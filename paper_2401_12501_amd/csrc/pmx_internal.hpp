@@ -146,6 +146,11 @@ struct NearLists {
   DBuf<double> C;           // nnz * q*q (remainder)
   DBuf<double> D;           // nnz * q*q (parametrix), built on demand
   bool have_D = false;
+  // by target patch (for several right-hand sides): the union of the near patches of the
+  // patch's targets, [tile_ptr[T], tile_ptr[T + 1]) into tile_patch, and for union entry u
+  // the pair of each of the patch's targets with that patch, tile_pair[u * q*q + t] (-1: none)
+  DBuf<int32_t> tile_ptr, tile_patch, tile_pair;
+  bool have_tiles = false;
 };
 
 struct FMM;  // fmm.hip
@@ -302,6 +307,8 @@ void source_prep_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool need32
 void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);   // FP64 direct partials
 // y = sigma + C sigma + (sum_j w_j sigma_j): everything but the far field, which the FMM adds later.
 void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);
+// Builds the by-target-patch view of the near lists (host, once per operator).
+void build_near_tiles(Ctx* ctx, const Geometry& g, NearLists& nl, hipStream_t st);
 void far_direct64_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);
 void weighted_mean_remove(pmx_operator* op, double* u, int n_rhs, hipStream_t st);
 // capi.hip
