@@ -75,11 +75,13 @@ def test_fmm_vs_direct_and_order(ctx, k):
     assert errs[6] < errs[4] / 3
 
 
-@pytest.mark.parametrize("n_rhs", [1, 3])
+@pytest.mark.parametrize("n_rhs", [1, 3, 16])
 def test_overlap_streams_bitwise(ctx, n_rhs):
     """Mixed applies with the near correction and P2P sums on the operator's second stream
     (overlap = 1) equal the one-stream order (overlap = 0) bit for bit: the same kernels run
-    with the same per-target summation order, and the far field is added only after the join."""
+    with the same per-target summation order, and the far field is added only after the join.
+    16 right-hand sides take the by-patch near correction, the multi-charge P2P and the
+    16-column M2L."""
     from paper_2401_12501_amd import pmx
     p = ellipsoid_problem(k=8, q=10)
     sig = random_density(p.n, n_rhs, seed=23).T.copy()
