@@ -43,13 +43,13 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
     "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
-                "kib": [("k_m2l", 12574.0, 414207.2)]},
+                "kib": [("k_m2l", 12561.9, 413796.4)]},
     "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
-                    "kib": [("k_m2l_reduce", 166733.6, 7382.8)]},
+                    "kib": [("k_m2l_reduce", 166735.8, 7382.0)]},
     "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
-                "kib": [("k_p2p", 46528.6, 9598.5)]},
-    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "c91ba4b91ef63256",
-             "kib": [("k_near_combine", 280270.4, 1317.7)]},
+                "kib": [("k_p2p", 46465.1, 9604.9)]},
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "080f4f015b50fac5",
+             "kib": [("k_near_combine", 280265.9, 1312.3)]},
 }
 
 
