@@ -72,6 +72,7 @@ struct FMM {
   DBuf<int32_t> p2p_slot;    // U-list slot of each P2P wave
   int64_t n_p2p_waves = 0;
   DBuf<int32_t> p2p_cptr;    // waves of each (leaf, 64-target chunk): [cptr[c], cptr[c + 1])
+  DBuf<int2> chunks;         // (leaf, first target) of each 64-target chunk (L2P blocks)
   int64_t n_p2p_chunks = 0;
   // several right-hand sides: source rows (x, y, z, qt_0 .. qt_{R-1}, zero padding) of stride
   // rstride floats, and the P2P sums per (rhs, sorted target)
@@ -734,6 +735,7 @@ struct L2PArgs {
   const int32_t* u_ptr;   // null: part holds one sum per target (several right-hand sides)
   const int32_t* perm;
   double* y;
+  const int2* chunks;     // (leaf, first target) of each block's 64-target chunk
 };
 
 // The leaf's local expansion is the same for all its targets, so the evaluation
@@ -754,13 +756,16 @@ __global__ void __launch_bounds__(256) k_l2p(Group<L2PArgs> g) {
   const int64_t leaf_off = A.leaf_off, N = A.N;
   const float* __restrict__ tab = A.tab;
   const float* __restrict__ pts = A.pts;
-  const int leaf = (int)lb;
+  const int2 ch = A.chunks[lb];
+  const int leaf = ch.x;
   const int64_t box = leaf_off + leaf;
   for (int e = threadIdx.x; e < 9 * p3; e += blockDim.x) sL[e] = A.Lc[box * lstride<P>() + e];
   __syncthreads();
   const float cx = A.center[3 * box], cy = A.center[3 * box + 1], cz = A.center[3 * box + 2];
   const float ih = 1.0f / A.h;
-  const int s0 = A.leaf_start[leaf], s1 = A.leaf_start[leaf + 1];
+  // one block per 64-target chunk of a leaf (16 targets per wave): many more blocks than
+  // leaves, so the launch fills the chip
+  const int s0 = ch.y, s1 = min(ch.y + 64, A.leaf_start[leaf + 1]);
   const int n_slot = A.u_ptr ? A.u_ptr[leaf + 1] - A.u_ptr[leaf] : 1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = lane & 15, kq = lane >> 4;
@@ -1060,9 +1065,12 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
         }
     F->n_p2p_waves = (int64_t)wd.size();
     std::vector<int32_t> cptr(1, 0);   // waves are ordered by (leaf, chunk, slot)
+    std::vector<int2> chunks;
     for (int64_t b = 0; b < F->n_leaves; ++b)
-      for (int32_t f = lstart[b]; f < lstart[b + 1]; f += 64)
+      for (int32_t f = lstart[b]; f < lstart[b + 1]; f += 64) {
         cptr.push_back(cptr.back() + (uptr[b + 1] - uptr[b]));
+        chunks.push_back(make_int2((int)b, f));
+      }
     for (int64_t b = 0; b < F->n_leaves; ++b)   // a leaf's U-list holds the leaf itself
       PMX_REQUIRE(uptr[b + 1] > uptr[b], PMX_ERR_DEVICE, "FMM leaf with an empty U-list");
     F->n_p2p_chunks = (int64_t)cptr.size() - 1;
@@ -1104,6 +1112,7 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     up(F->p2p_desc, wd);
     up(F->p2p_slot, ws);
     up(F->p2p_cptr, cptr);
+    up(F->chunks, chunks);
     up(F->tsrc, tsrc);
     up(F->lev_off_d, F->lev_off);
     up(F->tab, tab);
@@ -1300,8 +1309,8 @@ static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, int n_rhs, Pro
       const float hL = (float)(F->h0 / (double)(1 << F->L));
       la.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->Lc.p,
                     multi ? F->partR.p + (int64_t)(r - rb) * N : F->phis.p, multi ? nullptr : F->u_ptr.p, F->perm.p,
-                    j.y + (int64_t)r * N});
-      lb.push_back(F->n_leaves);
+                    j.y + (int64_t)r * N, F->chunks.p});
+      lb.push_back(F->n_p2p_chunks);
     }
     launch_grouped(la, lb, [&](const Group<L2PArgs>& g, int64_t nb) {
       hipLaunchKernelGGL(k_l2p<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
@@ -1452,8 +1461,8 @@ static void fmm_far_block16(const std::vector<ApplyJob>& jobs, int rb, Profiler*
       const float hL = (float)(F->h0 / (double)(1 << F->L));
       la.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p,
                     F->L16.p + (int64_t)j * F->n_boxes * lstride<P>(), F->partR.p + (int64_t)j * N, nullptr,
-                    F->perm.p, jb.y + (int64_t)(rb + j) * N});
-      lb.push_back(F->n_leaves);
+                    F->perm.p, jb.y + (int64_t)(rb + j) * N, F->chunks.p});
+      lb.push_back(F->n_p2p_chunks);
     }
     launch_grouped(la, lb, [&](const Group<L2PArgs>& g, int64_t nb) {
       hipLaunchKernelGGL(k_l2p<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
@@ -1523,7 +1532,7 @@ uint64_t fmm_bytes(const FMM* f) {
          f->octant.bytes() + f->leaf_start.bytes() + f->perm.bytes() + f->pts.bytes() + f->qs.bytes() +
          f->u_ptr.bytes() + f->u_idx.bytes() + f->p2p_desc.bytes() + f->p2p_slot.bytes() + f->m2l_t.bytes() +
          f->m2l_s.bytes() + f->m2l_lv.bytes() + f->items.bytes() + f->tab.bytes() + f->W.bytes() + f->Lc.bytes() + f->phis.bytes() +
-         f->slots.bytes() + f->r_ptr.bytes() + f->m2l_slot.bytes() + f->p2p_cptr.bytes() + f->qsR.bytes() +
+         f->slots.bytes() + f->r_ptr.bytes() + f->m2l_slot.bytes() + f->p2p_cptr.bytes() + f->chunks.bytes() + f->qsR.bytes() +
          f->partR.bytes() + f->tsrc.bytes() + f->lev_off_d.bytes() + f->W16.bytes() + f->L16.bytes();
 }
 
