@@ -202,49 +202,55 @@ struct M2MArgs {
 };
 
 // The interpolation operator is a tensor product, so each child's contribution is
-// applied one axis at a time (3 p^4 multiply-adds instead of p^6), through LDS.
+// applied one axis at a time (3 p^4 multiply-adds instead of p^6), through LDS.  All the
+// children go through each axis pass together (threads over child x node), and their
+// contributions are summed in child order at the end.
 template <int P>
 __global__ void __launch_bounds__(256) k_m2m(Group<M2MArgs> g) {
   constexpr int p = P, p3 = P * P * P;
-  __shared__ float sW[p3], sT[p3];
+  __shared__ float sW[8 * p3], sT[8 * p3];
   __shared__ float sM[2 * p * p];
+  __shared__ int sOct[8];
   int64_t lb;
   const M2MArgs& A = seg_of(g, blockIdx.x, lb);
   const int64_t Pb = A.lev_first + lb;
-  const int m = threadIdx.x;
-  for (int e = m; e < 2 * p * p; e += blockDim.x) sM[e] = A.tab[p + e];   // M1[b][k][k']
-  const int i1 = m / (p * p), i2 = (m / p) % p, i3 = m % p;
-  float acc = 0.0f;
-  for (int c = A.child_begin[Pb]; c < A.child_end[Pb]; ++c) {
-    const int o = A.octant[c];
-    const float* Mx = sM + (o & 1) * p * p;
-    const float* My = sM + ((o >> 1) & 1) * p * p;
-    const float* Mz = sM + ((o >> 2) & 1) * p * p;
-    __syncthreads();
-    if (m < p3) sW[m] = A.W[(int64_t)c * p3 + m];
-    __syncthreads();
-    // z: T[a][b][m3] = sum_d Mz[m3][d] W[a][b][d]
-    if (m < p3) {
+  const int c0 = A.child_begin[Pb], nch = A.child_end[Pb] - c0;   // at most 8 children
+  for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) sM[e] = A.tab[p + e];   // M1[b][k][k']
+  if (threadIdx.x < nch) sOct[threadIdx.x] = A.octant[c0 + threadIdx.x];
+  for (int e = threadIdx.x; e < nch * p3; e += blockDim.x) sW[e] = A.W[(int64_t)c0 * p3 + e];
+  __syncthreads();
+  // z: T[c][a][b][m3] = sum_d Mz_c[m3][d] W[c][a][b][d]
+  for (int e = threadIdx.x; e < nch * p3; e += blockDim.x) {
+    const int ch = e / p3, m = e - ch * p3;
+    const int i1 = m / (p * p), i2 = (m / p) % p, i3 = m % p;
+    const float* Mz = sM + ((sOct[ch] >> 2) & 1) * p * p;
+    float t = 0.0f;
+    for (int d = 0; d < p; ++d) t = fmaf(Mz[i3 * p + d], sW[ch * p3 + (i1 * p + i2) * p + d], t);
+    sT[e] = t;
+  }
+  __syncthreads();
+  // y: W'[c][a][m2][m3] = sum_b My_c[m2][b] T[c][a][b][m3]
+  for (int e = threadIdx.x; e < nch * p3; e += blockDim.x) {
+    const int ch = e / p3, m = e - ch * p3;
+    const int i1 = m / (p * p), i2 = (m / p) % p, i3 = m % p;
+    const float* My = sM + ((sOct[ch] >> 1) & 1) * p * p;
+    float t = 0.0f;
+    for (int bb = 0; bb < p; ++bb) t = fmaf(My[i2 * p + bb], sT[ch * p3 + (i1 * p + bb) * p + i3], t);
+    sW[e] = t;
+  }
+  __syncthreads();
+  // x: out[m1][m2][m3] = sum_c sum_a Mx_c[m1][a] W'[c][a][m2][m3], children in order
+  for (int m = threadIdx.x; m < p3; m += blockDim.x) {
+    const int i1 = m / (p * p), i2 = (m / p) % p, i3 = m % p;
+    float acc = 0.0f;
+    for (int ch = 0; ch < nch; ++ch) {
+      const float* Mx = sM + (sOct[ch] & 1) * p * p;
       float t = 0.0f;
-      for (int d = 0; d < p; ++d) t = fmaf(Mz[i3 * p + d], sW[(i1 * p + i2) * p + d], t);
-      sT[m] = t;
-    }
-    __syncthreads();
-    // y: W'[a][m2][m3] = sum_b My[m2][b] T[a][b][m3]
-    if (m < p3) {
-      float t = 0.0f;
-      for (int bb = 0; bb < p; ++bb) t = fmaf(My[i2 * p + bb], sT[(i1 * p + bb) * p + i3], t);
-      sW[m] = t;
-    }
-    __syncthreads();
-    // x: out[m1][m2][m3] = sum_a Mx[m1][a] W'[a][m2][m3]
-    if (m < p3) {
-      float t = 0.0f;
-      for (int aa = 0; aa < p; ++aa) t = fmaf(Mx[i1 * p + aa], sW[(aa * p + i2) * p + i3], t);
+      for (int aa = 0; aa < p; ++aa) t = fmaf(Mx[i1 * p + aa], sW[ch * p3 + (aa * p + i2) * p + i3], t);
       acc += t;
     }
+    A.W[Pb * p3 + m] = acc;
   }
-  if (m < p3) A.W[Pb * p3 + m] = acc;
 }
 
 // L2L: child L += interpolation of the parent's L (one block per child box of one level).
