@@ -48,7 +48,8 @@ constexpr int lstride() { return lstride_of(P); }
 namespace {
 constexpr int kRBlock = 16;     // right-hand sides per multi-charge P2P launch
 constexpr int kMaxLevel = 20;
-constexpr int kItemCols = 16;   // target boxes per M2L work item (one MFMA column block)
+constexpr int kColTiles = 2;    // MFMA column tiles per M2L work item
+constexpr int kItemCols = 16 * kColTiles;   // box pairs per M2L work item
 }  // namespace
 
 struct FMM {
@@ -331,7 +332,7 @@ struct M2LArgs {
 };
 
 template <int P>
-constexpr int m2l_waves() { return P == 6 ? 7 : 4; }   // 14, 8 and 4 row tiles
+constexpr int m2l_waves() { return (P * P * P + 15) / 16; }   // one row tile per wave: 14, 8, 4
 
 template <int P>
 __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
@@ -373,62 +374,57 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
   const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
               oz = 2.0f * (float)(code % 7 - 3);
   const int kq = lane >> 4, col = lane & 15;
-  // each wave takes NT row tiles at once: the source node and B operand of a k-step are
-  // loaded once for all of them, and 9 NT accumulator chains keep the MFMA pipe busy.
+  // each wave takes one row tile; a generated kernel value (A operand) serves the item's
+  // kColTiles column tiles, so the generation's VALU work is spread over 9 kColTiles MFMAs.
   // Rows past p^3 (last tile) use node 0: with the offset at least two box widths away the
   // kernel stays finite there, and those rows are never stored.
-  constexpr int NT = n_rt / n_waves;
-  static_assert(NT * n_waves == n_rt, "row tiles must divide evenly over the waves");
-  float tlx[NT], tly[NT], tlz[NT];
+  static_assert(n_waves == n_rt, "one row tile per wave");
+  const int row = wave * 16 + col;
+  const float4 tl = sN[row < p3 ? row : 0];
+  const float tlx = tl.x + ox, tly = tl.y + oy, tlz = tl.z + oz;
+  floatx4 acc[kColTiles][9];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int row = (wave + t * n_waves) * 16 + col;
-    const float4 tl = sN[row < p3 ? row : 0];
-    tlx[t] = tl.x + ox;
-    tly[t] = tl.y + oy;
-    tlz[t] = tl.z + oz;
-  }
-  floatx4 acc[NT][9];
+  for (int ct = 0; ct < kColTiles; ++ct)
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int c = 0; c < 9; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const float* sBc = sB + col * kM2LStride;
+    for (int c = 0; c < 9; ++c) acc[ct][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
   for (int k0 = 0; k0 < p3; k0 += 4) {
     const int m = k0 + kq;
     const float4 tm = sN[m < p3 ? m : 0];
     // k past p^3 (p^3 not a multiple of 4): a zero B row removes the term
-    const float b0 = (p3 % 4 == 0 || m < p3) ? sBc[m < p3 ? m : 0] : 0.0f;
+    float b0[kColTiles];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const float rx = tlx[t] - tm.x, ry = tly[t] - tm.y, rz = tlz[t] - tm.z;
-      const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
-      // r / r^2 and (r r^T) / r^4 = (r / r^2)(r / r^2)^T
-      float a[9];
-      a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
-      a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
-      a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
+    for (int ct = 0; ct < kColTiles; ++ct)
+      b0[ct] = (p3 % 4 == 0 || m < p3) ? sB[(ct * 16 + col) * kM2LStride + (m < p3 ? m : 0)] : 0.0f;
+    const float rx = tlx - tm.x, ry = tly - tm.y, rz = tlz - tm.z;
+    const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+    // r / r^2 and (r r^T) / r^4 = (r / r^2)(r / r^2)^T
+    float a[9];
+    a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
+    a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
+    a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[t][c], 0, 0, 0);
-    }
+    for (int ct = 0; ct < kColTiles; ++ct)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[ct][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0[ct], acc[ct][c], 0, 0, 0);
   }
-  if (col < ncol) {
-    float* out = slots + (int64_t)sP[col] * lstride<P>();
-    const float s1 = sS[0][col], s2 = sS[1][col];
+  const int l0 = wave * 16 + 4 * kq;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int l0 = (wave + t * n_waves) * 16 + 4 * kq;
+  for (int ct = 0; ct < kColTiles; ++ct) {
+    const int pj = ct * 16 + col;
+    if (pj < ncol) {
+      float* out = slots + (int64_t)sP[pj] * lstride<P>();
+      const float s1 = sS[0][pj], s2 = sS[1][pj];
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         const float sc = c < 3 ? s1 : s2;
         if (l0 + 3 < p3 && (p3 % 4) == 0) {   // four consecutive rows: one 16-byte store
           *reinterpret_cast<float4*>(out + c * p3 + l0) =
-              make_float4(sc * acc[t][c][0], sc * acc[t][c][1], sc * acc[t][c][2], sc * acc[t][c][3]);
+              make_float4(sc * acc[ct][c][0], sc * acc[ct][c][1], sc * acc[ct][c][2], sc * acc[ct][c][3]);
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            if (l0 + r < p3) out[c * p3 + l0 + r] = sc * acc[t][c][r];
+            if (l0 + r < p3) out[c * p3 + l0 + r] = sc * acc[ct][c][r];
         }
       }
     }
