@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(kBlock) k_sum_partials(Group<SumArgs> g) {
 struct CombineArgs {
   int64_t N;
   int q2, n_rhs, r0, n_far, identity;
+  int paired;   // q2 and N even, blocks and densities 16-byte aligned: two entries per lane and load
   uint32_t magic;
   const int64_t* ptr;
   const int32_t* patch;
@@ -155,19 +156,41 @@ __global__ void __launch_bounds__(kBlock) k_near_combine(Group<CombineArgs> g) {
     for (int o = kSub; o < 64; o <<= 1) ng_max = max(ng_max, __shfl_xor(ng_max, o, 64));
     const uint32_t len_max = (uint32_t)(ng_max * q2);
     // trip count uniform over the wave: every lane takes part in the shuffles, loads are predicated
+    if (A.paired) {
+      // entries 2k and 2k+1 lie in one block (q2 even), at consecutive columns: 16-byte loads
 #pragma unroll 8
-    for (uint32_t e0 = 0; e0 < len_max; e0 += kSub) {
-      const uint32_t e = e0 + sl;
-      const bool ok = e < len;
-      const uint32_t ee = ok ? e : 0;
-      const uint32_t blk = (uint32_t)(((uint64_t)ee * A.magic) >> 32);
-      const uint32_t loc = ee - blk * (uint32_t)q2;
-      const int P = __shfl(my_patch, (int)blk, kSub);
-      if (ok) {
-        const double c = Cg[e];
-        const int64_t col = (int64_t)P * q2 + loc;
+      for (uint32_t e0 = 0; e0 < len_max; e0 += 2 * kSub) {
+        const uint32_t e = e0 + 2 * sl;
+        const bool ok = e < len;
+        const uint32_t ee = ok ? e : 0;
+        const uint32_t blk = (uint32_t)(((uint64_t)ee * A.magic) >> 32);
+        const uint32_t loc = ee - blk * (uint32_t)q2;
+        const int P = __shfl(my_patch, (int)blk, kSub);
+        if (ok) {
+          const double2 c = *reinterpret_cast<const double2*>(Cg + e);
+          const int64_t col = (int64_t)P * q2 + loc;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) acc[r] = fma(c, sigma[(int64_t)(A.r0 + r) * N + col], acc[r]);
+          for (int r = 0; r < NR; ++r) {
+            const double2 sv = *reinterpret_cast<const double2*>(sigma + (int64_t)(A.r0 + r) * N + col);
+            acc[r] = fma(c.y, sv.y, fma(c.x, sv.x, acc[r]));
+          }
+        }
+      }
+    } else {
+#pragma unroll 8
+      for (uint32_t e0 = 0; e0 < len_max; e0 += kSub) {
+        const uint32_t e = e0 + sl;
+        const bool ok = e < len;
+        const uint32_t ee = ok ? e : 0;
+        const uint32_t blk = (uint32_t)(((uint64_t)ee * A.magic) >> 32);
+        const uint32_t loc = ee - blk * (uint32_t)q2;
+        const int P = __shfl(my_patch, (int)blk, kSub);
+        if (ok) {
+          const double c = Cg[e];
+          const int64_t col = (int64_t)P * q2 + loc;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) acc[r] = fma(c, sigma[(int64_t)(A.r0 + r) * N + col], acc[r]);
+        }
       }
     }
   }
@@ -360,6 +383,7 @@ CombineArgs combine_args(pmx_operator* op, const double* sigma, double* y, int n
   c.patch = op->nl.patch.p;
   c.Cb = parametrix ? op->nl.D.p : op->nl.C.p;
   c.sigma = sigma;
+  c.paired = (q2 % 2 == 0 && c.N % 2 == 0 && ((uintptr_t)sigma % 16) == 0 && ((uintptr_t)c.Cb % 16) == 0) ? 1 : 0;
   c.far = far;
   c.ssum = op->ssum.p;
   c.y = y;
