@@ -42,14 +42,14 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0
 # traffic is reported as null (the key hashes the file's code without its comments).
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
-                "kib": [("k_m2l", 12561.9, 413796.4)]},
-    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
-                    "kib": [("k_m2l_reduce", 166735.8, 7382.0)]},
-    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "765401913d976b10",
-                "kib": [("k_p2p", 46465.1, 9604.9)]},
-    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "080f4f015b50fac5",
-             "kib": [("k_near_combine", 280265.9, 1312.3)]},
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "89934e2df62e5092",
+                "kib": [("k_m2l", 11806.7, 372328.7)]},
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "89934e2df62e5092",
+                    "kib": [("k_m2l_reduce", 166736.5, 7385.0)]},
+    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "89934e2df62e5092",
+                "kib": [("k_p2p", 46501.7, 9603.9)]},
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "33a1b03a2cf04e3f",
+             "kib": [("k_near_combine", 279053.3, 1279.4)]},
 }
 
 
