@@ -217,8 +217,9 @@ def main():
                     help="run one device copy of this many MiB first (a known-size kernel for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
-              f"DESIGN.md and is not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the apply over several GPUs "
+              f"(by target ownership along the octree's Morton order) is designed but not implemented.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -307,15 +307,15 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
   }
 }
 
-// M2L on MFMA.  One workgroup per work item: up to 16 target boxes (one MFMA column
-// block) whose sources sit at the same offset (in box widths).  By homogeneity the
+// M2L on MFMA.  One workgroup per work item: up to 32 box pairs (two MFMA column
+// tiles) whose sources sit at the same offset (in box widths).  By homogeneity the
 // unit-box kernel of an offset is the same at every level, so an item may mix levels;
 // each column is scaled by its level's h^-1 (F1) or h^-2 (F2) when written.  The
-// item's source multipoles are staged in LDS once; each wave takes 16-row tiles,
+// item's source multipoles are staged in LDS once; each wave takes one 16-row tile,
 // generates the unit-box kernel for all nine components of its (row, m) pairs in
-// registers as MFMA A operands and keeps nine accumulator tiles.  Small items keep
-// the grid many times larger than the number of resident workgroups, so the chip
-// stays busy to the end of the launch; the wave count divides the row tiles evenly.
+// registers as MFMA A operands, each feeding both column tiles, and keeps eighteen
+// accumulator tiles.  The items are many more than the resident workgroups, and the
+// second stream's work fills the launch's tail.
 // Each pair writes its own output slot; k_m2l_reduce then sums a target's slots in a
 // fixed order, so no atomics are needed and the result does not depend on scheduling.
 constexpr int kM2LStride = 226;   // LDS row stride (== 2 mod 32: conflict-free B reads)
