@@ -146,6 +146,11 @@ PMX_API pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* 
 /* y = A sigma for n_rhs densities (eq:IE discretized, with the rank-one term):
  * y_i = sigma_i + sum_{j != i} w_j R(x_i, x_j) sigma_j + sum_{P near i} C_{i,P,:} sigma_P
  *       + sum_j w_j sigma_j.  precision selects the far-field evaluation (PMX_PREC_*).
+ * sigma and y: n_rhs rows of N doubles (row r at offset r N).  The first mixed apply of an
+ * operator builds its FMM tree, and the first with a larger n_rhs sizes its multi-rhs buffers
+ * (with n_rhs >= 8 also a by-patch view of the near lists, built on the host); these first
+ * calls allocate device memory and synchronize the stream, later ones with the same or a smaller
+ * n_rhs only enqueue work.  Mixed applies use the operator's second stream (pmx_options.overlap).
  * Errors: INVALID, OOM, DEVICE. */
 PMX_API pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, int mem_kind,
                      void* stream);
