@@ -331,103 +331,149 @@ struct M2LArgs {
   double h0;
 };
 
+// Workgroups of the persistent M2L launch: one per compute unit of the current device.
+static int64_t m2l_persistent_blocks() {
+  static thread_local int cached_dev = -1;
+  static thread_local int64_t cached = 0;
+  int dev = 0;
+  PMX_HIP(hipGetDevice(&dev));
+  if (dev != cached_dev) {
+    int cus = 0;
+    PMX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    cached = cus > 0 ? cus : 256;
+    cached_dev = dev;
+  }
+  return cached;
+}
+
 template <int P>
 constexpr int m2l_waves() { return (P * P * P + 15) / 16; }   // one row tile per wave: 14, 8, 4
 
 template <int P>
 __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
   constexpr int p3 = P * P * P;
-  int64_t lb;
-  const M2LArgs& A = seg_of(g, blockIdx.x, lb);
-  const float* __restrict__ tab = A.tab;
-  const int32_t* __restrict__ ps = A.ps;
-  const float* __restrict__ W = A.W;
-  float* __restrict__ slots = A.slots;
   static_assert(p3 <= kM2LStride, "multipole does not fit the LDS row");
   constexpr int n_rt = (p3 + 15) / 16;
   constexpr int n_waves = m2l_waves<P>();
-  __shared__ float sB[kItemCols * kM2LStride];
+  constexpr int kThr = 64 * n_waves;
+  constexpr int kPer = (kItemCols * p3 + kThr - 1) / kThr;   // staged multipole values per thread
+  // persistent: each workgroup takes items blockIdx.x, + gridDim.x, ...; the next item's
+  // multipoles are loaded into registers while the current item is computed, then written
+  // to the other LDS buffer, so the staging latency is off the critical path
+  __shared__ float sB[2][kItemCols * kM2LStride];
   __shared__ float4 sN[p3];
-  __shared__ float sS[2][kItemCols];
-  __shared__ int sP[kItemCols];
-  const int4 it = A.items[lb];
+  __shared__ float sS[2][2][kItemCols];
+  __shared__ int sP[2][kItemCols];
+  const int64_t total = g.off[g.n];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ncol = it.y;
-  // stage B[m][j] = W[source box of column j][m] as sB[j][m]
-  for (int e = threadIdx.x; e < kItemCols * p3; e += blockDim.x) {
-    const int j = e / p3, m = e - j * p3;
-    sB[j * kM2LStride + m] = j < ncol ? W[(int64_t)ps[it.x + j] * p3 + m] : 0.0f;
-  }
+  const int kq = lane >> 4, col = lane & 15;
   for (int m = threadIdx.x; m < p3; m += blockDim.x) {
-    const float* nd = tab + P + 2 * P * P + 3 * m;
+    const float* nd = g.a[0].tab + P + 2 * P * P + 3 * m;   // node table: the same for every operator
     sN[m] = make_float4(nd[0], nd[1], nd[2], 0.0f);
   }
-  if (threadIdx.x < kItemCols) {
-    const int j = threadIdx.x;
-    const double h = A.h0 / (double)(1 << (j < ncol ? A.plev[it.x + j] : 0));
-    sS[0][j] = (float)(1.0 / h);
-    sS[1][j] = (float)(1.0 / (h * h));
-    sP[j] = j < ncol ? A.pslot[it.x + j] : 0;
+  float stage[kPer];
+  auto load = [&](int64_t bi) {   // item bi's column multipoles, W[source box of column j][m]
+    int64_t lbi;
+    const M2LArgs& B = seg_of(g, bi, lbi);
+    const int4 itn = B.items[lbi];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + q * kThr;
+      const int j = e / p3, m = e - j * p3;
+      stage[q] = (e < kItemCols * p3 && j < itn.y) ? B.W[(int64_t)B.ps[itn.x + j] * p3 + m] : 0.0f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + q * kThr;
+      const int j = e / p3, m = e - j * p3;
+      if (e < kItemCols * p3) sB[buf][j * kM2LStride + m] = stage[q];
+    }
+  };
+  if (blockIdx.x < total) {
+    load(blockIdx.x);
+    store(0);
   }
-  __syncthreads();
-  const int code = it.w;
-  const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
-              oz = 2.0f * (float)(code % 7 - 3);
-  const int kq = lane >> 4, col = lane & 15;
-  // each wave takes one row tile; a generated kernel value (A operand) serves the item's
-  // kColTiles column tiles, so the generation's VALU work is spread over 9 kColTiles MFMAs.
-  // Rows past p^3 (last tile) use node 0: with the offset at least two box widths away the
-  // kernel stays finite there, and those rows are never stored.
-  static_assert(n_waves == n_rt, "one row tile per wave");
-  const int row = wave * 16 + col;
-  const float4 tl = sN[row < p3 ? row : 0];
-  const float tlx = tl.x + ox, tly = tl.y + oy, tlz = tl.z + oz;
-  floatx4 acc[kColTiles][9];
+  int k = 0;
+  for (int64_t bi = blockIdx.x; bi < total; bi += gridDim.x, ++k) {
+    const int buf = k & 1;
+    int64_t lb;
+    const M2LArgs& A = seg_of(g, bi, lb);
+    const int4 it = A.items[lb];
+    const int ncol = it.y;
+    if (threadIdx.x < kItemCols) {   // this buffer's previous item finished before the last barrier
+      const int j = threadIdx.x;
+      const double h = A.h0 / (double)(1 << (j < ncol ? A.plev[it.x + j] : 0));
+      sS[buf][0][j] = (float)(1.0 / h);
+      sS[buf][1][j] = (float)(1.0 / (h * h));
+      sP[buf][j] = j < ncol ? A.pslot[it.x + j] : 0;
+    }
+    const int64_t bn = bi + gridDim.x;
+    if (bn < total) load(bn);
+    __syncthreads();   // this item's multipoles (stored last iteration), scales and slots are in LDS
+    const int code = it.w;
+    const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
+                oz = 2.0f * (float)(code % 7 - 3);
+    // each wave takes one row tile; a generated kernel value (A operand) serves the item's
+    // kColTiles column tiles, so the generation's VALU work is spread over 9 kColTiles MFMAs.
+    // Rows past p^3 (last tile) use node 0: with the offset at least two box widths away the
+    // kernel stays finite there, and those rows are never stored.
+    static_assert(n_waves == n_rt, "one row tile per wave");
+    const int row = wave * 16 + col;
+    const float4 tl = sN[row < p3 ? row : 0];
+    const float tlx = tl.x + ox, tly = tl.y + oy, tlz = tl.z + oz;
+    floatx4 acc[kColTiles][9];
 #pragma unroll
-  for (int ct = 0; ct < kColTiles; ++ct)
+    for (int ct = 0; ct < kColTiles; ++ct)
 #pragma unroll
-    for (int c = 0; c < 9; ++c) acc[ct][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int c = 0; c < 9; ++c) acc[ct][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* sBb = sB[buf];
 #pragma unroll 2
-  for (int k0 = 0; k0 < p3; k0 += 4) {
-    const int m = k0 + kq;
-    const float4 tm = sN[m < p3 ? m : 0];
-    // k past p^3 (p^3 not a multiple of 4): a zero B row removes the term
-    float b0[kColTiles];
+    for (int k0 = 0; k0 < p3; k0 += 4) {
+      const int m = k0 + kq;
+      const float4 tm = sN[m < p3 ? m : 0];
+      // k past p^3 (p^3 not a multiple of 4): a zero B row removes the term
+      float b0[kColTiles];
 #pragma unroll
-    for (int ct = 0; ct < kColTiles; ++ct)
-      b0[ct] = (p3 % 4 == 0 || m < p3) ? sB[(ct * 16 + col) * kM2LStride + (m < p3 ? m : 0)] : 0.0f;
-    const float rx = tlx - tm.x, ry = tly - tm.y, rz = tlz - tm.z;
-    const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
-    // r / r^2 and (r r^T) / r^4 = (r / r^2)(r / r^2)^T
-    float a[9];
-    a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
-    a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
-    a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
+      for (int ct = 0; ct < kColTiles; ++ct)
+        b0[ct] = (p3 % 4 == 0 || m < p3) ? sBb[(ct * 16 + col) * kM2LStride + (m < p3 ? m : 0)] : 0.0f;
+      const float rx = tlx - tm.x, ry = tly - tm.y, rz = tlz - tm.z;
+      const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+      // r / r^2 and (r r^T) / r^4 = (r / r^2)(r / r^2)^T
+      float a[9];
+      a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
+      a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
+      a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
 #pragma unroll
-    for (int ct = 0; ct < kColTiles; ++ct)
+      for (int ct = 0; ct < kColTiles; ++ct)
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc[ct][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0[ct], acc[ct][c], 0, 0, 0);
-  }
-  const int l0 = wave * 16 + 4 * kq;
+        for (int c = 0; c < 9; ++c)
+          acc[ct][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0[ct], acc[ct][c], 0, 0, 0);
+    }
+    const int l0 = wave * 16 + 4 * kq;
 #pragma unroll
-  for (int ct = 0; ct < kColTiles; ++ct) {
-    const int pj = ct * 16 + col;
-    if (pj < ncol) {
-      float* out = slots + (int64_t)sP[pj] * lstride<P>();
-      const float s1 = sS[0][pj], s2 = sS[1][pj];
+    for (int ct = 0; ct < kColTiles; ++ct) {
+      const int pj = ct * 16 + col;
+      if (pj < ncol) {
+        float* out = A.slots + (int64_t)sP[buf][pj] * lstride<P>();
+        const float s1 = sS[buf][0][pj], s2 = sS[buf][1][pj];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        const float sc = c < 3 ? s1 : s2;
-        if (l0 + 3 < p3 && (p3 % 4) == 0) {   // four consecutive rows: one 16-byte store
-          *reinterpret_cast<float4*>(out + c * p3 + l0) =
-              make_float4(sc * acc[ct][c][0], sc * acc[ct][c][1], sc * acc[ct][c][2], sc * acc[ct][c][3]);
-        } else {
+        for (int c = 0; c < 9; ++c) {
+          const float sc = c < 3 ? s1 : s2;
+          if (l0 + 3 < p3 && (p3 % 4) == 0) {   // four consecutive rows: one 16-byte store
+            *reinterpret_cast<float4*>(out + c * p3 + l0) =
+                make_float4(sc * acc[ct][c][0], sc * acc[ct][c][1], sc * acc[ct][c][2], sc * acc[ct][c][3]);
+          } else {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (l0 + r < p3) out[c * p3 + l0 + r] = sc * acc[ct][c][r];
+            for (int r = 0; r < 4; ++r)
+              if (l0 + r < p3) out[c * p3 + l0 + r] = sc * acc[ct][c][r];
+          }
         }
       }
     }
+    if (bn < total) store(buf ^ 1);   // the other buffer's item was finished before this barrier
+    __syncthreads();
   }
 }
 
@@ -1272,7 +1318,9 @@ static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, int n_rhs, Pro
       rb.push_back(F->n_boxes - box2);
     }
     launch_grouped(la, lb, [&](const Group<M2LArgs>& g, int64_t nb) {
-      hipLaunchKernelGGL(k_m2l<P>, dim3((unsigned)nb), dim3(64 * m2l_waves<P>()), 0, st, g);
+      // persistent workgroups (one resident per CU at this size), striding over the items
+      const int64_t grid = std::min<int64_t>(nb, m2l_persistent_blocks());
+      hipLaunchKernelGGL(k_m2l<P>, dim3((unsigned)grid), dim3(64 * m2l_waves<P>()), 0, st, g);
       PMX_HIP(hipGetLastError());
     });
     done(t);
