@@ -314,8 +314,16 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
 // item's source multipoles are staged in LDS once; each wave takes one 16-row tile,
 // generates the unit-box kernel for all nine components of its (row, m) pairs in
 // registers as MFMA A operands, each feeding both column tiles, and keeps eighteen
-// accumulator tiles.  The items are many more than the resident workgroups, and the
-// second stream's work fills the launch's tail.
+// accumulator tiles.  A compute unit issues MFMAs from four SIMDs, so when the row tiles
+// are not a multiple of four (p = 6: 14 tiles) the split layout divides the last two
+// tiles by column tile over four half waves, one in each group of four waves and one per
+// SIMD whether the waves are dealt round-robin or in blocks: every SIMD then carries seven
+// tile-units instead of eight on two SIMDs and six on the other two.  Its sixteen waves
+// fill every SIMD's registers, so it is launched when the M2L has the compute units to
+// itself; beside the second stream's kernels the 14-wave layout runs, whose two SIMDs with
+// three waves leave register room for the P2P waves (measured faster that way, while the
+// split layout is faster alone).  The items are many more than the resident workgroups,
+// and the second stream's work fills the launch's tail.
 // Each pair writes its own output slot; k_m2l_reduce then sums a target's slots in a
 // fixed order, so no atomics are needed and the result does not depend on scheduling.
 constexpr int kM2LStride = 226;   // LDS row stride (== 2 mod 32: conflict-free B reads)
@@ -347,14 +355,21 @@ static int64_t m2l_persistent_blocks() {
 }
 
 template <int P>
-constexpr int m2l_waves() { return (P * P * P + 15) / 16; }   // one row tile per wave: 14, 8, 4
-
+constexpr int m2l_row_tiles() { return (P * P * P + 15) / 16; }   // 14, 8, 4
 template <int P>
-__global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
+constexpr bool m2l_can_split() { return m2l_row_tiles<P>() % 4 == 2; }   // p = 6
+template <int P, bool Split>
+constexpr int m2l_waves() { return m2l_row_tiles<P>() + (Split ? 2 : 0); }   // 16 split; 14, 8, 4
+
+template <int P, bool Split>
+__global__ void __launch_bounds__((64 * m2l_waves<P, Split>())) k_m2l(Group<M2LArgs> g) {
   constexpr int p3 = P * P * P;
   static_assert(p3 <= kM2LStride, "multipole does not fit the LDS row");
-  constexpr int n_rt = (p3 + 15) / 16;
-  constexpr int n_waves = m2l_waves<P>();
+  constexpr int n_rt = m2l_row_tiles<P>();
+  constexpr int n_waves = m2l_waves<P, Split>();
+  constexpr bool kSplit = Split;
+  static_assert(!kSplit || (m2l_can_split<P>() && n_waves == 16),
+                "half waves 0, 5, 10, 15: one per group of four and per SIMD");
   constexpr int kThr = 64 * n_waves;
   constexpr int kPer = (kItemCols * p3 + kThr - 1) / kThr;   // staged multipole values per thread
   // persistent: each workgroup takes items blockIdx.x, + gridDim.x, ...; the next item's
@@ -365,8 +380,12 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
   __shared__ float sS[2][2][kItemCols];
   __shared__ int sP[2][kItemCols];
   const int64_t total = g.off[g.n];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int kq = lane >> 4, col = lane & 15;
+  // this wave's row tile; a half wave (split layout) takes one column tile, hc, of it
+  const bool half = kSplit && (wave >> 2) == (wave & 3);
+  const int rt = !kSplit ? wave : half ? n_rt - 2 + (wave >> 3) : wave - (wave + 4) / 5;
+  const int hc = (wave >> 2) & 1;
   for (int m = threadIdx.x; m < p3; m += blockDim.x) {
     const float* nd = g.a[0].tab + P + 2 * P * P + 3 * m;   // node table: the same for every operator
     sN[m] = make_float4(nd[0], nd[1], nd[2], 0.0f);
@@ -415,12 +434,11 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
     const int code = it.w;
     const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
                 oz = 2.0f * (float)(code % 7 - 3);
-    // each wave takes one row tile; a generated kernel value (A operand) serves the item's
-    // kColTiles column tiles, so the generation's VALU work is spread over 9 kColTiles MFMAs.
-    // Rows past p^3 (last tile) use node 0: with the offset at least two box widths away the
-    // kernel stays finite there, and those rows are never stored.
-    static_assert(n_waves == n_rt, "one row tile per wave");
-    const int row = wave * 16 + col;
+    // a generated kernel value (A operand) serves the wave's column tiles, so the
+    // generation's VALU work is spread over 9 MFMAs per column tile.  Rows past p^3 (last
+    // tile) use node 0: with the offset at least two box widths away the kernel stays finite
+    // there, and those rows are never stored.
+    const int row = rt * 16 + col;
     const float4 tl = sN[row < p3 ? row : 0];
     const float tlx = tl.x + ox, tly = tl.y + oy, tlz = tl.z + oz;
     floatx4 acc[kColTiles][9];
@@ -429,32 +447,42 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[ct][c] = floatx4{0.f, 0.f, 0.f, 0.f};
     const float* sBb = sB[buf];
+    // NCT column tiles from column tile t0 on: a full wave takes all of them, a half wave one
+    auto run = [&](auto nct_tag, int t0) {
+      constexpr int NCT = decltype(nct_tag)::value;
 #pragma unroll 2
-    for (int k0 = 0; k0 < p3; k0 += 4) {
-      const int m = k0 + kq;
-      const float4 tm = sN[m < p3 ? m : 0];
-      // k past p^3 (p^3 not a multiple of 4): a zero B row removes the term
-      float b0[kColTiles];
+      for (int k0 = 0; k0 < p3; k0 += 4) {
+        const int m = k0 + kq;
+        const float4 tm = sN[m < p3 ? m : 0];
+        // k past p^3 (p^3 not a multiple of 4): a zero B row removes the term
+        float b0[NCT];
 #pragma unroll
-      for (int ct = 0; ct < kColTiles; ++ct)
-        b0[ct] = (p3 % 4 == 0 || m < p3) ? sBb[(ct * 16 + col) * kM2LStride + (m < p3 ? m : 0)] : 0.0f;
-      const float rx = tlx - tm.x, ry = tly - tm.y, rz = tlz - tm.z;
-      const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
-      // r / r^2 and (r r^T) / r^4 = (r / r^2)(r / r^2)^T
-      float a[9];
-      a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
-      a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
-      a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
+        for (int ct = 0; ct < NCT; ++ct)
+          b0[ct] = (p3 % 4 == 0 || m < p3) ? sBb[((t0 + ct) * 16 + col) * kM2LStride + (m < p3 ? m : 0)]
+                                           : 0.0f;
+        const float rx = tlx - tm.x, ry = tly - tm.y, rz = tlz - tm.z;
+        const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+        // r / r^2 and (r r^T) / r^4 = (r / r^2)(r / r^2)^T
+        float a[9];
+        a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
+        a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
+        a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
 #pragma unroll
-      for (int ct = 0; ct < kColTiles; ++ct)
+        for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-        for (int c = 0; c < 9; ++c)
-          acc[ct][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0[ct], acc[ct][c], 0, 0, 0);
-    }
-    const int l0 = wave * 16 + 4 * kq;
+          for (int c = 0; c < 9; ++c)
+            acc[ct][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0[ct], acc[ct][c], 0, 0, 0);
+      }
+    };
+    if (half)
+      run(std::integral_constant<int, 1>{}, hc);
+    else
+      run(std::integral_constant<int, kColTiles>{}, 0);
+    const int l0 = rt * 16 + 4 * kq;
 #pragma unroll
     for (int ct = 0; ct < kColTiles; ++ct) {
-      const int pj = ct * 16 + col;
+      if (half && ct > 0) break;
+      const int pj = (half ? hc : ct) * 16 + col;
       if (pj < ncol) {
         float* out = A.slots + (int64_t)sP[buf][pj] * lstride<P>();
         const float s1 = sS[buf][0][pj], s2 = sS[buf][1][pj];
@@ -482,6 +510,11 @@ __global__ void __launch_bounds__(64 * m2l_waves<P>()) k_m2l(Group<M2LArgs> g) {
 // generated kernel block serves all of them and the locals stay in registers across the
 // sources (no per-pair output slots and no slot sum).  The next source's multipoles are loaded
 // into registers while the current one is computed, then stored to the other LDS buffer.
+// Layouts: with 14 row tiles (p = 6) one 16-wave workgroup takes the whole box, and the last
+// two row tiles are split by source node (first and second half of the p^3) over four half
+// waves, one in each group of four and one per SIMD, whose two partial sums are added at the
+// end: every SIMD then carries 3.5 tile-units per source.  Otherwise two workgroups per box
+// take half the row tiles each.
 struct M2L16Args {
   const float* tab;
   const int32_t* rptr;    // box b's sources are [rptr[b - box2], rptr[b - box2 + 1])
@@ -495,7 +528,11 @@ struct M2L16Args {
 };
 
 template <int P>
-constexpr int m2l16_waves() { return (P * P * P + 31) / 32; }   // half the row tiles, one per wave
+constexpr bool m2l16_whole() { return m2l_can_split<P>(); }   // p = 6: one workgroup per box
+template <int P>
+constexpr int m2l16_groups_per_box() { return m2l16_whole<P>() ? 1 : 2; }
+template <int P>
+constexpr int m2l16_waves() { return m2l16_whole<P>() ? 16 : (P * P * P + 31) / 32; }   // 16; 4, 2
 
 template <int P>
 __global__ void __launch_bounds__(64 * m2l16_waves<P>()) __attribute__((amdgpu_waves_per_eu(4)))
@@ -503,20 +540,29 @@ k_m2l16(Group<M2L16Args> g) {
   constexpr int p3 = P * P * P;
   constexpr int n_rt = (p3 + 15) / 16;
   constexpr int n_waves = m2l16_waves<P>();
-  static_assert(2 * n_waves == n_rt, "two workgroups per box, one row tile per wave");
+  constexpr bool kWhole = m2l16_whole<P>();
+  static_assert(kWhole ? (n_rt == 14 && n_waves == 16 && (p3 / 2) % 4 == 0) : 2 * n_waves == n_rt,
+                "whole box: 12 full and 4 half waves; else two workgroups per box, one row tile per wave");
   constexpr int NT = 1;
   constexpr int kThr = 64 * n_waves;
   constexpr int kPer = (16 * p3 + kThr - 1) / kThr;   // staged multipole values per thread
   int64_t lb;
   const M2L16Args& A = seg_of(g, blockIdx.x, lb);
-  const int half = (int)(lb & 1);          // which half of the box's row tiles
-  lb >>= 1;
+  const int half = kWhole ? 0 : (int)(lb & 1);   // which half of the box's row tiles
+  if (!kWhole) lb >>= 1;
   const int64_t box = A.box2 + lb;
   const int s0 = A.rptr[lb], s1 = A.rptr[lb + 1];
   const int64_t slice = A.n_boxes * (int64_t)p3;
-  __shared__ float sB[2][16 * kM2LStride];
+  __shared__ __align__(16) float sB[2][16 * kM2LStride];
+  static_assert(!kWhole || 2 * 9 * 64 * 4 <= 2 * 16 * kM2LStride, "the half waves' sums fit in sB");
   __shared__ float4 sN[p3];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  // this wave's row tile and source-node range [kbeg, kend); a half wave (whole-box layout)
+  // takes half kh of the nodes of row tile 12 or 13
+  const bool hw = kWhole && (wave >> 2) == (wave & 3);
+  const int rt = !kWhole ? wave + half * n_waves : hw ? n_rt - 2 + (wave >> 3) : wave - (wave + 4) / 5;
+  const int kh = (wave >> 2) & 1;
+  const int kbeg = hw ? kh * (p3 / 2) : 0, kend = hw ? kbeg + p3 / 2 : p3;
   for (int m = threadIdx.x; m < p3; m += blockDim.x) {
     const float* nd = A.tab + P + 2 * P * P + 3 * m;
     sN[m] = make_float4(nd[0], nd[1], nd[2], 0.0f);
@@ -567,7 +613,7 @@ k_m2l16(Group<M2L16Args> g) {
     float tlx[NT], tly[NT], tlz[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int row = (wave + half * n_waves) * 16 + col;
+      const int row = rt * 16 + col;
       const float4 tl = sN[row < p3 ? row : 0];
       tlx[t] = tl.x + ox;
       tly[t] = tl.y + oy;
@@ -575,7 +621,7 @@ k_m2l16(Group<M2L16Args> g) {
     }
     const float* sBc = sB[buf] + col * kM2LStride;
 #pragma unroll 2
-    for (int k0 = 0; k0 < p3; k0 += 4) {
+    for (int k0 = kbeg; k0 < kend; k0 += 4) {
       const int m = k0 + kq;
       const float4 tm = sN[m < p3 ? m : 0];
       const float b0 = (p3 % 4 == 0 || m < p3) ? sBc[m < p3 ? m : 0] : 0.0f;
@@ -598,15 +644,27 @@ k_m2l16(Group<M2L16Args> g) {
     if (si + 1 < s1) store(buf ^ 1);
     __syncthreads();
   }
+  if (kWhole) {   // the second-half waves hand their sums to the first-half waves through LDS
+    floatx4* sC = reinterpret_cast<floatx4*>(&sB[0][0]);   // [2 row tiles][9][64 lanes]; sB is idle now
+    const int slot = (rt - (n_rt - 2)) * 9;
+    if (hw && kh == 1)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sC[(slot + c) * 64 + lane] = tot[0][c];
+    __syncthreads();
+    if (hw && kh == 0)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) tot[0][c] += sC[(slot + c) * 64 + lane];
+  }
   // every source of the box sits at the box's level: one scale per component group
   int lev = 2;
   while (lev < A.L && box >= A.lev_first[lev + 1]) ++lev;
   const double h = A.h0 / (double)(1 << lev);
   const float s1f = (float)(1.0 / h), s2f = (float)(1.0 / (h * h));
   float* out = A.L16 + (int64_t)col * A.n_boxes * lstride<P>() + box * lstride<P>();
+  if (hw && kh == 1) return;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int l0 = (wave + half * n_waves) * 16 + 4 * kq;
+    const int l0 = rt * 16 + 4 * kq;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const float sc = c < 3 ? s1f : s2f;
@@ -1317,10 +1375,18 @@ static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, int n_rhs, Pro
       ra.push_back({box2, F->r_ptr.p, F->slots.p, F->Lc.p});
       rb.push_back(F->n_boxes - box2);
     }
+    // the split layout when nothing runs beside this launch: the side stream's kernels are
+    // in flight only after a fork onto a distinct stream
+    constexpr bool kCanSplit = m2l_can_split<P>();
+    const bool beside = fork && side != st;
     launch_grouped(la, lb, [&](const Group<M2LArgs>& g, int64_t nb) {
       // persistent workgroups (one resident per CU at this size), striding over the items
       const int64_t grid = std::min<int64_t>(nb, m2l_persistent_blocks());
-      hipLaunchKernelGGL(k_m2l<P>, dim3((unsigned)grid), dim3(64 * m2l_waves<P>()), 0, st, g);
+      if (kCanSplit && !beside)
+        hipLaunchKernelGGL((k_m2l<P, kCanSplit>), dim3((unsigned)grid), dim3(64 * m2l_waves<P, kCanSplit>()), 0,
+                           st, g);
+      else
+        hipLaunchKernelGGL((k_m2l<P, false>), dim3((unsigned)grid), dim3(64 * m2l_waves<P, false>()), 0, st, g);
       PMX_HIP(hipGetLastError());
     });
     done(t);
@@ -1473,7 +1539,7 @@ static void fmm_far_block16(const std::vector<ApplyJob>& jobs, int rb, Profiler*
       const int64_t box2 = F->lev_off[2];
       la.push_back({F->tab.p, F->r_ptr.p, F->tsrc.p, box2, F->n_boxes, F->L, F->lev_off_d.p, F->W16.p, F->L16.p,
                     F->h0});
-      lb.push_back(2 * (F->n_boxes - box2));   // two workgroups per box
+      lb.push_back(m2l16_groups_per_box<P>() * (F->n_boxes - box2));
     }
     launch_grouped(la, lb, [&](const Group<M2L16Args>& g, int64_t nb) {
       hipLaunchKernelGGL(k_m2l16<P>, dim3((unsigned)nb), dim3(64 * m2l16_waves<P>()), 0, st, g);
