@@ -510,11 +510,10 @@ __global__ void __launch_bounds__((64 * m2l_waves<P, Split>())) k_m2l(Group<M2LA
 // generated kernel block serves all of them and the locals stay in registers across the
 // sources (no per-pair output slots and no slot sum).  The next source's multipoles are loaded
 // into registers while the current one is computed, then stored to the other LDS buffer.
-// Layouts: with 14 row tiles (p = 6) one 16-wave workgroup takes the whole box, and the last
-// two row tiles are split by source node (first and second half of the p^3) over four half
-// waves, one in each group of four and one per SIMD, whose two partial sums are added at the
-// end: every SIMD then carries 3.5 tile-units per source.  Otherwise two workgroups per box
-// take half the row tiles each.
+// One wave per 16-row tile (4 and 8 waves at p = 4, 5).  With 14 row tiles (p = 6) the last
+// two are split by source node (first and second half of the p^3) over four half waves, one
+// in each group of four and one per SIMD, whose two partial sums are added at the end: 16
+// waves, and every SIMD carries 3.5 tile-units per source.
 struct M2L16Args {
   const float* tab;
   const int32_t* rptr;    // box b's sources are [rptr[b - box2], rptr[b - box2 + 1])
@@ -528,11 +527,7 @@ struct M2L16Args {
 };
 
 template <int P>
-constexpr bool m2l16_whole() { return m2l_can_split<P>(); }   // p = 6: one workgroup per box
-template <int P>
-constexpr int m2l16_groups_per_box() { return m2l16_whole<P>() ? 1 : 2; }
-template <int P>
-constexpr int m2l16_waves() { return m2l16_whole<P>() ? 16 : (P * P * P + 31) / 32; }   // 16; 4, 2
+constexpr int m2l16_waves() { return m2l_row_tiles<P>() + (m2l_can_split<P>() ? 2 : 0); }   // 16, 8, 4
 
 template <int P>
 __global__ void __launch_bounds__(64 * m2l16_waves<P>()) __attribute__((amdgpu_waves_per_eu(4)))
@@ -540,29 +535,26 @@ k_m2l16(Group<M2L16Args> g) {
   constexpr int p3 = P * P * P;
   constexpr int n_rt = (p3 + 15) / 16;
   constexpr int n_waves = m2l16_waves<P>();
-  constexpr bool kWhole = m2l16_whole<P>();
-  static_assert(kWhole ? (n_rt == 14 && n_waves == 16 && (p3 / 2) % 4 == 0) : 2 * n_waves == n_rt,
-                "whole box: 12 full and 4 half waves; else two workgroups per box, one row tile per wave");
+  constexpr bool kSplit = m2l_can_split<P>();
+  static_assert(kSplit ? (n_rt == 14 && n_waves == 16 && (p3 / 2) % 4 == 0) : n_waves == n_rt,
+                "12 full and 4 half waves, or one row tile per wave");
   constexpr int NT = 1;
   constexpr int kThr = 64 * n_waves;
   constexpr int kPer = (16 * p3 + kThr - 1) / kThr;   // staged multipole values per thread
   int64_t lb;
   const M2L16Args& A = seg_of(g, blockIdx.x, lb);
-  const int half = kWhole ? 0 : (int)(lb & 1);   // which half of the box's row tiles
-  if (!kWhole) lb >>= 1;
   const int64_t box = A.box2 + lb;
   const int s0 = A.rptr[lb], s1 = A.rptr[lb + 1];
   const int64_t slice = A.n_boxes * (int64_t)p3;
   __shared__ __align__(16) float sB[2][16 * kM2LStride];
-  static_assert(!kWhole || 2 * 9 * 64 * 4 <= 2 * 16 * kM2LStride, "the half waves' sums fit in sB");
+  static_assert(!kSplit || 2 * 9 * 64 * 4 <= 2 * 16 * kM2LStride, "the half waves' sums fit in sB");
   __shared__ float4 sN[p3];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  // this wave's row tile and source-node range [kbeg, kend); a half wave (whole-box layout)
-  // takes half kh of the nodes of row tile 12 or 13
-  const bool hw = kWhole && (wave >> 2) == (wave & 3);
-  const int rt = !kWhole ? wave + half * n_waves : hw ? n_rt - 2 + (wave >> 3) : wave - (wave + 4) / 5;
+  // this wave's row tile; a half wave (split layout) takes half kh of the source nodes of
+  // row tile 12 or 13
+  const bool hw = kSplit && (wave >> 2) == (wave & 3);
+  const int rt = !kSplit ? wave : hw ? n_rt - 2 + (wave >> 3) : wave - (wave + 4) / 5;
   const int kh = (wave >> 2) & 1;
-  const int kbeg = hw ? kh * (p3 / 2) : 0, kend = hw ? kbeg + p3 / 2 : p3;
   for (int m = threadIdx.x; m < p3; m += blockDim.x) {
     const float* nd = A.tab + P + 2 * P * P + 3 * m;
     sN[m] = make_float4(nd[0], nd[1], nd[2], 0.0f);
@@ -620,23 +612,34 @@ k_m2l16(Group<M2L16Args> g) {
       tlz[t] = tl.z + oz;
     }
     const float* sBc = sB[buf] + col * kM2LStride;
+    // NK steps of four source nodes from node kb on (a compile-time count, so the loop unrolls)
+    auto run = [&](auto nk_tag, int kb) {
+      constexpr int NK = decltype(nk_tag)::value;
 #pragma unroll 2
-    for (int k0 = kbeg; k0 < kend; k0 += 4) {
-      const int m = k0 + kq;
-      const float4 tm = sN[m < p3 ? m : 0];
-      const float b0 = (p3 % 4 == 0 || m < p3) ? sBc[m < p3 ? m : 0] : 0.0f;
+      for (int ks = 0; ks < NK; ++ks) {
+        const int m = kb + 4 * ks + kq;
+        // with p^3 a multiple of 4 every node index is below p^3; otherwise the last step's
+        // extra nodes read node 0 against a zero B entry
+        const int mc = p3 % 4 == 0 ? m : (m < p3 ? m : 0);
+        const float4 tm = sN[mc];
+        const float b0 = (p3 % 4 == 0 || m < p3) ? sBc[mc] : 0.0f;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const float rx = tlx[t] - tm.x, ry = tly[t] - tm.y, rz = tlz[t] - tm.z;
-        const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
-        float a[9];
-        a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
-        a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
-        a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
+        for (int t = 0; t < NT; ++t) {
+          const float rx = tlx[t] - tm.x, ry = tly[t] - tm.y, rz = tlz[t] - tm.z;
+          const float inv = __builtin_amdgcn_rcpf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+          float a[9];
+          a[0] = rx * inv; a[1] = ry * inv; a[2] = rz * inv;
+          a[3] = a[0] * a[0]; a[4] = a[0] * a[1]; a[5] = a[0] * a[2];
+          a[6] = a[1] * a[1]; a[7] = a[1] * a[2]; a[8] = a[2] * a[2];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[t][c], 0, 0, 0);
+          for (int c = 0; c < 9; ++c) acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0, acc[t][c], 0, 0, 0);
+        }
       }
-    }
+    };
+    if (hw)
+      run(std::integral_constant<int, p3 / 8>{}, kh * (p3 / 2));
+    else
+      run(std::integral_constant<int, (p3 + 3) / 4>{}, 0);
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -644,7 +647,7 @@ k_m2l16(Group<M2L16Args> g) {
     if (si + 1 < s1) store(buf ^ 1);
     __syncthreads();
   }
-  if (kWhole) {   // the second-half waves hand their sums to the first-half waves through LDS
+  if (kSplit) {   // the second-half waves hand their sums to the first-half waves through LDS
     floatx4* sC = reinterpret_cast<floatx4*>(&sB[0][0]);   // [2 row tiles][9][64 lanes]; sB is idle now
     const int slot = (rt - (n_rt - 2)) * 9;
     if (hw && kh == 1)
@@ -1539,7 +1542,7 @@ static void fmm_far_block16(const std::vector<ApplyJob>& jobs, int rb, Profiler*
       const int64_t box2 = F->lev_off[2];
       la.push_back({F->tab.p, F->r_ptr.p, F->tsrc.p, box2, F->n_boxes, F->L, F->lev_off_d.p, F->W16.p, F->L16.p,
                     F->h0});
-      lb.push_back(m2l16_groups_per_box<P>() * (F->n_boxes - box2));
+      lb.push_back(F->n_boxes - box2);   // one workgroup per box
     }
     launch_grouped(la, lb, [&](const Group<M2L16Args>& g, int64_t nb) {
       hipLaunchKernelGGL(k_m2l16<P>, dim3((unsigned)nb), dim3(64 * m2l16_waves<P>()), 0, st, g);

@@ -97,6 +97,28 @@ def test_overlap_streams_bitwise(ctx, n_rhs):
     say(f"[overlap] N={p.n} rhs={n_rhs}: two-stream and one-stream applies identical (3 repeats each)")
 
 
+@pytest.mark.parametrize("order", [4, 5, 6])
+def test_block16_orders_match_single(ctx, order):
+    """A whole block of 16 right-hand sides takes the 16-column M2L (one workgroup per box walking
+    its sources; at p = 6 four half waves split the last two row tiles by source node) and the
+    multi-charge P2P.  Each column equals the single-rhs apply of the same order up to FP32
+    summation order, at every order the build supports."""
+    from paper_2401_12501_amd import pmx
+    p = ellipsoid_problem(k=4, q=10)
+    sig = random_density(p.n, 16, seed=37).T.copy()
+    surf, op = make(ctx, p, order=order, leaf=64)
+    ym = op.apply(sig, pmx.PMX_PREC_MIXED_FMM)
+    assert op.stats().fmm_m2l_pairs > 0      # the FMM is built by the first mixed apply
+    worst = 0.0
+    for r in (0, 7, 15):
+        y1 = op.apply(sig[r].copy(), pmx.PMX_PREC_MIXED_FMM)[0]
+        far1 = far_part(op, y1[None], sig[r][None])[0]
+        worst = max(worst, float(np.abs(ym[r] - y1).max() / np.abs(far1).max()))
+    say(f"[block16] N={p.n} p={order}: max |y_block - y_single| / max|far| = {worst:.2e}")
+    # the same FP32 summation-order bound as for the multi-charge P2P below
+    assert worst < 1e-5
+
+
 @pytest.mark.parametrize("n_rhs", [3, 16, 20])
 def test_multi_rhs_p2p_matches_single(ctx, n_rhs):
     """Several right-hand sides share each P2P pair evaluation (blocks of up to 16 charges per
