@@ -474,10 +474,17 @@ __global__ void __launch_bounds__((64 * m2l_waves<P, Split>())) k_m2l(Group<M2LA
             acc[ct][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b0[ct], acc[ct][c], 0, 0, 0);
       }
     };
-    if (half)
-      run(std::integral_constant<int, 1>{}, hc);
-    else
+    // an item of at most 16 pairs (an offset's last item) fills only the first column tile:
+    // the second tile's MFMAs are skipped (ncol is the same for the whole workgroup)
+    static_assert(kColTiles == 2, "one or two column tiles per item");
+    const bool one_tile = ncol <= 16;
+    if (half) {
+      if (!(one_tile && hc == 1)) run(std::integral_constant<int, 1>{}, hc);
+    } else if (one_tile) {
+      run(std::integral_constant<int, 1>{}, 0);
+    } else {
       run(std::integral_constant<int, kColTiles>{}, 0);
+    }
     const int l0 = rt * 16 + 4 * kq;
 #pragma unroll
     for (int ct = 0; ct < kColTiles; ++ct) {
