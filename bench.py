@@ -14,9 +14,11 @@ value = N * n_rhs * K / (wall time of K steps), in Gpts/s.
 
 The same run also reports the other path's apply rate, the time to reach a
 relative residual of 1e-8 on both paths (mixed: iterative refinement with FP64
-residuals), the apply error against the oracle on sampled rows, the roofline
+residuals), the representation u = K[sigma] of the mixed solution, the roofline
 of the dominant kernel (device time from HIP events on the library's stream),
-and the oracle timed on the host cores on a bounded sample of rows.
+and, in the CPU leg (skipped with --no-cpu, the only part that runs the oracle),
+the oracle's checks of the apply, the solutions and the representation on
+sampled rows and the oracle timed on the host cores on a bounded sample of rows.
 """
 from __future__ import annotations
 
@@ -82,6 +84,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measure_representation(op, s_dev, N: int, n_rhs: int):
+    """u = K[sigma] of the mixed solution: the FP64 direct log-kernel sum plus the parametrix near
+    blocks D, minus its weighted mean.  The first call also builds the D blocks.  Returns (record,
+    u on the host); the CPU leg checks u on sampled rows."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = op.represent(s_dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    u = op.represent(s_dev, out=u)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    u_h = u.cpu().numpy().T.copy()                # (N, n_rhs)
+    rep = {"ms": round((t2 - t1) * 1e3, 3), "first_call_ms": round((t1 - t0) * 1e3, 3),
+           "gpts_per_s": round(N * n_rhs / (t2 - t1) / 1e9, 5)}
+    log(f"[bench] representation u = K[sigma]: {rep}")
+    return rep, u_h
+
+
 def algorithmic_work(phase: str, st, N: int, q: int, n_rhs: int, fmm_order: int, path: str = "mixed"):
     """(amount per launch, unit, bound, peak) of a phase's kernel(s)."""
     p3 = fmm_order ** 3
@@ -104,12 +126,42 @@ def algorithmic_work(phase: str, st, N: int, q: int, n_rhs: int, fmm_order: int,
     return None
 
 
-def cpu_baseline(prob, sigma, budget_s: float = 15.0):
-    """The oracle's apply on sampled rows (near blocks precomputed per row, as on the GPU)."""
+def cpu_baseline(prob, sigma, budget_s: float, checks: dict):
+    """The CPU leg: the only part of this script that runs the oracle.  It checks the GPU results
+    kept in `checks` on sampled rows (apply error, solve residuals, representation) and then times
+    the oracle's apply on sampled rows (near blocks precomputed per row, as on the GPU).  Returns
+    (cpu_baseline record, check results)."""
     from threadpoolctl import threadpool_limits
     from oracle.operator import OracleOperator
+    orc = OracleOperator.from_problem(prob)
+    N = prob.n
+    rng = np.random.default_rng(5)
+    tg = np.concatenate([[0, N - 1], rng.choice(N, 10, replace=False)])
+    res = {}
+    # apply error of each path's y for the benchmark density
+    ref = orc.apply_rows(tg, sigma)
+    scale = np.abs(ref).max()
+    res["apply_rel_err_vs_oracle"] = {k: float(np.abs(v[tg] - ref).max() / scale) for k, v in checks["y"].items()}
+    log(f"[bench] sampled-row apply error vs oracle: {res['apply_rel_err_vs_oracle']}")
+    # residual of each returned density in the oracle's discrete system
+    f_rows = prob.f[tg] - (prob.f * orc.w[:, None]).sum(0) / orc.w.sum()   # mean-zero data at the rows
+    res["solve_rows"] = {}
+    for path, s_h in checks["sigma"].items():
+        r_rows = f_rows - orc.apply_rows(tg, s_h)
+        res["solve_rows"][path] = float(np.abs(r_rows).max() / np.abs(f_rows).max())
+    log(f"[bench] sampled-row relative residual of the solves: {res['solve_rows']}")
+    # representation: the GPU rows differ from the oracle's rows before the mean is removed by one
+    # constant per right-hand side (the weighted mean), so the spread of the differences is the
+    # error, relative to the spread of the oracle rows
+    if checks.get("u") is not None:
+        u_h, s_h = checks["u"], checks["sigma"]["mixed"]
+        ref_u = orc.represent_rows(tg, s_h)
+        d = u_h[tg] - ref_u
+        res["representation"] = {
+            "rows_rel_err_vs_oracle": float(np.abs(d - d.mean(0)).max() / np.abs(ref_u - ref_u.mean(0)).max()),
+            "weighted_mean_rel": float(np.abs(orc.w @ u_h).max() / orc.w.sum() / np.abs(u_h).max())}
+        log(f"[bench] representation vs oracle rows: {res['representation']}")
     with threadpool_limits(limits=1):
-        orc = OracleOperator.from_problem(prob)
         rng = np.random.default_rng(7)
         rows, t_apply, t_setup = 0, 0.0, 0.0
         t_start = time.perf_counter()
@@ -126,7 +178,7 @@ def cpu_baseline(prob, sigma, budget_s: float = 15.0):
     return {"value": rows / t_apply / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
             "sample": f"{rows} random target rows of the {prob.n}-node apply (far sum over all sources + "
                       f"precomputed near blocks), numpy FP64, 1 thread; near-block setup "
-                      f"{t_setup / rows * 1e3:.1f} ms/row timed separately"}
+                      f"{t_setup / rows * 1e3:.1f} ms/row timed separately"}, res
 
 
 def serving(ctx, n_req: int, slots: int):
@@ -380,19 +432,11 @@ def main():
         op.apply(sig_host, prec[args.path])
     host_s = (time.perf_counter() - th0) / 5
 
-    # apply error against the oracle on sampled rows
-    from oracle.operator import OracleOperator
-    orc = OracleOperator.from_problem(prob)
-    rng = np.random.default_rng(5)
-    tg = np.concatenate([[0, N - 1], rng.choice(N, 10, replace=False)])
-    ref = orc.apply_rows(tg, sig_h)
-    f_rows = prob.f[tg] - (prob.f * orc.w[:, None]).sum(0) / orc.w.sum()   # mean-zero data at the rows
-    scale = np.abs(ref).max()
-    ys = {args.path: y_main, other: y_other} if y_other is not None else {args.path: y_main}
-    err = {k: float(np.abs(v[tg] - ref).max() / scale) for k, v in ys.items()}
-    log(f"[bench] sampled-row apply error vs oracle: {err}")
-
+    # GPU results that the CPU leg checks against the oracle on sampled rows
+    checks = {"y": {args.path: y_main, other: y_other} if y_other is not None else {args.path: y_main},
+              "sigma": {}, "u": None}
     solve = {}
+    representation = None
     if not args.no_solve:
         f = torch.tensor(np.ascontiguousarray(prob.f.T), device="cuda:0")
         for path in ("mixed", "fp64"):
@@ -414,17 +458,18 @@ def main():
                 continue
             torch.cuda.synchronize()
             dt = time.perf_counter() - ts
-            # residual of the returned density in the oracle's discrete system, on the sampled rows
-            s_h = s_out.T if isinstance(s_out, np.ndarray) else s_out.cpu().numpy().T
-            r_rows = f_rows - orc.apply_rows(tg, s_h)
+            checks["sigma"][path] = s_out.T if isinstance(s_out, np.ndarray) else s_out.cpu().numpy().T.copy()
+            if path == "mixed":
+                s_mixed = s_out
             solve[path] = {"seconds": round(dt, 4), "iters": max(i.iters_total for i in info),
                            "ir_steps": max(i.ir_steps for i in info),
                            "applies_fp64": info[0].applies_fp64, "applies_fp32": info[0].applies_low,
                            "rel_residual": max(i.rel_residual for i in info),
-                           "oracle_rows_rel_residual": float(np.abs(r_rows).max() / np.abs(f_rows).max())}
+                           "oracle_rows_rel_residual": None}
             log(f"[bench] solve {path}: {dt:.3f} s {solve[path]}")
         if "mixed" in solve:
             solve["solves_per_s_mixed"] = round(1.0 / solve["mixed"]["seconds"], 3)
+            representation, checks["u"] = measure_representation(op, s_mixed, N, n_rhs)
 
     value = N * n_rhs / step_s / 1e9
     out = {
@@ -438,8 +483,9 @@ def main():
         "other_path": ({"path": other, "gpts_per_s": round(N * n_rhs / other_s / 1e9, 4),
                         "ms_per_apply": round(other_s * 1e3, 4)} if other_s else None),
         "one_stream": one_stream,
-        "apply_rel_err_vs_oracle": err,
+        "apply_rel_err_vs_oracle": None,
         "solve_to_1e-8": solve,
+        "representation": representation,
         "setup_s": round(t_setup, 3),
         "kernels": kernels,
         "host_buffers_gpts_per_s": round(N * n_rhs / host_s / 1e9, 4),
@@ -451,8 +497,13 @@ def main():
     if args.serve:
         out["serving"] = serving(ctx, args.serve, args.serve_slots)
     if not args.no_cpu:
-        log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(prob, sig_h, args.cpu_budget)
+        log("[bench] cpu leg: oracle checks on sampled rows and the oracle's own rate ...")
+        out["cpu_baseline"], res = cpu_baseline(prob, sig_h, args.cpu_budget, checks)
+        out["apply_rel_err_vs_oracle"] = res["apply_rel_err_vs_oracle"]
+        for path, r in res["solve_rows"].items():
+            solve[path]["oracle_rows_rel_residual"] = r
+        if representation is not None:
+            representation.update(res["representation"])
     print(json.dumps(out), flush=True)
 
 

@@ -177,11 +177,14 @@ __global__ void __launch_bounds__(kBlock) k_direct_log(int64_t N, const double* 
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+#pragma unroll 4
   for (int64_t j = j0; j < j1; ++j) {
     const sdp row = S + j * RL;
     const double dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const double v = j == i ? 0.0 : 0.5 * log(r2) * 0.15915494309189533577;
+    // log(r) / (2 pi) = log(r^2) / (4 pi).  The self pair (r2 = 0: zero mantissa) gives a finite
+    // value that a zero factor drops; computing it keeps the loop free of branches
+    const double v = log_pair(r2) * (j == i ? 0.0 : 0.07957747154594766788);
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = fma(row[3 + r], v, acc[r]);
   }

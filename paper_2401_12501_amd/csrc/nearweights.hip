@@ -158,7 +158,7 @@ __device__ inline double remainder_dev(const Target& T, const double* y, double 
 __device__ inline double parametrix_dev(const Target& T, const double* y, double inv_as) {
   const double r0 = T.x[0] - y[0], r1 = T.x[1] - y[1], r2 = T.x[2] - y[2];
   const double rr = r0 * r0 + r1 * r1 + r2 * r2;
-  return 0.5 * log(rr) * 0.15915494309189533577 * inv_as;
+  return log_pair(rr) * 0.07957747154594766788 * inv_as;   // log(r) / (2 pi a)
 }
 
 union Cell {                    // self: angular panel [p0, p1] of one edge; near: leaf (depth, iu, iv)

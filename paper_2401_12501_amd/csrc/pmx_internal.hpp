@@ -178,6 +178,40 @@ __device__ __forceinline__ const A& seg_of(const Group<A>& g, int64_t b, int64_t
   return g.a[s];
 }
 
+// Natural logarithm of a positive normal x (log-kernel sums and quadrature), from the artanh series: with
+// x = 2^e m, m in [sqrt(1/2), sqrt(2)) (hardware frexp), log x = e ln 2 + 2 artanh(s) where
+// s = (m - 1) / (m + 1), |s| <= 0.1716, and artanh(s) = sum_k s^(2k+1) / (2k+1) (Taylor series).
+// Ten terms (through s^19 / 19) leave a truncation error below 1e-17; the reciprocal takes two
+// Newton steps, and e ln 2 is one rounding (|e| <= 60 here: error below 3e-15 absolute, about one
+// ulp of the result).  About 30 FP64 instructions, against about 90 for the library's log, whose
+// extra precision the sums and quadratures do not need.
+__device__ __forceinline__ double log_pair(double x) {
+  constexpr double kSqrtHalf = 0.70710678118654752440;
+  constexpr double kLn2 = 0.69314718055994530942;
+  double m = __builtin_amdgcn_frexp_mant(x);      // [0.5, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  const bool lo = m < kSqrtHalf;
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
+  const double d = m + 1.0;
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  const double sv = (m - 1.0) * r;
+  const double s2 = sv * sv;
+  double p = 1.0 / 19.0;
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  p = fma(p, s2, 1.0);
+  return fma((double)e, kLn2, 2.0 * sv * p);
+}
+
 // Launch `fn(group, total_blocks)` for the records in chunks of kMaxSeg; segments
 // with no blocks are left out.
 template <class A, class F>

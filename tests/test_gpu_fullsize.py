@@ -1,5 +1,6 @@
-"""Full-size workloads on sampled outputs: the star (8,214 patches, q = 8, 525,696 nodes)
-and the wobbly torus (256 x 128 patches, q = 8, 2,097,152 nodes, 16 right-hand sides).
+"""Full-size workloads on sampled outputs: the star (8,214 patches, q = 8, 525,696 nodes;
+apply, mixed solve and representation) and the wobbly torus (256 x 128 patches, q = 8,
+2,097,152 nodes, 16 right-hand sides).
 
 The oracle evaluates single rows of the operator (near blocks and the far sum over all
 sources) at seeded random targets; the GPU applies the whole operator in the launch
@@ -72,6 +73,18 @@ def test_star_full(ctx):
     say(f"[fullsize] star mixed solve: ir {info[0].ir_steps}, inner iters {info[0].iters_total}, "
         f"residual {info[0].rel_residual:.2e}, oracle-row residual {rel:.2e}")
     assert info[0].rel_residual <= 1e-8 and rel <= 1e-7
+    # representation u = K[sigma] of that solution (FP64 log-kernel direct sum plus the parametrix
+    # near blocks D), mean removed.  The oracle's rows come before the mean is removed, so the GPU
+    # rows differ from them by one constant: the spread of the differences is the error.  FP64
+    # throughout; the small-case bar (weighted over all nodes) is 1e-12, the max over sampled rows
+    # gets 10x that.
+    u = op.represent(np.ascontiguousarray(sig)).T
+    ref_u = orc.represent_rows(tg, sig.T)
+    d = u[tg] - ref_u
+    err_u = np.abs(d - d.mean(0)).max() / np.abs(ref_u - ref_u.mean(0)).max()
+    mean_u = abs(float(orc.w @ u[:, 0])) / orc.w.sum() / np.abs(u).max()
+    say(f"[fullsize] star representation: sampled-row error {err_u:.2e}, weighted mean {mean_u:.1e}")
+    assert err_u <= 1e-11 and mean_u <= 1e-12
 
 
 def test_wobbly_torus_full_16rhs(ctx):
