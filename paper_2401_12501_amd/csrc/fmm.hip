@@ -307,8 +307,9 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
   }
 }
 
-// M2L on MFMA.  One workgroup per work item: up to 32 box pairs (two MFMA column
-// tiles) whose sources sit at the same offset (in box widths).  By homogeneity the
+// M2L on MFMA.  Work items of up to 32 box pairs (two MFMA column tiles) whose sources
+// sit at the same offset (in box widths); a persistent grid of one workgroup per compute
+// unit takes the items in turn.  By homogeneity the
 // unit-box kernel of an offset is the same at every level, so an item may mix levels;
 // each column is scaled by its level's h^-1 (F1) or h^-2 (F2) when written.  The
 // item's source multipoles are staged in LDS once; each wave takes one 16-row tile,
