@@ -314,7 +314,8 @@ def main():
         opts.overlap = 0
     op = pmx.Operator(surf, prob.a, prob.grad_a, opts)
     t_setup = time.perf_counter() - t0
-    prec = {"mixed": pmx.PMX_PREC_MIXED_FMM, "fp64": pmx.PMX_PREC_FP64_DIRECT}
+    prec = {"mixed": pmx.PMX_PREC_MIXED_FMM, "fp64": pmx.PMX_PREC_FP64_DIRECT,
+            "fp32_direct": pmx.PMX_PREC_FP32_DIRECT}
     other = "fp64" if args.path == "mixed" else "mixed"
     sig_h = random_density(N, n_rhs, seed=3)
     sig = torch.tensor(np.ascontiguousarray(sig_h.T), device="cuda:0")
@@ -351,6 +352,19 @@ def main():
     except pmx.PmxError as e:
         log(f"[bench] {other} path unavailable: {e}")
         other_s, y_other, other_phases = None, None, {}
+    # the optional FP32 direct far field (same pair kernel as the FP64 path, in FP32)
+    try:
+        d32_s, _ = timed("fp32_direct", max(3, args.steps // 4), 1, False)
+        y_d32 = y.cpu().numpy().T.copy()
+        d32_tf = float(N) * (N - 1) * (24 + 2 * n_rhs) / d32_s / 1e12
+        fp32_direct = {"ms_per_apply": round(d32_s * 1e3, 4), "gpts_per_s": round(N * n_rhs / d32_s / 1e9, 4),
+                       "achieved": round(d32_tf, 3), "unit": "TFLOP/s", "peak": PEAK["fp32_valu"],
+                       "frac": round(d32_tf / PEAK["fp32_valu"], 4),
+                       "note": "pair flops over the whole apply time (the FP64 near correction included)"}
+        log(f"[bench] fp32 direct: {fp32_direct}")
+    except pmx.PmxError as e:
+        log(f"[bench] fp32 direct path unavailable: {e}")
+        fp32_direct, y_d32 = None, None
 
     st = op.stats()
     # the same mixed apply with every kernel on one stream (operator option overlap = 0): the
@@ -435,6 +449,8 @@ def main():
     # GPU results that the CPU leg checks against the oracle on sampled rows
     checks = {"y": {args.path: y_main, other: y_other} if y_other is not None else {args.path: y_main},
               "sigma": {}, "u": None}
+    if y_d32 is not None:
+        checks["y"]["fp32_direct"] = y_d32
     solve = {}
     representation = None
     if not args.no_solve:
@@ -483,6 +499,7 @@ def main():
         "other_path": ({"path": other, "gpts_per_s": round(N * n_rhs / other_s / 1e9, 4),
                         "ms_per_apply": round(other_s * 1e3, 4)} if other_s else None),
         "one_stream": one_stream,
+        "fp32_direct": fp32_direct,
         "apply_rel_err_vs_oracle": None,
         "solve_to_1e-8": solve,
         "representation": representation,
