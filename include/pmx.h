@@ -26,6 +26,9 @@
  *  - stream: a hipStream_t (may be NULL = the null stream).  All device work
  *    of a call is enqueued on it; calls with host outputs return after the
  *    results are copied out.
+ *  - Threads: calls on one operator (or one server) must not overlap; calls on
+ *    different operators may run at once from different threads, on their own
+ *    streams.  Contexts and surfaces may be shared by such threads.
  *  - Node order: node i = P*q*q + iu*q + iv sits at the Gauss-Legendre pair
  *    (t_iu, t_iv) of patch P on [-1,1]^2.  Arrays of 3-vectors are row-major
  *    N x 3.  Multi-RHS arrays are n_rhs contiguous vectors of length N
