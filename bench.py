@@ -181,11 +181,11 @@ def cpu_baseline(prob, sigma, budget_s: float, checks: dict):
                       f"{t_setup / rows * 1e3:.1f} ms/row timed separately"}, res
 
 
-def serving(ctx, n_req: int, slots: int):
+def serving(ctx, n_req: int, slots: int, load: float = 0.7):
     """Serving workload: requests from the sphere / random-axis ellipsoid / torus families with
     2e3..2e5 nodes (log-uniform), mixed path, memory-admitted.  The first quarter of the requests,
     submitted at once, measures the saturated rate mu; the rest arrive as a Poisson stream at
-    0.7 mu.  Latency = submit -> result ready (server clock)."""
+    load * mu (0.7 by default).  Latency = submit -> result ready (server clock)."""
     from paper_2401_12501_amd import pmx
     from paper_2401_12501_amd.inputs import serving_requests
     log(f"[serve] generating {n_req} requests ...")
@@ -212,7 +212,7 @@ def serving(ctx, n_req: int, slots: int):
         drain(out, lat_cal, st_cal)
         time.sleep(0.001)
     mu = n_cal / (time.perf_counter() - t0)
-    lam = 0.7 * mu
+    lam = load * mu
     rng = np.random.default_rng(33)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req - n_cal))
     lat, status = [], []
@@ -232,7 +232,7 @@ def serving(ctx, n_req: int, slots: int):
     sv.close()
     lat = np.array(lat)
     res = {"requests": n_req, "calibration_requests": n_cal, "slots": slots,
-           "saturated_solves_per_s": round(mu, 3), "arrival_rate_per_s": round(lam, 3),
+           "saturated_solves_per_s": round(mu, 3), "load": load, "arrival_rate_per_s": round(lam, 3),
            "solves_per_s": round(len(lat) / wall, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
            "ok": int(sum(1 for s in status + st_cal if s == 0)),
@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--serve", type=int, default=64,
                     help="serving requests to run (0: skip); the first quarter calibrates the saturated rate")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="serving: Poisson arrival rate as a fraction of the measured saturated rate")
     ap.add_argument("--calib-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size kernel for traffic counters)")
     args = ap.parse_args()
@@ -512,7 +514,7 @@ def main():
         "near_pairs": st.near_pairs,
     }
     if args.serve:
-        out["serving"] = serving(ctx, args.serve, args.serve_slots)
+        out["serving"] = serving(ctx, args.serve, args.serve_slots, args.serve_load)
     if not args.no_cpu:
         log("[bench] cpu leg: oracle checks on sampled rows and the oracle's own rate ...")
         out["cpu_baseline"], res = cpu_baseline(prob, sig_h, args.cpu_budget, checks)
