@@ -167,11 +167,12 @@ def test_fmm_vs_oracle_sphere(ctx):
 
 
 def test_mixed_solve_full_ellipsoid(ctx):
-    """Ellipsoid workload at full size (153,600 nodes): the mixed path reaches a 1e-8
-    relative residual of the FP64 operator and agrees with the FP64-path solution."""
+    """Ellipsoid workload at full size (153,600 nodes), with the library's default FMM leaf target
+    (the benchmark's configuration): the mixed path reaches a 1e-8 relative residual of the FP64
+    operator and agrees with the FP64-path solution."""
     from paper_2401_12501_amd import pmx
     p = ellipsoid_problem()
-    surf, op = make(ctx, p)
+    surf, op = make(ctx, p, leaf=pmx.pmx_default_options().fmm_leaf)
     f = np.ascontiguousarray(p.f.T)
     o = pmx.pmx_default_options()
     o.precision = pmx.PMX_PREC_MIXED_FMM
