@@ -192,6 +192,66 @@ __global__ void __launch_bounds__(256) k_p2m(Group<P2MArgs> g) {
   if (m < p3) W[box * p3 + m] = acc;
 }
 
+// P2M for a block of 16 right-hand sides: as k_p2m (one block per leaf, thread m per
+// coefficient), with the sources' rows of the block (x, y, z, q_0 .. q_15): each source's
+// Chebyshev basis product is formed once and applied to its 16 charges.  Every right-hand
+// side's sum takes the same operations in the same order as k_p2m, so W16 holds the same bits.
+struct P2M16Args {
+  int64_t leaf_off;
+  float h;
+  int stride;             // source row length (x, y, z and the 16 charges first)
+  const float* tab;
+  const float* center;
+  const int32_t* leaf_start;
+  const float* qsR;
+  float* W16;
+  int64_t slice;          // floats between right-hand-side slices of W16
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) k_p2m16(Group<P2M16Args> g) {
+  constexpr int p = P, p3 = P * P * P;
+  constexpr int kW = 3 * P + kRBlock + 1;   // basis values, charges, one pad (odd row length)
+  __shared__ float sw[256][kW];
+  int64_t lb;
+  const P2M16Args& A = seg_of(g, blockIdx.x, lb);
+  const float* __restrict__ tab = A.tab;
+  const int leaf = (int)lb;
+  const int64_t box = A.leaf_off + leaf;
+  const int s0 = A.leaf_start[leaf], s1 = A.leaf_start[leaf + 1];
+  const float cx = A.center[3 * box], cy = A.center[3 * box + 1], cz = A.center[3 * box + 2];
+  const float ih = 1.0f / A.h;
+  const int m = threadIdx.x;
+  const int m1 = m / (p * p), m2 = (m / p) % p, m3 = m % p;
+  float acc[kRBlock];
+#pragma unroll
+  for (int r = 0; r < kRBlock; ++r) acc[r] = 0.0f;
+  for (int j0 = s0; j0 < s1; j0 += 256) {
+    const int j = j0 + threadIdx.x;
+    __syncthreads();
+    if (j < s1) {
+      const float* __restrict__ row = A.qsR + (int64_t)j * A.stride;
+      cheb_weights<P>(tab, (row[0] - cx) * ih, &sw[threadIdx.x][0]);
+      cheb_weights<P>(tab, (row[1] - cy) * ih, &sw[threadIdx.x][p]);
+      cheb_weights<P>(tab, (row[2] - cz) * ih, &sw[threadIdx.x][2 * p]);
+#pragma unroll
+      for (int r = 0; r < kRBlock; ++r) sw[threadIdx.x][3 * p + r] = row[3 + r];
+    }
+    __syncthreads();
+    const int lim = min(256, s1 - j0);
+    if (m < p3)
+      for (int t = 0; t < lim; ++t) {
+        const float b = sw[t][m1] * sw[t][p + m2] * sw[t][2 * p + m3];
+#pragma unroll
+        for (int r = 0; r < kRBlock; ++r) acc[r] = fmaf(b, sw[t][3 * p + r], acc[r]);
+      }
+  }
+  if (m < p3) {
+#pragma unroll
+    for (int r = 0; r < kRBlock; ++r) A.W16[r * A.slice + box * p3 + m] = acc[r];
+  }
+}
+
 // M2M: parent W from its children (one block per parent box of one level).
 struct M2MArgs {
   int64_t lev_first;
@@ -200,6 +260,7 @@ struct M2MArgs {
   const int32_t* child_end;
   const int32_t* octant;
   float* W;
+  int64_t slice;          // floats between right-hand-side slices of W (grid y), 0 for one
 };
 
 // The interpolation operator is a tensor product, so each child's contribution is
@@ -214,11 +275,12 @@ __global__ void __launch_bounds__(256) k_m2m(Group<M2MArgs> g) {
   __shared__ int sOct[8];
   int64_t lb;
   const M2MArgs& A = seg_of(g, blockIdx.x, lb);
+  float* __restrict__ W = A.W + (int64_t)blockIdx.y * A.slice;
   const int64_t Pb = A.lev_first + lb;
   const int c0 = A.child_begin[Pb], nch = A.child_end[Pb] - c0;   // at most 8 children
   for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) sM[e] = A.tab[p + e];   // M1[b][k][k']
   if (threadIdx.x < nch) sOct[threadIdx.x] = A.octant[c0 + threadIdx.x];
-  for (int e = threadIdx.x; e < nch * p3; e += blockDim.x) sW[e] = A.W[(int64_t)c0 * p3 + e];
+  for (int e = threadIdx.x; e < nch * p3; e += blockDim.x) sW[e] = W[(int64_t)c0 * p3 + e];
   __syncthreads();
   // z: T[c][a][b][m3] = sum_d Mz_c[m3][d] W[c][a][b][d]
   for (int e = threadIdx.x; e < nch * p3; e += blockDim.x) {
@@ -250,7 +312,7 @@ __global__ void __launch_bounds__(256) k_m2m(Group<M2MArgs> g) {
       for (int aa = 0; aa < p; ++aa) t = fmaf(Mx[i1 * p + aa], sW[ch * p3 + (aa * p + i2) * p + i3], t);
       acc += t;
     }
-    A.W[Pb * p3 + m] = acc;
+    W[Pb * p3 + m] = acc;
   }
 }
 
@@ -261,6 +323,7 @@ struct L2LArgs {
   const int32_t* parent;
   const int32_t* octant;
   float* Lc;
+  int64_t slice;          // floats between right-hand-side slices of Lc (grid y), 0 for one
 };
 
 // Child L += the parent's L interpolated to the child, one axis at a time through LDS
@@ -273,11 +336,12 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
   __shared__ float sM[2 * p * p];
   int64_t lb;
   const L2LArgs& A = seg_of(g, blockIdx.x, lb);
+  float* __restrict__ Lc = A.Lc + (int64_t)blockIdx.y * A.slice;
   const int64_t C = A.lev_first + lb;
   const int64_t Pb = A.parent[C];
   const int o = A.octant[C];
   for (int e = threadIdx.x; e < 2 * p * p; e += blockDim.x) sM[e] = A.tab[p + e];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) sA[e] = A.Lc[Pb * lstride<P>() + e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) sA[e] = Lc[Pb * lstride<P>() + e];
   __syncthreads();
   const float* Mx = sM + (o & 1) * p * p;          // Mx[a * p + l1] = S1(t_a, child node l1)
   const float* My = sM + ((o >> 1) & 1) * p * p;
@@ -303,7 +367,7 @@ __global__ void __launch_bounds__(256) k_l2l(Group<L2LArgs> g) {
     const int l23 = e % (p * p), l1 = (e / (p * p)) % p, cc = e / p3;
     float t = 0.0f;
     for (int aa = 0; aa < p; ++aa) t = fmaf(Mx[aa * p + l1], sA[cc * p3 + aa * p * p + l23], t);
-    A.Lc[C * lstride<P>() + e] += t;
+    Lc[C * lstride<P>() + e] += t;
   }
 }
 
@@ -1448,9 +1512,9 @@ static void fmm_far_rhs(const std::vector<ApplyJob>& jobs, int r, int n_rhs, Pro
   (void)n;
 }
 
-// A block of 16 right-hand sides [rb, rb + 16): upward passes per right-hand side into the
-// multipole slices, one M2L launch for all 16 (k_m2l16), then the downward passes per
-// right-hand side.  The multi-charge P2P of the block runs on the side stream as in the
+// A block of 16 right-hand sides [rb, rb + 16): the upward passes for all 16 at once (P2M
+// from the block's source rows, M2M with the slices along grid y) into the multipole slices,
+// one M2L launch for all 16 (k_m2l16), L2L for all 16, then L2P per right-hand side.  The multi-charge P2P of the block runs on the side stream as in the
 // per-rhs path, joined before the first L2P.
 template <int P>
 static void fmm_far_block16(const std::vector<ApplyJob>& jobs, int rb, Profiler* prof, hipStream_t st,
@@ -1497,49 +1561,41 @@ static void fmm_far_block16(const std::vector<ApplyJob>& jobs, int rb, Profiler*
     if (prof) prof->end(tp, side);
     if (side != st) PMX_HIP(hipEventRecord(ev_join, side));
   }
-  // upward passes, one right-hand side at a time, into the multipole slices
+  // upward passes for the 16 right-hand sides together, into the multipole slices: P2M from
+  // the block's source rows (built above), then M2M per level with the slices along grid y
   int t = phase(PMX_PHASE_FMM_P2M);
-  for (int j = 0; j < kRBlock; ++j) {
-    std::vector<PermArgs> pa;
-    std::vector<P2MArgs> ma;
-    std::vector<int64_t> pb, mb;
+  {
+    std::vector<P2M16Args> ma;
+    std::vector<int64_t> mb;
     for (pmx_operator* op : ops) {
       FMM* F = op->fmm;
-      const int64_t N = op->s->g.N;
-      float* Wj = F->W16.p + (int64_t)j * F->n_boxes * p3;
-      pa.push_back({N, F->perm.p, F->pts.p, op->qt32.p + (int64_t)(rb + j) * N, F->qs.p});
-      pb.push_back((N + 255) / 256);
       const float hL = (float)(F->h0 / (double)(1 << F->L));
-      ma.push_back({F->lev_off[F->L], N, hL, F->tab.p, F->center.p, F->leaf_start.p, F->pts.p, F->qs.p, Wj});
+      ma.push_back({F->lev_off[F->L], hL, F->rstride, F->tab.p, F->center.p, F->leaf_start.p, F->qsR.p, F->W16.p,
+                    F->n_boxes * (int64_t)p3});
       mb.push_back(F->n_leaves);
     }
-    launch_grouped(pa, pb, [&](const Group<PermArgs>& g, int64_t nb) {
-      hipLaunchKernelGGL(k_permute, dim3((unsigned)nb), dim3(256), 0, st, g);
-      PMX_HIP(hipGetLastError());
-    });
-    launch_grouped(ma, mb, [&](const Group<P2MArgs>& g, int64_t nb) {
-      hipLaunchKernelGGL(k_p2m<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
+    launch_grouped(ma, mb, [&](const Group<P2M16Args>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_p2m16<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
       PMX_HIP(hipGetLastError());
     });
   }
   done(t);
   t = phase(PMX_PHASE_FMM_M2M);
-  for (int j = 0; j < kRBlock; ++j)
-    for (int l = maxL - 1; l >= 2; --l) {
-      std::vector<M2MArgs> ma;
-      std::vector<int64_t> mb;
-      for (pmx_operator* op : ops) {
-        FMM* F = op->fmm;
-        if (l >= F->L) continue;
-        ma.push_back({F->lev_off[l], F->tab.p, F->child_begin.p, F->child_end.p, F->octant.p,
-                      F->W16.p + (int64_t)j * F->n_boxes * p3});
-        mb.push_back(F->lev_off[l + 1] - F->lev_off[l]);
-      }
-      launch_grouped(ma, mb, [&](const Group<M2MArgs>& g, int64_t nb) {
-        hipLaunchKernelGGL(k_m2m<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
-        PMX_HIP(hipGetLastError());
-      });
+  for (int l = maxL - 1; l >= 2; --l) {
+    std::vector<M2MArgs> ma;
+    std::vector<int64_t> mb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      if (l >= F->L) continue;
+      ma.push_back({F->lev_off[l], F->tab.p, F->child_begin.p, F->child_end.p, F->octant.p, F->W16.p,
+                    F->n_boxes * (int64_t)p3});
+      mb.push_back(F->lev_off[l + 1] - F->lev_off[l]);
     }
+    launch_grouped(ma, mb, [&](const Group<M2MArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_m2m<P>, dim3((unsigned)nb, (unsigned)kRBlock), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
   done(t);
   t = phase(PMX_PHASE_FMM_M2L);
   {
@@ -1559,22 +1615,21 @@ static void fmm_far_block16(const std::vector<ApplyJob>& jobs, int rb, Profiler*
   }
   done(t);
   t = phase(PMX_PHASE_FMM_L2L);
-  for (int j = 0; j < kRBlock; ++j)
-    for (int l = 3; l <= maxL; ++l) {
-      std::vector<L2LArgs> la;
-      std::vector<int64_t> lb;
-      for (pmx_operator* op : ops) {
-        FMM* F = op->fmm;
-        if (l > F->L) continue;
-        la.push_back({F->lev_off[l], F->tab.p, F->parent.p, F->octant.p,
-                      F->L16.p + (int64_t)j * F->n_boxes * lstride<P>()});
-        lb.push_back(F->lev_off[l + 1] - F->lev_off[l]);
-      }
-      launch_grouped(la, lb, [&](const Group<L2LArgs>& g, int64_t nb) {
-        hipLaunchKernelGGL(k_l2l<P>, dim3((unsigned)nb), dim3(256), 0, st, g);
-        PMX_HIP(hipGetLastError());
-      });
+  for (int l = 3; l <= maxL; ++l) {   // the 16 right-hand sides' slices along grid y
+    std::vector<L2LArgs> la;
+    std::vector<int64_t> lb;
+    for (pmx_operator* op : ops) {
+      FMM* F = op->fmm;
+      if (l > F->L) continue;
+      la.push_back({F->lev_off[l], F->tab.p, F->parent.p, F->octant.p, F->L16.p,
+                    F->n_boxes * (int64_t)lstride<P>()});
+      lb.push_back(F->lev_off[l + 1] - F->lev_off[l]);
     }
+    launch_grouped(la, lb, [&](const Group<L2LArgs>& g, int64_t nb) {
+      hipLaunchKernelGGL(k_l2l<P>, dim3((unsigned)nb, (unsigned)kRBlock), dim3(256), 0, st, g);
+      PMX_HIP(hipGetLastError());
+    });
+  }
   done(t);
   if (side != st) PMX_HIP(hipStreamWaitEvent(st, ev_join, 0));   // P2P sums and the near part of y
   t = phase(PMX_PHASE_FMM_L2P);
