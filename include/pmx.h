@@ -158,6 +158,25 @@ PMX_API pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* 
 PMX_API pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const double* sigma, double* y, int mem_kind,
                      void* stream);
 
+/* Allocation-free y = A sigma with the FP64 direct far field: the same result, bit for bit,
+ * as pmx_apply(op, PMX_PREC_FP64_DIRECT, n_rhs, sigma, y, PMX_MEM_DEVICE, stream).
+ * For callers that cannot allocate device memory: code under HIP graph capture, serving loops
+ * and harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or allocating library
+ * routine and does not synchronize; its scratch (source strengths, packed source rows, partial
+ * sums) lives in one static device array of PMX_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds until the process ends.  Every buffer of that scratch is written before it is
+ * read, so nothing needs clearing between calls, and results do not depend on earlier calls.
+ * Calls that overlap on one GPU (from two threads, or on two streams) share the array and race:
+ * the caller must order them.  sigma and y: device arrays of the operator's GPU, n_rhs rows of
+ * N doubles; the operator must be a fully built one (pmx_operator_create returned OK).
+ * Scratch needed: about 8 (n_rhs (N (1 + c) + N / 256) + N (3 + g + 1)) bytes, with c the
+ * direct sum's source chunks (between 1 and 64: 7 for 153,600 nodes, 1 from 1,048,576) and g the
+ * largest right-hand-side group (1, 2, 4, 8 or 16); for example up to 4 densities at 153,600 nodes.
+ * Errors: INVALID (null or host arrays, n_rhs out of range), TOO_LARGE (scratch above the
+ * maximum), DEVICE. */
+#define PMX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+PMX_API pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, double* y, void* stream);
+
 /* Solve A sigma = f - mean_w(f) for n_rhs right-hand sides.  opts->precision (or the
  * operator's options when opts is NULL) selects GMRES on A64 (FP64 path) or iterative
  * refinement with residuals on A64 and inner GMRES on A32 (mixed path).  sigma: in =

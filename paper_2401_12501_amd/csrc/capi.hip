@@ -132,6 +132,59 @@ using namespace pmx;
 
 namespace {
 
+// ----------------------------------------------------------------------------- static scratch
+// Scratch of the allocation-free apply: one array per GPU the library runs on, held until the
+// process ends.  Host code never uses the array's name as an address (on the host it is only a
+// stand-in for the symbol): its device address is looked up once per device, with that device
+// current, when a context is created there, and kept in g_scratch.
+constexpr size_t kScratchDoubles = (size_t)PMX_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Called with `device` current.  A failed lookup is kept and reported by the entry point, so
+// that contexts still work for every other call.
+void scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) {
+    g_scratch[device] = static_cast<double*>(ptr);
+    g_scratch_err[device] = hipSuccess;
+  } else {
+    g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    (void)hipGetLastError();   // do not leave the error for the next launch check
+  }
+}
+
+double* scratch_ptr(int device) {
+  PMX_REQUIRE(device >= 0 && device < kMaxDevices, PMX_ERR_INVALID, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device])
+    throw Error(PMX_ERR_DEVICE, std::string("static scratch address unavailable: ") +
+                                    hipGetErrorString(g_scratch_err[device] != hipSuccess ? g_scratch_err[device]
+                                                                                          : hipErrorInvalidSymbol));
+  return g_scratch[device];
+}
+
+// Requires p to be device memory (or managed memory) of `device`.
+void require_device_array(const void* p, int device, const char* what) {
+  hipPointerAttribute_t at;
+  const hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(PMX_ERR_INVALID, std::string(what) + " is not a device array");
+  }
+  PMX_REQUIRE(at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged, PMX_ERR_INVALID,
+              std::string(what) + " is not a device array");
+  PMX_REQUIRE(at.device == device, PMX_ERR_INVALID, std::string(what) + " lives on another device");
+}
+
 template <class F>
 pmx_status guarded(F&& f) {
   try {
@@ -204,6 +257,7 @@ pmx_status pmx_ctx_create(int device, uint64_t hbm_budget_bytes, pmx_ctx** out) 
     PMX_HIP(hipSetDevice(device));
     hipDeviceProp_t prop;
     PMX_HIP(hipGetDeviceProperties(&prop, device));
+    scratch_lookup(device);
     auto* c = new pmx_ctx;
     c->c.device = device;
     c->c.budget = hbm_budget_bytes;
@@ -330,6 +384,44 @@ pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const double* s
       PMX_HIP(hipMemcpyAsync(y, dy, n * sizeof(double), hipMemcpyDeviceToHost, st));
       PMX_HIP(hipStreamSynchronize(st));
     }
+  });
+}
+
+pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, double* y, void* stream) {
+  return guarded([&] {
+    PMX_REQUIRE(op && sigma && y, PMX_ERR_INVALID, "null argument");
+    PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    const int dev = op->s->ctx->c.device;
+    PMX_HIP(hipSetDevice(dev));
+    const int64_t N = op->s->g.N;
+    const size_t need = direct64_scratch_doubles(N, n_rhs);
+    if (need > kScratchDoubles)
+      throw Error(PMX_ERR_TOO_LARGE, "the allocation-free apply needs " + std::to_string(need * sizeof(double)) +
+                                         " bytes of scratch; the static scratch holds " +
+                                         std::to_string((size_t)PMX_NOALLOC_SCRATCH_BYTES));
+    require_device_array(sigma, dev, "sigma");
+    require_device_array(y, dev, "y");
+    double* base = scratch_ptr(dev);
+    // carve the buffers in the order and rounding direct64_scratch_doubles counts them
+    const size_t nr = (size_t)n_rhs, nb = (size_t)((N + 255) / 256);
+    auto up = [](size_t n) { return (n + 31) / 32 * 32; };
+    ApplyScratch sc;
+    size_t at = 0;
+    sc.qt64 = base + at;
+    at += up(nr * N);
+    sc.spart = base + at;
+    at += up(nr * nb);
+    sc.ssum = base + at;
+    at += up(nr);
+    const int g = n_rhs >= 16 ? 16 : (n_rhs >= 8 ? 8 : (n_rhs >= 4 ? 4 : (n_rhs >= 2 ? 2 : 1)));
+    sc.rows = base + at;
+    at += up((size_t)((3 + g + 1) / 2) * 2 * N);
+    sc.part = base + at;
+    hipStream_t st = (hipStream_t)stream;
+    const std::vector<ApplyJob> jobs{ApplyJob{op, sigma, y, &sc}};
+    source_prep_batch(jobs, n_rhs, false, st);
+    far_direct64_batch(jobs, n_rhs, st);
+    near_combine_batch(jobs, n_rhs, st);
   });
 }
 

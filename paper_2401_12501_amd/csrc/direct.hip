@@ -218,21 +218,27 @@ void pack_launch(const std::vector<PackArgs<T>>& recs, hipStream_t st) {
 }
 
 // FP64 remainder sums of one group of NR right-hand sides (from r0) for several operators.
+// Caller scratch (ApplyScratch) replaces the operator's buffers where given.
 template <int NR>
-void direct64_group(const std::vector<pmx_operator*>& ops, int n_rhs, int r0, hipStream_t st) {
+void direct64_group(const std::vector<pmx_operator*>& ops, const std::vector<const ApplyScratch*>& scs, int n_rhs,
+                    int r0, hipStream_t st) {
   constexpr int RL = row_len<NR, double>();
   constexpr int TPL = 1;   // one target per lane: more waves in flight beat reuse of a source row
   std::vector<PackArgs<double>> pk;
   std::vector<Direct64Args> da;
   std::vector<int64_t> nb;
-  for (pmx_operator* op : ops) {
+  for (size_t k = 0; k < ops.size(); ++k) {
+    pmx_operator* op = ops[k];
+    const ApplyScratch* sc = scs[k];
     const int64_t N = op->s->g.N;
     const int64_t nc = n_chunks_for(N);
-    if (op->rows64.n < (size_t)N * RL) op->rows64.alloc(&op->s->ctx->c, (size_t)N * RL);
-    pk.push_back({N, op->s->g.x.p, op->qt64.p + (int64_t)r0 * N, N, op->rows64.p});
+    if (!sc && op->rows64.n < (size_t)N * RL) op->rows64.alloc(&op->s->ctx->c, (size_t)N * RL);
+    double* rows = sc ? sc->rows : op->rows64.p;
+    const double* qt = sc ? sc->qt64 : op->qt64.p;
+    double* part = sc ? sc->part : op->part.p;
+    pk.push_back({N, op->s->g.x.p, qt + (int64_t)r0 * N, N, rows});
     const int64_t nbx = (N + TPL * kBlock - 1) / (TPL * kBlock);
-    da.push_back({N, (N + nc - 1) / nc, nbx, N, (int64_t)n_rhs * N, op->co.tf64.p, op->rows64.p,
-                  op->part.p + (int64_t)r0 * N});
+    da.push_back({N, (N + nc - 1) / nc, nbx, N, (int64_t)n_rhs * N, op->co.tf64.p, rows, part + (int64_t)r0 * N});
     nb.push_back(nbx * nc);
   }
   pack_launch<NR, double>(pk, st);
@@ -242,8 +248,11 @@ void direct64_group(const std::vector<pmx_operator*>& ops, int n_rhs, int r0, hi
   });
 }
 
-void direct64_all(const std::vector<pmx_operator*>& ops, int n_rhs, hipStream_t st) {
-  for (pmx_operator* op : ops) {
+void direct64_all(const std::vector<pmx_operator*>& ops, const std::vector<const ApplyScratch*>& scs, int n_rhs,
+                  hipStream_t st) {
+  for (size_t k = 0; k < ops.size(); ++k) {
+    if (scs[k]) continue;
+    pmx_operator* op = ops[k];
     const int64_t N = op->s->g.N;
     const size_t need = (size_t)n_chunks_for(N) * n_rhs * N;
     if (op->part.n < need) op->part.alloc(&op->s->ctx->c, need);
@@ -251,11 +260,11 @@ void direct64_all(const std::vector<pmx_operator*>& ops, int n_rhs, hipStream_t 
   int r0 = 0;
   while (r0 < n_rhs) {
     const int left = n_rhs - r0;
-    if (left >= 16) { direct64_group<16>(ops, n_rhs, r0, st); r0 += 16; }
-    else if (left >= 8) { direct64_group<8>(ops, n_rhs, r0, st); r0 += 8; }
-    else if (left >= 4) { direct64_group<4>(ops, n_rhs, r0, st); r0 += 4; }
-    else if (left >= 2) { direct64_group<2>(ops, n_rhs, r0, st); r0 += 2; }
-    else { direct64_group<1>(ops, n_rhs, r0, st); r0 += 1; }
+    if (left >= 16) { direct64_group<16>(ops, scs, n_rhs, r0, st); r0 += 16; }
+    else if (left >= 8) { direct64_group<8>(ops, scs, n_rhs, r0, st); r0 += 8; }
+    else if (left >= 4) { direct64_group<4>(ops, scs, n_rhs, r0, st); r0 += 4; }
+    else if (left >= 2) { direct64_group<2>(ops, scs, n_rhs, r0, st); r0 += 2; }
+    else { direct64_group<1>(ops, scs, n_rhs, r0, st); r0 += 1; }
   }
 }
 
@@ -285,7 +294,7 @@ void launch_group(pmx_operator* op, int mode, int n_rhs, int r0, int64_t nc, hip
 
 void far_direct_mode(pmx_operator* op, int mode, int n_rhs, hipStream_t st) {
   if (mode == 0) {
-    direct64_all({op}, n_rhs, st);
+    direct64_all({op}, {nullptr}, n_rhs, st);
     return;
   }
   const int64_t N = op->s->g.N;
@@ -310,8 +319,21 @@ void far_direct(pmx_operator* op, bool fp64, int n_rhs, hipStream_t st) { far_di
 
 void far_direct64_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
   std::vector<pmx_operator*> ops;
-  for (const ApplyJob& j : jobs) ops.push_back(j.op);
-  direct64_all(ops, n_rhs, st);
+  std::vector<const ApplyScratch*> scs;
+  for (const ApplyJob& j : jobs) {
+    ops.push_back(j.op);
+    scs.push_back(j.sc);
+  }
+  direct64_all(ops, scs, n_rhs, st);
+}
+
+size_t direct64_scratch_doubles(int64_t N, int n_rhs) {
+  auto up = [](size_t n) { return (n + 31) / 32 * 32; };
+  const size_t nr = (size_t)n_rhs;
+  const size_t nb = (size_t)((N + kBlock - 1) / kBlock);
+  const int g = n_rhs >= 16 ? 16 : (n_rhs >= 8 ? 8 : (n_rhs >= 4 ? 4 : (n_rhs >= 2 ? 2 : 1)));
+  const size_t rl = (size_t)((3 + g + 1) / 2) * 2;   // widest packed row of the groups used
+  return up(nr * N) + up(nr * nb) + up(nr) + up(rl * N) + up((size_t)n_chunks_for(N) * nr * N);
 }
 
 void far_direct_log(pmx_operator* op, int n_rhs, hipStream_t st) { far_direct_mode(op, 2, n_rhs, st); }

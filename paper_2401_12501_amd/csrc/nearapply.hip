@@ -335,12 +335,15 @@ void source_prep_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool need32
   std::vector<int64_t> pb, sb;
   for (const ApplyJob& j : jobs) {
     pmx_operator* op = j.op;
-    size_prep_buffers(op, n_rhs, need32);
+    PMX_REQUIRE(!(j.sc && need32), PMX_ERR_INVALID, "caller scratch serves the FP64 direct apply only");
+    if (!j.sc) size_prep_buffers(op, n_rhs, need32);
+    double* q64 = j.sc ? j.sc->qt64 : op->qt64.p;
+    double* spart = j.sc ? j.sc->spart : op->ssum_part.p;
+    double* ssum = j.sc ? j.sc->ssum : op->ssum.p;
     const int64_t N = op->s->g.N, nb = (N + kBlock - 1) / kBlock;
-    pa.push_back({N, nb, j.sigma, op->s->g.w.p, op->co.w_over_a.p, op->qt64.p, need32 ? op->qt32.p : nullptr,
-                  op->ssum_part.p});
+    pa.push_back({N, nb, j.sigma, op->s->g.w.p, op->co.w_over_a.p, q64, need32 ? op->qt32.p : nullptr, spart});
     pb.push_back(nb * n_rhs);
-    sa.push_back({nb, op->ssum_part.p, op->ssum.p});
+    sa.push_back({nb, spart, ssum});
     sb.push_back(n_rhs);
   }
   launch_grouped(pa, pb, [&](const Group<PrepArgs>& g, int64_t nblk) {
@@ -369,7 +372,7 @@ void combine_launch(const std::vector<CombineArgs>& recs, hipStream_t st) {
 }
 
 CombineArgs combine_args(pmx_operator* op, const double* sigma, double* y, int n_rhs, int r0, int n_far,
-                         const double* far, bool parametrix) {
+                         const double* far, bool parametrix, const double* ssum) {
   const int q2 = op->s->g.q * op->s->g.q;
   CombineArgs c;
   c.N = op->s->g.N;
@@ -385,7 +388,7 @@ CombineArgs combine_args(pmx_operator* op, const double* sigma, double* y, int n
   c.sigma = sigma;
   c.paired = (q2 % 2 == 0 && c.N % 2 == 0 && ((uintptr_t)sigma % 16) == 0 && ((uintptr_t)c.Cb % 16) == 0) ? 1 : 0;
   c.far = far;
-  c.ssum = op->ssum.p;
+  c.ssum = ssum;
   c.y = y;
   return c;
 }
@@ -400,8 +403,10 @@ void combine_all(const std::vector<ApplyJob>& jobs, const std::vector<int>& n_fa
     std::vector<CombineArgs> recs;
     for (size_t k = 0; k < jobs.size(); ++k) {
       pmx_operator* op = jobs[k].op;
-      recs.push_back(combine_args(op, jobs[k].sigma, jobs[k].y, n_rhs, r0, n_far[k], n_far[k] > 0 ? op->part.p : nullptr,
-                                  parametrix));
+      const ApplyScratch* sc = jobs[k].sc;
+      const double* far = n_far[k] > 0 ? (sc ? sc->part : op->part.p) : nullptr;
+      recs.push_back(combine_args(op, jobs[k].sigma, jobs[k].y, n_rhs, r0, n_far[k], far, parametrix,
+                                  sc ? sc->ssum : op->ssum.p));
     }
     if (nr == 8) combine_launch<8>(recs, st);
     else if (nr == 4) combine_launch<4>(recs, st);

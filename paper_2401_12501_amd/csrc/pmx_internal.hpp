@@ -312,11 +312,23 @@ struct pmx_operator {
 
 namespace pmx {
 
-// One operator apply y = A sigma of a batch (device arrays).
+// Scratch of the FP64 direct apply carved out of memory the caller supplies (the
+// allocation-free entry point); every buffer is written before it is read.
+struct ApplyScratch {
+  double* qt64;    // n_rhs * N: w sigma / a
+  double* spart;   // n_rhs * ceil(N / 256): block partials of sum w sigma
+  double* ssum;    // n_rhs
+  double* rows;    // N * row length: packed source rows
+  double* part;    // chunks * n_rhs * N: far-field partial sums
+};
+
+// One operator apply y = A sigma of a batch (device arrays).  sc == nullptr: the
+// operator's own scratch (sized, and allocated if needed, by the apply).
 struct ApplyJob {
   pmx_operator* op;
   const double* sigma;
   double* y;
+  const ApplyScratch* sc = nullptr;
 };
 
 // geometry.hip
@@ -330,6 +342,9 @@ void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists&
 // direct.hip
 void far_direct(pmx_operator* op, bool fp64, int n_rhs, hipStream_t st);   // fills op->part + chunk count
 int far_direct_chunks(const pmx_operator* op, bool fp64);
+// Doubles of scratch the FP64 direct apply of n_rhs densities needs (ApplyScratch, each
+// buffer rounded up to 32 doubles).
+size_t direct64_scratch_doubles(int64_t N, int n_rhs);
 void far_direct_log(pmx_operator* op, int n_rhs, hipStream_t st);          // representation far field (FP64)
 // nearapply.hip
 void source_prep(pmx_operator* op, const double* sigma, int n_rhs, bool need32, hipStream_t st);

@@ -65,6 +65,7 @@ _SIGS = {
     "pmx_operator_destroy": (None, [_vp]),
     "pmx_operator_get_stats": (C.c_int32, [_vp, C.POINTER(pmx_operator_stats)]),
     "pmx_apply": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_int, _vp]),
+    "pmx_apply_noalloc": (C.c_int32, [_vp, C.c_int, _vp, _vp, _vp]),
     "pmx_solve": (C.c_int32, [_vp, C.POINTER(pmx_options), C.c_int, _vp, _vp, C.c_int, _vp, C.c_int, _vp,
                               C.POINTER(pmx_info)]),
     "pmx_represent": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.c_int, _vp]),
@@ -250,6 +251,19 @@ class Operator:
             out = np.empty((n_rhs, self.N)) if not _is_torch(sigma) else sigma.new_empty(sigma.shape)
         ptrs, kind, stream, keep = _marshal(sigma, out)
         _check(lib().pmx_apply(self.h, precision, n_rhs, ptrs[0], ptrs[1], kind, stream))
+        return out
+
+    def apply_noalloc(self, sigma, out=None, check: bool = True):
+        """pmx_apply_noalloc: y = A sigma (FP64 direct far field) with the library's static scratch;
+        sigma and out are device tensors of shape (n_rhs, N).  Returns out (check=True) or the status."""
+        n_rhs = self._rhs(sigma)
+        if out is None:
+            out = sigma.new_empty(sigma.shape)
+        ptrs, kind, stream, keep = _marshal(sigma, out)
+        code = lib().pmx_apply_noalloc(self.h, n_rhs, ptrs[0], ptrs[1], stream)
+        if not check:
+            return code
+        _check(code)
         return out
 
     def solve(self, f, opts: pmx_options | None = None, sigma0=None, want_u: bool = False, check: bool = True):
