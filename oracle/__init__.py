@@ -19,8 +19,16 @@ PDEs"), for div_G(a grad_G u) = f on a closed surface (c = 0, b = 0):
 * ``operator``  the Nystrom system sigma + R[sigma] + int sigma = f (eq:IE with
   the rank-one term of Section 3), its dense solve, and the representation
   u = K[sigma] made mean zero (eq:representation).
+* ``cfar``      the same smooth-rule (far) sums in plain C with OpenMP (``far.c``,
+  compiled by ``cfar.build``), for whole-operator applies at large N.
+* ``gmres``     GMRES with classical Gram-Schmidt twice, for systems beyond dense LU.
+* ``system``    the whole operator at large N (blocks from worker processes, C far
+  sums, a sparse matrix of the blocks), its GMRES solve and representation, and
+  sampled rows of the operator.
 
 Pinned by ``tests/test_oracle_pins.py`` (closed forms, invariants, the
 diagonal limit eq:limiting_behaviour, exact integrals of the rules, and
-brute-force agreement).  No function here is "parity unpinned".
+brute-force agreement) and ``tests/test_oracle_large.py`` (C sums against the
+NumPy rows and the unit-sphere closed form, GMRES against dense LU, the whole
+system against the dense operator).  No function here is "parity unpinned".
 """
