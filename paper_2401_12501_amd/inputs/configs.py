@@ -30,7 +30,7 @@ from .surfaces import Surface, cube_sphere, real_sph_harm_cartesian, torus
 
 __all__ = [
     "Problem", "sphere_problem", "ellipsoid_problem", "star_problem", "wobbly_torus_problem",
-    "serving_requests", "random_density",
+    "wavy_torus_problem", "serving_requests", "random_density",
 ]
 
 
@@ -107,6 +107,18 @@ def wobbly_torus_problem(n_theta: int = 256, n_phi: int = 128, q: int = 8, n_rhs
     a, ga = F.eval_field(F.a_tanh_sin, s.x)
     f = np.stack([F.solid_harmonic_rhs(s.x, 4 * 100 + r) for r in range(n_rhs)], axis=1)
     return Problem(s, a, ga, f, name=f"wobbly_torus_{n_theta}x{n_phi}_q{q}")
+
+
+def wavy_torus_problem(n_u: int = 51, n_v: int = 18, q: int = 8, seed: int = 5) -> Problem:
+    """The paper's wavy torus, x(u, v) = ((3 + cos v + 0.6 cos 5u) cos u, (3 + cos v + 0.6 cos 5u) sin u,
+    sin v), as n_u x n_v patches (51 x 18 x 8 x 8 = 58,752 nodes by default), with a = 1 (the
+    Laplace-Beltrami remainder) and the N-body density sigma_i = (x_i)_1 + eta_i, eta ~ N(0, 1)
+    (seeded), in ``meta["sigma"]``; f is that density too."""
+    rfun = lambda th, ph: 1.0 + 0.0 * th
+    s = torus(n_u, n_v, q, R=lambda th, ph: 3.0 + 0.6 * torch.cos(5 * th), r=rfun, name="wavy_torus")
+    a, ga = F.eval_field(F.a_const(1.0), s.x)
+    sigma = s.x[:, 0] + np.random.default_rng(seed).normal(size=s.n)
+    return Problem(s, a, ga, sigma[:, None].copy(), name=f"wavy_torus_{n_u}x{n_v}_q{q}", meta={"sigma": sigma})
 
 
 def serving_requests(n_requests: int = 256, seed: int = 3, n_min: float = 2e3, n_max: float = 2e5, q: int = 8):

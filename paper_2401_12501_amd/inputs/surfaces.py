@@ -133,10 +133,10 @@ def cube_sphere(k: int, q: int, axes=(1.0, 1.0, 1.0), radial=None, rotation=None
     return Surface(name, n_patches, q, *arrs, meta={"k": k, "axes": tuple(axes)})
 
 
-def torus(n_theta: int, n_phi: int, q: int, R: float = 1.0, r=0.4, name: str = "torus") -> Surface:
+def torus(n_theta: int, n_phi: int, q: int, R=1.0, r=0.4, name: str = "torus") -> Surface:
     """Torus with patches in (theta toroidal, phi poloidal).
 
-    ``r`` is a constant tube radius or a torch function r(theta, phi).
+    ``R`` and ``r`` are constants or torch functions of (theta, phi).
     x = ((R + r cos phi) cos theta, (R + r cos phi) sin theta, r sin phi);
     (u, v) <-> (theta, phi) gives the outward orientation.
     """
@@ -149,11 +149,12 @@ def torus(n_theta: int, n_phi: int, q: int, R: float = 1.0, r=0.4, name: str = "
         th = 2 * math.pi * (it + (uu + 1) / 2) / n_theta
         ph = 2 * math.pi * (ip + (vv + 1) / 2) / n_phi
         rr = r(th, ph) if callable(r) else r * torch.ones_like(th)
-        ring = R + rr * torch.cos(ph)
+        RR = R(th, ph) if callable(R) else R
+        ring = RR + rr * torch.cos(ph)
         return torch.stack([ring * torch.cos(th), ring * torch.sin(th), rr * torch.sin(ph)], dim=1)
 
     arrs = _derivatives(fmap, u, v)
-    return Surface(name, n_patches, q, *arrs, meta={"n_theta": n_theta, "n_phi": n_phi, "R": R})
+    return Surface(name, n_patches, q, *arrs, meta={"n_theta": n_theta, "n_phi": n_phi})
 
 
 def _legendre_deriv_coeffs(l: int, m: int) -> np.ndarray:
