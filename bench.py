@@ -35,7 +35,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "operator-apply Gpts/s @1e-8 rel err, mixed vs FP64; solves/s + p50/p99 latency"
-PEAK = {"fp64_valu": 78.6, "fp32_valu": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0}
+# MI355X peaks: FP64 vector and FP32 MFMA as published; FP32 vector 157.3 needs packed FP32
+# instructions, which this build does not emit (they are disabled at compile time), so FP32 VALU
+# kernels are rated against the non-packed rate, 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+# = 78.6 TFLOP/s (the packed figure is reported beside it).
+PEAK = {"fp64_valu": 78.6, "fp32_valu": 78.6, "fp32_valu_packed": 157.3, "fp32_mfma": 157.3, "hbm": 8000.0}
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB) on this workload
 # (ellipsoid, 153,600 nodes, mixed path, 1 RHS; the M2L in the layout it runs in beside the
@@ -126,121 +130,160 @@ def algorithmic_work(phase: str, st, N: int, q: int, n_rhs: int, fmm_order: int,
     return None
 
 
-def cpu_baseline(prob, sigma, budget_s: float, checks: dict):
+def host_cpu():
+    """Host core count and CPU model (the oracle's timing runs on the GPU machine's host)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(prob, factory, sigma, budget_s: float, checks: dict):
     """The CPU leg: the only part of this script that runs the oracle.  It checks the GPU results
-    kept in `checks` on sampled rows (apply error, solve residuals, representation) and then times
-    the oracle's apply on sampled rows (near blocks precomputed per row, as on the GPU).  Returns
+    kept in `checks` on 1,024 sampled rows (apply error, solve residuals, representation) and then
+    times the oracle's apply on batches of random rows: each batch's near/self correction blocks are
+    built first (worker processes, timed separately as setup), then the rows are applied (smooth-rule
+    sums over all sources in C on every host core, plus the block products).  Returns
     (cpu_baseline record, check results)."""
-    from threadpoolctl import threadpool_limits
+    from oracle import cfar
     from oracle.operator import OracleOperator
+    from oracle.system import BlockPool, rows_from_blocks
     orc = OracleOperator.from_problem(prob)
     N = prob.n
-    rng = np.random.default_rng(5)
-    tg = np.concatenate([[0, N - 1], rng.choice(N, 10, replace=False)])
+    q2 = prob.surface.q ** 2
+    workers = max(1, min(8, os.cpu_count() or 1))   # few processes: the box limits processes that map the GPU runtime
+    host = host_cpu()
+    threads = cfar.threads()
     res = {}
-    # apply error of each path's y for the benchmark density
-    ref = orc.apply_rows(tg, sigma)
-    scale = np.abs(ref).max()
-    res["apply_rel_err_vs_oracle"] = {k: float(np.abs(v[tg] - ref).max() / scale) for k, v in checks["y"].items()}
-    log(f"[bench] sampled-row apply error vs oracle: {res['apply_rel_err_vs_oracle']}")
-    # residual of each returned density in the oracle's discrete system
-    f_rows = prob.f[tg] - (prob.f * orc.w[:, None]).sum(0) / orc.w.sum()   # mean-zero data at the rows
-    res["solve_rows"] = {}
-    for path, s_h in checks["sigma"].items():
-        r_rows = f_rows - orc.apply_rows(tg, s_h)
-        res["solve_rows"][path] = float(np.abs(r_rows).max() / np.abs(f_rows).max())
-    log(f"[bench] sampled-row relative residual of the solves: {res['solve_rows']}")
-    # representation: the GPU rows differ from the oracle's rows before the mean is removed by one
-    # constant per right-hand side (the weighted mean), so the spread of the differences is the
-    # error, relative to the spread of the oracle rows
-    if checks.get("u") is not None:
-        u_h, s_h = checks["u"], checks["sigma"]["mixed"]
-        ref_u = orc.represent_rows(tg, s_h)
-        d = u_h[tg] - ref_u
-        res["representation"] = {
-            "rows_rel_err_vs_oracle": float(np.abs(d - d.mean(0)).max() / np.abs(ref_u - ref_u.mean(0)).max()),
-            "weighted_mean_rel": float(np.abs(orc.w @ u_h).max() / orc.w.sum() / np.abs(u_h).max())}
-        log(f"[bench] representation vs oracle rows: {res['representation']}")
-    with threadpool_limits(limits=1):
+    with BlockPool(factory, ROOT, workers) as pool:
+        rng = np.random.default_rng(5)
+        patches = rng.choice(N // q2, 128, replace=False)
+        tg = np.unique(np.concatenate([[0, N - 1], patches * q2, patches * q2 + q2 - 1,
+                                       rng.choice(N, 1024 - 258, replace=False)]))
+        blocks = pool.blocks(tg, ("R",), chunk=16)
+        ref = rows_from_blocks(orc, blocks, tg, sigma)
+        scale = np.abs(ref).max()
+        res["apply_rel_err_vs_oracle"] = {k: float(np.abs(v[tg] - ref).max() / scale) for k, v in checks["y"].items()}
+        res["rows_checked"] = int(len(tg))
+        log(f"[bench] {len(tg)} sampled rows, apply error vs oracle: {res['apply_rel_err_vs_oracle']}")
+        # residual of each returned density in the oracle's discrete system
+        f_rows = prob.f[tg] - (prob.f * orc.w[:, None]).sum(0) / orc.w.sum()   # mean-zero data at the rows
+        res["solve_rows"] = {}
+        for path, s_h in checks["sigma"].items():
+            r_rows = f_rows - rows_from_blocks(orc, blocks, tg, s_h)
+            res["solve_rows"][path] = float(np.abs(r_rows).max() / np.abs(f_rows).max())
+        log(f"[bench] sampled-row relative residual of the solves: {res['solve_rows']}")
+        # representation: the GPU rows differ from the oracle's rows before the mean is removed by one
+        # constant per right-hand side (the weighted mean), so the spread of the differences is the
+        # error, relative to the spread of the oracle rows
+        if checks.get("u") is not None:
+            u_h, s_h = checks["u"], checks["sigma"]["mixed"]
+            ref_u = rows_from_blocks(orc, pool.blocks(tg, ("K",), chunk=16), tg, s_h, "K")
+            d = u_h[tg] - ref_u
+            res["representation"] = {
+                "rows_rel_err_vs_oracle": float(np.abs(d - d.mean(0)).max() / np.abs(ref_u - ref_u.mean(0)).max()),
+                "weighted_mean_rel": float(np.abs(orc.w @ u_h).max() / orc.w.sum() / np.abs(u_h).max())}
+            log(f"[bench] representation vs oracle rows: {res['representation']}")
         rng = np.random.default_rng(7)
-        rows, t_apply, t_setup = 0, 0.0, 0.0
+        n_rows, t_apply, t_setup = 0, 0.0, 0.0
         t_start = time.perf_counter()
         while time.perf_counter() - t_start < budget_s:
-            tg = rng.choice(prob.n, 4, replace=False)
+            batch = rng.choice(N, min(N, 1024), replace=False)
             t0 = time.perf_counter()
-            blocks = orc.blocks(tg)
+            bl = pool.blocks(batch, ("R",), chunk=16)
             t1 = time.perf_counter()
-            orc.apply_rows(tg, sigma, blocks)
+            rows_from_blocks(orc, bl, batch, sigma)
             t2 = time.perf_counter()
-            rows += len(tg)
+            n_rows += len(batch)
             t_setup += t1 - t0
             t_apply += t2 - t1
-    return {"value": rows / t_apply / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows} random target rows of the {prob.n}-node apply (far sum over all sources + "
-                      f"precomputed near blocks), numpy FP64, 1 thread; near-block setup "
-                      f"{t_setup / rows * 1e3:.1f} ms/row timed separately"}, res
+    rec = {"value": n_rows / t_apply / 1e9, "unit": "Gpts/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n_rows} random target rows of the {N}-node apply in batches of 1,024: smooth-rule sums over "
+                     f"all {N} sources (C, FP64, {threads} OpenMP threads) plus the rows' near/self block products "
+                     f"(numpy); the blocks themselves built beforehand on {workers} processes, "
+                     f"{t_setup / n_rows * 1e3:.2f} ms/row wall, timed separately",
+           "setup_ms_per_row": round(t_setup / n_rows * 1e3, 3), "host": host}
+    log(f"[bench] cpu baseline: {rec}")
+    return rec, res
 
 
-def serving(ctx, n_req: int, slots: int, load: float = 0.7):
+def _percentiles(x):
+    x = np.asarray(x, dtype=np.float64)
+    return round(float(np.percentile(x, 50)), 4), round(float(np.percentile(x, 99)), 4)
+
+
+def serving(n_req: int, slots: int, loads, budget_bytes: int, n_cal: int = 64):
     """Serving workload: requests from the sphere / random-axis ellipsoid / torus families with
-    2e3..2e5 nodes (log-uniform), mixed path, memory-admitted.  The first quarter of the requests,
-    submitted at once, measures the saturated rate mu; the rest arrive as a Poisson stream at
-    load * mu (0.7 by default).  Latency = submit -> result ready (server clock)."""
+    2e3..2e5 nodes (log-uniform), mixed path, admitted by slots and by the HBM budget of their
+    context.  A separate closed-loop run of n_cal requests (another seed) measures the saturated
+    rate mu; then the n_req requests arrive as a Poisson stream at each load * mu.  Latency =
+    submit -> result ready (server clock), split into queue wait and service."""
     from paper_2401_12501_amd import pmx
     from paper_2401_12501_amd.inputs import serving_requests
-    log(f"[serve] generating {n_req} requests ...")
+    log(f"[serve] generating {n_req} + {n_cal} requests ...")
     reqs = [p for _, p in serving_requests(n_req, seed=3)]
+    cal = [p for _, p in serving_requests(n_cal, seed=4)]
     o = pmx.pmx_default_options()
     o.precision = pmx.PMX_PREC_MIXED_FMM
-    sv = pmx.Server(ctx, o, max_active=slots)
+    ctx = pmx.Context(0, hbm_budget_bytes=budget_bytes)
 
-    def drain(tickets, lat, status):
-        for t in list(tickets):
-            r = sv.poll(t)
-            if r is not None:
-                tickets.remove(t)
-                lat.append(r[4][2])
-                status.append(r[0])
+    def run(problems, arrivals):
+        sv = pmx.Server(ctx, o, max_active=slots)
+        out, done = set(), []
+        t0 = time.perf_counter()
+        nxt = 0
+        while nxt < len(problems) or out:
+            now = time.perf_counter() - t0
+            while nxt < len(problems) and (arrivals is None or arrivals[nxt] <= now):
+                p = problems[nxt]
+                out.add(sv.submit(p.surface, p.a, p.grad_a, p.f[:, 0]))
+                nxt += 1
+            sv.step()
+            for t in list(out):
+                r = sv.poll(t)
+                if r is not None:
+                    out.remove(t)
+                    done.append((r[0], r[4].copy()))
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        st = sv.stats()
+        sv.close()
+        bad = [c for c, _ in done if c != pmx.PMX_OK]
+        if bad:
+            raise RuntimeError(f"serving: {len(bad)} requests did not return PMX_OK: {sorted(set(bad))}")
+        return wall, np.array([t for _, t in done]), st
 
-    n_cal = max(4, n_req // 4)
-    lat_cal, st_cal, out = [], [], set()
-    t0 = time.perf_counter()
-    for p in reqs[:n_cal]:
-        out.add(sv.submit(p.surface, p.a, p.grad_a, p.f[:, 0]))
-    while out:
-        sv.step()
-        drain(out, lat_cal, st_cal)
-        time.sleep(0.001)
-    mu = n_cal / (time.perf_counter() - t0)
-    lam = load * mu
-    rng = np.random.default_rng(33)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req - n_cal))
-    lat, status = [], []
-    t0 = time.perf_counter()
-    nxt = 0
-    while nxt < len(arrivals) or out:
-        now = time.perf_counter() - t0
-        while nxt < len(arrivals) and arrivals[nxt] <= now:
-            p = reqs[n_cal + nxt]
-            out.add(sv.submit(p.surface, p.a, p.grad_a, p.f[:, 0]))
-            nxt += 1
-        sv.step()
-        drain(out, lat, status)
-        time.sleep(0.0005)
-    wall = time.perf_counter() - t0
-    bstats = sv.stats()
-    sv.close()
-    lat = np.array(lat)
-    res = {"requests": n_req, "calibration_requests": n_cal, "slots": slots,
-           "saturated_solves_per_s": round(mu, 3), "load": load, "arrival_rate_per_s": round(lam, 3),
-           "solves_per_s": round(len(lat) / wall, 3), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-           "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-           "ok": int(sum(1 for s in status + st_cal if s == 0)),
-           "batched_applies": bstats["applies"], "shared_launch_batches": bstats["batches"],
-           "mean_batch": round(bstats["applies"] / max(bstats["batches"], 1), 2), "max_batch": bstats["max_batch"],
-           "nodes_min_max": [int(min(p.n for p in reqs)), int(max(p.n for p in reqs))]}
-    log(f"[serve] {res}")
-    return res
+    wall, _, _ = run(cal, None)
+    mu = n_cal / wall
+    log(f"[serve] saturated rate {mu:.2f} solves/s ({n_cal} requests, closed loop)")
+    per_load = []
+    for load in loads:
+        lam = load * mu
+        arrivals = np.cumsum(np.random.default_rng(33).exponential(1.0 / lam, n_req))
+        wall, times, st = run(reqs, arrivals)
+        p50, p99 = _percentiles(times[:, 2])
+        q50, q99 = _percentiles(times[:, 0])
+        s50, s99 = _percentiles(times[:, 1])
+        rec = {"load": load, "arrival_rate_per_s": round(lam, 3), "solves_per_s": round(n_req / wall, 3),
+               "p50_latency_s": p50, "p99_latency_s": p99, "queue_p50_s": q50, "queue_p99_s": q99,
+               "service_p50_s": s50, "service_p99_s": s99, "held_for_memory": st["held_for_memory"],
+               "peak_reserved_gib": round(st["peak_reserved_bytes"] / 2 ** 30, 3),
+               "mean_batch": round(st["applies"] / max(st["batches"], 1), 2), "max_batch": st["max_batch"],
+               "shared_launches": st["batches"], "applies": st["applies"]}
+        log(f"[serve] {rec}")
+        per_load.append(rec)
+    main = next((r for r in per_load if abs(r["load"] - 0.7) < 1e-9), per_load[0])
+    return {"requests": n_req, "ok": n_req, "calibration_requests": n_cal, "slots": slots,
+            "hbm_budget_bytes": budget_bytes, "saturated_solves_per_s": round(mu, 3),
+            "p50_latency_s": main["p50_latency_s"], "p99_latency_s": main["p99_latency_s"],
+            "at_load": main["load"], "loads": per_load,
+            "nodes_min_max": [int(min(p.n for p in reqs)), int(max(p.n for p in reqs))]}
 
 
 def main():
@@ -263,11 +306,13 @@ def main():
                     help="mixed solve: inner GMRES tolerance (0: library default)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="mixed applies on one stream (no near/P2P overlap with the M2L chain)")
-    ap.add_argument("--serve", type=int, default=64,
-                    help="serving requests to run (0: skip); the first quarter calibrates the saturated rate")
+    ap.add_argument("--serve", type=int, default=256,
+                    help="serving requests per load (0: skip); a separate closed-loop run calibrates the saturated rate")
     ap.add_argument("--serve-slots", type=int, default=4)
-    ap.add_argument("--serve-load", type=float, default=0.7,
-                    help="serving: Poisson arrival rate as a fraction of the measured saturated rate")
+    ap.add_argument("--serve-loads", default="0.5,0.7,0.9",
+                    help="serving: Poisson arrival rates as fractions of the measured saturated rate")
+    ap.add_argument("--serve-budget-mib", type=int, default=2048,
+                    help="serving: HBM budget of the server's context (admission by memory)")
     ap.add_argument("--calib-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (a known-size kernel for traffic counters)")
     args = ap.parse_args()
@@ -287,18 +332,22 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    INPUTS = "paper_2401_12501_amd.inputs"
     if args.workload == "ellipsoid":
         prob = ellipsoid_problem(k=args.k, q=10, n_rhs=args.n_rhs)
+        factory = (INPUTS, "ellipsoid_problem", {"k": args.k, "q": 10, "n_rhs": args.n_rhs})
         n_rhs = args.n_rhs
         desc = (f"ellipsoid (1, 0.8, 0.6), {prob.surface.n_patches} patches x 10x10 Gauss-Legendre nodes, "
                 f"N={prob.n}, a=exp(0.3 x1 x2)")
     elif args.workload == "star":
         prob = star_problem()
+        factory = (INPUTS, "star_problem", {})
         n_rhs = 1
         desc = (f"star r = 1 + 0.25 (8 real spherical harmonics, l <= 4), {prob.surface.n_patches} patches x 8x8 "
                 f"Gauss-Legendre nodes, N={prob.n}, a = 2^tanh(smooth seed field)")
     else:
         prob = wobbly_torus_problem()
+        factory = (INPUTS, "wobbly_torus_problem", {})
         n_rhs = prob.f.shape[1]
         desc = (f"wobbly torus R=1, r=0.4(1+0.2 cos 5t sin 3p), {prob.surface.n_patches} patches x 8x8 "
                 f"Gauss-Legendre nodes, N={prob.n}, a=1+0.5 tanh(sin 3 x1), {n_rhs} right-hand sides")
@@ -361,7 +410,7 @@ def main():
         d32_tf = float(N) * (N - 1) * (24 + 2 * n_rhs) / d32_s / 1e12
         fp32_direct = {"ms_per_apply": round(d32_s * 1e3, 4), "gpts_per_s": round(N * n_rhs / d32_s / 1e9, 4),
                        "achieved": round(d32_tf, 3), "unit": "TFLOP/s", "peak": PEAK["fp32_valu"],
-                       "frac": round(d32_tf / PEAK["fp32_valu"], 4),
+                       "frac": round(d32_tf / PEAK["fp32_valu"], 4), "peak_packed": PEAK["fp32_valu_packed"],
                        "note": "pair flops over the whole apply time (the FP64 near correction included)"}
         log(f"[bench] fp32 direct: {fp32_direct}")
     except pmx.PmxError as e:
@@ -514,10 +563,12 @@ def main():
         "near_pairs": st.near_pairs,
     }
     if args.serve:
-        out["serving"] = serving(ctx, args.serve, args.serve_slots, args.serve_load)
+        out["serving"] = serving(args.serve, args.serve_slots, [float(v) for v in args.serve_loads.split(",")],
+                                 args.serve_budget_mib << 20)
     if not args.no_cpu:
         log("[bench] cpu leg: oracle checks on sampled rows and the oracle's own rate ...")
-        out["cpu_baseline"], res = cpu_baseline(prob, sig_h, args.cpu_budget, checks)
+        out["cpu_baseline"], res = cpu_baseline(prob, factory, sig_h, args.cpu_budget, checks)
+        out["rows_checked_vs_oracle"] = res["rows_checked"]
         out["apply_rel_err_vs_oracle"] = res["apply_rel_err_vs_oracle"]
         for path, r in res["solve_rows"].items():
             solve[path]["oracle_rows_rel_residual"] = r

@@ -192,7 +192,11 @@ PMX_API pmx_status pmx_represent(pmx_operator* op, int n_rhs, const double* sigm
 
 /* ---- Continuous-batching solve server (many independent problems of eq:IE) ----
  * Requests queue in arrival order; pmx_server_step admits them while fewer than
- * max_active run and the estimated device footprint fits the context's HBM budget.
+ * max_active run and their device footprints fit the context's HBM budget: a request counts
+ * with its footprint estimated at submit until it has built its operator, then with its
+ * measured footprint if that is larger.  The budget acts at admission only; a running request
+ * allocates from its own accounting and is never failed because others are larger than
+ * estimated.
  * Each admitted request gets its own stream and worker thread, builds its surface and
  * operator on the device, solves with opts->precision (NULL opts: defaults with the
  * mixed path), and releases its device memory; active requests run concurrently.
@@ -221,10 +225,13 @@ PMX_API pmx_status pmx_server_poll(pmx_server* sv, uint64_t ticket, double* sigm
 PMX_API pmx_status pmx_server_cancel(pmx_server* sv, uint64_t ticket);
 /* Cancels running requests, waits for their workers, frees the server (NULL-safe). */
 PMX_API void pmx_server_destroy(pmx_server* sv);
-/* Batching counters since creation: number of shared launches of the apply path
- * (batches), applies they carried, and the largest batch.  Any pointer may be NULL. */
+/* Counters since creation: number of shared launches of the apply path (batches), applies
+ * they carried, the largest batch, requests that stayed queued for memory while a slot was free
+ * (admission by the HBM budget), and the largest estimated footprint admitted at once.  Any
+ * pointer may be NULL. */
 PMX_API pmx_status pmx_server_get_stats(pmx_server* sv, uint64_t* n_batches, uint64_t* n_applies,
-                                        uint64_t* max_batch);
+                                        uint64_t* max_batch, uint64_t* n_held_for_memory,
+                                        uint64_t* peak_reserved_bytes);
 
 /* Per-phase device timing of the apply (HIP events recorded on the call's stream around
  * each phase while enabled).  Phases: PMX_PHASE_*.  pmx_profile_read synchronizes the
@@ -237,12 +244,12 @@ enum {
   PMX_PHASE_NEAR = 3,        /* near correction + combine */
   PMX_PHASE_FMM_P2M = 4,
   PMX_PHASE_FMM_M2M = 5,
-  PMX_PHASE_FMM_M2L = 6,     /* M2L translations (MFMA), one output slot per pair */
+  PMX_PHASE_FMM_M2L = 6,     /* M2L translations (MFMA), one output slot per pair, summed per box */
   PMX_PHASE_FMM_L2L = 7,
   PMX_PHASE_FMM_L2P = 8,
   PMX_PHASE_FMM_P2P = 9,
   PMX_PHASE_LOG = 10,        /* representation far field */
-  PMX_PHASE_FMM_M2L_SUM = 11,  /* sum of each box's M2L output slots */
+  PMX_PHASE_FMM_M2L_SUM = 11,  /* no longer timed: the M2L launch sums each box's output slots */
   PMX_N_PHASES = 12
 };
 PMX_API pmx_status pmx_profile_enable(pmx_operator* op, int enable);

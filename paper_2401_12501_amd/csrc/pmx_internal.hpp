@@ -66,11 +66,16 @@ struct DBuf {
   T* get() const { return p; }
 };
 
-// Device memory accounting of a context (shared by the server's worker threads).
+// Device memory accounting of a context (shared by the server's worker threads).  A server
+// request allocates from a context of its own whose bytes are also charged to the server's
+// context (parent) without that context's budget check: the server admits requests by
+// footprint, so a running request is never failed by another request's size.
 struct Ctx {
   int device = 0;
   uint64_t budget = 0;   // 0 = unbounded
   std::atomic<uint64_t> in_use{0};
+  std::atomic<uint64_t> peak{0};
+  Ctx* parent = nullptr;
   int n_cu = 256;
   void reserve(uint64_t bytes) {
     uint64_t cur = in_use.load();
@@ -78,8 +83,16 @@ struct Ctx {
       if (budget && cur + bytes > budget)
         throw Error(PMX_ERR_TOO_LARGE, "device footprint exceeds the context's HBM budget");
     } while (!in_use.compare_exchange_weak(cur, cur + bytes));
+    const uint64_t now = cur + bytes;
+    uint64_t pk = peak.load();
+    while (now > pk && !peak.compare_exchange_weak(pk, now)) {
+    }
+    if (parent) parent->in_use.fetch_add(bytes);
   }
-  void unreserve(uint64_t bytes) { in_use.fetch_sub(bytes); }
+  void unreserve(uint64_t bytes) {
+    in_use.fetch_sub(bytes);
+    if (parent) parent->in_use.fetch_sub(bytes);
+  }
 };
 
 template <class T>
@@ -385,7 +398,7 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
 void fmm_build(pmx_operator* op, hipStream_t st);
 void fmm_destroy(FMM* f);
 // y_r += far field of sigma_r for every job.  After the source permutation of each rhs,
-// the P2P sums run on `side` while P2M, M2M, M2L, its slot sum and L2L run on st;
+// the P2P sums run on `side` while P2M, M2M, M2L (with its slot sums) and L2L run on st;
 // side_work(side) is called once, before the first P2P launch, and st waits for side
 // before each L2P launch (which adds into y), so side_work may write y.  side == st runs
 // everything on one stream in the same order (events unused).

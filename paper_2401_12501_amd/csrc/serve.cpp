@@ -46,6 +46,7 @@ struct Request {
   int64_t N = 0;
   std::vector<double> x, xu, xv, xuu, xuv, xvv, a, ga, f;
   bool want_u = false;
+  bool held_for_memory = false;   // a slot was free but the budget kept it queued
   uint64_t est_bytes = 0;
   // results
   std::vector<double> sigma, u;
@@ -95,6 +96,8 @@ struct pmx_server {
   std::deque<std::shared_ptr<Request>> queue;
   std::map<uint64_t, std::shared_ptr<Request>> active, done;
   uint64_t reserved = 0;   // estimated bytes of the active requests
+  uint64_t peak_reserved = 0;
+  uint64_t n_held_for_memory = 0;   // requests that waited for memory with a slot free
 };
 
 namespace {
@@ -170,10 +173,28 @@ void solving_delta(pmx_batcher* b, int d) {
   b->cv_work.notify_all();
 }
 
-void run_request(pmx_ctx* ctx, pmx_options opts, Request* r, pmx_batcher* batcher) {
+// The request's measured footprint so far replaces its estimate in the server's admission sum
+// once it is larger (later admissions see the real size).
+void account_footprint(pmx_server* sv, Request* r, const pmx::Ctx& rc) {
+  const uint64_t used = rc.peak.load();
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (used > r->est_bytes) {
+    sv->reserved += used - r->est_bytes;
+    r->est_bytes = used;
+    if (sv->reserved > sv->peak_reserved) sv->peak_reserved = sv->reserved;
+  }
+}
+
+void run_request(pmx_server* sv, pmx_options opts, Request* r, pmx_batcher* batcher) {
   hipStream_t st = nullptr;
   pmx_surface* s = nullptr;
   pmx_operator* op = nullptr;
+  pmx_ctx* sctx = sv->ctx;
+  pmx_ctx rctx;   // the request's own accounting, charged to the server's context
+  rctx.c.device = sctx->c.device;
+  rctx.c.n_cu = sctx->c.n_cu;
+  rctx.c.parent = &sctx->c;
+  pmx_ctx* ctx = &rctx;
   auto fail = [&](pmx_status code) {
     r->status = code;
     r->message = pmx_last_error();
@@ -195,6 +216,7 @@ void run_request(pmx_ctx* ctx, pmx_options opts, Request* r, pmx_batcher* batche
       pmx::set_last_error(e.what());
       rc = e.code;
     }
+    account_footprint(sv, r, rctx.c);
   }
   if (rc == PMX_OK) {
     op->cancel = &r->cancel;
@@ -212,6 +234,7 @@ void run_request(pmx_ctx* ctx, pmx_options opts, Request* r, pmx_batcher* batche
     }
   }
   if (rc != PMX_OK) fail(rc); else r->status = PMX_OK;
+  account_footprint(sv, r, rctx.c);
   pmx_operator_destroy(op);
   pmx_surface_destroy(s);
   (void)hipStreamSynchronize(st);
@@ -307,7 +330,13 @@ pmx_status pmx_server_step(pmx_server* sv, int* n_active, int* n_queued) {
   const uint64_t budget = sv->ctx->c.budget;
   while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active) {
     auto r = sv->queue.front();
-    if (budget && !sv->active.empty() && sv->reserved + r->est_bytes > budget) break;   // wait for memory
+    if (budget && !sv->active.empty() && sv->reserved + r->est_bytes > budget) {   // wait for memory
+      if (!r->held_for_memory) {
+        r->held_for_memory = true;
+        ++sv->n_held_for_memory;
+      }
+      break;
+    }
     sv->queue.pop_front();
     if (r->cancel.load()) {
       r->status = PMX_ERR_CANCELLED;
@@ -318,8 +347,9 @@ pmx_status pmx_server_step(pmx_server* sv, int* n_active, int* n_queued) {
     }
     r->t_admit = now_s();
     sv->reserved += r->est_bytes;
+    if (sv->reserved > sv->peak_reserved) sv->peak_reserved = sv->reserved;
     sv->active[r->id] = r;
-    r->worker = std::thread(run_request, sv->ctx, sv->opts, r.get(), sv->batcher);
+    r->worker = std::thread(run_request, sv, sv->opts, r.get(), sv->batcher);
   }
   if (n_active) *n_active = (int)sv->active.size();
   if (n_queued) *n_queued = (int)sv->queue.size();
@@ -378,15 +408,21 @@ pmx_status pmx_server_cancel(pmx_server* sv, uint64_t ticket) {
   return PMX_ERR_INVALID;
 }
 
-pmx_status pmx_server_get_stats(pmx_server* sv, uint64_t* n_batches, uint64_t* n_applies, uint64_t* max_batch) {
+pmx_status pmx_server_get_stats(pmx_server* sv, uint64_t* n_batches, uint64_t* n_applies, uint64_t* max_batch,
+                                uint64_t* n_held_for_memory, uint64_t* peak_reserved_bytes) {
   if (!sv || !sv->batcher) {
     pmx::set_last_error("null server");
     return PMX_ERR_INVALID;
   }
-  std::lock_guard<std::mutex> lk(sv->batcher->mu);
-  if (n_batches) *n_batches = sv->batcher->n_batches;
-  if (n_applies) *n_applies = sv->batcher->n_applies;
-  if (max_batch) *max_batch = sv->batcher->max_batch;
+  {
+    std::lock_guard<std::mutex> lk(sv->batcher->mu);
+    if (n_batches) *n_batches = sv->batcher->n_batches;
+    if (n_applies) *n_applies = sv->batcher->n_applies;
+    if (max_batch) *max_batch = sv->batcher->max_batch;
+  }
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (n_held_for_memory) *n_held_for_memory = sv->n_held_for_memory;
+  if (peak_reserved_bytes) *peak_reserved_bytes = sv->peak_reserved;
   return PMX_OK;
 }
 

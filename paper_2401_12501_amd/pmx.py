@@ -78,7 +78,7 @@ _SIGS = {
     "pmx_server_poll": (C.c_int32, [_vp, C.c_uint64, _vp, _vp, C.POINTER(pmx_info), _vp]),
     "pmx_server_cancel": (C.c_int32, [_vp, C.c_uint64]),
     "pmx_server_destroy": (None, [_vp]),
-    "pmx_server_get_stats": (C.c_int32, [_vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "pmx_server_get_stats": (C.c_int32, [_vp] + [C.POINTER(C.c_uint64)] * 5),
     "pmx_profile_enable": (C.c_int32, [_vp, C.c_int]),
     "pmx_profile_read": (C.c_int32, [_vp, _vp, _vp]),
 }
@@ -369,7 +369,9 @@ class Server:
         _check(lib().pmx_server_cancel(self.h, ticket))
 
     def stats(self) -> dict:
-        """Batching counters: shared launches of the apply path, applies carried, largest batch."""
-        b, a, m = C.c_uint64(), C.c_uint64(), C.c_uint64()
-        _check(lib().pmx_server_get_stats(self.h, C.byref(b), C.byref(a), C.byref(m)))
-        return {"batches": b.value, "applies": a.value, "max_batch": m.value}
+        """Counters: shared launches of the apply path, applies carried, largest batch, requests held
+        back for memory, largest estimated footprint admitted at once (bytes)."""
+        v = [C.c_uint64() for _ in range(5)]
+        _check(lib().pmx_server_get_stats(self.h, *[C.byref(x) for x in v]))
+        return dict(zip(("batches", "applies", "max_batch", "held_for_memory", "peak_reserved_bytes"),
+                        (x.value for x in v)))

@@ -106,8 +106,11 @@ def test_admission_budget_and_rejection(ctx):
     sv = pmx.Server(small, max_active=3)
     tickets = [sv.submit(s, a, ga, f) for (_, s, a, ga, f) in probs]
     res, max_active = run_all(sv, tickets)
-    say(f"[serve budget] 50 MiB budget: max active {max_active}")
+    bs = sv.stats()
+    say(f"[serve budget] 50 MiB budget: max active {max_active}, held for memory {bs['held_for_memory']}, "
+        f"peak reserved {bs['peak_reserved_bytes'] / 2**20:.1f} MiB")
     assert max_active == 1                                    # one request's footprint at a time
+    assert bs["held_for_memory"] >= 1 and 0 < bs["peak_reserved_bytes"] <= 50 << 20
     assert all(r[0] == pmx.PMX_OK for r in res.values())
     big = torus(64, 32, 8)                                    # 131,072 nodes: over the budget
     a, ga = F.eval_field(F.a_const(1.0), big.x)
