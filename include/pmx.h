@@ -244,12 +244,12 @@ enum {
   PMX_PHASE_NEAR = 3,        /* near correction + combine */
   PMX_PHASE_FMM_P2M = 4,
   PMX_PHASE_FMM_M2M = 5,
-  PMX_PHASE_FMM_M2L = 6,     /* M2L translations (MFMA), one output slot per pair, summed per box */
+  PMX_PHASE_FMM_M2L = 6,     /* M2L translations (MFMA), one output slot per pair */
   PMX_PHASE_FMM_L2L = 7,
   PMX_PHASE_FMM_L2P = 8,
   PMX_PHASE_FMM_P2P = 9,
   PMX_PHASE_LOG = 10,        /* representation far field */
-  PMX_PHASE_FMM_M2L_SUM = 11,  /* no longer timed: the M2L launch sums each box's output slots */
+  PMX_PHASE_FMM_M2L_SUM = 11,  /* sum of each box's M2L output slots */
   PMX_N_PHASES = 12
 };
 PMX_API pmx_status pmx_profile_enable(pmx_operator* op, int enable);

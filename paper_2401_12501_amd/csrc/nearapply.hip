@@ -242,13 +242,18 @@ __global__ void k_sub_mean(int64_t N, double* __restrict__ u, const double* __re
 }
 
 // Near correction for a group of RB right-hand sides (8 or 16), one workgroup per target
-// patch T.  The workgroup walks the union of the near patches of T's targets; for each such
-// patch P it stages sigma_P (q^2 x RB) in LDS once, and lane (target t, rhs r) forms
-// C_{t,P} . sigma_P[:, r] with the block row read once per target (the RB lanes of a target
-// read the same address).  Each target sums its patches in union order, so results are
-// deterministic; no cross-lane reduction is needed.
+// patch T.  For every patch P in the union of the near lists of T's targets, the rows of T's
+// targets with P form a q^2 x q^2 block C_{T,P} (rows of targets not near P are zero), and
+//   Y_T += C_{T,P} Sigma_P,   Sigma_P = sigma of P's nodes for the RB right-hand sides,
+// a dense contraction that runs on FP64 MFMA (16 x 16 x 4): the right-hand sides are the
+// sixteen columns, each wave owns 16-row tiles of Y_T, and the accumulators stay in registers
+// across the union.  The contraction runs over P's nodes in chunks of kKC: each chunk's slice of
+// every block row (kKC consecutive doubles of a row stored contiguously) and of Sigma_P are
+// staged in LDS with coalesced loads, so the blocks stream from HBM once in full-width loads.
+// Each target sums its patches in union order, so results are deterministic; the output goes
+// through LDS so that y is written with unit stride per right-hand side.
 struct TiledArgs {
-  int64_t N;
+  int64_t N, n_patches;
   int q2, r0;
   const int32_t* tile_ptr;
   const int32_t* tile_patch;
@@ -259,63 +264,103 @@ struct TiledArgs {
   double* y;
 };
 
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kXcds = 8;           // accelerator complex dies of the GPU, each with its own L2
+constexpr int kKC = 32;            // source nodes per staged chunk
+constexpr int kLdC = kKC + 1;      // LDS row stride of the block slices (doubles)
+constexpr int kLdY = 17;           // LDS row stride of the output tile (doubles)
+
+// One buffer of block slices and sigma slices, small enough for several workgroups per compute
+// unit: their loads hide each other's latency (double-buffering each workgroup's chunks with
+// register prefetch needs twice the LDS and was measured 2.4x slower on the torus).
 template <int RB>
 __global__ void __launch_bounds__(256) k_near_tiled(Group<TiledArgs> g) {
-  constexpr int TPW = 64 / RB;          // targets per wave
-  constexpr int TPP = 4 * TPW;          // targets per pass of the workgroup
-  constexpr int kPass = 256 / TPP;      // passes for q^2 <= 256
-  constexpr int LD = RB + 1;            // LDS row stride (doubles): staging writes spread over banks
-  extern __shared__ double ssig[];      // [q^2][LD]
-  int64_t T;
-  const TiledArgs& A = seg_of(g, blockIdx.x, T);
+  // LDS: block slices sC[q^2 rounded to 16][kLdC], then sS[kKC][16]; the output tile sY
+  // [q^2][kLdY] reuses sC once the contraction is done
+  extern __shared__ double lds[];
+  int64_t lb;
+  const TiledArgs& A = seg_of(g, blockIdx.x, lb);
+  // XCD-aware order: workgroups are dealt round-robin over the eight XCDs, so block lb runs on
+  // XCD lb % 8; that XCD takes a contiguous range of target patches, whose neighbours share
+  // near patches, so their densities are reused from the XCD's L2
+  const int64_t M = A.n_patches;
+  const int64_t xq = M / kXcds, xr = M % kXcds, xc = lb % kXcds;
+  const int64_t T = xc * xq + (xc < xr ? xc : xr) + lb / kXcds;
   const int64_t N = A.N;
   const int q2 = A.q2;
+  const int rows = (q2 + 15) & ~15;
+  double* sC = lds;
+  double* sS = lds + (size_t)rows * kLdC;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = lane % RB, tw = lane / RB;
-  const int npass = (q2 + TPP - 1) / TPP;
-  double acc[kPass];
+  const int kq = lane >> 4, col = lane & 15;
+  const int n_rt = rows / 16;                    // row tiles; wave w takes w, w + 4, ...
+  doublex4 acc[4];
 #pragma unroll
-  for (int ps = 0; ps < kPass; ++ps) acc[ps] = 0.0;
+  for (int k = 0; k < 4; ++k) acc[k] = doublex4{0.0, 0.0, 0.0, 0.0};
   for (int u = A.tile_ptr[T]; u < A.tile_ptr[T + 1]; ++u) {
     const int64_t P = A.tile_patch[u];
-    __syncthreads();   // the previous patch's densities are no longer read
-    for (int e = threadIdx.x; e < q2 * RB; e += 256) {
-      const int rr = e / q2, j = e - rr * q2;   // consecutive threads read consecutive nodes
-      ssig[j * LD + rr] = A.sigma[(int64_t)(A.r0 + rr) * N + P * q2 + j];
-    }
-    __syncthreads();
+    const int32_t* __restrict__ pairs = A.tile_pair + (int64_t)u * q2;
+    for (int kc = 0; kc < q2; kc += kKC) {
+      const int kw = q2 - kc < kKC ? q2 - kc : kKC;   // valid columns in this chunk
+      __syncthreads();   // the previous chunk's slices are no longer read
+      // block slices: row t, columns [kc, kc + kKC): eight lanes per row, four doubles each
+      for (int e = threadIdx.x; e < rows * (kKC / 4); e += 256) {
+        const int t = e / (kKC / 4), c4 = (e - t * (kKC / 4)) * 4;
+        const int pr = t < q2 ? pairs[t] : -1;
+        const double* src = A.Cb + (int64_t)(pr < 0 ? 0 : pr) * q2 + kc + c4;
 #pragma unroll
-    for (int ps = 0; ps < kPass; ++ps) {
-      if (ps < npass) {
-        const int t = ps * TPP + wave * TPW + tw;
-        const int pair = t < q2 ? A.tile_pair[(int64_t)u * q2 + t] : -1;
-        if (pair >= 0) {
-          const double* __restrict__ c = A.Cb + (int64_t)pair * q2;
-          // four partial sums (the row in four interleaved strands) keep four FMAs in flight
-          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-          int j = 0;
-          for (; j + 3 < q2; j += 4) {
-            s0 = fma(c[j], ssig[j * LD + r], s0);
-            s1 = fma(c[j + 1], ssig[(j + 1) * LD + r], s1);
-            s2 = fma(c[j + 2], ssig[(j + 2) * LD + r], s2);
-            s3 = fma(c[j + 3], ssig[(j + 3) * LD + r], s3);
+        for (int c = 0; c < 4; ++c)
+          sC[t * kLdC + c4 + c] = (pr >= 0 && c4 + c < kw) ? src[c] : 0.0;
+      }
+      // sigma slice: node kc + k of P for right-hand side r (unit stride in k)
+      for (int e = threadIdx.x; e < kKC * 16; e += 256) {
+        const int r = e / kKC, k = e - r * kKC;
+        sS[k * 16 + r] = (r < RB && k < kw) ? A.sigma[(int64_t)(A.r0 + r) * N + P * q2 + kc + k] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < kKC; ks += 4) {
+        const double b = sS[(ks + kq) * 16 + col];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int rt = wave + 4 * k;
+          if (rt < n_rt) {
+            const double a = sC[(rt * 16 + col) * kLdC + ks + kq];
+            acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
           }
-          for (; j < q2; ++j) s0 = fma(c[j], ssig[j * LD + r], s0);
-          acc[ps] += (s0 + s1) + (s2 + s3);
         }
       }
     }
   }
+  __syncthreads();   // every wave is done with sC: it becomes the output tile
+  double* sY = lds;
 #pragma unroll
-  for (int ps = 0; ps < kPass; ++ps) {
-    const int t = ps * TPP + wave * TPW + tw;
-    if (ps < npass && t < q2) {
-      const int64_t i = T * q2 + t;
-      const int64_t at = (int64_t)(A.r0 + r) * N + i;
-      A.y[at] = acc[ps] + A.sigma[at] + A.ssum[A.r0 + r];
+  for (int k = 0; k < 4; ++k) {
+    const int rt = wave + 4 * k;
+    if (rt < n_rt) {
+      // FP64 16x16x4 accumulators: register i of lane l holds row 4 i + l / 16, column l % 16
+      // (the FP32 16x16x4 form holds row 4 (l / 16) + i instead)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sY[(rt * 16 + 4 * i + kq) * kLdY + col] = acc[k][i];
     }
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < RB * q2; e += 256) {
+    const int r = e / q2, t = e - r * q2;
+    const int64_t at = (int64_t)(A.r0 + r) * N + T * q2 + t;
+    A.y[at] = sY[t * kLdY + r] + A.sigma[at] + A.ssum[A.r0 + r];
+  }
 }
+
+// LDS bytes of k_near_tiled for patches of q2 nodes; patches of more than 14 x 14 nodes would
+// need more than the default 64 KiB of a workgroup and take the per-target kernel instead.
+size_t near_tiled_lds(int q2) {
+  const size_t rows = (size_t)((q2 + 15) & ~15);
+  const size_t a = rows * kLdC + (size_t)kKC * 16, b = rows * kLdY;
+  return (a > b ? a : b) * sizeof(double);
+}
+
+bool near_tiled_fits(int q2) { return near_tiled_lds(q2) <= 65536; }
 
 namespace {
 void size_prep_buffers(pmx_operator* op, int n_rhs, bool need32) {
@@ -431,7 +476,8 @@ void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_
 void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
   // whole groups of 16 (then 8) right-hand sides by target patch, the rest per target
   bool tiles = n_rhs >= 8;
-  for (const ApplyJob& j : jobs) tiles = tiles && j.op->nl.have_tiles;
+  for (const ApplyJob& j : jobs)
+    tiles = tiles && j.op->nl.have_tiles && near_tiled_fits(j.op->s->g.q * j.op->s->g.q);
   int r0 = 0;
   while (tiles && n_rhs - r0 >= 8) {
     const int rb = n_rhs - r0 >= 16 ? 16 : 8;
@@ -440,14 +486,13 @@ void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t s
     for (const ApplyJob& j : jobs) {
       pmx_operator* op = j.op;
       const int q2 = op->s->g.q * op->s->g.q;
-      ta.push_back({op->s->g.N, q2, r0, op->nl.tile_ptr.p, op->nl.tile_patch.p, op->nl.tile_pair.p, op->nl.C.p,
-                    j.sigma, op->ssum.p, j.y});
+      ta.push_back({op->s->g.N, op->s->g.M, q2, r0, op->nl.tile_ptr.p, op->nl.tile_patch.p, op->nl.tile_pair.p,
+                    op->nl.C.p, j.sigma, op->ssum.p, j.y});
       tb.push_back(op->s->g.M);
     }
-    const int q2 = jobs[0].op->s->g.q * jobs[0].op->s->g.q;   // grouped operators share one LDS size
-    int q2max = q2;
+    int q2max = 0;   // grouped operators share one LDS size
     for (const ApplyJob& j : jobs) q2max = std::max(q2max, j.op->s->g.q * j.op->s->g.q);
-    const size_t lds = (size_t)q2max * (rb + 1) * sizeof(double);
+    const size_t lds = near_tiled_lds(q2max);
     launch_grouped(ta, tb, [&](const Group<TiledArgs>& g, int64_t nb) {
       if (rb == 16) hipLaunchKernelGGL(k_near_tiled<16>, dim3((unsigned)nb), dim3(256), lds, st, g);
       else hipLaunchKernelGGL(k_near_tiled<8>, dim3((unsigned)nb), dim3(256), lds, st, g);

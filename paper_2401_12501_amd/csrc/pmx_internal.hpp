@@ -398,7 +398,7 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
 void fmm_build(pmx_operator* op, hipStream_t st);
 void fmm_destroy(FMM* f);
 // y_r += far field of sigma_r for every job.  After the source permutation of each rhs,
-// the P2P sums run on `side` while P2M, M2M, M2L (with its slot sums) and L2L run on st;
+// the P2P sums run on `side` while P2M, M2M, M2L, its slot sum and L2L run on st;
 // side_work(side) is called once, before the first P2P launch, and st waits for side
 // before each L2P launch (which adds into y), so side_work may write y.  side == st runs
 // everything on one stream in the same order (events unused).
