@@ -234,12 +234,12 @@ def test_nbody_wavy_torus_order_decay(ctx):
     assert errs[6] * 20 <= errs[4]
 
 
-def test_m2l_fused_slot_sums_repeatable(ctx):
-    """The M2L launch sums each box's output slots itself: the workgroup that writes a box's last
-    slot sums them, in slot order, after a device-scope acquire.  Which workgroup that is varies
-    from launch to launch, the order of the sum does not: 40 mixed applies on 38,400 nodes with
-    64-point leaves (many boxes, sources spread over every workgroup) give identical bits, and
-    so do the 16- and 14-wave layouts (one stream, and beside the second stream)."""
+def test_mixed_apply_repeatable(ctx):
+    """The mixed apply's reductions (M2L output slots summed per box in slot order, P2P partials in
+    slot order, fixed-order near sums) do not depend on scheduling: 20 mixed applies on 38,400
+    nodes with 64-point leaves (many boxes and M2L work items spread over every workgroup) give
+    identical bits, and so do the 16- and 14-wave M2L layouts (one stream, and beside the second
+    stream)."""
     from paper_2401_12501_amd import pmx
     p = ellipsoid_problem(k=8, q=10)
     sig = random_density(p.n, 1, seed=91).T.copy()
@@ -255,5 +255,5 @@ def test_m2l_fused_slot_sums_repeatable(ctx):
             assert np.array_equal(y, ys[0])
         out[ov] = ys[0]
         st = op.stats()
-        say(f"[m2l fused] overlap {ov}: {st.fmm_boxes} boxes, {st.fmm_m2l_pairs} pairs, 20 applies identical")
+        say(f"[repeatable] overlap {ov}: {st.fmm_boxes} boxes, {st.fmm_m2l_pairs} pairs, 20 applies identical")
     assert np.array_equal(out[0], out[1])
