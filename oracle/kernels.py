@@ -1,19 +1,27 @@
 """Parametrix and remainder kernels (oracle, FP64).
 
-Section 4.1: for c = 0 the planar Green's function is G(r; a) = log(r) / (2 pi a)
-and the parametrix is K(x, x') = G(|x - x'|; a(x')) with the coefficient taken at
-the source.  eq:explicit_remainder gives the remainder for x != x':
+Section 4.1: the planar Green's function G(r; a, c) of (a Delta_2 + c) G = delta is
+G = log(r) / (2 pi a) for c = 0; the parametrix is K(x, x') = G(|x - x'|; a(x'), c(x'))
+with the coefficients taken at the source.  For c != 0 the paper prints
+G = (i / 4a) H0(sqrt(c/a) r), whose log part, -log(r) / (2 pi a), has the opposite sign of
+the c = 0 function: it solves (a Delta_2 + c) G = -delta.  We read G = -(i / 4a) H0(sqrt(c/a) r),
+which for c < 0 (modified Helmholtz type) is the real function
+    G = -K0(kappa r) / (2 pi a),   kappa = sqrt(-c / a)
+(H0(i z) = (2 / (i pi)) K0(z)), and tends to log(r) / (2 pi a) + const as c -> 0.
+eq:explicit_remainder gives the remainder for x != x':
 
   R = grad_G a(x) . r_hat G'  -  a(x) G'' (n.r)^2 / r^2  +  a(x) G' (n.r)^2 / r^3
-      - 2 a(x) H(x) (n . r_hat) G'                       (c = 0 term dropped)
+      - 2 a(x) H(x) (n . r_hat) G'  +  (c(x) - a(x) c(x') / a(x')) G
 
 with r = x - x', G' = dG/dr and G'' = d^2G/dr^2 (the definition line prints
 G'' = d^2/dr^2 G', which we read as the second derivative of G).  Target
-quantities n, H, a, grad_G a are at x.
+quantities n, H, a, c, grad_G a are at x.  The modified Bessel functions K0, K1 come
+from the library (scipy.special).
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.special as sp
 
 INV_2PI = 1.0 / (2.0 * np.pi)
 
@@ -26,22 +34,48 @@ def green_c0(r, a):
     return G, G1, G2
 
 
-def remainder(x, n, H, a_t, gs_t, y, a_s):
-    """R(x, y) of eq:explicit_remainder with c = 0; broadcasts over leading axes.
+def green_neg_c(r, a, c):
+    """G(r; a, c) = -K0(kappa r) / (2 pi a), kappa = sqrt(-c/a), c < 0, and its first two
+    r-derivatives: G' = kappa K1(kappa r) / (2 pi a) (K0' = -K1) and
+    G'' = -kappa^2 (K0(kappa r) + K1(kappa r) / (kappa r)) / (2 pi a) (K1'(z) = -K0(z) - K1(z)/z)."""
+    kappa = np.sqrt(-c / a)
+    z = kappa * r
+    k0, k1 = sp.k0(z), sp.k1(z)
+    G = -k0 / (2 * np.pi * a)
+    G1 = kappa * k1 / (2 * np.pi * a)
+    G2 = -kappa ** 2 * (k0 + k1 / z) / (2 * np.pi * a)
+    return G, G1, G2
+
+
+def green(r, a, c=None):
+    """G, G', G'' of the planar Green's function: c = None (c = 0) or c < 0 (every entry)."""
+    if c is None:
+        return green_c0(r, a)
+    if np.any(np.asarray(c) >= 0):
+        raise ValueError("the oracle's c != 0 kernels need c < 0")
+    return green_neg_c(r, a, c)
+
+
+def remainder(x, n, H, a_t, gs_t, y, a_s, c_t=None, c_s=None):
+    """R(x, y) of eq:explicit_remainder; broadcasts over leading axes.
 
     x, n, gs_t: (..., 3) target position, unit normal, surface gradient of a;
     H, a_t: (...) target mean curvature and coefficient; y: (..., 3) source
-    position; a_s: (...) coefficient at the source.
+    position; a_s: (...) coefficient at the source; c_t, c_s: c at the target and the
+    source (None: c = 0, the Laplace-Beltrami type).
     """
     r = x - y
     rn = np.linalg.norm(r, axis=-1)
     rhat = r / rn[..., None]
-    _, G1, G2 = green_c0(rn, a_s)
+    G, G1, G2 = green(rn, a_s, c_s)
     nr = np.sum(n * r, axis=-1)
-    return (np.sum(gs_t * rhat, axis=-1) * G1
-            - a_t * G2 * nr ** 2 / rn ** 2
-            + a_t * G1 * nr ** 2 / rn ** 3
-            - 2 * a_t * H * (nr / rn) * G1)
+    R = (np.sum(gs_t * rhat, axis=-1) * G1
+         - a_t * G2 * nr ** 2 / rn ** 2
+         + a_t * G1 * nr ** 2 / rn ** 3
+         - 2 * a_t * H * (nr / rn) * G1)
+    if c_s is not None:
+        R = R + (c_t - a_t * c_s / a_s) * G
+    return R
 
 
 def remainder_lb(x, n, H, y):
@@ -52,6 +86,8 @@ def remainder_lb(x, n, H, y):
     return t * t / np.pi - H * t / np.pi
 
 
-def parametrix(x, y, a_s):
-    """K(x, y) = log|x - y| / (2 pi a(y))."""
-    return np.log(np.linalg.norm(x - y, axis=-1)) / (2 * np.pi * a_s)
+def parametrix(x, y, a_s, c_s=None):
+    """K(x, y) = G(|x - y|; a(y), c(y)): log|x - y| / (2 pi a(y)) for c = 0."""
+    if c_s is None:
+        return np.log(np.linalg.norm(x - y, axis=-1)) / (2 * np.pi * a_s)
+    return green(np.linalg.norm(x - y, axis=-1), a_s, c_s)[0]

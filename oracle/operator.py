@@ -18,6 +18,12 @@ The rank-one term is Section 3's "adding the term int_G sigma", taken
 unscaled.  The representation u = K[sigma] (eq:representation) uses the same
 rules with the parametrix, then the weighted mean is removed so that u is the
 mean-zero solution.
+
+With c != 0 (here c < 0 at every node, the modified Helmholtz type) the problem has no
+null space: the system is sigma + R[sigma] = f (Theorem thm:second_kind), f is taken as
+given and u = K[sigma] is not shifted.  R and K then carry the c-dependent Green's
+function (``kernels``), c is interpolated on a patch like a, and the self rule integrates R
+with the log-graded radial panels, since R then has r^m log r parts.
 """
 from __future__ import annotations
 
@@ -33,7 +39,7 @@ class OracleOperator:
     """Plain FP64 discretization of eq:IE on a quad-patch surface."""
 
     def __init__(self, q, x, xu, xv, xuu, xuv, xvv, a, grad_a, eta: float = 1.5, n_gl: int = 16,
-                 split: float = 2.0):
+                 split: float = 2.0, c=None):
         self.q = q
         self.N = x.shape[0]
         self.M = self.N // (q * q)
@@ -50,20 +56,30 @@ class OracleOperator:
         self._P_xu = patch_nodes(xu, q)
         self._P_xv = patch_nodes(xv, q)
         self._P_a = patch_nodes(self.a[:, None], q)
+        self.c = None if c is None else np.asarray(c, dtype=np.float64)
+        if self.c is not None and np.any(self.c >= 0):
+            raise ValueError("c must be negative at every node (or None for c = 0)")
+        self._P_c = None if self.c is None else patch_nodes(self.c[:, None], q)
         self._self_cache = {}
 
     @classmethod
     def from_problem(cls, prob, **kw):
         s = prob.surface
+        if getattr(prob, "c", None) is not None and "c" not in kw:
+            kw["c"] = prob.c
         return cls(s.q, s.x, s.xu, s.xv, s.xuu, s.xuv, s.xvv, prob.a, prob.grad_a, **kw)
+
+    def _c(self, idx):
+        return None if self.c is None else self.c[idx]
 
     # ----------------------------------------------------------------- kernels at nodes
     def R_row(self, i: int, js) -> np.ndarray:
         """R(x_i, x_j) for node indices js (all must differ from i)."""
-        return remainder(self.x[i], self.n[i], self.H[i], self.a[i], self.gs[i], self.x[js], self.a[js])
+        return remainder(self.x[i], self.n[i], self.H[i], self.a[i], self.gs[i], self.x[js], self.a[js],
+                         self._c(i), self._c(js))
 
     def K_row(self, i: int, js) -> np.ndarray:
-        return parametrix(self.x[i], self.x[js], self.a[js])
+        return parametrix(self.x[i], self.x[js], self.a[js], self._c(js))
 
     # ----------------------------------------------------------------- near lists
     def near(self, targets) -> list:
@@ -91,19 +107,21 @@ class OracleOperator:
             for k in kernels:
                 out.update(self.pair_weights(i, P, (k,)))
             return out
-        u, v, wq = self.rule_points(i, P, "log" if kernels == ("K",) else "plain")
+        radial = "log" if (kernels == ("K",) or self.c is not None) else "plain"
+        u, v, wq = self.rule_points(i, P, radial)
         Lu = lagrange_basis(self.tnodes, u)
         Lv = lagrange_basis(self.tnodes, v)
         interp = lambda Xp: tensor_interp(Lu, Lv, Xp)
         y = interp(self._P_x[P])
         Jt = np.linalg.norm(np.cross(interp(self._P_xu[P]), interp(self._P_xv[P])), axis=1)
         a_s = interp(self._P_a[P])[:, 0]
+        c_s = None if self.c is None else interp(self._P_c[P])[:, 0]
         out = {}
         for kernel in kernels:
             if kernel == "R":
-                F = remainder(self.x[i], self.n[i], self.H[i], self.a[i], self.gs[i], y, a_s)
+                F = remainder(self.x[i], self.n[i], self.H[i], self.a[i], self.gs[i], y, a_s, self._c(i), c_s)
             elif kernel == "K":
-                F = parametrix(self.x[i], y, a_s)
+                F = parametrix(self.x[i], y, a_s, c_s)
             elif kernel == "one":
                 F = np.ones_like(a_s)
             else:
@@ -153,7 +171,9 @@ class OracleOperator:
         if blocks is None:
             blocks = self.blocks(targets)
         q2 = self.q * self.q
-        y = sigma[targets] + self.far_rows(targets, sigma) + (self.w @ sigma)[None, :]
+        y = sigma[targets] + self.far_rows(targets, sigma)
+        if self.c is None:
+            y += (self.w @ sigma)[None, :]
         for t, (plist, C) in enumerate(blocks):
             for P, Cb in zip(plist, C["R"]):
                 y[t] += Cb @ sigma[P * q2:(P + 1) * q2]
@@ -169,7 +189,9 @@ class OracleOperator:
             js = np.arange(N)
             js = js[js != i]
             A[i, js] = self.w[js] * self.R_row(i, js)
-        A += np.eye(N) + self.w[None, :]
+        A += np.eye(N)
+        if self.c is None:
+            A += self.w[None, :]
         for i, (plist, C) in zip(range(N), blocks):
             for P, Cb in zip(plist, C["R"]):
                 A[i, P * q2:(P + 1) * q2] += Cb
@@ -182,8 +204,11 @@ class OracleOperator:
 
     # ----------------------------------------------------------------- solve
     def project_mean_zero(self, f: np.ndarray):
-        """f - (sum w f)/(sum w): the c = 0 problem needs mean-zero data (Section 2.3)."""
+        """f - (sum w f)/(sum w): the c = 0 problem needs mean-zero data (Section 2.3).
+        With c != 0 f is used as given (mean reported as 0)."""
         f = f.reshape(self.N, -1)
+        if self.c is not None:
+            return f.copy(), np.zeros(f.shape[1])
         mean = (self.w @ f) / self.w.sum()
         return f - mean[None, :], mean
 
@@ -219,5 +244,6 @@ class OracleOperator:
         for t, (plist, D) in enumerate(blocks):
             for P, Db in zip(plist, D["K"]):
                 u[t] += Db @ sigma[P * q2:(P + 1) * q2]
-        u -= ((self.w @ u) / self.w.sum())[None, :]
+        if self.c is None:
+            u -= ((self.w @ u) / self.w.sum())[None, :]
         return u

@@ -7,5 +7,6 @@ right-hand sides.
 from .surfaces import Surface, cube_sphere, torus, gl_nodes, real_sph_harm_cartesian  # noqa: F401
 from .configs import (  # noqa: F401
     Problem, sphere_problem, ellipsoid_problem, star_problem, wobbly_torus_problem, wavy_torus_problem,
+    helmholtz_sphere_problem, helmholtz_ellipsoid_problem,
     serving_requests, random_density,
 )

@@ -30,7 +30,8 @@ from .surfaces import Surface, cube_sphere, real_sph_harm_cartesian, torus
 
 __all__ = [
     "Problem", "sphere_problem", "ellipsoid_problem", "star_problem", "wobbly_torus_problem",
-    "wavy_torus_problem", "serving_requests", "random_density",
+    "wavy_torus_problem", "helmholtz_sphere_problem", "helmholtz_ellipsoid_problem", "serving_requests",
+    "random_density",
 ]
 
 
@@ -42,6 +43,7 @@ class Problem:
     f: np.ndarray            # (N, n_rhs)
     name: str = ""
     meta: dict = field(default_factory=dict)
+    c: np.ndarray | None = None   # (N,) zero-order coefficient c < 0, or None for c = 0
 
     @property
     def n(self) -> int:
@@ -107,6 +109,37 @@ def wobbly_torus_problem(n_theta: int = 256, n_phi: int = 128, q: int = 8, n_rhs
     a, ga = F.eval_field(F.a_tanh_sin, s.x)
     f = np.stack([F.solid_harmonic_rhs(s.x, 4 * 100 + r) for r in range(n_rhs)], axis=1)
     return Problem(s, a, ga, f, name=f"wobbly_torus_{n_theta}x{n_phi}_q{q}")
+
+
+def helmholtz_sphere_problem(k: int = 2, q: int = 8, c0: float | None = None) -> Problem:
+    """Unit sphere for div_G(a grad_G u) + c u = f with c < 0 (the modified Helmholtz type).
+
+    c0 given: a = 1 and c = c0 (constant; f = 0, the caller chooses f, e.g. spherical harmonics).
+    c0 None: a = 2 + x3 and c = -4 - exp(x1 / 2), with the manufactured solution u = (x^2 - y^2) z
+    (a degree-3 harmonic, Delta_G u = -12 u on the unit sphere):
+    f = grad_G a . grad_G u - 12 a u + c u.
+    """
+    s = cube_sphere(k, q, name="sphere")
+    if c0 is not None:
+        a, ga = F.eval_field(F.a_const(1.0), s.x)
+        c = np.full(s.n, float(c0))
+        return Problem(s, a, ga, np.zeros((s.n, 1)), name=f"helmholtz_sphere_k{k}_q{q}_c{c0}", c=c)
+    a_fn = F.a_linear_z
+    a, ga = F.eval_field(a_fn, s.x)
+    c, _ = F.eval_field(F.c_exp_x, s.x)
+    f, u = _sphere_manufactured_rhs(s.x, a_fn)
+    return Problem(s, a, ga, (f + c * u)[:, None], name=f"helmholtz_sphere_k{k}_q{q}_var", c=c,
+                   meta={"u_exact": u})
+
+
+def helmholtz_ellipsoid_problem(k: int = 4, q: int = 8, axes=(1.0, 0.8, 0.6), seed: int = 1, n_rhs: int = 1):
+    """Ellipsoid with the variable coefficients a = 2 + x3 and c = -4 - exp(x1 / 2) (c < 0) and
+    right-hand sides of 20 solid harmonics (seeded)."""
+    s = cube_sphere(k, q, axes=axes, name="ellipsoid")
+    a, ga = F.eval_field(F.a_linear_z, s.x)
+    c, _ = F.eval_field(F.c_exp_x, s.x)
+    f = np.stack([F.solid_harmonic_rhs(s.x, seed + 100 * r) for r in range(n_rhs)], axis=1)
+    return Problem(s, a, ga, f, name=f"helmholtz_ellipsoid_k{k}_q{q}", c=c)
 
 
 def wavy_torus_problem(n_u: int = 51, n_v: int = 18, q: int = 8, seed: int = 5) -> Problem:

@@ -16,7 +16,7 @@ import torch
 from .surfaces import real_sph_harm_cartesian
 
 __all__ = [
-    "eval_field", "a_const", "a_sphere_cfg", "a_exp_xy", "a_seed_field", "a_tanh_sin",
+    "eval_field", "a_const", "a_sphere_cfg", "a_exp_xy", "a_seed_field", "a_tanh_sin", "a_linear_z", "c_exp_x",
     "solid_harmonic_rhs", "harmonic_basis_lm",
 ]
 
@@ -46,6 +46,16 @@ def a_exp_xy(X):
 def a_tanh_sin(X):
     """a(x) = 1 + 0.5 tanh(sin(3 x1))."""
     return 1.0 + 0.5 * torch.tanh(torch.sin(3 * X[:, 0]))
+
+
+def a_linear_z(X):
+    """a(x) = 2 + x3: linear in z, a factor of three over the unit sphere."""
+    return 2.0 + X[:, 2]
+
+
+def c_exp_x(X):
+    """c(x) = -4 - exp(x1 / 2) (negative everywhere: the modified Helmholtz type)."""
+    return -4.0 - torch.exp(0.5 * X[:, 0])
 
 
 def a_seed_field(seed: int, n_modes: int = 8):
