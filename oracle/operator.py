@@ -23,7 +23,7 @@ With c != 0 (here c < 0 at every node, the modified Helmholtz type) the problem 
 null space: the system is sigma + R[sigma] = f (Theorem thm:second_kind), f is taken as
 given and u = K[sigma] is not shifted.  R and K then carry the c-dependent Green's
 function (``kernels``), c is interpolated on a patch like a, and the self rule integrates R
-with the log-graded radial panels, since R then has r^m log r parts.
+on dyadically graded radial panels, since R then has r^m log r parts.
 """
 from __future__ import annotations
 
@@ -107,7 +107,7 @@ class OracleOperator:
             for k in kernels:
                 out.update(self.pair_weights(i, P, (k,)))
             return out
-        radial = "log" if (kernels == ("K",) or self.c is not None) else "plain"
+        radial = "log" if kernels == ("K",) else ("dyadic" if self.c is not None else "plain")
         u, v, wq = self.rule_points(i, P, radial)
         Lu = lagrange_basis(self.tnodes, u)
         Lv = lagrange_basis(self.tnodes, v)

@@ -55,19 +55,26 @@ def _radial_rule(n_gl: int, radial: str):
     "log": F has a log(rho) singularity (the parametrix K): dyadic panels
     [1/2, 1], [1/4, 1/2], [1/8, 1/4] and an innermost [0, 1/8] panel in the
     variable t with rho = t^3 / 8, which makes rho log(rho) drho smooth in t.
+    "dyadic": the same four dyadic panels, each a plain Gauss-Legendre panel in rho
+    (the remainder R with c != 0, whose rho^m log(rho) parts, m >= 2 with the
+    Jacobian, need the grading but not the t^3 map: that map puts points within
+    1e-10 of the target, where r = x - y keeps too few digits of its normal component
+    for R's (n.r)^2 / r^4 terms).
     """
     tg, wg = gauss_legendre(n_gl)
     t = 0.5 * (tg + 1.0)
     wt = 0.5 * wg
     if radial == "plain":
         return t, wt * t
-    if radial != "log":
+    if radial not in ("log", "dyadic"):
         raise ValueError(radial)
     s_parts, w_parts = [], []
-    for a, b in ((0.5, 1.0), (0.25, 0.5), (0.125, 0.25)):
+    for a, b in ((0.5, 1.0), (0.25, 0.5), (0.125, 0.25)) + (((0.0, 0.125),) if radial == "dyadic" else ()):
         s = a + (b - a) * t
         s_parts.append(s)
         w_parts.append((b - a) * wt * s)
+    if radial == "dyadic":
+        return np.concatenate(s_parts), np.concatenate(w_parts)
     # rho = t^3 / 8: rho drho = (t^3 / 8) (3 t^2 / 8) dt
     s_parts.append(t ** 3 / 8.0)
     w_parts.append(wt * 3.0 * t ** 5 / 64.0)

@@ -193,6 +193,27 @@ def test_self_rule_paper_test_functions(sig):
             assert abs(np.sum(w * np.log(np.hypot(u - u0, v - v0))) - _square_log(u0, v0)) < 1e-13
 
 
+def test_self_rule_dyadic_radial():
+    """The radial rule used for R when c != 0: four dyadic Gauss-Legendre panels in rho.  Along a
+    ray, with the polar Jacobian, int_0^1 rho^(m+1) log(rho) drho = -1 / (m+2)^2 (the rho^m log rho
+    parts of R); on the square, 1 and r^2 log r against the area and the library quadrature split
+    at the target."""
+    from oracle.rules import _radial_rule
+    s, w = _radial_rule(16, "dyadic")
+    assert np.all((s > 1.0 / 8.0 / 16.0 ** 2) & (s < 1.0))          # no point crowds the target
+    for m, tol in ((1, 1e-9), (2, 1e-12), (3, 1e-14)):
+        assert abs(np.sum(w * s ** m * np.log(s)) + 1.0 / (m + 2) ** 2) < tol * (m + 2) ** -2
+    for m in range(0, 30):
+        assert abs(np.sum(w * s ** m) - 1.0 / (m + 2)) < 1e-15
+    t, _ = gauss_legendre(10)
+    for u0, v0 in ((t[0], t[0]), (t[5], t[4]), (0.3, -0.96)):
+        u, v, w2 = self_rule(u0, v0, radial="dyadic")
+        assert abs(w2.sum() - 4.0) < 1e-13
+        F = lambda uu, vv: ((uu - u0) ** 2 + (vv - v0) ** 2) * np.log(np.hypot(uu - u0, vv - v0))
+        ref = _split_dblquad(F, u0, v0)
+        assert abs(np.sum(w2 * F(u, v)) - ref) < 1e-10
+
+
 def test_self_rule_angular_panels():
     """Angular panels split where L(theta) doubles: every panel varies L at most 2x."""
     u0, v0 = 0.97, -0.2
