@@ -143,6 +143,21 @@ PMX_API void pmx_surface_destroy(pmx_surface* s);
  * Errors: INVALID (a <= 0 or non-finite), TOO_LARGE (budget), OOM, DEVICE. */
 PMX_API pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* grad_a, const pmx_options* opts,
                                int mem_kind, void* stream, pmx_operator** out);
+/* Operator of the general surface PDE div_G(a grad_G u) + c u = f (eq:surf_PDE with b = 0) for a
+ * coefficient c < 0 at every node (N values; the modified Helmholtz-Beltrami type, Section 4.1 and
+ * Section 7).  The parametrix uses G(r; a, c) = -K0(sqrt(-c/a) r) / (2 pi a) with the coefficients
+ * at the source (eq:diff_param; the printed Hankel form read with the sign for which
+ * (a Delta + c) G = delta) and the remainder of eq:explicit_remainder with its c-term.  With c != 0
+ * the problem has no null space: the system is sigma + R sigma = f (Theorem thm:second_kind, no
+ * rank-one term), f is used as given (info.removed_mean = 0) and u = K sigma is not shifted.
+ * Only the FP64 direct far field is available (PMX_PREC_FP64_DIRECT for pmx_apply, pmx_solve and
+ * the allocation-free apply; other precisions give INVALID): the FMM's translation operators need a
+ * kernel of x - y alone up to a per-source factor, while here the decay rate sqrt(-c/a) changes from
+ * source to source.  Arguments as for pmx_operator_create, plus c (N, mem_kind memory).
+ * Errors: INVALID (c null, c >= 0 or non-finite at some node, and as pmx_operator_create), TOO_LARGE,
+ * OOM, DEVICE. */
+PMX_API pmx_status pmx_operator_create_c(pmx_surface* s, const double* a, const double* grad_a, const double* c,
+                                 const pmx_options* opts, int mem_kind, void* stream, pmx_operator** out);
 PMX_API void pmx_operator_destroy(pmx_operator* op);
 PMX_API pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* out);
 

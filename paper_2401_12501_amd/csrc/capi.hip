@@ -123,7 +123,7 @@ void represent_device(pmx_operator* op, int n_rhs, const double* sigma, double* 
   far_direct_log(op, n_rhs, st);
   op->prof.end(t, st);
   near_combine(op, sigma, u, n_rhs, far_direct_chunks(op, true), true, st);
-  weighted_mean_remove(op, u, n_rhs, st);
+  if (!op->co.has_c()) weighted_mean_remove(op, u, n_rhs, st);   // c = 0: the mean-zero solution
 }
 
 }  // namespace pmx
@@ -301,8 +301,9 @@ pmx_status pmx_surface_create(pmx_ctx* ctx, int n_patches, int q, const double* 
 
 void pmx_surface_destroy(pmx_surface* s) { delete s; }
 
-pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* grad_a, const pmx_options* opts,
-                               int mem_kind, void* stream, pmx_operator** out) {
+namespace {
+pmx_status operator_create(pmx_surface* s, const double* a, const double* grad_a, const double* c,
+                           const pmx_options* opts, int mem_kind, void* stream, pmx_operator** out) {
   return guarded([&] {
     PMX_REQUIRE(s && out, PMX_ERR_INVALID, "null handle");
     *out = nullptr;
@@ -315,10 +316,11 @@ pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* gr
       check_opts(op->opts);
       const double t0 = now_seconds();
       Ctx* ctx = &s->ctx->c;
-      DBuf<double> ba, bg;
+      DBuf<double> ba, bg, bc;
       const double* da = stage_in(ctx, ba, a, s->g.N, mem_kind, st);
       const double* dg = stage_in(ctx, bg, grad_a, 3 * (size_t)s->g.N, mem_kind, st);
-      build_coeff(ctx, s->g, op->co, da, dg, st);
+      const double* dc = c ? stage_in(ctx, bc, c, s->g.N, mem_kind, st) : nullptr;
+      build_coeff(ctx, s->g, op->co, da, dg, dc, st);
       build_near_lists(ctx, s->g, op->opts.eta_near, op->nl, st);
       build_near_weights(ctx, s->g, op->co, op->nl, op->opts, false, st);
       PMX_HIP(hipStreamSynchronize(st));
@@ -330,6 +332,22 @@ pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* gr
     }
     *out = op;
   });
+}
+}  // namespace
+
+pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* grad_a, const pmx_options* opts,
+                               int mem_kind, void* stream, pmx_operator** out) {
+  return operator_create(s, a, grad_a, nullptr, opts, mem_kind, stream, out);
+}
+
+pmx_status pmx_operator_create_c(pmx_surface* s, const double* a, const double* grad_a, const double* c,
+                                 const pmx_options* opts, int mem_kind, void* stream, pmx_operator** out) {
+  if (!c) {
+    set_last_error("c is null (use pmx_operator_create for c = 0)");
+    if (out) *out = nullptr;
+    return PMX_ERR_INVALID;
+  }
+  return operator_create(s, a, grad_a, c, opts, mem_kind, stream, out);
 }
 
 void pmx_operator_destroy(pmx_operator* op) {
@@ -368,6 +386,8 @@ pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const double* s
   return guarded([&] {
     PMX_REQUIRE(op && sigma && y, PMX_ERR_INVALID, "null argument");
     PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    PMX_REQUIRE(!op->co.has_c() || precision == PMX_PREC_FP64_DIRECT, PMX_ERR_INVALID,
+                "with c != 0 only the FP64 direct far field is available");
     PMX_HIP(hipSetDevice(op->s->ctx->c.device));
     hipStream_t st = (hipStream_t)stream;
     Ctx* ctx = &op->s->ctx->c;
@@ -415,7 +435,7 @@ pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, d
     at += up(nr);
     const int g = n_rhs >= 16 ? 16 : (n_rhs >= 8 ? 8 : (n_rhs >= 4 ? 4 : (n_rhs >= 2 ? 2 : 1)));
     sc.rows = base + at;
-    at += up((size_t)((3 + g + 1) / 2) * 2 * N);
+    at += up((size_t)((4 + g + 1) / 2) * 2 * N);
     sc.part = base + at;
     hipStream_t st = (hipStream_t)stream;
     const std::vector<ApplyJob> jobs{ApplyJob{op, sigma, y, &sc}};
@@ -435,6 +455,8 @@ pmx_status pmx_solve(pmx_operator* op, const pmx_options* opts, int n_rhs, const
     hipStream_t st = (hipStream_t)stream;
     pmx_options o = opts ? *opts : op->opts;
     check_opts(o);
+    PMX_REQUIRE(!op->co.has_c() || o.precision == PMX_PREC_FP64_DIRECT, PMX_ERR_INVALID,
+                "with c != 0 only the FP64 path (PMX_PREC_FP64_DIRECT) is available");
     Ctx* ctx = &op->s->ctx->c;
     const size_t n = (size_t)n_rhs * op->s->g.N;
     const double t0 = now_seconds();

@@ -194,6 +194,99 @@ __global__ void __launch_bounds__(kBlock) k_direct_log(int64_t N, const double* 
   }
 }
 
+// c < 0 (the modified Helmholtz type).  Packed source rows (x, y, z, kappa, qt_1 .. qt_NR, pad),
+// kappa = sqrt(-c / a) at the source.  With z = kappa r, k0, k1 = K0(z), K1(z):
+//   w_j R(x_i, x_j) sigma_j = qt_j { kappa k1 [g.r/r + 2 at2 (n.r)^2/r^3 - B n.r/r]
+//                                    + at2 kappa^2 k0 ((n.r)^2/r^2 - 1) - ct2 k0 },
+// the eq:explicit_remainder terms with G = -K0(kappa r) / (2 pi a') (target factors g = grad_G
+// a / (2 pi), at2 = a / (2 pi), B = a H / pi, ct2 = c / (2 pi)).  The self pair is removed by a
+// zero factor (its argument is kept away from zero so that every value stays finite).
+template <int NR>
+constexpr int row_len_c() { return ((4 + NR + 1) / 2) * 2; }
+
+struct PackCArgs {
+  int64_t N;
+  const double* X;       // 3N SoA
+  const double* a;       // N
+  const double* c;       // N
+  const double* q;       // densities of the group's first right-hand side (qt = w sigma / a)
+  int64_t ldq;
+  double* rows;
+};
+
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_pack_sources_c(PackCArgs A) {
+  constexpr int RL = row_len_c<NR>();
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= A.N) return;
+  const int64_t N = A.N;
+  double v[RL];
+  v[0] = A.X[j];
+  v[1] = A.X[N + j];
+  v[2] = A.X[2 * N + j];
+  v[3] = sqrt(-A.c[j] / A.a[j]);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) v[4 + r] = A.q[r * A.ldq + j];
+#pragma unroll
+  for (int k = 4 + NR; k < RL; ++k) v[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < RL; ++k) A.rows[j * RL + k] = v[k];
+}
+
+struct DirectCArgs {
+  int64_t N, chunk, ldp, ldc;
+  const double* tgt;   // 8N: x y z n A B
+  const double* tg;    // 3N: grad_G a / (2 pi)
+  const double* c;     // N
+  const double* rows;
+  double* part;        // part[chunk][rhs][i]
+  int kernel;          // 0: remainder, 1: parametrix (representation)
+};
+
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_direct64_c(DirectCArgs A) {
+  constexpr int RL = row_len_c<NR>();
+  const int64_t N = A.N;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = i0 < N ? i0 : N - 1;
+  const int64_t j0 = (int64_t)blockIdx.y * A.chunk;
+  const int64_t j1 = j0 + A.chunk < N ? j0 + A.chunk : N;
+  const double xi = A.tgt[i], yi = A.tgt[N + i], zi = A.tgt[2 * N + i];
+  const double nx = A.tgt[3 * N + i], ny = A.tgt[4 * N + i], nz = A.tgt[5 * N + i];
+  const double at2 = 0.5 * A.tgt[6 * N + i], B = A.tgt[7 * N + i];
+  const double gx = A.tg[i], gy = A.tg[N + i], gz = A.tg[2 * N + i];
+  const double ct2 = A.c[i] * 0.15915494309189533577;
+  const sdp S = (sdp)A.rows;
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const sdp row = S + j * RL;
+    const double dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
+    const double rr = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
+    const double ir = rsqrt(rr), rn = rr * ir;
+    const double kap = row[3];
+    double k0, k1;
+    bessel_k01(fmax(kap * rn, 1e-150), k0, k1);
+    double e;
+    if (A.kernel == 0) {
+      const double snr = (nx * dx + ny * dy + nz * dz) * ir;
+      const double gr = gx * dx + gy * dy + gz * dz;
+      const double bra = fma(ir, fma(2.0 * at2 * snr, snr, gr), -B * snr);
+      e = kap * k1 * bra + at2 * kap * kap * k0 * fma(snr, snr, -1.0) - ct2 * k0;
+    } else {
+      e = -k0 * 0.15915494309189533577;
+    }
+    e = j == i ? 0.0 : e;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = fma(row[4 + r], e, acc[r]);
+  }
+  if (i0 < N) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) A.part[(int64_t)blockIdx.y * A.ldc + r * A.ldp + i0] = acc[r];
+  }
+}
+
 namespace {
 // Source chunks so that the grid holds enough workgroups to fill 256 CUs.
 int64_t n_chunks_for(int64_t N) {
@@ -248,8 +341,54 @@ void direct64_group(const std::vector<pmx_operator*>& ops, const std::vector<con
   });
 }
 
-void direct64_all(const std::vector<pmx_operator*>& ops, const std::vector<const ApplyScratch*>& scs, int n_rhs,
-                  hipStream_t st) {
+// c < 0: one operator, right-hand-side groups of NR; kernel 0 remainder, 1 parametrix.
+template <int NR>
+void direct_c_group(pmx_operator* op, const ApplyScratch* sc, int kernel, int n_rhs, int r0, hipStream_t st) {
+  constexpr int RL = row_len_c<NR>();
+  const int64_t N = op->s->g.N;
+  const int64_t nc = n_chunks_for(N);
+  if (!sc && op->rows64.n < (size_t)N * RL) op->rows64.alloc(&op->s->ctx->c, (size_t)N * RL);
+  double* rows = sc ? sc->rows : op->rows64.p;
+  const double* qt = sc ? sc->qt64 : op->qt64.p;
+  double* part = sc ? sc->part : op->part.p;
+  const unsigned nbx = (unsigned)((N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_pack_sources_c<NR>, dim3(nbx), dim3(kBlock), 0, st,
+                     PackCArgs{N, op->s->g.x.p, op->co.a.p, op->co.c.p, qt + (int64_t)r0 * N, N, rows});
+  PMX_HIP(hipGetLastError());
+  const DirectCArgs da{N, (N + nc - 1) / nc, N, (int64_t)n_rhs * N, op->co.tgt.p, op->co.tg.p, op->co.c.p, rows,
+                       part + (int64_t)r0 * N, kernel};
+  hipLaunchKernelGGL(k_direct64_c<NR>, dim3(nbx, (unsigned)nc), dim3(kBlock), 0, st, da);
+  PMX_HIP(hipGetLastError());
+}
+
+void direct_c_all(pmx_operator* op, const ApplyScratch* sc, int kernel, int n_rhs, hipStream_t st) {
+  const int64_t N = op->s->g.N;
+  const size_t need = (size_t)n_chunks_for(N) * n_rhs * N;
+  if (!sc && op->part.n < need) op->part.alloc(&op->s->ctx->c, need);
+  int r0 = 0;
+  while (r0 < n_rhs) {
+    const int left = n_rhs - r0;
+    if (left >= 16) { direct_c_group<16>(op, sc, kernel, n_rhs, r0, st); r0 += 16; }
+    else if (left >= 8) { direct_c_group<8>(op, sc, kernel, n_rhs, r0, st); r0 += 8; }
+    else if (left >= 4) { direct_c_group<4>(op, sc, kernel, n_rhs, r0, st); r0 += 4; }
+    else if (left >= 2) { direct_c_group<2>(op, sc, kernel, n_rhs, r0, st); r0 += 2; }
+    else { direct_c_group<1>(op, sc, kernel, n_rhs, r0, st); r0 += 1; }
+  }
+}
+
+void direct64_all(const std::vector<pmx_operator*>& ops_in, const std::vector<const ApplyScratch*>& scs_in,
+                  int n_rhs, hipStream_t st) {
+  // operators with c < 0 take their own kernel, one operator at a time
+  std::vector<pmx_operator*> ops;
+  std::vector<const ApplyScratch*> scs;
+  for (size_t k = 0; k < ops_in.size(); ++k) {
+    if (ops_in[k]->co.has_c()) direct_c_all(ops_in[k], scs_in[k], 0, n_rhs, st);
+    else {
+      ops.push_back(ops_in[k]);
+      scs.push_back(scs_in[k]);
+    }
+  }
+  if (ops.empty()) return;
   for (size_t k = 0; k < ops.size(); ++k) {
     if (scs[k]) continue;
     pmx_operator* op = ops[k];
@@ -297,6 +436,11 @@ void far_direct_mode(pmx_operator* op, int mode, int n_rhs, hipStream_t st) {
     direct64_all({op}, {nullptr}, n_rhs, st);
     return;
   }
+  if (op->co.has_c()) {
+    PMX_REQUIRE(mode == 2, PMX_ERR_INVALID, "with c != 0 only the FP64 direct far field is available");
+    direct_c_all(op, nullptr, 1, n_rhs, st);
+    return;
+  }
   const int64_t N = op->s->g.N;
   const int64_t nc = n_chunks_for(N);
   const size_t need = (size_t)nc * n_rhs * N;
@@ -332,7 +476,7 @@ size_t direct64_scratch_doubles(int64_t N, int n_rhs) {
   const size_t nr = (size_t)n_rhs;
   const size_t nb = (size_t)((N + kBlock - 1) / kBlock);
   const int g = n_rhs >= 16 ? 16 : (n_rhs >= 8 ? 8 : (n_rhs >= 4 ? 4 : (n_rhs >= 2 ? 2 : 1)));
-  const size_t rl = (size_t)((3 + g + 1) / 2) * 2;   // widest packed row of the groups used
+  const size_t rl = (size_t)((4 + g + 1) / 2) * 2;   // widest packed row of the groups used (c rows too)
   return up(nr * N) + up(nr * nb) + up(nr) + up(rl * N) + up((size_t)n_chunks_for(N) * nr * N);
 }
 

@@ -280,7 +280,16 @@ void build_geometry(Ctx* ctx, Geometry& g, const double* x, const double* xu, co
   PMX_REQUIRE(wnx > 0.0, PMX_ERR_ORIENTATION, "surface normals point inward (sum w n.x <= 0)");
 }
 
-void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const double* grad_a, hipStream_t st) {
+__global__ void k_coeff_c(int64_t N, const double* __restrict__ c_in, double* __restrict__ c, int* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double v = c_in[i];
+  if (!(v < 0.0) || !isfinite(v)) atomicOr(bad, 2);
+  c[i] = v;
+}
+
+void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const double* grad_a, const double* c,
+                 hipStream_t st) {
   const int64_t N = g.N;
   co.a.alloc(ctx, N);
   co.gs.alloc(ctx, 3 * N);
@@ -295,10 +304,16 @@ void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const 
   hipLaunchKernelGGL(k_coeff, dim3((N + 255) / 256), dim3(256), 0, st, N, a, grad_a, g.x.p, g.n.p, g.H.p, g.w.p,
                      co.a.p, co.gs.p, co.tgt.p, co.tg.p, co.tf64.p, co.tgt32.p, co.w_over_a.p, bad.p);
   PMX_HIP(hipGetLastError());
+  if (c) {
+    co.c.alloc(ctx, N);
+    hipLaunchKernelGGL(k_coeff_c, dim3((N + 255) / 256), dim3(256), 0, st, N, c, co.c.p, bad.p);
+    PMX_HIP(hipGetLastError());
+  }
   int hbad = 0;
   PMX_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
   PMX_HIP(hipStreamSynchronize(st));
-  PMX_REQUIRE(!hbad, PMX_ERR_INVALID, "coefficient a must be positive and finite, grad a finite");
+  PMX_REQUIRE(!(hbad & 1), PMX_ERR_INVALID, "coefficient a must be positive and finite, grad a finite");
+  PMX_REQUIRE(!(hbad & 2), PMX_ERR_INVALID, "coefficient c must be negative and finite at every node");
 }
 
 void build_near_lists(Ctx* ctx, const Geometry& g, double eta, NearLists& nl, hipStream_t st) {

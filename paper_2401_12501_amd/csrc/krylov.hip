@@ -296,7 +296,9 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
   f.alloc(ctx, ld);
   r.alloc(ctx, ld);
   PMX_HIP(hipMemcpyAsync(f.p, f_in, ld * sizeof(double), hipMemcpyDeviceToDevice, st));
-  {
+  if (op->co.has_c()) {
+    removed_mean.assign(n_rhs, 0.0);   // c != 0: no null space, f is used as given
+  } else {
     // removed mean = (sum w f) / area, computed by weighted_mean_remove on a copy
     PMX_HIP(hipMemcpyAsync(r.p, f.p, ld * sizeof(double), hipMemcpyDeviceToDevice, st));
     weighted_mean_remove(op, f.p, n_rhs, st);

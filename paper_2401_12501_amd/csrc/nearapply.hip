@@ -93,6 +93,7 @@ struct CombineArgs {
   int64_t N;
   int q2, n_rhs, r0, n_far, identity;
   int paired;   // q2 and N even, blocks and densities 16-byte aligned: two entries per lane and load
+  int rank1;    // add sum_j w_j sigma_j (c = 0 only: the rank-one term)
   uint32_t magic;
   const int64_t* ptr;
   const int32_t* patch;
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_near_combine(Group<CombineArgs> g) {
     for (int r = 0; r < NR; ++r) {
       const int rr = A.r0 + r;
       double v = acc[r] + f[r];
-      if (A.identity) v += sig_i[r] + A.ssum[rr];
+      if (A.identity) v += sig_i[r] + (A.rank1 ? A.ssum[rr] : 0.0);
       A.y[(int64_t)rr * N + i] = v;
     }
   }
@@ -434,6 +435,7 @@ CombineArgs combine_args(pmx_operator* op, const double* sigma, double* y, int n
   c.paired = (q2 % 2 == 0 && c.N % 2 == 0 && ((uintptr_t)sigma % 16) == 0 && ((uintptr_t)c.Cb % 16) == 0) ? 1 : 0;
   c.far = far;
   c.ssum = ssum;
+  c.rank1 = op->co.has_c() ? 0 : 1;
   c.y = y;
   return c;
 }

@@ -6,7 +6,10 @@
 // where y~, x~_u, x~_v and a~ are tensor Lagrange interpolants of the patch's node
 // data (the paper interpolates sigma to the quadrature grid, Section 6.1.1 Remark
 // and Section 6.1.2), J~ = |x~_u x x~_v| and F is the remainder R or the
-// parametrix K.
+// parametrix K.  With c != 0 (c < 0, the modified Helmholtz type) c~ is interpolated like a,
+// F carries the c-dependent Green's function G = -K0(kappa r) / (2 pi a) and the c-term of
+// eq:explicit_remainder, and the self rule integrates R on the dyadic radial panels of K,
+// plain on the innermost one (R then has r^m log r parts).
 //
 // Self rule (i in P, Section 6.1.1, eq:radial_int): polar coordinates about the
 // target pre-image t0.  The square splits into four triangles (t0, c_k, c_k+1);
@@ -57,8 +60,9 @@ struct NWArgs {
   int n_gl;
   double eta;
   const double* X;      // 3N SoA
-  const double* XP;     // 10N node-major: x y z x_u x_v a per node
+  const double* XP;     // node-major fields x y z x_u x_v a (and c): 10 (11) per node
   const double* a;      // N
+  const double* c;      // N, c < 0 (kernels 2 and 3); null for c = 0
   const double* w;      // N
   const double* tgt;    // 8N: x y z nx ny nz A B
   const double* tg;     // 3N: grad_G a / (2 pi)
@@ -102,12 +106,12 @@ __device__ inline void lagrange_q(sdp tn, sdp cinv, double s, double (&l)[Q]) {
   }
 }
 
-// Tensor interpolation of the first NF of the ten node fields (x, x_u, x_v, a; node-major,
-// ten per node): g_f = sum_a l_a(u) sum_b l_b(v) X[(a q + b) 10 + f].  The node values are
+// Tensor interpolation of the first NF of the node fields (x, x_u, x_v, a and, with c, c;
+// node-major, ST per node): g_f = sum_a l_a(u) sum_b l_b(v) X[(a q + b) ST + f].  The node values are
 // uniform across the wave and come through the scalar cache; each node's loads are
 // issued one node ahead of its FMAs and the scheduling barriers keep the compiler from
 // hoisting more of them (which would exhaust the scalar registers).
-template <int Q, int NF>
+template <int Q, int NF, int ST>
 __device__ inline void interp_q(sdp XP, const double (&lu)[Q], const double (&lv)[Q], double (&g)[NF]) {
 #pragma unroll
   for (int f = 0; f < NF; ++f) g[f] = 0.0;
@@ -124,7 +128,7 @@ __device__ inline void interp_q(sdp XP, const double (&lu)[Q], const double (&lv
       const int n = a * Q + b;
       if (n + 1 < Q * Q) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) nxt[f] = XP[(n + 1) * 10 + f];
+        for (int f = 0; f < NF; ++f) nxt[f] = XP[(n + 1) * ST + f];
       }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
@@ -142,6 +146,7 @@ __device__ inline void interp_q(sdp XP, const double (&lu)[Q], const double (&lv
 
 struct Target {
   double x[3], n[3], A, B, g[3];
+  double at2, ct2;   // a / (2 pi) and c / (2 pi) at the target (c != 0)
 };
 
 // Factored c = 0 remainder: R = (1/a') [ g.r/r^2 + A (n.r)^2/r^4 - B (n.r)/r^2 ].
@@ -161,6 +166,44 @@ __device__ inline double parametrix_dev(const Target& T, const double* y, double
   return log_pair(rr) * 0.07957747154594766788 * inv_as;   // log(r) / (2 pi a)
 }
 
+// c < 0: with kappa = sqrt(-c'/a') at the source, z = kappa r and k0, k1 = K0(z), K1(z),
+// eq:explicit_remainder times a' is
+//   kappa k1 [g.r/r + 2 at2 (n.r)^2/r^3 - B n.r/r] + at2 kappa^2 k0 ((n.r)^2/r^2 - 1) - ct2 k0
+// (g = grad_G a / (2 pi), at2 = a / (2 pi), B = a H / pi, ct2 = c / (2 pi) at the target); it
+// reduces to the c = 0 form as c -> 0.
+__device__ inline double remainder_c_dev(const Target& T, const double* y, double inv_as, double c_s) {
+  const double r0 = T.x[0] - y[0], r1 = T.x[1] - y[1], r2 = T.x[2] - y[2];
+  const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+  const double ir = rsqrt(rr), rn = rr * ir;
+  const double kap = sqrt(-c_s * inv_as);
+  double k0, k1;
+  bessel_k01(kap * rn, k0, k1);
+  const double nr = T.n[0] * r0 + T.n[1] * r1 + T.n[2] * r2;
+  const double gr = T.g[0] * r0 + T.g[1] * r1 + T.g[2] * r2;
+  const double snr = nr * ir;   // n.r / r
+  const double bra = fma(ir, fma(2.0 * T.at2 * snr, snr, gr), -T.B * snr);
+  const double e = kap * k1 * bra + T.at2 * kap * kap * k0 * fma(snr, snr, -1.0) - T.ct2 * k0;
+  return e * inv_as;
+}
+
+__device__ inline double parametrix_c_dev(const Target& T, const double* y, double inv_as, double c_s) {
+  const double r0 = T.x[0] - y[0], r1 = T.x[1] - y[1], r2 = T.x[2] - y[2];
+  const double rn = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+  double k0, k1;
+  bessel_k01(sqrt(-c_s * inv_as) * rn, k0, k1);
+  return -k0 * 0.15915494309189533577 * inv_as;   // -K0(kappa r) / (2 pi a)
+}
+
+// Kernel F at a point y with coefficients a' = 1 / inv_as (and c_s): KERNEL 0 R, 1 K (c = 0);
+// 2 R, 3 K (c < 0).
+template <int KERNEL>
+__device__ inline double kernel_dev(const Target& T, const double* y, double inv_as, double c_s) {
+  if constexpr (KERNEL == 0) return remainder_dev(T, y, inv_as);
+  else if constexpr (KERNEL == 1) return parametrix_dev(T, y, inv_as);
+  else if constexpr (KERNEL == 2) return remainder_c_dev(T, y, inv_as, c_s);
+  else return parametrix_c_dev(T, y, inv_as, c_s);
+}
+
 union Cell {                    // self: angular panel [p0, p1] of one edge; near: leaf (depth, iu, iv)
   struct { double p0, p1; } s;
   struct { int depth, iu, iv, pad; } n;
@@ -178,7 +221,8 @@ __device__ inline sdp opaque(sdp p) {
 
 }  // namespace
 
-// KERNEL: 0 = remainder R (correction blocks C), 1 = parametrix K (blocks D).
+// KERNEL: 0 = remainder R (correction blocks C), 1 = parametrix K (blocks D); 2 and 3 the same
+// with c < 0 (eleven node fields: c interpolated like a).
 // SELF: one workgroup per target for the pair with its own patch; otherwise one per
 // near-list pair, the self pairs leaving at once (the two launches get their own
 // register allocation: the self rule is VALU work, the near rule MFMA work).
@@ -188,6 +232,8 @@ k_near_weights(NWArgs A) {
   constexpr int kW = waves_for<Q, SELF>();
   constexpr int kT = 64 * kW;
   constexpr int q2 = Q * Q;
+  constexpr bool kC = KERNEL >= 2;        // c < 0
+  constexpr int NF = kC ? 11 : 10;        // node fields (and their stride in XP)
   extern __shared__ double lds[];
   // stage[w][2][Q][kStage]; the subdivision front and flags overlay it before the point loop
   double* stage = lds;
@@ -220,7 +266,7 @@ k_near_weights(NWArgs A) {
   const int64_t base = (int64_t)P * q2;
   constexpr bool self = SELF;
 
-  const sdp F = (sdp)(A.XP + base * 10);
+  const sdp F = (sdp)(A.XP + base * NF);
   const sdp tn = (sdp)A.tn, cinv = (sdp)A.cinv, gl_t = (sdp)A.gl_t, gl_w = (sdp)A.gl_w;
 
   Target T;
@@ -231,6 +277,8 @@ k_near_weights(NWArgs A) {
   }
   T.A = A.tgt[6 * N + i];
   T.B = A.tgt[7 * N + i];
+  T.at2 = 0.5 * T.A;
+  T.ct2 = kC ? A.c[i] * 0.15915494309189533577 : 0.0;
   const int ngl = A.n_gl;
 
   // ------------------------------------------------------------------ cells
@@ -295,7 +343,7 @@ k_near_weights(NWArgs A) {
             double lu[Q], lv[Q], g[3];
             lagrange_q<Q>(tn, cinv, cu, lu);
             lagrange_q<Q>(tn, cinv, cv, lv);
-            interp_q<Q, 3>(opaque(F), lu, lv, g);
+            interp_q<Q, 3, NF>(opaque(F), lu, lv, g);
             corner_xyz[tid * 3] = g[0];
             corner_xyz[tid * 3 + 1] = g[1];
             corner_xyz[tid * 3 + 2] = g[2];
@@ -387,9 +435,9 @@ k_near_weights(NWArgs A) {
     // the patch's node fields go to LDS once per pair (sX[f][a][b]); the rule tables and
     // Lagrange denominators a lane needs are loaded into registers ahead of the leaves
     double* sX = stage;   // 10 q^2 doubles (the self rule's staging area is not used here)
-    for (int e = tid; e < 10 * q2; e += kT) {
+    for (int e = tid; e < NF * q2; e += kT) {
       const int f = e / q2, j = e - f * q2;
-      sX[e] = A.XP[(base + j) * 10 + f];
+      sX[e] = A.XP[(base + j) * NF + f];
     }
     __syncthreads();
     const bool rin = r16 < ngl;
@@ -402,7 +450,7 @@ k_near_weights(NWArgs A) {
     }
     // per wave, per leaf: Lagrange tables Lu[i][a] = l_a(u_i), Lv[k][b] = l_b(v_k) in LDS,
     // one point's row per lane (lanes 0-15: u_i, lanes 16-31: v_k)
-    double* sLu = stage + 10 * q2 + (size_t)wave * 32 * Q;
+    double* sLu = stage + NF * q2 + (size_t)wave * 32 * Q;
     double* sLv = sLu + 16 * Q;
     for (int cell = wave; cell < nc; cell += kW) {
       const Cell C = cells[cell];
@@ -426,9 +474,9 @@ k_near_weights(NWArgs A) {
         lua[ks] = j < Q ? sLu[r16 * Q + (j < Q ? j : 0)] : 0.0;   // B[a][i] = l_a(u_i), a = j, i = r16
       }
       // G_f^T: lane holds G_f at (k = g4 + 4 r, i = r16)
-      v4d acc2[10];
+      v4d acc2[NF];
 #pragma unroll
-      for (int f = 0; f < 10; ++f) {
+      for (int f = 0; f < NF; ++f) {
         v4d t1 = {0.0, 0.0, 0.0, 0.0};   // T_f[a = g4 + 4 r][k = r16]
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -446,15 +494,15 @@ k_near_weights(NWArgs A) {
       const double hh2 = hh * hh;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        double gv[10];
+        double gv[NF];
 #pragma unroll
-        for (int f = 0; f < 10; ++f) gv[f] = acc2[f][r];
+        for (int f = 0; f < NF; ++f) gv[f] = acc2[f][r];
         const double x0 = gv[4] * gv[8] - gv[5] * gv[7];
         const double x1 = gv[5] * gv[6] - gv[3] * gv[8];
         const double x2 = gv[3] * gv[7] - gv[4] * gv[6];
         const double Jt = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
         const double inv_as = 1.0 / gv[9];
-        const double Fk = KERNEL == 0 ? remainder_dev(T, gv, inv_as) : parametrix_dev(T, gv, inv_as);
+        const double Fk = kernel_dev<KERNEL>(T, gv, inv_as, kC ? gv[NF - 1] : 0.0);
         cval[r] = w_r * w_g[r] * hh2 * Fk * Jt;   // zero weight outside the n_gl x n_gl rule
       }
       // U = C L_v: A[i][k] = c[i][k] with k = 4 ks + g4 (register ks of this lane)
@@ -477,7 +525,7 @@ k_near_weights(NWArgs A) {
   }
 
   // ------------------------------------------------------------------ self rule: points
-  const unsigned n_rad = (self && KERNEL == 1) ? 4 * ngl : ngl;
+  const unsigned n_rad = (self && KERNEL != 0) ? 4 * ngl : ngl;   // log-graded panels for all but R, c = 0
   const unsigned ppc = self ? (unsigned)ngl * n_rad : (unsigned)(ngl * ngl);
   const unsigned n_pts = self ? ppc * (unsigned)nc : 0u;
   double* CL = stage + (size_t)wave * 2 * Q * kStage;   // c l_a(u) at [a][point]
@@ -504,8 +552,11 @@ k_near_weights(NWArgs A) {
         double s, wr;
         const unsigned pr = ir / ngl, jr = ir - pr * ngl;
         const double t = 0.5 * (gl_t[jr] + 1.0), wt = 0.5 * gl_w[jr];
-        if (KERNEL == 0 || pr < 3) {
-          const double lo = KERNEL == 0 ? 0.0 : ldexp(1.0, -(int)(pr + 1));
+        // R (c = 0): one panel [0, 1]; K: dyadic panels with rho = t^3 / 8 on the innermost;
+        // R (c < 0): the dyadic panels, plain on the innermost [0, 1/8] too (the t^3 map would put
+        // points within 1e-10 of the target, where r keeps too few digits of its normal component)
+        if (KERNEL == 0 || pr < 3 || KERNEL == 2) {
+          const double lo = (KERNEL == 0 || pr == 3) ? 0.0 : ldexp(1.0, -(int)(pr + 1));
           const double hi = KERNEL == 0 ? 1.0 : ldexp(1.0, -(int)pr);
           s = lo + (hi - lo) * t;
           wr = (hi - lo) * wt * s;
@@ -530,16 +581,16 @@ k_near_weights(NWArgs A) {
         wq = gl_w[ia] * gl_w[ib] * hh * hh;
       }
     }
-    double lu[Q], lv[Q], g[10];
+    double lu[Q], lv[Q], g[NF];
     lagrange_q<Q>(tn, cinv, u, lu);
     lagrange_q<Q>(tn, cinv, v, lv);
-    interp_q<Q, 10>(opaque(F), lu, lv, g);
+    interp_q<Q, NF, NF>(opaque(F), lu, lv, g);
     const double x0 = g[4] * g[8] - g[5] * g[7];
     const double x1 = g[5] * g[6] - g[3] * g[8];
     const double x2 = g[3] * g[7] - g[4] * g[6];
     const double Jt = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
     const double inv_as = 1.0 / g[9];
-    const double Fk = KERNEL == 0 ? remainder_dev(T, g, inv_as) : parametrix_dev(T, g, inv_as);
+    const double Fk = kernel_dev<KERNEL>(T, g, inv_as, kC ? g[NF - 1] : 0.0);
     const double c = valid ? wq * Fk * Jt : 0.0;
     // stage this wave's 64 points; LDS operations of one wave complete in order
     __builtin_amdgcn_wave_barrier();
@@ -581,24 +632,27 @@ k_near_weights(NWArgs A) {
     if (j != i) {
       const double y[3] = {A.X[j], A.X[N + j], A.X[2 * N + j]};
       const double inv_a = 1.0 / A.a[j];
-      const double Fs = KERNEL == 0 ? remainder_dev(T, y, inv_a) : parametrix_dev(T, y, inv_a);
+      const double Fs = kernel_dev<KERNEL>(T, y, inv_a, kC ? A.c[j] : 0.0);
       val -= A.w[j] * Fs;
     }
     A.out[pair * q2 + e] = val;
   }
 }
 
+// Node-major fields for the local rules: x, x_u, x_v, a and, when c is given, c (nf = 10 or 11).
 __global__ void k_interleave(int64_t N, const double* __restrict__ x, const double* __restrict__ xu,
-                             const double* __restrict__ xv, const double* __restrict__ a, double* __restrict__ xp) {
+                             const double* __restrict__ xv, const double* __restrict__ a,
+                             const double* __restrict__ c, int nf, double* __restrict__ xp) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= N) return;
-  double* o = xp + j * 10;
-  for (int c = 0; c < 3; ++c) {
-    o[c] = x[c * N + j];
-    o[3 + c] = xu[c * N + j];
-    o[6 + c] = xv[c * N + j];
+  double* o = xp + j * nf;
+  for (int k = 0; k < 3; ++k) {
+    o[k] = x[k * N + j];
+    o[3 + k] = xu[k * N + j];
+    o[6 + k] = xv[k * N + j];
   }
   o[9] = a[j];
+  if (nf == 11) o[10] = c[j];
 }
 
 namespace {
@@ -606,13 +660,21 @@ namespace {
 template <int Q, bool SELF>
 size_t lds_bytes() {
   constexpr int kW = waves_for<Q, SELF>();
-  // self: the waves' staging rows; near: the patch's node fields and each wave's Lagrange tables
+  // self: the waves' staging rows; near: the patch's node fields (up to 11) and each wave's
+  // Lagrange tables
   const size_t stage = SELF ? (size_t)kW * 2 * Q * kStage * sizeof(double)
-                            : (size_t)(10 * Q * Q + kW * 32 * Q) * sizeof(double);
+                            : (size_t)(11 * Q * Q + kW * 32 * Q) * sizeof(double);
   const size_t front = 2 * kMaxCells * sizeof(int2) + 64 * kW * sizeof(int) + 16 * kW * 12 * sizeof(double);
   const size_t red = (size_t)kW * 256 * sizeof(double);
   size_t m = stage > front ? stage : front;
   return m > red ? m : red;
+}
+
+template <int KERNEL, int Q>
+void launch_kq(const NWArgs& A, int64_t n, bool self, hipStream_t st, size_t lds) {
+  const dim3 block(64 * (self ? waves_for<Q, true>() : waves_for<Q, false>()));
+  if (self) hipLaunchKernelGGL((k_near_weights<KERNEL, Q, true>), dim3(n), block, lds, st, A);
+  else hipLaunchKernelGGL((k_near_weights<KERNEL, Q, false>), dim3(n), block, lds, st, A);
 }
 
 template <int Q>
@@ -620,13 +682,13 @@ void launch_q(const NWArgs& A, int64_t n, bool parametrix, bool self, hipStream_
   const size_t lds = self ? lds_bytes<Q, true>() : lds_bytes<Q, false>();
   PMX_REQUIRE(lds + 12 * 1024 <= lds_limit, PMX_ERR_INVALID,
               "q too large for the local-rule kernel's LDS on this device");
-  const dim3 block(64 * (self ? waves_for<Q, true>() : waves_for<Q, false>()));
-  if (parametrix) {
-    if (self) hipLaunchKernelGGL((k_near_weights<1, Q, true>), dim3(n), block, lds, st, A);
-    else hipLaunchKernelGGL((k_near_weights<1, Q, false>), dim3(n), block, lds, st, A);
+  const bool c = A.c != nullptr;
+  if (!c) {
+    if (parametrix) launch_kq<1, Q>(A, n, self, st, lds);
+    else launch_kq<0, Q>(A, n, self, st, lds);
   } else {
-    if (self) hipLaunchKernelGGL((k_near_weights<0, Q, true>), dim3(n), block, lds, st, A);
-    else hipLaunchKernelGGL((k_near_weights<0, Q, false>), dim3(n), block, lds, st, A);
+    if (parametrix) launch_kq<3, Q>(A, n, self, st, lds);
+    else launch_kq<2, Q>(A, n, self, st, lds);
   }
   PMX_HIP(hipGetLastError());
 }
@@ -682,12 +744,13 @@ void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists&
   PMX_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
   NWArgs A;
   A.N = g.N; A.q = q; A.n_gl = o.n_gl; A.eta = o.eta_near;
+  const int nf = co.has_c() ? 11 : 10;
   DBuf<double> xp;
-  xp.alloc(ctx, (size_t)g.N * 10);
+  xp.alloc(ctx, (size_t)g.N * nf);
   hipLaunchKernelGGL(k_interleave, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, (int64_t)g.N, g.x.p,
-                     g.xu_p.p, g.xv_p.p, co.a.p, xp.p);
+                     g.xu_p.p, g.xv_p.p, co.a.p, co.c.p, nf, xp.p);
   PMX_HIP(hipGetLastError());
-  A.X = g.x.p; A.XP = xp.p; A.a = co.a.p; A.w = g.w.p;
+  A.X = g.x.p; A.XP = xp.p; A.a = co.a.p; A.c = co.c.p; A.w = g.w.p;
   A.tgt = co.tgt.p; A.tg = co.tg.p;
   A.tn = tab.p; A.cinv = tab.p + q; A.gl_t = tab.p + 2 * q; A.gl_w = tab.p + 2 * q + o.n_gl;
   A.ptr = nl.ptr.p; A.pair_patch = nl.patch.p; A.pair_target = nl.target.p; A.out = out.p; A.err = err.p;

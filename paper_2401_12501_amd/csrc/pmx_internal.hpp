@@ -149,6 +149,8 @@ struct Coeff {
   DBuf<double> tf64;    // 9N: x y z n'x n'y n'z hx hy hz
   DBuf<float> tgt32;    // 9N: the same in FP32
   DBuf<double> w_over_a;  // N
+  DBuf<double> c;       // N: the zero-order coefficient c < 0; empty for c = 0
+  bool has_c() const { return c.p != nullptr; }
 };
 
 struct NearLists {
@@ -223,6 +225,66 @@ __device__ __forceinline__ double log_pair(double x) {
   p = fma(p, s2, 1.0 / 3.0);
   p = fma(p, s2, 1.0);
   return fma((double)e, kLn2, 2.0 * sv * p);
+}
+
+// Modified Bessel functions K0(z) and K1(z) of a positive argument (FP64): the Green's function
+// of (a Delta + c) G = delta with c < 0 is G = -K0(kappa r) / (2 pi a), kappa = sqrt(-c / a).
+//  * z <= 2: the power series in t = z^2 / 4 (Abramowitz & Stegun 9.6.13 for K0, 9.6.11 with
+//    n = 1 for K1), with I0 = sum t^k / (k!)^2, I1 = (z/2) sum t^k / (k! (k+1)!) and harmonic
+//    numbers H_k:  K0 = -(ln(z/2) + gamma) I0 + sum H_k t^k / (k!)^2,
+//    K1 = 1/z + (ln(z/2) + gamma) I1 - (z/4) sum (H_k + H_{k+1}) t^k / (k! (k+1)!).
+//    Fifteen terms leave a truncation below 1e-21 at z = 2; the cancellation in K0 there costs
+//    about one decimal digit (relative error up to 6e-15).
+//  * z > 2: the integral e^z K_nu(z) = int_0^inf exp(-z (cosh s - 1)) cosh(nu s) ds (A&S 9.6.24)
+//    with u = sqrt(2z) sinh(s/2), so that z (cosh s - 1) = u^2 and cosh s = 1 + u^2 / z:
+//      e^z K0 = sqrt(2/z) int_0^inf e^{-u^2} (1 + u^2/(2z))^{-1/2} du,
+//      e^z K1 = sqrt(2/z) int_0^inf e^{-u^2} (1 + u^2/z) (1 + u^2/(2z))^{-1/2} du.
+//    The integrands are even in u and analytic for |Im u| < sqrt(2z) (>= 2), so the trapezoidal
+//    rule converges exponentially (Trefethen and Weideman, SIAM Review 56, 2014); step 0.3 on
+//    [0, 6.9] (24 nodes, weights 0.3 exp(-u_j^2), half at u = 0, generated at 30 digits) gives
+//    1e-15 relative for every z >= 2.
+constexpr double kEulerGamma = 0.57721566490153286061;
+__device__ __forceinline__ void bessel_k01(double z, double& k0, double& k1) {
+  if (z <= 2.0) {
+    const double t = 0.25 * z * z;
+    double term0 = 1.0, term1 = 1.0, i0 = 0.0, i1 = 0.0, s0 = 0.0, s1 = 0.0, hk = 0.0;
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+      const double hk1 = hk + 1.0 / (double)(k + 1);
+      i0 += term0;
+      i1 += term1;
+      s0 = fma(hk, term0, s0);
+      s1 = fma(hk + hk1, term1, s1);
+      hk = hk1;
+      term0 *= t * (1.0 / ((double)(k + 1) * (double)(k + 1)));
+      term1 *= t * (1.0 / ((double)(k + 1) * (double)(k + 2)));
+    }
+    const double L = 0.5 * log_pair(t) + kEulerGamma;   // ln(z/2) + gamma
+    k0 = fma(-L, i0, s0);
+    k1 = 1.0 / z + L * (0.5 * z * i1) - 0.25 * z * s1;
+  } else {
+    constexpr double w[24] = {
+        0.15, 0.27417935558136845602, 0.20930289782130931716,
+        0.13345741986688234034, 0.071078327604636527017, 0.031619767368559301035,
+        0.011749168529696122122, 0.0036465534989744811645, 0.00094533347953333216735,
+        0.00020469841582691298489, 0.000037022941226003864849, 0.0000055931226994550491246,
+        7.057725600029318768e-7, 7.4387880541350888885e-8, 6.5488733853764376273e-9,
+        4.815684165556834826e-10, 2.9578516727974524722e-11, 1.5174758228531379705e-12,
+        6.5027066478568858269e-14, 2.3275206227088211402e-15, 6.9585684907307081649e-17,
+        1.737693865618457377e-18, 3.624546059699920715e-20, 6.3148199350192033368e-22};
+    const double invz = 1.0 / z, inv2z = 0.5 * invz;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 24; ++j) {
+      const double u2 = 0.09 * (double)(j * j);
+      const double r = rsqrt(fma(u2, inv2z, 1.0));
+      s0 = fma(w[j], r, s0);
+      s1 = fma(w[j] * r, fma(u2, invz, 1.0), s1);
+    }
+    const double c = sqrt(2.0 * invz) * exp(-z);
+    k0 = c * s0;
+    k1 = c * s1;
+  }
 }
 
 // Launch `fn(group, total_blocks)` for the records in chunks of kMaxSeg; segments
@@ -347,7 +409,9 @@ struct ApplyJob {
 // geometry.hip
 void build_geometry(Ctx* ctx, Geometry& g, const double* x, const double* xu, const double* xv, const double* xuu,
                     const double* xuv, const double* xvv, hipStream_t st);
-void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const double* grad_a, hipStream_t st);
+// c: nullptr for c = 0, else N values, each negative and finite (checked).
+void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const double* grad_a, const double* c,
+                 hipStream_t st);
 void build_near_lists(Ctx* ctx, const Geometry& g, double eta, NearLists& nl, hipStream_t st);
 // nearweights.hip
 void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists& nl, const pmx_options& o,

@@ -62,6 +62,7 @@ _SIGS = {
                                         C.POINTER(_vp)]),
     "pmx_surface_destroy": (None, [_vp]),
     "pmx_operator_create": (C.c_int32, [_vp, _vp, _vp, C.POINTER(pmx_options), C.c_int, _vp, C.POINTER(_vp)]),
+    "pmx_operator_create_c": (C.c_int32, [_vp, _vp, _vp, _vp, C.POINTER(pmx_options), C.c_int, _vp, C.POINTER(_vp)]),
     "pmx_operator_destroy": (None, [_vp]),
     "pmx_operator_get_stats": (C.c_int32, [_vp, C.POINTER(pmx_operator_stats)]),
     "pmx_apply": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_int, _vp]),
@@ -216,14 +217,20 @@ class Surface:
 class Operator:
     """pmx_operator_create and the calls on an operator."""
 
-    def __init__(self, surface: Surface, a, grad_a, opts: pmx_options | None = None):
+    def __init__(self, surface: Surface, a, grad_a, opts: pmx_options | None = None, c=None):
+        """pmx_operator_create, or pmx_operator_create_c when c (N values, all negative) is given."""
         self.surface = surface
         self.N = surface.N
         self.q = surface.q
         self.opts = opts if opts is not None else pmx_default_options()
-        ptrs, kind, stream, keep = _marshal(a, grad_a)
+        ptrs, kind, stream, keep = _marshal(a, grad_a, c)
         h = _vp()
-        _check(lib().pmx_operator_create(surface.h, ptrs[0], ptrs[1], C.byref(self.opts), kind, stream, C.byref(h)))
+        if c is None:
+            _check(lib().pmx_operator_create(surface.h, ptrs[0], ptrs[1], C.byref(self.opts), kind, stream,
+                                             C.byref(h)))
+        else:
+            _check(lib().pmx_operator_create_c(surface.h, ptrs[0], ptrs[1], ptrs[2], C.byref(self.opts), kind,
+                                               stream, C.byref(h)))
         self.h = h
 
     def close(self):
