@@ -17,6 +17,11 @@ with r = x - x', G' = dG/dr and G'' = d^2G/dr^2 (the definition line prints
 G'' = d^2/dr^2 G', which we read as the second derivative of G).  Target
 quantities n, H, a, c, grad_G a are at x.  The modified Bessel functions K0, K1 come
 from the library (scipy.special).
+
+Advection (eq:adv_remainder): with a first-order term b . grad_G u in the equation the same
+parametrix serves and the remainder gains b(x) . grad_G K(x, x').  K depends on x through
+r = |x - x'| only, so grad K = G' r_hat, and for a field b tangent at x the surface gradient's
+projection drops: the added term is G' (b . r_hat).
 """
 from __future__ import annotations
 
@@ -56,13 +61,15 @@ def green(r, a, c=None):
     return green_neg_c(r, a, c)
 
 
-def remainder(x, n, H, a_t, gs_t, y, a_s, c_t=None, c_s=None):
-    """R(x, y) of eq:explicit_remainder; broadcasts over leading axes.
+def remainder(x, n, H, a_t, gs_t, y, a_s, c_t=None, c_s=None, b_t=None):
+    """R(x, y) of eq:explicit_remainder (R_b of eq:adv_remainder when b_t is given);
+    broadcasts over leading axes.
 
     x, n, gs_t: (..., 3) target position, unit normal, surface gradient of a;
     H, a_t: (...) target mean curvature and coefficient; y: (..., 3) source
     position; a_s: (...) coefficient at the source; c_t, c_s: c at the target and the
-    source (None: c = 0, the Laplace-Beltrami type).
+    source (None: c = 0, the Laplace-Beltrami type); b_t: (..., 3) advection field at the
+    target, tangent there (None: no first-order term).
     """
     r = x - y
     rn = np.linalg.norm(r, axis=-1)
@@ -75,6 +82,8 @@ def remainder(x, n, H, a_t, gs_t, y, a_s, c_t=None, c_s=None):
          - 2 * a_t * H * (nr / rn) * G1)
     if c_s is not None:
         R = R + (c_t - a_t * c_s / a_s) * G
+    if b_t is not None:
+        R = R + np.sum(b_t * rhat, axis=-1) * G1
     return R
 
 

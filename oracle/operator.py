@@ -24,6 +24,13 @@ null space: the system is sigma + R[sigma] = f (Theorem thm:second_kind), f is t
 given and u = K[sigma] is not shifted.  R and K then carry the c-dependent Green's
 function (``kernels``), c is interpolated on a patch like a, and the self rule integrates R
 on dyadically graded radial panels, since R then has r^m log r parts.
+
+An advection field b (eq:surf_PDE's first-order term, Section 4's theorem
+thm:advectionparametrix) is taken with c < 0 only: the remainder becomes R_b of
+eq:adv_remainder, the system sigma + R_b[sigma] = f (eq:IE_adv) and u = K[sigma] as before.
+b is given as ambient vectors at the nodes and projected onto each node's tangent plane.
+With c = 0 constants still solve the homogeneous problem but the data's solvability
+condition is no longer a zero mean, which the paper does not treat.
 """
 from __future__ import annotations
 
@@ -39,7 +46,7 @@ class OracleOperator:
     """Plain FP64 discretization of eq:IE on a quad-patch surface."""
 
     def __init__(self, q, x, xu, xv, xuu, xuv, xvv, a, grad_a, eta: float = 1.5, n_gl: int = 16,
-                 split: float = 2.0, c=None):
+                 split: float = 2.0, c=None, b=None):
         self.q = q
         self.N = x.shape[0]
         self.M = self.N // (q * q)
@@ -60,6 +67,12 @@ class OracleOperator:
         if self.c is not None and np.any(self.c >= 0):
             raise ValueError("c must be negative at every node (or None for c = 0)")
         self._P_c = None if self.c is None else patch_nodes(self.c[:, None], q)
+        self.b = None
+        if b is not None:
+            if self.c is None:
+                raise ValueError("an advection field b needs c < 0")
+            b = np.asarray(b, dtype=np.float64).reshape(self.N, 3)
+            self.b = b - np.sum(b * self.n, axis=1)[:, None] * self.n
         self._self_cache = {}
 
     @classmethod
@@ -67,16 +80,21 @@ class OracleOperator:
         s = prob.surface
         if getattr(prob, "c", None) is not None and "c" not in kw:
             kw["c"] = prob.c
+        if getattr(prob, "b", None) is not None and "b" not in kw:
+            kw["b"] = prob.b
         return cls(s.q, s.x, s.xu, s.xv, s.xuu, s.xuv, s.xvv, prob.a, prob.grad_a, **kw)
 
     def _c(self, idx):
         return None if self.c is None else self.c[idx]
 
+    def _b(self, idx):
+        return None if self.b is None else self.b[idx]
+
     # ----------------------------------------------------------------- kernels at nodes
     def R_row(self, i: int, js) -> np.ndarray:
         """R(x_i, x_j) for node indices js (all must differ from i)."""
         return remainder(self.x[i], self.n[i], self.H[i], self.a[i], self.gs[i], self.x[js], self.a[js],
-                         self._c(i), self._c(js))
+                         self._c(i), self._c(js), self._b(i))
 
     def K_row(self, i: int, js) -> np.ndarray:
         return parametrix(self.x[i], self.x[js], self.a[js], self._c(js))
@@ -119,7 +137,8 @@ class OracleOperator:
         out = {}
         for kernel in kernels:
             if kernel == "R":
-                F = remainder(self.x[i], self.n[i], self.H[i], self.a[i], self.gs[i], y, a_s, self._c(i), c_s)
+                F = remainder(self.x[i], self.n[i], self.H[i], self.a[i], self.gs[i], y, a_s, self._c(i), c_s,
+                              self._b(i))
             elif kernel == "K":
                 F = parametrix(self.x[i], y, a_s, c_s)
             elif kernel == "one":

@@ -44,15 +44,17 @@ class Problem:
     name: str = ""
     meta: dict = field(default_factory=dict)
     c: np.ndarray | None = None   # (N,) zero-order coefficient c < 0, or None for c = 0
+    b: np.ndarray | None = None   # (N, 3) advection field (ambient vectors), or None
 
     @property
     def n(self) -> int:
         return self.surface.n
 
 
-def _sphere_manufactured_rhs(x: np.ndarray, a_fn) -> tuple[np.ndarray, np.ndarray]:
+def _sphere_manufactured_rhs(x: np.ndarray, a_fn, b: np.ndarray | None = None) -> tuple[np.ndarray, np.ndarray]:
     """On the unit sphere (exact normal = position): u = (x^2 - y^2) z and
-    f = div_G(a grad_G u) = a * (-12 u) + grad_G a . grad_G u (u is a degree-3 harmonic)."""
+    f = div_G(a grad_G u) = a * (-12 u) + grad_G a . grad_G u (u is a degree-3 harmonic),
+    plus b . grad_G u when an advection field b is given."""
     X = torch.tensor(x, dtype=torch.float64)
     nrm = X / torch.linalg.norm(X, dim=1, keepdim=True)
     u = (X[:, 0] ** 2 - X[:, 1] ** 2) * X[:, 2]
@@ -61,6 +63,8 @@ def _sphere_manufactured_rhs(x: np.ndarray, a_fn) -> tuple[np.ndarray, np.ndarra
     ga = torch.tensor(ga)
     tang = lambda g: g - nrm * (nrm * g).sum(dim=1, keepdim=True)
     f = torch.tensor(a) * (-12.0 * u) + (tang(ga) * tang(gu)).sum(dim=1)
+    if b is not None:
+        f = f + (torch.tensor(b) * tang(gu)).sum(dim=1)
     return f.numpy().copy(), u.numpy().copy()
 
 
@@ -111,35 +115,42 @@ def wobbly_torus_problem(n_theta: int = 256, n_phi: int = 128, q: int = 8, n_rhs
     return Problem(s, a, ga, f, name=f"wobbly_torus_{n_theta}x{n_phi}_q{q}")
 
 
-def helmholtz_sphere_problem(k: int = 2, q: int = 8, c0: float | None = None) -> Problem:
-    """Unit sphere for div_G(a grad_G u) + c u = f with c < 0 (the modified Helmholtz type).
+def helmholtz_sphere_problem(k: int = 2, q: int = 8, c0: float | None = None, omega: float | None = None,
+                             swirl: bool = False) -> Problem:
+    """Unit sphere for div_G(a grad_G u) + b . grad_G u + c u = f with c < 0 (the modified Helmholtz
+    type); b = 0 unless ``omega`` (the rotation omega e3 x x) or ``swirl`` (fields.b_swirl) is given.
 
     c0 given: a = 1 and c = c0 (constant; f = 0, the caller chooses f, e.g. spherical harmonics).
     c0 None: a = 2 + x3 and c = -4 - exp(x1 / 2), with the manufactured solution u = (x^2 - y^2) z
     (a degree-3 harmonic, Delta_G u = -12 u on the unit sphere):
-    f = grad_G a . grad_G u - 12 a u + c u.
+    f = grad_G a . grad_G u - 12 a u + b . grad_G u + c u.
     """
     s = cube_sphere(k, q, name="sphere")
+    b = F.b_rotation_z(s.x, omega) if omega is not None else (F.b_swirl(s.x) if swirl else None)
+    tag = (f"_w{omega}" if omega is not None else "") + ("_swirl" if swirl else "")
     if c0 is not None:
         a, ga = F.eval_field(F.a_const(1.0), s.x)
         c = np.full(s.n, float(c0))
-        return Problem(s, a, ga, np.zeros((s.n, 1)), name=f"helmholtz_sphere_k{k}_q{q}_c{c0}", c=c)
+        return Problem(s, a, ga, np.zeros((s.n, 1)), name=f"helmholtz_sphere_k{k}_q{q}_c{c0}{tag}", c=c, b=b)
     a_fn = F.a_linear_z
     a, ga = F.eval_field(a_fn, s.x)
     c, _ = F.eval_field(F.c_exp_x, s.x)
-    f, u = _sphere_manufactured_rhs(s.x, a_fn)
-    return Problem(s, a, ga, (f + c * u)[:, None], name=f"helmholtz_sphere_k{k}_q{q}_var", c=c,
+    f, u = _sphere_manufactured_rhs(s.x, a_fn, b)
+    return Problem(s, a, ga, (f + c * u)[:, None], name=f"helmholtz_sphere_k{k}_q{q}_var{tag}", c=c, b=b,
                    meta={"u_exact": u})
 
 
-def helmholtz_ellipsoid_problem(k: int = 4, q: int = 8, axes=(1.0, 0.8, 0.6), seed: int = 1, n_rhs: int = 1):
+def helmholtz_ellipsoid_problem(k: int = 4, q: int = 8, axes=(1.0, 0.8, 0.6), seed: int = 1, n_rhs: int = 1,
+                                swirl: bool = False):
     """Ellipsoid with the variable coefficients a = 2 + x3 and c = -4 - exp(x1 / 2) (c < 0) and
-    right-hand sides of 20 solid harmonics (seeded)."""
+    right-hand sides of 20 solid harmonics (seeded); with ``swirl`` the advection field
+    fields.b_swirl as well."""
     s = cube_sphere(k, q, axes=axes, name="ellipsoid")
     a, ga = F.eval_field(F.a_linear_z, s.x)
     c, _ = F.eval_field(F.c_exp_x, s.x)
     f = np.stack([F.solid_harmonic_rhs(s.x, seed + 100 * r) for r in range(n_rhs)], axis=1)
-    return Problem(s, a, ga, f, name=f"helmholtz_ellipsoid_k{k}_q{q}", c=c)
+    return Problem(s, a, ga, f, name=f"helmholtz_ellipsoid_k{k}_q{q}" + ("_swirl" if swirl else ""), c=c,
+                   b=F.b_swirl(s.x) if swirl else None)
 
 
 def wavy_torus_problem(n_u: int = 51, n_v: int = 18, q: int = 8, seed: int = 5) -> Problem:

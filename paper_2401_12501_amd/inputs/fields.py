@@ -58,6 +58,20 @@ def c_exp_x(X):
     return -4.0 - torch.exp(0.5 * X[:, 0])
 
 
+def b_rotation_z(x: np.ndarray, omega: float) -> np.ndarray:
+    """Advection field omega e3 x x = omega (-x2, x1, 0): the rotation about the x3 axis, tangent
+    to every surface of revolution about that axis (so b . grad u = omega du/dphi there)."""
+    x = np.asarray(x, dtype=np.float64)
+    return omega * np.stack([-x[:, 1], x[:, 0], np.zeros(len(x))], axis=1)
+
+
+def b_swirl(x: np.ndarray) -> np.ndarray:
+    """A smooth ambient field, not tangent to any of the surfaces here (the operator uses its
+    tangential part): (0.6 - x2, x1 + 0.4 x3, 0.5 x1 x2)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.stack([0.6 - x[:, 1], x[:, 0] + 0.4 * x[:, 2], 0.5 * x[:, 0] * x[:, 1]], axis=1)
+
+
 def a_seed_field(seed: int, n_modes: int = 8):
     """Smooth field with values in [0.5, 2]: a = 2^tanh(s), s = sum_k alpha_k cos(w_k . x + phi_k).
 
