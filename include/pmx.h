@@ -117,7 +117,11 @@ typedef struct pmx_operator_stats {
 } pmx_operator_stats;
 
 /* Context on one GPU.  hbm_budget_bytes bounds what the context's operators and
- * server may hold (0 = no bound).  Errors: INVALID (no such device), DEVICE. */
+ * server may hold (0 = no bound).  Errors: INVALID (no such device), DEVICE.
+ * Handle lifetimes: a surface holds a reference on its context, an operator on its surface
+ * and a server on its context, so the destroy calls may come in any order (a garbage
+ * collector's, say): a context or surface is freed once it has been destroyed and the last
+ * handle made from it is gone.  Each handle is destroyed once; destroy calls are NULL-safe. */
 PMX_API pmx_status pmx_ctx_create(int device, uint64_t hbm_budget_bytes, pmx_ctx** out);
 PMX_API void pmx_ctx_destroy(pmx_ctx* ctx);
 /* Message of the last error on the calling thread ("" if none). */
@@ -139,25 +143,30 @@ PMX_API void pmx_surface_destroy(pmx_surface* s);
 /* Operator for the coefficient a > 0 at the nodes (N) with its ambient or surface
  * gradient (N x 3; the tangential part is used, Section 4.1).  Builds near lists and
  * the FP64 correction blocks of the self and near rules (Sections 6.1.1, 6.1.2).
- * opts may be NULL (defaults).  The surface must outlive the operator.
+ * opts may be NULL (defaults).  The operator holds a reference on the surface.
  * Errors: INVALID (a <= 0 or non-finite), TOO_LARGE (budget), OOM, DEVICE. */
 PMX_API pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* grad_a, const pmx_options* opts,
                                int mem_kind, void* stream, pmx_operator** out);
-/* Operator of the general surface PDE div_G(a grad_G u) + c u = f (eq:surf_PDE with b = 0) for a
+/* Operator of the general surface PDE div_G(a grad_G u) + b . grad_G u + c u = f (eq:surf_PDE) for a
  * coefficient c < 0 at every node (N values; the modified Helmholtz-Beltrami type, Section 4.1 and
- * Section 7).  The parametrix uses G(r; a, c) = -K0(sqrt(-c/a) r) / (2 pi a) with the coefficients
+ * Section 7) and an optional advection field b (3N values, node i's vector at b[3i..3i+2] as for
+ * grad_a, ambient components; its tangential part is used; NULL: b = 0).  The parametrix uses G(r; a, c) = -K0(sqrt(-c/a) r) / (2 pi a) with the coefficients
  * at the source (eq:diff_param; the printed Hankel form read with the sign for which
- * (a Delta + c) G = delta) and the remainder of eq:explicit_remainder with its c-term.  With c != 0
+ * (a Delta + c) G = delta) and the remainder of eq:explicit_remainder with its c-term, plus
+ * b . grad_G K with b (eq:adv_remainder; the system is then eq:IE_adv).  b is taken with c < 0
+ * only: with c = 0 the solvability condition on f is not a zero mean once b != 0.  With c != 0
  * the problem has no null space: the system is sigma + R sigma = f (Theorem thm:second_kind, no
  * rank-one term), f is used as given (info.removed_mean = 0) and u = K sigma is not shifted.
  * Only the FP64 direct far field is available (PMX_PREC_FP64_DIRECT for pmx_apply, pmx_solve and
  * the allocation-free apply; other precisions give INVALID): the FMM's translation operators need a
  * kernel of x - y alone up to a per-source factor, while here the decay rate sqrt(-c/a) changes from
- * source to source.  Arguments as for pmx_operator_create, plus c (N, mem_kind memory).
- * Errors: INVALID (c null, c >= 0 or non-finite at some node, and as pmx_operator_create), TOO_LARGE,
- * OOM, DEVICE. */
+ * source to source.  Arguments as for pmx_operator_create, plus c (N) and b (3N or NULL), both in
+ * mem_kind memory and read during the call only.
+ * Errors: INVALID (c null, c >= 0 or non-finite at some node, b non-finite, and as
+ * pmx_operator_create), TOO_LARGE, OOM, DEVICE. */
 PMX_API pmx_status pmx_operator_create_c(pmx_surface* s, const double* a, const double* grad_a, const double* c,
-                                 const pmx_options* opts, int mem_kind, void* stream, pmx_operator** out);
+                                 const double* b, const pmx_options* opts, int mem_kind, void* stream,
+                                 pmx_operator** out);
 PMX_API void pmx_operator_destroy(pmx_operator* op);
 PMX_API pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* out);
 

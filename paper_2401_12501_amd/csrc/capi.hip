@@ -266,7 +266,9 @@ pmx_status pmx_ctx_create(int device, uint64_t hbm_budget_bytes, pmx_ctx** out) 
   });
 }
 
-void pmx_ctx_destroy(pmx_ctx* ctx) { delete ctx; }
+void pmx_ctx_destroy(pmx_ctx* ctx) {
+  if (ctx) ctx_release(ctx);
+}
 
 pmx_status pmx_surface_create(pmx_ctx* ctx, int n_patches, int q, const double* x, const double* xu,
                               const double* xv, const double* xuu, const double* xuv, const double* xvv, int mem_kind,
@@ -295,14 +297,17 @@ pmx_status pmx_surface_create(pmx_ctx* ctx, int n_patches, int q, const double* 
       delete s;
       throw;
     }
+    ctx_retain(ctx);
     *out = s;
   });
 }
 
-void pmx_surface_destroy(pmx_surface* s) { delete s; }
+void pmx_surface_destroy(pmx_surface* s) {
+  if (s) surface_release(s);
+}
 
 namespace {
-pmx_status operator_create(pmx_surface* s, const double* a, const double* grad_a, const double* c,
+pmx_status operator_create(pmx_surface* s, const double* a, const double* grad_a, const double* c, const double* b,
                            const pmx_options* opts, int mem_kind, void* stream, pmx_operator** out) {
   return guarded([&] {
     PMX_REQUIRE(s && out, PMX_ERR_INVALID, "null handle");
@@ -316,11 +321,12 @@ pmx_status operator_create(pmx_surface* s, const double* a, const double* grad_a
       check_opts(op->opts);
       const double t0 = now_seconds();
       Ctx* ctx = &s->ctx->c;
-      DBuf<double> ba, bg, bc;
+      DBuf<double> ba, bg, bc, bb;
       const double* da = stage_in(ctx, ba, a, s->g.N, mem_kind, st);
       const double* dg = stage_in(ctx, bg, grad_a, 3 * (size_t)s->g.N, mem_kind, st);
       const double* dc = c ? stage_in(ctx, bc, c, s->g.N, mem_kind, st) : nullptr;
-      build_coeff(ctx, s->g, op->co, da, dg, dc, st);
+      const double* db = b ? stage_in(ctx, bb, b, 3 * (size_t)s->g.N, mem_kind, st) : nullptr;
+      build_coeff(ctx, s->g, op->co, da, dg, dc, db, st);
       build_near_lists(ctx, s->g, op->opts.eta_near, op->nl, st);
       build_near_weights(ctx, s->g, op->co, op->nl, op->opts, false, st);
       PMX_HIP(hipStreamSynchronize(st));
@@ -330,6 +336,7 @@ pmx_status operator_create(pmx_surface* s, const double* a, const double* grad_a
       delete op;
       throw;
     }
+    surface_retain(s);
     *out = op;
   });
 }
@@ -337,17 +344,18 @@ pmx_status operator_create(pmx_surface* s, const double* a, const double* grad_a
 
 pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* grad_a, const pmx_options* opts,
                                int mem_kind, void* stream, pmx_operator** out) {
-  return operator_create(s, a, grad_a, nullptr, opts, mem_kind, stream, out);
+  return operator_create(s, a, grad_a, nullptr, nullptr, opts, mem_kind, stream, out);
 }
 
 pmx_status pmx_operator_create_c(pmx_surface* s, const double* a, const double* grad_a, const double* c,
-                                 const pmx_options* opts, int mem_kind, void* stream, pmx_operator** out) {
+                                 const double* b, const pmx_options* opts, int mem_kind, void* stream,
+                                 pmx_operator** out) {
   if (!c) {
-    set_last_error("c is null (use pmx_operator_create for c = 0)");
+    set_last_error("c is null (use pmx_operator_create for c = 0, which takes no advection field)");
     if (out) *out = nullptr;
     return PMX_ERR_INVALID;
   }
-  return operator_create(s, a, grad_a, c, opts, mem_kind, stream, out);
+  return operator_create(s, a, grad_a, c, b, opts, mem_kind, stream, out);
 }
 
 void pmx_operator_destroy(pmx_operator* op) {
@@ -358,7 +366,9 @@ void pmx_operator_destroy(pmx_operator* op) {
   if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
   if (op->ev_join) (void)hipEventDestroy(op->ev_join);
   if (op->side) (void)hipStreamDestroy(op->side);
+  pmx_surface* s = op->s;
   delete op;
+  surface_release(s);
 }
 
 pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* out) {

@@ -288,8 +288,30 @@ __global__ void k_coeff_c(int64_t N, const double* __restrict__ c_in, double* __
   c[i] = v;
 }
 
+// Advection (eq:adv_remainder): b . grad_G K = G' (b_t . r_hat) for the tangential part b_t of b,
+// the same form as the grad_G a . r_hat G' term, so b_t / (2 pi) joins g = grad_G a / (2 pi) in
+// the target vectors (g, and h = g - B n).
+__global__ void k_coeff_b(int64_t N, const double* __restrict__ b_in, const double* __restrict__ Nn,
+                          double* __restrict__ tg, double* __restrict__ tf, float* __restrict__ t32,
+                          int* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double b0 = b_in[3 * i], b1 = b_in[3 * i + 1], b2 = b_in[3 * i + 2];
+  if (!isfinite(b0) || !isfinite(b1) || !isfinite(b2)) atomicOr(bad, 4);
+  const double n0 = Nn[i], n1 = Nn[N + i], n2 = Nn[2 * N + i];
+  const double nd = n0 * b0 + n1 * b1 + n2 * b2;
+  const double inv_2pi = 0.15915494309189533577;
+  const double t[3] = {(b0 - n0 * nd) * inv_2pi, (b1 - n1 * nd) * inv_2pi, (b2 - n2 * nd) * inv_2pi};
+  for (int k = 0; k < 3; ++k) {
+    tg[k * N + i] += t[k];
+    const double h = tf[(6 + k) * N + i] + t[k];
+    tf[(6 + k) * N + i] = h;
+    t32[(6 + k) * N + i] = (float)h;
+  }
+}
+
 void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const double* grad_a, const double* c,
-                 hipStream_t st) {
+                 const double* b, hipStream_t st) {
   const int64_t N = g.N;
   co.a.alloc(ctx, N);
   co.gs.alloc(ctx, 3 * N);
@@ -309,11 +331,18 @@ void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const 
     hipLaunchKernelGGL(k_coeff_c, dim3((N + 255) / 256), dim3(256), 0, st, N, c, co.c.p, bad.p);
     PMX_HIP(hipGetLastError());
   }
+  if (b) {
+    hipLaunchKernelGGL(k_coeff_b, dim3((N + 255) / 256), dim3(256), 0, st, N, b, g.n.p, co.tg.p, co.tf64.p,
+                       co.tgt32.p, bad.p);
+    PMX_HIP(hipGetLastError());
+    co.has_b = true;
+  }
   int hbad = 0;
   PMX_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
   PMX_HIP(hipStreamSynchronize(st));
   PMX_REQUIRE(!(hbad & 1), PMX_ERR_INVALID, "coefficient a must be positive and finite, grad a finite");
   PMX_REQUIRE(!(hbad & 2), PMX_ERR_INVALID, "coefficient c must be negative and finite at every node");
+  PMX_REQUIRE(!(hbad & 4), PMX_ERR_INVALID, "advection field b must be finite");
 }
 
 void build_near_lists(Ctx* ctx, const Geometry& g, double eta, NearLists& nl, hipStream_t st) {

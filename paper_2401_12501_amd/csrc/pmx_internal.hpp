@@ -145,11 +145,12 @@ struct Coeff {
   DBuf<double> a;       // N
   DBuf<double> gs;      // 3N surface gradient
   DBuf<double> tgt;     // 8N: x y z nx ny nz A B | (g stored below)
-  DBuf<double> tg;      // 3N: g = grad_G a / (2 pi)
-  DBuf<double> tf64;    // 9N: x y z n'x n'y n'z hx hy hz
+  DBuf<double> tg;      // 3N: g = (grad_G a + b_t) / (2 pi), b_t the tangential advection field (0 without b)
+  DBuf<double> tf64;    // 9N: x y z n'x n'y n'z hx hy hz (h = g - B n)
   DBuf<float> tgt32;    // 9N: the same in FP32
   DBuf<double> w_over_a;  // N
   DBuf<double> c;       // N: the zero-order coefficient c < 0; empty for c = 0
+  bool has_b = false;   // an advection field is folded into g and h
   bool has_c() const { return c.p != nullptr; }
 };
 
@@ -349,14 +350,34 @@ struct Profiler {
 
 }  // namespace pmx
 
+// Handles hold references on what they were created from (surface -> context, operator ->
+// surface, server -> context), so the caller may destroy handles in any order: a context or
+// surface is freed when its own destroy call and the last handle using it have both gone.
+// refs counts the caller's handle (1 until its destroy call) plus the dependent handles.
 struct pmx_ctx {
   pmx::Ctx c;
+  std::atomic<int> refs{1};
+  bool owned = true;   // false for a context on the stack (a serving request's accounting)
 };
 
 struct pmx_surface {
   pmx_ctx* ctx = nullptr;
   pmx::Geometry g;
+  std::atomic<int> refs{1};
 };
+
+inline void ctx_retain(pmx_ctx* c) { c->refs.fetch_add(1, std::memory_order_relaxed); }
+inline void ctx_release(pmx_ctx* c) {
+  if (c->refs.fetch_sub(1, std::memory_order_acq_rel) == 1 && c->owned) delete c;
+}
+inline void surface_retain(pmx_surface* s) { s->refs.fetch_add(1, std::memory_order_relaxed); }
+inline void surface_release(pmx_surface* s) {
+  if (s->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+    pmx_ctx* c = s->ctx;
+    delete s;   // its buffers return their bytes to the context, which is still alive
+    ctx_release(c);
+  }
+}
 
 struct pmx_operator {
   pmx_surface* s = nullptr;
@@ -411,7 +432,7 @@ void build_geometry(Ctx* ctx, Geometry& g, const double* x, const double* xu, co
                     const double* xuv, const double* xvv, hipStream_t st);
 // c: nullptr for c = 0, else N values, each negative and finite (checked).
 void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const double* grad_a, const double* c,
-                 hipStream_t st);
+                 const double* b, hipStream_t st);
 void build_near_lists(Ctx* ctx, const Geometry& g, double eta, NearLists& nl, hipStream_t st);
 // nearweights.hip
 void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists& nl, const pmx_options& o,

@@ -191,6 +191,7 @@ void run_request(pmx_server* sv, pmx_options opts, Request* r, pmx_batcher* batc
   pmx_operator* op = nullptr;
   pmx_ctx* sctx = sv->ctx;
   pmx_ctx rctx;   // the request's own accounting, charged to the server's context
+  rctx.owned = false;
   rctx.c.device = sctx->c.device;
   rctx.c.n_cu = sctx->c.n_cu;
   rctx.c.parent = &sctx->c;
@@ -285,6 +286,7 @@ pmx_status pmx_server_create(pmx_ctx* ctx, const pmx_options* opts, int max_acti
   }
   b->thr = std::thread(batcher_loop, b);
   sv->batcher = b;
+  ctx_retain(ctx);
   *out = sv;
   return PMX_OK;
 }
@@ -445,7 +447,9 @@ void pmx_server_destroy(pmx_server* sv) {
     (void)hipStreamDestroy(b->st);
     delete b;
   }
+  pmx_ctx* ctx = sv->ctx;
   delete sv;
+  ctx_release(ctx);
 }
 
 }  // extern "C"

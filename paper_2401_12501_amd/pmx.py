@@ -62,7 +62,8 @@ _SIGS = {
                                         C.POINTER(_vp)]),
     "pmx_surface_destroy": (None, [_vp]),
     "pmx_operator_create": (C.c_int32, [_vp, _vp, _vp, C.POINTER(pmx_options), C.c_int, _vp, C.POINTER(_vp)]),
-    "pmx_operator_create_c": (C.c_int32, [_vp, _vp, _vp, _vp, C.POINTER(pmx_options), C.c_int, _vp, C.POINTER(_vp)]),
+    "pmx_operator_create_c": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(pmx_options), C.c_int, _vp,
+                                          C.POINTER(_vp)]),
     "pmx_operator_destroy": (None, [_vp]),
     "pmx_operator_get_stats": (C.c_int32, [_vp, C.POINTER(pmx_operator_stats)]),
     "pmx_apply": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_int, _vp]),
@@ -217,20 +218,23 @@ class Surface:
 class Operator:
     """pmx_operator_create and the calls on an operator."""
 
-    def __init__(self, surface: Surface, a, grad_a, opts: pmx_options | None = None, c=None):
-        """pmx_operator_create, or pmx_operator_create_c when c (N values, all negative) is given."""
+    def __init__(self, surface: Surface, a, grad_a, opts: pmx_options | None = None, c=None, b=None):
+        """pmx_operator_create, or pmx_operator_create_c when c (N values, all negative) is given,
+        with the advection field b ((N, 3) ambient vectors) or without (b None)."""
         self.surface = surface
         self.N = surface.N
         self.q = surface.q
         self.opts = opts if opts is not None else pmx_default_options()
-        ptrs, kind, stream, keep = _marshal(a, grad_a, c)
+        ptrs, kind, stream, keep = _marshal(a, grad_a, c, b)
         h = _vp()
         if c is None:
+            if b is not None:
+                raise PmxError(PMX_ERR_INVALID, "an advection field b needs c < 0 (pmx_operator_create_c)")
             _check(lib().pmx_operator_create(surface.h, ptrs[0], ptrs[1], C.byref(self.opts), kind, stream,
                                              C.byref(h)))
         else:
-            _check(lib().pmx_operator_create_c(surface.h, ptrs[0], ptrs[1], ptrs[2], C.byref(self.opts), kind,
-                                               stream, C.byref(h)))
+            _check(lib().pmx_operator_create_c(surface.h, ptrs[0], ptrs[1], ptrs[2], ptrs[3], C.byref(self.opts),
+                                               kind, stream, C.byref(h)))
         self.h = h
 
     def close(self):

@@ -1,12 +1,15 @@
-"""The c < 0 path (div_G(a grad_G u) + c u = f, the modified Helmholtz-Beltrami type) through the C ABI
-against the FP64 oracle, element by element (max-abs error over max-abs value).
+"""The c < 0 path (div_G(a grad_G u) + b . grad_G u + c u = f, the modified Helmholtz-Beltrami type,
+with or without the advection field b) through the C ABI against the FP64 oracle, element by element
+(max-abs error over max-abs value).
 
 Cases: an ellipsoid with 6 patches of 7 x 7 nodes (294 nodes, not a multiple of any launch tile)
 and the unit sphere (24 patches, q = 8), both with the variable coefficients a = 2 + z and
-c = -4 - exp(x/2) (the kind of Section 7.4), and the unit sphere with a = 1, c = -4.  Bars: the
-correction blocks C and D within 1e-13 of their largest entry (plus 16x the oracle's one-ulp
-sensitivity where the geometry is under-resolved), FP64 applies, solves and the representation
-within 1e-12; the sphere eigenvalues -l(l+1) + c (Section 7.1) within the discretization error.
+c = -4 - exp(x/2) (the kind of Section 7.4), each without and with a non-tangent advection field
+(eq:adv_remainder); the unit sphere with a = 1, c = -4 (and with the rotation b = 1.5 e3 x x).
+Bars: the correction blocks C and D within 1e-13 of their largest entry (plus 16x the oracle's
+one-ulp sensitivity where the rules sample close to the target), FP64 applies, solves and the
+representation within 1e-12; the sphere eigenvalues -l(l+1) + c (Section 7.1) and the rotation's
+closed form within the discretization error.
 """
 import sys
 
@@ -43,7 +46,7 @@ class Case:
         self.prob = prob
         say(f"[case] {prob.name}: N={prob.n}, c in [{prob.c.min():.3f}, {prob.c.max():.3f}]")
         self.surf = pmx.Surface.from_inputs(ctx, prob.surface)
-        self.op = pmx.Operator(self.surf, prob.a, prob.grad_a, c=prob.c)
+        self.op = pmx.Operator(self.surf, prob.a, prob.grad_a, c=prob.c, b=prob.b)
         self.orc = OracleOperator.from_problem(prob)
         self.blocks = self.orc.blocks(np.arange(prob.n), kernels=("R", "K"))
         self.A = self.orc.dense_matrix(self.blocks)
@@ -59,7 +62,20 @@ def sphere(ctx):
     return Case(helmholtz_sphere_problem(k=2, q=8), ctx)
 
 
-@pytest.mark.parametrize("which", ["ragged", "sphere"])
+@pytest.fixture(scope="module")
+def ragged_b(ctx):
+    return Case(helmholtz_ellipsoid_problem(k=1, q=7, swirl=True), ctx)
+
+
+@pytest.fixture(scope="module")
+def sphere_b(ctx):
+    return Case(helmholtz_sphere_problem(k=2, q=8, swirl=True), ctx)
+
+
+CASES = ["ragged", "sphere", "ragged_b", "sphere_b"]
+
+
+@pytest.mark.parametrize("which", CASES)
 def test_blocks_c(which, request):
     """Correction blocks C (remainder with c) and D (parametrix with c) against the oracle's.  The
     bar is that of the patch-order parity test: 1e-13 of the largest entry, plus 16x the oracle's
@@ -98,7 +114,7 @@ def test_blocks_c(which, request):
             f"sensitivity")
 
 
-@pytest.mark.parametrize("which", ["ragged", "sphere"])
+@pytest.mark.parametrize("which", CASES)
 def test_apply_solve_represent_c(which, request):
     from paper_2401_12501_amd import pmx
     case = request.getfixturevalue(which)
@@ -147,6 +163,26 @@ def test_sphere_eigenvalues_shift_by_c_gpu(ctx):
     assert worst < 1e-4
 
 
+def test_sphere_rotation_closed_form_gpu(ctx):
+    """a = 1, c = -4, b = 1.5 e3 x x on the unit sphere (24 patches, q = 8): f = Y_l^m cos gives
+    the closed form alpha Y_l^m cos + beta Y_l^m sin (b . grad_G = 1.5 d/dphi there)."""
+    from paper_2401_12501_amd import pmx
+    from test_oracle_advection import rotation_solution
+    import torch
+    p = helmholtz_sphere_problem(k=2, q=8, c0=-4.0, omega=1.5)
+    surf = pmx.Surface.from_inputs(ctx, p.surface)
+    op = pmx.Operator(surf, p.a, p.grad_a, c=p.c, b=p.b)
+    X = torch.tensor(p.surface.x)
+    worst = 0.0
+    for l, m in ((1, 1), (2, 1), (3, 2), (4, 3), (2, 0)):
+        f, ref = rotation_solution(l, m, 1.5, -4.0, X)
+        _, u, info = op.solve(f[None, :].copy(), want_u=True)
+        e = float(np.abs(u[0] - ref).max() / np.abs(ref).max())
+        worst = max(worst, e)
+        say(f"[rotation] l={l} m={m}: u error {e:.2e}, iters {info[0].iters_total}")
+    assert worst < 1e-6
+
+
 def test_c_error_contract(ctx):
     from paper_2401_12501_amd import pmx
     p = helmholtz_ellipsoid_problem(k=1, q=5)
@@ -168,3 +204,11 @@ def test_c_error_contract(ctx):
     assert e.value.code == pmx.PMX_ERR_INVALID
     y = op.apply(sig, pmx.PMX_PREC_FP64_DIRECT)      # still usable
     assert np.all(np.isfinite(y))
+    bb = np.zeros((p.n, 3))
+    bb[5, 1] = np.inf
+    with pytest.raises(pmx.PmxError) as e:
+        pmx.Operator(surf, p.a, p.grad_a, c=p.c, b=bb)
+    assert e.value.code == pmx.PMX_ERR_INVALID
+    # b = 0 gives the operator without b, bit for bit
+    y0 = pmx.Operator(surf, p.a, p.grad_a, c=p.c, b=np.zeros((p.n, 3))).apply(sig, pmx.PMX_PREC_FP64_DIRECT)
+    assert np.array_equal(y0, y)

@@ -56,3 +56,31 @@ def test_create_use_destroy_returns_memory():
     assert base - after < min(held), (base, after, held)
     say(f"[lifetime] 6 create/use/destroy cycles: operator footprint {held[0] / 2**20:.1f} MiB, "
         f"free memory change {(base - after) / 2**20:.2f} MiB")
+
+
+def test_destroy_in_any_order():
+    """A surface holds a reference on its context and an operator on its surface: the context may
+    be destroyed first and the operator still applies (the same values), then the surface, then
+    the operator; a garbage cycle holding all three (finalizers in arbitrary order) is collected
+    cleanly."""
+    from paper_2401_12501_amd import pmx
+    p = ellipsoid_problem(k=2, q=6)
+    sig = np.ascontiguousarray(random_density(p.n, 1, seed=4).T)
+    ctx = pmx.Context(0)
+    surf = pmx.Surface.from_inputs(ctx, p.surface)
+    op = pmx.Operator(surf, p.a, p.grad_a)
+    y0 = op.apply(sig, pmx.PMX_PREC_FP64_DIRECT)
+    ctx.close()
+    y1 = op.apply(sig, pmx.PMX_PREC_FP64_DIRECT)
+    surf.close()
+    y2 = op.apply(sig, pmx.PMX_PREC_FP64_DIRECT)
+    op.close()
+    assert np.array_equal(y0, y1) and np.array_equal(y0, y2)
+    for _ in range(3):
+        ctx = pmx.Context(0)
+        surf = pmx.Surface.from_inputs(ctx, p.surface)
+        holder = {"ops": [pmx.Operator(surf, p.a, p.grad_a) for _ in range(2)], "surf": surf, "ctx": ctx}
+        holder["self"] = holder
+        del ctx, surf, holder
+        gc.collect()
+    say("[lifetime] out-of-order destroys and garbage cycles: clean")
