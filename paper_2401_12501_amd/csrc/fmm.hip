@@ -435,11 +435,9 @@ __global__ void __launch_bounds__((64 * m2l_waves<P, Split>())) k_m2l(Group<M2LA
   constexpr bool kSplit = Split;
   static_assert(!kSplit || (m2l_can_split<P>() && n_waves == 16),
                 "half waves 0, 5, 10, 15: one per group of four and per SIMD");
-  constexpr int kThr = 64 * n_waves;
-  constexpr int kPer = (kItemCols * p3 + kThr - 1) / kThr;   // staged multipole values per thread
   // persistent: each workgroup takes items blockIdx.x, + gridDim.x, ...; the next item's
-  // multipoles are loaded into registers while the current item is computed, then written
-  // to the other LDS buffer, so the staging latency is off the critical path
+  // multipoles travel into the other LDS buffer while the current item is computed, so the
+  // staging latency is off the critical path
   __shared__ float sB[2][kItemCols * kM2LStride];
   __shared__ float4 sN[p3];
   __shared__ float sS[2][2][kItemCols];
@@ -455,47 +453,66 @@ __global__ void __launch_bounds__((64 * m2l_waves<P, Split>())) k_m2l(Group<M2LA
     const float* nd = g.a[0].tab + P + 2 * P * P + 3 * m;   // node table: the same for every operator
     sN[m] = make_float4(nd[0], nd[1], nd[2], 0.0f);
   }
-  float stage[kPer];
-  auto load = [&](int64_t bi) {   // item bi's column multipoles, W[source box of column j][m]
+  // Item bi's column multipoles go straight from memory into LDS buffer buf (global_load_lds:
+  // no registers, no wait until the next item's barrier): column j of the item is W[source box
+  // of column j][0, p^3), in segments of 64 values, one wave-wide load each, dealt round the
+  // waves.  The columns' source boxes (sQ) and the item's record (sQit) come from LDS, filled
+  // by 32 threads before a barrier, so the loads do not wait on one another.  Columns past the item's count are not
+  // loaded: an MFMA output column depends on its own B column only, and those outputs are
+  // never stored.
+  constexpr int kSeg = (p3 + 63) / 64;
+  __shared__ int sQ[kItemCols];   // source box of each column of the next item
+  __shared__ int4 sQit[2];        // item records: item k's in sQit[k & 1]
+  auto fetch_next = [&](int64_t bi, int slot) {   // threads below kItemCols: item bi's record, sources
     int64_t lbi;
     const M2LArgs& B = seg_of(g, bi, lbi);
     const int4 itn = B.items[lbi];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = threadIdx.x + q * kThr;
-      const int j = e / p3, m = e - j * p3;
-      stage[q] = (e < kItemCols * p3 && j < itn.y) ? B.W[(int64_t)B.ps[itn.x + j] * p3 + m] : 0.0f;
-    }
+    const int j = threadIdx.x;
+    sQ[j] = B.ps[itn.x + (j < itn.y ? j : 0)];
+    if (j == 0) sQit[slot] = itn;
   };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = threadIdx.x + q * kThr;
-      const int j = e / p3, m = e - j * p3;
-      if (e < kItemCols * p3) sB[buf][j * kM2LStride + m] = stage[q];
+  auto prefetch = [&](int64_t bi, int buf, int nc) {
+    int64_t lbi;
+    const M2LArgs& B = seg_of(g, bi, lbi);
+    for (int t = wave; t < nc * kSeg; t += n_waves) {
+      const int j = t / kSeg, m0 = (t - j * kSeg) * 64;
+      const int32_t sb = __builtin_amdgcn_readfirstlane(sQ[j]);
+      if (m0 + lane < p3)
+        __builtin_amdgcn_global_load_lds(
+            (const void __attribute__((address_space(1)))*)(B.W + (int64_t)sb * p3 + m0 + lane),
+            (void __attribute__((address_space(3)))*)(&sB[buf][j * kM2LStride + m0]), 4, 0, 0);
     }
   };
   if (blockIdx.x < total) {
-    load(blockIdx.x);
-    store(0);
+    if (threadIdx.x < kItemCols) fetch_next(blockIdx.x, 0);
+    __syncthreads();
+    prefetch(blockIdx.x, 0, __builtin_amdgcn_readfirstlane(sQit[0].y));
+    __syncthreads();   // sQ is rewritten before the first item's barrier
   }
   int k = 0;
   for (int64_t bi = blockIdx.x; bi < total; bi += gridDim.x, ++k) {
     const int buf = k & 1;
     int64_t lb;
     const M2LArgs& A = seg_of(g, bi, lb);
-    const int4 it = A.items[lb];
+    // this item's record (written before an earlier barrier; the next one goes to the other slot)
+    const int4 it = make_int4(__builtin_amdgcn_readfirstlane(sQit[buf].x), __builtin_amdgcn_readfirstlane(sQit[buf].y),
+                              0, __builtin_amdgcn_readfirstlane(sQit[buf].w));
     const int ncol = it.y;
+    const int64_t bn = bi + gridDim.x;
     if (threadIdx.x < kItemCols) {   // this buffer's previous item finished before the last barrier
       const int j = threadIdx.x;
-      const double h = A.h0 / (double)(1 << (j < ncol ? A.plev[it.x + j] : 0));
+      const int jj = j < ncol ? j : 0;
+      const int lev = A.plev[it.x + jj], slot = A.pslot[it.x + jj];
+      if (bn < total) fetch_next(bn, buf ^ 1);   // the last prefetch read sQ before the last barrier
+      const double h = A.h0 / (double)(1 << lev);
       sS[buf][0][j] = (float)(1.0 / h);
       sS[buf][1][j] = (float)(1.0 / (h * h));
-      sP[buf][j] = j < ncol ? A.pslot[it.x + j] : 0;
+      sP[buf][j] = slot;
     }
-    const int64_t bn = bi + gridDim.x;
-    if (bn < total) load(bn);
-    __syncthreads();   // this item's multipoles (stored last iteration), scales and slots are in LDS
+    // this wave's loads of the item's multipoles (issued during the previous item) have landed;
+    // after the barrier every wave's have, and the scales and slots are in LDS
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
     const int code = it.w;
     const float ox = 2.0f * (float)(code / 49 - 3), oy = 2.0f * (float)((code / 7) % 7 - 3),
                 oz = 2.0f * (float)(code % 7 - 3);
@@ -550,6 +567,10 @@ __global__ void __launch_bounds__((64 * m2l_waves<P, Split>())) k_m2l(Group<M2LA
     } else {
       run(std::integral_constant<int, kColTiles>{}, 0);
     }
+    // the next item's multipoles into the other buffer (its item finished before the last
+    // barrier); issued after the MFMA loop, whose LDS reads would otherwise wait for them, so
+    // their latency overlaps the slot stores and the barriers
+    if (bn < total) prefetch(bn, buf ^ 1, __builtin_amdgcn_readfirstlane(sQit[buf ^ 1].y));
     const int l0 = rt * 16 + 4 * kq;
 #pragma unroll
     for (int ct = 0; ct < kColTiles; ++ct) {
@@ -572,8 +593,7 @@ __global__ void __launch_bounds__((64 * m2l_waves<P, Split>())) k_m2l(Group<M2LA
         }
       }
     }
-    if (bn < total) store(buf ^ 1);   // the other buffer's item was finished before this barrier
-    __syncthreads();
+    __syncthreads();   // every wave is done with this item's LDS buffers
   }
 }
 
