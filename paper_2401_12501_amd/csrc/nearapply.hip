@@ -242,20 +242,23 @@ __global__ void k_sub_mean(int64_t N, double* __restrict__ u, const double* __re
   if (i < N) u[(int64_t)r * N + i] -= s[r] / area;
 }
 
-// Near correction for a group of RB right-hand sides (8 or 16), one workgroup per target
-// patch T.  For every patch P in the union of the near lists of T's targets, the rows of T's
-// targets with P form a q^2 x q^2 block C_{T,P} (rows of targets not near P are zero), and
+// Near correction for a group of RB right-hand sides (8 or 16), one workgroup per slab of at
+// most 64 target rows of a target patch T.  For every patch P in the union of the near lists of
+// T's targets, the rows of T's targets with P form a q^2 x q^2 block C_{T,P} (rows of targets
+// not near P are zero), and
 //   Y_T += C_{T,P} Sigma_P,   Sigma_P = sigma of P's nodes for the RB right-hand sides,
 // a dense contraction that runs on FP64 MFMA (16 x 16 x 4): the right-hand sides are the
-// sixteen columns, each wave owns 16-row tiles of Y_T, and the accumulators stay in registers
-// across the union.  The contraction runs over P's nodes in chunks of kKC: each chunk's slice of
-// every block row (kKC consecutive doubles of a row stored contiguously) and of Sigma_P are
-// staged in LDS with coalesced loads, so the blocks stream from HBM once in full-width loads.
-// Each target sums its patches in union order, so results are deterministic; the output goes
-// through LDS so that y is written with unit stride per right-hand side.
+// sixteen columns, each wave owns one 16-row tile of the slab, and the accumulators stay in
+// registers across the union.  The contraction runs over P's nodes in chunks of kKC = 32: each
+// chunk's slice of every block row of the slab (32 consecutive doubles of a row stored
+// contiguously) and of Sigma_P goes straight from memory into LDS (global_load_lds, 16 bytes
+// per lane), every load of the chunk in flight at once and one wait before the barrier.  Each
+// target sums its patches in union order, so results are deterministic; the output goes through
+// LDS so that y is written with unit stride per right-hand side.
 struct TiledArgs {
   int64_t N, n_patches;
   int q2, r0;
+  int n_slab;   // slabs of at most 64 rows per target patch
   const int32_t* tile_ptr;
   const int32_t* tile_patch;
   const int32_t* tile_pair;
@@ -267,101 +270,132 @@ struct TiledArgs {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int kXcds = 8;           // accelerator complex dies of the GPU, each with its own L2
-constexpr int kKC = 32;            // source nodes per staged chunk
-constexpr int kLdC = kKC + 1;      // LDS row stride of the block slices (doubles)
+constexpr int kKC = 32;            // source nodes per staged chunk: 256-byte LDS rows of 16 slots
 constexpr int kLdY = 17;           // LDS row stride of the output tile (doubles)
+constexpr int kSlab = 64;          // target rows per workgroup: four waves of one 16-row tile
 
-// One buffer of block slices and sigma slices, small enough for several workgroups per compute
-// unit: their loads hide each other's latency (double-buffering each workgroup's chunks with
-// register prefetch needs twice the LDS and was measured 2.4x slower on the torus).
+// Sixteen zero bytes: the source of every staged slot that lies past a chunk's columns or in
+// the row of a target not near P (a direct-to-LDS load cannot write a constant).
+__device__ __align__(16) double near_zero16[2] = {0.0, 0.0};
+
+// LDS rows hold 16 slots of two doubles; slot s of row t is stored at position s ^ (t & 15), so
+// that the sixteen rows an MFMA operand read touches (same column, consecutive rows) fall in
+// different banks.
+__device__ __forceinline__ int near_swz(int t, int c) { return t * kKC + (((c >> 1) ^ (t & 15)) << 1) + (c & 1); }
+
+__device__ __forceinline__ void lds_load16(const double* src, double* dst_wave_base) {
+  __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                   (void __attribute__((address_space(3)))*)dst_wave_base, 16, 0, 0);
+}
+
 template <int RB>
-__global__ void __launch_bounds__(256) k_near_tiled(Group<TiledArgs> g) {
-  // LDS: block slices sC[q^2 rounded to 16][kLdC], then sS[kKC][16]; the output tile sY
-  // [q^2][kLdY] reuses sC once the contraction is done
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_near_tiled(Group<TiledArgs> g) {
+  constexpr int kGroups = kSlab / 4 / 4;   // four-row staging groups per wave
+  // LDS: block slices sC[64][kKC], then sigma slices sS[16][kKC] (right-hand side, node), both
+  // swizzled; the output tile sY[64][kLdY] reuses sC once the contraction is done
   extern __shared__ double lds[];
   int64_t lb;
   const TiledArgs& A = seg_of(g, blockIdx.x, lb);
-  // XCD-aware order: workgroups are dealt round-robin over the eight XCDs, so block lb runs on
-  // XCD lb % 8; that XCD takes a contiguous range of target patches, whose neighbours share
-  // near patches, so their densities are reused from the XCD's L2
-  const int64_t M = A.n_patches;
-  const int64_t xq = M / kXcds, xr = M % kXcds, xc = lb % kXcds;
-  const int64_t T = xc * xq + (xc < xr ? xc : xr) + lb / kXcds;
+  // XCD-aware order over the slabs V = T n_slab + h: workgroups are dealt round-robin over the
+  // eight XCDs, so block lb runs on XCD lb % 8; that XCD takes a contiguous range of slabs, so
+  // neighbouring target patches, which share near patches, reuse densities from its L2
+  const int64_t MS = A.n_patches * A.n_slab;
+  const int64_t xq = MS / kXcds, xr = MS % kXcds, xc = lb % kXcds;
+  const int64_t V = xc * xq + (xc < xr ? xc : xr) + lb / kXcds;
+  const int64_t T = V / A.n_slab;
+  const int t0 = (int)(V - T * A.n_slab) * kSlab;   // the slab's first target row
   const int64_t N = A.N;
   const int q2 = A.q2;
-  const int rows = (q2 + 15) & ~15;
+  const int qs = q2 - t0 < kSlab ? q2 - t0 : kSlab; // target rows of the slab
+  const int rows = (qs + 15) & ~15;
   double* sC = lds;
-  double* sS = lds + (size_t)rows * kLdC;
+  double* sS = lds + (size_t)kSlab * kKC;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4, col = lane & 15;
-  const int n_rt = rows / 16;                    // row tiles; wave w takes w, w + 4, ...
-  doublex4 acc[4];
+  const bool has_tile = wave * 16 < rows;        // wave w owns row tile w
+  // staging: a wave-wide load writes four consecutive 256-byte rows; lane l writes slot l % 16
+  // of slab row 4 G + l / 16 of its group G = wave, wave + 4, ... (that row's pair index below)
+  const int lr = lane >> 4, ls = lane & 15;
+  const int n_groups = rows / 4;
+  doublex4 acc = doublex4{0.0, 0.0, 0.0, 0.0};
+  const int u0 = A.tile_ptr[T], u1 = A.tile_ptr[T + 1];
+  // pair indices of this lane's staged rows for union entry u, one entry ahead in registers
+  auto load_pairs = [&](int u, int32_t* pr) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) acc[k] = doublex4{0.0, 0.0, 0.0, 0.0};
-  for (int u = A.tile_ptr[T]; u < A.tile_ptr[T + 1]; ++u) {
-    const int64_t P = A.tile_patch[u];
-    const int32_t* __restrict__ pairs = A.tile_pair + (int64_t)u * q2;
+    for (int i = 0; i < kGroups; ++i) {
+      const int t = t0 + 4 * (wave + 4 * i) + lr;
+      pr[i] = (u < u1 && t < q2) ? A.tile_pair[(int64_t)u * q2 + t] : -1;
+    }
+  };
+  int32_t pr_cur[kGroups], pr_next[kGroups];
+  load_pairs(u0, pr_cur);
+  int32_t P_cur = u0 < u1 ? A.tile_patch[u0] : 0;
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the first entry's indices are in registers
+  for (int u = u0; u < u1; ++u) {
+    const int64_t P = P_cur;
+    const int32_t P_next = u + 1 < u1 ? A.tile_patch[u + 1] : 0;   // one entry ahead, with its pairs
+    load_pairs(u + 1, pr_next);
     for (int kc = 0; kc < q2; kc += kKC) {
-      const int kw = q2 - kc < kKC ? q2 - kc : kKC;   // valid columns in this chunk
+      const int kw = q2 - kc < kKC ? q2 - kc : kKC;   // valid columns in this chunk (even)
       __syncthreads();   // the previous chunk's slices are no longer read
-      // block slices: row t, columns [kc, kc + kKC): eight lanes per row, four doubles each
-      for (int e = threadIdx.x; e < rows * (kKC / 4); e += 256) {
-        const int t = e / (kKC / 4), c4 = (e - t * (kKC / 4)) * 4;
-        const int pr = t < q2 ? pairs[t] : -1;
-        const double* src = A.Cb + (int64_t)(pr < 0 ? 0 : pr) * q2 + kc + c4;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          sC[t * kLdC + c4 + c] = (pr >= 0 && c4 + c < kw) ? src[c] : 0.0;
+      for (int i = 0; i < kGroups; ++i) {
+        const int G = wave + 4 * i;
+        if (G < n_groups) {
+          const int tl = 4 * G + lr;
+          const int c = 2 * (ls ^ (tl & 15));         // the columns slot ls of slab row tl holds
+          const double* src = (pr_cur[i] >= 0 && c < kw) ? A.Cb + (int64_t)pr_cur[i] * q2 + kc + c : near_zero16;
+          lds_load16(src, sC + 4 * G * kKC);
+        }
       }
-      // sigma slice: node kc + k of P for right-hand side r (unit stride in k)
-      for (int e = threadIdx.x; e < kKC * 16; e += 256) {
-        const int r = e / kKC, k = e - r * kKC;
-        sS[k * 16 + r] = (r < RB && k < kw) ? A.sigma[(int64_t)(A.r0 + r) * N + P * q2 + kc + k] : 0.0;
+      {   // sigma: right-hand side r = 4 wave + lr, nodes kc + c, c + 1 of P
+        const int r = 4 * wave + lr;
+        const int c = 2 * (ls ^ (r & 15));
+        const double* src = (r < RB && c < kw) ? A.sigma + (int64_t)(A.r0 + r) * N + P * q2 + kc + c : near_zero16;
+        lds_load16(src, sS + 4 * wave * kKC);
       }
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's slices have landed
       __syncthreads();
+      if (has_tile) {
 #pragma unroll
-      for (int ks = 0; ks < kKC; ks += 4) {
-        const double b = sS[(ks + kq) * 16 + col];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int rt = wave + 4 * k;
-          if (rt < n_rt) {
-            const double a = sC[(rt * 16 + col) * kLdC + ks + kq];
-            acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
-          }
+        for (int ks = 0; ks < kKC; ks += 4) {
+          const double bv = sS[near_swz(col, ks + kq)];
+          const double av = sC[near_swz(wave * 16 + col, ks + kq)];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
       }
     }
+#pragma unroll
+    for (int i = 0; i < kGroups; ++i) pr_cur[i] = pr_next[i];
+    P_cur = P_next;
   }
   __syncthreads();   // every wave is done with sC: it becomes the output tile
   double* sY = lds;
+  if (has_tile) {
+    // FP64 16x16x4 accumulators: register i of lane l holds row 4 i + l / 16, column l % 16
+    // (the FP32 16x16x4 form holds row 4 (l / 16) + i instead)
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int rt = wave + 4 * k;
-    if (rt < n_rt) {
-      // FP64 16x16x4 accumulators: register i of lane l holds row 4 i + l / 16, column l % 16
-      // (the FP32 16x16x4 form holds row 4 (l / 16) + i instead)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sY[(rt * 16 + 4 * i + kq) * kLdY + col] = acc[k][i];
-    }
+    for (int i = 0; i < 4; ++i) sY[(wave * 16 + 4 * i + kq) * kLdY + col] = acc[i];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < RB * q2; e += 256) {
-    const int r = e / q2, t = e - r * q2;
-    const int64_t at = (int64_t)(A.r0 + r) * N + T * q2 + t;
-    A.y[at] = sY[t * kLdY + r] + A.sigma[at] + A.ssum[A.r0 + r];
+  for (int e = threadIdx.x; e < RB * qs; e += 256) {
+    const int r = e / qs, tl = e - r * qs;
+    const int64_t at = (int64_t)(A.r0 + r) * N + T * q2 + t0 + tl;
+    A.y[at] = sY[tl * kLdY + r] + A.sigma[at] + A.ssum[A.r0 + r];
   }
 }
 
-// LDS bytes of k_near_tiled for patches of q2 nodes; patches of more than 14 x 14 nodes would
-// need more than the default 64 KiB of a workgroup and take the per-target kernel instead.
-size_t near_tiled_lds(int q2) {
-  const size_t rows = (size_t)((q2 + 15) & ~15);
-  const size_t a = rows * kLdC + (size_t)kKC * 16, b = rows * kLdY;
+// LDS bytes of k_near_tiled (the same for every patch size: one slab of at most 64 rows).
+size_t near_tiled_lds(int) {
+  const size_t a = (size_t)kSlab * kKC + (size_t)16 * kKC, b = (size_t)kSlab * kLdY;
   return (a > b ? a : b) * sizeof(double);
 }
 
-bool near_tiled_fits(int q2) { return near_tiled_lds(q2) <= 65536; }
+int near_tiled_slabs(int q2) { return (q2 + kSlab - 1) / kSlab; }
+
+// The tiled kernel takes even patch sizes (16-byte staged slots); odd ones use the per-target
+// kernel.
+bool near_tiled_fits(int q2) { return q2 % 2 == 0; }
 
 namespace {
 void size_prep_buffers(pmx_operator* op, int n_rhs, bool need32) {
@@ -479,7 +513,8 @@ void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t s
   // whole groups of 16 (then 8) right-hand sides by target patch, the rest per target
   bool tiles = n_rhs >= 8;
   for (const ApplyJob& j : jobs)
-    tiles = tiles && j.op->nl.have_tiles && near_tiled_fits(j.op->s->g.q * j.op->s->g.q);
+    tiles = tiles && j.op->nl.have_tiles && near_tiled_fits(j.op->s->g.q * j.op->s->g.q) &&
+            (uintptr_t)j.sigma % 16 == 0 && (uintptr_t)j.op->nl.C.p % 16 == 0;   // 16-byte staged slots
   int r0 = 0;
   while (tiles && n_rhs - r0 >= 8) {
     const int rb = n_rhs - r0 >= 16 ? 16 : 8;
@@ -488,13 +523,12 @@ void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t s
     for (const ApplyJob& j : jobs) {
       pmx_operator* op = j.op;
       const int q2 = op->s->g.q * op->s->g.q;
-      ta.push_back({op->s->g.N, op->s->g.M, q2, r0, op->nl.tile_ptr.p, op->nl.tile_patch.p, op->nl.tile_pair.p,
-                    op->nl.C.p, j.sigma, op->ssum.p, j.y});
-      tb.push_back(op->s->g.M);
+      const int ns = near_tiled_slabs(q2);
+      ta.push_back({op->s->g.N, op->s->g.M, q2, r0, ns, op->nl.tile_ptr.p, op->nl.tile_patch.p,
+                    op->nl.tile_pair.p, op->nl.C.p, j.sigma, op->ssum.p, j.y});
+      tb.push_back(op->s->g.M * ns);
     }
-    int q2max = 0;   // grouped operators share one LDS size
-    for (const ApplyJob& j : jobs) q2max = std::max(q2max, j.op->s->g.q * j.op->s->g.q);
-    const size_t lds = near_tiled_lds(q2max);
+    const size_t lds = near_tiled_lds(0);
     launch_grouped(ta, tb, [&](const Group<TiledArgs>& g, int64_t nb) {
       if (rb == 16) hipLaunchKernelGGL(k_near_tiled<16>, dim3((unsigned)nb), dim3(256), lds, st, g);
       else hipLaunchKernelGGL(k_near_tiled<8>, dim3((unsigned)nb), dim3(256), lds, st, g);
