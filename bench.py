@@ -49,14 +49,14 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 78.6, "fp32_valu_packed": 157.3, "fp32_m
 # traffic is reported as null (the key hashes the file's code without its comments).
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "fa9bcaca4aa5a90a",
-                "kib": [("k_m2l", 14656.7, 373189.0)]},
-    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "fa9bcaca4aa5a90a",
-                    "kib": [("k_m2l_reduce", 166738.9, 7382.4)]},
-    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "fa9bcaca4aa5a90a",
-                "kib": [("k_p2p", 46485.7, 9603.0)]},
-    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "33a1b03a2cf04e3f",
-             "kib": [("k_near_combine", 279134.6, 1262.1)]},
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "73aec918c3f837fa",
+                "kib": [("k_m2l", 12065.9, 372009.3)]},
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "73aec918c3f837fa",
+                    "kib": [("k_m2l_reduce", 166728.6, 7382.5)]},
+    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "73aec918c3f837fa",
+                "kib": [("k_p2p", 46446.4, 9602.3)]},
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "f5adb6ce2f6cff51",
+             "kib": [("k_near_combine", 281884.5, 1266.4)]},
 }
 
 
