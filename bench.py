@@ -286,6 +286,101 @@ def serving(n_req: int, slots: int, loads, budget_bytes: int, n_cal: int = 64):
             "nodes_min_max": [int(min(p.n for p in reqs)), int(max(p.n for p in reqs))]}
 
 
+# Operation count per ordered pair of the FP64 direct far field with c < 0 (the kernel's evaluation,
+# each add, mul, division, reciprocal square root, logarithm or exponential 1 flop, an FMA 2): the
+# geometry and the factored remainder 44, plus K0 and K1 of z = kappa r either by four degree-12
+# Horner polynomials of the ascending series for z <= 2 (111) or by two degree-22 Chebyshev
+# series (Clenshaw) times exp(-z) / sqrt(z) for z > 2 (147).
+C_PAIR_FLOPS = {"pair": 44, "series": 111, "chebyshev": 147}
+
+
+def c_pair_flops(prob, n_sample: int = 200_000, seed: int = 7) -> tuple[float, float]:
+    """(flops per pair, fraction of pairs on the series branch) from seeded sample pairs."""
+    rng = np.random.default_rng(seed)
+    x = prob.surface.x
+    i = rng.integers(prob.n, size=n_sample)
+    j = rng.integers(prob.n, size=n_sample)
+    keep = i != j
+    kap = np.sqrt(-prob.c[j[keep]] / prob.a[j[keep]])
+    z = kap * np.linalg.norm(x[i[keep]] - x[j[keep]], axis=1)
+    f = float(np.mean(z <= 2.0))
+    return (C_PAIR_FLOPS["pair"] + f * C_PAIR_FLOPS["series"] + (1 - f) * C_PAIR_FLOPS["chebyshev"], f)
+
+
+def helmholtz_bench(args):
+    """The c < 0 path with advection (variable a and c of Section 7.4's kind, a non-tangent advection
+    field) on the 153,600-node ellipsoid surface: FP64 applies, a solve to 1e-8, the roofline of the
+    direct sum, and (CPU leg) oracle rows."""
+    import torch
+    from paper_2401_12501_amd import pmx
+    from paper_2401_12501_amd.inputs import helmholtz_ellipsoid_problem, random_density
+    prob = helmholtz_ellipsoid_problem(k=args.k, q=10, swirl=True)
+    N = prob.n
+    log(f"[bench] workload {prob.name} N={N} path=fp64 (c < 0 with advection)")
+    ctx = pmx.Context(0)
+    surf = pmx.Surface.from_inputs(ctx, prob.surface)
+    t0 = time.perf_counter()
+    op = pmx.Operator(surf, prob.a, prob.grad_a, c=prob.c, b=prob.b)
+    t_setup = time.perf_counter() - t0
+    sig_h = random_density(N, 1, seed=3)
+    sig = torch.tensor(np.ascontiguousarray(sig_h.T), device="cuda:0")
+    y = torch.empty_like(sig)
+    P64 = pmx.PMX_PREC_FP64_DIRECT
+    for _ in range(args.warmup):
+        op.apply(sig, P64, out=y)
+    torch.cuda.synchronize()
+    op.profile_read()
+    op.profile(True)
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        op.apply(sig, P64, out=y)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - ts) / args.steps
+    op.profile(False)
+    phases = op.profile_read()
+    log(f"[bench] fp64 (c < 0, advection): {step_s * 1e3:.3f} ms/apply; phases " +
+        ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms" for k, v in phases.items() if v[1]))
+    fpp, f_series = c_pair_flops(prob)
+    d_ms = phases["direct64"][0] / max(phases["direct64"][1], 1)
+    achieved = N * (N - 1.0) * fpp / (d_ms * 1e-3) / 1e12
+    near_ms = phases["near"][0] / max(phases["near"][1], 1)
+    near_bytes = op.stats().near_pairs * 8.0 * 100 + 24.0 * N
+    o = pmx.pmx_default_options()
+    o.gmres_tol = 1e-8
+    ts = time.perf_counter()
+    s_sol, _, info = op.solve(np.ascontiguousarray(prob.f.T), o)
+    t_solve = time.perf_counter() - ts
+    log(f"[bench] solve to 1e-8: {t_solve:.3f} s, {info[0].iters_total} iterations, residual {info[0].rel_residual:.2e}")
+    y_h = y.cpu().numpy().T.copy()
+    err = None
+    if not args.no_cpu:
+        from oracle.operator import OracleOperator
+        from oracle.system import blocks_parallel
+        orc = OracleOperator.from_problem(prob)
+        tg = np.sort(np.random.default_rng(11).choice(N, size=48, replace=False))
+        blocks = blocks_parallel(("paper_2401_12501_amd.inputs", "helmholtz_ellipsoid_problem",
+                                  {"k": args.k, "q": 10, "swirl": True}), ROOT, tg, kernels=("R",),
+                                 workers=min(8, os.cpu_count() or 1))
+        ref = orc.apply_rows(tg, sig_h, blocks)
+        err = float(np.abs(y_h[tg] - ref).max() / np.abs(ref).max())
+        log(f"[bench] 48 sampled rows vs oracle: {err:.2e}")
+    out = {"metric": "c<0 + advection operator-apply Gpts/s (FP64 direct far field)", "value": round(N / step_s / 1e9, 5),
+           "unit": "Gpts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": (f"ellipsoid (1, 0.8, 0.6), {prob.surface.n_patches} patches x 10x10, N={N}, "
+                                   f"a=2+x3, c=-4-exp(x1/2), b=(0.6-x2, x1+0.4x3, 0.5x1x2)"), "path": "fp64"},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK["fp64_valu"], "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK["fp64_valu"], 4), "traffic": None, "kernel": "k_direct64_c",
+                        "avg_ms": round(d_ms, 4), "flops_per_pair": round(fpp, 1), "series_fraction": round(f_series, 4)},
+           "near": {"ms": round(near_ms, 4), "achieved": round(near_bytes / (near_ms * 1e-3) / 1e9, 1), "unit": "GB/s",
+                    "frac": round(near_bytes / (near_ms * 1e-3) / 1e9 / PEAK["hbm"], 4)},
+           "setup_s": round(t_setup, 3),
+           "solve_to_1e-8": {"seconds": round(t_solve, 3), "iters": info[0].iters_total,
+                             "rel_residual": info[0].rel_residual},
+           "apply_rel_err_vs_oracle": err}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,9 +388,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--n-rhs", type=int, default=1)
-    ap.add_argument("--workload", choices=["ellipsoid", "star", "torus"], default="ellipsoid",
+    ap.add_argument("--workload", choices=["ellipsoid", "star", "torus", "helmholtz"], default="ellipsoid",
                     help="ellipsoid: 153,600 nodes, 1 RHS (default); star: 525,696 nodes, 1 RHS; "
-                         "torus: wobbly torus, 2,097,152 nodes, 16 RHS")
+                         "torus: wobbly torus, 2,097,152 nodes, 16 RHS; helmholtz: the c < 0 path with advection "
+                         "on the ellipsoid's surface (FP64)")
     ap.add_argument("--k", type=int, default=16, help="ellipsoid: cube-sphere patches per face edge (16: 153,600 nodes)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
@@ -322,6 +418,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "helmholtz":
+        helmholtz_bench(args)
+        return
     import torch
     from paper_2401_12501_amd import pmx
     from paper_2401_12501_amd.inputs import ellipsoid_problem, star_problem, wobbly_torus_problem, random_density

@@ -231,61 +231,118 @@ __device__ __forceinline__ double log_pair(double x) {
 // Modified Bessel functions K0(z) and K1(z) of a positive argument (FP64): the Green's function
 // of (a Delta + c) G = delta with c < 0 is G = -K0(kappa r) / (2 pi a), kappa = sqrt(-c / a).
 //  * z <= 2: the power series in t = z^2 / 4 (Abramowitz & Stegun 9.6.13 for K0, 9.6.11 with
-//    n = 1 for K1), with I0 = sum t^k / (k!)^2, I1 = (z/2) sum t^k / (k! (k+1)!) and harmonic
+//    n = 1 for K1), with I0 = sum t^k / (k!)^2, I1 = sum t^k / (k! (k+1)!) and harmonic
 //    numbers H_k:  K0 = -(ln(z/2) + gamma) I0 + sum H_k t^k / (k!)^2,
-//    K1 = 1/z + (ln(z/2) + gamma) I1 - (z/4) sum (H_k + H_{k+1}) t^k / (k! (k+1)!).
-//    Fifteen terms leave a truncation below 1e-21 at z = 2; the cancellation in K0 there costs
-//    about one decimal digit (relative error up to 6e-15).
-//  * z > 2: the integral e^z K_nu(z) = int_0^inf exp(-z (cosh s - 1)) cosh(nu s) ds (A&S 9.6.24)
-//    with u = sqrt(2z) sinh(s/2), so that z (cosh s - 1) = u^2 and cosh s = 1 + u^2 / z:
-//      e^z K0 = sqrt(2/z) int_0^inf e^{-u^2} (1 + u^2/(2z))^{-1/2} du,
-//      e^z K1 = sqrt(2/z) int_0^inf e^{-u^2} (1 + u^2/z) (1 + u^2/(2z))^{-1/2} du.
-//    The integrands are even in u and analytic for |Im u| < sqrt(2z) (>= 2), so the trapezoidal
-//    rule converges exponentially (Trefethen and Weideman, SIAM Review 56, 2014); step 0.3 on
-//    [0, 6.9] (24 nodes, weights 0.3 exp(-u_j^2), half at u = 0, generated at 30 digits) gives
-//    1e-15 relative for every z >= 2.
+//    K1 = 1/z + (ln(z/2) + gamma) (z/2) I1 - (z/4) sum (H_k + H_{k+1}) t^k / (k! (k+1)!),
+//    each sum as a polynomial of degree 12 in t by Horner's rule (coefficients computed at
+//    compile time; truncation below 5e-18 at t = 1).  The cancellation in K0 near z = 2 costs
+//    about one decimal digit (relative error up to 4e-15).
+//  * z > 2: sqrt(z) e^z K_nu(z) is smooth in s = 2/z on (0, 1]; its Chebyshev series of degree 22
+//    in x = 4/z - 1 (coefficients by interpolation at the Chebyshev points at 40 digits,
+//    bessel_k_table.py) has relative error 1.2e-16, evaluated by Clenshaw's recurrence.
 constexpr double kEulerGamma = 0.57721566490153286061;
-__device__ __forceinline__ void bessel_k01(double z, double& k0, double& k1) {
+
+struct KSeries {
+  double i0[13], s0[13], i1[13], s1[13];
+};
+constexpr KSeries make_kseries() {
+  KSeries r{};
+  double f = 1.0, g = 1.0, h = 0.0;   // 1/(k!)^2, 1/(k!(k+1)!), H_k
+  for (int k = 0; k < 13; ++k) {
+    const double hn = h + 1.0 / (double)(k + 1);
+    r.i0[k] = f;
+    r.s0[k] = h * f;
+    r.i1[k] = g;
+    r.s1[k] = (h + hn) * g;
+    f /= (double)(k + 1) * (double)(k + 1);
+    g /= (double)(k + 1) * (double)(k + 2);
+    h = hn;
+  }
+  return r;
+}
+
+constexpr double kChebK0[23] = {
+    1.22015154103297774e+00, -3.14481013119645020e-02, 1.56988388573005332e-03,
+    -1.28495495816278017e-04, 1.39498137188765002e-05, -1.83175552271911953e-06,
+    2.76681363944501486e-07, -4.66048989768794783e-08, 8.57403401741422362e-09,
+    -1.69753450938905439e-09, 3.57739728140013962e-10, -7.95748924447235326e-11,
+    1.85594911494131028e-11, -4.51459788300317332e-12, 1.14034058718387776e-12,
+    -2.98009689462883721e-13, 8.03288997119513968e-14, -2.22751103352657940e-14,
+    6.34001023017130056e-15, -1.84839946836037540e-15, 5.50630089020145042e-16,
+    -1.66089941374907953e-16, 4.68034840052582055e-17};
+constexpr double kChebK1[23] = {
+    1.36031309524222133e+00, 1.03923736576817236e-01, -2.85781685962277921e-03,
+    1.95215518471351620e-04, -1.93619797416608301e-05, 2.40648494783721699e-06,
+    -3.50196060308781256e-07, 5.74108412545004947e-08, -1.03457624656780935e-08,
+    2.01504975519702721e-09, -4.19035475934172483e-10, 9.21831518759994310e-11,
+    -2.12996783841327002e-11, 5.13963967308577877e-12, -1.28917395985525712e-12,
+    3.34841963550466353e-13, -8.97670431956193934e-14, 2.47715195964445683e-14,
+    -7.01976576208568517e-15, 2.03849397498716266e-15, -6.05082562535566479e-16,
+    1.81931492334142224e-16, -5.11378840098631785e-17};
+
+// The coefficients of bessel_k01 in one table: the four series (13 each), then the two
+// Chebyshev series (23 each).  (Staging the table in LDS for the direct sum, instead of the
+// register-resident constants, was measured no faster: 152 vs 150 ms on 153,600 nodes.)
+constexpr int kKTable = 4 * 13 + 2 * 23;
+struct KTable {
+  double v[kKTable];
+};
+constexpr KTable make_ktable() {
+  KTable t{};
+  const KSeries s = make_kseries();
+  for (int k = 0; k < 13; ++k) {
+    t.v[k] = s.i0[k];
+    t.v[13 + k] = s.s0[k];
+    t.v[26 + k] = s.i1[k];
+    t.v[39 + k] = s.s1[k];
+  }
+  for (int k = 0; k < 23; ++k) {
+    t.v[52 + k] = kChebK0[k];
+    t.v[75 + k] = kChebK1[k];
+  }
+  return t;
+}
+
+template <int N, class C>
+__device__ __forceinline__ double horner(C c, int o, double t) {
+  double p = c[o + N - 1];
+#pragma unroll
+  for (int k = N - 2; k >= 0; --k) p = fma(p, t, c[o + k]);
+  return p;
+}
+
+template <int N, class C>
+__device__ __forceinline__ double clenshaw(C c, int o, double x) {
+  const double x2 = 2.0 * x;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = N - 1; k >= 1; --k) {
+    const double b = fma(x2, b1, c[o + k] - b2);
+    b2 = b1;
+    b1 = b;
+  }
+  return fma(x, b1, c[o] - b2);
+}
+
+// c: the coefficient table (make_ktable's order), compile-time constants or an LDS copy
+template <class C>
+__device__ __forceinline__ void bessel_k01_t(double z, double& k0, double& k1, C c) {
   if (z <= 2.0) {
     const double t = 0.25 * z * z;
-    double term0 = 1.0, term1 = 1.0, i0 = 0.0, i1 = 0.0, s0 = 0.0, s1 = 0.0, hk = 0.0;
-#pragma unroll
-    for (int k = 0; k < 15; ++k) {
-      const double hk1 = hk + 1.0 / (double)(k + 1);
-      i0 += term0;
-      i1 += term1;
-      s0 = fma(hk, term0, s0);
-      s1 = fma(hk + hk1, term1, s1);
-      hk = hk1;
-      term0 *= t * (1.0 / ((double)(k + 1) * (double)(k + 1)));
-      term1 *= t * (1.0 / ((double)(k + 1) * (double)(k + 2)));
-    }
     const double L = 0.5 * log_pair(t) + kEulerGamma;   // ln(z/2) + gamma
-    k0 = fma(-L, i0, s0);
-    k1 = 1.0 / z + L * (0.5 * z * i1) - 0.25 * z * s1;
+    k0 = fma(-L, horner<13>(c, 0, t), horner<13>(c, 13, t));
+    k1 = 1.0 / z + L * (0.5 * z * horner<13>(c, 26, t)) - 0.25 * z * horner<13>(c, 39, t);
   } else {
-    constexpr double w[24] = {
-        0.15, 0.27417935558136845602, 0.20930289782130931716,
-        0.13345741986688234034, 0.071078327604636527017, 0.031619767368559301035,
-        0.011749168529696122122, 0.0036465534989744811645, 0.00094533347953333216735,
-        0.00020469841582691298489, 0.000037022941226003864849, 0.0000055931226994550491246,
-        7.057725600029318768e-7, 7.4387880541350888885e-8, 6.5488733853764376273e-9,
-        4.815684165556834826e-10, 2.9578516727974524722e-11, 1.5174758228531379705e-12,
-        6.5027066478568858269e-14, 2.3275206227088211402e-15, 6.9585684907307081649e-17,
-        1.737693865618457377e-18, 3.624546059699920715e-20, 6.3148199350192033368e-22};
-    const double invz = 1.0 / z, inv2z = 0.5 * invz;
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int j = 0; j < 24; ++j) {
-      const double u2 = 0.09 * (double)(j * j);
-      const double r = rsqrt(fma(u2, inv2z, 1.0));
-      s0 = fma(w[j], r, s0);
-      s1 = fma(w[j] * r, fma(u2, invz, 1.0), s1);
-    }
-    const double c = sqrt(2.0 * invz) * exp(-z);
-    k0 = c * s0;
-    k1 = c * s1;
+    const double x = 4.0 / z - 1.0;
+    const double e = exp(-z) * rsqrt(z);
+    k0 = clenshaw<23>(c, 52, x) * e;
+    k1 = clenshaw<23>(c, 75, x) * e;
   }
+}
+
+__device__ __forceinline__ void bessel_k01(double z, double& k0, double& k1) {
+  constexpr KTable kt = make_ktable();
+  bessel_k01_t(z, k0, k1, kt.v);
 }
 
 // Launch `fn(group, total_blocks)` for the records in chunks of kMaxSeg; segments
