@@ -33,6 +33,8 @@
 #include <cmath>
 #include <unordered_map>
 
+#include <hipcub/hipcub.hpp>
+
 #include "pmx_internal.hpp"
 
 namespace pmx {
@@ -1036,7 +1038,9 @@ __global__ void k_gather_pts(int64_t N, const int32_t* __restrict__ perm, const 
 // ----------------------------------------------------------------------------- host: tree build
 namespace {
 
-inline uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
+constexpr int kBits = 21;   // Morton key bits per coordinate
+
+__host__ __device__ inline uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
   v &= 0x1fffff;
   v = (v | v << 32) & 0x1f00000000ffffULL;
   v = (v | v << 16) & 0x1f0000ff0000ffULL;
@@ -1045,7 +1049,9 @@ inline uint64_t spread3(uint64_t v) {   // 21 bits -> every third bit
   v = (v | v << 2) & 0x1249249249249249ULL;
   return v;
 }
-inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) { return spread3(x) | spread3(y) << 1 | spread3(z) << 2; }
+__host__ __device__ inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) {
+  return spread3(x) | spread3(y) << 1 | spread3(z) << 2;
+}
 inline uint64_t compact3(uint64_t v) {
   v &= 0x1249249249249249ULL;
   v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ULL;
@@ -1055,7 +1061,24 @@ inline uint64_t compact3(uint64_t v) {
   v = (v ^ (v >> 32)) & 0x1fffff;
   return v;
 }
-constexpr int kBits = 21;
+
+// Morton key of every node's cell at the finest of kBits levels (the host's arithmetic: the same
+// IEEE operations on the same doubles), with the node index for the sort.
+__global__ void k_morton(int64_t N, const double* __restrict__ X, double lo0, double lo1, double lo2, double w,
+                         double cells, uint64_t* __restrict__ key, int32_t* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double lo[3] = {lo0, lo1, lo2};
+  uint64_t ic[3];
+  for (int c = 0; c < 3; ++c) {
+    const double sc = (X[c * N + i] - lo[c]) / w * cells;
+    int64_t v = (int64_t)floor(sc);
+    v = v < 0 ? 0 : (v > ((int64_t)1 << kBits) - 1 ? ((int64_t)1 << kBits) - 1 : v);
+    ic[c] = (uint64_t)v;
+  }
+  key[i] = morton(ic[0], ic[1], ic[2]);
+  idx[i] = (int32_t)i;
+}
 
 double cheb_w_host(int p, double tk, double x) {
   double s = 0.0, a0 = 1.0, a1 = tk, b0 = 1.0, b1 = x;
@@ -1089,18 +1112,33 @@ void fmm_build(pmx_operator* op, hipStream_t st) {
     }
     F->h0 = 0.5 * std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]}) * (1.0 + 1e-6) + 1e-12;
     const double cells = (double)(1u << kBits);
+    // Morton keys and their sort on the GPU (a stable radix sort of (key, node) pairs, so equal
+    // keys keep node order, as a sort of the pairs would), then the sorted pairs to the host
     std::vector<std::pair<uint64_t, int32_t>> key(N);
-    for (int64_t i = 0; i < N; ++i) {
-      uint64_t ic[3];
-      for (int c = 0; c < 3; ++c) {
-        double s = (X[c * N + i] - (F->c0[c] - F->h0)) / (2.0 * F->h0) * cells;
-        int64_t v = (int64_t)std::floor(s);
-        v = std::min<int64_t>(std::max<int64_t>(v, 0), (1 << kBits) - 1);
-        ic[c] = (uint64_t)v;
-      }
-      key[i] = {morton(ic[0], ic[1], ic[2]), (int32_t)i};
+    {
+      DBuf<uint64_t> k_in, k_out;
+      DBuf<int32_t> i_in, i_out;
+      k_in.alloc(ctx, N);
+      k_out.alloc(ctx, N);
+      i_in.alloc(ctx, N);
+      i_out.alloc(ctx, N);
+      hipLaunchKernelGGL(k_morton, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, op->s->g.x.p,
+                         F->c0[0] - F->h0, F->c0[1] - F->h0, F->c0[2] - F->h0, 2.0 * F->h0, cells, k_in.p, i_in.p);
+      PMX_HIP(hipGetLastError());
+      size_t tmp_bytes = 0;
+      PMX_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, k_in.p, k_out.p, i_in.p, i_out.p, (int)N, 0,
+                                                 3 * kBits, st));
+      DBuf<unsigned char> tmp;
+      tmp.alloc(ctx, std::max<size_t>(tmp_bytes, 1));
+      PMX_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, k_in.p, k_out.p, i_in.p, i_out.p, (int)N, 0,
+                                                 3 * kBits, st));
+      std::vector<uint64_t> hk(N);
+      std::vector<int32_t> hi(N);
+      PMX_HIP(hipMemcpyAsync(hk.data(), k_out.p, N * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+      PMX_HIP(hipMemcpyAsync(hi.data(), i_out.p, N * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      PMX_HIP(hipStreamSynchronize(st));
+      for (int64_t i = 0; i < N; ++i) key[i] = {hk[i], hi[i]};
     }
-    std::sort(key.begin(), key.end());
     // leaf level: smallest level >= 2 whose mean occupancy is at most fmm_leaf
     int L = 2;
     for (; L < kMaxLevel; ++L) {
