@@ -49,11 +49,11 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 78.6, "fp32_valu_packed": 157.3, "fp32_m
 # traffic is reported as null (the key hashes the file's code without its comments).
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "73aec918c3f837fa",
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "388bb654748a8207",
                 "kib": [("k_m2l", 12065.9, 372009.3)]},
-    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "73aec918c3f837fa",
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "388bb654748a8207",
                     "kib": [("k_m2l_reduce", 166728.6, 7382.5)]},
-    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "73aec918c3f837fa",
+    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "388bb654748a8207",
                 "kib": [("k_p2p", 46446.4, 9602.3)]},
     "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "f5adb6ce2f6cff51",
              "kib": [("k_near_combine", 281884.5, 1266.4)]},
