@@ -7,7 +7,11 @@ G = (i / 4a) H0(sqrt(c/a) r), whose log part, -log(r) / (2 pi a), has the opposi
 the c = 0 function: it solves (a Delta_2 + c) G = -delta.  We read G = -(i / 4a) H0(sqrt(c/a) r),
 which for c < 0 (modified Helmholtz type) is the real function
     G = -K0(kappa r) / (2 pi a),   kappa = sqrt(-c / a)
-(H0(i z) = (2 / (i pi)) K0(z)), and tends to log(r) / (2 pi a) + const as c -> 0.
+(H0(i z) = (2 / (i pi)) K0(z)), and tends to log(r) / (2 pi a) + const as c -> 0.  For c > 0
+(the Helmholtz type of Section 7.3) the same reading gives the complex function
+    G = -(i / 4a) H0(k r),   k = sqrt(c / a)   (H0 = H0^(1), the Hankel function of the first kind),
+whose real part Y0(k r) / (4a) carries the log singularity and whose imaginary part
+-J0(k r) / (4a) is smooth; R, the blocks, the system and u = K[sigma] are then complex.
 eq:explicit_remainder gives the remainder for x != x':
 
   R = grad_G a(x) . r_hat G'  -  a(x) G'' (n.r)^2 / r^2  +  a(x) G' (n.r)^2 / r^3
@@ -15,8 +19,8 @@ eq:explicit_remainder gives the remainder for x != x':
 
 with r = x - x', G' = dG/dr and G'' = d^2G/dr^2 (the definition line prints
 G'' = d^2/dr^2 G', which we read as the second derivative of G).  Target
-quantities n, H, a, c, grad_G a are at x.  The modified Bessel functions K0, K1 come
-from the library (scipy.special).
+quantities n, H, a, c, grad_G a are at x.  The modified Bessel functions K0, K1 and the Hankel
+functions H0, H1 come from the library (scipy.special).
 
 Advection (eq:adv_remainder): with a first-order term b . grad_G u in the equation the same
 parametrix serves and the remainder gains b(x) . grad_G K(x, x').  K depends on x through
@@ -52,13 +56,30 @@ def green_neg_c(r, a, c):
     return G, G1, G2
 
 
+def green_pos_c(r, a, c):
+    """G(r; a, c) = -(i / 4a) H0(k r), k = sqrt(c/a), c > 0, and its first two r-derivatives:
+    G' = (i k / 4a) H1(k r) (H0' = -H1) and G'' = (i k^2 / 4a) (H0(k r) - H1(k r) / (k r))
+    (H1'(z) = H0(z) - H1(z) / z)."""
+    k = np.sqrt(c / a)
+    z = k * r
+    h0, h1 = sp.hankel1(0, z), sp.hankel1(1, z)
+    G = -1j * h0 / (4 * a)
+    G1 = 1j * k * h1 / (4 * a)
+    G2 = 1j * k ** 2 * (h0 - h1 / z) / (4 * a)
+    return G, G1, G2
+
+
 def green(r, a, c=None):
-    """G, G', G'' of the planar Green's function: c = None (c = 0) or c < 0 (every entry)."""
+    """G, G', G'' of the planar Green's function: c = None (c = 0), c < 0 at every entry (real) or
+    c > 0 at every entry (complex)."""
     if c is None:
         return green_c0(r, a)
-    if np.any(np.asarray(c) >= 0):
-        raise ValueError("the oracle's c != 0 kernels need c < 0")
-    return green_neg_c(r, a, c)
+    c = np.asarray(c)
+    if np.all(c < 0):
+        return green_neg_c(r, a, c)
+    if np.all(c > 0):
+        return green_pos_c(r, a, c)
+    raise ValueError("the oracle's c != 0 kernels need c < 0 everywhere or c > 0 everywhere")
 
 
 def remainder(x, n, H, a_t, gs_t, y, a_s, c_t=None, c_s=None, b_t=None):

@@ -19,14 +19,17 @@ unscaled.  The representation u = K[sigma] (eq:representation) uses the same
 rules with the parametrix, then the weighted mean is removed so that u is the
 mean-zero solution.
 
-With c != 0 (here c < 0 at every node, the modified Helmholtz type) the problem has no
-null space: the system is sigma + R[sigma] = f (Theorem thm:second_kind), f is taken as
+With c != 0 (c < 0 at every node, the modified Helmholtz type, or c > 0 at every node, the
+Helmholtz type with its complex kernel) the problem has no null space: the system is sigma + R[sigma] = f (Theorem thm:second_kind), f is taken as
 given and u = K[sigma] is not shifted.  R and K then carry the c-dependent Green's
 function (``kernels``), c is interpolated on a patch like a, and the self rule integrates R
 on dyadically graded radial panels, since R then has r^m log r parts.
 
+With c > 0 the blocks, the matrix, sigma and u are complex (numpy complex128); real data f
+gives a complex sigma whose u = K[sigma] is real up to the discretization error.
+
 An advection field b (eq:surf_PDE's first-order term, Section 4's theorem
-thm:advectionparametrix) is taken with c < 0 only: the remainder becomes R_b of
+thm:advectionparametrix) is taken with c != 0 only: the remainder becomes R_b of
 eq:adv_remainder, the system sigma + R_b[sigma] = f (eq:IE_adv) and u = K[sigma] as before.
 b is given as ambient vectors at the nodes and projected onto each node's tangent plane.
 With c = 0 constants still solve the homogeneous problem but the data's solvability
@@ -64,13 +67,15 @@ class OracleOperator:
         self._P_xv = patch_nodes(xv, q)
         self._P_a = patch_nodes(self.a[:, None], q)
         self.c = None if c is None else np.asarray(c, dtype=np.float64)
-        if self.c is not None and np.any(self.c >= 0):
-            raise ValueError("c must be negative at every node (or None for c = 0)")
+        if self.c is not None and not (np.all(self.c < 0) or np.all(self.c > 0)):
+            raise ValueError("c must be negative at every node or positive at every node (or None for c = 0)")
+        self.complex = self.c is not None and bool(self.c[0] > 0)
+        self.dtype = np.complex128 if self.complex else np.float64
         self._P_c = None if self.c is None else patch_nodes(self.c[:, None], q)
         self.b = None
         if b is not None:
             if self.c is None:
-                raise ValueError("an advection field b needs c < 0")
+                raise ValueError("an advection field b needs c != 0")
             b = np.asarray(b, dtype=np.float64).reshape(self.N, 3)
             self.b = b - np.sum(b * self.n, axis=1)[:, None] * self.n
         self._self_cache = {}
@@ -175,7 +180,7 @@ class OracleOperator:
     def far_rows(self, targets, sigma: np.ndarray, kernel: str = "R") -> np.ndarray:
         """sum_{j != i} w_j F(x_i, x_j) sigma_j for the given targets; sigma (N, n_rhs)."""
         sigma = sigma.reshape(self.N, -1)
-        out = np.zeros((len(targets), sigma.shape[1]))
+        out = np.zeros((len(targets), sigma.shape[1]), dtype=np.result_type(self.dtype, sigma.dtype))
         alls = np.arange(self.N)
         for t, i in enumerate(targets):
             js = alls[alls != i]
@@ -203,7 +208,7 @@ class OracleOperator:
         N, q2 = self.N, self.q * self.q
         if blocks is None:
             blocks = self.blocks(np.arange(N))
-        A = np.zeros((N, N))
+        A = np.zeros((N, N), dtype=self.dtype)
         for i in range(N):
             js = np.arange(N)
             js = js[js != i]

@@ -116,14 +116,15 @@ def wobbly_torus_problem(n_theta: int = 256, n_phi: int = 128, q: int = 8, n_rhs
 
 
 def helmholtz_sphere_problem(k: int = 2, q: int = 8, c0: float | None = None, omega: float | None = None,
-                             swirl: bool = False) -> Problem:
+                             swirl: bool = False, positive: bool = False) -> Problem:
     """Unit sphere for div_G(a grad_G u) + b . grad_G u + c u = f with c < 0 (the modified Helmholtz
-    type); b = 0 unless ``omega`` (the rotation omega e3 x x) or ``swirl`` (fields.b_swirl) is given.
+    type) or, with ``positive``, c > 0 (the Helmholtz type); b = 0 unless ``omega`` (the rotation
+    omega e3 x x) or ``swirl`` (fields.b_swirl) is given.
 
-    c0 given: a = 1 and c = c0 (constant; f = 0, the caller chooses f, e.g. spherical harmonics).
-    c0 None: a = 2 + x3 and c = -4 - exp(x1 / 2), with the manufactured solution u = (x^2 - y^2) z
-    (a degree-3 harmonic, Delta_G u = -12 u on the unit sphere):
-    f = grad_G a . grad_G u - 12 a u + b . grad_G u + c u.
+    c0 given: a = 1 and c = c0 (constant, either sign; f = 0, the caller chooses f, e.g. spherical
+    harmonics).  c0 None: a = 2 + x3 and c = -4 - exp(x1 / 2) (or c = 2 (1 + 0.2 x2) with
+    ``positive``), with the manufactured solution u = (x^2 - y^2) z (a degree-3 harmonic,
+    Delta_G u = -12 u on the unit sphere): f = grad_G a . grad_G u - 12 a u + b . grad_G u + c u.
     """
     s = cube_sphere(k, q, name="sphere")
     b = F.b_rotation_z(s.x, omega) if omega is not None else (F.b_swirl(s.x) if swirl else None)
@@ -134,23 +135,24 @@ def helmholtz_sphere_problem(k: int = 2, q: int = 8, c0: float | None = None, om
         return Problem(s, a, ga, np.zeros((s.n, 1)), name=f"helmholtz_sphere_k{k}_q{q}_c{c0}{tag}", c=c, b=b)
     a_fn = F.a_linear_z
     a, ga = F.eval_field(a_fn, s.x)
-    c, _ = F.eval_field(F.c_exp_x, s.x)
+    c, _ = F.eval_field(F.c_pos_y if positive else F.c_exp_x, s.x)
     f, u = _sphere_manufactured_rhs(s.x, a_fn, b)
+    tag += "_pos" if positive else ""
     return Problem(s, a, ga, (f + c * u)[:, None], name=f"helmholtz_sphere_k{k}_q{q}_var{tag}", c=c, b=b,
                    meta={"u_exact": u})
 
 
 def helmholtz_ellipsoid_problem(k: int = 4, q: int = 8, axes=(1.0, 0.8, 0.6), seed: int = 1, n_rhs: int = 1,
-                                swirl: bool = False):
-    """Ellipsoid with the variable coefficients a = 2 + x3 and c = -4 - exp(x1 / 2) (c < 0) and
-    right-hand sides of 20 solid harmonics (seeded); with ``swirl`` the advection field
-    fields.b_swirl as well."""
+                                swirl: bool = False, positive: bool = False):
+    """Ellipsoid with the variable coefficients a = 2 + x3 and c = -4 - exp(x1 / 2) (c < 0; with
+    ``positive`` c = 2 (1 + 0.2 x2) > 0) and right-hand sides of 20 solid harmonics (seeded); with
+    ``swirl`` the advection field fields.b_swirl as well."""
     s = cube_sphere(k, q, axes=axes, name="ellipsoid")
     a, ga = F.eval_field(F.a_linear_z, s.x)
-    c, _ = F.eval_field(F.c_exp_x, s.x)
+    c, _ = F.eval_field(F.c_pos_y if positive else F.c_exp_x, s.x)
     f = np.stack([F.solid_harmonic_rhs(s.x, seed + 100 * r) for r in range(n_rhs)], axis=1)
-    return Problem(s, a, ga, f, name=f"helmholtz_ellipsoid_k{k}_q{q}" + ("_swirl" if swirl else ""), c=c,
-                   b=F.b_swirl(s.x) if swirl else None)
+    name = f"helmholtz_ellipsoid_k{k}_q{q}" + ("_swirl" if swirl else "") + ("_pos" if positive else "")
+    return Problem(s, a, ga, f, name=name, c=c, b=F.b_swirl(s.x) if swirl else None)
 
 
 def wavy_torus_problem(n_u: int = 51, n_v: int = 18, q: int = 8, seed: int = 5) -> Problem:

@@ -58,6 +58,14 @@ def c_exp_x(X):
     return -4.0 - torch.exp(0.5 * X[:, 0])
 
 
+def c_pos_y(X):
+    """c(x) = 2 (1 + 0.2 x2) (positive on the unit sphere and the test ellipsoids: the Helmholtz
+    type).  The real part of the form c0 (1 + 0.2 y + 0.2 i sin x) of the variable-coefficient
+    experiment, with c0 = 2 so that c stays between the first two eigenvalue bands of
+    -div_G(a grad_G) for a = 2 + x3 on the unit sphere (about 0 and 4)."""
+    return 2.0 * (1.0 + 0.2 * X[:, 1])
+
+
 def b_rotation_z(x: np.ndarray, omega: float) -> np.ndarray:
     """Advection field omega e3 x x = omega (-x2, x1, 0): the rotation about the x3 axis, tangent
     to every surface of revolution about that axis (so b . grad u = omega du/dphi there)."""
