@@ -148,21 +148,28 @@ PMX_API void pmx_surface_destroy(pmx_surface* s);
 PMX_API pmx_status pmx_operator_create(pmx_surface* s, const double* a, const double* grad_a, const pmx_options* opts,
                                int mem_kind, void* stream, pmx_operator** out);
 /* Operator of the general surface PDE div_G(a grad_G u) + b . grad_G u + c u = f (eq:surf_PDE) for a
- * coefficient c < 0 at every node (N values; the modified Helmholtz-Beltrami type, Section 4.1 and
- * Section 7) and an optional advection field b (3N values, node i's vector at b[3i..3i+2] as for
- * grad_a, ambient components; its tangential part is used; NULL: b = 0).  The parametrix uses G(r; a, c) = -K0(sqrt(-c/a) r) / (2 pi a) with the coefficients
- * at the source (eq:diff_param; the printed Hankel form read with the sign for which
- * (a Delta + c) G = delta) and the remainder of eq:explicit_remainder with its c-term, plus
- * b . grad_G K with b (eq:adv_remainder; the system is then eq:IE_adv).  b is taken with c < 0
- * only: with c = 0 the solvability condition on f is not a zero mean once b != 0.  With c != 0
- * the problem has no null space: the system is sigma + R sigma = f (Theorem thm:second_kind, no
- * rank-one term), f is used as given (info.removed_mean = 0) and u = K sigma is not shifted.
+ * coefficient c of one sign at every node (N values): c < 0, the modified Helmholtz-Beltrami type, or
+ * c > 0, the Helmholtz-Beltrami type (Section 4.1, Section 7.3), and an optional advection field b
+ * (3N values, node i's vector at b[3i..3i+2] as for grad_a, ambient components; its tangential part
+ * is used; NULL: b = 0).  The parametrix is G(r; a, c) = -(i / 4a) H0(sqrt(c/a) r) with the
+ * coefficients at the source (eq:diff_param; the printed Hankel form read with the sign for which
+ * (a Delta + c) G = delta): for c < 0 the real -K0(sqrt(-c/a) r) / (2 pi a), for c > 0 complex
+ * (H0 = J0 + i Y0, the Hankel function of the first kind).  The remainder is eq:explicit_remainder
+ * with its c-term, plus b . grad_G K with b (eq:adv_remainder; the system is then eq:IE_adv).  b is
+ * taken with c != 0 only: with c = 0 the solvability condition on f is not a zero mean once b != 0.
+ * With c != 0 the problem has no null space: the system is sigma + R sigma = f (Theorem
+ * thm:second_kind, no rank-one term), f is used as given (info.removed_mean = 0) and u = K sigma is
+ * not shifted.
+ * With c > 0 the operator is complex (pmx_operator_is_complex): every vector that pmx_apply, pmx_solve
+ * and pmx_represent take or return holds 2N doubles per right-hand side, the real parts of the N node
+ * values followed by their imaginary parts (n_rhs counts complex vectors; right-hand side r starts
+ * at offset 2 r N); GMRES runs on the equivalent real system of size 2N, and info has n_rhs entries.
  * Only the FP64 direct far field is available (PMX_PREC_FP64_DIRECT for pmx_apply, pmx_solve and
  * the allocation-free apply; other precisions give INVALID): the FMM's translation operators need a
- * kernel of x - y alone up to a per-source factor, while here the decay rate sqrt(-c/a) changes from
+ * kernel of x - y alone up to a per-source factor, while here the wavenumber sqrt(|c|/a) changes from
  * source to source.  Arguments as for pmx_operator_create, plus c (N) and b (3N or NULL), both in
  * mem_kind memory and read during the call only.
- * Errors: INVALID (c null, c >= 0 or non-finite at some node, b non-finite, and as
+ * Errors: INVALID (c null, c zero or non-finite at some node, c of both signs, b non-finite, and as
  * pmx_operator_create), TOO_LARGE, OOM, DEVICE. */
 PMX_API pmx_status pmx_operator_create_c(pmx_surface* s, const double* a, const double* grad_a, const double* c,
                                  const double* b, const pmx_options* opts, int mem_kind, void* stream,
@@ -196,8 +203,9 @@ PMX_API pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const d
  * Scratch needed: about 8 (n_rhs (N (1 + c) + N / 256) + N (3 + g + 1)) bytes, with c the
  * direct sum's source chunks (between 1 and 64: 7 for 153,600 nodes, 1 from 1,048,576) and g the
  * largest right-hand-side group (1, 2, 4, 8 or 16); for example up to 4 densities at 153,600 nodes.
- * Errors: INVALID (null or host arrays, n_rhs out of range), TOO_LARGE (scratch above the
- * maximum), DEVICE. */
+ * Complex operators (c > 0) are not taken.
+ * Errors: INVALID (null or host arrays, n_rhs out of range, a complex operator), TOO_LARGE (scratch
+ * above the maximum), DEVICE. */
 #define PMX_NOALLOC_SCRATCH_BYTES (64ull << 20)
 PMX_API pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, double* y, void* stream);
 
@@ -285,6 +293,13 @@ PMX_API pmx_status pmx_operator_export_geometry(pmx_operator* op, double* n, dou
 /* Near lists in CSR form by target (ptr: N + 1, patch: near_pairs, sorted per target) and
  * the FP64 correction blocks C (near_pairs x q*q; D for the parametrix, NULL to skip). */
 PMX_API pmx_status pmx_operator_export_near(pmx_operator* op, int64_t* ptr, int32_t* patch, double* C, double* D);
+/* Complex operators (c > 0): the imaginary parts of the correction blocks C and D, in the layout of
+ * pmx_operator_export_near (which returns the real parts).  Either pointer may be NULL.
+ * Errors: INVALID (null handle, a real operator), DEVICE. */
+PMX_API pmx_status pmx_operator_export_near_imag(pmx_operator* op, double* Ci, double* Di);
+/* *out = 1 for a complex operator (built with c > 0: vectors of 2N doubles), 0 otherwise.
+ * Errors: INVALID (null argument). */
+PMX_API pmx_status pmx_operator_is_complex(pmx_operator* op, int* out);
 
 #ifdef __cplusplus
 }

@@ -123,6 +123,7 @@ void represent_device(pmx_operator* op, int n_rhs, const double* sigma, double* 
   far_direct_log(op, n_rhs, st);
   op->prof.end(t, st);
   near_combine(op, sigma, u, n_rhs, far_direct_chunks(op, true), true, st);
+  if (op->cplx()) near_cross(op, sigma, u, n_rhs, true, st);
   if (!op->co.has_c()) weighted_mean_remove(op, u, n_rhs, st);   // c = 0: the mean-zero solution
 }
 
@@ -381,7 +382,8 @@ pmx_status pmx_operator_get_stats(pmx_operator* op, pmx_operator_stats* out) {
     out->near_pairs = op->nl.nnz;
     uint64_t b = op->co.a.bytes() + op->co.gs.bytes() + op->co.tgt.bytes() + op->co.tg.bytes() + op->co.tf64.bytes() +
                  op->co.tgt32.bytes() + op->co.w_over_a.bytes() + op->nl.ptr.bytes() + op->nl.patch.bytes() +
-                 op->nl.target.bytes() + op->nl.C.bytes() + op->nl.D.bytes() + op->part.bytes() +
+                 op->nl.target.bytes() + op->nl.C.bytes() + op->nl.D.bytes() + op->nl.Ci.bytes() +
+                 op->nl.Di.bytes() + op->part.bytes() +
                  op->qt64.bytes() + op->qt32.bytes();
     if (op->fmm) {
       fmm_stats(op->fmm, out);
@@ -401,7 +403,7 @@ pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const double* s
     PMX_HIP(hipSetDevice(op->s->ctx->c.device));
     hipStream_t st = (hipStream_t)stream;
     Ctx* ctx = &op->s->ctx->c;
-    const size_t n = (size_t)n_rhs * op->s->g.N;
+    const size_t n = (size_t)op->cols(n_rhs) * op->s->g.N;   // c > 0: 2N reals per complex vector
     DBuf<double> bin, bout;
     const double* ds = stage_in(ctx, bin, sigma, n, mem_kind, st);
     double* dy = y;
@@ -409,7 +411,7 @@ pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const double* s
       bout.alloc(ctx, n);
       dy = bout.p;
     }
-    apply_device(op, precision, n_rhs, ds, dy, st);
+    apply_device(op, precision, op->cols(n_rhs), ds, dy, st);
     if (mem_kind == PMX_MEM_HOST) {
       PMX_HIP(hipMemcpyAsync(y, dy, n * sizeof(double), hipMemcpyDeviceToHost, st));
       PMX_HIP(hipStreamSynchronize(st));
@@ -421,6 +423,7 @@ pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, d
   return guarded([&] {
     PMX_REQUIRE(op && sigma && y, PMX_ERR_INVALID, "null argument");
     PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    PMX_REQUIRE(!op->cplx(), PMX_ERR_INVALID, "the allocation-free apply takes real operators only (c <= 0)");
     const int dev = op->s->ctx->c.device;
     PMX_HIP(hipSetDevice(dev));
     const int64_t N = op->s->g.N;
@@ -468,7 +471,7 @@ pmx_status pmx_solve(pmx_operator* op, const pmx_options* opts, int n_rhs, const
     PMX_REQUIRE(!op->co.has_c() || o.precision == PMX_PREC_FP64_DIRECT, PMX_ERR_INVALID,
                 "with c != 0 only the FP64 path (PMX_PREC_FP64_DIRECT) is available");
     Ctx* ctx = &op->s->ctx->c;
-    const size_t n = (size_t)n_rhs * op->s->g.N;
+    const size_t n = (size_t)op->cols(n_rhs) * op->s->g.N;   // c > 0: 2N reals per complex vector
     const double t0 = now_seconds();
     DBuf<double> bf, bs, bu;
     const double* df = stage_in(ctx, bf, f, n, mem_kind, st);
@@ -485,7 +488,7 @@ pmx_status pmx_solve(pmx_operator* op, const pmx_options* opts, int n_rhs, const
     }
     std::vector<double> removed;
     SolveResult r = solve_device(op, o, n_rhs, df, dsig, sigma_in_is_guess != 0, st, removed);
-    if (u) represent_device(op, n_rhs, dsig, du, st);
+    if (u) represent_device(op, op->cols(n_rhs), dsig, du, st);
     if (mem_kind == PMX_MEM_HOST) {
       PMX_HIP(hipMemcpyAsync(sigma, dsig, n * sizeof(double), hipMemcpyDeviceToHost, st));
       if (u) PMX_HIP(hipMemcpyAsync(u, du, n * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -517,7 +520,7 @@ pmx_status pmx_represent(pmx_operator* op, int n_rhs, const double* sigma, doubl
     PMX_HIP(hipSetDevice(op->s->ctx->c.device));
     hipStream_t st = (hipStream_t)stream;
     Ctx* ctx = &op->s->ctx->c;
-    const size_t n = (size_t)n_rhs * op->s->g.N;
+    const size_t n = (size_t)op->cols(n_rhs) * op->s->g.N;   // c > 0: 2N reals per complex vector
     DBuf<double> bin, bout;
     const double* ds = stage_in(ctx, bin, sigma, n, mem_kind, st);
     double* du = u;
@@ -525,7 +528,7 @@ pmx_status pmx_represent(pmx_operator* op, int n_rhs, const double* sigma, doubl
       bout.alloc(ctx, n);
       du = bout.p;
     }
-    represent_device(op, n_rhs, ds, du, st);
+    represent_device(op, op->cols(n_rhs), ds, du, st);
     if (mem_kind == PMX_MEM_HOST) PMX_HIP(hipMemcpyAsync(u, du, n * sizeof(double), hipMemcpyDeviceToHost, st));
     PMX_HIP(hipStreamSynchronize(st));
   });
@@ -562,6 +565,27 @@ pmx_status pmx_operator_export_near(pmx_operator* op, int64_t* ptr, int32_t* pat
       if (!op->nl.have_D) build_near_weights(&op->s->ctx->c, op->s->g, op->co, op->nl, op->opts, true, nullptr);
       PMX_HIP(hipMemcpy(D, op->nl.D.p, (size_t)nnz * q2 * sizeof(double), hipMemcpyDeviceToHost));
     }
+  });
+}
+
+pmx_status pmx_operator_export_near_imag(pmx_operator* op, double* Ci, double* Di) {
+  return guarded([&] {
+    PMX_REQUIRE(op, PMX_ERR_INVALID, "null handle");
+    PMX_REQUIRE(op->cplx(), PMX_ERR_INVALID, "the operator is real (c <= 0): its blocks have no imaginary part");
+    PMX_HIP(hipSetDevice(op->s->ctx->c.device));
+    const size_t n = (size_t)op->nl.nnz * op->s->g.q * op->s->g.q;
+    if (Ci) PMX_HIP(hipMemcpy(Ci, op->nl.Ci.p, n * sizeof(double), hipMemcpyDeviceToHost));
+    if (Di) {
+      if (!op->nl.have_D) build_near_weights(&op->s->ctx->c, op->s->g, op->co, op->nl, op->opts, true, nullptr);
+      PMX_HIP(hipMemcpy(Di, op->nl.Di.p, n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+  });
+}
+
+pmx_status pmx_operator_is_complex(pmx_operator* op, int* out) {
+  return guarded([&] {
+    PMX_REQUIRE(op && out, PMX_ERR_INVALID, "null argument");
+    *out = op->cplx() ? 1 : 0;
   });
 }
 

@@ -287,6 +287,88 @@ __global__ void __launch_bounds__(kBlock) k_direct64_c(DirectCArgs A) {
   }
 }
 
+// c > 0 (the Helmholtz type): G = -(i / 4a') H0(k r), k = sqrt(c'/a'), is complex, and so are
+// sigma and the sums.  A complex density is two real columns (real parts, then imaginary parts);
+// packed source rows are (x, y, z, k, re qt_1, im qt_1, .., re qt_NP, im qt_NP).  With z = k r and
+// J0, J1, Y0, Y1 at z, a' times the remainder is (i pi / 2) {k H1 bra - m H0} with bra as for c < 0
+// and m = at2 k^2 ((n.r)^2/r^2 - 1) + ct2:
+//   e = (pi/2) [(m Y0 - k Y1 bra) + i (k J1 bra - m J0)];
+// a' times the parametrix is (Y0 - i J0) / 4.  Each pair adds e times the complex qt_j.
+template <int NP>
+constexpr int row_len_cz() { return 4 + 2 * NP; }
+
+template <int NP>
+__global__ void __launch_bounds__(kBlock) k_pack_sources_cz(PackCArgs A) {
+  constexpr int RL = row_len_cz<NP>();
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= A.N) return;
+  const int64_t N = A.N;
+  double v[RL];
+  v[0] = A.X[j];
+  v[1] = A.X[N + j];
+  v[2] = A.X[2 * N + j];
+  v[3] = sqrt(A.c[j] / A.a[j]);
+#pragma unroll
+  for (int r = 0; r < 2 * NP; ++r) v[4 + r] = A.q[r * A.ldq + j];   // columns re_1, im_1, re_2, ..
+#pragma unroll
+  for (int k = 0; k < RL; ++k) A.rows[j * RL + k] = v[k];
+}
+
+template <int NP>
+__global__ void __launch_bounds__(kBlock) k_direct64_cz(DirectCArgs A) {
+  constexpr int RL = row_len_cz<NP>();
+  const int64_t N = A.N;
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = i0 < N ? i0 : N - 1;
+  const int64_t j0 = (int64_t)blockIdx.y * A.chunk;
+  const int64_t j1 = j0 + A.chunk < N ? j0 + A.chunk : N;
+  const double xi = A.tgt[i], yi = A.tgt[N + i], zi = A.tgt[2 * N + i];
+  const double nx = A.tgt[3 * N + i], ny = A.tgt[4 * N + i], nz = A.tgt[5 * N + i];
+  const double at2 = 0.5 * A.tgt[6 * N + i], B = A.tgt[7 * N + i];
+  const double gx = A.tg[i], gy = A.tg[N + i], gz = A.tg[2 * N + i];
+  const double ct2 = A.c[i] * 0.15915494309189533577;
+  const sdp S = (sdp)A.rows;
+  double ar[NP], ai[NP];
+#pragma unroll
+  for (int r = 0; r < NP; ++r) ar[r] = ai[r] = 0.0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const sdp row = S + j * RL;
+    const double dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
+    const double rr = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
+    const double ir = rsqrt(rr), rn = rr * ir;
+    const double k = row[3];
+    double bj0, bj1, by0, by1;
+    bessel_jy01(fmax(k * rn, 1e-150), bj0, bj1, by0, by1);
+    double er, ei;
+    if (A.kernel == 0) {
+      const double snr = (nx * dx + ny * dy + nz * dz) * ir;
+      const double gr = gx * dx + gy * dy + gz * dz;
+      const double bra = fma(ir, fma(2.0 * at2 * snr, snr, gr), -B * snr);
+      const double m = fma(at2 * k * k, fma(snr, snr, -1.0), ct2);
+      er = 1.5707963267948966192 * fma(m, by0, -k * by1 * bra);
+      ei = 1.5707963267948966192 * fma(k * bj1, bra, -m * bj0);
+    } else {
+      er = 0.25 * by0;
+      ei = -0.25 * bj0;
+    }
+    er = j == i ? 0.0 : er;
+    ei = j == i ? 0.0 : ei;
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+      const double qr = row[4 + 2 * r], qi = row[5 + 2 * r];
+      ar[r] = fma(qr, er, fma(-qi, ei, ar[r]));
+      ai[r] = fma(qr, ei, fma(qi, er, ai[r]));
+    }
+  }
+  if (i0 < N) {
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+      A.part[(int64_t)blockIdx.y * A.ldc + (2 * r) * A.ldp + i0] = ar[r];
+      A.part[(int64_t)blockIdx.y * A.ldc + (2 * r + 1) * A.ldp + i0] = ai[r];
+    }
+  }
+}
+
 namespace {
 // Source chunks so that the grid holds enough workgroups to fill 256 CUs.
 int64_t n_chunks_for(int64_t N) {
@@ -361,10 +443,43 @@ void direct_c_group(pmx_operator* op, const ApplyScratch* sc, int kernel, int n_
   PMX_HIP(hipGetLastError());
 }
 
+// c > 0: complex densities NP at a time (columns c0 .. c0 + 2 NP - 1 of the n_cols real columns).
+template <int NP>
+void direct_cz_group(pmx_operator* op, const ApplyScratch* sc, int kernel, int n_cols, int c0, hipStream_t st) {
+  constexpr int RL = row_len_cz<NP>();
+  const int64_t N = op->s->g.N;
+  const int64_t nc = n_chunks_for(N);
+  if (!sc && op->rows64.n < (size_t)N * RL) op->rows64.alloc(&op->s->ctx->c, (size_t)N * RL);
+  double* rows = sc ? sc->rows : op->rows64.p;
+  const double* qt = sc ? sc->qt64 : op->qt64.p;
+  double* part = sc ? sc->part : op->part.p;
+  const unsigned nbx = (unsigned)((N + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_pack_sources_cz<NP>, dim3(nbx), dim3(kBlock), 0, st,
+                     PackCArgs{N, op->s->g.x.p, op->co.a.p, op->co.c.p, qt + (int64_t)c0 * N, N, rows});
+  PMX_HIP(hipGetLastError());
+  const DirectCArgs da{N, (N + nc - 1) / nc, N, (int64_t)n_cols * N, op->co.tgt.p, op->co.tg.p, op->co.c.p, rows,
+                       part + (int64_t)c0 * N, kernel};
+  hipLaunchKernelGGL(k_direct64_cz<NP>, dim3(nbx, (unsigned)nc), dim3(kBlock), 0, st, da);
+  PMX_HIP(hipGetLastError());
+}
+
+// n_rhs: real columns (for c > 0, twice the number of complex densities).
 void direct_c_all(pmx_operator* op, const ApplyScratch* sc, int kernel, int n_rhs, hipStream_t st) {
   const int64_t N = op->s->g.N;
   const size_t need = (size_t)n_chunks_for(N) * n_rhs * N;
   if (!sc && op->part.n < need) op->part.alloc(&op->s->ctx->c, need);
+  if (op->cplx()) {
+    const int nv = n_rhs / 2;
+    int v0 = 0;
+    while (v0 < nv) {
+      const int left = nv - v0;
+      if (left >= 8) { direct_cz_group<8>(op, sc, kernel, n_rhs, 2 * v0, st); v0 += 8; }
+      else if (left >= 4) { direct_cz_group<4>(op, sc, kernel, n_rhs, 2 * v0, st); v0 += 4; }
+      else if (left >= 2) { direct_cz_group<2>(op, sc, kernel, n_rhs, 2 * v0, st); v0 += 2; }
+      else { direct_cz_group<1>(op, sc, kernel, n_rhs, 2 * v0, st); v0 += 1; }
+    }
+    return;
+  }
   int r0 = 0;
   while (r0 < n_rhs) {
     const int left = n_rhs - r0;

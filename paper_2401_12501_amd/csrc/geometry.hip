@@ -280,11 +280,18 @@ void build_geometry(Ctx* ctx, Geometry& g, const double* x, const double* xu, co
   PMX_REQUIRE(wnx > 0.0, PMX_ERR_ORIENTATION, "surface normals point inward (sum w n.x <= 0)");
 }
 
+// c at the nodes: flag 2 for a zero or non-finite value; the signs present are reported once per
+// wave (8: some c > 0, 16: some c < 0), since c must keep one sign.
 __global__ void k_coeff_c(int64_t N, const double* __restrict__ c_in, double* __restrict__ c, int* __restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const double v = c_in[i];
-  if (!(v < 0.0) || !isfinite(v)) atomicOr(bad, 2);
+  if (!(v != 0.0) || !isfinite(v)) atomicOr(bad, 2);
+  const uint64_t pos = __ballot(v > 0.0), neg = __ballot(v < 0.0);
+  if ((threadIdx.x & 63) == 0) {
+    const int f = (pos ? 8 : 0) | (neg ? 16 : 0);
+    if (f) atomicOr(bad, f);
+  }
   c[i] = v;
 }
 
@@ -341,7 +348,9 @@ void build_coeff(Ctx* ctx, const Geometry& g, Coeff& co, const double* a, const 
   PMX_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
   PMX_HIP(hipStreamSynchronize(st));
   PMX_REQUIRE(!(hbad & 1), PMX_ERR_INVALID, "coefficient a must be positive and finite, grad a finite");
-  PMX_REQUIRE(!(hbad & 2), PMX_ERR_INVALID, "coefficient c must be negative and finite at every node");
+  PMX_REQUIRE(!(hbad & 2), PMX_ERR_INVALID, "coefficient c must be nonzero and finite at every node");
+  PMX_REQUIRE((hbad & 24) != 24, PMX_ERR_INVALID, "coefficient c must have one sign at every node");
+  co.complex_ = c && (hbad & 8);
   PMX_REQUIRE(!(hbad & 4), PMX_ERR_INVALID, "advection field b must be finite");
 }
 

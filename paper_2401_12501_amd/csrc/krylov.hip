@@ -146,7 +146,10 @@ struct GmresOut {
 GmresOut gmres(pmx_operator* op, int precision, int n_rhs, const double* b, double* x, bool x_zero, double tol,
                int m, int max_iter, hipStream_t st) {
   Ctx* ctx = &op->s->ctx->c;
-  const int64_t N = op->s->g.N;
+  // vector length: N, or 2N real values for a complex operator (c > 0), where GMRES runs on the
+  // equivalent real system of twice the size
+  const int64_t N = op->cplx() ? 2 * op->s->g.N : op->s->g.N;
+  const int nc = op->cols(n_rhs);   // real columns of N nodes per apply
   const int64_t ldk = (int64_t)n_rhs * N;
   DBuf<double> V, W;
   V.alloc(ctx, (size_t)(m + 1) * ldk);
@@ -177,7 +180,7 @@ GmresOut gmres(pmx_operator* op, int precision, int n_rhs, const double* b, doub
     if (x_zero && total == 0) {
       PMX_HIP(hipMemcpyAsync(W.p, b, ldk * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
-      apply_device(op, precision, n_rhs, x, W.p, st);
+      apply_device(op, precision, nc, x, W.p, st);
       res.applies++;
       hipLaunchKernelGGL(k_sub, g1, dim3(kBlock), 0, st, ldk, b, W.p, W.p);
       PMX_HIP(hipGetLastError());
@@ -208,7 +211,7 @@ GmresOut gmres(pmx_operator* op, int precision, int n_rhs, const double* b, doub
     std::vector<double> hh1((size_t)n_rhs * (m + 1)), hh2((size_t)n_rhs * (m + 1)), hn(n_rhs);
     for (; j < m && total < max_iter; ++j) {
       if (op->cancel && op->cancel->load()) throw Error(PMX_ERR_CANCELLED, "solve cancelled");
-      apply_device(op, precision, n_rhs, V.p + (int64_t)j * ldk, W.p, st);
+      apply_device(op, precision, nc, V.p + (int64_t)j * ldk, W.p, st);
       res.applies++;
       const int nk = j + 1;
       D.run(V.p, ldk, nk, W.p, h1.p, st);
@@ -286,7 +289,8 @@ GmresOut gmres(pmx_operator* op, int precision, int n_rhs, const double* b, doub
 SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, const double* f_in, double* sigma,
                          bool warm, hipStream_t st, std::vector<double>& removed_mean) {
   Ctx* ctx = &op->s->ctx->c;
-  const int64_t N = op->s->g.N;
+  const int64_t N = op->cplx() ? 2 * op->s->g.N : op->s->g.N;   // vector length (complex: 2N reals)
+  const int nc = op->cols(n_rhs);
   const int64_t ld = (int64_t)n_rhs * N;
   SolveResult out;
   out.iters.assign(n_rhs, 0);
@@ -330,7 +334,7 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
       if (k == 0 && !warm) {
         PMX_HIP(hipMemcpyAsync(r.p, f.p, ld * sizeof(double), hipMemcpyDeviceToDevice, st));
       } else {
-        apply_device(op, PMX_PREC_FP64_DIRECT, n_rhs, sigma, r.p, st);
+        apply_device(op, PMX_PREC_FP64_DIRECT, nc, sigma, r.p, st);
         out.applies64++;
         hipLaunchKernelGGL(k_sub, g1, dim3(kBlock), 0, st, ld, f.p, r.p, r.p);
         PMX_HIP(hipGetLastError());
@@ -357,7 +361,7 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
     return out;
   }
   // FP64 / FP32 path: report the true residual with the FP64 operator
-  apply_device(op, PMX_PREC_FP64_DIRECT, n_rhs, sigma, r.p, st);
+  apply_device(op, PMX_PREC_FP64_DIRECT, nc, sigma, r.p, st);
   out.applies64++;
   hipLaunchKernelGGL(k_sub, g1, dim3(kBlock), 0, st, ld, f.p, r.p, r.p);
   PMX_HIP(hipGetLastError());

@@ -503,10 +503,62 @@ void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, i
   combine_all({ApplyJob{op, sigma, y}}, {n_part}, parametrix, n_rhs, st);
 }
 
+// c > 0: the imaginary parts Ci of the blocks couple the two real columns of each complex
+// density: after the combine has added the real parts, Re y -= Ci Im sigma and Im y += Ci Re sigma.
+// Half a wavefront per target streams the target's blocks, one complex density per grid row.
+struct CrossArgs {
+  int64_t N;
+  int q2;
+  const int64_t* ptr;
+  const int32_t* patch;
+  const double* Ci;
+  const double* sigma;   // 2 n_vec columns of N
+  double* y;
+};
+
+__global__ void __launch_bounds__(kBlock) k_near_cross(CrossArgs A) {
+  const int64_t N = A.N;
+  const int q2 = A.q2;
+  const int sl = threadIdx.x & (kSub - 1);
+  const int64_t i = (int64_t)blockIdx.x * kTPB + (threadIdx.x / kSub);
+  const bool live = i < N;                  // both halves of a wave stay for the shuffles
+  const int64_t ii = live ? i : N - 1;
+  const double* __restrict__ sr = A.sigma + (int64_t)(2 * blockIdx.y) * N;
+  const double* __restrict__ si = sr + N;
+  double ar = 0.0, ai = 0.0;
+  for (int64_t e = A.ptr[ii]; e < A.ptr[ii + 1]; ++e) {
+    const int64_t base = (int64_t)A.patch[e] * q2;
+    const double* __restrict__ cb = A.Ci + e * q2;
+    for (int t = sl; t < q2; t += kSub) {
+      const double c = cb[t];
+      ar = fma(-c, si[base + t], ar);
+      ai = fma(c, sr[base + t], ai);
+    }
+  }
+  ar = sub_sum(ar);
+  ai = sub_sum(ai);
+  if (live && sl == 0) {
+    A.y[(int64_t)(2 * blockIdx.y) * N + i] += ar;
+    A.y[(int64_t)(2 * blockIdx.y + 1) * N + i] += ai;
+  }
+}
+
+void near_cross(pmx_operator* op, const double* sigma, double* y, int n_cols, bool parametrix, hipStream_t st) {
+  const int64_t N = op->s->g.N;
+  const double* Ci = parametrix ? op->nl.Di.p : op->nl.Ci.p;
+  PMX_REQUIRE(Ci != nullptr, PMX_ERR_INVALID, "imaginary near blocks missing");
+  const CrossArgs a{N, op->s->g.q * op->s->g.q, op->nl.ptr.p, op->nl.patch.p, Ci, sigma, y};
+  hipLaunchKernelGGL(k_near_cross, dim3((unsigned)((N + kTPB - 1) / kTPB), (unsigned)(n_cols / 2)), dim3(kBlock), 0,
+                     st, a);
+  PMX_HIP(hipGetLastError());
+}
+
 void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {
   std::vector<int> nf;
   for (const ApplyJob& j : jobs) nf.push_back(far_direct_chunks(j.op, true));
   combine_all(jobs, nf, false, n_rhs, st);
+  for (const ApplyJob& j : jobs)
+    if (j.op->cplx()) near_cross(j.op, j.sigma, j.y, n_rhs, false, st);
 }
 
 void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st) {

@@ -6,10 +6,11 @@
 // where y~, x~_u, x~_v and a~ are tensor Lagrange interpolants of the patch's node
 // data (the paper interpolates sigma to the quadrature grid, Section 6.1.1 Remark
 // and Section 6.1.2), J~ = |x~_u x x~_v| and F is the remainder R or the
-// parametrix K.  With c != 0 (c < 0, the modified Helmholtz type) c~ is interpolated like a,
-// F carries the c-dependent Green's function G = -K0(kappa r) / (2 pi a) and the c-term of
-// eq:explicit_remainder, and the self rule integrates R on the dyadic radial panels of K,
-// plain on the innermost one (R then has r^m log r parts).
+// parametrix K.  With c != 0 c~ is interpolated like a, F carries the c-dependent Green's function
+// (G = -K0(kappa r) / (2 pi a) for c < 0; for c > 0 the complex G = -(i / 4a) H0(k r), whose real
+// and imaginary parts are integrated by two launches, each an ordinary real kernel) and the
+// c-term of eq:explicit_remainder, and the self rule integrates R on the dyadic radial panels of
+// K, plain on the innermost one (R then has r^m log r parts).
 //
 // Self rule (i in P, Section 6.1.1, eq:radial_int): polar coordinates about the
 // target pre-image t0.  The square splits into four triangles (t0, c_k, c_k+1);
@@ -62,7 +63,7 @@ struct NWArgs {
   const double* X;      // 3N SoA
   const double* XP;     // node-major fields x y z x_u x_v a (and c): 10 (11) per node
   const double* a;      // N
-  const double* c;      // N, c < 0 (kernels 2 and 3); null for c = 0
+  const double* c;      // N, c < 0 (kernels 2 and 3) or c > 0 (kernels 4 and 5); null for c = 0
   const double* w;      // N
   const double* tgt;    // 8N: x y z nx ny nz A B
   const double* tg;     // 3N: grad_G a / (2 pi)
@@ -76,6 +77,8 @@ struct NWArgs {
   double* out;          // nnz * q*q
   int* err;
   int64_t pair0;
+  int cpos;             // c > 0: kernels 4 and 5
+  int imag;             // c > 0: 0 the real part of F, 1 the imaginary part
 };
 
 // Waves per workgroup.  Self rule: the target's panels are spread over several waves.
@@ -147,6 +150,7 @@ __device__ inline void interp_q(sdp XP, const double (&lu)[Q], const double (&lv
 struct Target {
   double x[3], n[3], A, B, g[3];
   double at2, ct2;   // a / (2 pi) and c / (2 pi) at the target (c != 0)
+  int imag;          // c > 0: which part of the complex kernel
 };
 
 // Factored c = 0 remainder: R = (1/a') [ g.r/r^2 + A (n.r)^2/r^4 - B (n.r)/r^2 ].
@@ -194,14 +198,45 @@ __device__ inline double parametrix_c_dev(const Target& T, const double* y, doub
   return -k0 * 0.15915494309189533577 * inv_as;   // -K0(kappa r) / (2 pi a)
 }
 
+// c > 0: with k = sqrt(c'/a') at the source, z = k r and J0, J1, Y0, Y1 at z, eq:explicit_remainder
+// times a' for G = -(i / 4a') H0(k r) is (i pi / 2) {k H1 bra - m H0}, bra as above and
+// m = at2 k^2 ((n.r)^2/r^2 - 1) + ct2, i.e.
+//   real part (pi/2) (m Y0 - k Y1 bra),   imaginary part (pi/2) (k J1 bra - m J0).
+__device__ inline double remainder_cpos_dev(const Target& T, const double* y, double inv_as, double c_s) {
+  const double r0 = T.x[0] - y[0], r1 = T.x[1] - y[1], r2 = T.x[2] - y[2];
+  const double rr = r0 * r0 + r1 * r1 + r2 * r2;
+  const double ir = rsqrt(rr), rn = rr * ir;
+  const double k = sqrt(c_s * inv_as);
+  double j0, j1, y0, y1;
+  bessel_jy01(k * rn, j0, j1, y0, y1);
+  const double nr = T.n[0] * r0 + T.n[1] * r1 + T.n[2] * r2;
+  const double gr = T.g[0] * r0 + T.g[1] * r1 + T.g[2] * r2;
+  const double snr = nr * ir;
+  const double bra = fma(ir, fma(2.0 * T.at2 * snr, snr, gr), -T.B * snr);
+  const double m = fma(T.at2 * k * k, fma(snr, snr, -1.0), T.ct2);
+  const double e = T.imag ? fma(k * j1, bra, -m * j0) : fma(m, y0, -k * y1 * bra);
+  return 1.5707963267948966192 * e * inv_as;
+}
+
+// K = (Y0(k r) - i J0(k r)) / (4 a')
+__device__ inline double parametrix_cpos_dev(const Target& T, const double* y, double inv_as, double c_s) {
+  const double r0 = T.x[0] - y[0], r1 = T.x[1] - y[1], r2 = T.x[2] - y[2];
+  const double rn = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+  double j0, j1, y0, y1;
+  bessel_jy01(sqrt(c_s * inv_as) * rn, j0, j1, y0, y1);
+  return 0.25 * (T.imag ? -j0 : y0) * inv_as;
+}
+
 // Kernel F at a point y with coefficients a' = 1 / inv_as (and c_s): KERNEL 0 R, 1 K (c = 0);
-// 2 R, 3 K (c < 0).
+// 2 R, 3 K (c < 0); 4 R, 5 K (c > 0, the part T.imag selects).
 template <int KERNEL>
 __device__ inline double kernel_dev(const Target& T, const double* y, double inv_as, double c_s) {
   if constexpr (KERNEL == 0) return remainder_dev(T, y, inv_as);
   else if constexpr (KERNEL == 1) return parametrix_dev(T, y, inv_as);
   else if constexpr (KERNEL == 2) return remainder_c_dev(T, y, inv_as, c_s);
-  else return parametrix_c_dev(T, y, inv_as, c_s);
+  else if constexpr (KERNEL == 3) return parametrix_c_dev(T, y, inv_as, c_s);
+  else if constexpr (KERNEL == 4) return remainder_cpos_dev(T, y, inv_as, c_s);
+  else return parametrix_cpos_dev(T, y, inv_as, c_s);
 }
 
 union Cell {                    // self: angular panel [p0, p1] of one edge; near: leaf (depth, iu, iv)
@@ -222,7 +257,7 @@ __device__ inline sdp opaque(sdp p) {
 }  // namespace
 
 // KERNEL: 0 = remainder R (correction blocks C), 1 = parametrix K (blocks D); 2 and 3 the same
-// with c < 0 (eleven node fields: c interpolated like a).
+// with c < 0, 4 and 5 with c > 0 (eleven node fields: c interpolated like a).
 // SELF: one workgroup per target for the pair with its own patch; otherwise one per
 // near-list pair, the self pairs leaving at once (the two launches get their own
 // register allocation: the self rule is VALU work, the near rule MFMA work).
@@ -232,7 +267,7 @@ k_near_weights(NWArgs A) {
   constexpr int kW = waves_for<Q, SELF>();
   constexpr int kT = 64 * kW;
   constexpr int q2 = Q * Q;
-  constexpr bool kC = KERNEL >= 2;        // c < 0
+  constexpr bool kC = KERNEL >= 2;        // c != 0
   constexpr int NF = kC ? 11 : 10;        // node fields (and their stride in XP)
   extern __shared__ double lds[];
   // stage[w][2][Q][kStage]; the subdivision front and flags overlay it before the point loop
@@ -279,6 +314,7 @@ k_near_weights(NWArgs A) {
   T.B = A.tgt[7 * N + i];
   T.at2 = 0.5 * T.A;
   T.ct2 = kC ? A.c[i] * 0.15915494309189533577 : 0.0;
+  T.imag = A.imag;
   const int ngl = A.n_gl;
 
   // ------------------------------------------------------------------ cells
@@ -553,9 +589,9 @@ k_near_weights(NWArgs A) {
         const unsigned pr = ir / ngl, jr = ir - pr * ngl;
         const double t = 0.5 * (gl_t[jr] + 1.0), wt = 0.5 * gl_w[jr];
         // R (c = 0): one panel [0, 1]; K: dyadic panels with rho = t^3 / 8 on the innermost;
-        // R (c < 0): the dyadic panels, plain on the innermost [0, 1/8] too (the t^3 map would put
+        // R (c != 0): the dyadic panels, plain on the innermost [0, 1/8] too (the t^3 map would put
         // points within 1e-10 of the target, where r keeps too few digits of its normal component)
-        if (KERNEL == 0 || pr < 3 || KERNEL == 2) {
+        if (KERNEL == 0 || pr < 3 || KERNEL == 2 || KERNEL == 4) {
           const double lo = (KERNEL == 0 || pr == 3) ? 0.0 : ldexp(1.0, -(int)(pr + 1));
           const double hi = KERNEL == 0 ? 1.0 : ldexp(1.0, -(int)pr);
           s = lo + (hi - lo) * t;
@@ -686,9 +722,12 @@ void launch_q(const NWArgs& A, int64_t n, bool parametrix, bool self, hipStream_
   if (!c) {
     if (parametrix) launch_kq<1, Q>(A, n, self, st, lds);
     else launch_kq<0, Q>(A, n, self, st, lds);
-  } else {
+  } else if (!A.cpos) {
     if (parametrix) launch_kq<3, Q>(A, n, self, st, lds);
     else launch_kq<2, Q>(A, n, self, st, lds);
+  } else {
+    if (parametrix) launch_kq<5, Q>(A, n, self, st, lds);
+    else launch_kq<4, Q>(A, n, self, st, lds);
   }
   PMX_HIP(hipGetLastError());
 }
@@ -723,6 +762,8 @@ void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists&
   PMX_REQUIRE(o.n_gl >= 2 && o.n_gl <= kNglMax, PMX_ERR_INVALID, "n_gl must be in [2, 16]");
   DBuf<double>& out = parametrix ? nl.D : nl.C;
   out.alloc(ctx, (size_t)nl.nnz * q2);
+  DBuf<double>& out_im = parametrix ? nl.Di : nl.Ci;   // c > 0: the imaginary parts
+  if (co.complex_) out_im.alloc(ctx, (size_t)nl.nnz * q2);
   // host tables: Gauss-Legendre rule of the local rules, Lagrange denominators
   std::vector<double> tn(q), tw(q), cinv(q), gt(o.n_gl), gw(o.n_gl);
   gauss_legendre_host(q, tn.data(), tw.data());
@@ -753,21 +794,26 @@ void build_near_weights(Ctx* ctx, const Geometry& g, const Coeff& co, NearLists&
   A.X = g.x.p; A.XP = xp.p; A.a = co.a.p; A.c = co.c.p; A.w = g.w.p;
   A.tgt = co.tgt.p; A.tg = co.tg.p;
   A.tn = tab.p; A.cinv = tab.p + q; A.gl_t = tab.p + 2 * q; A.gl_w = tab.p + 2 * q + o.n_gl;
-  A.ptr = nl.ptr.p; A.pair_patch = nl.patch.p; A.pair_target = nl.target.p; A.out = out.p; A.err = err.p;
+  A.ptr = nl.ptr.p; A.pair_patch = nl.patch.p; A.pair_target = nl.target.p; A.err = err.p;
+  A.cpos = co.complex_ ? 1 : 0;
   int dev = 0;
   PMX_HIP(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   PMX_HIP(hipGetDeviceProperties(&prop, dev));
   const int64_t chunk = 1 << 20;
-  for (int64_t p0 = 0; p0 < g.N; p0 += chunk) {   // self pairs, one per target
-    A.pair0 = p0;
-    const int64_t n = g.N - p0 < chunk ? g.N - p0 : chunk;
-    launch_dispatch(q, A, n, parametrix, true, st, prop.sharedMemPerBlock);
-  }
-  for (int64_t p0 = 0; p0 < nl.nnz; p0 += chunk) {   // the other near pairs
-    A.pair0 = p0;
-    const int64_t n = nl.nnz - p0 < chunk ? nl.nnz - p0 : chunk;
-    launch_dispatch(q, A, n, parametrix, false, st, prop.sharedMemPerBlock);
+  for (int part = 0; part < (co.complex_ ? 2 : 1); ++part) {   // c > 0: real parts, then imaginary
+    A.imag = part;
+    A.out = part ? out_im.p : out.p;
+    for (int64_t p0 = 0; p0 < g.N; p0 += chunk) {   // self pairs, one per target
+      A.pair0 = p0;
+      const int64_t n = g.N - p0 < chunk ? g.N - p0 : chunk;
+      launch_dispatch(q, A, n, parametrix, true, st, prop.sharedMemPerBlock);
+    }
+    for (int64_t p0 = 0; p0 < nl.nnz; p0 += chunk) {   // the other near pairs
+      A.pair0 = p0;
+      const int64_t n = nl.nnz - p0 < chunk ? nl.nnz - p0 : chunk;
+      launch_dispatch(q, A, n, parametrix, false, st, prop.sharedMemPerBlock);
+    }
   }
   int herr = 0;
   PMX_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -149,8 +149,9 @@ struct Coeff {
   DBuf<double> tf64;    // 9N: x y z n'x n'y n'z hx hy hz (h = g - B n)
   DBuf<float> tgt32;    // 9N: the same in FP32
   DBuf<double> w_over_a;  // N
-  DBuf<double> c;       // N: the zero-order coefficient c < 0; empty for c = 0
+  DBuf<double> c;       // N: the zero-order coefficient (c < 0 or c > 0 at every node); empty for c = 0
   bool has_b = false;   // an advection field is folded into g and h
+  bool complex_ = false;  // c > 0: the complex Helmholtz-type kernel
   bool has_c() const { return c.p != nullptr; }
 };
 
@@ -161,6 +162,7 @@ struct NearLists {
   DBuf<int32_t> target;     // nnz (pair -> target node)
   DBuf<double> C;           // nnz * q*q (remainder)
   DBuf<double> D;           // nnz * q*q (parametrix), built on demand
+  DBuf<double> Ci, Di;      // imaginary parts of C and D (c > 0 only)
   bool have_D = false;
   // by target patch (for several right-hand sides): the union of the near patches of the
   // patch's targets, [tile_ptr[T], tile_ptr[T + 1]) into tile_patch, and for union entry u
@@ -398,6 +400,112 @@ __device__ __forceinline__ void bessel_k01_compact(double z, double& k0, double&
   }
 }
 
+// Bessel functions J0, J1, Y0, Y1 of a real argument z > 0 (FP64): the Green's function of
+// (a Delta + c) G = delta with c > 0 is the complex G = -(i / 4a) H0(k r), k = sqrt(c / a), with
+// H0 = J0 + i Y0 and H0' = -H1 = -(J1 + i Y1).
+//  * z <= 8: Chebyshev series of degree 16 in x = z^2 / 32 - 1 of the entire functions J0, J1 / z,
+//    S0 = Y0 - (2/pi) ln(z/2) J0 and S1 = (Y1 - (2/pi) ln(z/2) J1 + 2/(pi z)) / z (the power
+//    series of Y0 and Y1 split into their log and entire parts);
+//  * z > 8: Hankel's form H_nu = sqrt(2/(pi z)) (P_nu + i Q_nu) e^{i chi}, chi = z - nu pi/2 - pi/4,
+//    with P_nu, Q_nu as Chebyshev series of degree 14 in x = 16 / z - 1.
+// Coefficients by interpolation at the Chebyshev points at 40 digits (bessel_jy_table.py), summed
+// by Clenshaw's recurrence: absolute error below 1e-15 for z <= 8, and below 4e-16 times the
+// envelope sqrt(2/(pi z)) beyond (plus the rounding of chi for large z).
+constexpr double kChebJ0[17] = {
+    1.57727971474890122e-01, -8.72344235285222105e-03, 2.65178613203336799e-01,
+    -3.70094993872649769e-01, 1.58067102332097253e-01, -3.48937694114088842e-02,
+    4.81918006946760458e-03, -4.60626166206275038e-04, 3.24603288210050832e-05,
+    -1.76194690776215074e-06, 7.60816359241878206e-08, -2.67925353055767280e-09,
+    7.84869631447946477e-11, -1.94383468673701443e-12, 4.12532059560903340e-14,
+    -7.58850787689090404e-16, 1.22163200807580911e-17};
+constexpr double kChebJ1z[17] = {
+    8.10448463256581153e-02, -1.48975145067652109e-01, 1.60999262357209710e-01,
+    -8.26804917668179096e-02, 2.22136396549660366e-02, -3.64694060076927590e-03,
+    4.05033772835482198e-04, -3.25555486685725868e-05, 1.98587740499151654e-06,
+    -9.52198475675043612e-08, 3.68713375909714814e-09, -1.17802662269588496e-10,
+    3.16015458034800320e-12, -7.22175523965176834e-14, 1.42321440034525375e-15,
+    -2.44419722826302914e-17, 3.69067791636300323e-19};
+constexpr double kChebS0[17] = {
+    3.64546980911604410e-02, -2.78323709407582498e-01, 2.96049999020714827e-01,
+    9.82550840818786353e-02, -1.07551552806277831e-01, 3.17990740844145137e-02,
+    -5.16139710581071508e-03, 5.49852532003901199e-04, -4.19969831494201336e-05,
+    2.42903611079237928e-06, -1.10499697934729567e-07, 4.06651736597911041e-09,
+    -1.23741488982898536e-10, 3.16857255289459007e-12, -6.92695603238257180e-14,
+    1.30863081590583929e-15, -2.15821547475169886e-17};
+constexpr double kChebS1[17] = {
+    3.83007698524237758e-02, -8.18256141273282639e-02, -2.48677076121964005e-02,
+    4.79674527527469835e-02, -1.85258845108980212e-02, 3.68060768782351106e-03,
+    -4.62725406029336874e-04, 4.06940026958086984e-05, -2.66176951252956248e-06,
+    1.35060269132543387e-07, -5.48352411033627623e-09, 1.82450868412290067e-10,
+    -5.07066663659112876e-12, 1.19561625175879380e-13, -2.42316244270063974e-15,
+    4.26812639301533527e-17, -6.59496226022674799e-19};
+constexpr double kChebP0[15] = {
+    9.99595064768672881e-01, -5.38079561396069181e-04, -1.31796771233615704e-04,
+    1.51422497048644466e-06, 1.58468617920632462e-07, -8.56069553945711599e-09,
+    -2.95723433548997341e-10, 6.57355625370310452e-11, -2.23749702832823310e-12,
+    -4.48211403609405547e-13, 6.95482668020278653e-14, -1.51340142546660594e-15,
+    -9.24212105515919074e-16, 1.55618053885131831e-16, -5.36266268289223379e-18};
+constexpr double kChebQ0[15] = {
+    -7.76935569420532119e-03, -7.74803230965447672e-03, 2.53654116543079604e-05,
+    3.94273598399711378e-06, -1.07234982991288198e-07, -7.21389799327753528e-09,
+    7.37646028933544292e-10, 1.50687810891936521e-12, -5.74589537316565120e-12,
+    4.59965741902894660e-13, 2.27032322588495181e-14, -8.87890122888076548e-15,
+    7.44949474122565498e-16, 5.85684924495839078e-17, -2.42267554176777644e-17};
+constexpr double kChebP1[15] = {
+    1.00067753586591346e+00, 9.01007251959081855e-04, 2.21724349185994539e-04,
+    -1.96575946319104395e-06, -2.08895311432702157e-07, 1.02814435089397333e-08,
+    3.75970547893049245e-10, -7.63889135778662110e-11, 2.38734669892881568e-12,
+    5.18254887309946603e-13, -7.69396898176723118e-14, 1.44008460247785360e-15,
+    1.03293157223598494e-15, -1.68247485453780656e-16, 5.23442402189761112e-18};
+constexpr double kChebQ1[15] = {
+    2.33768299862858048e-02, 2.33468012235455748e-02, -3.57601059090138212e-05,
+    -5.60863149492627211e-06, 1.32738940843397802e-07, 9.16975845066427102e-09,
+    -8.68388803707271890e-10, -3.78073005146958109e-12, 6.63145586075118320e-12,
+    -5.05843904179735278e-13, -2.72078161818527664e-14, 9.85380680235480784e-15,
+    -7.93959914335076049e-16, -6.76771891484821019e-17, 2.64010413416378994e-17};
+
+template <int N>
+__device__ __forceinline__ double cheb(const double (&c)[N], double x) {
+  const double x2 = 2.0 * x;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = N - 1; k >= 1; --k) {
+    const double b = fma(x2, b1, c[k] - b2);
+    b2 = b1;
+    b1 = b;
+  }
+  return fma(x, b1, c[0] - b2);
+}
+
+__device__ __forceinline__ void bessel_jy01(double z, double& j0, double& j1, double& y0, double& y1) {
+  constexpr double k2OverPi = 0.63661977236758134308;   // 2 / pi
+  if (z <= 8.0) {
+    const double w = z * z;
+    const double x = fma(w, 1.0 / 32.0, -1.0);
+    const double a0 = cheb(kChebJ0, x), a1 = cheb(kChebJ1z, x);
+    const double s0 = cheb(kChebS0, x), s1 = cheb(kChebS1, x);
+    const double L = 0.5 * k2OverPi * log_pair(0.25 * w);   // (2/pi) ln(z/2)
+    j0 = a0;
+    j1 = z * a1;
+    y0 = fma(L, a0, s0);
+    y1 = fma(L, j1, fma(z, s1, -k2OverPi / z));
+  } else {
+    const double x = 16.0 / z - 1.0;
+    const double p0 = cheb(kChebP0, x), q0 = cheb(kChebQ0, x);
+    const double p1 = cheb(kChebP1, x), q1 = cheb(kChebQ1, x);
+    double sn, cs;
+    sincos(z, &sn, &cs);
+    const double env = sqrt(k2OverPi / z);
+    const double c0 = (cs + sn) * 0.70710678118654752440;   // cos(z - pi/4)
+    const double s0 = (sn - cs) * 0.70710678118654752440;   // sin(z - pi/4)
+    // chi_1 = chi_0 - pi/2: cos chi_1 = sin chi_0, sin chi_1 = -cos chi_0
+    j0 = env * fma(p0, c0, -q0 * s0);
+    y0 = env * fma(p0, s0, q0 * c0);
+    j1 = env * fma(p1, s0, q1 * c0);
+    y1 = env * fma(q1, s0, -p1 * c0);
+  }
+}
+
 // Launch `fn(group, total_blocks)` for the records in chunks of kMaxSeg; segments
 // with no blocks are left out.
 template <class A, class F>
@@ -514,6 +622,10 @@ struct pmx_operator {
   // join before L2P); default priority, created on first use
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // c > 0 makes the operator complex: a complex vector of N values is stored as two real
+  // columns of N (real parts, then imaginary parts), so n complex vectors are 2 n real columns
+  bool cplx() const { return co.complex_; }
+  int cols(int n_vec) const { return co.complex_ ? 2 * n_vec : n_vec; }
 };
 
 namespace pmx {
@@ -562,6 +674,8 @@ void near_combine(pmx_operator* op, const double* sigma, double* y, int n_rhs, i
                   hipStream_t st);
 void source_prep_batch(const std::vector<ApplyJob>& jobs, int n_rhs, bool need32, hipStream_t st);
 void near_combine_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);   // FP64 direct partials
+// c > 0: y += i Ci sigma for the n_cols / 2 complex densities (Di for the parametrix)
+void near_cross(pmx_operator* op, const double* sigma, double* y, int n_cols, bool parametrix, hipStream_t st);
 // y = sigma + C sigma + (sum_j w_j sigma_j): everything but the far field, which the FMM adds later.
 void near_only_batch(const std::vector<ApplyJob>& jobs, int n_rhs, hipStream_t st);
 // Builds the by-target-patch view of the near lists (host, once per operator).

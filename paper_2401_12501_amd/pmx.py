@@ -73,6 +73,8 @@ _SIGS = {
     "pmx_represent": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.c_int, _vp]),
     "pmx_operator_export_geometry": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
     "pmx_operator_export_near": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "pmx_operator_export_near_imag": (C.c_int32, [_vp, _vp, _vp]),
+    "pmx_operator_is_complex": (C.c_int32, [_vp, C.POINTER(C.c_int)]),
     "pmx_server_create": (C.c_int32, [_vp, C.POINTER(pmx_options), C.c_int, C.POINTER(_vp)]),
     "pmx_server_submit": (C.c_int32, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int,
                                       C.POINTER(C.c_uint64)]),
@@ -219,8 +221,10 @@ class Operator:
     """pmx_operator_create and the calls on an operator."""
 
     def __init__(self, surface: Surface, a, grad_a, opts: pmx_options | None = None, c=None, b=None):
-        """pmx_operator_create, or pmx_operator_create_c when c (N values, all negative) is given,
-        with the advection field b ((N, 3) ambient vectors) or without (b None)."""
+        """pmx_operator_create, or pmx_operator_create_c when c (N values of one sign) is given,
+        with the advection field b ((N, 3) ambient vectors) or without (b None).  With c > 0 the
+        operator is complex: apply, solve and represent take and return complex arrays (n_rhs, N),
+        passed to the library as 2N reals per vector (real parts, then imaginary parts)."""
         self.surface = surface
         self.N = surface.N
         self.q = surface.q
@@ -229,13 +233,16 @@ class Operator:
         h = _vp()
         if c is None:
             if b is not None:
-                raise PmxError(PMX_ERR_INVALID, "an advection field b needs c < 0 (pmx_operator_create_c)")
+                raise PmxError(PMX_ERR_INVALID, "an advection field b needs c != 0 (pmx_operator_create_c)")
             _check(lib().pmx_operator_create(surface.h, ptrs[0], ptrs[1], C.byref(self.opts), kind, stream,
                                              C.byref(h)))
         else:
             _check(lib().pmx_operator_create_c(surface.h, ptrs[0], ptrs[1], ptrs[2], ptrs[3], C.byref(self.opts),
                                                kind, stream, C.byref(h)))
         self.h = h
+        flag = C.c_int(0)
+        _check(lib().pmx_operator_is_complex(h, C.byref(flag)))
+        self.complex = bool(flag.value)
 
     def close(self):
         if getattr(self, "h", None):
@@ -255,8 +262,36 @@ class Operator:
             raise ValueError("array size is not a multiple of N")
         return n_rhs
 
+    def _planar(self, a):
+        """A complex operator's layout: complex (n, N) values as real (n, 2, N), real parts first."""
+        if a is None:
+            return None
+        if _is_torch(a):
+            import torch
+            a = a.reshape(-1, self.N)
+            if not a.is_complex():
+                a = a.to(torch.complex128)
+            return torch.stack([a.real, a.imag], dim=1).contiguous()
+        a = np.asarray(a).reshape(-1, self.N).astype(np.complex128)
+        return np.ascontiguousarray(np.stack([a.real, a.imag], axis=1))
+
+    @staticmethod
+    def _unplanar(p):
+        if p is None:
+            return None
+        if _is_torch(p):
+            import torch
+            return torch.complex(p[:, 0].contiguous(), p[:, 1].contiguous())
+        return p[:, 0] + 1j * p[:, 1]
+
     def apply(self, sigma, precision: int = PMX_PREC_FP64_DIRECT, out=None):
-        """y = A sigma; sigma is (n_rhs, N) (host numpy or device tensor)."""
+        """y = A sigma; sigma is (n_rhs, N) (host numpy or device tensor; complex for a complex operator)."""
+        if self.complex:
+            sp = self._planar(sigma)
+            y = np.empty(sp.shape) if not _is_torch(sp) else sp.new_empty(sp.shape)
+            ptrs, kind, stream, keep = _marshal(sp, y)
+            _check(lib().pmx_apply(self.h, precision, sp.shape[0], ptrs[0], ptrs[1], kind, stream))
+            return self._unplanar(y)
         n_rhs = self._rhs(sigma)
         if out is None:
             out = np.empty((n_rhs, self.N)) if not _is_torch(sigma) else sigma.new_empty(sigma.shape)
@@ -278,10 +313,17 @@ class Operator:
         return out
 
     def solve(self, f, opts: pmx_options | None = None, sigma0=None, want_u: bool = False, check: bool = True):
-        """(sigma, u or None, [pmx_info]) for f of shape (n_rhs, N)."""
-        n_rhs = self._rhs(f)
+        """(sigma, u or None, [pmx_info]) for f of shape (n_rhs, N) (complex results for a complex operator)."""
+        if self.complex:
+            fp = self._planar(f)
+            sig, u, infos = self._solve_real(fp, fp.shape[0], opts, self._planar(sigma0), want_u, check)
+            return self._unplanar(sig), self._unplanar(u), infos
+        return self._solve_real(f, self._rhs(f), opts, sigma0, want_u, check)
+
+    def _solve_real(self, f, n_rhs, opts, sigma0, want_u, check):
         torch_in = _is_torch(f)
-        mk = (lambda: f.new_empty(f.shape)) if torch_in else (lambda: np.empty((n_rhs, self.N)))
+        shape = np.shape(f) if np.ndim(f) == 3 else (n_rhs, self.N)   # 3-d: a complex operator's (n, 2, N)
+        mk = (lambda: f.new_empty(f.shape)) if torch_in else (lambda: np.empty(shape))
         sigma = mk() if sigma0 is None else (sigma0.clone() if torch_in else np.array(sigma0, dtype=np.float64))
         u = mk() if want_u else None
         ptrs, kind, stream, keep = _marshal(f, sigma, u)
@@ -295,6 +337,12 @@ class Operator:
         return sigma, u, list(infos)
 
     def represent(self, sigma, out=None):
+        if self.complex:
+            sp = self._planar(sigma)
+            u = np.empty(sp.shape) if not _is_torch(sp) else sp.new_empty(sp.shape)
+            ptrs, kind, stream, keep = _marshal(sp, u)
+            _check(lib().pmx_represent(self.h, sp.shape[0], ptrs[0], ptrs[1], kind, stream))
+            return self._unplanar(u)
         n_rhs = self._rhs(sigma)
         if out is None:
             out = np.empty((n_rhs, self.N)) if not _is_torch(sigma) else sigma.new_empty(sigma.shape)
@@ -329,6 +377,14 @@ class Operator:
         _check(lib().pmx_operator_export_near(self.h, ptr.ctypes.data, patch.ctypes.data, Cb.ctypes.data,
                                                Db.ctypes.data if with_D else None))
         return ptr, patch, Cb, Db
+
+    def export_near_imag(self, with_D: bool = False):
+        """Imaginary parts of the blocks C (and D) of a complex operator, in export_near's layout."""
+        nnz, q2 = self.stats().near_pairs, self.q * self.q
+        Ci = np.empty((nnz, q2))
+        Di = np.empty((nnz, q2)) if with_D else None
+        _check(lib().pmx_operator_export_near_imag(self.h, Ci.ctypes.data, Di.ctypes.data if with_D else None))
+        return Ci, Di
 
 
 class Server:

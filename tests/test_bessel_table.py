@@ -1,4 +1,5 @@
-"""The device routine for K0 and K1 (bessel_k01 in pmx_internal.hpp), replayed on the host.
+"""The device routines for K0 and K1 (bessel_k01) and for J0, J1, Y0, Y1 (bessel_jy01) in
+pmx_internal.hpp, replayed on the host.
 
 The Chebyshev coefficient tables are read from the header and the series coefficients are built the
 way make_kseries builds them; the evaluation follows the routine step by step (Horner's rule in
@@ -88,3 +89,55 @@ def test_tables_match_the_generator():
         assert len(c) == 23
         val_at_infinity = sum(cj * (-1) ** j for j, cj in enumerate(c))   # x = -1: T_j(-1) = (-1)^j
         assert abs(val_at_infinity - math.sqrt(math.pi / 2)) < 1e-15
+
+
+def jy01(z, T):
+    """The device routine bessel_jy01 step by step (natural log in place of the device's log)."""
+    cheb = clenshaw
+    k2pi = 2.0 / math.pi
+    if z <= 8.0:
+        w = z * z
+        x = w / 32.0 - 1.0
+        a0, a1, s0, s1 = (cheb(T[n], x) for n in ("kChebJ0", "kChebJ1z", "kChebS0", "kChebS1"))
+        L = 0.5 * k2pi * math.log(0.25 * w)
+        j1 = z * a1
+        return a0, j1, L * a0 + s0, L * j1 + z * s1 - k2pi / z
+    x = 16.0 / z - 1.0
+    p0, q0, p1, q1 = (cheb(T[n], x) for n in ("kChebP0", "kChebQ0", "kChebP1", "kChebQ1"))
+    sn, cs = math.sin(z), math.cos(z)
+    env = math.sqrt(k2pi / z)
+    c0, s0 = (cs + sn) * math.sqrt(0.5), (sn - cs) * math.sqrt(0.5)
+    return env * (p0 * c0 - q0 * s0), env * (p1 * s0 + q1 * c0), env * (p0 * s0 + q0 * c0), env * (q1 * s0 - p1 * c0)
+
+
+def test_device_jy01_against_mpmath():
+    """J0, J1, Y0, Y1 of the device routine against mpmath at 30 digits from z = 1e-10 to 80: absolute
+    error below 3e-15 for z <= 8 (Y0, Y1 relative near z = 0, where they diverge), and below
+    3e-15 times the envelope sqrt(2 / (pi z)) beyond."""
+    mp.mp.dps = 30
+    T = {n: table(n) for n in ("kChebJ0", "kChebJ1z", "kChebS0", "kChebS1", "kChebP0", "kChebQ0", "kChebP1",
+                                "kChebQ1")}
+    zs = np.concatenate([np.logspace(-10, 0, 200), np.linspace(1.0, 8.0, 700), np.linspace(7.99, 8.01, 41),
+                         np.linspace(8.0, 80.0, 1500)])
+    worst = 0.0
+    for z in zs:
+        z = float(z)
+        got = jy01(z, T)
+        refs = (mp.besselj(0, z), mp.besselj(1, z), mp.bessely(0, z), mp.bessely(1, z))
+        scale = 1.0 if z <= 8.0 else math.sqrt(2.0 / (math.pi * z))
+        for g, ref in zip(got, refs):
+            err = float(abs(g - ref)) / max(scale, float(abs(ref)) if z < 1.0 else scale)
+            worst = max(worst, err)
+    assert worst < 3e-15, worst
+
+
+def test_jy_tables_limits():
+    """P_nu -> 1 and Q_nu -> 0 as z -> infinity (x = -1), and the small-range fits equal their
+    values at z = 0: J0(0) = 1, J1(z)/z -> 1/2."""
+    at_minus_one = lambda c: sum(cj * (-1) ** j for j, cj in enumerate(c))
+    assert abs(at_minus_one(table("kChebP0")) - 1.0) < 1e-15
+    assert abs(at_minus_one(table("kChebP1")) - 1.0) < 1e-15
+    assert abs(at_minus_one(table("kChebQ0"))) < 1e-15
+    assert abs(at_minus_one(table("kChebQ1"))) < 1e-15
+    assert abs(at_minus_one(table("kChebJ0")) - 1.0) < 1e-15
+    assert abs(at_minus_one(table("kChebJ1z")) - 0.5) < 1e-15

@@ -187,7 +187,8 @@ def test_c_error_contract(ctx):
     from paper_2401_12501_amd import pmx
     p = helmholtz_ellipsoid_problem(k=1, q=5)
     surf = pmx.Surface.from_inputs(ctx, p.surface)
-    for bad in (np.abs(p.c), np.where(np.arange(p.n) == 7, 0.0, p.c), np.where(np.arange(p.n) == 3, np.nan, p.c)):
+    for bad in (np.where(np.arange(p.n) == 11, -p.c, p.c), np.where(np.arange(p.n) == 7, 0.0, p.c),
+                np.where(np.arange(p.n) == 3, np.nan, p.c)):
         with pytest.raises(pmx.PmxError) as e:
             pmx.Operator(surf, p.a, p.grad_a, c=bad)
         assert e.value.code == pmx.PMX_ERR_INVALID

@@ -1,0 +1,190 @@
+"""The c > 0 path (div_G(a grad_G u) + b . grad_G u + c u = f, the Helmholtz-Beltrami type of
+Section 7.3, with the complex kernel G = -(i / 4a) H0(k r)) through the C ABI against the FP64
+oracle, element by element (max-abs error over max-abs value, complex).
+
+Cases: an ellipsoid with 6 patches of 7 x 7 nodes (294 nodes, not a multiple of any launch tile)
+and the unit sphere (24 patches, q = 8), both with a = 2 + z and c = 2 (1 + 0.2 y), the ellipsoid
+also with a non-tangent advection field (eq:adv_remainder).  Bars: the real and imaginary parts of
+the correction blocks C and D within 1e-13 of the largest entry (plus 16x the oracle's one-ulp
+sensitivity where the rules sample close to the target); FP64 applies over 1, 2 and 8 complex
+densities at once, solves and the representation within 1e-12; Section 7.3's c = 4 with a = 1 on
+the sphere gives the eigenvalues -l(l+1) + 4 within the discretization error.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2401_12501_amd.inputs import (helmholtz_ellipsoid_problem, helmholtz_sphere_problem, random_density,
+                                         real_sph_harm_cartesian)
+from oracle.operator import OracleOperator
+from oracle.system import blocks_parallel
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def max_rel(a, b):
+    a = np.asarray(a).reshape(np.shape(b)[0], -1)
+    b = np.asarray(b).reshape(np.shape(b)[0], -1)
+    return max(float(np.abs(a[:, r] - b[:, r]).max() / np.abs(b[:, r]).max()) for r in range(b.shape[1]))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2401_12501_amd import pmx
+    return pmx.Context(0)
+
+
+class Case:
+    def __init__(self, factory, kw, ctx):
+        from paper_2401_12501_amd import pmx
+        prob = factory(**kw)
+        self.prob = prob
+        say(f"[case] {prob.name}: N={prob.n}, c in [{prob.c.min():.3f}, {prob.c.max():.3f}]")
+        self.surf = pmx.Surface.from_inputs(ctx, prob.surface)
+        self.op = pmx.Operator(self.surf, prob.a, prob.grad_a, c=prob.c, b=prob.b)
+        assert self.op.complex
+        self.orc = OracleOperator.from_problem(prob)
+        self.blocks = blocks_parallel(("paper_2401_12501_amd.inputs", factory.__name__, kw), ROOT,
+                                      np.arange(prob.n), kernels=("R", "K"), workers=min(8, os.cpu_count() or 1))
+        self.A = self.orc.dense_matrix(self.blocks)
+        say(f"[case] {prob.name}: oracle blocks and matrix ready")
+
+
+@pytest.fixture(scope="module")
+def ragged(ctx):
+    return Case(helmholtz_ellipsoid_problem, {"k": 1, "q": 7, "positive": True}, ctx)
+
+
+@pytest.fixture(scope="module")
+def sphere(ctx):
+    return Case(helmholtz_sphere_problem, {"k": 2, "q": 8, "positive": True}, ctx)
+
+
+@pytest.fixture(scope="module")
+def ragged_b(ctx):
+    return Case(helmholtz_ellipsoid_problem, {"k": 1, "q": 7, "positive": True, "swirl": True}, ctx)
+
+
+CASES = ["ragged", "sphere", "ragged_b"]
+
+
+@pytest.mark.parametrize("which", CASES)
+def test_blocks_cpos(which, request):
+    """Real and imaginary parts of the correction blocks C (remainder) and D (parametrix) against the
+    oracle's complex blocks: 1e-13 of the largest entry, plus 16x the oracle's own change under
+    one-ulp moves of the target for the targets above that (as for c < 0)."""
+    from test_gpu_parity import ulp_sensitivity
+    case = request.getfixturevalue(which)
+    ptr, patch, Cr, Dr = case.op.export_near(with_D=True)
+    Ci, Di = case.op.export_near_imag(with_D=True)
+    G = {"R": Cr + 1j * Ci, "K": Dr + 1j * Di}
+    err = {"R": np.zeros(case.prob.n), "K": np.zeros(case.prob.n)}
+    scale = {"R": 0.0, "K": 0.0}
+    for i in range(case.prob.n):
+        plist, blk = case.blocks[i]
+        assert np.array_equal(patch[ptr[i]:ptr[i + 1]], plist)
+        for k in ("R", "K"):
+            scale[k] = max(scale[k], np.abs(blk[k]).max())
+            err[k][i] = np.abs(G[k][ptr[i]:ptr[i + 1]] - blk[k]).max()
+    imag_part = max(np.abs(case.blocks[i][1]["R"].imag).max() for i in range(case.prob.n))
+    say(f"[blocks c>0] {which}: C {err['R'].max() / scale['R']:.2e}, D {err['K'].max() / scale['K']:.2e} of max "
+        f"(largest imaginary part of C {imag_part:.2e})")
+    assert imag_part > 1e-6 * scale["R"]      # the imaginary parts are really there
+    for k in ("R", "K"):
+        over = np.nonzero(err[k] > 1e-13 * scale[k])[0]
+        for i in over:
+            plist, blk = case.blocks[i]
+            sens = ulp_sensitivity(case.orc, int(i), plist, (k,), {k: blk[k]})[k]
+            assert err[k][i] <= 1e-13 * scale[k] + 16.0 * sens, (k, i, err[k][i], sens)
+        say(f"[blocks c>0] {which} {k}: {len(over)} targets above 1e-13 of max, all within 16x their 1-ulp "
+            f"sensitivity")
+
+
+@pytest.mark.parametrize("which", CASES)
+def test_apply_solve_represent_cpos(which, request):
+    from paper_2401_12501_amd import pmx
+    case = request.getfixturevalue(which)
+    N = case.prob.n
+    # 11 complex densities: the direct sum's groups of 8, 2 and 1
+    sig = random_density(N, 11, seed=91) + 1j * random_density(N, 11, seed=92)
+    y = case.op.apply(np.ascontiguousarray(sig.T), pmx.PMX_PREC_FP64_DIRECT).T
+    e_apply = max_rel(y, case.A @ sig)
+    y1 = case.op.apply(np.ascontiguousarray(sig[:, 3:4].T), pmx.PMX_PREC_FP64_DIRECT).T
+    e_one = max_rel(y1, case.A @ sig[:, 3:4])
+    o = pmx.pmx_default_options()
+    o.gmres_tol = 1e-14
+    s, u, info = case.op.solve(np.ascontiguousarray(case.prob.f.T), o, want_u=True)
+    s_ref = case.orc.solve(case.prob.f, case.A)
+    u_ref = case.orc.represent(s_ref, case.blocks)
+    e_s, e_u = max_rel(s.T, s_ref), max_rel(u.T, u_ref)
+    say(f"[c>0 path] {which}: apply {e_apply:.2e} (one density {e_one:.2e}), sigma {e_s:.2e}, u {e_u:.2e}, "
+        f"iters {info[0].iters_total}, residual {info[0].rel_residual:.1e}")
+    assert np.abs(s.imag).max() > 1e-6 * np.abs(s).max()
+    assert e_apply <= 1e-12 and e_one <= 1e-12 and e_s <= 1e-12 and e_u <= 1e-12
+    assert info[0].removed_mean == 0.0
+    if "u_exact" in case.prob.meta:   # manufactured solution: the discretization error, and u is real
+        ue = case.prob.meta["u_exact"]
+        err = float(np.abs(u[0] - ue).max() / np.abs(ue).max())
+        say(f"[c>0 path] {which}: manufactured u error {err:.2e}, max |Im u| {np.abs(u[0].imag).max():.2e}")
+        assert err < 1e-5
+
+
+def test_sphere_eigenvalues_cpos_gpu(ctx):
+    """Section 7.3's c = 4 with a = 1 on the unit sphere (24 patches, q = 8): f = Y_lm gives
+    u = f / (-l(l+1) + 4), real, on the GPU."""
+    import torch
+    from paper_2401_12501_amd import pmx
+    p = helmholtz_sphere_problem(k=2, q=8, c0=4.0)
+    surf = pmx.Surface.from_inputs(ctx, p.surface)
+    op = pmx.Operator(surf, p.a, p.grad_a, c=p.c)
+    X = torch.tensor(p.surface.x)
+    worst = 0.0
+    for l in (0, 1, 2, 3, 4):
+        f = real_sph_harm_cartesian(l, min(l, 1), X).numpy()
+        _, u, info = op.solve(f[None, :].copy(), want_u=True)
+        ref = f / (-l * (l + 1) + 4.0)
+        e = float(np.abs(u[0] - ref).max() / np.abs(ref).max())
+        worst = max(worst, e)
+        say(f"[c>0 eigen] l={l}: u error {e:.2e}, iters {info[0].iters_total}")
+    assert worst < 1e-4
+
+
+def test_cpos_device_arrays_and_contract(ctx):
+    """Device tensors in and out (complex torch tensors, planar on the library side); the one-sign rule
+    for c; the allocation-free apply and the low-precision paths refuse a complex operator; a real
+    operator has no imaginary blocks."""
+    import torch
+    from paper_2401_12501_amd import pmx
+    p = helmholtz_ellipsoid_problem(k=1, q=5, positive=True)
+    surf = pmx.Surface.from_inputs(ctx, p.surface)
+    op = pmx.Operator(surf, p.a, p.grad_a, c=p.c)
+    sig = random_density(p.n, 2, seed=5).T + 1j * random_density(p.n, 2, seed=6).T
+    y_host = op.apply(np.ascontiguousarray(sig))
+    y_dev = op.apply(torch.tensor(sig, device="cuda:0"))
+    assert y_dev.is_cuda and y_dev.is_complex()
+    assert np.array_equal(y_dev.cpu().numpy(), y_host)
+    with pytest.raises(pmx.PmxError) as e:
+        op.apply_noalloc(torch.zeros((1, 2 * p.n), dtype=torch.float64, device="cuda:0"))
+    assert e.value.code == pmx.PMX_ERR_INVALID
+    for prec in (pmx.PMX_PREC_MIXED_FMM, pmx.PMX_PREC_FP32_DIRECT):
+        with pytest.raises(pmx.PmxError) as e:
+            op.apply(sig, prec)
+        assert e.value.code == pmx.PMX_ERR_INVALID
+    mixed = np.where(np.arange(p.n) == 17, -p.c, p.c)
+    with pytest.raises(pmx.PmxError) as e:
+        pmx.Operator(surf, p.a, p.grad_a, c=mixed)
+    assert e.value.code == pmx.PMX_ERR_INVALID
+    real_op = pmx.Operator(surf, p.a, p.grad_a, c=-p.c)
+    assert not real_op.complex
+    with pytest.raises(pmx.PmxError) as e:
+        real_op.export_near_imag()
+    assert e.value.code == pmx.PMX_ERR_INVALID
