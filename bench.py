@@ -292,66 +292,85 @@ def serving(n_req: int, slots: int, loads, budget_bytes: int, n_cal: int = 64):
 # Horner polynomials of the ascending series for z <= 2 (111) or by two degree-22 Chebyshev
 # series (Clenshaw) times exp(-z) / sqrt(z) for z > 2 (147).
 C_PAIR_FLOPS = {"pair": 44, "series": 111, "chebyshev": 147}
+# The same count for c > 0 (complex kernel, one complex density): geometry, the factored remainder's
+# real and imaginary parts and the complex multiply-add 54, plus J0, J1, Y0, Y1 of z = k r either by
+# four degree-16 polynomials in z^2 (Horner's rule) and a logarithm for z <= 8 (142, the "series"
+# entry) or by four degree-14 polynomials in 8 / z, a sine, a cosine and the envelope
+# sqrt(2 / (pi z)) for z > 8 (138, the "chebyshev" entry).
+C_PAIR_FLOPS_POS = {"pair": 54, "series": 142, "chebyshev": 138}
 
 
 def c_pair_flops(prob, n_sample: int = 200_000, seed: int = 7) -> tuple[float, float]:
-    """(flops per pair, fraction of pairs on the series branch) from seeded sample pairs."""
+    """(flops per pair, fraction of pairs on the first branch: z <= 2 for c < 0, z <= 8 for c > 0)
+    from seeded sample pairs."""
     rng = np.random.default_rng(seed)
     x = prob.surface.x
     i = rng.integers(prob.n, size=n_sample)
     j = rng.integers(prob.n, size=n_sample)
     keep = i != j
-    kap = np.sqrt(-prob.c[j[keep]] / prob.a[j[keep]])
+    pos = bool(prob.c[0] > 0)
+    kap = np.sqrt(np.abs(prob.c[j[keep]]) / prob.a[j[keep]])
     z = kap * np.linalg.norm(x[i[keep]] - x[j[keep]], axis=1)
-    f = float(np.mean(z <= 2.0))
-    return (C_PAIR_FLOPS["pair"] + f * C_PAIR_FLOPS["series"] + (1 - f) * C_PAIR_FLOPS["chebyshev"], f)
+    f = float(np.mean(z <= (8.0 if pos else 2.0)))
+    cnt = C_PAIR_FLOPS_POS if pos else C_PAIR_FLOPS
+    return (cnt["pair"] + f * cnt["series"] + (1 - f) * cnt["chebyshev"], f)
 
 
 def helmholtz_bench(args):
-    """The c < 0 path with advection (variable a and c of Section 7.4's kind, a non-tangent advection
+    """The c != 0 path with advection (variable a and c of Section 7.4's kind, a non-tangent advection
     field) on the 153,600-node ellipsoid surface: FP64 applies, a solve to 1e-8, the roofline of the
-    direct sum, and (CPU leg) oracle rows."""
+    direct sum, and (CPU leg) oracle rows.  Workload helmholtz: c = -4 - exp(x1/2) < 0; helmholtz_pos:
+    c = 2 (1 + 0.2 x2) > 0, the complex Helmholtz-type kernel (one complex density, timed in the
+    library's layout of two real columns)."""
     import torch
     from paper_2401_12501_amd import pmx
     from paper_2401_12501_amd.inputs import helmholtz_ellipsoid_problem, random_density
-    prob = helmholtz_ellipsoid_problem(k=args.k, q=10, swirl=True)
+    pos = args.workload == "helmholtz_pos"
+    prob = helmholtz_ellipsoid_problem(k=args.k, q=10, swirl=True, positive=pos)
     N = prob.n
-    log(f"[bench] workload {prob.name} N={N} path=fp64 (c < 0 with advection)")
+    tag = "c > 0" if pos else "c < 0"
+    log(f"[bench] workload {prob.name} N={N} path=fp64 ({tag} with advection)")
     ctx = pmx.Context(0)
     surf = pmx.Surface.from_inputs(ctx, prob.surface)
     t0 = time.perf_counter()
     op = pmx.Operator(surf, prob.a, prob.grad_a, c=prob.c, b=prob.b)
     t_setup = time.perf_counter() - t0
     sig_h = random_density(N, 1, seed=3)
-    sig = torch.tensor(np.ascontiguousarray(sig_h.T), device="cuda:0")
+    if pos:
+        sig_h = sig_h + 1j * random_density(N, 1, seed=4)
+        sig = torch.tensor(np.ascontiguousarray(np.stack([sig_h.real.T, sig_h.imag.T], axis=1)), device="cuda:0")
+    else:
+        sig = torch.tensor(np.ascontiguousarray(sig_h.T), device="cuda:0")
     y = torch.empty_like(sig)
     P64 = pmx.PMX_PREC_FP64_DIRECT
+    run = (lambda: op.apply_planar(sig, P64, out=y)) if pos else (lambda: op.apply(sig, P64, out=y))
     for _ in range(args.warmup):
-        op.apply(sig, P64, out=y)
+        run()
     torch.cuda.synchronize()
     op.profile_read()
     op.profile(True)
     ts = time.perf_counter()
     for _ in range(args.steps):
-        op.apply(sig, P64, out=y)
+        run()
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - ts) / args.steps
     op.profile(False)
     phases = op.profile_read()
-    log(f"[bench] fp64 (c < 0, advection): {step_s * 1e3:.3f} ms/apply; phases " +
+    log(f"[bench] fp64 ({tag}, advection): {step_s * 1e3:.3f} ms/apply; phases " +
         ", ".join(f"{k} {v[0] / max(v[1], 1):.3f} ms" for k, v in phases.items() if v[1]))
     fpp, f_series = c_pair_flops(prob)
     d_ms = phases["direct64"][0] / max(phases["direct64"][1], 1)
     achieved = N * (N - 1.0) * fpp / (d_ms * 1e-3) / 1e12
     near_ms = phases["near"][0] / max(phases["near"][1], 1)
-    near_bytes = op.stats().near_pairs * 8.0 * 100 + 24.0 * N
+    near_bytes = op.stats().near_pairs * 8.0 * 100 * (2 if pos else 1) + 24.0 * N * (2 if pos else 1)
     o = pmx.pmx_default_options()
     o.gmres_tol = 1e-8
     ts = time.perf_counter()
     s_sol, _, info = op.solve(np.ascontiguousarray(prob.f.T), o)
     t_solve = time.perf_counter() - ts
     log(f"[bench] solve to 1e-8: {t_solve:.3f} s, {info[0].iters_total} iterations, residual {info[0].rel_residual:.2e}")
-    y_h = y.cpu().numpy().T.copy()
+    y_h = y.cpu().numpy()
+    y_h = (y_h[:, 0] + 1j * y_h[:, 1]).T.copy() if pos else y_h.T.copy()
     err = None
     if not args.no_cpu:
         from oracle.operator import OracleOperator
@@ -359,18 +378,21 @@ def helmholtz_bench(args):
         orc = OracleOperator.from_problem(prob)
         tg = np.sort(np.random.default_rng(11).choice(N, size=48, replace=False))
         blocks = blocks_parallel(("paper_2401_12501_amd.inputs", "helmholtz_ellipsoid_problem",
-                                  {"k": args.k, "q": 10, "swirl": True}), ROOT, tg, kernels=("R",),
+                                  {"k": args.k, "q": 10, "swirl": True, "positive": pos}), ROOT, tg, kernels=("R",),
                                  workers=min(8, os.cpu_count() or 1))
         ref = orc.apply_rows(tg, sig_h, blocks)
         err = float(np.abs(y_h[tg] - ref).max() / np.abs(ref).max())
         log(f"[bench] 48 sampled rows vs oracle: {err:.2e}")
-    out = {"metric": "c<0 + advection operator-apply Gpts/s (FP64 direct far field)", "value": round(N / step_s / 1e9, 5),
+    cdesc = "c=2(1+0.2x2)" if pos else "c=-4-exp(x1/2)"
+    out = {"metric": f"{'c>0' if pos else 'c<0'} + advection operator-apply Gpts/s (FP64 direct far field)",
+           "value": round(N / step_s / 1e9, 5),
            "unit": "Gpts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "config": {"workload": (f"ellipsoid (1, 0.8, 0.6), {prob.surface.n_patches} patches x 10x10, N={N}, "
-                                   f"a=2+x3, c=-4-exp(x1/2), b=(0.6-x2, x1+0.4x3, 0.5x1x2)"), "path": "fp64"},
+                                   f"a=2+x3, {cdesc}, b=(0.6-x2, x1+0.4x3, 0.5x1x2)"), "path": "fp64"},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK["fp64_valu"], "unit": "TFLOP/s",
-                        "frac": round(achieved / PEAK["fp64_valu"], 4), "traffic": None, "kernel": "k_direct64_c",
+                        "frac": round(achieved / PEAK["fp64_valu"], 4), "traffic": None,
+                        "kernel": "k_direct64_cz" if pos else "k_direct64_c",
                         "avg_ms": round(d_ms, 4), "flops_per_pair": round(fpp, 1), "series_fraction": round(f_series, 4)},
            "near": {"ms": round(near_ms, 4), "achieved": round(near_bytes / (near_ms * 1e-3) / 1e9, 1), "unit": "GB/s",
                     "frac": round(near_bytes / (near_ms * 1e-3) / 1e9 / PEAK["hbm"], 4)},
@@ -388,10 +410,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--n-rhs", type=int, default=1)
-    ap.add_argument("--workload", choices=["ellipsoid", "star", "torus", "helmholtz"], default="ellipsoid",
+    ap.add_argument("--workload", choices=["ellipsoid", "star", "torus", "helmholtz", "helmholtz_pos"],
+                    default="ellipsoid",
                     help="ellipsoid: 153,600 nodes, 1 RHS (default); star: 525,696 nodes, 1 RHS; "
                          "torus: wobbly torus, 2,097,152 nodes, 16 RHS; helmholtz: the c < 0 path with advection "
-                         "on the ellipsoid's surface (FP64)")
+                         "on the ellipsoid's surface (FP64); helmholtz_pos: the same with c > 0 (complex kernel)")
     ap.add_argument("--k", type=int, default=16, help="ellipsoid: cube-sphere patches per face edge (16: 153,600 nodes)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
@@ -418,7 +441,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "helmholtz":
+    if args.workload in ("helmholtz", "helmholtz_pos"):
         helmholtz_bench(args)
         return
     import torch

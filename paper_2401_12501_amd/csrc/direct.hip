@@ -260,23 +260,51 @@ __global__ void __launch_bounds__(kBlock) k_direct64_c(DirectCArgs A) {
   double acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  for (int64_t j = j0; j < j1; ++j) {
-    const sdp row = S + j * RL;
-    const double dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
-    const double rr = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
-    const double ir = rsqrt(rr), rn = rr * ir;
-    const double kap = row[3];
-    double k0, k1;
-    bessel_k01(fmax(kap * rn, 1e-150), k0, k1);
-    double e;
+  // e = a' F(x_i, x_j) from K0, K1 at kappa r
+  auto term = [&](double dx, double dy, double dz, double ir, double kap, double k0, double k1) {
     if (A.kernel == 0) {
       const double snr = (nx * dx + ny * dy + nz * dz) * ir;
       const double gr = gx * dx + gy * dy + gz * dz;
       const double bra = fma(ir, fma(2.0 * at2 * snr, snr, gr), -B * snr);
-      e = kap * k1 * bra + at2 * kap * kap * k0 * fma(snr, snr, -1.0) - ct2 * k0;
-    } else {
-      e = -k0 * 0.15915494309189533577;
+      return kap * k1 * bra + at2 * kap * kap * k0 * fma(snr, snr, -1.0) - ct2 * k0;
     }
+    return -k0 * 0.15915494309189533577;
+  };
+  // sources two at a time, their Bessel functions sharing coefficients (bessel_k01_x2)
+  int64_t j = j0;
+  for (; j + 1 < j1; j += 2) {
+    double d[2][3], ir[2], kap[2], z[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const sdp row = S + (j + m) * RL;
+      d[m][0] = xi - row[0];
+      d[m][1] = yi - row[1];
+      d[m][2] = zi - row[2];
+      const double rr = fma(d[m][0], d[m][0], fma(d[m][1], d[m][1], fma(d[m][2], d[m][2], 1e-300)));
+      ir[m] = rsqrt(rr);
+      kap[m] = row[3];
+      z[m] = fmax(kap[m] * (rr * ir[m]), 1e-150);
+    }
+    double k0[2], k1[2];
+    bessel_k01_x2(z, k0, k1);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      double e = term(d[m][0], d[m][1], d[m][2], ir[m], kap[m], k0[m], k1[m]);
+      e = j + m == i ? 0.0 : e;
+      const sdp row = S + (j + m) * RL;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = fma(row[4 + r], e, acc[r]);
+    }
+  }
+  if (j < j1) {
+    const sdp row = S + j * RL;
+    const double dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
+    const double rr = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
+    const double ir = rsqrt(rr);
+    const double kap = row[3];
+    double k0, k1;
+    bessel_k01(fmax(kap * (rr * ir), 1e-150), k0, k1);
+    double e = term(dx, dy, dz, ir, kap, k0, k1);
     e = j == i ? 0.0 : e;
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = fma(row[4 + r], e, acc[r]);
@@ -314,6 +342,30 @@ __global__ void __launch_bounds__(kBlock) k_pack_sources_cz(PackCArgs A) {
   for (int k = 0; k < RL; ++k) A.rows[j * RL + k] = v[k];
 }
 
+// Target quantities of the complex direct sum.
+struct CzTarget {
+  double x, y, z, nx, ny, nz, at2, B, gx, gy, gz, ct2;
+  int kernel;
+};
+
+// e = a' F(x_i, x_j) (real and imaginary parts) for one source, from J0, J1, Y0, Y1 at k r.
+__device__ __forceinline__ void cz_term(const CzTarget& T, double dx, double dy, double dz, double ir, double k,
+                                        double bj0, double bj1, double by0, double by1, double& er, double& ei) {
+  if (T.kernel == 0) {
+    const double snr = (T.nx * dx + T.ny * dy + T.nz * dz) * ir;
+    const double gr = T.gx * dx + T.gy * dy + T.gz * dz;
+    const double bra = fma(ir, fma(2.0 * T.at2 * snr, snr, gr), -T.B * snr);
+    const double m = fma(T.at2 * k * k, fma(snr, snr, -1.0), T.ct2);
+    er = 1.5707963267948966192 * fma(m, by0, -k * by1 * bra);
+    ei = 1.5707963267948966192 * fma(k * bj1, bra, -m * bj0);
+  } else {
+    er = 0.25 * by0;
+    ei = -0.25 * bj0;
+  }
+}
+
+// Sources two at a time: the Bessel functions of the two pairs share their coefficients
+// (bessel_jy01_x2); an odd chunk ends with one source.
 template <int NP>
 __global__ void __launch_bounds__(kBlock) k_direct64_cz(DirectCArgs A) {
   constexpr int RL = row_len_cz<NP>();
@@ -322,43 +374,70 @@ __global__ void __launch_bounds__(kBlock) k_direct64_cz(DirectCArgs A) {
   const int64_t i = i0 < N ? i0 : N - 1;
   const int64_t j0 = (int64_t)blockIdx.y * A.chunk;
   const int64_t j1 = j0 + A.chunk < N ? j0 + A.chunk : N;
-  const double xi = A.tgt[i], yi = A.tgt[N + i], zi = A.tgt[2 * N + i];
-  const double nx = A.tgt[3 * N + i], ny = A.tgt[4 * N + i], nz = A.tgt[5 * N + i];
-  const double at2 = 0.5 * A.tgt[6 * N + i], B = A.tgt[7 * N + i];
-  const double gx = A.tg[i], gy = A.tg[N + i], gz = A.tg[2 * N + i];
-  const double ct2 = A.c[i] * 0.15915494309189533577;
+  CzTarget T;
+  T.x = A.tgt[i];
+  T.y = A.tgt[N + i];
+  T.z = A.tgt[2 * N + i];
+  T.nx = A.tgt[3 * N + i];
+  T.ny = A.tgt[4 * N + i];
+  T.nz = A.tgt[5 * N + i];
+  T.at2 = 0.5 * A.tgt[6 * N + i];
+  T.B = A.tgt[7 * N + i];
+  T.gx = A.tg[i];
+  T.gy = A.tg[N + i];
+  T.gz = A.tg[2 * N + i];
+  T.ct2 = A.c[i] * 0.15915494309189533577;
+  T.kernel = A.kernel;
   const sdp S = (sdp)A.rows;
   double ar[NP], ai[NP];
 #pragma unroll
   for (int r = 0; r < NP; ++r) ar[r] = ai[r] = 0.0;
-  for (int64_t j = j0; j < j1; ++j) {
-    const sdp row = S + j * RL;
-    const double dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
-    const double rr = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
-    const double ir = rsqrt(rr), rn = rr * ir;
-    const double k = row[3];
-    double bj0, bj1, by0, by1;
-    bessel_jy01(fmax(k * rn, 1e-150), bj0, bj1, by0, by1);
-    double er, ei;
-    if (A.kernel == 0) {
-      const double snr = (nx * dx + ny * dy + nz * dz) * ir;
-      const double gr = gx * dx + gy * dy + gz * dz;
-      const double bra = fma(ir, fma(2.0 * at2 * snr, snr, gr), -B * snr);
-      const double m = fma(at2 * k * k, fma(snr, snr, -1.0), ct2);
-      er = 1.5707963267948966192 * fma(m, by0, -k * by1 * bra);
-      ei = 1.5707963267948966192 * fma(k * bj1, bra, -m * bj0);
-    } else {
-      er = 0.25 * by0;
-      ei = -0.25 * bj0;
-    }
-    er = j == i ? 0.0 : er;
-    ei = j == i ? 0.0 : ei;
+  auto accumulate = [&](const sdp row, double er, double ei) {
 #pragma unroll
     for (int r = 0; r < NP; ++r) {
       const double qr = row[4 + 2 * r], qi = row[5 + 2 * r];
       ar[r] = fma(qr, er, fma(-qi, ei, ar[r]));
       ai[r] = fma(qr, ei, fma(qi, er, ai[r]));
     }
+  };
+  int64_t j = j0;
+  for (; j + 1 < j1; j += 2) {
+    double d[2][3], ir[2], k[2], z[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const sdp row = S + (j + m) * RL;
+      d[m][0] = T.x - row[0];
+      d[m][1] = T.y - row[1];
+      d[m][2] = T.z - row[2];
+      const double rr = fma(d[m][0], d[m][0], fma(d[m][1], d[m][1], fma(d[m][2], d[m][2], 1e-300)));
+      ir[m] = rsqrt(rr);
+      k[m] = row[3];
+      z[m] = fmax(k[m] * (rr * ir[m]), 1e-150);
+    }
+    double bj0[2], bj1[2], by0[2], by1[2];
+    bessel_jy01_x2(z, bj0, bj1, by0, by1);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      double er, ei;
+      cz_term(T, d[m][0], d[m][1], d[m][2], ir[m], k[m], bj0[m], bj1[m], by0[m], by1[m], er, ei);
+      er = j + m == i ? 0.0 : er;
+      ei = j + m == i ? 0.0 : ei;
+      accumulate(S + (j + m) * RL, er, ei);
+    }
+  }
+  if (j < j1) {
+    const sdp row = S + j * RL;
+    const double dx = T.x - row[0], dy = T.y - row[1], dz = T.z - row[2];
+    const double rr = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
+    const double ir = rsqrt(rr);
+    const double k = row[3];
+    double bj0, bj1, by0, by1;
+    bessel_jy01(fmax(k * (rr * ir), 1e-150), bj0, bj1, by0, by1);
+    double er, ei;
+    cz_term(T, dx, dy, dz, ir, k, bj0, bj1, by0, by1, er, ei);
+    er = j == i ? 0.0 : er;
+    ei = j == i ? 0.0 : ei;
+    accumulate(row, er, ei);
   }
   if (i0 < N) {
 #pragma unroll

@@ -305,11 +305,19 @@ constexpr KTable make_ktable() {
   return t;
 }
 
+// c: compile-time constants.  Each passes through an empty asm that takes it in scalar registers,
+// so that it is materialised where it is used (scalar moves, issued beside the vector arithmetic)
+// rather than hoisted out of the caller's loop into vector registers (98 constants, 196 VGPRs).
+__device__ __forceinline__ double sconst(double v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
 template <int N, class C>
 __device__ __forceinline__ double horner(C c, int o, double t) {
   double p = c[o + N - 1];
 #pragma unroll
-  for (int k = N - 2; k >= 0; --k) p = fma(p, t, c[o + k]);
+  for (int k = N - 2; k >= 0; --k) p = fma(p, t, sconst(c[o + k]));
   return p;
 }
 
@@ -319,14 +327,14 @@ __device__ __forceinline__ double clenshaw(C c, int o, double x) {
   double b1 = 0.0, b2 = 0.0;
 #pragma unroll
   for (int k = N - 1; k >= 1; --k) {
-    const double b = fma(x2, b1, c[o + k] - b2);
+    const double b = fma(x2, b1, sconst(c[o + k]) - b2);
     b2 = b1;
     b1 = b;
   }
-  return fma(x, b1, c[o] - b2);
+  return fma(x, b1, sconst(c[o]) - b2);
 }
 
-// c: the coefficient table (make_ktable's order), compile-time constants or an LDS copy
+// c: the coefficient table (make_ktable's order), compile-time constants
 template <class C>
 __device__ __forceinline__ void bessel_k01_t(double z, double& k0, double& k1, C c) {
   if (z <= 2.0) {
@@ -345,6 +353,72 @@ __device__ __forceinline__ void bessel_k01_t(double z, double& k0, double& k1, C
 __device__ __forceinline__ void bessel_k01(double z, double& k0, double& k1) {
   constexpr KTable kt = make_ktable();
   bessel_k01_t(z, k0, k1, kt.v);
+}
+
+// K0, K1 at two arguments on the same side of z = 2 (else one at a time), with each coefficient
+// materialised once for both (the scalar moves of a 64-bit constant, shared by two FMAs, keep the
+// vector unit busy: see poly).
+__device__ __forceinline__ void bessel_k01_x2(const double (&z)[2], double (&k0)[2], double (&k1)[2]) {
+  constexpr KTable kt = make_ktable();
+  const bool sa = z[0] <= 2.0, sb = z[1] <= 2.0;
+  if (sa != sb) {
+    bessel_k01_t(z[0], k0[0], k1[0], kt.v);
+    bessel_k01_t(z[1], k0[1], k1[1], kt.v);
+    return;
+  }
+  if (sa) {
+    double t[2], i0[2], s0[2], i1[2], s1[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) t[m] = 0.25 * z[m] * z[m];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) i0[m] = s0[m] = i1[m] = s1[m] = 0.0;
+#pragma unroll
+    for (int k = 12; k >= 0; --k) {
+      const double c0 = sconst(kt.v[k]), c1 = sconst(kt.v[13 + k]), c2 = sconst(kt.v[26 + k]),
+                   c3 = sconst(kt.v[39 + k]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        i0[m] = fma(i0[m], t[m], c0);
+        s0[m] = fma(s0[m], t[m], c1);
+        i1[m] = fma(i1[m], t[m], c2);
+        s1[m] = fma(s1[m], t[m], c3);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double L = 0.5 * log_pair(t[m]) + kEulerGamma;   // ln(z/2) + gamma
+      k0[m] = fma(-L, i0[m], s0[m]);
+      k1[m] = 1.0 / z[m] + L * (0.5 * z[m] * i1[m]) - 0.25 * z[m] * s1[m];
+    }
+  } else {
+    double x2[2], a1[2], a2[2], b1[2], b2[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      x2[m] = 2.0 * (4.0 / z[m] - 1.0);
+      a1[m] = a2[m] = b1[m] = b2[m] = 0.0;
+    }
+#pragma unroll
+    for (int k = 22; k >= 1; --k) {
+      const double c0 = sconst(kt.v[52 + k]), c1 = sconst(kt.v[75 + k]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const double a = fma(x2[m], a1[m], c0 - a2[m]);
+        a2[m] = a1[m];
+        a1[m] = a;
+        const double b = fma(x2[m], b1[m], c1 - b2[m]);
+        b2[m] = b1[m];
+        b1[m] = b;
+      }
+    }
+    const double c0 = sconst(kt.v[52]), c1 = sconst(kt.v[75]);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double x = 0.5 * x2[m];
+      const double e = exp(-z[m]) * rsqrt(z[m]);
+      k0[m] = fma(x, a1[m], c0 - a2[m]) * e;
+      k1[m] = fma(x, b1[m], c1 - b2[m]) * e;
+    }
+  }
 }
 
 // The same K0, K1 for kernels short of registers (the local-rule weights): the series summed by
@@ -403,106 +477,152 @@ __device__ __forceinline__ void bessel_k01_compact(double z, double& k0, double&
 // Bessel functions J0, J1, Y0, Y1 of a real argument z > 0 (FP64): the Green's function of
 // (a Delta + c) G = delta with c > 0 is the complex G = -(i / 4a) H0(k r), k = sqrt(c / a), with
 // H0 = J0 + i Y0 and H0' = -H1 = -(J1 + i Y1).
-//  * z <= 8: Chebyshev series of degree 16 in x = z^2 / 32 - 1 of the entire functions J0, J1 / z,
+//  * z <= 8: interpolants of degree 16 in x = z^2 / 32 - 1 of the entire functions J0, J1 / z,
 //    S0 = Y0 - (2/pi) ln(z/2) J0 and S1 = (Y1 - (2/pi) ln(z/2) J1 + 2/(pi z)) / z (the power
 //    series of Y0 and Y1 split into their log and entire parts);
 //  * z > 8: Hankel's form H_nu = sqrt(2/(pi z)) (P_nu + i Q_nu) e^{i chi}, chi = z - nu pi/2 - pi/4,
-//    with P_nu, Q_nu as Chebyshev series of degree 14 in x = 16 / z - 1.
-// Coefficients by interpolation at the Chebyshev points at 40 digits (bessel_jy_table.py), summed
-// by Clenshaw's recurrence: absolute error below 1e-15 for z <= 8, and below 4e-16 times the
-// envelope sqrt(2/(pi z)) beyond (plus the rounding of chi for large z).
-constexpr double kChebJ0[17] = {
-    1.57727971474890122e-01, -8.72344235285222105e-03, 2.65178613203336799e-01,
-    -3.70094993872649769e-01, 1.58067102332097253e-01, -3.48937694114088842e-02,
-    4.81918006946760458e-03, -4.60626166206275038e-04, 3.24603288210050832e-05,
-    -1.76194690776215074e-06, 7.60816359241878206e-08, -2.67925353055767280e-09,
-    7.84869631447946477e-11, -1.94383468673701443e-12, 4.12532059560903340e-14,
-    -7.58850787689090404e-16, 1.22163200807580911e-17};
-constexpr double kChebJ1z[17] = {
-    8.10448463256581153e-02, -1.48975145067652109e-01, 1.60999262357209710e-01,
-    -8.26804917668179096e-02, 2.22136396549660366e-02, -3.64694060076927590e-03,
-    4.05033772835482198e-04, -3.25555486685725868e-05, 1.98587740499151654e-06,
-    -9.52198475675043612e-08, 3.68713375909714814e-09, -1.17802662269588496e-10,
-    3.16015458034800320e-12, -7.22175523965176834e-14, 1.42321440034525375e-15,
-    -2.44419722826302914e-17, 3.69067791636300323e-19};
-constexpr double kChebS0[17] = {
-    3.64546980911604410e-02, -2.78323709407582498e-01, 2.96049999020714827e-01,
-    9.82550840818786353e-02, -1.07551552806277831e-01, 3.17990740844145137e-02,
-    -5.16139710581071508e-03, 5.49852532003901199e-04, -4.19969831494201336e-05,
-    2.42903611079237928e-06, -1.10499697934729567e-07, 4.06651736597911041e-09,
-    -1.23741488982898536e-10, 3.16857255289459007e-12, -6.92695603238257180e-14,
-    1.30863081590583929e-15, -2.15821547475169886e-17};
-constexpr double kChebS1[17] = {
-    3.83007698524237758e-02, -8.18256141273282639e-02, -2.48677076121964005e-02,
-    4.79674527527469835e-02, -1.85258845108980212e-02, 3.68060768782351106e-03,
-    -4.62725406029336874e-04, 4.06940026958086984e-05, -2.66176951252956248e-06,
-    1.35060269132543387e-07, -5.48352411033627623e-09, 1.82450868412290067e-10,
-    -5.07066663659112876e-12, 1.19561625175879380e-13, -2.42316244270063974e-15,
-    4.26812639301533527e-17, -6.59496226022674799e-19};
-constexpr double kChebP0[15] = {
-    9.99595064768672881e-01, -5.38079561396069181e-04, -1.31796771233615704e-04,
-    1.51422497048644466e-06, 1.58468617920632462e-07, -8.56069553945711599e-09,
-    -2.95723433548997341e-10, 6.57355625370310452e-11, -2.23749702832823310e-12,
-    -4.48211403609405547e-13, 6.95482668020278653e-14, -1.51340142546660594e-15,
-    -9.24212105515919074e-16, 1.55618053885131831e-16, -5.36266268289223379e-18};
-constexpr double kChebQ0[15] = {
-    -7.76935569420532119e-03, -7.74803230965447672e-03, 2.53654116543079604e-05,
-    3.94273598399711378e-06, -1.07234982991288198e-07, -7.21389799327753528e-09,
-    7.37646028933544292e-10, 1.50687810891936521e-12, -5.74589537316565120e-12,
-    4.59965741902894660e-13, 2.27032322588495181e-14, -8.87890122888076548e-15,
-    7.44949474122565498e-16, 5.85684924495839078e-17, -2.42267554176777644e-17};
-constexpr double kChebP1[15] = {
-    1.00067753586591346e+00, 9.01007251959081855e-04, 2.21724349185994539e-04,
-    -1.96575946319104395e-06, -2.08895311432702157e-07, 1.02814435089397333e-08,
-    3.75970547893049245e-10, -7.63889135778662110e-11, 2.38734669892881568e-12,
-    5.18254887309946603e-13, -7.69396898176723118e-14, 1.44008460247785360e-15,
-    1.03293157223598494e-15, -1.68247485453780656e-16, 5.23442402189761112e-18};
-constexpr double kChebQ1[15] = {
-    2.33768299862858048e-02, 2.33468012235455748e-02, -3.57601059090138212e-05,
-    -5.60863149492627211e-06, 1.32738940843397802e-07, 9.16975845066427102e-09,
-    -8.68388803707271890e-10, -3.78073005146958109e-12, 6.63145586075118320e-12,
-    -5.05843904179735278e-13, -2.72078161818527664e-14, 9.85380680235480784e-15,
-    -7.93959914335076049e-16, -6.76771891484821019e-17, 2.64010413416378994e-17};
+//    with P_nu, Q_nu as interpolants of degree 14 in x = 16 / z - 1.
+// Interpolation at the Chebyshev points at 40 digits, converted to the power form in x
+// (bessel_jy_table.py) and evaluated by Horner's rule, one FMA per degree: absolute error below
+// 1e-15 for z <= 8, and below 4e-16 times the envelope sqrt(2/(pi z)) beyond (plus the rounding of
+// chi for large z).
+constexpr double kPolyJ0[17] = {
+    4.58296648598137679e-02, 9.30301247295857170e-01, -6.48469283087183657e-01,
+    -8.08088807669687159e-01, 1.03837946114372115e+00, -5.07468045847100035e-01,
+    1.45988848567592672e-01, -2.84727186108820439e-02, 4.05807898914080541e-03,
+    -4.43545922431152020e-04, 3.84731978563400856e-05, -2.71774922362980731e-06,
+    1.59561090577813045e-07, -7.91532308447919211e-09, 3.36345045686666908e-10,
+    -1.24330113054980572e-11, 4.00304376406281128e-13};
+constexpr double kPolyJ1z[17] = {
+    -5.81438279559910731e-02, 8.10586603858979571e-02, 1.51516651438066335e-01,
+    -2.59594865285930287e-01, 1.58583764327219379e-01, -5.47458182128472207e-02,
+    1.24568143922554383e-02, -2.02903949457059959e-03, 2.49494581390904936e-04,
+    -2.40457486596869831e-05, 1.86845253720572723e-06, -1.19670818678721719e-07,
+    6.43126878575308811e-09, -2.94301379839091608e-10, 1.16105979140429647e-11,
+    -4.00457273878614694e-13, 1.20936133963382890e-14};
+constexpr double kPolyS0[17] = {
+    -3.62027343237145194e-01, -4.17920742320695204e-01, 1.36094565996554562e+00,
+    -2.12459994420659437e-01, -6.19340782630335762e-01, 4.48246044635631391e-01,
+    -1.54536796523105618e-01, 3.38028569639960627e-02, -5.23502767079865160e-03,
+    6.10434564379922656e-04, -5.58183046277945538e-05, 4.12205434835447046e-06,
+    -2.51441069429675456e-07, 1.28980708993269862e-08, -5.64627421985713677e-10,
+    2.14406072878012710e-11, -7.07204046766636683e-13};
+constexpr double kPolyS1[17] = {
+    4.51026620686948293e-02, -2.07608578428306018e-01, 9.02275063673093486e-02,
+    1.20520354268881608e-01, -1.26419950565698824e-01, 5.43901163079462957e-02,
+    -1.41319233942484926e-02, 2.52713404668281549e-03, -3.33722570111453490e-04,
+    3.40636337531640451e-05, -2.77650558057605094e-06, 1.85242018405127545e-07,
+    -1.03153888256016932e-08, 4.87102079864533318e-10, -1.97641052412663956e-11,
+    6.99289828231632531e-13, -2.16103723343110078e-14};
+constexpr double kPolyP0[15] = {
+    9.99727020301939828e-01, -5.42665503949395678e-04, -2.64866539289064355e-04,
+    6.23184838001214216e-06, 1.28155708141464465e-06, -1.44524821291491504e-07,
+    -8.80919465124196836e-09, 4.45943034178490071e-09, -3.81665406833019405e-10,
+    -1.07890896493245268e-10, 4.10756541653177263e-11, -3.62131059299667937e-12,
+    -1.73902812765271616e-12, 6.37411548713499982e-13, -4.39309326982531792e-14};
+constexpr double kPolyQ0[15] = {
+    -7.79482908425647904e-03, -7.75989659340645989e-03, 5.16021657488700038e-05,
+    1.59152491104618754e-05, -8.94214634126615001e-07, -1.15381323682373488e-07,
+    2.50981519373035109e-08, -1.94087802054372866e-10, -7.58734439105768389e-10,
+    1.43728795502030351e-10, 6.09196974193538222e-12, -9.87165862986276619e-12,
+    2.22028605433867113e-12, 2.39896545073495687e-13, -1.98465580381616246e-13};
+constexpr double kPolyP1[15] = {
+    1.00045560224791075e+00, 9.06956476934860523e-04, 4.45126548017375789e-04,
+    -8.07300631462911114e-06, -1.68879546695778430e-06, 1.73280276454166754e-07,
+    1.13300715437623104e-08, -5.18167022293861879e-09, 4.11062102139095498e-10,
+    1.25818334752817792e-10, -4.55330908338268183e-11, 3.71435715929805041e-12,
+    1.96536245438344920e-12, -6.89141700418685567e-13, 4.28804015873852303e-14};
+constexpr double kPolyQ1[15] = {
+    2.34127237061823069e-02, 2.33636729886258498e-02, -7.25979678504675048e-05,
+    -2.26180699758607612e-05, 1.10466539706616358e-06, 1.46908715443831984e-07,
+    -2.95134732397787612e-08, 7.78233745253638928e-11, 8.77454843969775786e-10,
+    -1.58370507852874116e-10, -8.01147751758117773e-12, 1.09912169075559172e-11,
+    -2.38300056190567776e-12, -2.77205766752182690e-13, 2.16277330670697672e-13};
 
-template <int N>
-__device__ __forceinline__ double cheb(const double (&c)[N], double x) {
-  const double x2 = 2.0 * x;
-  double b1 = 0.0, b2 = 0.0;
+// Horner's rule on compile-time coefficients at M points, each coefficient materialised once at its
+// use (sconst) and shared by the M points.  On this hardware a 64-bit constant operand takes two
+// scalar moves, and scalar and vector instructions each issue at most once per four cycles per
+// SIMD, so one point per coefficient leaves the vector unit half idle; two points balance them.
+// (Hoisted out of the caller's loops, the 128 constants of bessel_jy01 would take 256 VGPRs.)
+template <int N, int M>
+__device__ __forceinline__ void poly(const double (&a)[N], const double (&x)[M], double (&p)[M]) {
 #pragma unroll
-  for (int k = N - 1; k >= 1; --k) {
-    const double b = fma(x2, b1, c[k] - b2);
-    b2 = b1;
-    b1 = b;
+  for (int m = 0; m < M; ++m) p[m] = a[N - 1];
+#pragma unroll
+  for (int k = N - 2; k >= 0; --k) {
+    const double c = sconst(a[k]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) p[m] = fma(p[m], x[m], c);
   }
-  return fma(x, b1, c[0] - b2);
+}
+
+// J0, J1, Y0, Y1 at M arguments that lie on the same side of z = 8 (the caller checks).
+template <int M>
+__device__ __forceinline__ void bessel_jy01_same(const double (&z)[M], bool small, double (&j0)[M],
+                                                 double (&j1)[M], double (&y0)[M], double (&y1)[M]) {
+  constexpr double k2OverPi = 0.63661977236758134308;   // 2 / pi
+  double x[M], a0[M], a1[M], s0[M], s1[M];
+  if (small) {
+    double w[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      w[m] = z[m] * z[m];
+      x[m] = fma(w[m], 1.0 / 32.0, -1.0);
+    }
+    poly(kPolyJ0, x, a0);
+    poly(kPolyJ1z, x, a1);
+    poly(kPolyS0, x, s0);
+    poly(kPolyS1, x, s1);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const double L = 0.5 * k2OverPi * log_pair(0.25 * w[m]);   // (2/pi) ln(z/2)
+      j0[m] = a0[m];
+      j1[m] = z[m] * a1[m];
+      y0[m] = fma(L, a0[m], s0[m]);
+      y1[m] = fma(L, j1[m], fma(z[m], s1[m], -k2OverPi / z[m]));
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] = 16.0 / z[m] - 1.0;
+    poly(kPolyP0, x, a0);   // P0
+    poly(kPolyQ0, x, s0);   // Q0
+    poly(kPolyP1, x, a1);   // P1
+    poly(kPolyQ1, x, s1);   // Q1
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double sn, cs;
+      sincos(z[m], &sn, &cs);
+      const double env = sqrt(k2OverPi / z[m]);
+      const double c0 = (cs + sn) * 0.70710678118654752440;   // cos(z - pi/4)
+      const double s0m = (sn - cs) * 0.70710678118654752440;  // sin(z - pi/4)
+      // chi_1 = chi_0 - pi/2: cos chi_1 = sin chi_0, sin chi_1 = -cos chi_0
+      j0[m] = env * fma(a0[m], c0, -s0[m] * s0m);
+      y0[m] = env * fma(a0[m], s0m, s0[m] * c0);
+      j1[m] = env * fma(a1[m], s0m, s1[m] * c0);
+      y1[m] = env * fma(s1[m], s0m, -a1[m] * c0);
+    }
+  }
 }
 
 __device__ __forceinline__ void bessel_jy01(double z, double& j0, double& j1, double& y0, double& y1) {
-  constexpr double k2OverPi = 0.63661977236758134308;   // 2 / pi
-  if (z <= 8.0) {
-    const double w = z * z;
-    const double x = fma(w, 1.0 / 32.0, -1.0);
-    const double a0 = cheb(kChebJ0, x), a1 = cheb(kChebJ1z, x);
-    const double s0 = cheb(kChebS0, x), s1 = cheb(kChebS1, x);
-    const double L = 0.5 * k2OverPi * log_pair(0.25 * w);   // (2/pi) ln(z/2)
-    j0 = a0;
-    j1 = z * a1;
-    y0 = fma(L, a0, s0);
-    y1 = fma(L, j1, fma(z, s1, -k2OverPi / z));
+  double zz[1] = {z}, a[1], b[1], c[1], d[1];
+  bessel_jy01_same<1>(zz, z <= 8.0, a, b, c, d);
+  j0 = a[0];
+  j1 = b[0];
+  y0 = c[0];
+  y1 = d[0];
+}
+
+// Two arguments at once (the direct sum's pairs of sources): shared coefficients when both lie on
+// the same side of z = 8, else one at a time.
+__device__ __forceinline__ void bessel_jy01_x2(const double (&z)[2], double (&j0)[2], double (&j1)[2],
+                                               double (&y0)[2], double (&y1)[2]) {
+  const bool sa = z[0] <= 8.0, sb = z[1] <= 8.0;
+  if (sa == sb) {
+    bessel_jy01_same<2>(z, sa, j0, j1, y0, y1);
   } else {
-    const double x = 16.0 / z - 1.0;
-    const double p0 = cheb(kChebP0, x), q0 = cheb(kChebQ0, x);
-    const double p1 = cheb(kChebP1, x), q1 = cheb(kChebQ1, x);
-    double sn, cs;
-    sincos(z, &sn, &cs);
-    const double env = sqrt(k2OverPi / z);
-    const double c0 = (cs + sn) * 0.70710678118654752440;   // cos(z - pi/4)
-    const double s0 = (sn - cs) * 0.70710678118654752440;   // sin(z - pi/4)
-    // chi_1 = chi_0 - pi/2: cos chi_1 = sin chi_0, sin chi_1 = -cos chi_0
-    j0 = env * fma(p0, c0, -q0 * s0);
-    y0 = env * fma(p0, s0, q0 * c0);
-    j1 = env * fma(p1, s0, q1 * c0);
-    y1 = env * fma(q1, s0, -p1 * c0);
+    bessel_jy01(z[0], j0[0], j1[0], y0[0], y1[0]);
+    bessel_jy01(z[1], j0[1], j1[1], y0[1], y1[1]);
   }
 }
 

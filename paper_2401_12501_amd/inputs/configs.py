@@ -143,15 +143,17 @@ def helmholtz_sphere_problem(k: int = 2, q: int = 8, c0: float | None = None, om
 
 
 def helmholtz_ellipsoid_problem(k: int = 4, q: int = 8, axes=(1.0, 0.8, 0.6), seed: int = 1, n_rhs: int = 1,
-                                swirl: bool = False, positive: bool = False):
+                                swirl: bool = False, positive: bool = False, c_scale: float = 1.0):
     """Ellipsoid with the variable coefficients a = 2 + x3 and c = -4 - exp(x1 / 2) (c < 0; with
-    ``positive`` c = 2 (1 + 0.2 x2) > 0) and right-hand sides of 20 solid harmonics (seeded); with
-    ``swirl`` the advection field fields.b_swirl as well."""
+    ``positive`` c = 2 (1 + 0.2 x2) > 0), c multiplied by ``c_scale``, and right-hand sides of 20 solid
+    harmonics (seeded); with ``swirl`` the advection field fields.b_swirl as well."""
     s = cube_sphere(k, q, axes=axes, name="ellipsoid")
     a, ga = F.eval_field(F.a_linear_z, s.x)
     c, _ = F.eval_field(F.c_pos_y if positive else F.c_exp_x, s.x)
+    c = c * c_scale
     f = np.stack([F.solid_harmonic_rhs(s.x, seed + 100 * r) for r in range(n_rhs)], axis=1)
-    name = f"helmholtz_ellipsoid_k{k}_q{q}" + ("_swirl" if swirl else "") + ("_pos" if positive else "")
+    name = (f"helmholtz_ellipsoid_k{k}_q{q}" + ("_swirl" if swirl else "") + ("_pos" if positive else "") +
+            (f"_cx{c_scale:g}" if c_scale != 1.0 else ""))
     return Problem(s, a, ga, f, name=name, c=c, b=F.b_swirl(s.x) if swirl else None)
 
 

@@ -299,6 +299,15 @@ class Operator:
         _check(lib().pmx_apply(self.h, precision, n_rhs, ptrs[0], ptrs[1], kind, stream))
         return out
 
+    def apply_planar(self, sp, precision: int = PMX_PREC_FP64_DIRECT, out=None):
+        """pmx_apply on a complex operator in the library's own layout: sp is (n_rhs, 2, N) float64
+        (real parts, then imaginary parts), out likewise; nothing is converted."""
+        if out is None:
+            out = np.empty(sp.shape) if not _is_torch(sp) else sp.new_empty(sp.shape)
+        ptrs, kind, stream, keep = _marshal(sp, out)
+        _check(lib().pmx_apply(self.h, precision, sp.shape[0], ptrs[0], ptrs[1], kind, stream))
+        return out
+
     def apply_noalloc(self, sigma, out=None, check: bool = True):
         """pmx_apply_noalloc: y = A sigma (FP64 direct far field) with the library's static scratch;
         sigma and out are device tensors of shape (n_rhs, N).  Returns out (check=True) or the status."""

@@ -93,17 +93,17 @@ def test_tables_match_the_generator():
 
 def jy01(z, T):
     """The device routine bessel_jy01 step by step (natural log in place of the device's log)."""
-    cheb = clenshaw
+    cheb = horner
     k2pi = 2.0 / math.pi
     if z <= 8.0:
         w = z * z
         x = w / 32.0 - 1.0
-        a0, a1, s0, s1 = (cheb(T[n], x) for n in ("kChebJ0", "kChebJ1z", "kChebS0", "kChebS1"))
+        a0, a1, s0, s1 = (cheb(T[n], x) for n in ("kPolyJ0", "kPolyJ1z", "kPolyS0", "kPolyS1"))
         L = 0.5 * k2pi * math.log(0.25 * w)
         j1 = z * a1
         return a0, j1, L * a0 + s0, L * j1 + z * s1 - k2pi / z
     x = 16.0 / z - 1.0
-    p0, q0, p1, q1 = (cheb(T[n], x) for n in ("kChebP0", "kChebQ0", "kChebP1", "kChebQ1"))
+    p0, q0, p1, q1 = (cheb(T[n], x) for n in ("kPolyP0", "kPolyQ0", "kPolyP1", "kPolyQ1"))
     sn, cs = math.sin(z), math.cos(z)
     env = math.sqrt(k2pi / z)
     c0, s0 = (cs + sn) * math.sqrt(0.5), (sn - cs) * math.sqrt(0.5)
@@ -115,8 +115,8 @@ def test_device_jy01_against_mpmath():
     error below 3e-15 for z <= 8 (Y0, Y1 relative near z = 0, where they diverge), and below
     3e-15 times the envelope sqrt(2 / (pi z)) beyond."""
     mp.mp.dps = 30
-    T = {n: table(n) for n in ("kChebJ0", "kChebJ1z", "kChebS0", "kChebS1", "kChebP0", "kChebQ0", "kChebP1",
-                                "kChebQ1")}
+    T = {n: table(n) for n in ("kPolyJ0", "kPolyJ1z", "kPolyS0", "kPolyS1", "kPolyP0", "kPolyQ0", "kPolyP1",
+                                "kPolyQ1")}
     zs = np.concatenate([np.logspace(-10, 0, 200), np.linspace(1.0, 8.0, 700), np.linspace(7.99, 8.01, 41),
                          np.linspace(8.0, 80.0, 1500)])
     worst = 0.0
@@ -132,12 +132,18 @@ def test_device_jy01_against_mpmath():
 
 
 def test_jy_tables_limits():
-    """P_nu -> 1 and Q_nu -> 0 as z -> infinity (x = -1), and the small-range fits equal their
-    values at z = 0: J0(0) = 1, J1(z)/z -> 1/2."""
-    at_minus_one = lambda c: sum(cj * (-1) ** j for j, cj in enumerate(c))
-    assert abs(at_minus_one(table("kChebP0")) - 1.0) < 1e-15
-    assert abs(at_minus_one(table("kChebP1")) - 1.0) < 1e-15
-    assert abs(at_minus_one(table("kChebQ0"))) < 1e-15
-    assert abs(at_minus_one(table("kChebQ1"))) < 1e-15
-    assert abs(at_minus_one(table("kChebJ0")) - 1.0) < 1e-15
-    assert abs(at_minus_one(table("kChebJ1z")) - 0.5) < 1e-15
+    """Power forms in x: P_nu -> 1 and Q_nu -> 0 as z -> infinity (x = -1), and the small-range fits
+    equal their values at z = 0 (x = -1): J0(0) = 1, J1(z)/z -> 1/2; and at z = 8 (x = 1) the
+    small-range J0 meets the large-range Hankel form."""
+    at = lambda c, x: sum(cj * x ** j for j, cj in enumerate(c))
+    assert abs(at(table("kPolyP0"), -1.0) - 1.0) < 1e-15
+    assert abs(at(table("kPolyP1"), -1.0) - 1.0) < 1e-15
+    assert abs(at(table("kPolyQ0"), -1.0)) < 1e-15
+    assert abs(at(table("kPolyQ1"), -1.0)) < 1e-15
+    assert abs(at(table("kPolyJ0"), -1.0) - 1.0) < 1e-15
+    assert abs(at(table("kPolyJ1z"), -1.0) - 0.5) < 1e-15
+    z = 8.0
+    env = math.sqrt(2.0 / (math.pi * z))
+    chi = z - math.pi / 4
+    j0_large = env * (at(table("kPolyP0"), 1.0) * math.cos(chi) - at(table("kPolyQ0"), 1.0) * math.sin(chi))
+    assert abs(at(table("kPolyJ0"), 1.0) - j0_large) < 2e-15

@@ -7,8 +7,9 @@ and the unit sphere (24 patches, q = 8), both with a = 2 + z and c = 2 (1 + 0.2 
 also with a non-tangent advection field (eq:adv_remainder).  Bars: the real and imaginary parts of
 the correction blocks C and D within 1e-13 of the largest entry (plus 16x the oracle's one-ulp
 sensitivity where the rules sample close to the target); FP64 applies over 1, 2 and 8 complex
-densities at once, solves and the representation within 1e-12; Section 7.3's c = 4 with a = 1 on
-the sphere gives the eigenvalues -l(l+1) + 4 within the discretization error.
+densities at once, solves and the representation within 1e-12; with c scaled by 50 the blocks and
+applies take both ranges of the device Bessel functions; Section 7.3's c = 4 with a = 1 on the
+sphere gives the eigenvalues -l(l+1) + 4 within the discretization error.
 """
 import os
 import sys
@@ -74,10 +75,17 @@ def ragged_b(ctx):
     return Case(helmholtz_ellipsoid_problem, {"k": 1, "q": 7, "positive": True, "swirl": True}, ctx)
 
 
+@pytest.fixture(scope="module")
+def ragged_hi(ctx):
+    """c multiplied by 50 (k = sqrt(c/a) from 6.0 to 8.6): k r runs to about 15 (half the pairs above 8),
+    so the Bessel functions take both of their ranges, also within one pair of sources."""
+    return Case(helmholtz_ellipsoid_problem, {"k": 1, "q": 7, "positive": True, "c_scale": 50.0}, ctx)
+
+
 CASES = ["ragged", "sphere", "ragged_b"]
 
 
-@pytest.mark.parametrize("which", CASES)
+@pytest.mark.parametrize("which", CASES + ["ragged_hi"])
 def test_blocks_cpos(which, request):
     """Real and imaginary parts of the correction blocks C (remainder) and D (parametrix) against the
     oracle's complex blocks: 1e-13 of the largest entry, plus 16x the oracle's own change under
@@ -136,6 +144,23 @@ def test_apply_solve_represent_cpos(which, request):
         err = float(np.abs(u[0] - ue).max() / np.abs(ue).max())
         say(f"[c>0 path] {which}: manufactured u error {err:.2e}, max |Im u| {np.abs(u[0].imag).max():.2e}")
         assert err < 1e-5
+
+
+def test_apply_cpos_both_bessel_ranges(ragged_hi):
+    """Applies over 1, 2 and 8 complex densities with k r up to about 15 (both ranges of the device
+    Bessel functions, and pairs of sources that straddle z = 8) against the oracle's dense matrix."""
+    from paper_2401_12501_amd import pmx
+    case = ragged_hi
+    x = case.prob.surface.x
+    kap = np.sqrt(case.prob.c / case.prob.a)
+    z = kap[None, :] * np.linalg.norm(x[:, None, :] - x[None, :, :], axis=2)
+    frac_large = float(np.mean(z > 8.0))
+    sig = random_density(case.prob.n, 11, seed=93) + 1j * random_density(case.prob.n, 11, seed=94)
+    y = case.op.apply(np.ascontiguousarray(sig.T), pmx.PMX_PREC_FP64_DIRECT).T
+    e = max_rel(y, case.A @ sig)
+    say(f"[c>0 hi] apply {e:.2e}, pairs with k r > 8: {frac_large:.2f}")
+    assert 0.1 < frac_large < 0.9
+    assert e <= 1e-12
 
 
 def test_sphere_eigenvalues_cpos_gpu(ctx):
