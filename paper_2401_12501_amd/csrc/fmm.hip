@@ -709,7 +709,7 @@ k_m2l16(Group<M2L16Args> g) {
     // NK steps of four source nodes from node kb on (a compile-time count, so the loop unrolls)
     auto run = [&](auto nk_tag, int kb) {
       constexpr int NK = decltype(nk_tag)::value;
-#pragma unroll 2
+#pragma unroll 1
       for (int ks = 0; ks < NK; ++ks) {
         const int m = kb + 4 * ks + kq;
         // with p^3 a multiple of 4 every node index is below p^3; otherwise the last step's
