@@ -45,32 +45,38 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 78.6, "fp32_valu_packed": 157.3, "fp32_m
 # (ellipsoid, 153,600 nodes, mixed path, 1 RHS; the M2L in the layout it runs in beside the
 # second stream, as in the timed region), scaled by what the counters read for a plain
 # 256 MiB device copy (FETCH_SIZE 131,088 KiB -> x2.0, WRITE_SIZE 262,144 KiB -> x1.0).  Each
-# record is tied to the kernel's source file; a different file means a changed kernel and the
-# traffic is reported as null (the key hashes the file's code without its comments).
+# record is tied to its kernel's source text (the definition in its file, comments removed); a
+# different text means a changed kernel and the traffic is reported as null.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC = {
-    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "388bb654748a8207",
+    "fmm_m2l": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "fn": "k_m2l", "sha": "d9444ab3830a46d6",
                 "kib": [("k_m2l", 12065.9, 372009.3)]},
-    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "388bb654748a8207",
+    "fmm_m2l_sum": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "fn": "k_m2l_reduce", "sha": "13d98ce94106f035",
                     "kib": [("k_m2l_reduce", 166728.6, 7382.5)]},
-    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "sha": "388bb654748a8207",
+    "fmm_p2p": {"src": "paper_2401_12501_amd/csrc/fmm.hip", "fn": "k_p2p", "sha": "eebd985a1eecaf25",
                 "kib": [("k_p2p", 46446.4, 9602.3)]},
-    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "sha": "f5adb6ce2f6cff51",
+    "near": {"src": "paper_2401_12501_amd/csrc/nearapply.hip", "fn": "k_near_combine", "sha": "dbbc8c35cbb2ac42",
              "kib": [("k_near_combine", 281884.5, 1266.4)]},
 }
 
 
-def code_hash(path: str) -> str:
-    """Hash of a source file's code: line comments, trailing spaces and blank lines removed, so
-    that editing a comment does not count as changing the kernel."""
+def code_hash(path: str, fn: str | None = None) -> str:
+    """Hash of source code with line comments, trailing spaces and blank lines removed (editing a
+    comment does not count as changing the kernel): the whole file, or with ``fn`` the definition of
+    that kernel (from its __global__ line to the closing brace in the first column)."""
     import hashlib
     import re
-    lines = []
     with open(path, encoding="utf-8") as fh:
-        for line in fh:
-            line = re.sub(r"//.*$", "", line.rstrip("\n")).rstrip()
-            if line:
-                lines.append(line)
+        src = fh.read().splitlines()
+    if fn is not None:
+        start = next(i for i, l in enumerate(src) if l.startswith("__global__") and f" {fn}(" in l)
+        end = next(i for i in range(start, len(src)) if src[i] == "}")
+        src = src[start:end + 1]
+    lines = []
+    for line in src:
+        line = re.sub(r"//.*$", "", line).rstrip()
+        if line:
+            lines.append(line)
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
@@ -79,7 +85,7 @@ def traffic_bytes(phase: str, n_rhs: int, k: int):
     rec = TRAFFIC.get(phase)
     if rec is None or n_rhs != 1 or k != 16:
         return None
-    if code_hash(os.path.join(ROOT, rec["src"])) != rec["sha"]:
+    if code_hash(os.path.join(ROOT, rec["src"]), rec.get("fn")) != rec["sha"]:
         return None
     return sum((f * FETCH_SCALE + w * WRITE_SCALE) * 1024.0 for _, f, w in rec["kib"])
 

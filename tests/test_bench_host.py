@@ -30,6 +30,19 @@ def test_code_hash_ignores_comments_only(bench, tmp_path):
     assert bench.code_hash(str(a)) != h0
 
 
+def test_code_hash_of_one_kernel(bench, tmp_path):
+    """With a kernel name the hash covers that kernel's definition only: editing another kernel of
+    the same file keeps it, editing this one changes it."""
+    a = tmp_path / "k.hip"
+    a.write_text("__global__ void k(float* x) {\n  x[0] = 1.0f;\n}\n\n__global__ void k2(float* x) {\n  x[1] = 0;\n}\n")
+    h0 = bench.code_hash(str(a), "k")
+    a.write_text("__global__ void k(float* x) {\n  x[0] = 1.0f;   // store\n}\n\n__global__ void k2(float* x) {\n"
+                 "  x[1] = 5;\n}\n")
+    assert bench.code_hash(str(a), "k") == h0
+    a.write_text("__global__ void k(float* x) {\n  x[0] = 3.0f;\n}\n\n__global__ void k2(float* x) {\n  x[1] = 5;\n}\n")
+    assert bench.code_hash(str(a), "k") != h0
+
+
 def test_traffic_scaling_and_null_rule(bench, tmp_path, monkeypatch):
     src = tmp_path / "k.hip"
     src.write_text("__global__ void k() {}\n")
