@@ -295,9 +295,10 @@ def serving(n_req: int, slots: int, loads, budget_bytes: int, n_cal: int = 64):
 # Operation count per ordered pair of the FP64 direct far field with c < 0 (the kernel's evaluation,
 # each add, mul, division, reciprocal square root, logarithm or exponential 1 flop, an FMA 2): the
 # geometry and the factored remainder 44, plus K0 and K1 of z = kappa r either by four degree-12
-# Horner polynomials of the ascending series for z <= 2 (111) or by two degree-22 Chebyshev
-# series (Clenshaw) times exp(-z) / sqrt(z) for z > 2 (147).
-C_PAIR_FLOPS = {"pair": 44, "series": 111, "chebyshev": 147}
+# Horner polynomials of the ascending series for z <= 2 (111, the "series" entry) or by the power
+# forms of two degree-22 interpolants in 4/z - 1 (Horner's rule) times exp(-z) / sqrt(z) for z > 2
+# (95, the "chebyshev" entry).
+C_PAIR_FLOPS = {"pair": 44, "series": 111, "chebyshev": 95}
 # The same count for c > 0 (complex kernel, one complex density): geometry, the factored remainder's
 # real and imaginary parts and the complex multiply-add 54, plus J0, J1, Y0, Y1 of z = k r either by
 # four degree-16 polynomials in z^2 (Horner's rule) and a logarithm for z <= 8 (142, the "series"

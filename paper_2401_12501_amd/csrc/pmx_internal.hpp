@@ -239,9 +239,9 @@ __device__ __forceinline__ double log_pair(double x) {
 //    each sum as a polynomial of degree 12 in t by Horner's rule (coefficients computed at
 //    compile time; truncation below 5e-18 at t = 1).  The cancellation in K0 near z = 2 costs
 //    about one decimal digit (relative error up to 4e-15).
-//  * z > 2: sqrt(z) e^z K_nu(z) is smooth in s = 2/z on (0, 1]; its Chebyshev series of degree 22
-//    in x = 4/z - 1 (coefficients by interpolation at the Chebyshev points at 40 digits,
-//    bessel_k_table.py) has relative error 1.2e-16, evaluated by Clenshaw's recurrence.
+//  * z > 2: sqrt(z) e^z K_nu(z) is smooth in s = 2/z on (0, 1]; its interpolant of degree 22 in
+//    x = 4/z - 1 (interpolation at the Chebyshev points at 40 digits, converted to the power form,
+//    bessel_k_table.py) has relative error 1.2e-16, evaluated by Horner's rule.
 constexpr double kEulerGamma = 0.57721566490153286061;
 
 struct KSeries {
@@ -263,27 +263,27 @@ constexpr KSeries make_kseries() {
   return r;
 }
 
-constexpr double kChebK0[23] = {
-    1.22015154103297774e+00, -3.14481013119645020e-02, 1.56988388573005332e-03,
-    -1.28495495816278017e-04, 1.39498137188765002e-05, -1.83175552271911953e-06,
-    2.76681363944501486e-07, -4.66048989768794783e-08, 8.57403401741422362e-09,
-    -1.69753450938905439e-09, 3.57739728140013962e-10, -7.95748924447235326e-11,
-    1.85594911494131028e-11, -4.51459788300317332e-12, 1.14034058718387776e-12,
-    -2.98009689462883721e-13, 8.03288997119513968e-14, -2.22751103352657940e-14,
-    6.34001023017130056e-15, -1.84839946836037540e-15, 5.50630089020145042e-16,
-    -1.66089941374907953e-16, 4.68034840052582055e-17};
-constexpr double kChebK1[23] = {
-    1.36031309524222133e+00, 1.03923736576817236e-01, -2.85781685962277921e-03,
-    1.95215518471351620e-04, -1.93619797416608301e-05, 2.40648494783721699e-06,
-    -3.50196060308781256e-07, 5.74108412545004947e-08, -1.03457624656780935e-08,
-    2.01504975519702721e-09, -4.19035475934172483e-10, 9.21831518759994310e-11,
-    -2.12996783841327002e-11, 5.13963967308577877e-12, -1.28917395985525712e-12,
-    3.34841963550466353e-13, -8.97670431956193934e-14, 2.47715195964445683e-14,
-    -7.01976576208568517e-15, 2.03849397498716266e-15, -6.05082562535566479e-16,
-    1.81931492334142224e-16, -5.11378840098631785e-17};
+constexpr double kPolyK0[23] = {
+    1.21859533851339052e+00, -3.10714618248898629e-02, 3.03289181027414315e-03,
+    -4.79769056735349661e-04, 9.95605474680700934e-05, -2.47352053744823634e-05,
+    7.00224489119246702e-06, -2.19116792521650616e-06, 7.42786224915629391e-07,
+    -2.68973007185193227e-07, 1.02925573280657489e-07, -4.10665802711522117e-08,
+    1.71318560067890199e-08, -8.00485151596186128e-09, 3.64970419674587604e-09,
+    -6.90944553209526845e-10, 2.39282475774540067e-10, -1.21546469253292140e-09,
+    6.69690967735319141e-10, 4.29782283193599083e-10, -2.51158362375080098e-10,
+    -1.74157926367135482e-10, 9.81540200885952561e-11};
+constexpr double kPolyK1[23] = {
+    1.36315189037134199e+00, 1.03349737753865606e-01, -5.56672988007330879e-03,
+    7.35724154874510560e-04, -1.39590219614627790e-04, 3.28438664438236949e-05,
+    -8.96120656800817468e-06, 2.73003069116461256e-06, -9.06715391779199444e-07,
+    3.23053491198630796e-07, -1.22000639091108527e-07, 4.81650114775029143e-08,
+    -1.99091691254213902e-08, 9.19183829361296321e-09, -4.15956404449566279e-09,
+    8.25400261129896233e-10, -2.91588972545863801e-10, 1.33858499774653138e-09,
+    -7.34780754419483894e-10, -4.67158267076234187e-10, 2.72604009952142169e-10,
+    1.90768996505765517e-10, -1.07243915727052585e-10};
 
 // The coefficients of bessel_k01 in one table: the four series (13 each), then the two
-// Chebyshev series (23 each).  (Staging the table in LDS for the direct sum, instead of the
+// interpolants' power forms (23 each).  (Staging the table in LDS for the direct sum, instead of the
 // register-resident constants, was measured no faster: 152 vs 150 ms on 153,600 nodes.)
 constexpr int kKTable = 4 * 13 + 2 * 23;
 struct KTable {
@@ -299,8 +299,8 @@ constexpr KTable make_ktable() {
     t.v[39 + k] = s.s1[k];
   }
   for (int k = 0; k < 23; ++k) {
-    t.v[52 + k] = kChebK0[k];
-    t.v[75 + k] = kChebK1[k];
+    t.v[52 + k] = kPolyK0[k];
+    t.v[75 + k] = kPolyK1[k];
   }
   return t;
 }
@@ -321,18 +321,6 @@ __device__ __forceinline__ double horner(C c, int o, double t) {
   return p;
 }
 
-template <int N, class C>
-__device__ __forceinline__ double clenshaw(C c, int o, double x) {
-  const double x2 = 2.0 * x;
-  double b1 = 0.0, b2 = 0.0;
-#pragma unroll
-  for (int k = N - 1; k >= 1; --k) {
-    const double b = fma(x2, b1, sconst(c[o + k]) - b2);
-    b2 = b1;
-    b1 = b;
-  }
-  return fma(x, b1, sconst(c[o]) - b2);
-}
 
 // c: the coefficient table (make_ktable's order), compile-time constants
 template <class C>
@@ -345,8 +333,8 @@ __device__ __forceinline__ void bessel_k01_t(double z, double& k0, double& k1, C
   } else {
     const double x = 4.0 / z - 1.0;
     const double e = exp(-z) * rsqrt(z);
-    k0 = clenshaw<23>(c, 52, x) * e;
-    k1 = clenshaw<23>(c, 75, x) * e;
+    k0 = horner<23>(c, 52, x) * e;
+    k1 = horner<23>(c, 75, x) * e;
   }
 }
 
@@ -391,32 +379,27 @@ __device__ __forceinline__ void bessel_k01_x2(const double (&z)[2], double (&k0)
       k1[m] = 1.0 / z[m] + L * (0.5 * z[m] * i1[m]) - 0.25 * z[m] * s1[m];
     }
   } else {
-    double x2[2], a1[2], a2[2], b1[2], b2[2];
+    double x[2], p0[2], p1[2];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      x2[m] = 2.0 * (4.0 / z[m] - 1.0);
-      a1[m] = a2[m] = b1[m] = b2[m] = 0.0;
+      x[m] = 4.0 / z[m] - 1.0;
+      p0[m] = kt.v[52 + 22];
+      p1[m] = kt.v[75 + 22];
     }
 #pragma unroll
-    for (int k = 22; k >= 1; --k) {
+    for (int k = 21; k >= 0; --k) {
       const double c0 = sconst(kt.v[52 + k]), c1 = sconst(kt.v[75 + k]);
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
-        const double a = fma(x2[m], a1[m], c0 - a2[m]);
-        a2[m] = a1[m];
-        a1[m] = a;
-        const double b = fma(x2[m], b1[m], c1 - b2[m]);
-        b2[m] = b1[m];
-        b1[m] = b;
+        p0[m] = fma(p0[m], x[m], c0);
+        p1[m] = fma(p1[m], x[m], c1);
       }
     }
-    const double c0 = sconst(kt.v[52]), c1 = sconst(kt.v[75]);
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const double x = 0.5 * x2[m];
       const double e = exp(-z[m]) * rsqrt(z[m]);
-      k0[m] = fma(x, a1[m], c0 - a2[m]) * e;
-      k1[m] = fma(x, b1[m], c1 - b2[m]) * e;
+      k0[m] = p0[m] * e;
+      k1[m] = p1[m] * e;
     }
   }
 }

@@ -1,11 +1,11 @@
 """The device routines for K0 and K1 (bessel_k01) and for J0, J1, Y0, Y1 (bessel_jy01) in
 pmx_internal.hpp, replayed on the host.
 
-The Chebyshev coefficient tables are read from the header and the series coefficients are built the
-way make_kseries builds them; the evaluation follows the routine step by step (Horner's rule in
-t = z^2/4 for z <= 2, Clenshaw's recurrence in x = 4/z - 1 times exp(-z)/sqrt(z) above).  Against
-mpmath at 30 digits the relative error stays below 5e-15 from z = 1e-12 to 60, and the tables
-are those bessel_k_table.py prints (degree 22, checked by the script itself).
+The interpolants' power-form tables are read from the header and the series coefficients are built
+the way make_kseries builds them; the evaluation follows the routine step by step (Horner's rule in
+t = z^2/4 for z <= 2, and in x = 4/z - 1 times exp(-z)/sqrt(z) above).  Against mpmath at 30
+digits the relative error stays below 5e-15 from z = 1e-12 to 60, and the tables are those
+bessel_k_table.py prints (degree 22, checked by the script itself).
 """
 import math
 import os
@@ -49,13 +49,6 @@ def horner(c, t):
     return p
 
 
-def clenshaw(c, x):
-    b1 = b2 = 0.0
-    for cj in reversed(c[1:]):
-        b1, b2 = 2.0 * x * b1 + (cj - b2), b1
-    return x * b1 + (c[0] - b2)
-
-
 def k01(z, S, C0, C1):
     if z <= 2.0:
         t = 0.25 * z * z
@@ -64,12 +57,12 @@ def k01(z, S, C0, C1):
         return -L * horner(i0, t) + horner(s0, t), 1.0 / z + L * (0.5 * z * horner(i1, t)) - 0.25 * z * horner(s1, t)
     x = 4.0 / z - 1.0
     e = math.exp(-z) / math.sqrt(z)
-    return clenshaw(C0, x) * e, clenshaw(C1, x) * e
+    return horner(C0, x) * e, horner(C1, x) * e
 
 
 def test_device_k01_against_mpmath():
     mp.mp.dps = 30
-    S, C0, C1 = series(), table("kChebK0"), table("kChebK1")
+    S, C0, C1 = series(), table("kPolyK0"), table("kPolyK1")
     worst = [0.0, 0.0]
     zs = np.concatenate([np.logspace(-12, math.log10(2.0), 500), np.linspace(1.95, 2.05, 101),
                          np.geomspace(2.0, 60.0, 500)])
@@ -82,12 +75,12 @@ def test_device_k01_against_mpmath():
 
 
 def test_tables_match_the_generator():
-    """The header's tables are the generator's output (degree 22: 23 coefficients each, leading
-    coefficients sqrt(pi/2)-like: g_nu tends to sqrt(pi/2) = 1.2533 as z -> infinity, x -> -1)."""
-    for name in ("kChebK0", "kChebK1"):
+    """The header's tables are the generator's output (degree 22: 23 power-form coefficients each;
+    g_nu tends to sqrt(pi/2) = 1.2533 as z -> infinity, x -> -1)."""
+    for name in ("kPolyK0", "kPolyK1"):
         c = table(name)
         assert len(c) == 23
-        val_at_infinity = sum(cj * (-1) ** j for j, cj in enumerate(c))   # x = -1: T_j(-1) = (-1)^j
+        val_at_infinity = sum(cj * (-1) ** j for j, cj in enumerate(c))   # x = -1
         assert abs(val_at_infinity - math.sqrt(math.pi / 2)) < 1e-15
 
 
