@@ -572,7 +572,7 @@ void direct_c_all(pmx_operator* op, const ApplyScratch* sc, int kernel, int n_rh
 
 void direct64_all(const std::vector<pmx_operator*>& ops_in, const std::vector<const ApplyScratch*>& scs_in,
                   int n_rhs, hipStream_t st) {
-  // operators with c < 0 take their own kernel, one operator at a time
+  // operators with c != 0 take their own kernels, one operator at a time
   std::vector<pmx_operator*> ops;
   std::vector<const ApplyScratch*> scs;
   for (size_t k = 0; k < ops_in.size(); ++k) {
