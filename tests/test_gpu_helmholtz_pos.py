@@ -234,3 +234,32 @@ def test_cpos_largest_call(ragged):
     e = max(float(np.abs(y[[0, 1023]][k] - ref[k]).max() / np.abs(ref[k]).max()) for k in range(2))
     say(f"[c>0 1024] sampled columns vs oracle {e:.2e}")
     assert e <= 1e-12
+
+
+def test_cpos_multi_rhs_solve_and_warm_start(ragged):
+    """Three right-hand sides solved together (GMRES in lockstep on the real systems of size 2N): a
+    real one and two complex ones, each column against the oracle's dense solve and against its own
+    single-column solve; then a warm start from the solution, which returns it after at most one
+    iteration (tolerance 1e-12 there)."""
+    from paper_2401_12501_amd import pmx
+    case = ragged
+    N = case.prob.n
+    rng = np.random.default_rng(96)
+    F = np.stack([case.prob.f[:, 0], rng.normal(size=N) + 1j * rng.normal(size=N),
+                  1j * case.prob.f[:, 0] + rng.normal(size=N)], axis=0)
+    o = pmx.pmx_default_options()
+    o.gmres_tol = 1e-14
+    s, u, info = case.op.solve(F.copy(), o, want_u=True)
+    ref = np.linalg.solve(case.A, F.T).T
+    u_ref = case.orc.represent(ref.T, case.blocks).T
+    errs = [float(np.abs(s[k] - ref[k]).max() / np.abs(ref[k]).max()) for k in range(3)]
+    errs_u = [float(np.abs(u[k] - u_ref[k]).max() / np.abs(u_ref[k]).max()) for k in range(3)]
+    say(f"[c>0 3 rhs] sigma {max(errs):.2e}, u {max(errs_u):.2e}, iters {[i.iters_total for i in info]}")
+    assert max(errs) <= 1e-12 and max(errs_u) <= 1e-12
+    s1, _, _ = case.op.solve(F[1:2].copy(), o)
+    assert np.abs(s1[0] - s[1]).max() <= 1e-13 * np.abs(s[1]).max()
+    o2 = pmx.pmx_default_options()
+    o2.gmres_tol = 1e-12   # the solution's residual (about 1e-14) is below this: no iteration is needed
+    s2, _, info2 = case.op.solve(F.copy(), o2, sigma0=s)
+    assert all(i.iters_total <= 1 for i in info2), [i.iters_total for i in info2]
+    assert np.abs(s2 - s).max() <= 1e-13 * np.abs(s).max()
