@@ -163,7 +163,7 @@ PMX_API pmx_status pmx_operator_create(pmx_surface* s, const double* a, const do
  * With c > 0 the operator is complex (pmx_operator_is_complex): every vector that pmx_apply, pmx_solve
  * and pmx_represent take or return holds 2N doubles per right-hand side, the real parts of the N node
  * values followed by their imaginary parts (n_rhs counts complex vectors; right-hand side r starts
- * at offset 2 r N); GMRES runs on the equivalent real system of size 2N, and info has n_rhs entries.
+ * at offset 2 r N); GMRES runs in complex arithmetic, and info has n_rhs entries.
  * Only the FP64 direct far field is available (PMX_PREC_FP64_DIRECT for pmx_apply, pmx_solve and
  * the allocation-free apply; other precisions give INVALID): the FMM's translation operators need a
  * kernel of x - y alone up to a per-source factor, while here the wavenumber sqrt(|c|/a) changes from

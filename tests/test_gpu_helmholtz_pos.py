@@ -237,7 +237,7 @@ def test_cpos_largest_call(ragged):
 
 
 def test_cpos_multi_rhs_solve_and_warm_start(ragged):
-    """Three right-hand sides solved together (GMRES in lockstep on the real systems of size 2N): a
+    """Three right-hand sides solved together (complex GMRES in lockstep): a
     real one and two complex ones, each column against the oracle's dense solve and against its own
     single-column solve; then a warm start from the solution, which returns it after at most one
     iteration (tolerance 1e-12 there)."""
