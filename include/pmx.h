@@ -203,9 +203,10 @@ PMX_API pmx_status pmx_apply(pmx_operator* op, int precision, int n_rhs, const d
  * Scratch needed: about 8 (n_rhs (N (1 + c) + N / 256) + N (3 + g + 1)) bytes, with c the
  * direct sum's source chunks (between 1 and 64: 7 for 153,600 nodes, 1 from 1,048,576) and g the
  * largest right-hand-side group (1, 2, 4, 8 or 16); for example up to 4 densities at 153,600 nodes.
- * Complex operators (c > 0) are not taken.
- * Errors: INVALID (null or host arrays, n_rhs out of range, a complex operator), TOO_LARGE (scratch
- * above the maximum), DEVICE. */
+ * A complex operator (c > 0) takes n_rhs complex densities, 2N doubles each (real parts, then
+ * imaginary parts, as for pmx_apply), and needs the scratch of 2 n_rhs real columns.
+ * Errors: INVALID (null or host arrays, n_rhs out of range), TOO_LARGE (scratch above the maximum),
+ * DEVICE. */
 #define PMX_NOALLOC_SCRATCH_BYTES (64ull << 20)
 PMX_API pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, double* y, void* stream);
 

@@ -423,11 +423,11 @@ pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, d
   return guarded([&] {
     PMX_REQUIRE(op && sigma && y, PMX_ERR_INVALID, "null argument");
     PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
-    PMX_REQUIRE(!op->cplx(), PMX_ERR_INVALID, "the allocation-free apply takes real operators only (c <= 0)");
     const int dev = op->s->ctx->c.device;
     PMX_HIP(hipSetDevice(dev));
     const int64_t N = op->s->g.N;
-    const size_t need = direct64_scratch_doubles(N, n_rhs);
+    const int nc = op->cols(n_rhs);   // real columns (a complex operator: two per density)
+    const size_t need = direct64_scratch_doubles(N, nc);
     if (need > kScratchDoubles)
       throw Error(PMX_ERR_TOO_LARGE, "the allocation-free apply needs " + std::to_string(need * sizeof(double)) +
                                          " bytes of scratch; the static scratch holds " +
@@ -436,7 +436,7 @@ pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, d
     require_device_array(y, dev, "y");
     double* base = scratch_ptr(dev);
     // carve the buffers in the order and rounding direct64_scratch_doubles counts them
-    const size_t nr = (size_t)n_rhs, nb = (size_t)((N + 255) / 256);
+    const size_t nr = (size_t)nc, nb = (size_t)((N + 255) / 256);
     auto up = [](size_t n) { return (n + 31) / 32 * 32; };
     ApplyScratch sc;
     size_t at = 0;
@@ -446,15 +446,15 @@ pmx_status pmx_apply_noalloc(pmx_operator* op, int n_rhs, const double* sigma, d
     at += up(nr * nb);
     sc.ssum = base + at;
     at += up(nr);
-    const int g = n_rhs >= 16 ? 16 : (n_rhs >= 8 ? 8 : (n_rhs >= 4 ? 4 : (n_rhs >= 2 ? 2 : 1)));
+    const int g = nc >= 16 ? 16 : (nc >= 8 ? 8 : (nc >= 4 ? 4 : (nc >= 2 ? 2 : 1)));
     sc.rows = base + at;
     at += up((size_t)((4 + g + 1) / 2) * 2 * N);
     sc.part = base + at;
     hipStream_t st = (hipStream_t)stream;
     const std::vector<ApplyJob> jobs{ApplyJob{op, sigma, y, &sc}};
-    source_prep_batch(jobs, n_rhs, false, st);
-    far_direct64_batch(jobs, n_rhs, st);
-    near_combine_batch(jobs, n_rhs, st);
+    source_prep_batch(jobs, nc, false, st);
+    far_direct64_batch(jobs, nc, st);
+    near_combine_batch(jobs, nc, st);
   });
 }
 

@@ -310,8 +310,10 @@ class Operator:
 
     def apply_noalloc(self, sigma, out=None, check: bool = True):
         """pmx_apply_noalloc: y = A sigma (FP64 direct far field) with the library's static scratch;
-        sigma and out are device tensors of shape (n_rhs, N).  Returns out (check=True) or the status."""
-        n_rhs = self._rhs(sigma)
+        sigma and out are device tensors of shape (n_rhs, N), or for a complex operator float64 tensors
+        of shape (n_rhs, 2, N) in the library's layout (real parts, then imaginary parts: nothing is
+        converted, so nothing is allocated).  Returns out (check=True) or the status."""
+        n_rhs = sigma.shape[0] if self.complex else self._rhs(sigma)
         if out is None:
             out = sigma.new_empty(sigma.shape)
         ptrs, kind, stream, keep = _marshal(sigma, out)

@@ -6,7 +6,8 @@ equal pmx_apply's bit for bit.  Two calls in a row, the second on a smaller inpu
 operator, fewer nodes and right-hand sides), check that what the first call left in the shared
 array does not leak into the second.  The operator used only through the allocation-free call
 must hold no more device memory afterwards than before, and the library must refuse inputs
-whose scratch exceeds the array and host arrays (before any device work).
+whose scratch exceeds the array and host arrays (before any device work).  A complex operator
+(c > 0) takes its densities in the library's layout of 2N doubles each.
 """
 import sys
 
@@ -49,6 +50,36 @@ def test_noalloc_matches_apply_twice():
         # a repeat on the same operator gives the same bits
         assert torch.equal(op_na.apply_noalloc(sig), y_ref)
         say(f"[noalloc] {prob.name}: identical to pmx_apply (FP64 direct)")
+
+
+def test_noalloc_complex_matches_apply_twice():
+    """A complex operator (c > 0): densities in the library's layout (n_rhs, 2, N), real parts then
+    imaginary parts; the allocation-free apply equals pmx_apply bit for bit, on two calls in a row,
+    the second with fewer nodes and densities."""
+    import torch
+    from paper_2401_12501_amd import pmx
+    from paper_2401_12501_amd.inputs import helmholtz_ellipsoid_problem, helmholtz_sphere_problem
+    ctx = pmx.Context(0)
+    cases = [(helmholtz_sphere_problem(k=2, q=8, positive=True), 3, 61),
+             (helmholtz_ellipsoid_problem(k=1, q=7, positive=True), 1, 62)]   # 1,536 then 294 nodes
+    for prob, n_rhs, seed in cases:
+        say(f"[noalloc c>0] {prob.name}: N={prob.n}, {n_rhs} complex densities")
+        surf = pmx.Surface.from_inputs(ctx, prob.surface)
+        op_ref = pmx.Operator(surf, prob.a, prob.grad_a, c=prob.c)
+        op_na = pmx.Operator(surf, prob.a, prob.grad_a, c=prob.c)
+        assert op_na.complex
+        d = np.stack([random_density(prob.n, n_rhs, seed=seed).T, random_density(prob.n, n_rhs, seed=seed + 1).T],
+                     axis=1)
+        sig = torch.tensor(np.ascontiguousarray(d), device="cuda:0")
+        bytes_before = op_na.stats().device_bytes
+        y_na = op_na.apply_noalloc(sig)
+        torch.cuda.synchronize()
+        assert op_na.stats().device_bytes == bytes_before
+        y_ref = op_ref.apply_planar(sig, pmx.PMX_PREC_FP64_DIRECT)
+        torch.cuda.synchronize()
+        assert torch.equal(y_na, y_ref), f"max diff {(y_na - y_ref).abs().max().item():.3e}"
+        assert torch.equal(op_na.apply_noalloc(sig), y_ref)
+        say(f"[noalloc c>0] {prob.name}: identical to pmx_apply (FP64 direct)")
 
 
 def test_noalloc_rejections():
