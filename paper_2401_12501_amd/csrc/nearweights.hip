@@ -181,7 +181,7 @@ __device__ inline double remainder_c_dev(const Target& T, const double* y, doubl
   const double ir = rsqrt(rr), rn = rr * ir;
   const double kap = sqrt(-c_s * inv_as);
   double k0, k1;
-  bessel_k01_compact(kap * rn, k0, k1);
+  bessel_k01(kap * rn, k0, k1);
   const double nr = T.n[0] * r0 + T.n[1] * r1 + T.n[2] * r2;
   const double gr = T.g[0] * r0 + T.g[1] * r1 + T.g[2] * r2;
   const double snr = nr * ir;   // n.r / r
@@ -194,7 +194,7 @@ __device__ inline double parametrix_c_dev(const Target& T, const double* y, doub
   const double r0 = T.x[0] - y[0], r1 = T.x[1] - y[1], r2 = T.x[2] - y[2];
   const double rn = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
   double k0, k1;
-  bessel_k01_compact(sqrt(-c_s * inv_as) * rn, k0, k1);
+  bessel_k01(sqrt(-c_s * inv_as) * rn, k0, k1);
   return -k0 * 0.15915494309189533577 * inv_as;   // -K0(kappa r) / (2 pi a)
 }
 

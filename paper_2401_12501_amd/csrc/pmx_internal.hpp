@@ -404,58 +404,6 @@ __device__ __forceinline__ void bessel_k01_x2(const double (&z)[2], double (&k0)
   }
 }
 
-// The same K0, K1 for kernels short of registers (the local-rule weights): the series summed by
-// its term recurrence (15 terms) for z <= 2, and for z > 2 the integral
-// e^z K_nu(z) = int_0^inf exp(-z (cosh s - 1)) cosh(nu s) ds (A&S 9.6.24) with u = sqrt(2z) sinh(s/2):
-//   e^z K0 = sqrt(2/z) int_0^inf e^{-u^2} (1 + u^2/(2z))^{-1/2} du,
-//   e^z K1 = sqrt(2/z) int_0^inf e^{-u^2} (1 + u^2/z) (1 + u^2/(2z))^{-1/2} du,
-// by the trapezoidal rule, which converges exponentially for these analytic integrands (Trefethen
-// and Weideman, SIAM Review 56, 2014): step 0.3 on [0, 6.9] (24 nodes, weights 0.3 exp(-u_j^2),
-// half at u = 0, generated at 30 digits).  Relative error up to 6e-15.  It keeps about 30
-// constants live instead of 98, which the weights kernels need (with bessel_k01 the self-rule
-// kernel spilled 105 registers and took 1.8x as long).
-__device__ __forceinline__ void bessel_k01_compact(double z, double& k0, double& k1) {
-  if (z <= 2.0) {
-    const double t = 0.25 * z * z;
-    double term0 = 1.0, term1 = 1.0, i0 = 0.0, i1 = 0.0, s0 = 0.0, s1 = 0.0, hk = 0.0;
-#pragma unroll
-    for (int k = 0; k < 15; ++k) {
-      const double hk1 = hk + 1.0 / (double)(k + 1);
-      i0 += term0;
-      i1 += term1;
-      s0 = fma(hk, term0, s0);
-      s1 = fma(hk + hk1, term1, s1);
-      hk = hk1;
-      term0 *= t * (1.0 / ((double)(k + 1) * (double)(k + 1)));
-      term1 *= t * (1.0 / ((double)(k + 1) * (double)(k + 2)));
-    }
-    const double L = 0.5 * log_pair(t) + kEulerGamma;   // ln(z/2) + gamma
-    k0 = fma(-L, i0, s0);
-    k1 = 1.0 / z + L * (0.5 * z * i1) - 0.25 * z * s1;
-  } else {
-    constexpr double w[24] = {
-        0.15, 0.27417935558136845602, 0.20930289782130931716,
-        0.13345741986688234034, 0.071078327604636527017, 0.031619767368559301035,
-        0.011749168529696122122, 0.0036465534989744811645, 0.00094533347953333216735,
-        0.00020469841582691298489, 0.000037022941226003864849, 0.0000055931226994550491246,
-        7.057725600029318768e-7, 7.4387880541350888885e-8, 6.5488733853764376273e-9,
-        4.815684165556834826e-10, 2.9578516727974524722e-11, 1.5174758228531379705e-12,
-        6.5027066478568858269e-14, 2.3275206227088211402e-15, 6.9585684907307081649e-17,
-        1.737693865618457377e-18, 3.624546059699920715e-20, 6.3148199350192033368e-22};
-    const double invz = 1.0 / z, inv2z = 0.5 * invz;
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int j = 0; j < 24; ++j) {
-      const double u2 = 0.09 * (double)(j * j);
-      const double r = rsqrt(fma(u2, inv2z, 1.0));
-      s0 = fma(w[j], r, s0);
-      s1 = fma(w[j] * r, fma(u2, invz, 1.0), s1);
-    }
-    const double c = sqrt(2.0 * invz) * exp(-z);
-    k0 = c * s0;
-    k1 = c * s1;
-  }
-}
 
 // Bessel functions J0, J1, Y0, Y1 of a real argument z > 0 (FP64): the Green's function of
 // (a Delta + c) G = delta with c > 0 is the complex G = -(i / 4a) H0(k r), k = sqrt(c / a), with
