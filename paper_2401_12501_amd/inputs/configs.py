@@ -12,6 +12,9 @@ star   r = 1 + 0.25 sum_8 w_k Y_k (1 <= l <= 4, w ~ U(-1,1)), cube-sphere
 torus  wobbly torus R = 1, r = 0.4 (1 + 0.2 cos 5 theta sin 3 phi), 256 x 128
        patches, q=8 (2,097,152 nodes); a = 1 + 0.5 tanh(sin 3 x1); 16 RHS
 serve  request stream: sphere / random-axis ellipsoid / torus, 2e3..2e5 nodes
+edge   the paper's wavy torus cut to the band 4 pi / 3 < u < 2 pi (17 x 18 patches, q=8,
+       19,584 nodes) and its two boundary circles, 200 equispaced samples each;
+       a = 1 or exp(0.3 x1 x2); boundary density mu = exp(x1)
 =====  ==========================================================================
 
 Every builder takes a size knob so that tests can run the same family at
@@ -26,12 +29,12 @@ import numpy as np
 import torch
 
 from . import fields as F
-from .surfaces import Surface, cube_sphere, real_sph_harm_cartesian, torus
+from .surfaces import Surface, cube_sphere, real_sph_harm_cartesian, torus, torus_boundary_curve
 
 __all__ = [
     "Problem", "sphere_problem", "ellipsoid_problem", "star_problem", "wobbly_torus_problem",
     "wavy_torus_problem", "helmholtz_sphere_problem", "helmholtz_ellipsoid_problem", "serving_requests",
-    "random_density",
+    "random_density", "EdgeSamples", "wavy_torus_piece_problem",
 ]
 
 
@@ -167,6 +170,58 @@ def wavy_torus_problem(n_u: int = 51, n_v: int = 18, q: int = 8, seed: int = 5) 
     a, ga = F.eval_field(F.a_const(1.0), s.x)
     sigma = s.x[:, 0] + np.random.default_rng(seed).normal(size=s.n)
     return Problem(s, a, ga, sigma[:, None].copy(), name=f"wavy_torus_{n_u}x{n_v}_q{q}", meta={"sigma": sigma})
+
+
+@dataclass
+class EdgeSamples:
+    """Equispaced samples of the closed boundary curves of an open surface, curve after curve:
+    curve k owns rows [offsets[k], offsets[k + 1]), sample j of a curve of n samples sits at
+    t = 2 pi j / n of its periodic parameterization.  x, xt (= dx/dt) and d (the surface map's
+    derivative across the curve, pointing out of the surface) are (M, 3); a (M,) and grad_a (M, 3,
+    ambient) are the coefficient there; mu (M, n_rhs) is a boundary density."""
+
+    x: np.ndarray
+    xt: np.ndarray
+    d: np.ndarray
+    a: np.ndarray
+    grad_a: np.ndarray
+    mu: np.ndarray
+    offsets: np.ndarray
+
+    @property
+    def m(self) -> int:
+        return self.x.shape[0]
+
+
+def wavy_torus_piece_problem(n_u: int = 17, n_v: int = 18, q: int = 8, n_edge=200, variable_a: bool = False,
+                             n_rhs: int = 1, seed: int = 7) -> Problem:
+    """The paper's wavy torus (``wavy_torus_problem``'s map) restricted to the band 4 pi / 3 < u < 2 pi
+    (the open surface of Section 7.5), n_u x n_v patches (17 x 18 x 8 x 8 = 19,584 nodes by default:
+    the band's third of the 51 x 18 closed surface), and its two boundary circles u = 4 pi / 3 and
+    u = 2 pi with ``n_edge`` samples each (an int, or one count per curve).  a = 1 (the
+    Laplace-Beltrami problem) or exp(0.3 x1 x2).  The boundary density is mu = exp(x1) in column 0
+    (Section 7.5's edge-quadrature test) and seeded N(0, 1) values in the other columns; it is in
+    ``meta["edge"]`` (EdgeSamples), with f = exp(x1) at the nodes."""
+    Rf = lambda th, ph: 3.0 + 0.6 * torch.cos(5 * th)
+    rf = lambda th, ph: 1.0 + 0.0 * th
+    band = (4 * math.pi / 3, 2 * math.pi)
+    s = torus(n_u, n_v, q, R=Rf, r=rf, name="wavy_torus_piece", theta_range=band)
+    fa = F.a_exp_xy if variable_a else F.a_const(1.0)
+    a, ga = F.eval_field(fa, s.x)
+    counts = [n_edge, n_edge] if isinstance(n_edge, int) else list(n_edge)
+    curves = [torus_boundary_curve(band[0], counts[0], -1, R=Rf, r=rf),
+              torus_boundary_curve(band[1], counts[1], +1, R=Rf, r=rf)]
+    x = np.concatenate([c["x"] for c in curves])
+    ea, ega = F.eval_field(fa, x)
+    mu = np.empty((x.shape[0], n_rhs))
+    mu[:, 0] = np.exp(x[:, 0])
+    if n_rhs > 1:
+        mu[:, 1:] = np.random.default_rng(seed).normal(size=(x.shape[0], n_rhs - 1))
+    edge = EdgeSamples(x, np.concatenate([c["xt"] for c in curves]), np.concatenate([c["d"] for c in curves]),
+                       ea, ega, mu, np.array([0, counts[0], counts[0] + counts[1]], dtype=np.int64))
+    f = np.exp(s.x[:, 0])[:, None].copy()
+    name = f"wavy_torus_piece_{n_u}x{n_v}_q{q}_e{counts[0]}" + ("_vara" if variable_a else "")
+    return Problem(s, a, ga, f, name=name, meta={"edge": edge})
 
 
 def serving_requests(n_requests: int = 256, seed: int = 3, n_min: float = 2e3, n_max: float = 2e5, q: int = 8):

@@ -15,7 +15,8 @@ Surfaces (all outward oriented, u x v pointing out of the enclosed volume):
 * ``cube_sphere``: equiangular gnomonic cube-sphere, 6 k^2 patches, optionally
   scaled per axis (ellipsoid), radially deformed (star shape) and rotated.
 * ``torus``: n_theta x n_phi patches in (toroidal, poloidal) angle, with an
-  optional angle-dependent tube radius (wobbly torus).
+  optional angle-dependent tube radius (wobbly torus), whole or a band of toroidal angle.
+* ``torus_boundary_curve``: samples of a poloidal circle bounding such a band.
 """
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ import numpy as np
 import torch
 from torch.func import jvp
 
-__all__ = ["Surface", "gl_nodes", "cube_sphere", "torus", "real_sph_harm_cartesian"]
+__all__ = ["Surface", "gl_nodes", "cube_sphere", "torus", "torus_boundary_curve", "real_sph_harm_cartesian"]
 
 
 @dataclass
@@ -133,12 +134,15 @@ def cube_sphere(k: int, q: int, axes=(1.0, 1.0, 1.0), radial=None, rotation=None
     return Surface(name, n_patches, q, *arrs, meta={"k": k, "axes": tuple(axes)})
 
 
-def torus(n_theta: int, n_phi: int, q: int, R=1.0, r=0.4, name: str = "torus") -> Surface:
+def torus(n_theta: int, n_phi: int, q: int, R=1.0, r=0.4, name: str = "torus",
+          theta_range: tuple[float, float] | None = None) -> Surface:
     """Torus with patches in (theta toroidal, phi poloidal).
 
     ``R`` and ``r`` are constants or torch functions of (theta, phi).
     x = ((R + r cos phi) cos theta, (R + r cos phi) sin theta, r sin phi);
-    (u, v) <-> (theta, phi) gives the outward orientation.
+    (u, v) <-> (theta, phi) gives the outward orientation.  ``theta_range`` = (theta0, theta1)
+    covers only that band of toroidal angle (an open surface bounded by the two poloidal circles
+    theta = theta0 and theta = theta1); None covers the whole torus.
     """
     n_patches = n_theta * n_phi
     pid, u, v = _reference_grid(n_patches, q)
@@ -146,7 +150,10 @@ def torus(n_theta: int, n_phi: int, q: int, R=1.0, r=0.4, name: str = "torus") -
     ip = (pid % n_phi).to(torch.float64)
 
     def fmap(uu, vv):
-        th = 2 * math.pi * (it + (uu + 1) / 2) / n_theta
+        if theta_range is None:
+            th = 2 * math.pi * (it + (uu + 1) / 2) / n_theta
+        else:
+            th = theta_range[0] + (theta_range[1] - theta_range[0]) * (it + (uu + 1) / 2) / n_theta
         ph = 2 * math.pi * (ip + (vv + 1) / 2) / n_phi
         rr = r(th, ph) if callable(r) else r * torch.ones_like(th)
         RR = R(th, ph) if callable(R) else R
@@ -154,7 +161,35 @@ def torus(n_theta: int, n_phi: int, q: int, R=1.0, r=0.4, name: str = "torus") -
         return torch.stack([ring * torch.cos(th), ring * torch.sin(th), rr * torch.sin(ph)], dim=1)
 
     arrs = _derivatives(fmap, u, v)
-    return Surface(name, n_patches, q, *arrs, meta={"n_theta": n_theta, "n_phi": n_phi})
+    meta = {"n_theta": n_theta, "n_phi": n_phi}
+    if theta_range is not None:
+        meta["theta_range"] = tuple(theta_range)
+    return Surface(name, n_patches, q, *arrs, meta=meta)
+
+
+def torus_boundary_curve(theta0: float, n: int, side: int, R=1.0, r=0.4) -> dict:
+    """n equispaced samples t_j = 2 pi j / n of the poloidal circle theta = theta0 of the torus map
+    of ``torus`` (t = phi, a smooth periodic parameterization of a boundary curve of a theta band).
+
+    Returns the position ``x`` = y(theta0, t_j), its derivative along the curve ``xt`` = dy/dphi and
+    ``d`` = side * dy/dtheta, the map's derivative across the curve, pointing out of the band for
+    side = +1 at its upper end (theta0 = theta1) and side = -1 at its lower end.  All (n, 3), exact to
+    rounding; the conormal and the arc-length element are left to the method.
+    """
+    t = torch.arange(n, dtype=torch.float64) * (2 * math.pi / n)
+    th0 = torch.full_like(t, float(theta0))
+
+    def fmap(th, ph):
+        rr = r(th, ph) if callable(r) else r * torch.ones_like(th)
+        RR = R(th, ph) if callable(R) else R
+        ring = RR + rr * torch.cos(ph)
+        return torch.stack([ring * torch.cos(th), ring * torch.sin(th), rr * torch.sin(ph)], dim=1)
+
+    one = torch.ones_like(t)
+    x = fmap(th0, t)
+    xt = jvp(lambda w: fmap(th0, w), (t,), (one,))[1]
+    xth = jvp(lambda w: fmap(w, t), (th0,), (one,))[1]
+    return {"x": x.numpy().copy(), "xt": xt.numpy().copy(), "d": (side * xth).numpy().copy()}
 
 
 def _legendre_deriv_coeffs(l: int, m: int) -> np.ndarray:
