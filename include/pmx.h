@@ -54,6 +54,7 @@ typedef struct pmx_ctx pmx_ctx;
 typedef struct pmx_surface pmx_surface;
 typedef struct pmx_operator pmx_operator;
 typedef struct pmx_server pmx_server;
+typedef struct pmx_edge pmx_edge;
 
 enum {
   PMX_OK = 0,
@@ -301,6 +302,51 @@ PMX_API pmx_status pmx_operator_export_near_imag(pmx_operator* op, double* Ci, d
 /* *out = 1 for a complex operator (built with c > 0: vectors of 2N doubles), 0 otherwise.
  * Errors: INVALID (null argument). */
 PMX_API pmx_status pmx_operator_is_complex(pmx_operator* op, int* out);
+
+/* ---------------------------------------------------------------- open surfaces: edge operators
+ * Section 5 solves the problem on an open surface Gamma with Neumann or Dirichlet data on its
+ * boundary gamma through a second density mu on gamma.  Four operators map mu to the surface nodes:
+ *   PMX_EDGE_K: K_gamma[mu](x) = int_gamma K(x, x') mu ds          (eq:BC_rep, the Neumann u)
+ *   PMX_EDGE_N: N_gamma[mu](x) = int_gamma nu . grad'_G K mu ds     (eq:DirichletRep, the Dirichlet u)
+ *   PMX_EDGE_R: R_gamma[mu](x) = int_gamma R(x, x') mu ds          (eq:NeuBVPsystem, Lemma lem:surf_term)
+ *   PMX_EDGE_T: T_gamma[mu](x) = int_gamma nu . grad'_G R mu ds     (eq:DirBVPsystem, Lemma lem:Dirichlet_surf_term)
+ * nu is the unit conormal at x' (tangent to Gamma, normal to gamma, out of Gamma); the primed gradient
+ * acts on the source point x', through r = x - x' and through a(x') in K(x, x') = log r / (2 pi a(x')).
+ * Discretization (Section 6.1.4): every quantity sampled on a curve is replaced by its trigonometric
+ * interpolant at m times as many equispaced points, and the trapezoid rule runs there.  Only the
+ * c = 0 operators (variable a, no advection) are provided. */
+enum { PMX_EDGE_K = 0, PMX_EDGE_N = 1, PMX_EDGE_R = 2, PMX_EDGE_T = 3 };
+
+/* Boundary curves for the edge operators.  n_curves (1..64) closed curves, curve k sampled at
+ * n_samples[k] (>= 3) equispaced values t_j = 2 pi j / n_k of a smooth periodic parameter t; the M
+ * samples are stored curve after curve.  Per sample (row-major M x 3 arrays, M arrays for a): the
+ * position x, its derivative xt = dx/dt, a direction d tangent to the surface, pointing out of it
+ * and not along the curve (e.g. the surface map's derivative across the curve; its part normal to
+ * the curve is normalized into nu), the coefficient a > 0 and its gradient grad_a (ambient; only
+ * nu . grad_a is used).  oversample: m in [1, 1024], with m * M < 2^31.  The arrays are in mem_kind
+ * memory and read during the call only.
+ * Errors: INVALID (bad sizes, a <= 0, a zero xt, d along the curve or non-finite data, at a sample
+ * or at an interpolated point), TOO_LARGE, OOM, DEVICE. */
+PMX_API pmx_status pmx_edge_create(pmx_ctx* ctx, int n_curves, const int64_t* n_samples, const double* x,
+                                   const double* xt, const double* d, const double* a, const double* grad_a,
+                                   int oversample, int mem_kind, void* stream, pmx_edge** out);
+PMX_API void pmx_edge_destroy(pmx_edge* e);
+/* *m_samples = M, *n_fine = m M (either pointer may be NULL).  Errors: INVALID (null handle). */
+PMX_API pmx_status pmx_edge_size(pmx_edge* e, int64_t* m_samples, int64_t* n_fine);
+/* The fine quadrature points to host arrays (any pointer may be NULL): position y (n_fine x 3),
+ * conormal nu (n_fine x 3), trapezoid weight w, coefficient a and nu . grad a (n_fine each).
+ * Errors: INVALID (null handle), DEVICE. */
+PMX_API pmx_status pmx_edge_export_points(pmx_edge* e, double* y, double* nu, double* w, double* a,
+                                          double* nu_grad_a);
+/* y = op_kind[mu] at the N nodes of the operator's surface (the targets; their n, H, a and
+ * grad_G a come from op): mu holds n_rhs rows of M doubles (row r at offset r M), y n_rhs rows of N,
+ * both in mem_kind memory.  The operator's surface may be open (a set of patches that does not
+ * close); the targets must lie off the curves.  Calls on one edge object must not overlap (it holds
+ * the apply's scratch); different edge objects may run concurrently.
+ * Errors: INVALID (null argument, unknown kind, n_rhs outside [1, 1024], op and e on different
+ * devices, an operator with c != 0 or an advection field), OOM, DEVICE. */
+PMX_API pmx_status pmx_edge_apply(pmx_operator* op, pmx_edge* e, int kind, int n_rhs, const double* mu, double* y,
+                                  int mem_kind, void* stream);
 
 #ifdef __cplusplus
 }

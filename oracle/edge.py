@@ -155,6 +155,18 @@ def edge_apply(kind: str, tgt: dict, edge, mu: np.ndarray, m: int, targets=None,
     return out
 
 
+def edge_abs_sum(kind: str, tgt: dict, edge, m: int, targets=None, chunk: int = 256) -> np.ndarray:
+    """sum_p |k(x_i, y_p)| w_p over the fine points for each target: the scale of the rounding error of
+    the trapezoid sum (used for tolerances, not part of the operator)."""
+    pts = edge_points(edge, m)
+    idx = np.arange(tgt["x"].shape[0]) if targets is None else np.asarray(targets)
+    out = np.empty(len(idx))
+    for s in range(0, len(idx), chunk):
+        i = idx[s:s + chunk]
+        out[s:s + chunk] = np.abs(edge_kernel(kind, tgt, i, pts)) @ pts["w"]
+    return out
+
+
 def targets_of(orc) -> dict:
     """Target node arrays of an OracleOperator."""
     return {"x": orc.x, "n": orc.n, "H": orc.H, "a": orc.a, "gs": orc.gs}

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpmx.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["geometry.hip", "nearweights.hip", "direct.hip", "nearapply.hip", "krylov.hip", "fmm.hip",
-           "capi.hip", "serve.cpp"]
+           "edge.hip", "capi.hip", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-fvisibility=hidden",
          # packed FP32 instructions stay off (they are not used on purpose anywhere)

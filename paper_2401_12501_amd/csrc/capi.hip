@@ -617,3 +617,128 @@ pmx_status pmx_profile_read(pmx_operator* op, double* ms, int64_t* count) {
 }
 
 }  // extern "C"
+
+// ----------------------------------------------------------------------------- edge operators
+pmx_status pmx_edge_create(pmx_ctx* ctx, int n_curves, const int64_t* n_samples, const double* x, const double* xt,
+                           const double* d, const double* a, const double* grad_a, int oversample, int mem_kind,
+                           void* stream, pmx_edge** out) {
+  return guarded([&] {
+    PMX_REQUIRE(ctx && out && n_samples, PMX_ERR_INVALID, "null argument");
+    *out = nullptr;
+    PMX_REQUIRE(x && xt && d && a && grad_a, PMX_ERR_INVALID, "null input array");
+    PMX_REQUIRE(n_curves >= 1 && n_curves <= 64, PMX_ERR_INVALID, "n_curves must be in [1, 64]");
+    PMX_REQUIRE(oversample >= 1 && oversample <= 1024, PMX_ERR_INVALID, "oversample must be in [1, 1024]");
+    PMX_REQUIRE(mem_kind == PMX_MEM_HOST || mem_kind == PMX_MEM_DEVICE, PMX_ERR_INVALID,
+                "mem_kind must be PMX_MEM_HOST or PMX_MEM_DEVICE");
+    std::vector<int64_t> off(n_curves + 1, 0);
+    for (int k = 0; k < n_curves; ++k) {
+      PMX_REQUIRE(n_samples[k] >= 3 && n_samples[k] < ((int64_t)1 << 31), PMX_ERR_INVALID,
+                  "every curve needs at least 3 samples");
+      off[k + 1] = off[k] + n_samples[k];
+    }
+    const int64_t M = off.back();
+    PMX_REQUIRE(M * oversample < ((int64_t)1 << 31), PMX_ERR_INVALID, "too many fine points");
+    PMX_HIP(hipSetDevice(ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    // the samples on the host (small): validated here, uploaded as 13 rows of M
+    std::vector<double> h3[4], ha(M);
+    const double* src3[4] = {x, xt, d, grad_a};
+    for (int k = 0; k < 4; ++k) {
+      h3[k].resize(3 * M);
+      PMX_HIP(hipMemcpy(h3[k].data(), src3[k], 3 * M * sizeof(double),
+                        mem_kind == PMX_MEM_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    }
+    PMX_HIP(hipMemcpy(ha.data(), a, M * sizeof(double),
+                      mem_kind == PMX_MEM_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    std::vector<double> soa(13 * M);
+    for (int64_t j = 0; j < M; ++j) {
+      const double* t = &h3[1][3 * j];
+      const double* dd = &h3[2][3 * j];
+      const double tl = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+      const double dl = std::sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+      const double dt = tl > 0 ? (dd[0] * t[0] + dd[1] * t[1] + dd[2] * t[2]) / tl : 0.0;
+      PMX_REQUIRE(tl > 0 && std::isfinite(tl), PMX_ERR_INVALID, "edge: a sample has a zero or non-finite xt");
+      PMX_REQUIRE(std::isfinite(dl) && dl * dl - dt * dt > 1e-12 * dl * dl, PMX_ERR_INVALID,
+                  "edge: a direction d is zero, non-finite or along the curve");
+      PMX_REQUIRE(ha[j] > 0 && std::isfinite(ha[j]), PMX_ERR_INVALID, "edge: a must be positive and finite");
+      for (int c = 0; c < 3; ++c) {
+        PMX_REQUIRE(std::isfinite(h3[0][3 * j + c]) && std::isfinite(h3[3][3 * j + c]), PMX_ERR_INVALID,
+                    "edge: non-finite position or grad_a");
+        for (int k = 0; k < 3; ++k) soa[(3 * k + c) * M + j] = h3[k][3 * j + c];
+        soa[(10 + c) * M + j] = h3[3][3 * j + c];
+      }
+      soa[9 * M + j] = ha[j];
+    }
+    auto* e = new pmx_edge;
+    try {
+      e->ctx = ctx;
+      e->e.ctx = &ctx->c;
+      edge_build(&ctx->c, e->e, off, soa, oversample, st);
+    } catch (...) {
+      delete e;
+      throw;
+    }
+    ctx_retain(ctx);
+    *out = e;
+  });
+}
+
+void pmx_edge_destroy(pmx_edge* e) {
+  if (!e) return;
+  pmx_ctx* c = e->ctx;
+  delete e;
+  ctx_release(c);
+}
+
+pmx_status pmx_edge_size(pmx_edge* e, int64_t* m_samples, int64_t* n_fine) {
+  return guarded([&] {
+    PMX_REQUIRE(e, PMX_ERR_INVALID, "null handle");
+    if (m_samples) *m_samples = e->e.M;
+    if (n_fine) *n_fine = e->e.Mf;
+  });
+}
+
+pmx_status pmx_edge_export_points(pmx_edge* e, double* y, double* nu, double* w, double* a, double* nu_grad_a) {
+  return guarded([&] {
+    PMX_REQUIRE(e, PMX_ERR_INVALID, "null handle");
+    PMX_HIP(hipSetDevice(e->ctx->c.device));
+    const int64_t Mf = e->e.Mf;
+    std::vector<double> P(10 * Mf);
+    PMX_HIP(hipMemcpy(P.data(), e->e.pts.p, 10 * Mf * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < Mf; ++p) {
+      for (int c = 0; c < 3; ++c) {
+        if (y) y[3 * p + c] = P[c * Mf + p];
+        if (nu) nu[3 * p + c] = P[(3 + c) * Mf + p];
+      }
+      if (w) w[p] = P[8 * Mf + p];
+      if (a) a[p] = P[9 * Mf + p];
+      if (nu_grad_a) nu_grad_a[p] = P[6 * Mf + p] * P[9 * Mf + p];
+    }
+  });
+}
+
+pmx_status pmx_edge_apply(pmx_operator* op, pmx_edge* e, int kind, int n_rhs, const double* mu, double* y,
+                          int mem_kind, void* stream) {
+  return guarded([&] {
+    PMX_REQUIRE(op && e && mu && y, PMX_ERR_INVALID, "null argument");
+    PMX_REQUIRE(kind >= PMX_EDGE_K && kind <= PMX_EDGE_T, PMX_ERR_INVALID, "unknown edge operator");
+    PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    PMX_REQUIRE(op->s->ctx->c.device == e->ctx->c.device, PMX_ERR_INVALID, "operator and edge on different devices");
+    PMX_REQUIRE(!op->cplx() && !op->co.has_c() && !op->co.has_b, PMX_ERR_INVALID,
+                "edge operators are provided for c = 0 without advection");
+    PMX_HIP(hipSetDevice(e->ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    Ctx* ctx = &e->ctx->c;
+    const size_t nin = (size_t)n_rhs * e->e.M, nout = (size_t)n_rhs * op->s->g.N;
+    DBuf<double> bin, bout;
+    const double* dmu = stage_in(ctx, bin, mu, nin, mem_kind, st);
+    double* dy = y;
+    if (mem_kind == PMX_MEM_HOST) {
+      bout.alloc(ctx, nout);
+      dy = bout.p;
+    }
+    edge_apply(op, e->e, kind, n_rhs, dmu, dy, st);
+    if (mem_kind == PMX_MEM_HOST) PMX_HIP(hipMemcpyAsync(y, dy, nout * sizeof(double), hipMemcpyDeviceToHost, st));
+    PMX_HIP(hipStreamSynchronize(st));
+  });
+}

@@ -1,0 +1,333 @@
+// Edge operators of the open-surface problems (Section 5): boundary-curve sources, surface targets.
+//
+// For a density mu on the boundary gamma of an open surface Gamma and a target x in Gamma:
+//   K_gamma[mu](x) = int_gamma K(x, x') mu(x') ds(x')                       (representation, Neumann)
+//   N_gamma[mu](x) = int_gamma nu(x') . grad'_G K(x, x') mu(x') ds(x')       (representation, Dirichlet)
+//   R_gamma[mu](x) = int_gamma R(x, x') mu(x') ds(x')                       (Neumann system)
+//   T_gamma[mu](x) = int_gamma nu(x') . grad'_G R(x, x') mu(x') ds(x')       (Dirichlet system)
+// with nu the unit conormal at x' (tangent to Gamma, normal to gamma, out of Gamma) and the primed
+// derivative acting on the source point, which enters through r = x - x' and through a(x').
+// c = 0: K = log r / (2 pi a(x')), and with the target factors of the far-field sums
+//   a(x') R(x, x') = Phi(r) = rho ((n'.r)^2 rho + h.r),  rho = 1 / r^2,  n' = sqrt(a / pi) n,
+//   h = grad_G a / (2 pi) - (a H / pi) n,
+// so that, with beta = nu . grad a(x') / a(x') and dr/dx' = -I,
+//   a' nu.grad' K = (-(nu.r) rho - log(r) beta) / (2 pi)
+//   a' nu.grad' R = -nu.grad_r Phi - Phi beta,
+//   nu.grad_r Phi = rho (h.nu + rho (2 (n'.r)(n'.nu) - 2 (h.r)(nu.r) - 4 (n'.r)^2 (nu.r) rho)).
+//
+// Discretization (Section 6.1.4): each curve is given at n equispaced samples of a periodic
+// parameter t in [0, 2 pi).  Every sampled quantity is replaced by its trigonometric interpolant at
+// m n equispaced points, f(t_k) = sum_j f_j D(t_k - t_j), with the periodic Dirichlet kernel
+//   D(tau) = sin(n tau / 2) cot(tau / 2) / n  (n even: the Nyquist mode split evenly),
+//   D(tau) = sin(n tau / 2) / (n sin(tau / 2))  (n odd),
+// which takes only the m n values tau = 2 pi k / (m n), tabulated once per curve.  The trapezoid rule
+// on the fine points then has weights (2 pi / (m n)) |dgamma/dt|.
+//
+// Layout: fine points in structure-of-arrays form, pts[c * Mf + p] for c = y (3), nu (3), beta,
+// w / a, w, a (the last two for export only).  An apply interpolates mu, packs source rows (y, nu,
+// beta, w mu / a per right-hand side) that every lane of a wavefront reads alike (through the scalar
+// data cache), and sums over a chunk of fine points per workgroup row; the chunks' partial sums are
+// added in a fixed order.
+#include "pmx_internal.hpp"
+
+namespace pmx {
+
+namespace {
+constexpr int kBlock = 256;
+constexpr int kUpCh = 4;   // channels per pass of the interpolation kernel
+
+typedef const __attribute__((address_space(4))) double* sdp;
+
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+struct CurveIdx {
+  const int64_t* off;    // coarse sample offsets, n_curves + 1
+  const int64_t* foff;   // fine point offsets, n_curves + 1
+  int nc;
+  int m;
+};
+
+__device__ __forceinline__ int curve_of(const CurveIdx& c, int64_t g) {
+  int k = 0;
+  while (k + 1 < c.nc && g >= c.foff[k + 1]) ++k;
+  return k;
+}
+
+__global__ void __launch_bounds__(kBlock) k_edge_table(CurveIdx c, int64_t Mf, double* __restrict__ D) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= Mf) return;
+  const int k = curve_of(c, g);
+  const int64_t i = g - c.foff[k];
+  const int64_t n = c.off[k + 1] - c.off[k];
+  const int m = c.m;
+  double v;
+  if (i % m == 0) {
+    v = i == 0 ? 1.0 : 0.0;
+  } else {
+    const double s = sinpi((double)(i % (2 * m)) / m);          // sin(n tau / 2), tau = 2 pi i / (m n)
+    const double h = (double)i / (double)(m * n);                // tau / (2 pi)
+    v = (n % 2 == 0) ? s * cospi(h) / (n * sinpi(h)) : s / (n * sinpi(h));
+  }
+  D[g] = v;
+}
+
+struct UpArgs {
+  CurveIdx c;
+  int64_t Mf;
+  int nch;
+  const double* src;   // nch rows of M coarse values
+  int64_t lds;
+  double* dst;         // nch rows of Mf fine values
+  int64_t ldd;
+  const double* D;
+};
+
+__global__ void __launch_bounds__(kBlock) k_edge_upsample(UpArgs A) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= A.Mf) return;
+  const int k = curve_of(A.c, g);
+  const int64_t i = g - A.c.foff[k];
+  const int64_t base = A.c.off[k], n = A.c.off[k + 1] - base;
+  const int64_t mn = (int64_t)A.c.m * n;
+  const double* __restrict__ Dk = A.D + A.c.foff[k];
+  for (int c0 = 0; c0 < A.nch; c0 += kUpCh) {
+    double acc[kUpCh] = {0.0, 0.0, 0.0, 0.0};
+    int64_t idx = i;   // i - m j, wrapped into [0, m n)
+    for (int64_t j = 0; j < n; ++j) {
+      const double d = Dk[idx];
+#pragma unroll
+      for (int c = 0; c < kUpCh; ++c)
+        if (c0 + c < A.nch) acc[c] = fma(A.src[(c0 + c) * A.lds + base + j], d, acc[c]);
+      idx -= A.c.m;
+      if (idx < 0) idx += mn;
+    }
+#pragma unroll
+    for (int c = 0; c < kUpCh; ++c)
+      if (c0 + c < A.nch) A.dst[(c0 + c) * A.ldd + g] = acc[c];
+  }
+}
+
+// Fine geometry channels in: y (3), dy/dt (3), d (3), a, grad a (3).  Out: y, nu, beta, w / a, w, a.
+__global__ void __launch_bounds__(kBlock) k_edge_geom(CurveIdx c, int64_t Mf, const double* __restrict__ F,
+                                                      double* __restrict__ P, int* __restrict__ bad) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= Mf) return;
+  const int k = curve_of(c, g);
+  const int64_t n = c.off[k + 1] - c.off[k];
+  double f[13];
+#pragma unroll
+  for (int q = 0; q < 13; ++q) f[q] = F[q * Mf + g];
+  const double L = sqrt(f[3] * f[3] + f[4] * f[4] + f[5] * f[5]);
+  const double t0 = f[3] / L, t1 = f[4] / L, t2 = f[5] / L;
+  const double dt = f[6] * t0 + f[7] * t1 + f[8] * t2;
+  double v0 = f[6] - dt * t0, v1 = f[7] - dt * t1, v2 = f[8] - dt * t2;
+  const double vl = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+  const double dl = sqrt(f[6] * f[6] + f[7] * f[7] + f[8] * f[8]);
+  v0 /= vl; v1 /= vl; v2 /= vl;
+  const double a = f[9];
+  const double w = (2.0 * M_PI / ((double)c.m * (double)n)) * L;
+  const bool ok = L > 0.0 && isfinite(L) && vl > 1e-8 * dl && a > 0.0 && isfinite(a) &&
+                  isfinite(f[0] + f[1] + f[2] + f[10] + f[11] + f[12]);
+  if (!ok) atomicOr(bad, 1);
+  P[0 * Mf + g] = f[0];
+  P[1 * Mf + g] = f[1];
+  P[2 * Mf + g] = f[2];
+  P[3 * Mf + g] = v0;
+  P[4 * Mf + g] = v1;
+  P[5 * Mf + g] = v2;
+  P[6 * Mf + g] = (v0 * f[10] + v1 * f[11] + v2 * f[12]) / a;
+  P[7 * Mf + g] = w / a;
+  P[8 * Mf + g] = w;
+  P[9 * Mf + g] = a;
+}
+
+// Row of a packed source: y (3), nu (3), beta, NR weighted densities, padded to an even length.
+template <int NR>
+constexpr int edge_row_len() { return ((7 + NR + 1) / 2) * 2; }
+
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_edge_pack(int64_t Mf, const double* __restrict__ P,
+                                                      const double* __restrict__ muf, double* __restrict__ rows) {
+  constexpr int RL = edge_row_len<NR>();
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= Mf) return;
+  double* row = rows + p * RL;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) row[q] = P[q * Mf + p];
+  const double wa = P[7 * Mf + p];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) row[7 + r] = wa * muf[r * Mf + p];
+#pragma unroll
+  for (int q = 7 + NR; q < RL; ++q) row[q] = 0.0;
+}
+
+struct EdgePairArgs {
+  int64_t N, Mf, chunk, nbx;
+  const double* tf;    // 9N target factors: x y z n' h
+  const double* rows;
+  double* part;        // part[chunk][rhs][i]
+  int64_t ldc;         // NR * N
+};
+
+// KIND: 0 K, 1 N, 2 R, 3 T.
+template <int KIND, int NR>
+__global__ void __launch_bounds__(kBlock) k_edge_pairs(EdgePairArgs A) {
+  constexpr int RL = edge_row_len<NR>();
+  constexpr double kInv2Pi = 0.15915494309189533577;
+  const int64_t N = A.N;
+  const int64_t by = blockIdx.x / A.nbx, bx = blockIdx.x - by * A.nbx;
+  const int64_t p0 = by * A.chunk;
+  const int64_t p1 = p0 + A.chunk < A.Mf ? p0 + A.chunk : A.Mf;
+  const int64_t it = bx * kBlock + threadIdx.x;
+  const int64_t i = it < N ? it : N - 1;
+  const double* __restrict__ tf = A.tf;
+  const double xi = tf[i], yi = tf[N + i], zi = tf[2 * N + i];
+  double px = 0, py = 0, pz = 0, hx = 0, hy = 0, hz = 0;
+  if (KIND >= 2) {
+    px = tf[3 * N + i]; py = tf[4 * N + i]; pz = tf[5 * N + i];
+    hx = tf[6 * N + i]; hy = tf[7 * N + i]; hz = tf[8 * N + i];
+  }
+  const sdp S = (sdp)A.rows;
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+#pragma unroll 4
+  for (int64_t p = p0; p < p1; ++p) {
+    const sdp row = S + p * RL;
+    const double dx = xi - row[0], dy = yi - row[1], dz = zi - row[2];
+    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, 1e-300)));
+    double val;
+    if (KIND == 0) {
+      val = (0.5 * kInv2Pi) * log_pair(r2);
+    } else if (KIND == 1) {
+      const double rho = rcp_nr(r2);
+      const double v = fma(row[3], dx, fma(row[4], dy, row[5] * dz));
+      val = -kInv2Pi * fma(v, rho, 0.5 * log_pair(r2) * row[6]);
+    } else {
+      const double rho = rcp_nr(r2);
+      const double u = fma(px, dx, fma(py, dy, pz * dz));
+      const double hr = fma(hx, dx, fma(hy, dy, hz * dz));
+      const double phi = fma(u * rho, u, hr) * rho;
+      if (KIND == 2) {
+        val = phi;
+      } else {
+        const double nx = row[3], ny = row[4], nz = row[5];
+        const double v = fma(nx, dx, fma(ny, dy, nz * dz));
+        const double un = fma(px, nx, fma(py, ny, pz * nz));
+        const double hn = fma(hx, nx, fma(hy, ny, hz * nz));
+        const double in = fma(2.0 * u, un, -2.0 * hr * v) - 4.0 * u * u * v * rho;
+        const double dphi = rho * fma(rho, in, hn);
+        val = -fma(phi, row[6], dphi);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = fma(row[7 + r], val, acc[r]);
+  }
+  if (it < N) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) A.part[by * A.ldc + r * N + it] = acc[r];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_edge_reduce(int64_t len, int64_t nchunk, int64_t ldc,
+                                                        const double* __restrict__ part, double* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= len) return;
+  double s = 0.0;
+  for (int64_t c = 0; c < nchunk; ++c) s += part[c * ldc + e];
+  y[e] = s;
+}
+
+int64_t nblk(int64_t n) { return (n + kBlock - 1) / kBlock; }
+
+CurveIdx curve_idx(const EdgeSet& E) { return {E.doff.p, E.dfoff.p, E.n_curves, E.m}; }
+
+template <int KIND, int NR>
+void launch_pairs(const EdgePairArgs& a, int64_t blocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_edge_pairs<KIND, NR>), dim3(blocks), dim3(kBlock), 0, st, a);
+}
+
+template <int NR>
+void pairs_kind(int kind, const EdgePairArgs& a, int64_t blocks, hipStream_t st) {
+  switch (kind) {
+    case 0: launch_pairs<0, NR>(a, blocks, st); break;
+    case 1: launch_pairs<1, NR>(a, blocks, st); break;
+    case 2: launch_pairs<2, NR>(a, blocks, st); break;
+    default: launch_pairs<3, NR>(a, blocks, st); break;
+  }
+}
+}  // namespace
+
+void edge_build(Ctx* ctx, EdgeSet& E, const std::vector<int64_t>& off, const std::vector<double>& soa, int m,
+                hipStream_t st) {
+  E.n_curves = (int)off.size() - 1;
+  E.m = m;
+  E.off = off;
+  E.M = off.back();
+  E.foff.assign(off.size(), 0);
+  for (size_t k = 0; k < off.size(); ++k) E.foff[k] = off[k] * m;
+  E.Mf = E.foff.back();
+  E.doff.alloc(ctx, off.size());
+  E.dfoff.alloc(ctx, off.size());
+  PMX_HIP(hipMemcpyAsync(E.doff.p, E.off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  PMX_HIP(hipMemcpyAsync(E.dfoff.p, E.foff.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  DBuf<double> coarse, fine;
+  DBuf<int> bad;
+  coarse.alloc(ctx, 13 * E.M);
+  fine.alloc(ctx, 13 * E.Mf);
+  bad.alloc(ctx, 1);
+  PMX_HIP(hipMemcpyAsync(coarse.p, soa.data(), 13 * E.M * sizeof(double), hipMemcpyHostToDevice, st));
+  E.table.alloc(ctx, E.Mf);
+  E.pts.alloc(ctx, 10 * E.Mf);
+  const CurveIdx c = curve_idx(E);
+  hipLaunchKernelGGL(k_edge_table, dim3(nblk(E.Mf)), dim3(kBlock), 0, st, c, E.Mf, E.table.p);
+  UpArgs u{c, E.Mf, 13, coarse.p, E.M, fine.p, E.Mf, E.table.p};
+  hipLaunchKernelGGL(k_edge_upsample, dim3(nblk(E.Mf)), dim3(kBlock), 0, st, u);
+  const int zero = 0;
+  PMX_HIP(hipMemcpyAsync(bad.p, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_edge_geom, dim3(nblk(E.Mf)), dim3(kBlock), 0, st, c, E.Mf, fine.p, E.pts.p, bad.p);
+  PMX_HIP(hipGetLastError());
+  int flag = 0;
+  PMX_HIP(hipMemcpyAsync(&flag, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  PMX_HIP(hipStreamSynchronize(st));
+  PMX_REQUIRE(flag == 0, PMX_ERR_INVALID,
+              "edge: an interpolated point has a vanishing curve derivative, a direction d along the curve, "
+              "a <= 0 or non-finite data");
+}
+
+void edge_apply(const pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double* mu, double* y, hipStream_t st) {
+  Ctx* ctx = E.ctx;
+  const int64_t N = op->s->g.N, Mf = E.Mf;
+  if (E.muf.n < (size_t)n_rhs * Mf) E.muf.alloc(ctx, (size_t)n_rhs * Mf);
+  const CurveIdx c = curve_idx(E);
+  UpArgs u{c, Mf, n_rhs, mu, E.M, E.muf.p, Mf, E.table.p};
+  hipLaunchKernelGGL(k_edge_upsample, dim3(nblk(Mf)), dim3(kBlock), 0, st, u);
+  // source chunks: enough workgroups to fill the chip several times over
+  const int64_t nbx = nblk(N);
+  int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((4096 + nbx - 1) / nbx, (Mf + 127) / 128));
+  const int64_t chunk = (Mf + nchunk - 1) / nchunk;
+  nchunk = (Mf + chunk - 1) / chunk;
+  const int nr_max = n_rhs >= 4 ? 4 : 1;
+  if (E.rows.n < (size_t)edge_row_len<4>() * Mf) E.rows.alloc(ctx, (size_t)edge_row_len<4>() * Mf);
+  if (E.part.n < (size_t)nchunk * nr_max * N) E.part.alloc(ctx, (size_t)nchunk * nr_max * N);
+  for (int r0 = 0; r0 < n_rhs;) {
+    const int nr = n_rhs - r0 >= 4 ? 4 : 1;
+    EdgePairArgs a{N, Mf, chunk, nbx, op->co.tf64.p, E.rows.p, E.part.p, (int64_t)nr * N};
+    if (nr == 4) {
+      hipLaunchKernelGGL(k_edge_pack<4>, dim3(nblk(Mf)), dim3(kBlock), 0, st, Mf, E.pts.p, E.muf.p + r0 * Mf, E.rows.p);
+      pairs_kind<4>(kind, a, nbx * nchunk, st);
+    } else {
+      hipLaunchKernelGGL(k_edge_pack<1>, dim3(nblk(Mf)), dim3(kBlock), 0, st, Mf, E.pts.p, E.muf.p + r0 * Mf, E.rows.p);
+      pairs_kind<1>(kind, a, nbx * nchunk, st);
+    }
+    hipLaunchKernelGGL(k_edge_reduce, dim3(nblk((int64_t)nr * N)), dim3(kBlock), 0, st, (int64_t)nr * N, nchunk,
+                       (int64_t)nr * N, E.part.p, y + (int64_t)r0 * N);
+    r0 += nr;
+  }
+  PMX_HIP(hipGetLastError());
+}
+
+}  // namespace pmx

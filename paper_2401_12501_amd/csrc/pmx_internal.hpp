@@ -171,6 +171,19 @@ struct NearLists {
   bool have_tiles = false;
 };
 
+// Boundary curves of an open surface, Fourier-oversampled for the edge quadrature (edge.hip):
+// curve k owns coarse samples [off[k], off[k+1]) and fine points [m off[k], m off[k+1]).
+struct EdgeSet {
+  Ctx* ctx = nullptr;
+  int n_curves = 0, m = 1;
+  int64_t M = 0, Mf = 0;
+  std::vector<int64_t> off, foff;
+  DBuf<int64_t> doff, dfoff;
+  DBuf<double> table;   // Mf: periodic Dirichlet kernel of each curve at its m n offsets
+  DBuf<double> pts;     // 10 Mf: y (3), nu (3), beta = nu . grad a / a, w / a, w, a
+  DBuf<double> muf, rows, part;   // scratch of an apply
+};
+
 struct FMM;  // fmm.hip
 
 // ----------------------------------------------------------------------------- grouped launches
@@ -679,6 +692,12 @@ struct pmx_operator {
   int cols(int n_vec) const { return co.complex_ ? 2 * n_vec : n_vec; }
 };
 
+// Boundary curves of an open surface (pmx_edge_create); holds a reference on its context.
+struct pmx_edge {
+  pmx_ctx* ctx = nullptr;
+  pmx::EdgeSet e;
+};
+
 namespace pmx {
 
 // Scratch of the FP64 direct apply carved out of memory the caller supplies (the
@@ -754,6 +773,12 @@ struct SolveResult {
 };
 SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, const double* f_d, double* sigma_d,
                          bool warm, hipStream_t st, std::vector<double>& removed_mean);
+// edge.hip
+// soa: 13 rows of M values (y, dy/dt, d, a, grad a); validates the fine points (INVALID).
+void edge_build(Ctx* ctx, EdgeSet& E, const std::vector<int64_t>& off, const std::vector<double>& soa, int m,
+                hipStream_t st);
+// y (n_rhs rows of N) = edge operator `kind` (0 K, 1 N, 2 R, 3 T) of mu (n_rhs rows of M), device arrays.
+void edge_apply(const pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double* mu, double* y, hipStream_t st);
 // fmm.hip
 void fmm_build(pmx_operator* op, hipStream_t st);
 void fmm_destroy(FMM* f);

@@ -84,6 +84,12 @@ _SIGS = {
     "pmx_server_destroy": (None, [_vp]),
     "pmx_server_get_stats": (C.c_int32, [_vp] + [C.POINTER(C.c_uint64)] * 5),
     "pmx_profile_enable": (C.c_int32, [_vp, C.c_int]),
+    "pmx_edge_create": (C.c_int32, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, _vp,
+                                    C.POINTER(_vp)]),
+    "pmx_edge_destroy": (None, [_vp]),
+    "pmx_edge_size": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "pmx_edge_export_points": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "pmx_edge_apply": (C.c_int32, [_vp, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int, _vp]),
     "pmx_profile_read": (C.c_int32, [_vp, _vp, _vp]),
 }
 
@@ -396,6 +402,58 @@ class Operator:
         Di = np.empty((nnz, q2)) if with_D else None
         _check(lib().pmx_operator_export_near_imag(self.h, Ci.ctypes.data, Di.ctypes.data if with_D else None))
         return Ci, Di
+
+
+EDGE_KINDS = {"K": 0, "N": 1, "R": 2, "T": 3}   # PMX_EDGE_K, _N, _R, _T
+
+
+class Edge:
+    """pmx_edge_create: boundary curves of an open surface, sampled at equispaced parameter values,
+    Fourier-oversampled ``oversample`` times for the edge quadrature.  ``counts`` gives the samples of
+    each curve (stored curve after curve); x, xt, d, grad_a are (M, 3), a is (M,)."""
+
+    def __init__(self, ctx: Context, counts, x, xt, d, a, grad_a, oversample: int = 1):
+        self.ctx = ctx
+        cnt = np.ascontiguousarray(counts, dtype=np.int64)
+        self.counts = cnt
+        ptrs, kind, stream, keep = _marshal(x, xt, d, a, grad_a)
+        h = _vp()
+        _check(lib().pmx_edge_create(ctx.h, len(cnt), cnt.ctypes.data, *ptrs, int(oversample), kind, stream,
+                                     C.byref(h)))
+        self.h = h
+        m, f = C.c_int64(0), C.c_int64(0)
+        _check(lib().pmx_edge_size(h, C.byref(m), C.byref(f)))
+        self.M, self.n_fine = m.value, f.value
+
+    @classmethod
+    def from_inputs(cls, ctx, edge, oversample: int = 1):
+        """From an ``inputs.EdgeSamples``."""
+        return cls(ctx, np.diff(edge.offsets), edge.x, edge.xt, edge.d, edge.a, edge.grad_a, oversample)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pmx_edge_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def points(self) -> dict:
+        """pmx_edge_export_points: the fine quadrature points (y, nu, w, a, nu . grad a)."""
+        F = self.n_fine
+        out = {"y": np.empty((F, 3)), "nu": np.empty((F, 3)), "w": np.empty(F), "a": np.empty(F),
+               "nu_ga": np.empty(F)}
+        _check(lib().pmx_edge_export_points(self.h, *(out[k].ctypes.data for k in ("y", "nu", "w", "a", "nu_ga"))))
+        return out
+
+    def apply(self, op: "Operator", kind: str, mu, out=None):
+        """pmx_edge_apply: the edge operator ``kind`` (K, N, R or T) of mu (n_rhs, M) at the operator's
+        nodes, (n_rhs, N); numpy arrays (host) or float64 CUDA tensors (device)."""
+        n_rhs = (mu.numel() if _is_torch(mu) else np.size(mu)) // self.M
+        if out is None:
+            out = np.empty((n_rhs, op.N)) if not _is_torch(mu) else mu.new_empty((n_rhs, op.N))
+        ptrs, kind_mem, stream, keep = _marshal(mu, out)
+        _check(lib().pmx_edge_apply(op.h, self.h, EDGE_KINDS[kind], n_rhs, ptrs[0], ptrs[1], kind_mem, stream))
+        return out
 
 
 class Server:

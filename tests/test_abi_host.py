@@ -72,3 +72,8 @@ def test_null_arguments_are_errors():
     L.pmx_operator_destroy(None)     # NULL-safe
     L.pmx_surface_destroy(None)
     L.pmx_ctx_destroy(None)
+    assert L.pmx_edge_create(None, 1, None, None, None, None, None, None, 1, 0, None, None) == pmx.PMX_ERR_INVALID
+    assert L.pmx_edge_apply(None, None, 0, 1, None, None, 0, None) == pmx.PMX_ERR_INVALID
+    assert L.pmx_edge_size(None, None, None) == pmx.PMX_ERR_INVALID
+    assert L.pmx_edge_export_points(None, None, None, None, None, None) == pmx.PMX_ERR_INVALID
+    L.pmx_edge_destroy(None)

@@ -1,0 +1,220 @@
+"""Edge operators of the open-surface problems (K_gamma, N_gamma, R_gamma, T_gamma of Section 5; edge
+quadrature of Section 6.1.4) through the C ABI against the FP64 oracle, element by element.
+
+Cases: the wavy-torus band 4 pi / 3 < u < 2 pi as 4 x 6 patches of 6 x 6 nodes (864 targets, a ragged
+last workgroup) with a = exp(0.3 x1 x2), its two boundary circles with 200 samples each (even: the
+split Nyquist mode) or 75 and 50 (odd and even, unequal), oversampling 1, 3, 8 and 64, one and five
+densities (a group of four and a single); the fine quadrature points themselves; a flat surface
+whose nodes all lie inside an ellipse in their plane, where N_gamma[1] = 1 and R_gamma = T_gamma = 0
+hold exactly (independently of the oracle); device arrays; argument errors; and the 19,584-node band
+with 25,600 fine points (the benchmark's workload) at 256 stratified targets.
+Bar, per element: (1e-13 + kappa delta / r_i) sum_p |k(x_i, y_p)| w_p max|mu|.  The sum of absolute
+terms is the scale of a sum whose terms cancel (near the curve, while the oversampling has not resolved
+the near singularity, the terms of R and T reach 1e4 times the result).  The second part is the
+kernel's sensitivity to the fine points' positions: the library and the oracle interpolate them by
+different algorithms (a tabulated Dirichlet kernel, an FFT), whose rounding differs by up to about
+sqrt(n) 4 eps max|y| Lambda = 1.3e-13 for n = 200 samples, |y| <= 4.6 and the interpolation's Lebesgue
+constant Lambda = 4.4; they agree to delta = 1e-13 (asserted here; 1.5e-14 measured), and a kernel
+homogeneous of degree -kappa in r (kappa = 1 for K and N, 2 for R, 3 for T)
+changes by kappa delta / r relative under such a shift; r_i is the target's distance to the nearest
+fine point.  The error against each column's largest value is printed beside it.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2401_12501_amd.inputs import EdgeSamples, Surface, wavy_torus_piece_problem
+from oracle.edge import edge_abs_sum, edge_apply, edge_points, targets_of
+from oracle.operator import OracleOperator
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def col_err(y, ref):
+    return max(float(np.abs(y[:, r] - ref[:, r]).max() / np.abs(ref[:, r]).max()) for r in range(ref.shape[1]))
+
+
+DELTA = 1e-13                          # fine-point positions: library vs oracle
+KAPPA = {"K": 1, "N": 1, "R": 2, "T": 3}
+
+
+def sum_err(y, ref, kind, tgt, edge, m, targets=None):
+    """Largest |y - ref| over the bar (1e-13 + kappa delta / r_i) sum_p |k| w_p max|mu_r| (per element
+    and column): at most 1 passes."""
+    idx = np.arange(tgt["x"].shape[0]) if targets is None else np.asarray(targets)
+    yp = edge_points(edge, m)["y"]
+    rmin = np.array([np.sqrt(((yp - tgt["x"][i]) ** 2).sum(axis=1)).min() for i in idx])
+    rel = 1e-13 + KAPPA[kind] * DELTA / rmin
+    scale = (rel * edge_abs_sum(kind, tgt, edge, m, targets))[:, None] * np.abs(edge.mu).max(axis=0)[None, : ref.shape[1]]
+    return float((np.abs(y - ref) / scale).max())
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2401_12501_amd import pmx
+    return pmx.Context(0)
+
+
+class Piece:
+    def __init__(self, ctx, n_edge, variable_a=True, n_rhs=5, **kw):
+        from paper_2401_12501_amd import pmx
+        self.prob = wavy_torus_piece_problem(n_edge=n_edge, variable_a=variable_a, n_rhs=n_rhs, **kw)
+        say(f"[edge] {self.prob.name}: N={self.prob.n}, M={self.prob.meta['edge'].m}")
+        self.surf = pmx.Surface.from_inputs(ctx, self.prob.surface)
+        self.op = pmx.Operator(self.surf, self.prob.a, self.prob.grad_a)
+        self.tgt = targets_of(OracleOperator.from_problem(self.prob))
+        self.edge = self.prob.meta["edge"]
+        x = self.tgt["x"]
+        th = np.mod(np.arctan2(x[:, 1], x[:, 0]), 2 * np.pi)
+        self.nearest = np.argsort(np.minimum(np.abs(th - 4 * np.pi / 3), np.abs(2 * np.pi - th)))
+
+
+@pytest.fixture(scope="module")
+def piece(ctx):
+    return Piece(ctx, 200, n_u=4, n_v=6, q=6)
+
+
+@pytest.mark.parametrize("m", [1, 8, 64])
+@pytest.mark.parametrize("kind", ["K", "N", "R", "T"])
+def test_edge_apply_matches_oracle(ctx, piece, kind, m):
+    from paper_2401_12501_amd import pmx
+    e = piece.edge
+    E = pmx.Edge.from_inputs(ctx, e, m)
+    say(f"[edge] {kind} m={m}: {E.n_fine} fine points")
+    y = E.apply(piece.op, kind, np.ascontiguousarray(e.mu.T)).T
+    tg = np.arange(piece.prob.n)
+    if m > 8:   # the oracle's rows at m = 64: every third node, the last one and the 24 nearest the curves
+        tg = np.unique(np.concatenate([tg[::3], [tg[-1]], piece.nearest[:24]]))
+    ref = edge_apply(kind, piece.tgt, e, e.mu, m, targets=tg)
+    err = sum_err(y[tg], ref, kind, piece.tgt, e, m, tg)
+    say(f"[edge] {kind} m={m}: error {err:.2f} of the bar, {col_err(y[tg], ref):.2e} of the columns")
+    assert err <= 1
+    y1 = E.apply(piece.op, kind, np.ascontiguousarray(e.mu[:, :1].T)).T     # one density alone
+    assert np.array_equal(y1[:, 0], y[:, 0]) or sum_err(y1[tg], ref[:, :1], kind, piece.tgt, e, m, tg) <= 1
+
+
+def test_fine_points_match_oracle(ctx, piece):
+    from paper_2401_12501_amd import pmx
+    for m in (1, 5):
+        E = pmx.Edge.from_inputs(ctx, piece.edge, m)
+        got = E.points()
+        ref = edge_points(piece.edge, m)
+        assert np.abs(got["y"] - ref["y"]).max() <= DELTA, m
+        for k in ("nu", "w", "a", "nu_ga"):
+            scale = max(1.0, float(np.abs(ref[k]).max()))
+            assert np.abs(got[k] - ref[k]).max() <= 1e-13 * scale, (m, k)
+        say(f"[edge] fine points m={m}: positions within {np.abs(got['y'] - ref['y']).max():.1e}")
+
+
+@pytest.mark.parametrize("kind", ["N", "T"])
+def test_odd_and_unequal_curves(ctx, kind):
+    from paper_2401_12501_amd import pmx
+    pc = Piece(ctx, (75, 50), variable_a=False, n_rhs=1, n_u=3, n_v=5, q=7)
+    E = pmx.Edge.from_inputs(ctx, pc.edge, 3)
+    assert E.M == 125 and E.n_fine == 375
+    y = E.apply(pc.op, kind, np.ascontiguousarray(pc.edge.mu.T)).T
+    ref = edge_apply(kind, pc.tgt, pc.edge, pc.edge.mu, 3)
+    assert sum_err(y, ref, kind, pc.tgt, pc.edge, 3) <= 1
+
+
+def _flat_surface(k=2, q=6, z=1.0, half=0.5):
+    """k x k flat patches covering [-half, half]^2 in the plane z (normal +e_z)."""
+    t, _ = np.polynomial.legendre.leggauss(q)
+    h = 2 * half / k
+    xs = []
+    for pi in range(k):
+        for pj in range(k):
+            for iu in range(q):
+                for iv in range(q):
+                    xs.append([-half + (pi + (t[iu] + 1) / 2) * h, -half + (pj + (t[iv] + 1) / 2) * h, z])
+    x = np.array(xs)
+    N = len(x)
+    xu = np.tile([h / 2, 0.0, 0.0], (N, 1))
+    xv = np.tile([0.0, h / 2, 0.0], (N, 1))
+    zero = np.zeros((N, 3))
+    return Surface("flat", k * k, q, x, xu, xv, zero, zero.copy(), zero.copy())
+
+
+def test_planar_gauss_identity(ctx):
+    from paper_2401_12501_amd import pmx
+    s = _flat_surface()
+    surf = pmx.Surface.from_inputs(ctx, s)
+    op = pmx.Operator(surf, np.ones(s.n), np.zeros((s.n, 3)))
+    n = 96
+    t = 2 * np.pi * np.arange(n) / n
+    x = np.stack([1.3 * np.cos(t), 0.8 * np.sin(t), np.ones(n)], axis=1)
+    xt = np.stack([-1.3 * np.sin(t), 0.8 * np.cos(t), 0 * t], axis=1)
+    d = np.stack([np.cos(t), np.sin(t), 0 * t], axis=1)
+    E = pmx.Edge(ctx, [n], x, xt, d, np.ones(n), np.zeros((n, 3)), 16)
+    one = np.ones((1, n))
+    assert np.abs(E.apply(op, "N", one) - 1.0).max() < 1e-12
+    for kind in ("R", "T"):
+        assert np.abs(E.apply(op, kind, one)).max() < 1e-13
+
+
+def test_device_arrays_match_host(ctx, piece):
+    import torch
+    from paper_2401_12501_amd import pmx
+    E = pmx.Edge.from_inputs(ctx, piece.edge, 8)
+    mu = np.ascontiguousarray(piece.edge.mu.T)
+    yh = E.apply(piece.op, "T", mu)
+    yd = E.apply(piece.op, "T", torch.tensor(mu, device="cuda:0"))
+    torch.cuda.synchronize()
+    assert np.array_equal(yd.cpu().numpy(), yh)
+    e = piece.edge
+    Ed = pmx.Edge(ctx, np.diff(e.offsets), *(torch.tensor(np.ascontiguousarray(v), device="cuda:0")
+                                            for v in (e.x, e.xt, e.d, e.a, e.grad_a)), 8)
+    assert np.array_equal(Ed.apply(piece.op, "T", mu), yh)
+
+
+def test_edge_errors(ctx, piece):
+    from paper_2401_12501_amd import pmx
+    e = piece.edge
+    cnt = np.diff(e.offsets)
+    with pytest.raises(pmx.PmxError):
+        pmx.Edge(ctx, cnt, e.x, e.xt, e.d, -e.a, e.grad_a, 2)          # a <= 0
+    with pytest.raises(pmx.PmxError):
+        pmx.Edge(ctx, cnt, e.x, e.xt, e.xt, e.a, e.grad_a, 2)          # d along the curve
+    with pytest.raises(pmx.PmxError):
+        pmx.Edge(ctx, cnt, e.x, 0 * e.xt, e.d, e.a, e.grad_a, 2)       # zero derivative
+    with pytest.raises(pmx.PmxError):
+        pmx.Edge(ctx, cnt, e.x, e.xt, e.d, e.a, e.grad_a, 0)           # oversample 0
+    with pytest.raises(pmx.PmxError):
+        pmx.Edge(ctx, [2, int(e.m) - 2], e.x, e.xt, e.d, e.a, e.grad_a, 1)   # a curve of 2 samples
+    E = pmx.Edge.from_inputs(ctx, e, 2)
+    L = pmx.lib()
+    mu = np.ascontiguousarray(e.mu[:, :1].T)
+    out = np.empty((1, piece.op.N))
+    assert L.pmx_edge_apply(piece.op.h, E.h, 4, 1, mu.ctypes.data, out.ctypes.data, 0, None) == pmx.PMX_ERR_INVALID
+    assert L.pmx_edge_apply(piece.op.h, E.h, 0, 0, mu.ctypes.data, out.ctypes.data, 0, None) == pmx.PMX_ERR_INVALID
+    p = piece.prob
+    opc = pmx.Operator(piece.surf, p.a, p.grad_a, c=-np.ones(p.n))
+    with pytest.raises(pmx.PmxError):
+        E.apply(opc, "R", mu)
+
+
+def test_full_band_sampled_rows(ctx):
+    """The benchmark's workload: 17 x 18 patches of 8 x 8 nodes, 200 samples per circle, m = 64."""
+    from paper_2401_12501_amd import pmx
+    from _oracle_rows import stratified_targets
+    pc = Piece(ctx, 200, variable_a=True, n_rhs=2)
+    E = pmx.Edge.from_inputs(ctx, pc.edge, 64)
+    assert E.n_fine == 25600
+    ptr = np.empty(pc.prob.n + 1, dtype=np.int64)
+    import ctypes as C
+    pmx._check(pmx.lib().pmx_operator_export_near(pc.op.h, ptr.ctypes.data_as(C.c_void_p), None, None, None))
+    tg = stratified_targets(pc.prob.n, pc.prob.surface.q, ptr, 256, seed=51)
+    tg = np.unique(np.concatenate([tg, pc.nearest[:32]]))
+    mu = np.ascontiguousarray(pc.edge.mu.T)
+    for kind in ("R", "T"):
+        y = E.apply(pc.op, kind, mu).T
+        ref = edge_apply(kind, pc.tgt, pc.edge, pc.edge.mu, 64, targets=tg)
+        err = sum_err(y[tg], ref, kind, pc.tgt, pc.edge, 64, tg)
+        say(f"[edge full] {kind}: {len(tg)} rows, error {err:.2f} of the bar, {col_err(y[tg], ref):.2e} of the columns")
+        assert err <= 1
