@@ -410,6 +410,102 @@ def helmholtz_bench(args):
     print(json.dumps(out), flush=True)
 
 
+# Algorithmic FP64 flops per (target, fine point) pair of the edge-operator kernels, one density:
+# the difference and r^2 (9); K: the logarithm (counted as 1) and its scale (2); N: the reciprocal,
+# nu.r (5), the logarithm term (3) and the combination (3); R: the reciprocal, n'.r and h.r (10) and
+# Phi (4); T: R's 15 plus nu.r, n'.nu, h.nu (15), the derivative's bracket (10), its scale (3) and the
+# combination with Phi (2); and 2 for the accumulation.
+EDGE_PAIR_FLOPS = {"K": 13, "N": 23, "R": 26, "T": 56}
+
+
+def edge_bench(args):
+    """Open surfaces: the edge operators K, N, R, T (Section 5) applied from the boundary circles of
+    the wavy-torus band 4 pi / 3 < u < 2 pi (17 x 18 patches of 8 x 8 nodes, 19,584 targets) with 200
+    samples per circle oversampled 64 times (25,600 fine points, Section 7.5's setting), a =
+    exp(0.3 x1 x2), mu = exp(x1).  Reports each kind's apply time, the roofline of the T pair kernel
+    (device time from HIP events on the launch stream), Section 7.5's error against oversampling, and
+    (CPU leg) the oracle's rows and its rate on a bounded sample."""
+    import torch
+    from paper_2401_12501_amd import pmx
+    from paper_2401_12501_amd.inputs import wavy_torus_piece_problem
+    m_over = 64
+    prob = wavy_torus_piece_problem(n_u=17, n_v=18, q=8, n_edge=200, variable_a=True, n_rhs=1)
+    edge = prob.meta["edge"]
+    N = prob.n
+    ctx = pmx.Context(0)
+    surf = pmx.Surface.from_inputs(ctx, prob.surface)
+    op = pmx.Operator(surf, prob.a, prob.grad_a)
+    t0 = time.perf_counter()
+    E = pmx.Edge.from_inputs(ctx, edge, m_over)
+    t_edge = time.perf_counter() - t0
+    Mf = E.n_fine
+    log(f"[bench] workload {prob.name} N={N}, {edge.m} samples, oversampling {m_over}: {Mf} fine points "
+        f"(edge setup {t_edge * 1e3:.1f} ms)")
+    mu = torch.tensor(np.ascontiguousarray(edge.mu.T), device="cuda:0")
+    y = torch.empty((1, N), dtype=torch.float64, device="cuda:0")
+    res = {}
+    for kind in ("K", "N", "R", "T"):
+        for _ in range(args.warmup):
+            E.apply(op, kind, mu, out=y)
+        torch.cuda.synchronize()
+        op.profile_read()
+        op.profile(True)
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            E.apply(op, kind, mu, out=y)
+        torch.cuda.synchronize()
+        step_s = (time.perf_counter() - ts) / args.steps
+        op.profile(False)
+        ph = op.profile_read()["edge"]
+        pair_ms = ph[0] / max(ph[1], 1)
+        tf = N * Mf * EDGE_PAIR_FLOPS[kind] / (pair_ms * 1e-3) / 1e12
+        res[kind] = {"ms": round(step_s * 1e3, 4), "pair_kernel_ms": round(pair_ms, 4), "tflops": round(tf, 3),
+                     "frac": round(tf / PEAK["fp64_valu"], 4)}
+        log(f"[bench] edge {kind}: {step_s * 1e3:.4f} ms/apply, pair kernel {pair_ms:.4f} ms, "
+            f"{tf:.2f} TFLOP/s ({tf / PEAK['fp64_valu']:.3f} of FP64)")
+    # Section 7.5: error of R and T against the finest rule as the oversampling grows
+    study = {}
+    for kind in ("R", "T"):
+        ref = pmx.Edge.from_inputs(ctx, edge, 128).apply(op, kind, mu).cpu().numpy()
+        errs = {}
+        for m in (1, 2, 4, 8, 16, 32, 64):
+            v = pmx.Edge.from_inputs(ctx, edge, m).apply(op, kind, mu).cpu().numpy()
+            errs[m] = float(np.abs(v - ref).max() / np.abs(ref).max())
+        study[kind] = {str(k): float(f"{v:.3g}") for k, v in errs.items()}
+        log(f"[bench] edge {kind} error vs oversampling (max over nodes, against m = 128): " +
+            ", ".join(f"m={k} {v:.2e}" for k, v in errs.items()))
+    E.apply(op, "T", mu, out=y)
+    y_t = y.cpu().numpy()[0]
+    cpu, err = None, None
+    if not args.no_cpu:
+        from oracle.edge import edge_apply, targets_of
+        from oracle.operator import OracleOperator
+        tgt = targets_of(OracleOperator.from_problem(prob))
+        tg = np.sort(np.random.default_rng(13).choice(N, size=48, replace=False))
+        ts = time.perf_counter()
+        ref = edge_apply("T", tgt, edge, edge.mu, m_over, targets=tg)[:, 0]
+        t_cpu = time.perf_counter() - ts
+        err = float(np.abs(y_t[tg] - ref).max() / np.abs(ref).max())
+        cpu = {"value": round(len(tg) * Mf / t_cpu / 1e9, 6), "unit": "Gpairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"T_gamma at {len(tg)} seeded targets x {Mf} fine points (NumPy, one thread), "
+                         f"{t_cpu:.2f} s", **host_cpu()}
+        log(f"[bench] oracle T rows: {len(tg)} targets in {t_cpu:.2f} s; GPU vs oracle {err:.2e} of the column")
+    t = res["T"]
+    out = {"metric": "open-surface edge operators: target-source pairs/s (T_gamma, FP64, trapezoid x64)",
+           "value": round(N * Mf / (t["ms"] * 1e-3) / 1e9, 3), "unit": "Gpairs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t["ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": (f"wavy torus band 4pi/3 < u < 2pi, 17 x 18 patches x 8x8, N={N}; 2 boundary "
+                                   f"circles x 200 samples, oversampling {m_over} ({Mf} fine points); "
+                                   f"a=exp(0.3 x1 x2), mu=exp(x1)"), "kinds": res},
+           "roofline": {"bound": "alu", "achieved": t["tflops"], "peak": PEAK["fp64_valu"], "unit": "TFLOP/s",
+                        "frac": t["frac"], "traffic": None, "kernel": "k_edge_pairs<3,1>",
+                        "avg_ms": t["pair_kernel_ms"], "flops_per_pair": EDGE_PAIR_FLOPS["T"]},
+           "oversampling_study": study, "edge_setup_ms": round(t_edge * 1e3, 2),
+           "apply_rel_err_vs_oracle": err, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,11 +513,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--n-rhs", type=int, default=1)
-    ap.add_argument("--workload", choices=["ellipsoid", "star", "torus", "helmholtz", "helmholtz_pos"],
+    ap.add_argument("--workload", choices=["ellipsoid", "star", "torus", "helmholtz", "helmholtz_pos", "edge"],
                     default="ellipsoid",
                     help="ellipsoid: 153,600 nodes, 1 RHS (default); star: 525,696 nodes, 1 RHS; "
                          "torus: wobbly torus, 2,097,152 nodes, 16 RHS; helmholtz: the c < 0 path with advection "
-                         "on the ellipsoid's surface (FP64); helmholtz_pos: the same with c > 0 (complex kernel)")
+                         "on the ellipsoid's surface (FP64); helmholtz_pos: the same with c > 0 (complex kernel); "
+                         "edge: the open-surface edge operators on the wavy-torus band")
     ap.add_argument("--k", type=int, default=16, help="ellipsoid: cube-sphere patches per face edge (16: 153,600 nodes)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
@@ -450,6 +547,9 @@ def main():
 
     if args.workload in ("helmholtz", "helmholtz_pos"):
         helmholtz_bench(args)
+        return
+    if args.workload == "edge":
+        edge_bench(args)
         return
     import torch
     from paper_2401_12501_amd import pmx

@@ -284,7 +284,8 @@ enum {
   PMX_PHASE_FMM_P2P = 9,
   PMX_PHASE_LOG = 10,        /* representation far field */
   PMX_PHASE_FMM_M2L_SUM = 11,  /* sum of each box's M2L output slots */
-  PMX_N_PHASES = 12
+  PMX_PHASE_EDGE = 12,       /* edge-operator pair sums (pmx_edge_apply) */
+  PMX_N_PHASES = 13
 };
 PMX_API pmx_status pmx_profile_enable(pmx_operator* op, int enable);
 PMX_API pmx_status pmx_profile_read(pmx_operator* op, double* ms /* PMX_N_PHASES */, int64_t* count /* PMX_N_PHASES */);

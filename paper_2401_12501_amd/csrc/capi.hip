@@ -616,7 +616,6 @@ pmx_status pmx_profile_read(pmx_operator* op, double* ms, int64_t* count) {
   });
 }
 
-}  // extern "C"
 
 // ----------------------------------------------------------------------------- edge operators
 pmx_status pmx_edge_create(pmx_ctx* ctx, int n_curves, const int64_t* n_samples, const double* x, const double* xt,
@@ -742,3 +741,5 @@ pmx_status pmx_edge_apply(pmx_operator* op, pmx_edge* e, int kind, int n_rhs, co
     PMX_HIP(hipStreamSynchronize(st));
   });
 }
+
+}  // extern "C"

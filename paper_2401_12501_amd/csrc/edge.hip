@@ -298,7 +298,7 @@ void edge_build(Ctx* ctx, EdgeSet& E, const std::vector<int64_t>& off, const std
               "a <= 0 or non-finite data");
 }
 
-void edge_apply(const pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double* mu, double* y, hipStream_t st) {
+void edge_apply(pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double* mu, double* y, hipStream_t st) {
   Ctx* ctx = E.ctx;
   const int64_t N = op->s->g.N, Mf = E.Mf;
   if (E.muf.n < (size_t)n_rhs * Mf) E.muf.alloc(ctx, (size_t)n_rhs * Mf);
@@ -318,10 +318,14 @@ void edge_apply(const pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const d
     EdgePairArgs a{N, Mf, chunk, nbx, op->co.tf64.p, E.rows.p, E.part.p, (int64_t)nr * N};
     if (nr == 4) {
       hipLaunchKernelGGL(k_edge_pack<4>, dim3(nblk(Mf)), dim3(kBlock), 0, st, Mf, E.pts.p, E.muf.p + r0 * Mf, E.rows.p);
+      const int t = op->prof.begin(PMX_PHASE_EDGE, st);
       pairs_kind<4>(kind, a, nbx * nchunk, st);
+      op->prof.end(t, st);
     } else {
       hipLaunchKernelGGL(k_edge_pack<1>, dim3(nblk(Mf)), dim3(kBlock), 0, st, Mf, E.pts.p, E.muf.p + r0 * Mf, E.rows.p);
+      const int t = op->prof.begin(PMX_PHASE_EDGE, st);
       pairs_kind<1>(kind, a, nbx * nchunk, st);
+      op->prof.end(t, st);
     }
     hipLaunchKernelGGL(k_edge_reduce, dim3(nblk((int64_t)nr * N)), dim3(kBlock), 0, st, (int64_t)nr * N, nchunk,
                        (int64_t)nr * N, E.part.p, y + (int64_t)r0 * N);

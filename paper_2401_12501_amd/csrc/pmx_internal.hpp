@@ -778,7 +778,7 @@ SolveResult solve_device(pmx_operator* op, const pmx_options& o, int n_rhs, cons
 void edge_build(Ctx* ctx, EdgeSet& E, const std::vector<int64_t>& off, const std::vector<double>& soa, int m,
                 hipStream_t st);
 // y (n_rhs rows of N) = edge operator `kind` (0 K, 1 N, 2 R, 3 T) of mu (n_rhs rows of M), device arrays.
-void edge_apply(const pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double* mu, double* y, hipStream_t st);
+void edge_apply(pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double* mu, double* y, hipStream_t st);
 // fmm.hip
 void fmm_build(pmx_operator* op, hipStream_t st);
 void fmm_destroy(FMM* f);

@@ -94,7 +94,7 @@ _SIGS = {
 }
 
 PHASES = ["prep", "direct64", "direct32", "near", "fmm_p2m", "fmm_m2m", "fmm_m2l", "fmm_l2l", "fmm_l2p",
-          "fmm_p2p", "log", "fmm_m2l_sum"]
+          "fmm_p2p", "log", "fmm_m2l_sum", "edge"]
 
 _lib = None
 
