@@ -85,28 +85,40 @@ struct UpArgs {
   const double* D;
 };
 
+// kUpLanes lanes per fine point, lane l summing the samples j = l (mod kUpLanes); the lanes' partial
+// sums are combined by a fixed shuffle tree (deterministic), and lane 0 writes.
+constexpr int kUpLanes = 8;
+
 __global__ void __launch_bounds__(kBlock) k_edge_upsample(UpArgs A) {
-  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= A.Mf) return;
-  const int k = curve_of(A.c, g);
-  const int64_t i = g - A.c.foff[k];
-  const int64_t base = A.c.off[k], n = A.c.off[k + 1] - base;
-  const int64_t mn = (int64_t)A.c.m * n;
+  const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kUpLanes;
+  const int l = threadIdx.x % kUpLanes;
+  const bool live = g < A.Mf;
+  const int k = live ? curve_of(A.c, g) : 0;
+  const int64_t i = live ? g - A.c.foff[k] : 0;
+  const int64_t base = A.c.off[k], n = live ? A.c.off[k + 1] - base : 0;
+  const int64_t mn = (int64_t)A.c.m * (A.c.off[k + 1] - base);
+  const int64_t step = ((int64_t)A.c.m * kUpLanes) % mn;
   const double* __restrict__ Dk = A.D + A.c.foff[k];
   for (int c0 = 0; c0 < A.nch; c0 += kUpCh) {
     double acc[kUpCh] = {0.0, 0.0, 0.0, 0.0};
-    int64_t idx = i;   // i - m j, wrapped into [0, m n)
-    for (int64_t j = 0; j < n; ++j) {
+    int64_t idx = i - (int64_t)A.c.m * l;   // i - m j, wrapped into [0, m n)
+    while (idx < 0) idx += mn;
+    for (int64_t j = l; j < n; j += kUpLanes) {
       const double d = Dk[idx];
 #pragma unroll
       for (int c = 0; c < kUpCh; ++c)
         if (c0 + c < A.nch) acc[c] = fma(A.src[(c0 + c) * A.lds + base + j], d, acc[c]);
-      idx -= A.c.m;
+      idx -= step;
       if (idx < 0) idx += mn;
     }
 #pragma unroll
-    for (int c = 0; c < kUpCh; ++c)
-      if (c0 + c < A.nch) A.dst[(c0 + c) * A.ldd + g] = acc[c];
+    for (int c = 0; c < kUpCh; ++c) {
+      double v = acc[c];
+      v += __shfl_xor(v, 4, kUpLanes);
+      v += __shfl_xor(v, 2, kUpLanes);
+      v += __shfl_xor(v, 1, kUpLanes);
+      if (live && l == 0 && c0 + c < A.nch) A.dst[(c0 + c) * A.ldd + g] = v;
+    }
   }
 }
 
@@ -285,7 +297,7 @@ void edge_build(Ctx* ctx, EdgeSet& E, const std::vector<int64_t>& off, const std
   const CurveIdx c = curve_idx(E);
   hipLaunchKernelGGL(k_edge_table, dim3(nblk(E.Mf)), dim3(kBlock), 0, st, c, E.Mf, E.table.p);
   UpArgs u{c, E.Mf, 13, coarse.p, E.M, fine.p, E.Mf, E.table.p};
-  hipLaunchKernelGGL(k_edge_upsample, dim3(nblk(E.Mf)), dim3(kBlock), 0, st, u);
+  hipLaunchKernelGGL(k_edge_upsample, dim3(nblk(E.Mf * kUpLanes)), dim3(kBlock), 0, st, u);
   const int zero = 0;
   PMX_HIP(hipMemcpyAsync(bad.p, &zero, sizeof(int), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_edge_geom, dim3(nblk(E.Mf)), dim3(kBlock), 0, st, c, E.Mf, fine.p, E.pts.p, bad.p);
@@ -304,7 +316,7 @@ void edge_apply(pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double*
   if (E.muf.n < (size_t)n_rhs * Mf) E.muf.alloc(ctx, (size_t)n_rhs * Mf);
   const CurveIdx c = curve_idx(E);
   UpArgs u{c, Mf, n_rhs, mu, E.M, E.muf.p, Mf, E.table.p};
-  hipLaunchKernelGGL(k_edge_upsample, dim3(nblk(Mf)), dim3(kBlock), 0, st, u);
+  hipLaunchKernelGGL(k_edge_upsample, dim3(nblk(Mf * kUpLanes)), dim3(kBlock), 0, st, u);
   // source chunks: enough workgroups to fill the chip several times over
   const int64_t nbx = nblk(N);
   int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>((4096 + nbx - 1) / nbx, (Mf + 127) / 128));
