@@ -19,6 +19,9 @@ surface gradient along nu equals the ambient one, so nu . grad'_G a = nu . grad 
 Only c = 0 is taken here (K = log r / (2 pi a(x')), the Laplace-Beltrami type and its variable-a
 generalization, as in the paper's boundary-value tests).
 
+One edge-to-edge operator of the systems' boundary rows is here too: K'_gamma, the conormal derivative
+at a target on gamma (``kprime_gamma``), with a smooth kernel and the trapezoid rule on the samples.
+
 Discretization (Section 6.1.4, edge quadrature): each boundary curve has a smooth periodic
 parameterization gamma(t), t in [0, 2 pi), sampled at n equispaced t.  Every sampled quantity (the
 position, dgamma/dt, the across-curve direction d, a, grad a and mu) is Fourier-interpolated to m n
@@ -153,6 +156,48 @@ def edge_apply(kind: str, tgt: dict, edge, mu: np.ndarray, m: int, targets=None,
         i = idx[s:s + chunk]
         out[s:s + chunk] = edge_kernel(kind, tgt, i, pts) @ wm
     return out
+
+
+def fourier_derivative(f: np.ndarray) -> np.ndarray:
+    """d/dt of the trigonometric interpolant of the n samples f[j] = f(2 pi j / n) (axis 0), at the
+    samples: FFT, multiplication by i k, inverse FFT (for even n the Nyquist mode, split evenly, has a
+    derivative that vanishes at the samples)."""
+    f = np.asarray(f, dtype=np.float64)
+    n = f.shape[0]
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    if n % 2 == 0:
+        k[n // 2] = 0.0
+    shape = (n,) + (1,) * (f.ndim - 1)
+    return np.fft.ifft(1j * k.reshape(shape) * np.fft.fft(f, axis=0), axis=0).real
+
+
+def kprime_gamma(edge, mu: np.ndarray) -> np.ndarray:
+    """K'_gamma[mu] at the samples of every curve (Theorem thm:NeumannBCsrep, eq:neumann):
+        K'_gamma[mu](x) = int_gamma nu(x) . grad_G K(x, x') mu(x') ds(x'),   x in gamma,
+    the conormal derivative at the target of K = log|x - x'| / (2 pi a(x')), i.e.
+    nu(x) . (x - x') / (2 pi a(x') |x - x'|^2).  The kernel is smooth (Theorem thm:kern_smth), so the
+    trapezoid rule runs on the samples themselves (weights (2 pi / n) |dgamma/dt|).  At x' = x it takes
+    its limit: with x' = gamma(t + h), nu . (x - x') = -(nu . gamma'') h^2 / 2 + O(h^3) and
+    |x - x'|^2 = |gamma'|^2 h^2 + O(h^3), so the kernel tends to -(nu . gamma'') / (4 pi a |gamma'|^2);
+    gamma'' is the derivative of the interpolant of the sampled dgamma/dt.  Returns (M, n_rhs)."""
+    off = np.asarray(edge.offsets)
+    mu = np.asarray(mu, dtype=np.float64).reshape(edge.x.shape[0], -1)
+    nu = conormal(edge.xt, edge.d)
+    w = np.empty(edge.x.shape[0])
+    lim = np.empty(edge.x.shape[0])
+    for k in range(len(off) - 1):
+        s = slice(int(off[k]), int(off[k + 1]))
+        n = off[k + 1] - off[k]
+        xtt = fourier_derivative(edge.xt[s])
+        L2 = np.sum(edge.xt[s] ** 2, axis=1)
+        w[s] = 2 * np.pi / n * np.sqrt(L2)
+        lim[s] = -np.sum(nu[s] * xtt, axis=1) / (4 * np.pi * edge.a[s] * L2)
+    r = edge.x[:, None, :] - edge.x[None, :, :]
+    r2 = np.sum(r * r, axis=-1)
+    np.fill_diagonal(r2, 1.0)
+    Kp = np.sum(nu[:, None, :] * r, axis=-1) / (2 * np.pi * edge.a[None, :] * r2)
+    np.fill_diagonal(Kp, lim)
+    return Kp @ (w[:, None] * mu)
 
 
 def edge_abs_sum(kind: str, tgt: dict, edge, m: int, targets=None, chunk: int = 256) -> np.ndarray:

@@ -15,7 +15,12 @@ against facts that do not come from the oracle's own formulas:
 * the oversampled trapezoid sums equal adaptive quadrature (scipy's quad) of the exact integrand on
   the exact curve, with the conormal built independently as n x tau;
 * Section 7.5's observation: the error at targets near the edge falls quickly once the oversampling
-  resolves the near singularity.
+  resolves the near singularity;
+* K'_gamma (targets on gamma): on a circle of radius rho in a plane with a = 1 the kernel is the
+  constant 1 / (4 pi rho), so K'_gamma[1] = 1/2 at every sample; the diagonal limit equals the kernel
+  at nearby points of the exact curve; the trapezoid sums on an ellipse and on the wavy-torus circles
+  equal adaptive quadrature of the exact integrand; the spectral derivative is exact on trigonometric
+  polynomials.
 """
 import math
 
@@ -24,7 +29,8 @@ import pytest
 import scipy.integrate as si
 
 from paper_2401_12501_amd.inputs import EdgeSamples, wavy_torus_piece_problem
-from oracle.edge import conormal, edge_apply, edge_points, fourier_upsample, n_kernel, t_kernel, targets_of
+from oracle.edge import (conormal, edge_apply, edge_points, fourier_derivative, fourier_upsample, kprime_gamma,
+                         n_kernel, t_kernel, targets_of)
 from oracle.kernels import parametrix, remainder
 from oracle.operator import OracleOperator
 
@@ -229,3 +235,82 @@ def test_edge_points_weights_sum_to_length():
     e = _planar_edge(24, 0.9, 0.9)
     for m in (1, 2, 7):
         assert abs(edge_points(e, m)["w"].sum() - 2 * math.pi * 0.9) < 1e-13
+
+
+# ------------------------------------------------------------------ K'_gamma, targets on the curve
+@pytest.mark.parametrize("n", [16, 15])
+def test_fourier_derivative_trig_polynomial(n):
+    t = 2 * np.pi * np.arange(n) / n
+    f = 1.0 + np.cos(t) - 0.7 * np.sin(2 * t) + 0.3 * np.sin(5 * t)
+    df = -np.sin(t) - 1.4 * np.cos(2 * t) + 1.5 * np.cos(5 * t)
+    if n % 2 == 0:
+        f = f + 0.2 * np.cos(n / 2 * t)      # its derivative vanishes at the samples
+    assert np.abs(fourier_derivative(f) - df).max() < 1e-13
+
+
+def test_kprime_circle_is_one_half():
+    for rho, n in ((0.7, 12), (2.0, 33)):
+        e = _planar_edge(n, rho, rho)
+        v = kprime_gamma(e, np.ones(n))[:, 0]
+        np.testing.assert_allclose(v, 0.5, atol=1e-14)
+
+
+def _ellipse(t, A=1.3, B=0.8):
+    return (np.array([A * np.cos(t), B * np.sin(t), 0.0]), np.array([-A * np.sin(t), B * np.cos(t), 0.0]),
+            np.array([-A * np.cos(t), -B * np.sin(t), 0.0]))
+
+
+def test_kprime_limit_is_the_kernel_near_the_diagonal():
+    """The diagonal value equals the kernel at x' = gamma(t + h) as h -> 0 (first order in h)."""
+    n = 64
+    e = _planar_edge(n)
+    j = 5
+    t0 = 2 * np.pi * j / n
+    x, xt, _ = _ellipse(t0)
+    nu = conormal(xt[None], np.array([[np.cos(t0), np.sin(t0), 0.0]]))[0]
+    mu = np.zeros(n)
+    mu[j] = 1.0
+    lim = kprime_gamma(e, mu)[j, 0] / (2 * np.pi / n * np.linalg.norm(xt))
+    vals = []
+    for h in (1e-3, 5e-4):
+        y = _ellipse(t0 + h)[0]
+        vals.append(nu @ (x - y) / (2 * np.pi * np.sum((x - y) ** 2)))
+    extrap = 2 * vals[1] - vals[0]          # Richardson: the kernel is smooth in h
+    assert abs(extrap - lim) < 1e-6 * abs(lim), (extrap, lim)
+
+
+def _kprime_exact(x, nu, curve, a_fn, mu_fn, t_at):
+    def g(t):
+        y, yt = curve(t)
+        r = x - y
+        return float(nu @ r / (2 * np.pi * a_fn(y) * (r @ r))) * np.linalg.norm(yt) * mu_fn(y)
+    return si.quad(g, t_at, t_at + 2 * np.pi, epsabs=1e-14, epsrel=1e-13, limit=400)[0]
+
+
+def test_kprime_ellipse_matches_adaptive_quadrature():
+    n = 96
+    e = _planar_edge(n)
+    e.mu[:, 0] = np.exp(e.x[:, 0])
+    v = kprime_gamma(e, e.mu)[:, 0]
+    nu = conormal(e.xt, e.d)
+    for j in (0, 17, 50):
+        t0 = 2 * np.pi * j / n
+        ref = _kprime_exact(e.x[j], nu[j], lambda t: _ellipse(t)[:2], lambda y: 1.0, lambda y: np.exp(y[0]), t0)
+        assert abs(v[j] - ref) < 1e-12 * max(1.0, abs(ref)), (j, v[j], ref)
+
+
+def test_kprime_torus_circles_match_adaptive_quadrature():
+    """Both boundary circles of the band: the target's own circle (smooth kernel through the
+    diagonal) and the other circle (far), variable a, mu = exp(x1)."""
+    p = wavy_torus_piece_problem(n_u=4, n_v=6, q=6, n_edge=120, variable_a=True)
+    e = p.meta["edge"]
+    v = kprime_gamma(e, e.mu)[:, 0]
+    nu = conormal(e.xt, e.d)
+    for j in (0, 37, 150):
+        own = 0 if j < 120 else 1
+        t0 = 2 * np.pi * (j - 120 * own) / 120
+        ref = 0.0
+        for c, (th0, side) in enumerate(((_BAND[0], -1), (_BAND[1], +1))):
+            ref += _kprime_exact(e.x[j], nu[j], lambda t, th0=th0: _curve(th0, t)[:2], _a, lambda y: math.exp(y[0]),
+                                 t0 if c == own else 0.0)
+        assert abs(v[j] - ref) < 1e-11 * max(1.0, abs(ref)), (j, v[j], ref)
