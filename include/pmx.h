@@ -348,6 +348,16 @@ PMX_API pmx_status pmx_edge_export_points(pmx_edge* e, double* y, double* nu, do
  * devices, an operator with c != 0 or an advection field), OOM, DEVICE. */
 PMX_API pmx_status pmx_edge_apply(pmx_operator* op, pmx_edge* e, int kind, int n_rhs, const double* mu, double* y,
                                   int mem_kind, void* stream);
+/* y = K'_gamma[mu] at the M samples of the curves: the conormal derivative at a target on gamma of the
+ * potential of K, K'_gamma[mu](x) = int_gamma nu(x) . grad_G K(x, x') mu(x') ds(x') (Theorem
+ * thm:NeumannBCsrep, eq:neumann; the mu-term of the boundary rows of eq:NeuBVPsystem and
+ * eq:DirBVPsystem, whose -mu / (2a) the caller adds).  The kernel nu(x) . (x - x') / (2 pi a(x') r^2)
+ * is smooth (Theorem thm:kern_smth): the trapezoid rule on the samples (no oversampling), with the
+ * kernel's limit -(nu . gamma'') / (4 pi a |gamma'|^2) at x' = x, gamma'' the derivative of the
+ * trigonometric interpolant of the sampled dgamma/dt.  mu and y: n_rhs rows of M doubles, mem_kind
+ * memory.  Errors: INVALID (null argument, n_rhs outside [1, 1024]), OOM, DEVICE. */
+PMX_API pmx_status pmx_edge_apply_kprime(pmx_edge* e, int n_rhs, const double* mu, double* y, int mem_kind,
+                                         void* stream);
 
 #ifdef __cplusplus
 }

@@ -742,4 +742,25 @@ pmx_status pmx_edge_apply(pmx_operator* op, pmx_edge* e, int kind, int n_rhs, co
   });
 }
 
+pmx_status pmx_edge_apply_kprime(pmx_edge* e, int n_rhs, const double* mu, double* y, int mem_kind, void* stream) {
+  return guarded([&] {
+    PMX_REQUIRE(e && mu && y, PMX_ERR_INVALID, "null argument");
+    PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    PMX_HIP(hipSetDevice(e->ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    Ctx* ctx = &e->ctx->c;
+    const size_t n = (size_t)n_rhs * e->e.M;
+    DBuf<double> bin, bout;
+    const double* dmu = stage_in(ctx, bin, mu, n, mem_kind, st);
+    double* dy = y;
+    if (mem_kind == PMX_MEM_HOST) {
+      bout.alloc(ctx, n);
+      dy = bout.p;
+    }
+    edge_apply_kprime(e->e, n_rhs, dmu, dy, st);
+    if (mem_kind == PMX_MEM_HOST) PMX_HIP(hipMemcpyAsync(y, dy, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    PMX_HIP(hipStreamSynchronize(st));
+  });
+}
+
 }  // extern "C"

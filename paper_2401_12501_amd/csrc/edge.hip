@@ -23,6 +23,13 @@
 // which takes only the m n values tau = 2 pi k / (m n), tabulated once per curve.  The trapezoid rule
 // on the fine points then has weights (2 pi / (m n)) |dgamma/dt|.
 //
+// K'_gamma, the conormal derivative at a target on gamma of the potential of K (the boundary rows of
+// the Neumann and Dirichlet systems), has the smooth kernel nu(x) . (x - x') / (2 pi a(x') |x - x'|^2):
+// the trapezoid rule runs on the samples themselves, and at x' = x the kernel takes its limit
+// -(nu . gamma'') / (4 pi a |gamma'|^2), with gamma'' the derivative of the interpolant of the sampled
+// dgamma/dt at the samples, sum_k D1(j - k) gamma'_k with D1(l) = (-1)^l cot(pi l / n) / 2 (n even)
+// or (-1)^l / (2 sin(pi l / n)) (n odd), D1(0) = 0.
+//
 // Layout: fine points in structure-of-arrays form, pts[c * Mf + p] for c = y (3), nu (3), beta,
 // w / a, w, a (the last two for export only).  An apply interpolates mu, packs source rows (y, nu,
 // beta, w mu / a per right-hand side) that every lane of a wavefront reads alike (through the scalar
@@ -154,6 +161,71 @@ __global__ void __launch_bounds__(kBlock) k_edge_geom(CurveIdx c, int64_t Mf, co
   P[7 * Mf + g] = w / a;
   P[8 * Mf + g] = w;
   P[9 * Mf + g] = a;
+}
+
+// Per sample (coarse geometry rows in: y (3), dy/dt (3), d (3), a, grad a (3)): x (3), nu (3), a, the
+// trapezoid weight (2 pi / n) |dgamma/dt| and the diagonal limit of the K'_gamma kernel.
+__global__ void __launch_bounds__(kBlock) k_edge_samples(CurveIdx c, int64_t M, const double* __restrict__ F,
+                                                         double* __restrict__ S) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= M) return;
+  int k = 0;
+  while (k + 1 < c.nc && j >= c.off[k + 1]) ++k;
+  const int64_t base = c.off[k], n = c.off[k + 1] - base, jl = j - base;
+  double tt[3] = {0.0, 0.0, 0.0};   // gamma'' at the sample
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t l = (jl - q + n) % n;
+    if (l == 0) continue;
+    const double h = (double)l / (double)n;
+    const double sgn = (l & 1) ? -0.5 : 0.5;
+    const double wd = (n % 2 == 0) ? sgn * cospi(h) / sinpi(h) : sgn / sinpi(h);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) tt[cc] = fma(wd, F[(3 + cc) * M + base + q], tt[cc]);
+  }
+  const double t0 = F[3 * M + j], t1 = F[4 * M + j], t2 = F[5 * M + j];
+  const double L2 = t0 * t0 + t1 * t1 + t2 * t2, L = sqrt(L2);
+  const double u0 = t0 / L, u1 = t1 / L, u2 = t2 / L;
+  const double d0 = F[6 * M + j], d1 = F[7 * M + j], d2 = F[8 * M + j];
+  const double dt = d0 * u0 + d1 * u1 + d2 * u2;
+  double v0 = d0 - dt * u0, v1 = d1 - dt * u1, v2 = d2 - dt * u2;
+  const double vl = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+  v0 /= vl; v1 /= vl; v2 /= vl;
+  const double a = F[9 * M + j];
+  S[0 * M + j] = F[0 * M + j];
+  S[1 * M + j] = F[1 * M + j];
+  S[2 * M + j] = F[2 * M + j];
+  S[3 * M + j] = v0;
+  S[4 * M + j] = v1;
+  S[5 * M + j] = v2;
+  S[6 * M + j] = a;
+  S[7 * M + j] = (2.0 * M_PI / (double)n) * L;
+  S[8 * M + j] = -(v0 * tt[0] + v1 * tt[1] + v2 * tt[2]) / (4.0 * M_PI * a * L2);
+}
+
+// y[r][i] = sum_j w_j k(x_i, x_j) mu[r][j] over all samples, k the K'_gamma kernel (its limit at j = i).
+// One thread per (target sample, right-hand side): grid y is the right-hand side.
+__global__ void __launch_bounds__(kBlock) k_edge_kprime(int64_t M, const double* __restrict__ S,
+                                                        const double* __restrict__ mu, double* __restrict__ y) {
+  constexpr double kInv2Pi = 0.15915494309189533577;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (i >= M) return;
+  const double xi = S[i], yi = S[M + i], zi = S[2 * M + i];
+  const double n0 = S[3 * M + i], n1 = S[4 * M + i], n2 = S[5 * M + i];
+  const double* __restrict__ m = mu + r * M;
+  double acc = 0.0;
+  for (int64_t j = 0; j < M; ++j) {
+    double val;
+    if (j == i) {
+      val = S[8 * M + i];
+    } else {
+      const double dx = xi - S[j], dy = yi - S[M + j], dz = zi - S[2 * M + j];
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      val = kInv2Pi * fma(n0, dx, fma(n1, dy, n2 * dz)) / (S[6 * M + j] * r2);
+    }
+    acc = fma(S[7 * M + j] * m[j], val, acc);
+  }
+  y[r * M + i] = acc;
 }
 
 // Row of a packed source: y (3), nu (3), beta, NR weighted densities, padded to an even length.
@@ -301,6 +373,8 @@ void edge_build(Ctx* ctx, EdgeSet& E, const std::vector<int64_t>& off, const std
   const int zero = 0;
   PMX_HIP(hipMemcpyAsync(bad.p, &zero, sizeof(int), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_edge_geom, dim3(nblk(E.Mf)), dim3(kBlock), 0, st, c, E.Mf, fine.p, E.pts.p, bad.p);
+  E.samp.alloc(ctx, 9 * E.M);
+  hipLaunchKernelGGL(k_edge_samples, dim3(nblk(E.M)), dim3(kBlock), 0, st, c, E.M, coarse.p, E.samp.p);
   PMX_HIP(hipGetLastError());
   int flag = 0;
   PMX_HIP(hipMemcpyAsync(&flag, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -343,6 +417,11 @@ void edge_apply(pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double*
                        (int64_t)nr * N, E.part.p, y + (int64_t)r0 * N);
     r0 += nr;
   }
+  PMX_HIP(hipGetLastError());
+}
+
+void edge_apply_kprime(EdgeSet& E, int n_rhs, const double* mu, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_edge_kprime, dim3(nblk(E.M), n_rhs), dim3(kBlock), 0, st, E.M, E.samp.p, mu, y);
   PMX_HIP(hipGetLastError());
 }
 

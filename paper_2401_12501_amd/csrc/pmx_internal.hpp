@@ -181,6 +181,7 @@ struct EdgeSet {
   DBuf<int64_t> doff, dfoff;
   DBuf<double> table;   // Mf: periodic Dirichlet kernel of each curve at its m n offsets
   DBuf<double> pts;     // 10 Mf: y (3), nu (3), beta = nu . grad a / a, w / a, w, a
+  DBuf<double> samp;    // 9 M: per sample x (3), nu (3), a, trapezoid weight, K'_gamma diagonal limit
   DBuf<double> muf, rows, part;   // scratch of an apply
 };
 
@@ -779,6 +780,8 @@ void edge_build(Ctx* ctx, EdgeSet& E, const std::vector<int64_t>& off, const std
                 hipStream_t st);
 // y (n_rhs rows of N) = edge operator `kind` (0 K, 1 N, 2 R, 3 T) of mu (n_rhs rows of M), device arrays.
 void edge_apply(pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double* mu, double* y, hipStream_t st);
+// y (n_rhs rows of M) = K'_gamma of mu (n_rhs rows of M) at the samples, device arrays.
+void edge_apply_kprime(EdgeSet& E, int n_rhs, const double* mu, double* y, hipStream_t st);
 // fmm.hip
 void fmm_build(pmx_operator* op, hipStream_t st);
 void fmm_destroy(FMM* f);

@@ -90,6 +90,7 @@ _SIGS = {
     "pmx_edge_size": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "pmx_edge_export_points": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pmx_edge_apply": (C.c_int32, [_vp, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int, _vp]),
+    "pmx_edge_apply_kprime": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.c_int, _vp]),
     "pmx_profile_read": (C.c_int32, [_vp, _vp, _vp]),
 }
 
@@ -453,6 +454,15 @@ class Edge:
             out = np.empty((n_rhs, op.N)) if not _is_torch(mu) else mu.new_empty((n_rhs, op.N))
         ptrs, kind_mem, stream, keep = _marshal(mu, out)
         _check(lib().pmx_edge_apply(op.h, self.h, EDGE_KINDS[kind], n_rhs, ptrs[0], ptrs[1], kind_mem, stream))
+        return out
+
+    def kprime(self, mu, out=None):
+        """pmx_edge_apply_kprime: K'_gamma of mu (n_rhs, M) at the samples, (n_rhs, M)."""
+        n_rhs = (mu.numel() if _is_torch(mu) else np.size(mu)) // self.M
+        if out is None:
+            out = np.empty((n_rhs, self.M)) if not _is_torch(mu) else mu.new_empty((n_rhs, self.M))
+        ptrs, kind_mem, stream, keep = _marshal(mu, out)
+        _check(lib().pmx_edge_apply_kprime(self.h, n_rhs, ptrs[0], ptrs[1], kind_mem, stream))
         return out
 
 

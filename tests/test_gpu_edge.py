@@ -7,7 +7,9 @@ split Nyquist mode) or 75 and 50 (odd and even, unequal), oversampling 1, 3, 8 a
 densities (a group of four and a single); the fine quadrature points themselves; a flat surface
 whose nodes all lie inside an ellipse in their plane, where N_gamma[1] = 1 and R_gamma = T_gamma = 0
 hold exactly (independently of the oracle); device arrays; argument errors; and the 19,584-node band
-with 25,600 fine points (the benchmark's workload) at 256 stratified targets.
+with 25,600 fine points (the benchmark's workload) at 256 stratified targets.  K'_gamma (targets on the
+curves, the trapezoid rule on the samples with the kernel's diagonal limit) against the oracle on the
+same curves (200 and 200, 75 and 50 samples, five densities), and K'_gamma[1] = 1/2 on a circle.
 Bar, per element: (1e-13 + kappa delta / r_i) sum_p |k(x_i, y_p)| w_p max|mu|.  The sum of absolute
 terms is the scale of a sum whose terms cancel (near the curve, while the oversampling has not resolved
 the near singularity, the terms of R and T reach 1e4 times the result).  The second part is the
@@ -25,7 +27,7 @@ import numpy as np
 import pytest
 
 from paper_2401_12501_amd.inputs import EdgeSamples, Surface, wavy_torus_piece_problem
-from oracle.edge import edge_abs_sum, edge_apply, edge_points, targets_of
+from oracle.edge import edge_abs_sum, edge_apply, edge_points, kprime_gamma, targets_of
 from oracle.operator import OracleOperator
 
 pytestmark = pytest.mark.gpu
@@ -218,3 +220,36 @@ def test_full_band_sampled_rows(ctx):
         err = sum_err(y[tg], ref, kind, pc.tgt, pc.edge, 64, tg)
         say(f"[edge full] {kind}: {len(tg)} rows, error {err:.2f} of the bar, {col_err(y[tg], ref):.2e} of the columns")
         assert err <= 1
+
+
+def kprime_err(y, ref, edge):
+    """Largest |y - ref| over 1e-12 sum_j |k_ij| w_j max|mu_r|, the rounding scale of the sums (the
+    kernel's numerator nu . (x - x') is of order h^2 next to the diagonal, with absolute rounding
+    eps |x|, about 1e-12 of it at these spacings)."""
+    absk = np.abs(kprime_gamma(edge, np.eye(edge.m)))          # |k_ij| w_j
+    scale = 1e-12 * absk.sum(axis=1)[:, None] * np.abs(edge.mu).max(axis=0)[None, : ref.shape[1]]
+    return float((np.abs(y - ref) / scale).max())
+
+
+@pytest.mark.parametrize("counts", [200, (75, 50)])
+def test_kprime_matches_oracle(ctx, counts):
+    from paper_2401_12501_amd import pmx
+    p = wavy_torus_piece_problem(n_u=4, n_v=6, q=6, n_edge=counts, variable_a=True, n_rhs=5)
+    e = p.meta["edge"]
+    E = pmx.Edge.from_inputs(ctx, e, 3)
+    y = E.kprime(np.ascontiguousarray(e.mu.T)).T
+    ref = kprime_gamma(e, e.mu)
+    err = kprime_err(y, ref, e)
+    say(f"[kprime] {counts}: error {err:.2f} of the bar, {col_err(y, ref):.2e} of the columns")
+    assert err <= 1
+
+
+def test_kprime_circle(ctx):
+    from paper_2401_12501_amd import pmx
+    n, rho = 40, 0.7
+    t = 2 * np.pi * np.arange(n) / n
+    x = np.stack([rho * np.cos(t), rho * np.sin(t), np.ones(n)], axis=1)
+    xt = np.stack([-rho * np.sin(t), rho * np.cos(t), 0 * t], axis=1)
+    d = np.stack([np.cos(t), np.sin(t), 0 * t], axis=1)
+    E = pmx.Edge(ctx, [n], x, xt, d, np.ones(n), np.zeros((n, 3)), 1)
+    assert np.abs(E.kprime(np.ones((1, n))) - 0.5).max() < 1e-14
