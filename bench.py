@@ -463,17 +463,33 @@ def edge_bench(args):
                      "frac": round(tf / PEAK["fp64_valu"], 4)}
         log(f"[bench] edge {kind}: {step_s * 1e3:.4f} ms/apply, pair kernel {pair_ms:.4f} ms, "
             f"{tf:.2f} TFLOP/s ({tf / PEAK['fp64_valu']:.3f} of FP64)")
-    # Section 7.5: error of R and T against the finest rule as the oversampling grows
+    # K'_gamma: targets on the curves (the samples), trapezoid rule on the samples
+    yk = torch.empty_like(mu)
+    for _ in range(args.warmup):
+        E.kprime(mu, out=yk)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        E.kprime(mu, out=yk)
+    torch.cuda.synchronize()
+    kp_ms = (time.perf_counter() - ts) / args.steps * 1e3
+    res["Kprime_gamma"] = {"ms": round(kp_ms, 4), "pairs": edge.m * edge.m}
+    log(f"[bench] edge K'_gamma at the {edge.m} samples: {kp_ms:.4f} ms/apply")
+    # Section 7.5: error of R and T against the finest rule as the oversampling grows, on this surface
+    # and on one refined twice across the band (its nodes twice as close to the curves)
     study = {}
-    for kind in ("R", "T"):
-        ref = pmx.Edge.from_inputs(ctx, edge, 128).apply(op, kind, mu).cpu().numpy()
-        errs = {}
-        for m in (1, 2, 4, 8, 16, 32, 64):
-            v = pmx.Edge.from_inputs(ctx, edge, m).apply(op, kind, mu).cpu().numpy()
-            errs[m] = float(np.abs(v - ref).max() / np.abs(ref).max())
-        study[kind] = {str(k): float(f"{v:.3g}") for k, v in errs.items()}
-        log(f"[bench] edge {kind} error vs oversampling (max over nodes, against m = 128): " +
-            ", ".join(f"m={k} {v:.2e}" for k, v in errs.items()))
+    fine_prob = wavy_torus_piece_problem(n_u=34, n_v=18, q=8, n_edge=200, variable_a=True, n_rhs=1)
+    fine_op = pmx.Operator(pmx.Surface.from_inputs(ctx, fine_prob.surface), fine_prob.a, fine_prob.grad_a)
+    for label, o in (("17x18", op), ("34x18", fine_op)):
+        for kind in ("R", "T"):
+            ref = pmx.Edge.from_inputs(ctx, edge, 128).apply(o, kind, mu).cpu().numpy()
+            errs = {}
+            for m in (1, 2, 4, 8, 16, 32, 64):
+                v = pmx.Edge.from_inputs(ctx, edge, m).apply(o, kind, mu).cpu().numpy()
+                errs[m] = float(np.abs(v - ref).max() / np.abs(ref).max())
+            study[f"{kind}_{label}"] = {str(k): float(f"{v:.3g}") for k, v in errs.items()}
+            log(f"[bench] edge {kind} on {label} patches, error vs oversampling (max over nodes, against m = 128): " +
+                ", ".join(f"m={k} {v:.2e}" for k, v in errs.items()))
     E.apply(op, "T", mu, out=y)
     y_t = y.cpu().numpy()[0]
     cpu, err = None, None
