@@ -639,7 +639,9 @@ pmx_status pmx_edge_create(pmx_ctx* ctx, int n_curves, const int64_t* n_samples,
     PMX_REQUIRE(M * oversample < ((int64_t)1 << 31), PMX_ERR_INVALID, "too many fine points");
     PMX_HIP(hipSetDevice(ctx->c.device));
     hipStream_t st = (hipStream_t)stream;
-    // the samples on the host (small): validated here, uploaded as 13 rows of M
+    // the samples on the host (small): validated here, uploaded as 13 rows of M; device arrays are
+    // read after the caller's stream has finished writing them
+    if (mem_kind == PMX_MEM_DEVICE) PMX_HIP(hipStreamSynchronize(st));
     std::vector<double> h3[4], ha(M);
     const double* src3[4] = {x, xt, d, grad_a};
     for (int k = 0; k < 4; ++k) {

@@ -438,6 +438,18 @@ class Edge:
 
     __del__ = close
 
+    def _n_rhs(self, mu) -> int:
+        size = mu.numel() if _is_torch(mu) else np.size(mu)
+        if size == 0 or size % self.M:
+            raise ValueError(f"mu must hold n_rhs rows of {self.M} values (got {size})")
+        return size // self.M
+
+    @staticmethod
+    def _check_out(out, size: int):
+        got = out.numel() if _is_torch(out) else np.size(out)
+        if got != size:
+            raise ValueError(f"out must hold {size} values (got {got})")
+
     def points(self) -> dict:
         """pmx_edge_export_points: the fine quadrature points (y, nu, w, a, nu . grad a)."""
         F = self.n_fine
@@ -449,18 +461,20 @@ class Edge:
     def apply(self, op: "Operator", kind: str, mu, out=None):
         """pmx_edge_apply: the edge operator ``kind`` (K, N, R or T) of mu (n_rhs, M) at the operator's
         nodes, (n_rhs, N); numpy arrays (host) or float64 CUDA tensors (device)."""
-        n_rhs = (mu.numel() if _is_torch(mu) else np.size(mu)) // self.M
+        n_rhs = self._n_rhs(mu)
         if out is None:
             out = np.empty((n_rhs, op.N)) if not _is_torch(mu) else mu.new_empty((n_rhs, op.N))
+        self._check_out(out, n_rhs * op.N)
         ptrs, kind_mem, stream, keep = _marshal(mu, out)
         _check(lib().pmx_edge_apply(op.h, self.h, EDGE_KINDS[kind], n_rhs, ptrs[0], ptrs[1], kind_mem, stream))
         return out
 
     def kprime(self, mu, out=None):
         """pmx_edge_apply_kprime: K'_gamma of mu (n_rhs, M) at the samples, (n_rhs, M)."""
-        n_rhs = (mu.numel() if _is_torch(mu) else np.size(mu)) // self.M
+        n_rhs = self._n_rhs(mu)
         if out is None:
             out = np.empty((n_rhs, self.M)) if not _is_torch(mu) else mu.new_empty((n_rhs, self.M))
+        self._check_out(out, n_rhs * self.M)
         ptrs, kind_mem, stream, keep = _marshal(mu, out)
         _check(lib().pmx_edge_apply_kprime(self.h, n_rhs, ptrs[0], ptrs[1], kind_mem, stream))
         return out

@@ -199,6 +199,10 @@ def test_edge_errors(ctx, piece):
     opc = pmx.Operator(piece.surf, p.a, p.grad_a, c=-np.ones(p.n))
     with pytest.raises(pmx.PmxError):
         E.apply(opc, "R", mu)
+    with pytest.raises(ValueError):
+        E.apply(piece.op, "R", mu[:, :-1])                               # not a multiple of M
+    with pytest.raises(ValueError):
+        E.apply(piece.op, "R", mu, out=np.empty((1, piece.op.N - 1)))     # output too small
 
 
 def test_full_band_sampled_rows(ctx):
