@@ -203,29 +203,33 @@ __global__ void __launch_bounds__(kBlock) k_edge_samples(CurveIdx c, int64_t M, 
 }
 
 // y[r][i] = sum_j w_j k(x_i, x_j) mu[r][j] over all samples, k the K'_gamma kernel (its limit at j = i).
-// One thread per (target sample, right-hand side): grid y is the right-hand side.
+// One wavefront per (target sample, right-hand side), four per workgroup, grid y the right-hand side:
+// lane l takes the samples j = l (mod 64) and a fixed shuffle tree adds the lanes' sums.
 __global__ void __launch_bounds__(kBlock) k_edge_kprime(int64_t M, const double* __restrict__ S,
                                                         const double* __restrict__ mu, double* __restrict__ y) {
   constexpr double kInv2Pi = 0.15915494309189533577;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
   const int64_t r = blockIdx.y;
-  if (i >= M) return;
+  if (i >= M) return;   // whole wavefronts leave together
   const double xi = S[i], yi = S[M + i], zi = S[2 * M + i];
   const double n0 = S[3 * M + i], n1 = S[4 * M + i], n2 = S[5 * M + i];
   const double* __restrict__ m = mu + r * M;
   double acc = 0.0;
-  for (int64_t j = 0; j < M; ++j) {
+  for (int64_t j = lane; j < M; j += 64) {
     double val;
     if (j == i) {
       val = S[8 * M + i];
     } else {
       const double dx = xi - S[j], dy = yi - S[M + j], dz = zi - S[2 * M + j];
-      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      val = kInv2Pi * fma(n0, dx, fma(n1, dy, n2 * dz)) / (S[6 * M + j] * r2);
+      const double den = S[6 * M + j] * fma(dx, dx, fma(dy, dy, dz * dz));
+      val = kInv2Pi * fma(n0, dx, fma(n1, dy, n2 * dz)) * rcp_nr(den);
     }
     acc = fma(S[7 * M + j] * m[j], val, acc);
   }
-  y[r * M + i] = acc;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) y[r * M + i] = acc;
 }
 
 // Row of a packed source: y (3), nu (3), beta, NR weighted densities, padded to an even length.
@@ -421,7 +425,8 @@ void edge_apply(pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double*
 }
 
 void edge_apply_kprime(EdgeSet& E, int n_rhs, const double* mu, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_edge_kprime, dim3(nblk(E.M), n_rhs), dim3(kBlock), 0, st, E.M, E.samp.p, mu, y);
+  hipLaunchKernelGGL(k_edge_kprime, dim3((E.M + kBlock / 64 - 1) / (kBlock / 64), n_rhs), dim3(kBlock), 0, st, E.M,
+                     E.samp.p, mu, y);
   PMX_HIP(hipGetLastError());
 }
 
