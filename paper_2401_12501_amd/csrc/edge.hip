@@ -70,12 +70,16 @@ __global__ void __launch_bounds__(kBlock) k_edge_table(CurveIdx c, int64_t Mf, d
   const int64_t i = g - c.foff[k];
   const int64_t n = c.off[k + 1] - c.off[k];
   const int m = c.m;
+  // D is even in tau: evaluate at the smaller of i and m n - i, so that tau / (2 pi) <= 1/2 and sinpi
+  // of it keeps its relative accuracy (near tau = 2 pi the rounding of i / (m n) would cost about
+  // eps m n relative in the weights of the nearest samples)
+  const int64_t ie = i <= m * n - i ? i : m * n - i;
   double v;
-  if (i % m == 0) {
-    v = i == 0 ? 1.0 : 0.0;
+  if (ie % m == 0) {
+    v = ie == 0 ? 1.0 : 0.0;
   } else {
-    const double s = sinpi((double)(i % (2 * m)) / m);          // sin(n tau / 2), tau = 2 pi i / (m n)
-    const double h = (double)i / (double)(m * n);                // tau / (2 pi)
+    const double s = sinpi((double)(ie % (2 * m)) / m);         // sin(n tau / 2), tau = 2 pi ie / (m n)
+    const double h = (double)ie / (double)(m * n);               // tau / (2 pi)
     v = (n % 2 == 0) ? s * cospi(h) / (n * sinpi(h)) : s / (n * sinpi(h));
   }
   D[g] = v;
@@ -176,8 +180,10 @@ __global__ void __launch_bounds__(kBlock) k_edge_samples(CurveIdx c, int64_t M, 
   for (int64_t q = 0; q < n; ++q) {
     const int64_t l = (jl - q + n) % n;
     if (l == 0) continue;
-    const double h = (double)l / (double)n;
-    const double sgn = (l & 1) ? -0.5 : 0.5;
+    // D1 is odd in l (D1(n - l) = -D1(l)): evaluate at the smaller of l and n - l (as for D above)
+    const int64_t le = l <= n - l ? l : n - l;
+    const double h = (double)le / (double)n;
+    const double sgn = ((le & 1) ? -0.5 : 0.5) * (le == l ? 1.0 : -1.0);
     const double wd = (n % 2 == 0) ? sgn * cospi(h) / sinpi(h) : sgn / sinpi(h);
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) tt[cc] = fma(wd, F[(3 + cc) * M + base + q], tt[cc]);
