@@ -306,3 +306,28 @@ def test_largest_call_1024_densities(ctx, piece):
     yk = E.kprime(mu)
     for c in (0, 1023):
         assert np.array_equal(E.kprime(mu[c:c + 1])[0], yk[c]), c
+
+
+@pytest.mark.parametrize("kind", ["K", "T"])
+def test_three_curves(ctx, piece, kind):
+    """The band's two circles (200 samples each) and a third, smaller circle of 31 samples beside the band
+    (far from the surface): three curves of two sizes in one edge object, against the oracle."""
+    from paper_2401_12501_amd import pmx
+    e = piece.edge
+    t = 2 * np.pi * np.arange(31) / 31
+    x3 = np.stack([0.5 + 0.3 * np.cos(t), 3.5 + 0.3 * np.sin(t), 0.2 + 0 * t], axis=1)
+    xt3 = np.stack([-0.3 * np.sin(t), 0.3 * np.cos(t), 0 * t], axis=1)
+    d3 = np.stack([np.cos(t), np.sin(t), 0 * t], axis=1)
+    a3 = np.exp(0.3 * x3[:, 0] * x3[:, 1])
+    ga3 = 0.3 * a3[:, None] * np.stack([x3[:, 1], x3[:, 0], 0 * t], axis=1)
+    mu3 = np.random.default_rng(71).normal(size=(31, e.mu.shape[1]))
+    e3 = EdgeSamples(np.concatenate([e.x, x3]), np.concatenate([e.xt, xt3]), np.concatenate([e.d, d3]),
+                     np.concatenate([e.a, a3]), np.concatenate([e.grad_a, ga3]), np.concatenate([e.mu, mu3]),
+                     np.array([0, 200, 400, 431]))
+    E = pmx.Edge.from_inputs(ctx, e3, 8)
+    assert E.M == 431 and E.n_fine == 3448
+    y = E.apply(piece.op, kind, np.ascontiguousarray(e3.mu.T)).T
+    ref = edge_apply(kind, piece.tgt, e3, e3.mu, 8)
+    assert sum_err(y, ref, kind, piece.tgt, e3, 8) <= 1
+    yk = E.kprime(np.ascontiguousarray(e3.mu.T)).T
+    assert kprime_err(yk, kprime_gamma(e3, e3.mu), e3) <= 1
