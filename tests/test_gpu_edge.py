@@ -9,7 +9,9 @@ whose nodes all lie inside an ellipse in their plane, where N_gamma[1] = 1 and R
 hold exactly (independently of the oracle); device arrays; argument errors; and the 19,584-node band
 with 25,600 fine points (the benchmark's workload) at 256 stratified targets.  K'_gamma (targets on the
 curves, the trapezoid rule on the samples with the kernel's diagonal limit) against the oracle on the
-same curves (200 and 200, 75 and 50 samples, five densities), and K'_gamma[1] = 1/2 on a circle.
+same curves (200 and 200, 75 and 50 samples, five densities), and K'_gamma[1] = 1/2 on a circle.  Lemma
+lem:surf_term and Lemma lem:Dirichlet_surf_term from the library's outputs alone: div_G(a grad_G .) of
+K_gamma[mu] and N_gamma[mu] (spectral differentiation on the patches) equals R_gamma[mu] and T_gamma[mu].
 Bar, per element: (1e-13 + kappa delta / r_i) sum_p |k(x_i, y_p)| w_p max|mu|.  The sum of absolute
 terms is the scale of a sum whose terms cancel (near the curve, while the oversampling has not resolved
 the near singularity, the terms of R and T reach 1e4 times the result).  The second part is the
@@ -331,3 +333,26 @@ def test_three_curves(ctx, piece, kind):
     assert sum_err(y, ref, kind, piece.tgt, e3, 8) <= 1
     yk = E.kprime(np.ascontiguousarray(e3.mu.T)).T
     assert kprime_err(yk, kprime_gamma(e3, e3.mu), e3) <= 1
+
+
+def test_lemmas_on_the_gpu(ctx):
+    """Lemma lem:surf_term and Lemma lem:Dirichlet_surf_term from the library's own outputs, no oracle:
+    div_G(a grad_G .) of K_gamma[mu] and N_gamma[mu] (spectral differentiation of the applies' nodal values
+    on the middle row of the band, 12 x 12 patches of 12 x 12 nodes) equals R_gamma[mu] and T_gamma[mu]
+    within 1e-6 (the differentiation error of this patch order)."""
+    from paper_2401_12501_amd import pmx
+    from _surface_ops import middle_row_nodes, surface_operator
+    p = wavy_torus_piece_problem(n_u=12, n_v=12, q=12, n_edge=200, variable_a=True)
+    e = p.meta["edge"]
+    op = pmx.Operator(pmx.Surface.from_inputs(ctx, p.surface), p.a, p.grad_a)
+    E = pmx.Edge.from_inputs(ctx, e, 16)
+    mu = np.ascontiguousarray(e.mu.T)
+    v = {k: E.apply(op, k, mu)[0] for k in "KNRT"}
+    idx = middle_row_nodes(12, 12, 12)
+    s = p.surface
+    DK = surface_operator(v["K"][idx], p.a[idx], s.xu[idx], s.xv[idx], 12)
+    DN = surface_operator(v["N"][idx], p.a[idx], s.xu[idx], s.xv[idx], 12)
+    eK = np.abs(DK - v["R"][idx]).max() / np.abs(v["R"][idx]).max()
+    eN = np.abs(DN - v["T"][idx]).max() / np.abs(v["T"][idx]).max()
+    say(f"[edge lemmas] |D K - R| {eK:.2e}, |D N - T| {eN:.2e}")
+    assert eK < 1e-6 and eN < 1e-6

@@ -16,6 +16,9 @@ against facts that do not come from the oracle's own formulas:
   the exact curve, with the conormal built independently as n x tau;
 * Section 7.5's observation: the error at targets near the edge falls quickly once the oversampling
   resolves the near singularity;
+* Lemma lem:surf_term and Lemma lem:Dirichlet_surf_term: away from the boundary, div_G(a grad_G .)
+  applied to K_gamma[mu] and N_gamma[mu] (spectral differentiation on the patches) gives R_gamma[mu] and
+  T_gamma[mu], with an error that falls spectrally in the patch order;
 * K'_gamma (targets on gamma): on a circle of radius rho in a plane with a = 1 the kernel is the
   constant 1 / (4 pi rho), so K'_gamma[1] = 1/2 at every sample; the diagonal limit equals the kernel
   at nearby points of the exact curve; the trapezoid sums on an ellipse and on the wavy-torus circles
@@ -314,3 +317,27 @@ def test_kprime_torus_circles_match_adaptive_quadrature():
             ref += _kprime_exact(e.x[j], nu[j], lambda t, th0=th0: _curve(th0, t)[:2], _a, lambda y: math.exp(y[0]),
                                  t0 if c == own else 0.0)
         assert abs(v[j] - ref) < 1e-11 * max(1.0, abs(ref)), (j, v[j], ref)
+
+
+# ------------------------------------------------------------------ the lemmas: D K_gamma = R_gamma, D N_gamma = T_gamma
+def _lemma_errors(n_u, q):
+    from _surface_ops import middle_row_nodes, surface_operator
+    p = wavy_torus_piece_problem(n_u=n_u, n_v=12, q=q, n_edge=200, variable_a=True)
+    tgt = targets_of(OracleOperator.from_problem(p))
+    e = p.meta["edge"]
+    idx = middle_row_nodes(n_u, 12, q)
+    v = {k: edge_apply(k, tgt, e, e.mu, 16, targets=idx)[:, 0] for k in "KNRT"}
+    s = p.surface
+    DK = surface_operator(v["K"], p.a[idx], s.xu[idx], s.xv[idx], q)
+    DN = surface_operator(v["N"], p.a[idx], s.xu[idx], s.xv[idx], q)
+    return (np.abs(DK - v["R"]).max() / np.abs(v["R"]).max(), np.abs(DN - v["T"]).max() / np.abs(v["T"]).max())
+
+
+def test_surface_operator_of_edge_potentials():
+    """div_G(a grad_G K_gamma[mu]) = R_gamma[mu] and div_G(a grad_G N_gamma[mu]) = T_gamma[mu] in the
+    interior (the lemmas), on the middle row of the band, 12 x 12 patches of 12 x 12 nodes; and the
+    differentiation error falls spectrally with the patch order (q = 10 to 14 on 8 rows)."""
+    eK, eN = _lemma_errors(12, 12)
+    assert eK < 1e-6 and eN < 1e-6, (eK, eN)
+    lo, hi = _lemma_errors(8, 10), _lemma_errors(8, 14)
+    assert hi[0] < lo[0] / 100 and hi[1] < lo[1] / 100, (lo, hi)
