@@ -1,0 +1,67 @@
+"""The identity the method rests on, from the library's outputs alone (no oracle): on a closed surface the
+representation u = K[sigma] and the operator satisfy (div_G(a grad_G) + c) K[sigma] = sigma + R[sigma]
+(eq:diff_repr with no boundary; Theorem thm:parametrix, Theorem thm:second_kind).  The FP64 apply returns
+y = sigma + R sigma + int sigma for c = 0 (the rank-one term, a constant) and y = sigma + R sigma for
+c < 0; pmx_represent returns K[sigma] less its weighted mean for c = 0 (a constant, which the operator
+annihilates) and K[sigma] for c < 0.  The operator is applied to the nodal values of u by spectral
+differentiation on the patches (tests/_surface_ops.py).
+
+Workloads: the ellipsoid (1, 0.8, 0.6) as cube-spheres with k = 3, 4, 6 patches per face edge and
+q = 10, a = exp(0.3 x1 x2) (c = 0), or a = 2 + x3 with c = -4 - exp(x1 / 2) (c < 0) or c = 2 (1 + 0.2 x2)
+(c > 0: u, y complex, the real operator applied to both parts), and the smooth density
+sigma = cos(1.3 x1) + x2 x3 + 1/2.  The differentiation error falls spectrally under refinement;
+the bar: below 1e-6 of the largest value on the finest surface, and at least 30 times smaller there
+than on the coarsest.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from _surface_ops import surface_operator
+from paper_2401_12501_amd.inputs import ellipsoid_problem, helmholtz_ellipsoid_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2401_12501_amd import pmx
+    return pmx.Context(0)
+
+
+def identity_error(ctx, k, case):
+    from paper_2401_12501_amd import pmx
+    if case == "c0":
+        p = ellipsoid_problem(k=k, q=10)
+    else:
+        p = helmholtz_ellipsoid_problem(k=k, q=10, positive=case == "cpos")
+    s = p.surface
+    surf = pmx.Surface.from_inputs(ctx, s)
+    op = pmx.Operator(surf, p.a, p.grad_a) if case == "c0" else pmx.Operator(surf, p.a, p.grad_a, c=p.c)
+    sig = (np.cos(1.3 * s.x[:, 0]) + s.x[:, 1] * s.x[:, 2] + 0.5)[None, :].copy()
+    if case == "cpos":
+        sig = sig.astype(np.complex128)
+    y = op.apply(sig, pmx.PMX_PREC_FP64_DIRECT)[0]
+    u = op.represent(sig)[0]
+    D = lambda v: surface_operator(v, p.a, s.xu, s.xv, s.q)
+    if case == "c0":
+        w = op.export_geometry()["w"]
+        lhs, rhs = D(u), y - w @ sig[0]
+    elif case == "cneg":
+        lhs, rhs = D(u) + p.c * u, y
+    else:
+        lhs, rhs = D(u.real) + 1j * D(u.imag) + p.c * u, y
+    return float(np.abs(lhs - rhs).max() / np.abs(rhs).max())
+
+
+@pytest.mark.parametrize("case", ["c0", "cneg", "cpos"])
+def test_parametrix_identity_from_library_outputs(ctx, case):
+    errs = [identity_error(ctx, k, case) for k in (3, 4, 6)]
+    say(f"[identity] {case}: k = 3, 4, 6: " + ", ".join(f"{e:.2e}" for e in errs))
+    assert errs[-1] < 1e-6 and errs[-1] < errs[0] / 30, errs
