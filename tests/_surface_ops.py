@@ -39,6 +39,25 @@ def surface_operator(u, a, xu, xv, q: int) -> np.ndarray:
     return out
 
 
+def advection_term(u, b, xu, xv, q: int) -> np.ndarray:
+    """b . grad_G u at the nodes (grad_G u = g^ij d_j u x_i, tangent; b ambient, so only its tangential
+    part counts)."""
+    t, _ = np.polynomial.legendre.leggauss(q)
+    D = diff_matrix(t)
+    out = np.empty_like(u)
+    for p in range(u.shape[0] // (q * q)):
+        s = slice(p * q * q, (p + 1) * q * q)
+        U = u[s].reshape(q, q)
+        Xu, Xv, B = xu[s].reshape(q, q, 3), xv[s].reshape(q, q, 3), b[s].reshape(q, q, 3)
+        E, F, G = (Xu * Xu).sum(-1), (Xu * Xv).sum(-1), (Xv * Xv).sum(-1)
+        g = E * G - F * F
+        Uu, Uv = D @ U, U @ D.T
+        cu = (G * Uu - F * Uv) / g          # contravariant components g^uj d_j u, g^vj d_j u
+        cv = (-F * Uu + E * Uv) / g
+        out[s] = ((B * Xu).sum(-1) * cu + (B * Xv).sum(-1) * cv).ravel()
+    return out
+
+
 def middle_row_nodes(n_u: int, n_v: int, q: int, cols=(0, 3, 6, 9)) -> np.ndarray:
     """Node indices of a few patches of the band's middle row of patches (farthest from its edges)."""
     row = n_u // 2

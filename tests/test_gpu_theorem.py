@@ -8,8 +8,9 @@ differentiation on the patches (tests/_surface_ops.py).
 
 Workloads: the ellipsoid (1, 0.8, 0.6) as cube-spheres with k = 3, 4, 6 patches per face edge and
 q = 10, a = exp(0.3 x1 x2) (c = 0), or a = 2 + x3 with c = -4 - exp(x1 / 2) (c < 0) or c = 2 (1 + 0.2 x2)
-(c > 0: u, y complex, the real operator applied to both parts), and the smooth density
-sigma = cos(1.3 x1) + x2 x3 + 1/2.  The differentiation error falls spectrally under refinement;
+(c > 0: u, y complex, the real operator applied to both parts), c < 0 with the advection field
+b = (0.6 - x2, x1 + 0.4 x3, 0.5 x1 x2) (the operator gains b . grad_G, eq:adv_remainder), and the smooth
+density sigma = cos(1.3 x1) + x2 x3 + 1/2.  The differentiation error falls spectrally under refinement;
 the bar: below 1e-6 of the largest value on the finest surface, and at least 30 times smaller there
 than on the coarsest.
 """
@@ -18,7 +19,7 @@ import sys
 import numpy as np
 import pytest
 
-from _surface_ops import surface_operator
+from _surface_ops import advection_term, surface_operator
 from paper_2401_12501_amd.inputs import ellipsoid_problem, helmholtz_ellipsoid_problem
 
 pytestmark = pytest.mark.gpu
@@ -40,10 +41,10 @@ def identity_error(ctx, k, case):
     if case == "c0":
         p = ellipsoid_problem(k=k, q=10)
     else:
-        p = helmholtz_ellipsoid_problem(k=k, q=10, positive=case == "cpos")
+        p = helmholtz_ellipsoid_problem(k=k, q=10, positive=case == "cpos", swirl=case == "cneg_b")
     s = p.surface
     surf = pmx.Surface.from_inputs(ctx, s)
-    op = pmx.Operator(surf, p.a, p.grad_a) if case == "c0" else pmx.Operator(surf, p.a, p.grad_a, c=p.c)
+    op = pmx.Operator(surf, p.a, p.grad_a) if case == "c0" else pmx.Operator(surf, p.a, p.grad_a, c=p.c, b=p.b)
     sig = (np.cos(1.3 * s.x[:, 0]) + s.x[:, 1] * s.x[:, 2] + 0.5)[None, :].copy()
     if case == "cpos":
         sig = sig.astype(np.complex128)
@@ -55,12 +56,14 @@ def identity_error(ctx, k, case):
         lhs, rhs = D(u), y - w @ sig[0]
     elif case == "cneg":
         lhs, rhs = D(u) + p.c * u, y
+    elif case == "cneg_b":
+        lhs, rhs = D(u) + advection_term(u, p.b, s.xu, s.xv, s.q) + p.c * u, y
     else:
         lhs, rhs = D(u.real) + 1j * D(u.imag) + p.c * u, y
     return float(np.abs(lhs - rhs).max() / np.abs(rhs).max())
 
 
-@pytest.mark.parametrize("case", ["c0", "cneg", "cpos"])
+@pytest.mark.parametrize("case", ["c0", "cneg", "cpos", "cneg_b"])
 def test_parametrix_identity_from_library_outputs(ctx, case):
     errs = [identity_error(ctx, k, case) for k in (3, 4, 6)]
     say(f"[identity] {case}: k = 3, 4, 6: " + ", ".join(f"{e:.2e}" for e in errs))
