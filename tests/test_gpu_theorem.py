@@ -68,3 +68,38 @@ def test_parametrix_identity_from_library_outputs(ctx, case):
     errs = [identity_error(ctx, k, case) for k in (3, 4, 6)]
     say(f"[identity] {case}: k = 3, 4, 6: " + ", ".join(f"{e:.2e}" for e in errs))
     assert errs[-1] < 1e-6 and errs[-1] < errs[0] / 30, errs
+
+
+@pytest.mark.parametrize("case", ["c0_fp64", "c0_mixed", "cneg_fp64"])
+def test_solution_satisfies_the_pde(ctx, case):
+    """The solve path end to end: sigma from pmx_solve and u = K[sigma] from its representation satisfy
+    the PDE at the nodes, div_G(a grad_G u) + c u = f - mean_w(f) for c = 0 (integrating the equation
+    gives int sigma = 0, so the rank-one term drops) and = f for c < 0; 20 solid harmonics as f on the
+    k = 6 ellipsoid (q = 10).  FP64 GMRES to 1e-12 or mixed-precision refinement to 1e-8; the bar is the
+    differentiation error of the identity above (below 1e-6) plus the solve's tolerance."""
+    from paper_2401_12501_amd import pmx
+    with_c = case.startswith("cneg")
+    p = helmholtz_ellipsoid_problem(k=6, q=10) if with_c else ellipsoid_problem(k=6, q=10)
+    s = p.surface
+    op = pmx.Operator(pmx.Surface.from_inputs(ctx, s), p.a, p.grad_a, c=p.c) if with_c else \
+        pmx.Operator(pmx.Surface.from_inputs(ctx, s), p.a, p.grad_a)
+    o = pmx.pmx_default_options()
+    if case.endswith("mixed"):
+        o.precision = pmx.PMX_PREC_MIXED_FMM
+        o.ir_tol = 1e-8
+    else:
+        o.precision = pmx.PMX_PREC_FP64_DIRECT
+        o.gmres_tol = 1e-12
+    f = np.ascontiguousarray(p.f.T)
+    sig, u, info = op.solve(f, o, want_u=True)
+    u = u[0]
+    lhs = surface_operator(u, p.a, s.xu, s.xv, s.q)
+    if with_c:
+        lhs = lhs + p.c * u
+        rhs = f[0]
+    else:
+        w = op.export_geometry()["w"]
+        rhs = f[0] - (w @ f[0]) / w.sum()
+    err = float(np.abs(lhs - rhs).max() / np.abs(rhs).max())
+    say(f"[pde] {case}: {info[0].iters_total} iterations, residual {info[0].rel_residual:.1e}, PDE error {err:.2e}")
+    assert err < 1e-6 + (1e-8 if case.endswith("mixed") else 1e-12) * 100
