@@ -356,3 +356,28 @@ def test_lemmas_on_the_gpu(ctx):
     eN = np.abs(DN - v["T"][idx]).max() / np.abs(v["T"][idx]).max()
     say(f"[edge lemmas] |D K - R| {eK:.2e}, |D N - T| {eN:.2e}")
     assert eK < 1e-6 and eN < 1e-6
+
+
+def test_neumann_jump_relation_on_the_gpu(ctx):
+    """Theorem thm:NeumannBCsrep for the curve potential, from the library's outputs alone: the conormal
+    derivative of the GPU's K_gamma[mu] on the band's last row of patches (16 x 16 nodes), extrapolated to
+    the circle u = 2 pi, equals -mu / (2a) + the GPU's K'_gamma[mu] there (interpolated along the circle)
+    to 1e-8."""
+    from paper_2401_12501_amd import pmx
+    from _surface_ops import conormal_derivative_at_edge, trig_eval
+    n_u, n_v, q = 8, 12, 16
+    p = wavy_torus_piece_problem(n_u=n_u, n_v=n_v, q=q, n_edge=200, variable_a=True)
+    e = p.meta["edge"]
+    op = pmx.Operator(pmx.Surface.from_inputs(ctx, p.surface), p.a, p.grad_a)
+    E = pmx.Edge.from_inputs(ctx, e, 64)
+    mu = np.ascontiguousarray(e.mu.T)
+    Kv = E.apply(op, "K", mu)[0]
+    Kp = E.kprime(mu)[0][200:400]
+    patches = [(n_u - 1) * n_v + c for c in range(n_v)]
+    idx = np.concatenate([np.arange(P * q * q, (P + 1) * q * q) for P in patches])
+    s = p.surface
+    lhs, tq, xe = conormal_derivative_at_edge(Kv[idx], s.xu[idx], s.xv[idx], s.x[idx], q, patches, n_v)
+    rhs = -np.exp(xe[:, 0]) / (2 * np.exp(0.3 * xe[:, 0] * xe[:, 1])) + trig_eval(Kp, tq)
+    err = float(np.abs(lhs - rhs).max() / np.abs(rhs).max())
+    say(f"[edge jump] {err:.2e}")
+    assert err < 1e-8

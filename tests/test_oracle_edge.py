@@ -19,6 +19,9 @@ against facts that do not come from the oracle's own formulas:
 * Lemma lem:surf_term and Lemma lem:Dirichlet_surf_term: away from the boundary, div_G(a grad_G .)
   applied to K_gamma[mu] and N_gamma[mu] (spectral differentiation on the patches) gives R_gamma[mu] and
   T_gamma[mu], with an error that falls spectrally in the patch order;
+* Theorem thm:NeumannBCsrep for the curve potential: the conormal derivative of K_gamma[mu] on the
+  surface side, extrapolated to gamma, equals -mu / (2a) + K'_gamma[mu] (the jump and the edge-to-edge
+  operator of the Neumann row), the error falling spectrally with the patch order;
 * K'_gamma (targets on gamma): on a circle of radius rho in a plane with a = 1 the kernel is the
   constant 1 / (4 pi rho), so K'_gamma[1] = 1/2 at every sample; the diagonal limit equals the kernel
   at nearby points of the exact curve; the trapezoid sums on an ellipse and on the wavy-torus circles
@@ -341,3 +344,30 @@ def test_surface_operator_of_edge_potentials():
     assert eK < 1e-6 and eN < 1e-6, (eK, eN)
     lo, hi = _lemma_errors(8, 10), _lemma_errors(8, 14)
     assert hi[0] < lo[0] / 100 and hi[1] < lo[1] / 100, (lo, hi)
+
+
+def _jump_error(q, K_fn, Kp_fn):
+    """max |nu . grad K_gamma[mu] at gamma - (-mu / 2a + K'_gamma[mu])| / max|...| on the band's upper
+    circle (u = 2 pi, the last row of patches), mu = exp(x1), a = exp(0.3 x1 x2); K_fn(problem, node
+    indices) and Kp_fn(problem) supply the two operators' values."""
+    from _surface_ops import conormal_derivative_at_edge, trig_eval
+    n_u, n_v = 8, 12
+    p = wavy_torus_piece_problem(n_u=n_u, n_v=n_v, q=q, n_edge=200, variable_a=True)
+    patches = [(n_u - 1) * n_v + c for c in range(n_v)]
+    idx = np.concatenate([np.arange(P * q * q, (P + 1) * q * q) for P in patches])
+    s = p.surface
+    lhs, tq, xe = conormal_derivative_at_edge(K_fn(p, idx), s.xu[idx], s.xv[idx], s.x[idx], q, patches, n_v)
+    Kp = Kp_fn(p)[200:400]                     # the upper circle's samples
+    rhs = -np.exp(xe[:, 0]) / (2 * np.exp(0.3 * xe[:, 0] * xe[:, 1])) + trig_eval(Kp, tq)
+    return float(np.abs(lhs - rhs).max() / np.abs(rhs).max())
+
+
+def test_neumann_jump_relation():
+    def K_fn(p, idx):
+        return edge_apply("K", targets_of(OracleOperator.from_problem(p)), p.meta["edge"], p.meta["edge"].mu, 64,
+                          targets=idx)[:, 0]
+
+    def Kp_fn(p):
+        return kprime_gamma(p.meta["edge"], p.meta["edge"].mu)[:, 0]
+    lo, hi = _jump_error(12, K_fn, Kp_fn), _jump_error(16, K_fn, Kp_fn)
+    assert hi < 1e-8 and hi < lo / 100, (lo, hi)
