@@ -381,3 +381,37 @@ def test_neumann_jump_relation_on_the_gpu(ctx):
     err = float(np.abs(lhs - rhs).max() / np.abs(rhs).max())
     say(f"[edge jump] {err:.2e}")
     assert err < 1e-8
+
+
+def test_dirichlet_jump_relation_on_the_gpu(ctx):
+    """The double-layer jump for the Dirichlet representation (eq:DirichletRep) with a = 1 (where
+    nu . grad a = 0 and the on-curve kernel is smooth): the GPU's N_gamma[mu] on the band's last row,
+    extrapolated to the circle u = 2 pi, equals +mu / (2a) + D_gamma[mu] there, D_gamma the double layer
+    on the circle (trapezoid rule with its diagonal limit), to 1e-8.  The sign is the one K = log r /
+    (2 pi a) and the outward conormal fix (N_gamma[1] = 1 inside a planar curve, 1/2 on it); the printed
+    eq:DirBVPsystem has -mu / (2a) (a reading: its sign, or an inward conormal there)."""
+    from paper_2401_12501_amd import pmx
+    from oracle.edge import conormal
+    from _surface_ops import double_layer_on_curve, trig_eval, values_at_edge
+    n_u, n_v, q = 8, 12, 16
+    p = wavy_torus_piece_problem(n_u=n_u, n_v=n_v, q=q, n_edge=200, variable_a=False)
+    e = p.meta["edge"]
+    op = pmx.Operator(pmx.Surface.from_inputs(ctx, p.surface), p.a, p.grad_a)
+    E = pmx.Edge.from_inputs(ctx, e, 64)
+    Nv = E.apply(op, "N", np.ascontiguousarray(e.mu.T))[0]
+    patches = [(n_u - 1) * n_v + c for c in range(n_v)]
+    idx = np.concatenate([np.arange(P * q * q, (P + 1) * q * q) for P in patches])
+    lhs, tq = values_at_edge(Nv[idx], q, patches, n_v)
+    up = slice(200, 400)
+    # the potential of both circles: the lower one is smooth at the upper circle (plain trapezoid sum)
+    nu_all = conormal(e.xt, e.d)
+    D_up = double_layer_on_curve(e.x[up], e.xt[up], nu_all[up], e.a[up], e.mu[up, 0])
+    lo = slice(0, 200)
+    r = e.x[lo][None, :, :] - e.x[up][:, None, :]
+    w_lo = 2 * np.pi / 200 * np.linalg.norm(e.xt[lo], axis=1)
+    D_lo = ((nu_all[lo][None] * r).sum(-1) / (2 * np.pi * e.a[lo][None] * (r * r).sum(-1))) @ (w_lo * e.mu[lo, 0])
+    rhs_samples = e.mu[up, 0] / (2 * e.a[up]) + D_up + D_lo
+    rhs = trig_eval(rhs_samples, tq)
+    err = float(np.abs(lhs - rhs).max() / np.abs(rhs).max())
+    say(f"[edge dirichlet jump] {err:.2e}")
+    assert err < 1e-8

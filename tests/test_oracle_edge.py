@@ -22,6 +22,9 @@ against facts that do not come from the oracle's own formulas:
 * Theorem thm:NeumannBCsrep for the curve potential: the conormal derivative of K_gamma[mu] on the
   surface side, extrapolated to gamma, equals -mu / (2a) + K'_gamma[mu] (the jump and the edge-to-edge
   operator of the Neumann row), the error falling spectrally with the patch order;
+* the double-layer jump for the Dirichlet representation (a = 1): N_gamma[mu] extrapolated to gamma
+  equals +mu / (2a) + D_gamma[mu] (D_gamma the double layer on the curve), the sign fixed by
+  K = log r / (2 pi a) and the outward conormal;
 * K'_gamma (targets on gamma): on a circle of radius rho in a plane with a = 1 the kernel is the
   constant 1 / (4 pi rho), so K'_gamma[1] = 1/2 at every sample; the diagonal limit equals the kernel
   at nearby points of the exact curve; the trapezoid sums on an ellipse and on the wavy-torus circles
@@ -371,3 +374,25 @@ def test_neumann_jump_relation():
         return kprime_gamma(p.meta["edge"], p.meta["edge"].mu)[:, 0]
     lo, hi = _jump_error(12, K_fn, Kp_fn), _jump_error(16, K_fn, Kp_fn)
     assert hi < 1e-8 and hi < lo / 100, (lo, hi)
+
+
+def test_dirichlet_jump_relation():
+    from _surface_ops import double_layer_on_curve, trig_eval, values_at_edge
+    errs = []
+    for q in (12, 16):
+        n_u, n_v = 8, 12
+        p = wavy_torus_piece_problem(n_u=n_u, n_v=n_v, q=q, n_edge=200, variable_a=False)
+        e = p.meta["edge"]
+        patches = [(n_u - 1) * n_v + c for c in range(n_v)]
+        idx = np.concatenate([np.arange(P * q * q, (P + 1) * q * q) for P in patches])
+        Nv = edge_apply("N", targets_of(OracleOperator.from_problem(p)), e, e.mu, 64, targets=idx)[:, 0]
+        lhs, tq = values_at_edge(Nv, q, patches, n_v)
+        up, lo = slice(200, 400), slice(0, 200)
+        nu_all = conormal(e.xt, e.d)
+        D_up = double_layer_on_curve(e.x[up], e.xt[up], nu_all[up], e.a[up], e.mu[up, 0])
+        r = e.x[lo][None, :, :] - e.x[up][:, None, :]
+        w_lo = 2 * np.pi / 200 * np.linalg.norm(e.xt[lo], axis=1)
+        D_lo = ((nu_all[lo][None] * r).sum(-1) / (2 * np.pi * e.a[lo][None] * (r * r).sum(-1))) @ (w_lo * e.mu[lo, 0])
+        rhs = trig_eval(e.mu[up, 0] / (2 * e.a[up]) + D_up + D_lo, tq)
+        errs.append(float(np.abs(lhs - rhs).max() / np.abs(rhs).max()))
+    assert errs[1] < 1e-10 and errs[1] < errs[0] / 100, errs
