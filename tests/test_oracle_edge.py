@@ -356,7 +356,7 @@ def _jump_error(q, K_fn, Kp_fn):
     from _surface_ops import conormal_derivative_at_edge, trig_eval
     n_u, n_v = 8, 12
     p = wavy_torus_piece_problem(n_u=n_u, n_v=n_v, q=q, n_edge=200, variable_a=True)
-    patches = [(n_u - 1) * n_v + c for c in range(n_v)]
+    patches = [(n_u - 1) * n_v + c for c in (0, 5, 9)]      # three patches of the last row
     idx = np.concatenate([np.arange(P * q * q, (P + 1) * q * q) for P in patches])
     s = p.surface
     lhs, tq, xe = conormal_derivative_at_edge(K_fn(p, idx), s.xu[idx], s.xv[idx], s.x[idx], q, patches, n_v)
@@ -383,7 +383,7 @@ def test_dirichlet_jump_relation():
         n_u, n_v = 8, 12
         p = wavy_torus_piece_problem(n_u=n_u, n_v=n_v, q=q, n_edge=200, variable_a=False)
         e = p.meta["edge"]
-        patches = [(n_u - 1) * n_v + c for c in range(n_v)]
+        patches = [(n_u - 1) * n_v + c for c in (0, 5, 9)]  # three patches of the last row
         idx = np.concatenate([np.arange(P * q * q, (P + 1) * q * q) for P in patches])
         Nv = edge_apply("N", targets_of(OracleOperator.from_problem(p)), e, e.mu, 64, targets=idx)[:, 0]
         lhs, tq = values_at_edge(Nv, q, patches, n_v)
