@@ -358,6 +358,16 @@ PMX_API pmx_status pmx_edge_apply(pmx_operator* op, pmx_edge* e, int kind, int n
  * memory.  Errors: INVALID (null argument, n_rhs outside [1, 1024]), OOM, DEVICE. */
 PMX_API pmx_status pmx_edge_apply_kprime(pmx_edge* e, int n_rhs, const double* mu, double* y, int mem_kind,
                                          void* stream);
+/* y = D_gamma[mu] at the M samples: the double layer on the curves, D_gamma[mu](x) = int_gamma nu(x') .
+ * grad' K(x, x') mu(x') ds(x') for x on gamma, i.e. N_gamma[mu] on gamma less its jump (eq:DirichletRep;
+ * the mu-term of the boundary row of eq:DirBVPsystem: from the surface side N_gamma[mu] tends to
+ * +mu / (2a) + D_gamma[mu] with the outward conormal).  Taken when nu . grad a = 0 at every sample, where
+ * the kernel nu(x') . (x' - x) / (2 pi a(x') r^2) is smooth: the trapezoid rule on the samples, with the
+ * limit -(nu . gamma'') / (4 pi a |gamma'|^2) at x' = x.  mu and y as for pmx_edge_apply_kprime.
+ * Errors: INVALID (null argument, n_rhs outside [1, 1024], nu . grad a != 0 at some sample: the kernel
+ * then has a log|x - x'| term), OOM, DEVICE. */
+PMX_API pmx_status pmx_edge_apply_dlayer(pmx_edge* e, int n_rhs, const double* mu, double* y, int mem_kind,
+                                         void* stream);
 
 #ifdef __cplusplus
 }

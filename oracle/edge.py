@@ -19,8 +19,9 @@ surface gradient along nu equals the ambient one, so nu . grad'_G a = nu . grad 
 Only c = 0 is taken here (K = log r / (2 pi a(x')), the Laplace-Beltrami type and its variable-a
 generalization, as in the paper's boundary-value tests).
 
-One edge-to-edge operator of the systems' boundary rows is here too: K'_gamma, the conormal derivative
-at a target on gamma (``kprime_gamma``), with a smooth kernel and the trapezoid rule on the samples.
+Two edge-to-edge operators of the systems' boundary rows are here too, with targets on gamma, smooth
+kernels and the trapezoid rule on the samples: K'_gamma, the conormal derivative at the target
+(``kprime_gamma``), and D_gamma, the double layer (``dlayer_gamma``, for nu . grad a = 0 on gamma).
 
 Discretization (Section 6.1.4, edge quadrature): each boundary curve has a smooth periodic
 parameterization gamma(t), t in [0, 2 pi), sampled at n equispaced t.  Every sampled quantity (the
@@ -198,6 +199,37 @@ def kprime_gamma(edge, mu: np.ndarray) -> np.ndarray:
     Kp = np.sum(nu[:, None, :] * r, axis=-1) / (2 * np.pi * edge.a[None, :] * r2)
     np.fill_diagonal(Kp, lim)
     return Kp @ (w[:, None] * mu)
+
+
+def dlayer_gamma(edge, mu: np.ndarray) -> np.ndarray:
+    """D_gamma[mu] at the samples of every curve: the limit on gamma of N_gamma[mu] less its jump,
+        D_gamma[mu](x) = int_gamma nu(x') . grad' K(x, x') mu(x') ds(x'),   x in gamma,
+    the source-conormal (double-layer) kernel nu(x') . (x' - x) / (2 pi a(x') |x - x'|^2) when
+    nu . grad a = 0 along gamma (otherwise the kernel has a log|x - x'| term, not taken here: ValueError).
+    The kernel is smooth, so the trapezoid rule runs on the samples; at x' = x it takes its limit: with
+    x' = gamma(t + h), nu(x') . (x' - x) = -(nu . gamma'') h^2 / 2 + O(h^3), the same limit as K'_gamma,
+    -(nu . gamma'') / (4 pi a |gamma'|^2).  Returns (M, n_rhs)."""
+    nu = conormal(edge.xt, edge.d)
+    nga = np.sum(nu * edge.grad_a, axis=1)
+    if np.abs(nga).max() > 1e-14 * np.abs(edge.grad_a).max(initial=1.0):
+        raise ValueError("the on-curve double layer is taken for nu . grad a = 0 along the curve only")
+    off = np.asarray(edge.offsets)
+    mu = np.asarray(mu, dtype=np.float64).reshape(edge.x.shape[0], -1)
+    w = np.empty(edge.x.shape[0])
+    lim = np.empty(edge.x.shape[0])
+    for k in range(len(off) - 1):
+        s = slice(int(off[k]), int(off[k + 1]))
+        n = off[k + 1] - off[k]
+        xtt = fourier_derivative(edge.xt[s])
+        L2 = np.sum(edge.xt[s] ** 2, axis=1)
+        w[s] = 2 * np.pi / n * np.sqrt(L2)
+        lim[s] = -np.sum(nu[s] * xtt, axis=1) / (4 * np.pi * edge.a[s] * L2)
+    r = edge.x[None, :, :] - edge.x[:, None, :]          # x' - x (source j, target i)
+    r2 = np.sum(r * r, axis=-1)
+    np.fill_diagonal(r2, 1.0)
+    Dk = np.sum(nu[None, :, :] * r, axis=-1) / (2 * np.pi * edge.a[None, :] * r2)
+    np.fill_diagonal(Dk, lim)
+    return Dk @ (w[:, None] * mu)
 
 
 def edge_abs_sum(kind: str, tgt: dict, edge, m: int, targets=None, chunk: int = 256) -> np.ndarray:

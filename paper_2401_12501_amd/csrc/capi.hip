@@ -670,10 +670,24 @@ pmx_status pmx_edge_create(pmx_ctx* ctx, int n_curves, const int64_t* n_samples,
       }
       soa[9 * M + j] = ha[j];
     }
+    // nu . grad a at the samples (nu = the part of d normal to xt, normalized), for D_gamma's condition
+    double ga_max = 0.0, nga_max = 0.0;
+    for (int64_t j = 0; j < M; ++j) {
+      const double* t = &h3[1][3 * j];
+      const double* dd = &h3[2][3 * j];
+      const double* ga = &h3[3][3 * j];
+      const double tl2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+      const double dt = (dd[0] * t[0] + dd[1] * t[1] + dd[2] * t[2]) / tl2;
+      const double v[3] = {dd[0] - dt * t[0], dd[1] - dt * t[1], dd[2] - dt * t[2]};
+      const double vl = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      nga_max = std::max(nga_max, std::fabs(v[0] * ga[0] + v[1] * ga[1] + v[2] * ga[2]) / vl);
+      for (int c = 0; c < 3; ++c) ga_max = std::max(ga_max, std::fabs(ga[c]));
+    }
     auto* e = new pmx_edge;
     try {
       e->ctx = ctx;
       e->e.ctx = &ctx->c;
+      e->e.nu_grad_a_zero = nga_max <= 1e-14 * std::max(ga_max, 1.0);
       edge_build(&ctx->c, e->e, off, soa, oversample, st);
     } catch (...) {
       delete e;
@@ -759,7 +773,30 @@ pmx_status pmx_edge_apply_kprime(pmx_edge* e, int n_rhs, const double* mu, doubl
       bout.alloc(ctx, n);
       dy = bout.p;
     }
-    edge_apply_kprime(e->e, n_rhs, dmu, dy, st);
+    edge_apply_on_curve(e->e, false, n_rhs, dmu, dy, st);
+    if (mem_kind == PMX_MEM_HOST) PMX_HIP(hipMemcpyAsync(y, dy, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    PMX_HIP(hipStreamSynchronize(st));
+  });
+}
+
+pmx_status pmx_edge_apply_dlayer(pmx_edge* e, int n_rhs, const double* mu, double* y, int mem_kind, void* stream) {
+  return guarded([&] {
+    PMX_REQUIRE(e && mu && y, PMX_ERR_INVALID, "null argument");
+    PMX_REQUIRE(n_rhs >= 1 && n_rhs <= 1024, PMX_ERR_INVALID, "n_rhs must be in [1, 1024]");
+    PMX_REQUIRE(e->e.nu_grad_a_zero, PMX_ERR_INVALID,
+                "the on-curve double layer needs nu . grad a = 0 along the curves (else its kernel has a log term)");
+    PMX_HIP(hipSetDevice(e->ctx->c.device));
+    hipStream_t st = (hipStream_t)stream;
+    Ctx* ctx = &e->ctx->c;
+    const size_t n = (size_t)n_rhs * e->e.M;
+    DBuf<double> bin, bout;
+    const double* dmu = stage_in(ctx, bin, mu, n, mem_kind, st);
+    double* dy = y;
+    if (mem_kind == PMX_MEM_HOST) {
+      bout.alloc(ctx, n);
+      dy = bout.p;
+    }
+    edge_apply_on_curve(e->e, true, n_rhs, dmu, dy, st);
     if (mem_kind == PMX_MEM_HOST) PMX_HIP(hipMemcpyAsync(y, dy, n * sizeof(double), hipMemcpyDeviceToHost, st));
     PMX_HIP(hipStreamSynchronize(st));
   });

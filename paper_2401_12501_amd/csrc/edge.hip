@@ -24,7 +24,8 @@
 // on the fine points then has weights (2 pi / (m n)) |dgamma/dt|.
 //
 // K'_gamma, the conormal derivative at a target on gamma of the potential of K (the boundary rows of
-// the Neumann and Dirichlet systems), has the smooth kernel nu(x) . (x - x') / (2 pi a(x') |x - x'|^2):
+// the Neumann and Dirichlet systems), has the smooth kernel nu(x) . (x - x') / (2 pi a(x') |x - x'|^2),
+// and so has the double layer D_gamma (the conormal at the source) when nu . grad a = 0 on gamma:
 // the trapezoid rule runs on the samples themselves, and at x' = x the kernel takes its limit
 // -(nu . gamma'') / (4 pi a |gamma'|^2), with gamma'' the derivative of the interpolant of the sampled
 // dgamma/dt at the samples, sum_k D1(j - k) gamma'_k with D1(l) = (-1)^l cot(pi l / n) / 2 (n even)
@@ -208,11 +209,15 @@ __global__ void __launch_bounds__(kBlock) k_edge_samples(CurveIdx c, int64_t M, 
   S[8 * M + j] = -(v0 * tt[0] + v1 * tt[1] + v2 * tt[2]) / (4.0 * M_PI * a * L2);
 }
 
-// y[r][i] = sum_j w_j k(x_i, x_j) mu[r][j] over all samples, k the K'_gamma kernel (its limit at j = i).
+// y[r][i] = sum_j w_j k(x_i, x_j) mu[r][j] over all samples with the smooth on-curve kernel
+//   DL = false: K'_gamma, nu(x_i) . (x_i - x_j) / (2 pi a_j r^2)  (the conormal at the target),
+//   DL = true:  D_gamma,  nu(x_j) . (x_j - x_i) / (2 pi a_j r^2)  (at the source; nu . grad a = 0),
+// both with the limit -(nu . gamma'') / (4 pi a |gamma'|^2) at j = i.
 // One wavefront per (target sample, right-hand side), four per workgroup, grid y the right-hand side:
 // lane l takes the samples j = l (mod 64) and a fixed shuffle tree adds the lanes' sums.
-__global__ void __launch_bounds__(kBlock) k_edge_kprime(int64_t M, const double* __restrict__ S,
-                                                        const double* __restrict__ mu, double* __restrict__ y) {
+template <bool DL>
+__global__ void __launch_bounds__(kBlock) k_edge_on_curve(int64_t M, const double* __restrict__ S,
+                                                          const double* __restrict__ mu, double* __restrict__ y) {
   constexpr double kInv2Pi = 0.15915494309189533577;
   const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
@@ -229,7 +234,9 @@ __global__ void __launch_bounds__(kBlock) k_edge_kprime(int64_t M, const double*
     } else {
       const double dx = xi - S[j], dy = yi - S[M + j], dz = zi - S[2 * M + j];
       const double den = S[6 * M + j] * fma(dx, dx, fma(dy, dy, dz * dz));
-      val = kInv2Pi * fma(n0, dx, fma(n1, dy, n2 * dz)) * rcp_nr(den);
+      const double num = DL ? -fma(S[3 * M + j], dx, fma(S[4 * M + j], dy, S[5 * M + j] * dz))
+                            : fma(n0, dx, fma(n1, dy, n2 * dz));
+      val = kInv2Pi * num * rcp_nr(den);
     }
     acc = fma(S[7 * M + j] * m[j], val, acc);
   }
@@ -430,9 +437,12 @@ void edge_apply(pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double*
   PMX_HIP(hipGetLastError());
 }
 
-void edge_apply_kprime(EdgeSet& E, int n_rhs, const double* mu, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_edge_kprime, dim3((E.M + kBlock / 64 - 1) / (kBlock / 64), n_rhs), dim3(kBlock), 0, st, E.M,
-                     E.samp.p, mu, y);
+void edge_apply_on_curve(EdgeSet& E, bool double_layer, int n_rhs, const double* mu, double* y, hipStream_t st) {
+  const dim3 grid((E.M + kBlock / 64 - 1) / (kBlock / 64), n_rhs);
+  if (double_layer)
+    hipLaunchKernelGGL(k_edge_on_curve<true>, grid, dim3(kBlock), 0, st, E.M, E.samp.p, mu, y);
+  else
+    hipLaunchKernelGGL(k_edge_on_curve<false>, grid, dim3(kBlock), 0, st, E.M, E.samp.p, mu, y);
   PMX_HIP(hipGetLastError());
 }
 

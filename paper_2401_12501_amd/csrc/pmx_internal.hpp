@@ -176,6 +176,7 @@ struct NearLists {
 struct EdgeSet {
   Ctx* ctx = nullptr;
   int n_curves = 0, m = 1;
+  bool nu_grad_a_zero = false;   // nu . grad a = 0 at every sample (D_gamma is then smooth)
   int64_t M = 0, Mf = 0;
   std::vector<int64_t> off, foff;
   DBuf<int64_t> doff, dfoff;
@@ -780,8 +781,9 @@ void edge_build(Ctx* ctx, EdgeSet& E, const std::vector<int64_t>& off, const std
                 hipStream_t st);
 // y (n_rhs rows of N) = edge operator `kind` (0 K, 1 N, 2 R, 3 T) of mu (n_rhs rows of M), device arrays.
 void edge_apply(pmx_operator* op, EdgeSet& E, int kind, int n_rhs, const double* mu, double* y, hipStream_t st);
-// y (n_rhs rows of M) = K'_gamma of mu (n_rhs rows of M) at the samples, device arrays.
-void edge_apply_kprime(EdgeSet& E, int n_rhs, const double* mu, double* y, hipStream_t st);
+// y (n_rhs rows of M) = K'_gamma (double_layer false) or D_gamma (true) of mu (n_rhs rows of M) at the
+// samples, device arrays.
+void edge_apply_on_curve(EdgeSet& E, bool double_layer, int n_rhs, const double* mu, double* y, hipStream_t st);
 // fmm.hip
 void fmm_build(pmx_operator* op, hipStream_t st);
 void fmm_destroy(FMM* f);

@@ -91,6 +91,7 @@ _SIGS = {
     "pmx_edge_export_points": (C.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "pmx_edge_apply": (C.c_int32, [_vp, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int, _vp]),
     "pmx_edge_apply_kprime": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.c_int, _vp]),
+    "pmx_edge_apply_dlayer": (C.c_int32, [_vp, C.c_int, _vp, _vp, C.c_int, _vp]),
     "pmx_profile_read": (C.c_int32, [_vp, _vp, _vp]),
 }
 
@@ -477,6 +478,16 @@ class Edge:
         self._check_out(out, n_rhs * self.M)
         ptrs, kind_mem, stream, keep = _marshal(mu, out)
         _check(lib().pmx_edge_apply_kprime(self.h, n_rhs, ptrs[0], ptrs[1], kind_mem, stream))
+        return out
+
+    def dlayer(self, mu, out=None):
+        """pmx_edge_apply_dlayer: D_gamma of mu (n_rhs, M) at the samples, (n_rhs, M)."""
+        n_rhs = self._n_rhs(mu)
+        if out is None:
+            out = np.empty((n_rhs, self.M)) if not _is_torch(mu) else mu.new_empty((n_rhs, self.M))
+        self._check_out(out, n_rhs * self.M)
+        ptrs, kind_mem, stream, keep = _marshal(mu, out)
+        _check(lib().pmx_edge_apply_dlayer(self.h, n_rhs, ptrs[0], ptrs[1], kind_mem, stream))
         return out
 
 

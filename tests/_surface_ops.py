@@ -121,21 +121,3 @@ def values_at_edge(u, q: int, patches, n_v: int):
     ts = [2 * np.pi * ((P % n_v) + (t + 1) / 2) / n_v for P in patches]
     return np.concatenate(vals), np.concatenate(ts)
 
-
-def double_layer_on_curve(x, xt, nu, a, mu):
-    """D_gamma[mu](x_i) = sum_j w_j nu_j . (x_j - x_i) / (2 pi a_j |x_i - x_j|^2) mu_j on one closed curve
-    sampled at n equispaced parameters (weights (2 pi / n) |x_t|), with the kernel's limit
-    -(nu . x_tt) / (4 pi a |x_t|^2) on the diagonal (x_tt by FFT differentiation of x_t)."""
-    n = x.shape[0]
-    k = np.fft.fftfreq(n, d=1.0 / n)
-    if n % 2 == 0:
-        k[n // 2] = 0.0
-    xtt = np.fft.ifft(1j * k[:, None] * np.fft.fft(xt, axis=0), axis=0).real
-    L2 = (xt * xt).sum(1)
-    w = 2 * np.pi / n * np.sqrt(L2)
-    r = x[None, :, :] - x[:, None, :]               # x_j - x_i
-    r2 = (r * r).sum(-1)
-    np.fill_diagonal(r2, 1.0)
-    Kd = (nu[None, :, :] * r).sum(-1) / (2 * np.pi * a[None, :] * r2)
-    np.fill_diagonal(Kd, -(nu * xtt).sum(1) / (4 * np.pi * a * L2))
-    return Kd @ (w * mu)

@@ -78,3 +78,4 @@ def test_null_arguments_are_errors():
     assert L.pmx_edge_export_points(None, None, None, None, None, None) == pmx.PMX_ERR_INVALID
     L.pmx_edge_destroy(None)
     assert L.pmx_edge_apply_kprime(None, 1, None, None, 0, None) == pmx.PMX_ERR_INVALID
+    assert L.pmx_edge_apply_dlayer(None, 1, None, None, 0, None) == pmx.PMX_ERR_INVALID

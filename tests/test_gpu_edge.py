@@ -29,7 +29,7 @@ import numpy as np
 import pytest
 
 from paper_2401_12501_amd.inputs import EdgeSamples, Surface, wavy_torus_piece_problem
-from oracle.edge import edge_abs_sum, edge_apply, edge_points, kprime_gamma, targets_of
+from oracle.edge import dlayer_gamma, edge_abs_sum, edge_apply, edge_points, kprime_gamma, targets_of
 from oracle.operator import OracleOperator
 
 pytestmark = pytest.mark.gpu
@@ -385,33 +385,55 @@ def test_neumann_jump_relation_on_the_gpu(ctx):
 
 def test_dirichlet_jump_relation_on_the_gpu(ctx):
     """The double-layer jump for the Dirichlet representation (eq:DirichletRep) with a = 1 (where
-    nu . grad a = 0 and the on-curve kernel is smooth): the GPU's N_gamma[mu] on the band's last row,
-    extrapolated to the circle u = 2 pi, equals +mu / (2a) + D_gamma[mu] there, D_gamma the double layer
-    on the circle (trapezoid rule with its diagonal limit), to 1e-8.  The sign is the one K = log r /
-    (2 pi a) and the outward conormal fix (N_gamma[1] = 1 inside a planar curve, 1/2 on it); the printed
-    eq:DirBVPsystem has -mu / (2a) (a reading: its sign, or an inward conormal there)."""
+    nu . grad a = 0 and the on-curve kernel is smooth), from the library's outputs alone: the GPU's
+    N_gamma[mu] on the band's last row, extrapolated to the circle u = 2 pi, equals +mu / (2a) + the GPU's
+    D_gamma[mu] there, to 1e-8.  The sign is the one K = log r / (2 pi a) and the outward conormal fix
+    (N_gamma[1] = 1 inside a planar curve, 1/2 on it); the printed eq:DirBVPsystem has -mu / (2a) (a
+    reading: its sign, or an inward conormal there)."""
     from paper_2401_12501_amd import pmx
-    from oracle.edge import conormal
-    from _surface_ops import double_layer_on_curve, trig_eval, values_at_edge
+    from _surface_ops import trig_eval, values_at_edge
     n_u, n_v, q = 8, 12, 16
     p = wavy_torus_piece_problem(n_u=n_u, n_v=n_v, q=q, n_edge=200, variable_a=False)
     e = p.meta["edge"]
     op = pmx.Operator(pmx.Surface.from_inputs(ctx, p.surface), p.a, p.grad_a)
     E = pmx.Edge.from_inputs(ctx, e, 64)
-    Nv = E.apply(op, "N", np.ascontiguousarray(e.mu.T))[0]
+    mu = np.ascontiguousarray(e.mu.T)
+    Nv = E.apply(op, "N", mu)[0]
+    Dg = E.dlayer(mu)[0][200:400]
     patches = [(n_u - 1) * n_v + c for c in range(n_v)]
     idx = np.concatenate([np.arange(P * q * q, (P + 1) * q * q) for P in patches])
     lhs, tq = values_at_edge(Nv[idx], q, patches, n_v)
     up = slice(200, 400)
-    # the potential of both circles: the lower one is smooth at the upper circle (plain trapezoid sum)
-    nu_all = conormal(e.xt, e.d)
-    D_up = double_layer_on_curve(e.x[up], e.xt[up], nu_all[up], e.a[up], e.mu[up, 0])
-    lo = slice(0, 200)
-    r = e.x[lo][None, :, :] - e.x[up][:, None, :]
-    w_lo = 2 * np.pi / 200 * np.linalg.norm(e.xt[lo], axis=1)
-    D_lo = ((nu_all[lo][None] * r).sum(-1) / (2 * np.pi * e.a[lo][None] * (r * r).sum(-1))) @ (w_lo * e.mu[lo, 0])
-    rhs_samples = e.mu[up, 0] / (2 * e.a[up]) + D_up + D_lo
-    rhs = trig_eval(rhs_samples, tq)
+    rhs = trig_eval(e.mu[up, 0] / (2 * e.a[up]) + Dg, tq)
     err = float(np.abs(lhs - rhs).max() / np.abs(rhs).max())
     say(f"[edge dirichlet jump] {err:.2e}")
     assert err < 1e-8
+
+
+@pytest.mark.parametrize("counts", [200, (75, 50)])
+def test_dlayer_matches_oracle(ctx, counts):
+    from paper_2401_12501_amd import pmx
+    p = wavy_torus_piece_problem(n_u=4, n_v=6, q=6, n_edge=counts, variable_a=False, n_rhs=5)
+    e = p.meta["edge"]
+    E = pmx.Edge.from_inputs(ctx, e, 2)
+    y = E.dlayer(np.ascontiguousarray(e.mu.T)).T
+    ref = dlayer_gamma(e, e.mu)
+    absk = np.abs(dlayer_gamma(e, np.eye(e.m)))
+    scale = 1e-12 * absk.sum(axis=1)[:, None] * np.abs(e.mu).max(axis=0)[None, :]
+    err = float((np.abs(y - ref) / scale).max())
+    say(f"[dlayer] {counts}: error {err:.2f} of the bar, {col_err(y, ref):.2e} of the columns")
+    assert err <= 1
+
+
+def test_dlayer_circle_and_refusal(ctx, piece):
+    from paper_2401_12501_amd import pmx
+    n, rho = 40, 0.7
+    t = 2 * np.pi * np.arange(n) / n
+    x = np.stack([rho * np.cos(t), rho * np.sin(t), np.ones(n)], axis=1)
+    xt = np.stack([-rho * np.sin(t), rho * np.cos(t), 0 * t], axis=1)
+    d = np.stack([np.cos(t), np.sin(t), 0 * t], axis=1)
+    E = pmx.Edge(ctx, [n], x, xt, d, np.ones(n), np.zeros((n, 3)), 1)
+    assert np.abs(E.dlayer(np.ones((1, n))) - 0.5).max() < 1e-14
+    Ev = pmx.Edge.from_inputs(ctx, piece.edge, 1)       # a = exp(0.3 x1 x2): nu . grad a != 0 on the circles
+    with pytest.raises(pmx.PmxError):
+        Ev.dlayer(np.ones((1, piece.edge.m)))

@@ -38,8 +38,8 @@ import pytest
 import scipy.integrate as si
 
 from paper_2401_12501_amd.inputs import EdgeSamples, wavy_torus_piece_problem
-from oracle.edge import (conormal, edge_apply, edge_points, fourier_derivative, fourier_upsample, kprime_gamma,
-                         n_kernel, t_kernel, targets_of)
+from oracle.edge import (conormal, dlayer_gamma, edge_apply, edge_points, fourier_derivative, fourier_upsample,
+                         kprime_gamma, n_kernel, t_kernel, targets_of)
 from oracle.kernels import parametrix, remainder
 from oracle.operator import OracleOperator
 
@@ -377,7 +377,7 @@ def test_neumann_jump_relation():
 
 
 def test_dirichlet_jump_relation():
-    from _surface_ops import double_layer_on_curve, trig_eval, values_at_edge
+    from _surface_ops import trig_eval, values_at_edge
     errs = []
     for q in (12, 16):
         n_u, n_v = 8, 12
@@ -388,11 +388,33 @@ def test_dirichlet_jump_relation():
         Nv = edge_apply("N", targets_of(OracleOperator.from_problem(p)), e, e.mu, 64, targets=idx)[:, 0]
         lhs, tq = values_at_edge(Nv, q, patches, n_v)
         up, lo = slice(200, 400), slice(0, 200)
-        nu_all = conormal(e.xt, e.d)
-        D_up = double_layer_on_curve(e.x[up], e.xt[up], nu_all[up], e.a[up], e.mu[up, 0])
-        r = e.x[lo][None, :, :] - e.x[up][:, None, :]
-        w_lo = 2 * np.pi / 200 * np.linalg.norm(e.xt[lo], axis=1)
-        D_lo = ((nu_all[lo][None] * r).sum(-1) / (2 * np.pi * e.a[lo][None] * (r * r).sum(-1))) @ (w_lo * e.mu[lo, 0])
-        rhs = trig_eval(e.mu[up, 0] / (2 * e.a[up]) + D_up + D_lo, tq)
+        D_all = dlayer_gamma(e, e.mu)[up, 0]          # both circles' double layer at the upper samples
+        rhs = trig_eval(e.mu[up, 0] / (2 * e.a[up]) + D_all, tq)
         errs.append(float(np.abs(lhs - rhs).max() / np.abs(rhs).max()))
     assert errs[1] < 1e-10 and errs[1] < errs[0] / 100, errs
+
+
+
+def test_dlayer_circle_and_quadrature():
+    """D_gamma[1] = 1/2 on a circle (a = 1: the kernel is the constant 1 / (4 pi rho)); on an ellipse the
+    trapezoid sums equal adaptive quadrature of the exact integrand; a varying along the curve is refused."""
+    for rho, n in ((0.7, 12), (2.0, 33)):
+        e = _planar_edge(n, rho, rho)
+        np.testing.assert_allclose(dlayer_gamma(e, np.ones(n))[:, 0], 0.5, atol=1e-14)
+    n = 96
+    e = _planar_edge(n)
+    v = dlayer_gamma(e, np.exp(e.x[:, 0]))[:, 0]
+    for j in (0, 17, 50):
+        t0 = 2 * np.pi * j / n
+        x = e.x[j]
+
+        def g(t):
+            y, yt, _ = _ellipse(t)
+            nuy = conormal(yt[None], np.array([[np.cos(t), np.sin(t), 0.0]]))[0]
+            r = y - x
+            return float(nuy @ r / (2 * np.pi * (r @ r))) * np.linalg.norm(yt) * np.exp(y[0])
+        ref = si.quad(g, t0, t0 + 2 * np.pi, epsabs=1e-14, epsrel=1e-13, limit=400)[0]
+        assert abs(v[j] - ref) < 1e-12 * max(1.0, abs(ref)), (j, v[j], ref)
+    p = wavy_torus_piece_problem(n_u=4, n_v=6, q=6, n_edge=40, variable_a=True)
+    with pytest.raises(ValueError):
+        dlayer_gamma(p.meta["edge"], p.meta["edge"].mu)
